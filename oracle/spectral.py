@@ -1,0 +1,40 @@
+"""Oracle: sector eigensolve and the dynamic structure factor.
+
+Eigensolve: LAPACK ``zheevd`` (divide and conquer) through scipy; eigenvalues
+ascending, eigenvectors in the columns of Z (the paper's M = Z^T, DSF section).
+
+Dynamic structure factor at k = 0 (eq. 8 with the amplitude formula below it):
+the amplitude of |psi_{0,a}> is sqrt(N) * sum_{mu,nu} M*_{1 mu} G_{mu nu} M_{a nu}
+with G = <phi|gamma_1|phi> in the K = 0 sector, i.e. sqrt(N) * conj(b_a) with
+w = G z_1 and b = Z^H w.  Then
+    S(0, omega) = 2 pi N sum_a |b_a|^2 delta(omega - (E_a - E_1)),
+the delta replaced by a Lorentzian of half-width eta: (eta/pi) / (x^2 + eta^2).
+The sum runs over a = 1..chi including the elastic a = 1 term.
+"""
+import numpy as np
+import scipy.linalg
+
+
+def eigh(H):
+    """(E ascending, Z) of a Hermitian (or real symmetric) matrix via LAPACK *heevd/*syevd."""
+    return scipy.linalg.eigh(H, driver="evd")
+
+
+def dsf_weights(G, Z):
+    """b = Z^H (G z_1): projected amplitudes, |b_a|^2 are the spectral weights."""
+    w = G @ Z[:, 0]
+    return Z.conj().T @ w
+
+
+def dsf(N, E, Z, G, omega, eta):
+    """S(k=0, omega_j) for an array of frequencies (eq. 8, Lorentzian broadening)."""
+    b = dsf_weights(G, Z)
+    wt = np.abs(b) ** 2
+    x = np.asarray(omega)[:, None] - (E[None, :] - E[0])
+    lor = (eta / np.pi) / (x * x + eta * eta)
+    return 2.0 * np.pi * N * (lor @ wt)
+
+
+def masses(E, n=3):
+    """m_i = E_{i+1} - E_1 for the lowest K = 0 levels (DSF section, Table I)."""
+    return np.asarray(E[1:n + 1]) - E[0]

@@ -1,0 +1,120 @@
+"""Pins of the oracle's spectral sums (DSF, eq. 8) and quench (eq. 9, eqs. S5-S6, eq. 10).
+
+Independent references: spin-space exact diagonalisation and exact time
+evolution expm(-iHt) of eq. 3, brute-force overlaps, norm conservation.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse.linalg
+
+from oracle import basis, brute, heff, model, quench, spectral
+
+
+def _lorentz(x, eta):
+    return (eta / np.pi) / (x * x + eta * eta)
+
+
+@pytest.mark.parametrize("N,h,hp", [(8, 1.0, 0.1), (10, 1.0, 0.1), (8, 0.6, 0.3)])
+def test_dsf_full_basis_equals_spin_space_lehmann_sum(N, h, hp):
+    B = basis.build_basis(N, h)
+    G = heff.gamma1_matrix(N, h, B[0])
+    H = heff.heff(N, h, hp, B[0], G=G)
+    E, Z = spectral.eigh(H)
+    omega = np.linspace(0, 8, 257)
+    eta = 0.02
+    S = spectral.dsf(N, E, Z, G, omega, eta)
+    # spin space: ground state of K=0, sigma^x_{k=0} = N^{-1/2} sum_j sigma^x_j
+    Ek, Vk = brute.ed_sector(N, h, hp, 0, vectors=True)
+    sx = brute.sigma_x_sum(N) / np.sqrt(N)
+    amp = Vk.conj().T @ (sx @ Vk[:, 0])
+    Sref = 2 * np.pi * (_lorentz(omega[:, None] - (Ek[None, :] - Ek[0]), eta) @ np.abs(amp) ** 2)
+    assert np.abs(S - Sref).max() < 1e-9 * np.abs(Sref).max()
+    assert np.abs(E - Ek).max() < 1e-11
+
+
+def test_dsf_sum_rule():
+    N, h, hp = 10, 1.0, 0.1
+    B = basis.build_basis(N, h, e_cut=8.0)
+    G = heff.gamma1_matrix(N, h, B[0])
+    E, Z = spectral.eigh(heff.heff(N, h, hp, B[0], G=G))
+    b = spectral.dsf_weights(G, Z)
+    assert np.sum(np.abs(b) ** 2) == pytest.approx(np.linalg.norm(G @ Z[:, 0]) ** 2, rel=1e-13)
+
+
+@pytest.mark.parametrize("hpre,hpost", [(0.5, 1.0), (1.7, 1.2), (0.3, 0.9)])
+@pytest.mark.parametrize("sector", [model.NS, model.R])
+def test_cef_overlaps_equal_brute_force(hpre, hpost, sector):
+    N = 8
+    Fpre = brute.Fermions(N, hpre, sector)
+    Fpost = brute.Fermions(N, hpost, sector, cs=Fpre.cs)
+    masks = [m for m in range(1 << N) if bin(m).count("1") % 2 == 0]
+    ref = np.array([np.vdot(Fpost.state(m), Fpre.vac) for m in masks])
+    got = quench.cef_overlaps(N, hpre, hpost, sector, masks)
+    assert np.abs(got - ref).max() < 1e-13
+    assert np.sum(np.abs(got) ** 2) == pytest.approx(1.0, abs=1e-12)
+
+
+def _initial_state_coeffs(N, hpre, hpost, sec):
+    cn = quench.cef_overlaps(N, hpre, hpost, model.NS, sec["ns_masks"])
+    cr = quench.cef_overlaps(N, hpre, hpost, model.R, sec["r_masks"])
+    return np.concatenate([cn, cr]) / np.sqrt(2)
+
+
+def test_quench_full_basis_equals_exact_spin_evolution():
+    """(h_perp, h_par) = (0.5, 0) -> (1.0, 0.1), Phi_0 = (|0>_NS + s|0>_R)/sqrt 2."""
+    N, hpre, hpost, hp = 8, 0.5, 1.0, 0.1
+    B = basis.build_basis(N, hpost)
+    sec = B[0]
+    G = heff.gamma1_matrix(N, hpost, sec)
+    E, Z = spectral.eigh(heff.heff(N, hpost, hp, sec, G=G))
+    c = _initial_state_coeffs(N, hpre, hpost, sec)
+    # choose the sign giving positive magnetisation
+    s = 1.0 if quench.sigma_x(c[:, None], G, c)[0] > 0 else -1.0
+    na = len(sec["ns_masks"])
+    c[na:] *= s
+    times = np.linspace(0, 6, 25)
+    Bt = quench.evolve(E, Z, c, times)
+    sx = quench.sigma_x(Bt, G, c)
+    # spin space reference
+    Fn = brute.Fermions(N, hpre, model.NS)
+    Fr = brute.Fermions(N, hpre, model.R, cs=Fn.cs)
+    psi0 = (Fn.vac + s * Fr.vac) / np.sqrt(2)
+    Hs = brute.spin_hamiltonian(N, hpost, hp).toarray()
+    X = brute.sigma_x_sum(N).toarray() / N
+    ref = []
+    for t in times:
+        psi = scipy.linalg.expm(-1j * Hs * t) @ psi0
+        ref.append(np.vdot(psi, X @ psi).real)
+    assert sx[0] > 0
+    assert np.abs(sx - np.array(ref)).max() < 1e-10
+
+
+def test_quench_identities():
+    N, h, hp = 10, 1.0, 0.1
+    B = basis.build_basis(N, h, e_cut=7.0)
+    sec = B[0]
+    G = heff.gamma1_matrix(N, h, sec)
+    E, Z = spectral.eigh(heff.heff(N, h, hp, sec, G=G))
+    rng = np.random.default_rng(3)
+    c = rng.normal(size=E.size) + 1j * rng.normal(size=E.size)
+    times = np.linspace(0, 50, 101)
+    Bt = quench.evolve(E, Z, c, times)
+    assert np.abs(Bt[:, 0] - c).max() < 1e-12          # B(0) = c
+    nrm = np.linalg.norm(Bt, axis=0)
+    assert np.abs(nrm - np.linalg.norm(c)).max() < 1e-11  # norm is time independent
+    # h_par = 0: H_eff diagonal, B = exp(-i E0 t) c
+    e0 = np.concatenate([sec["ns_e"], sec["r_e"]])
+    E0, Z0 = spectral.eigh(heff.heff(N, h, 0.0, sec, G=G))
+    B0 = quench.evolve(E0, Z0, c, times)
+    assert np.abs(B0 - np.exp(-1j * np.outer(e0, times)) * c[:, None]).max() < 1e-11
+
+
+def test_eps_metric_nested_and_identical():
+    rng = np.random.default_rng(5)
+    Bl = rng.normal(size=(6, 4)) + 1j * rng.normal(size=(6, 4))
+    keys = [(0, i) for i in range(6)]
+    assert quench.eps_metric(keys, Bl, keys, Bl) == 0.0
+    Bs = Bl[:4] + 0.1
+    direct = np.sqrt(np.max(np.sum(np.abs(Bs - Bl[:4]) ** 2, axis=0) + np.sum(np.abs(Bl[4:]) ** 2, axis=0)))
+    assert quench.eps_metric(keys[:4], Bs, keys, Bl) == pytest.approx(direct, rel=1e-14)
