@@ -1,0 +1,223 @@
+/*
+ * tgba.h -- C ABI of the MI355X (gfx950) implementation of the hot path of
+ * the Truncated Gaussian Basis Approach (TGBA, arXiv 2410.04204).
+ *
+ * Problem statement (Method section): H = H0 + V with H0 quadratic in
+ * fermions.  Here H0 is the transverse-field Ising chain and V the
+ * longitudinal field (eq. 3):
+ *     H0 = - sum_j s^x_j s^x_{j+1} - h_perp sum_j s^z_j,   V = - h_par sum_j s^x_j
+ * on a periodic chain of even length N.  The eigenstates of H0 are fermionic
+ * Gaussian states d^dag_{k1}..d^dag_{kM}|0>_{NS/R} (Example section); a
+ * truncated subset of them in each momentum sector K spans the variational
+ * space, and the effective Hamiltonian (eq. 2)
+ *     H_ab = E_a^(0) delta_ab + <phi_a|V|phi_b>,
+ *     <phi_a|V|phi_b> = -N h_par <phi_a|(c_1 + c_1^dag)|phi_b>   (eq. S4)
+ * is assembled and diagonalised per sector; its eigenpairs give the dynamic
+ * structure factor (eq. 8) and quench dynamics (eq. 9, eq. 10).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All functions return int: TGBA_OK (0) or a negative TGBA_E* code; the
+ *    message of the last failure on the calling thread is returned by
+ *    tgba_last_error().  No C++ exception crosses this boundary.
+ *  - Pointers documented as "device" address MI355X global memory (for
+ *    example the data pointer of a torch.cuda tensor); "host" pointers are
+ *    ordinary CPU memory.  The caller owns every input and output buffer.
+ *    The library owns only the opaque tgba_basis handle (freed by
+ *    tgba_basis_free) and internal workspace it allocates with hipMalloc
+ *    and keeps cached per device until tgba_release_workspace().
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work on that stream and return without synchronising unless stated.
+ *  - Dense matrices are column-major with an explicit leading dimension
+ *    (element (i, j) at A[i + j*ld]).  Complex data is interleaved (re, im)
+ *    double.  Eigenvalues are ascending; eigenvectors are the columns of Z
+ *    (the paper's coefficient matrix is M = Z^T, DSF section).
+ *  - Momentum sectors are indexed by m in 0..N-1, K = 2 pi m / N.
+ *
+ * Gauge.  Every element <phi_a|gamma_1|phi_b> of a sector equals
+ * i^{-(M_a+M_b)/2} times a real number (a consequence of the antiunitary
+ * symmetry "reflection through site 1 x complex conjugation" of eq. 3).  The
+ * device path therefore works in the real gauge
+ *     |phi~_a> = g_a^* |phi_a>,  g_a = (-i)^{M_a/2} (NS),  g_b = i^{M_b/2} (R),
+ * in which H_eff is real symmetric: H = diag(g) H~ diag(g)^*.  The paper's
+ * complex gauge is available from tgba_assemble_heff (TGBA_GAUGE_PAPER).
+ */
+#ifndef TGBA_H
+#define TGBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define TGBA_OK 0
+#define TGBA_EINVAL (-1)       /* bad argument (odd N, N > 64, h_perp <= 0, bad K, ...) */
+#define TGBA_ENOMEM (-2)       /* host or device allocation failed                      */
+#define TGBA_EDEVICE (-3)      /* a HIP runtime call or kernel launch failed            */
+#define TGBA_ENUMERIC (-4)     /* a numerical health check failed (see tgba_last_error) */
+#define TGBA_EUNSUPPORTED (-5) /* valid request this build does not implement           */
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *tgba_last_error(void);
+
+/* ---- model and basis (Example section; DSF section; Appendix B) --------- */
+
+/* The chain of eq. 3.  N even, 2 <= N <= 64; h_perp > 0. */
+typedef struct tgba_model {
+    int N;
+    double h_perp;
+    double h_par;
+} tgba_model;
+
+#define TGBA_TRUNC_ECUT 0 /* keep E^(0) - E0 <= e_cut (E0 = min vacuum energy)          */
+#define TGBA_TRUNC_CHI 1  /* keep chi[K] lowest per sector, order (E^(0), NS<R, mask)   */
+
+/*
+ * Truncation of the Gaussian basis (Method section; Appendix B).
+ *   mode   TGBA_TRUNC_ECUT or TGBA_TRUNC_CHI
+ *   e_cut  ECUT: the cutoff.  CHI: cutoff of the candidate pool (< 0: the pool
+ *          is the whole space, only sensible for small N).
+ *   m_max  keep only M <= m_max quasiparticles (<= 0: no cap)
+ *   chi    CHI: host array of N per-sector dimensions, or NULL to use chi_all
+ * Cutoffs are inclusive with an absolute slack of 1e-9.  Energies are sums of
+ * libm-evaluated mode energies in ascending mode order, so inclusion and order
+ * decisions are reproducible bit for bit by any implementation doing the same.
+ */
+typedef struct tgba_trunc {
+    int mode;
+    double e_cut;
+    int m_max;
+    const int64_t *chi;
+    int64_t chi_all;
+} tgba_trunc;
+
+typedef struct tgba_basis tgba_basis;
+
+/*
+ * Enumerate the truncated Gaussian basis of every momentum sector and build
+ * the device-side tables the other calls use: the Bogoliubov mode tables
+ * (Example section) and the real contraction table of the common operator
+ * string (Appendix A, eqs. S1-S3; see tgba_basis_constants).  Enumeration
+ * runs on the host; the table is built by a device kernel on `stream`, and
+ * the call synchronises that stream before returning.
+ * Per sector the basis is listed NS block first, then R block, each ordered by
+ * (E^(0), mask); a state is a uint64 mask over its sector's ascending mode
+ * table (bit a = mode a).
+ * Errors: TGBA_EINVAL (model/trunc), TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC
+ * (vacuum-vacuum element |c0| below 1e-12, or the real-gauge check failed).
+ */
+int tgba_build_basis(const tgba_model *model, const tgba_trunc *trunc, void *stream, tgba_basis **out);
+void tgba_basis_free(tgba_basis *basis);
+
+/* Sector sizes (host). */
+int tgba_basis_sector_size(const tgba_basis *basis, int K, int64_t *n_ns, int64_t *n_r);
+
+/* Copy a sector's masks and E^(0) (host arrays of n_ns + n_r entries; either may be NULL). */
+int tgba_basis_sector_copy(const tgba_basis *basis, int K, uint64_t *masks, double *e0);
+
+/*
+ * Scalars of the model (host): c0 = <0_NS|gamma_1|0_R> (real, eq. S3-S4 with
+ * no excitations), the vacuum energies E_vac^NS, E_vac^R (eq. 5) and
+ * E0 = min of the two.
+ */
+int tgba_basis_constants(const tgba_basis *basis, double *c0, double *e_vac_ns, double *e_vac_r, double *e0);
+
+/*
+ * Gauge of a sector as quarter turns (host int8 array of n_ns + n_r):
+ * g_a = i^{q_a}.  q = -M/2 mod 4 for NS states, +M/2 mod 4 for R states.
+ */
+int tgba_basis_gauge(const tgba_basis *basis, int K, int8_t *q);
+
+/* ---- assembly of H_eff (eq. 2, eq. S4, Appendix A) ---------------------- */
+
+#define TGBA_HEFF 0x0        /* H_eff = diag(E^(0)) + V                           */
+#define TGBA_GAMMA1 0x1      /* G = <phi|gamma_1|phi> (no diagonal, no -N h_par)   */
+#define TGBA_GAUGE_PAPER 0x2 /* complex Hermitian output in the paper's gauge;     */
+                             /* default: real symmetric (real gauge), double      */
+#define TGBA_LOWER 0x4       /* write only the lower triangle incl. the diagonal  */
+
+/*
+ * Assemble one sector's matrix into device memory H (n x n, n = n_ns + n_r,
+ * column-major, leading dimension ld >= n, element type double or interleaved
+ * complex double with TGBA_GAUGE_PAPER).  Every NS x R element is a Pfaffian
+ * of the real contraction table restricted to the state's quasiparticles
+ * (Appendix A); NS x NS and R x R off-diagonal elements vanish by fermion
+ * parity (Appendix A) and are written as zeros.
+ * Errors: TGBA_EINVAL (K, ld, flags), TGBA_EDEVICE, TGBA_ENUMERIC.
+ */
+int tgba_assemble_heff(const tgba_basis *basis, int K, void *H, int64_t ld, int flags, void *stream);
+
+/*
+ * All listed sectors in one launch of each kernel (the work of every sector
+ * is flattened into one grid).  Ks, H and ld are host arrays of nsec entries.
+ */
+int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks, void *const *H,
+                               const int64_t *ld, int flags, void *stream);
+
+/* ---- dense symmetric eigensolve (Method section: diagonalise H_eff) ----- */
+
+#define TGBA_EIG_FP64 0x0    /* all stages in double precision                          */
+#define TGBA_EIG_MIXED 0x1   /* FP32 matrix-core products, FP64 tridiagonal + refinement */
+#define TGBA_EIG_NOVEC 0x2   /* eigenvalues only                                         */
+
+/*
+ * Eigen-decomposition A = Z diag(w) Z^T of a real symmetric n x n device
+ * matrix (lower triangle referenced).  On return A holds Z (unless
+ * TGBA_EIG_NOVEC) and w (device, n doubles) the ascending eigenvalues.
+ * The call synchronises `stream`.
+ * Errors: TGBA_EINVAL, TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC.
+ */
+int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags, void *stream);
+
+/* ---- dynamic structure factor at k = 0 (DSF section, eq. 8) -------------- */
+
+/*
+ * S(omega_j) = 2 pi N sum_a |b_a|^2 (eta/pi) / ((omega_j - (w_a - w_0))^2 + eta^2),
+ * b = Z^T (G z_0), for the real-gauge eigenvectors Z (n x n, ldz), eigenvalues
+ * w and gamma_1 matrix G (n x n, ldg) of the K = 0 sector; N_sites = N.
+ * All arrays are device arrays; weights (n, may be NULL) receives |b_a|^2.
+ */
+int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+             int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
+             void *stream);
+
+/* ---- quench (Quench section, eq. 9, eq. 10, Appendix B eqs. S5-S6) ------- */
+
+/*
+ * Time evolution in a sector: c~ = real-gauge overlaps of the initial state
+ * with the basis (device, interleaved complex, n entries), Z, w the sector's
+ * eigenpairs and G its gamma_1 matrix (real gauge).  For t_n = t0 + n dt,
+ * n = 0..nt-1:
+ *   B(t_n) = Z diag(exp(-i w t_n)) Z^T c~      (eq. 9)
+ *   sx[n]  = B^H G B / (c~^H c~)                (<sigma^x>(t), K = 0)
+ *   nrm[n] = |B(t_n)|                           (time independent, Quench section)
+ * B_out (device, interleaved complex, n x nt, column t, may be NULL) receives B.
+ */
+int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+                const double *c, double t0, double dt, int nt, double *sx, double *nrm, double *B_out,
+                void *stream);
+
+/*
+ * Overlaps <phi_a(post)|Phi_0> of a sector's basis with the initial state
+ * Phi_0 = (|0,pre>_NS + s |0,pre>_R)/sqrt(2) (s = +1 or -1), the vacua of H0 at
+ * the pre-quench transverse field h_perp_pre (closed form of eq. S5), written
+ * in the real gauge to c (device, interleaved complex, n_ns + n_r).  With
+ * s = 0, Phi_0 = |0,post>_NS (the H0 ground state at h_perp = 1).
+ */
+int tgba_quench_overlaps(const tgba_basis *basis, int K, double h_perp_pre, int s, double *c, void *stream);
+
+/* ---- bookkeeping -------------------------------------------------------- */
+
+/* Free the cached device workspace of the current device. */
+int tgba_release_workspace(void);
+
+/* Library version string. */
+const char *tgba_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGBA_H */

@@ -37,7 +37,7 @@ def eps_libm(N, h_perp, sector):
             out.append(2.0 * (1.0 - h_perp))
         else:
             c = math.cos(0.5 * k)
-            out.append(2.0 * math.sqrt((h_perp - 1.0) ** 2 + 4.0 * h_perp * c * c))
+            out.append(2.0 * math.sqrt((h_perp - 1.0) * (h_perp - 1.0) + 4.0 * h_perp * c * c))
     return out
 
 

@@ -1,0 +1,145 @@
+"""MI355X (gfx950) implementation of the hot path of the Truncated Gaussian
+Basis Approach (arXiv 2410.04204): Gaussian basis per momentum sector,
+Pfaffian assembly of H_eff, dense eigensolve, dynamic structure factor and
+quench observables, all in HIP kernels behind the C ABI of include/tgba.h.
+
+This package is a thin binding: functions marshal torch tensors (device
+memory) and numpy arrays (host) into the C ABI and raise on any error code.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
+                   TGBA_LOWER, TgbaError)
+
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "dsf", "quench", "quench_overlaps",
+           "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
+           "TGBA_EIG_NOVEC", "TgbaError", "version"]
+
+
+def version():
+    return _lib.load().tgba_version().decode()
+
+
+class Basis:
+    """Truncated Gaussian basis of every momentum sector (tgba_build_basis).
+
+    Exactly one of e_cut (energy cutoff) or chi (int or per-sector list) selects
+    the truncation; with chi, pool_e_cut bounds the candidate pool (None: whole
+    space, small N only).  m_max caps the quasiparticle number.
+    """
+
+    def __init__(self, N, h_perp, h_par, e_cut=None, chi=None, m_max=None, pool_e_cut=None, stream=None):
+        L = _lib.load()
+        self.N, self.h_perp, self.h_par = int(N), float(h_perp), float(h_par)
+        model = _lib.Model(self.N, self.h_perp, self.h_par)
+        self._chi_buf = None
+        if chi is None:
+            if e_cut is None:
+                raise ValueError("give e_cut or chi")
+            tr = _lib.Trunc(_lib.TGBA_TRUNC_ECUT, float(e_cut), int(m_max or 0), None, 0)
+        else:
+            pool = -1.0 if pool_e_cut is None else float(pool_e_cut)
+            if np.isscalar(chi):
+                tr = _lib.Trunc(_lib.TGBA_TRUNC_CHI, pool, int(m_max or 0), None, int(chi))
+            else:
+                self._chi_buf = np.ascontiguousarray(np.asarray(chi, dtype=np.int64))
+                tr = _lib.Trunc(_lib.TGBA_TRUNC_CHI, pool, int(m_max or 0),
+                                self._chi_buf.ctypes.data_as(_lib.P_i64), 0)
+        h = ctypes.c_void_p()
+        _lib.check(L.tgba_build_basis(ctypes.byref(model), ctypes.byref(tr), _lib.stream_handle(stream),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sector_size(self, K):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.load().tgba_basis_sector_size(self._h, int(K), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def sector(self, K):
+        """(masks uint64[n], E0 float64[n]) of sector K: NS block then R block."""
+        n_ns, n_r = self.sector_size(K)
+        m = np.zeros(n_ns + n_r, dtype=np.uint64)
+        e = np.zeros(n_ns + n_r, dtype=np.float64)
+        _lib.check(_lib.load().tgba_basis_sector_copy(self._h, int(K), _lib.ptr(m), _lib.ptr(e)))
+        return m, e
+
+    def constants(self):
+        v = [ctypes.c_double() for _ in range(4)]
+        _lib.check(_lib.load().tgba_basis_constants(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(c0=v[0].value, e_vac_ns=v[1].value, e_vac_r=v[2].value, e0=v[3].value)
+
+    def gauge(self, K):
+        """Quarter turns q (g = i^q) of the real gauge of sector K."""
+        n = sum(self.sector_size(K))
+        q = np.zeros(n, dtype=np.int8)
+        _lib.check(_lib.load().tgba_basis_gauge(self._h, int(K), _lib.ptr(q)))
+        return q
+
+    def free(self):
+        if getattr(self, "_h", None):
+            _lib.load().tgba_basis_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _ld(H):
+    # column-major matrix stored as a torch tensor of shape (ncols, ld) or (ncols, ld, 2) (complex interleaved)
+    return H.shape[1]
+
+
+def assemble_heff(basis, K, H, flags=TGBA_HEFF, stream=None):
+    """Assemble sector K into the device tensor H (column-major: H[j, i] is element (i, j))."""
+    _lib.check(_lib.load().tgba_assemble_heff(basis.handle, int(K), _lib.ptr(H), _ld(H), int(flags),
+                                              _lib.stream_handle(stream)))
+    return H
+
+
+def assemble_heff_batched(basis, Ks, Hs, flags=TGBA_HEFF, stream=None):
+    n = len(Ks)
+    ks = np.ascontiguousarray(np.asarray(Ks, dtype=np.int32))
+    ptrs = (ctypes.c_void_p * n)(*[H.data_ptr() for H in Hs])
+    lds = np.ascontiguousarray(np.array([_ld(H) for H in Hs], dtype=np.int64))
+    _lib.check(_lib.load().tgba_assemble_heff_batched(basis.handle, n, _lib.ptr(ks), ptrs, _lib.ptr(lds),
+                                                      int(flags), _lib.stream_handle(stream)))
+    return Hs
+
+
+def eig(A, w, flags=TGBA_EIG_FP64, stream=None):
+    """A = Z diag(w) Z^T for a column-major symmetric device matrix; A is overwritten by Z."""
+    n = w.shape[0]
+    _lib.check(_lib.load().tgba_eig(int(n), _lib.ptr(A), _ld(A), _lib.ptr(w), int(flags), _lib.stream_handle(stream)))
+    return w
+
+
+def dsf(Z, w, G, N_sites, omega, eta, S, weights=None, stream=None):
+    n = w.shape[0]
+    _lib.check(_lib.load().tgba_dsf(int(n), _lib.ptr(Z), _ld(Z), _lib.ptr(w), _lib.ptr(G), _ld(G), int(N_sites),
+                                    _lib.ptr(omega), int(omega.shape[0]), float(eta), _lib.ptr(S),
+                                    _lib.ptr(weights), _lib.stream_handle(stream)))
+    return S
+
+
+def quench(Z, w, G, c, t0, dt, nt, sx, nrm, B=None, stream=None):
+    n = w.shape[0]
+    _lib.check(_lib.load().tgba_quench(int(n), _lib.ptr(Z), _ld(Z), _lib.ptr(w), _lib.ptr(G), _ld(G), _lib.ptr(c),
+                                       float(t0), float(dt), int(nt), _lib.ptr(sx), _lib.ptr(nrm), _lib.ptr(B),
+                                       _lib.stream_handle(stream)))
+    return sx
+
+
+def quench_overlaps(basis, K, h_perp_pre, s, c, stream=None):
+    _lib.check(_lib.load().tgba_quench_overlaps(basis.handle, int(K), float(h_perp_pre), int(s), _lib.ptr(c),
+                                                _lib.stream_handle(stream)))
+    return c

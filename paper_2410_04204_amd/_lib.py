@@ -1,0 +1,107 @@
+"""ctypes binding of libtgba.so (the C ABI declared in include/tgba.h).
+
+Argument marshalling only: every computation runs in the library.  Importing
+this module without a built library raises; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtgba.so")
+
+TGBA_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
+
+TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI = 0, 1
+TGBA_HEFF, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_LOWER = 0x0, 0x1, 0x2, 0x4
+TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC = 0x0, 0x1, 0x2
+
+EXPORTS = [
+    "tgba_last_error", "tgba_version", "tgba_build_basis", "tgba_basis_free", "tgba_basis_sector_size",
+    "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
+    "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
+    "tgba_release_workspace",
+]
+
+
+class TgbaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("h_perp", ctypes.c_double), ("h_par", ctypes.c_double)]
+
+
+class Trunc(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("e_cut", ctypes.c_double), ("m_max", ctypes.c_int),
+                ("chi", ctypes.POINTER(ctypes.c_int64)), ("chi_all", ctypes.c_int64)]
+
+
+_lib = None
+c_void_p, c_int, c_int64, c_double = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+P_i64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def load():
+    """Load libtgba.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch first: its HIP runtime (soname libamdhip64.so.7) then also serves
+    # this library, so tensors, streams and our kernels live in one runtime.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_04204_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.tgba_last_error.restype = ctypes.c_char_p
+    L.tgba_version.restype = ctypes.c_char_p
+    L.tgba_build_basis.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Trunc), c_void_p, ctypes.POINTER(c_void_p)]
+    L.tgba_basis_free.argtypes = [c_void_p]
+    L.tgba_basis_free.restype = None
+    L.tgba_basis_sector_size.argtypes = [c_void_p, c_int, P_i64, P_i64]
+    L.tgba_basis_sector_copy.argtypes = [c_void_p, c_int, c_void_p, c_void_p]
+    L.tgba_basis_constants.argtypes = [c_void_p] + [ctypes.POINTER(c_double)] * 4
+    L.tgba_basis_gauge.argtypes = [c_void_p, c_int, c_void_p]
+    L.tgba_assemble_heff.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_int, c_void_p]
+    L.tgba_assemble_heff_batched.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+    L.tgba_eig.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int, c_void_p]
+    L.tgba_dsf.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int,
+                           c_double, c_void_p, c_void_p, c_void_p]
+    L.tgba_quench.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_double,
+                              c_double, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_quench_overlaps.argtypes = [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p]
+    L.tgba_release_workspace.argtypes = []
+    for name in EXPORTS:
+        if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free"):
+            getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != TGBA_OK:
+        raise TgbaError(rc, load().tgba_last_error().decode())
+
+
+def ptr(t):
+    """Device (or host) address of a tensor / array, None -> NULL."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ctypes.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return ctypes.c_void_p(t.ctypes.data)
+    raise TypeError(type(t))
+
+
+def stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(stream)

@@ -1,0 +1,625 @@
+// Assembly of the truncated effective Hamiltonian of a momentum sector
+// (eq. 2 with eq. S4; Appendix A).
+//
+// Every V element of a sector is
+//     <phi_a|gamma_1|phi_b> = c0 * (-i)^{(M_a+M_b)/2} * Pf(R[I_a u I_b])
+// with R the real 2N x 2N contraction table of the excitation operators (see
+// tgba_table.hip), I_a the bra indices of the NS state a (its modes in
+// descending momentum) and I_b the ket indices of the R state b (ascending).
+//
+// Work decomposition (MI355X): a workgroup owns ROWS consecutive NS states.
+// For each of its rows it first eliminates that row's bra indices from
+// R[I_a u ket-all] in LDS (Schur complement with complete pivoting inside the
+// bra block, Pf(R[I_a]) accumulated from the pivots):
+//     Pf(R[I_a u I_b]) = Pf(R[I_a]) * Pf(S_a[I_b]),
+//     S_a = R_kk + R_ak^T R_aa^{-1} R_ak           (N x N, skew)
+// and keeps S_a packed in LDS.  Then every thread takes R columns b and
+// evaluates the small Pfaffian Pf(S_a[I_b]) of size M_b for all ROWS rows:
+//   M_b <= 6   closed-form expansion along the first row (division free),
+//   M_b = 8,10 one step of partial pivoting done while gathering from LDS,
+//              then the expansion of the remaining 6 or 8,
+//   M_b > 10   pivoted elimination in private memory (rare).
+// A row whose bra elimination shows large element growth is flagged and its
+// elements are evaluated directly as Pf(R[I_a u I_b]) by pivoted elimination.
+//
+// Output (column-major, ld): the sector's NS block first, then R block:
+//   H = [[diag E_NS, B], [B^T, diag E_R]]   (real gauge, double), or the
+//   complex Hermitian matrix of the paper's gauge (B -> (-i)^{m/2} B).
+// The workgroup writes its NS columns completely (NS x NS zeros + diagonal,
+// B^T part coalesced along b) and, unless TGBA_LOWER, the B part as ROWS
+// consecutive entries per R column.  The R x R block (zeros + diagonal) is
+// written by a separate fill kernel.
+#include <cmath>
+#include <cstdio>
+
+#include "tgba_internal.h"
+
+namespace tgba {
+
+// Per-sector launch descriptor (batched launches flatten all sectors).
+struct SectorDesc {
+    const uint64_t *masks;  // n_ns NS masks then n_r R masks
+    const double *e;        // E^(0)
+    void *H;
+    int64_t ld;
+    int64_t n_ns, n_r;
+    int64_t first_block;    // first workgroup index of this sector
+    int max_m_bra;          // largest M among the sector's NS states
+    int pad;
+};
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kGenMax = 24;          // largest Pfaffian of the generic path
+constexpr double kGrowthLimit = 1e6; // flag a row when the Schur complement grows beyond this
+
+// ---- small Pfaffians by expansion along the first remaining index ------------
+template <unsigned MASK>
+__device__ __forceinline__ double pf_rec(const double (&a)[10][10]);
+
+template <unsigned REST, int I, int J, bool PLUS>
+__device__ __forceinline__ double pf_terms(const double (&a)[10][10]) {
+    if constexpr (J >= 10) {
+        return 0.0;
+    } else if constexpr (((REST >> J) & 1u) == 0u) {
+        return pf_terms<REST, I, J + 1, PLUS>(a);
+    } else {
+        const double t = a[I][J] * pf_rec<REST & ~(1u << J)>(a);
+        const double r = pf_terms<REST, I, J + 1, !PLUS>(a);
+        return PLUS ? r + t : r - t;
+    }
+}
+
+template <unsigned MASK>
+__device__ __forceinline__ double pf_rec(const double (&a)[10][10]) {
+    if constexpr (MASK == 0u) {
+        return 1.0;
+    } else {
+        constexpr int I = __builtin_ctz(MASK);
+        return pf_terms<MASK & (MASK - 1u), I, I + 1, true>(a);
+    }
+}
+
+// packed upper-triangular LDS table of an N x N skew matrix:
+// element (u, v), u < v, at rowoff(u) + v with rowoff(u) = u*N - u(u+1)/2 - u - 1
+__device__ __forceinline__ int rowoff(int u, int N) { return u * N - (u * (u + 1)) / 2 - u - 1; }
+
+__device__ __forceinline__ double skew_at(const double *tab, int N, int u, int v) {
+    return (u < v) ? tab[rowoff(u, N) + v] : -tab[rowoff(v, N) + u];
+}
+
+// Pf(S[idx[0..M)]) for M in {0,2,4,6}; idx ascending; off[i] = rowoff(idx[i]).
+template <int M>
+__device__ __forceinline__ double pf_direct(const double *tab, const int *idx, const int *off) {
+    if constexpr (M == 0) {
+        return 1.0;
+    } else {
+        double a[10][10];
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = i + 1; j < M; ++j) a[i][j] = tab[off[i] + idx[j]];
+        return pf_rec<(1u << M) - 1u>(a);
+    }
+}
+
+// Pf for M in {8, 10}: pivot the first row while gathering, then expand the rest.
+template <int M>
+__device__ __forceinline__ double pf_pivot_expand(const double *tab, int N, const int *idx, const int *off) {
+    double r0[M];
+#pragma unroll
+    for (int j = 1; j < M; ++j) r0[j] = tab[off[0] + idx[j]];
+    int p = 1;
+    double best = fabs(r0[1]);
+#pragma unroll
+    for (int j = 2; j < M; ++j) {
+        double v = fabs(r0[j]);
+        if (v > best) { best = v; p = j; }
+    }
+    if (best == 0.0) return 0.0;
+    double piv = r0[1];
+    int ip = idx[1];
+#pragma unroll
+    for (int j = 2; j < M; ++j)
+        if (p == j) { piv = r0[j]; ip = idx[j]; }
+    // remaining positions t -> original position (t+1 < p ? t+1 : t+2)
+    int ri[M - 2];
+    double y[M - 2], x[M - 2];
+#pragma unroll
+    for (int t = 0; t < M - 2; ++t) {
+        const bool lo = (t + 1 < p);
+        ri[t] = lo ? idx[t + 1] : idx[t + 2];
+        y[t] = lo ? r0[t + 1] : r0[t + 2];
+        x[t] = skew_at(tab, N, ip, ri[t]);
+    }
+    const double inv = 1.0 / piv;
+    double a[10][10];
+#pragma unroll
+    for (int t = 0; t < M - 2; ++t) {
+        const int ot = rowoff(ri[t], N);
+#pragma unroll
+        for (int u = t + 1; u < M - 2; ++u) a[t][u] = tab[ot + ri[u]] + (x[t] * y[u] - y[t] * x[u]) * inv;
+    }
+    const double sgn = (p & 1) ? 1.0 : -1.0;  // (-1)^(p-1)
+    return sgn * piv * pf_rec<(1u << (M - 2)) - 1u>(a);
+}
+
+// Pfaffian of the M x M skew matrix in A (row-major, ld kGenMax), destroyed.
+__device__ __noinline__ double pf_eliminate(double *A, int M) {
+    double pf = 1.0;
+    for (int k = 0; k + 1 < M; k += 2) {
+        int p = k + 1;
+        double best = fabs(A[k * kGenMax + k + 1]);
+        for (int j = k + 2; j < M; ++j) {
+            double v = fabs(A[k * kGenMax + j]);
+            if (v > best) { best = v; p = j; }
+        }
+        if (best == 0.0) return 0.0;
+        if (p != k + 1) {
+            for (int c = 0; c < M; ++c) {
+                double t = A[(k + 1) * kGenMax + c]; A[(k + 1) * kGenMax + c] = A[p * kGenMax + c]; A[p * kGenMax + c] = t;
+            }
+            for (int r = 0; r < M; ++r) {
+                double t = A[r * kGenMax + k + 1]; A[r * kGenMax + k + 1] = A[r * kGenMax + p]; A[r * kGenMax + p] = t;
+            }
+            pf = -pf;
+        }
+        const double a = A[k * kGenMax + k + 1];
+        pf *= a;
+        const double inv = 1.0 / a;
+        for (int i = k + 2; i < M; ++i) {
+            const double xi = A[(k + 1) * kGenMax + i], yi = A[k * kGenMax + i];
+            for (int j = i + 1; j < M; ++j) {
+                double v = A[i * kGenMax + j] + (xi * A[k * kGenMax + j] - yi * A[(k + 1) * kGenMax + j]) * inv;
+                A[i * kGenMax + j] = v;
+                A[j * kGenMax + i] = -v;
+            }
+        }
+    }
+    return pf;
+}
+
+// Generic small-table Pfaffian (packed LDS S_a), any M <= kGenMax.
+__device__ __noinline__ double pf_generic_packed(const double *tab, int N, const int *idx, int M) {
+    double A[kGenMax * kGenMax];
+    for (int i = 0; i < M; ++i) {
+        A[i * kGenMax + i] = 0.0;
+        for (int j = i + 1; j < M; ++j) {
+            double v = tab[rowoff(idx[i], N) + idx[j]];
+            A[i * kGenMax + j] = v;
+            A[j * kGenMax + i] = -v;
+        }
+    }
+    return pf_eliminate(A, M);
+}
+
+// Direct Pf(R[I_a u I_b]) from the global real table (flagged rows).
+__device__ __noinline__ double pf_generic_full(const double *__restrict__ R, int N, uint64_t bra, const int *kidx, int Mb) {
+    int g[kGenMax];
+    int M = 0;
+    for (int a = N - 1; a >= 0; --a)
+        if ((bra >> a) & 1ULL) g[M++] = N - 1 - a;
+    for (int j = 0; j < Mb; ++j) g[M++] = N + kidx[j];
+    double A[kGenMax * kGenMax];
+    const int n2 = 2 * N;
+    for (int i = 0; i < M; ++i) {
+        A[i * kGenMax + i] = 0.0;
+        for (int j = i + 1; j < M; ++j) {
+            double v = R[g[i] * n2 + g[j]];
+            A[i * kGenMax + j] = v;
+            A[j * kGenMax + i] = -v;
+        }
+    }
+    return pf_eliminate(A, M);
+}
+
+__device__ __forceinline__ int sector_of(const SectorDesc *d, int nsec, int64_t blk) {
+    int lo = 0, hi = nsec - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].first_block <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// quarter-turn phase (-i)^q applied to a real value: returns (re, im)
+__device__ __forceinline__ void phase_mi(int q, double v, double &re, double &im) {
+    switch (q & 3) {
+        case 0: re = v; im = 0.0; break;
+        case 1: re = 0.0; im = -v; break;
+        case 2: re = -v; im = 0.0; break;
+        default: re = 0.0; im = v; break;
+    }
+}
+
+// Positions of the set bits of a ket mask, statically indexed (registers).
+template <int M>
+__device__ __forceinline__ void decode_ket(uint64_t x, int N, int (&idx)[M > 0 ? M : 1], int (&off)[M > 0 ? M : 1]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        idx[j] = __ffsll((long long)x) - 1;
+        off[j] = rowoff(idx[j], N);
+        x &= x - 1ULL;
+    }
+}
+
+// Generic path for one element of a flagged row or a large ket (rare): decodes
+// into private memory.
+__device__ __noinline__ double element_generic(const double *tab, int N, uint64_t ket, int flagged, uint64_t bra,
+                                               const double *__restrict__ R, unsigned long long *counters) {
+    int kidx[kGenMax];
+    int m = 0;
+    for (int q = 0; q < N; ++q)
+        if ((ket >> q) & 1ULL) {
+            if (m == kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
+            kidx[m++] = q;
+        }
+    if (flagged) {
+        if (__popcll(bra) + m > kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
+        return pf_generic_full(R, N, bra, kidx, m);
+    }
+    atomicAdd(&counters[1], 1ULL);
+    return pf_generic_packed(tab, N, kidx, m);
+}
+
+// Pf(S_r[I_b]) times the row factor for every valid row r of the workgroup.
+template <int MB, int ROWS>
+__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, int ntab, int N, uint64_t ket,
+                                           int nvalid, const int *s_flag, const uint64_t *s_bra, const double *s_fac,
+                                           const double *__restrict__ R, unsigned long long *counters) {
+    int idx[MB > 0 ? MB : 1], off[MB > 0 ? MB : 1];
+    if constexpr (MB > 0) decode_ket<MB>(ket, N, idx, off);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        double pfv = 0.0;
+        if (r < nvalid) {
+            const double *tab = tabs + r * ntab;
+            if (MB < 0 || s_flag[r]) {
+                pfv = element_generic(tab, N, ket, s_flag[r], s_bra[r], R, counters);
+            } else if constexpr (MB == 0) {
+                pfv = 1.0;
+            } else if constexpr (MB == 2) {
+                pfv = tab[off[0] + idx[1]];
+            } else if constexpr (MB == 4 || MB == 6) {
+                pfv = pf_direct<MB>(tab, idx, off);
+            } else if constexpr (MB == 8 || MB == 10) {
+                pfv = pf_pivot_expand<MB>(tab, N, idx, off);
+            }
+        }
+        val[r] = s_fac[r] * pfv;
+    }
+}
+
+__global__ void zero_counters_kernel(unsigned long long *c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0ULL;
+}
+
+template <int ROWS, bool CPLX>
+__global__ void __launch_bounds__(kThreads)
+assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, const double *__restrict__ R,
+                     double r_max, double c0, double scale, int with_diag, int lower,
+                     unsigned long long *__restrict__ counters) {
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int s = sector_of(descs, nsec, blockIdx.x);
+    const SectorDesc D = descs[s];
+    const int64_t a0 = (int64_t)(blockIdx.x - D.first_block) * ROWS;
+    const int ntab = N * (N - 1) / 2;
+    const int wdim = D.max_m_bra + N;
+    double *tabs = lds;                          // ROWS packed S_a tables
+    double *W = lds + ROWS * ntab;               // dense scratch wdim x wdim
+    __shared__ double s_fac[ROWS];
+    __shared__ int s_flag[ROWS], s_mbra[ROWS];
+    __shared__ uint64_t s_bra[ROWS];
+    __shared__ int s_bidx[kGenMax];
+    __shared__ int s_pp, s_pq;
+    __shared__ double s_growth;
+
+    // ---- per-row Schur complement over the bra indices -------------------
+    for (int r = 0; r < ROWS; ++r) {
+        const int64_t a = a0 + r;
+        if (a >= D.n_ns) {
+            if (tid == 0) { s_fac[r] = 0.0; s_flag[r] = 0; s_mbra[r] = 0; s_bra[r] = 0; }
+            continue;
+        }
+        const uint64_t bra = D.masks[a];
+        const int Ma = __popcll(bra);
+        if (tid == 0) {
+            int m = 0;
+            for (int q = N - 1; q >= 0; --q)
+                if ((bra >> q) & 1ULL) s_bidx[m++] = N - 1 - q;  // ascending table index
+            s_bra[r] = bra;
+            s_mbra[r] = Ma;
+            s_growth = 0.0;
+        }
+        __syncthreads();
+        const int n = Ma + N;
+        for (int idx = tid; idx < n * n; idx += kThreads) {
+            const int i = idx / n, j = idx % n;
+            const int gi = (i < Ma) ? s_bidx[i] : N + (i - Ma);
+            const int gj = (j < Ma) ? s_bidx[j] : N + (j - Ma);
+            W[i * wdim + j] = R[gi * (2 * N) + gj];
+        }
+        __syncthreads();
+        double pf = 1.0;
+        for (int k = 0; k < Ma; k += 2) {
+            if (tid < 64) {  // complete pivot search over the remaining bra block
+                double best = -1.0;
+                int bp = k, bq = k + 1;
+                const int rem = Ma - k;
+                for (int e = tid; e < rem * rem; e += 64) {
+                    const int i = k + e / rem, j = k + e % rem;
+                    if (j <= i) continue;
+                    const double v = fabs(W[i * wdim + j]);
+                    if (v > best) { best = v; bp = i; bq = j; }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ob = __shfl_down(best, off, 64);
+                    const int op = __shfl_down(bp, off, 64), oq = __shfl_down(bq, off, 64);
+                    if (ob > best || (ob == best && (op < bp || (op == bp && oq < bq)))) { best = ob; bp = op; bq = oq; }
+                }
+                if (tid == 0) { s_pp = bp; s_pq = bq; }
+            }
+            __syncthreads();
+            const int p = s_pp, q = s_pq;
+            if (p != k) {  // swap index p -> k
+                for (int c = tid; c < n; c += kThreads) {
+                    double t = W[k * wdim + c]; W[k * wdim + c] = W[p * wdim + c]; W[p * wdim + c] = t;
+                }
+                __syncthreads();
+                for (int c = tid; c < n; c += kThreads) {
+                    double t = W[c * wdim + k]; W[c * wdim + k] = W[c * wdim + p]; W[c * wdim + p] = t;
+                }
+                __syncthreads();
+                pf = -pf;
+            }
+            if (q != k + 1) {  // swap index q -> k+1 (q > p >= k, so q != k)
+                for (int c = tid; c < n; c += kThreads) {
+                    double t = W[(k + 1) * wdim + c]; W[(k + 1) * wdim + c] = W[q * wdim + c]; W[q * wdim + c] = t;
+                }
+                __syncthreads();
+                for (int c = tid; c < n; c += kThreads) {
+                    double t = W[c * wdim + k + 1]; W[c * wdim + k + 1] = W[c * wdim + q]; W[c * wdim + q] = t;
+                }
+                __syncthreads();
+                pf = -pf;
+            }
+            const double piv = W[k * wdim + k + 1];
+            pf *= piv;
+            const double inv = (piv != 0.0) ? 1.0 / piv : 0.0;
+            const int t0 = k + 2, nt = n - t0;
+            for (int e = tid; e < nt * nt; e += kThreads) {
+                const int i = t0 + e / nt, j = t0 + e % nt;
+                W[i * wdim + j] += (W[(k + 1) * wdim + i] * W[k * wdim + j] - W[k * wdim + i] * W[(k + 1) * wdim + j]) * inv;
+            }
+            __syncthreads();
+        }
+        // pack the ket block into the row's table and measure its growth
+        double g = 0.0;
+        double *tab = tabs + r * ntab;
+        for (int e = tid; e < ntab; e += kThreads) {
+            // invert the packed index: row u with rowoff(u)+u+1 <= e < rowoff(u+1)+u+2
+            int u = 0;
+            while (rowoff(u + 1, N) + u + 2 <= e) ++u;
+            const int v = e - rowoff(u, N);
+            const double val = W[(Ma + u) * wdim + Ma + v];
+            tab[e] = val;
+            g = fmax(g, fabs(val));
+        }
+        for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_down(g, off, 64));
+        if ((tid & 63) == 0) atomicMax((unsigned long long *)&s_growth, __double_as_longlong(g));
+        __syncthreads();
+        if (tid == 0) {
+            const bool bad = !(pf != 0.0) || !(s_growth <= kGrowthLimit * r_max) || !isfinite(pf);
+            s_flag[r] = bad ? 1 : 0;
+            s_fac[r] = bad ? c0 * scale : c0 * scale * pf;
+            if (bad) atomicAdd(&counters[0], 1ULL);
+        }
+        __syncthreads();
+    }
+
+    // ---- NS columns: zeros of the NS x NS block and the diagonal -----------
+    const int64_t ld = D.ld;
+    for (int r = 0; r < ROWS; ++r) {
+        const int64_t a = a0 + r;
+        if (a >= D.n_ns) break;
+        const int64_t i0 = lower ? a : 0;
+        for (int64_t i = i0 + tid; i < D.n_ns; i += kThreads) {
+            const double v = (i == a && with_diag) ? D.e[a] : 0.0;
+            if constexpr (CPLX) {
+                reinterpret_cast<double2 *>(D.H)[i + a * ld] = make_double2(v, 0.0);
+            } else {
+                reinterpret_cast<double *>(D.H)[i + a * ld] = v;
+            }
+        }
+    }
+
+    // ---- B elements -------------------------------------------------------
+    const int nvalid = (int)((D.n_ns - a0) < ROWS ? (D.n_ns - a0) : ROWS);
+    for (int64_t b = tid; b < D.n_r; b += kThreads) {
+        const uint64_t ket = D.masks[D.n_ns + b];
+        const int Mb = __popcll(ket);
+        double val[ROWS];
+        switch (Mb) {
+            case 0: row_values<0>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 2: row_values<2>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 4: row_values<4>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 6: row_values<6>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 8: row_values<8>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 10: row_values<10>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            default: row_values<-1>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+        }
+        // B^T part: column a, row n_ns + b  (coalesced along b)
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            if (r >= nvalid) break;
+            const int64_t a = a0 + r;
+            if constexpr (CPLX) {
+                double re, im;
+                phase_mi((s_mbra[r] + Mb) / 2, val[r], re, im);
+                reinterpret_cast<double2 *>(D.H)[D.n_ns + b + a * ld] = make_double2(re, -im);
+            } else {
+                reinterpret_cast<double *>(D.H)[D.n_ns + b + a * ld] = val[r];
+            }
+        }
+        // B part: rows a0..a0+ROWS-1 of column n_ns + b (contiguous per thread)
+        if (!lower) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                if (r >= nvalid) break;
+                const int64_t a = a0 + r;
+                if constexpr (CPLX) {
+                    double re, im;
+                    phase_mi((s_mbra[r] + Mb) / 2, val[r], re, im);
+                    reinterpret_cast<double2 *>(D.H)[a + (D.n_ns + b) * ld] = make_double2(re, im);
+                } else {
+                    reinterpret_cast<double *>(D.H)[a + (D.n_ns + b) * ld] = val[r];
+                }
+            }
+        }
+    }
+}
+
+// R x R block of every sector: zeros and the diagonal (columns n_ns .. n-1).
+template <bool CPLX>
+__global__ void __launch_bounds__(kThreads)
+fill_rr_kernel(const SectorDesc *__restrict__ descs, int nsec, int with_diag, int lower, const int64_t *col_first) {
+    // one workgroup per R column of some sector; col_first = prefix sums of n_r
+    const int64_t col = blockIdx.x;
+    int s = 0;
+    {
+        int lo = 0, hi = nsec - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (col_first[mid] <= col) lo = mid; else hi = mid - 1;
+        }
+        s = lo;
+    }
+    const SectorDesc D = descs[s];
+    const int64_t b = col - col_first[s];
+    if (b >= D.n_r) return;
+    const int64_t j = D.n_ns + b;
+    const int64_t i0 = lower ? j : D.n_ns;
+    for (int64_t i = i0 + threadIdx.x; i < D.n_ns + D.n_r; i += kThreads) {
+        const double v = (i == j && with_diag) ? D.e[j] : 0.0;
+        if constexpr (CPLX) {
+            reinterpret_cast<double2 *>(D.H)[i + j * D.ld] = make_double2(v, 0.0);
+        } else {
+            reinterpret_cast<double *>(D.H)[i + j * D.ld] = v;
+        }
+    }
+}
+
+template <int ROWS, bool CPLX>
+int launch_rows(const SectorDesc *d_desc, int nsec, int64_t nblocks, size_t lds, const Basis *b, double r_max,
+                double scale, int with_diag, int lower, unsigned long long *counters, hipStream_t stream) {
+    auto kern = assemble_rows_kernel<ROWS, CPLX>;
+    if (lds > 65536) TGBA_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kThreads), lds, stream, d_desc, nsec, b->N, b->d_table, r_max,
+                       b->c0, scale, with_diag, lower, counters);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+}  // namespace
+
+// Rows per workgroup as a function of N and the LDS budget (chosen by tuning).
+static int rows_for(int N) { return N <= 48 ? 4 : 2; }
+
+int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, const int64_t *ld, int flags,
+                     hipStream_t stream) {
+    const bool cplx = (flags & TGBA_GAUGE_PAPER) != 0;
+    const int lower = (flags & TGBA_LOWER) ? 1 : 0;
+    const int with_diag = (flags & TGBA_GAMMA1) ? 0 : 1;
+    const double scale = (flags & TGBA_GAMMA1) ? 1.0 : -(double)b->N * b->h_par;
+    const int N = b->N;
+    const int rows = rows_for(N);
+    std::vector<SectorDesc> desc;
+    std::vector<int64_t> colfirst;
+    int64_t nblocks = 0, ncols = 0;
+    int max_m = 0;
+    for (int i = 0; i < nsec; ++i) {
+        const int K = Ks[i];
+        if (K < 0 || K >= N) return set_error(TGBA_EINVAL, "sector index out of range");
+        const Sector &sc = b->sec[K];
+        const int64_t n = sc.n_ns + sc.n_r;
+        if (ld[i] < (n > 0 ? n : 1)) return set_error(TGBA_EINVAL, "leading dimension smaller than the sector size");
+        if (n > 0 && !H[i]) return set_error(TGBA_EINVAL, "NULL output matrix");
+        int mb = 0;
+        for (int64_t a = 0; a < sc.n_ns; ++a) mb = std::max(mb, __builtin_popcountll(sc.masks[a]));
+        if (mb > kGenMax) return set_error(TGBA_EUNSUPPORTED, "bra states with more than 24 quasiparticles");
+        SectorDesc d{};
+        d.masks = sc.d_masks;
+        d.e = sc.d_e;
+        d.H = H[i];
+        d.ld = ld[i];
+        d.n_ns = sc.n_ns;
+        d.n_r = sc.n_r;
+        d.first_block = nblocks;
+        d.max_m_bra = mb;
+        desc.push_back(d);
+        colfirst.push_back(ncols);
+        nblocks += (sc.n_ns + rows - 1) / rows;
+        ncols += sc.n_r;
+        max_m = std::max(max_m, mb);
+    }
+    // R x R blocks may exist even for sectors without NS states
+    const size_t lds = sizeof(double) * ((size_t)rows * N * (N - 1) / 2 + (size_t)(max_m + N) * (max_m + N));
+    // all descriptors with the same LDS layout: pad max_m_bra to the global maximum
+    for (auto &d : desc) d.max_m_bra = max_m;
+    void *ws = nullptr;
+    const size_t desc_bytes = desc.size() * sizeof(SectorDesc);
+    const size_t col_bytes = colfirst.size() * sizeof(int64_t);
+    int rc = workspace_get(desc_bytes + col_bytes + 4 * sizeof(unsigned long long) + 256, 0, &ws);
+    if (rc) return rc;
+    char *base = (char *)ws;
+    SectorDesc *d_desc = (SectorDesc *)base;
+    int64_t *d_col = (int64_t *)(base + desc_bytes);
+    unsigned long long *d_cnt = (unsigned long long *)(base + ((desc_bytes + col_bytes + 63) / 64) * 64);
+    TGBA_HIP(hipMemcpyAsync(d_desc, desc.data(), desc_bytes, hipMemcpyHostToDevice, stream));
+    TGBA_HIP(hipMemcpyAsync(d_col, colfirst.data(), col_bytes, hipMemcpyHostToDevice, stream));
+    // the matrix's absolute scale for the growth check
+    const double r_max = 1.0;  // R entries are O(1): contractions of normalised operators
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, d_cnt, 4);
+    TGBA_HIP(hipGetLastError());
+    if (nblocks > 0) {
+        if (rows == 4) {
+            rc = cplx ? launch_rows<4, true>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream)
+                      : launch_rows<4, false>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream);
+        } else {
+            rc = cplx ? launch_rows<2, true>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream)
+                      : launch_rows<2, false>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream);
+        }
+        if (rc) return rc;
+    }
+    if (ncols > 0) {
+        if (cplx)
+            hipLaunchKernelGGL(fill_rr_kernel<true>, dim3((unsigned)ncols), dim3(kThreads), 0, stream, d_desc, nsec,
+                               with_diag, lower, d_col);
+        else
+            hipLaunchKernelGGL(fill_rr_kernel<false>, dim3((unsigned)ncols), dim3(kThreads), 0, stream, d_desc, nsec,
+                               with_diag, lower, d_col);
+        TGBA_HIP(hipGetLastError());
+    }
+    return TGBA_OK;
+}
+
+}  // namespace tgba
+
+extern "C" int tgba_assemble_heff(const tgba_basis *hb, int K, void *H, int64_t ld, int flags, void *stream) {
+    tgba::clear_error();
+    if (!hb) return tgba::set_error(TGBA_EINVAL, "NULL basis");
+    if (flags & ~(TGBA_GAMMA1 | TGBA_GAUGE_PAPER | TGBA_LOWER)) return tgba::set_error(TGBA_EINVAL, "unknown flags");
+    void *Hs[1] = {H};
+    return tgba::assemble_sectors(&hb->b, 1, &K, Hs, &ld, flags, (hipStream_t)stream);
+}
+
+extern "C" int tgba_assemble_heff_batched(const tgba_basis *hb, int nsec, const int *Ks, void *const *H,
+                                          const int64_t *ld, int flags, void *stream) {
+    tgba::clear_error();
+    if (!hb || nsec < 0 || (nsec > 0 && (!Ks || !H || !ld))) return tgba::set_error(TGBA_EINVAL, "bad arguments");
+    if (flags & ~(TGBA_GAMMA1 | TGBA_GAUGE_PAPER | TGBA_LOWER)) return tgba::set_error(TGBA_EINVAL, "unknown flags");
+    if (nsec == 0) return TGBA_OK;
+    return tgba::assemble_sectors(&hb->b, nsec, Ks, H, ld, flags, (hipStream_t)stream);
+}

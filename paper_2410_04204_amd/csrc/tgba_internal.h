@@ -1,0 +1,64 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tgba.h"
+
+namespace tgba {
+
+// Thread-local last error message; set_error returns the code for chaining.
+int set_error(int code, const std::string &msg);
+void clear_error();
+
+#define TGBA_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::tgba::set_error(TGBA_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kNS = 0, kR = 1;
+constexpr int kMaxN = 64;
+
+struct Sector {
+    std::vector<uint64_t> masks;  // n_ns NS masks then n_r R masks
+    std::vector<double> e;        // E^(0) per state
+    int64_t n_ns = 0, n_r = 0;
+    uint64_t *d_masks = nullptr;  // device copies
+    double *d_e = nullptr;
+};
+
+struct Basis {
+    int N = 0;
+    double h_perp = 0, h_par = 0;
+    int device = 0;
+    double k[2][kMaxN], eps[2][kMaxN], th[2][kMaxN];
+    double evac[2] = {0, 0}, e0 = 0;
+    double c0 = 0;                 // <0_NS|gamma_1|0_R>
+    double table_imag_residual = 0;
+    std::vector<Sector> sec;
+    double *d_table = nullptr;     // real contraction table, 2N x 2N row-major
+    double *d_modes = nullptr;     // device copy of k, theta per sector: [sector][k|th][N]
+};
+
+// basis.cpp
+void mode_tables(int N, double h_perp, double k[2][kMaxN], double eps[2][kMaxN], double th[2][kMaxN]);
+int momentum_index(int N, int sector, uint64_t mask);
+
+// table.hip: real contraction table of the common string and c0.
+int build_contraction_table(Basis *b, hipStream_t stream);
+
+// Device workspace cache (grow-only, per device and slot).
+int workspace_get(size_t bytes, int slot, void **out);
+int release_all_workspace();
+
+}  // namespace tgba
+
+struct tgba_basis {
+    tgba::Basis b;
+};
