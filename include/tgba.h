@@ -131,6 +131,16 @@ int tgba_basis_constants(const tgba_basis *basis, double *c0, double *e_vac_ns, 
  */
 int tgba_basis_gauge(const tgba_basis *basis, int K, int8_t *q);
 
+/*
+ * Diagnostic counters of all assembly calls on this basis so far (host,
+ * synchronises the device): stats[0] rows whose bra elimination grew too much
+ * and were evaluated by direct pivoted elimination; stats[1] elements taken by
+ * the generic pivoted path (more than 10 ket quasiparticles); stats[2]
+ * elements beyond the generic path's 24 quasiparticles (written as 0: any
+ * nonzero value means the result is incomplete).
+ */
+int tgba_basis_stats(const tgba_basis *basis, int64_t *stats);
+
 /* ---- assembly of H_eff (eq. 2, eq. S4, Appendix A) ---------------------- */
 
 #define TGBA_HEFF 0x0        /* H_eff = diag(E^(0)) + V                           */

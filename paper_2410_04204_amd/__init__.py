@@ -82,6 +82,12 @@ class Basis:
         _lib.check(_lib.load().tgba_basis_gauge(self._h, int(K), _lib.ptr(q)))
         return q
 
+    def stats(self):
+        """(flagged rows, generic-path elements, unsupported elements) over all assembly calls."""
+        out = np.zeros(3, dtype=np.int64)
+        _lib.check(_lib.load().tgba_basis_stats(self._h, _lib.ptr(out)))
+        return tuple(int(x) for x in out)
+
     def free(self):
         if getattr(self, "_h", None):
             _lib.load().tgba_basis_free(self._h)

@@ -26,9 +26,9 @@
 //   H = [[diag E_NS, B], [B^T, diag E_R]]   (real gauge, double), or the
 //   complex Hermitian matrix of the paper's gauge (B -> (-i)^{m/2} B).
 // The workgroup writes its NS columns completely (NS x NS zeros + diagonal,
-// B^T part coalesced along b) and, unless TGBA_LOWER, the B part as ROWS
-// consecutive entries per R column.  The R x R block (zeros + diagonal) is
-// written by a separate fill kernel.
+// B^T part coalesced along b), unless TGBA_LOWER the B part as ROWS
+// consecutive entries per R column, and an equal share of the R columns'
+// R x R block (zeros + diagonal): one launch writes the whole matrix.
 #include <cmath>
 #include <cstdio>
 
@@ -44,6 +44,7 @@ struct SectorDesc {
     int64_t ld;
     int64_t n_ns, n_r;
     int64_t first_block;    // first workgroup index of this sector
+    int64_t nblk;           // workgroups of this sector
     int max_m_bra;          // largest M among the sector's NS states
     int pad;
 };
@@ -52,7 +53,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kGenMax = 24;          // largest Pfaffian of the generic path
-constexpr double kGrowthLimit = 1e6; // flag a row when the Schur complement grows beyond this
+constexpr double kGrowthLimit = 1e12; // flag a row whose Schur complement is (near) singular
 
 // ---- small Pfaffians by expansion along the first remaining index ------------
 template <unsigned MASK>
@@ -291,10 +292,6 @@ __device__ __forceinline__ void row_values(double (&val)[ROWS], const double *ta
     }
 }
 
-__global__ void zero_counters_kernel(unsigned long long *c, int n) {
-    if ((int)threadIdx.x < n) c[threadIdx.x] = 0ULL;
-}
-
 template <int ROWS, bool CPLX>
 __global__ void __launch_bounds__(kThreads)
 assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, const double *__restrict__ R,
@@ -435,9 +432,28 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         }
     }
 
+    // ---- this workgroup's share of the R x R block: zeros and the diagonal --
+    {
+        const int64_t w = blockIdx.x - D.first_block;
+        const int64_t per = (D.n_r + D.nblk - 1) / D.nblk;
+        const int64_t c0c = w * per, c1c = (c0c + per < D.n_r) ? c0c + per : D.n_r;
+        for (int64_t bc = c0c; bc < c1c; ++bc) {
+            const int64_t j = D.n_ns + bc;
+            const int64_t i0 = lower ? j : D.n_ns;
+            for (int64_t i = i0 + tid; i < D.n_ns + D.n_r; i += kThreads) {
+                const double v = (i == j && with_diag) ? D.e[j] : 0.0;
+                if constexpr (CPLX) {
+                    reinterpret_cast<double2 *>(D.H)[i + j * ld] = make_double2(v, 0.0);
+                } else {
+                    reinterpret_cast<double *>(D.H)[i + j * ld] = v;
+                }
+            }
+        }
+    }
+
     // ---- B elements -------------------------------------------------------
     const int nvalid = (int)((D.n_ns - a0) < ROWS ? (D.n_ns - a0) : ROWS);
-    for (int64_t b = tid; b < D.n_r; b += kThreads) {
+    for (int64_t b = tid; nvalid > 0 && b < D.n_r; b += kThreads) {
         const uint64_t ket = D.masks[D.n_ns + b];
         const int Mb = __popcll(ket);
         double val[ROWS];
@@ -481,36 +497,6 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     }
 }
 
-// R x R block of every sector: zeros and the diagonal (columns n_ns .. n-1).
-template <bool CPLX>
-__global__ void __launch_bounds__(kThreads)
-fill_rr_kernel(const SectorDesc *__restrict__ descs, int nsec, int with_diag, int lower, const int64_t *col_first) {
-    // one workgroup per R column of some sector; col_first = prefix sums of n_r
-    const int64_t col = blockIdx.x;
-    int s = 0;
-    {
-        int lo = 0, hi = nsec - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (col_first[mid] <= col) lo = mid; else hi = mid - 1;
-        }
-        s = lo;
-    }
-    const SectorDesc D = descs[s];
-    const int64_t b = col - col_first[s];
-    if (b >= D.n_r) return;
-    const int64_t j = D.n_ns + b;
-    const int64_t i0 = lower ? j : D.n_ns;
-    for (int64_t i = i0 + threadIdx.x; i < D.n_ns + D.n_r; i += kThreads) {
-        const double v = (i == j && with_diag) ? D.e[j] : 0.0;
-        if constexpr (CPLX) {
-            reinterpret_cast<double2 *>(D.H)[i + j * D.ld] = make_double2(v, 0.0);
-        } else {
-            reinterpret_cast<double *>(D.H)[i + j * D.ld] = v;
-        }
-    }
-}
-
 template <int ROWS, bool CPLX>
 int launch_rows(const SectorDesc *d_desc, int nsec, int64_t nblocks, size_t lds, const Basis *b, double r_max,
                 double scale, int with_diag, int lower, unsigned long long *counters, hipStream_t stream) {
@@ -536,8 +522,7 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
     const int N = b->N;
     const int rows = rows_for(N);
     std::vector<SectorDesc> desc;
-    std::vector<int64_t> colfirst;
-    int64_t nblocks = 0, ncols = 0;
+    int64_t nblocks = 0;
     int max_m = 0;
     for (int i = 0; i < nsec; ++i) {
         const int K = Ks[i];
@@ -557,11 +542,11 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
         d.n_ns = sc.n_ns;
         d.n_r = sc.n_r;
         d.first_block = nblocks;
+        d.nblk = (sc.n_ns + rows - 1) / rows;
+        if (d.nblk == 0 && sc.n_r > 0) d.nblk = 1;  // R-only sector: one block fills the R x R block
         d.max_m_bra = mb;
         desc.push_back(d);
-        colfirst.push_back(ncols);
-        nblocks += (sc.n_ns + rows - 1) / rows;
-        ncols += sc.n_r;
+        nblocks += d.nblk;
         max_m = std::max(max_m, mb);
     }
     // R x R blocks may exist even for sectors without NS states
@@ -570,19 +555,13 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
     for (auto &d : desc) d.max_m_bra = max_m;
     void *ws = nullptr;
     const size_t desc_bytes = desc.size() * sizeof(SectorDesc);
-    const size_t col_bytes = colfirst.size() * sizeof(int64_t);
-    int rc = workspace_get(desc_bytes + col_bytes + 4 * sizeof(unsigned long long) + 256, 0, &ws);
+    int rc = workspace_get(desc_bytes, 0, &ws);
     if (rc) return rc;
-    char *base = (char *)ws;
-    SectorDesc *d_desc = (SectorDesc *)base;
-    int64_t *d_col = (int64_t *)(base + desc_bytes);
-    unsigned long long *d_cnt = (unsigned long long *)(base + ((desc_bytes + col_bytes + 63) / 64) * 64);
+    SectorDesc *d_desc = (SectorDesc *)ws;
+    unsigned long long *d_cnt = b->d_counters;
     TGBA_HIP(hipMemcpyAsync(d_desc, desc.data(), desc_bytes, hipMemcpyHostToDevice, stream));
-    TGBA_HIP(hipMemcpyAsync(d_col, colfirst.data(), col_bytes, hipMemcpyHostToDevice, stream));
     // the matrix's absolute scale for the growth check
     const double r_max = 1.0;  // R entries are O(1): contractions of normalised operators
-    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, d_cnt, 4);
-    TGBA_HIP(hipGetLastError());
     if (nblocks > 0) {
         if (rows == 4) {
             rc = cplx ? launch_rows<4, true>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream)
@@ -592,15 +571,6 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
                       : launch_rows<2, false>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream);
         }
         if (rc) return rc;
-    }
-    if (ncols > 0) {
-        if (cplx)
-            hipLaunchKernelGGL(fill_rr_kernel<true>, dim3((unsigned)ncols), dim3(kThreads), 0, stream, d_desc, nsec,
-                               with_diag, lower, d_col);
-        else
-            hipLaunchKernelGGL(fill_rr_kernel<false>, dim3((unsigned)ncols), dim3(kThreads), 0, stream, d_desc, nsec,
-                               with_diag, lower, d_col);
-        TGBA_HIP(hipGetLastError());
     }
     return TGBA_OK;
 }

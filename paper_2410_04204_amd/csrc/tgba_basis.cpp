@@ -144,8 +144,10 @@ static void free_device(Basis &b) {
     }
     if (b.d_table) (void)hipFree(b.d_table);
     if (b.d_modes) (void)hipFree(b.d_modes);
+    if (b.d_counters) (void)hipFree(b.d_counters);
     b.d_table = nullptr;
     b.d_modes = nullptr;
+    b.d_counters = nullptr;
 }
 
 }  // namespace tgba
@@ -234,6 +236,12 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
             return set_error(TGBA_EDEVICE, "copy of the basis to the device failed");
         }
     }
+    if (hipMalloc(&b.d_counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(b.d_counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        free_device(b);
+        delete hb;
+        return set_error(TGBA_ENOMEM, "device allocation of the basis counters failed");
+    }
     rc = build_contraction_table(&b, (hipStream_t)stream);
     if (rc) {
         free_device(b);
@@ -282,5 +290,14 @@ extern "C" int tgba_basis_gauge(const tgba_basis *hb, int K, int8_t *q) {
         int v = (i < sc.n_ns) ? -half : half;
         q[i] = (int8_t)(((v % 4) + 4) % 4);
     }
+    return TGBA_OK;
+}
+
+extern "C" int tgba_basis_stats(const tgba_basis *hb, int64_t *stats) {
+    if (!hb || !stats) return set_error(TGBA_EINVAL, "bad basis or output");
+    unsigned long long c[4] = {0, 0, 0, 0};
+    TGBA_HIP(hipDeviceSynchronize());
+    TGBA_HIP(hipMemcpy(c, hb->b.d_counters, sizeof(c), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 3; ++i) stats[i] = (int64_t)c[i];
     return TGBA_OK;
 }

@@ -44,6 +44,7 @@ struct Basis {
     std::vector<Sector> sec;
     double *d_table = nullptr;     // real contraction table, 2N x 2N row-major
     double *d_modes = nullptr;     // device copy of k, theta per sector: [sector][k|th][N]
+    unsigned long long *d_counters = nullptr;  // [flagged rows, generic elements, unsupported elements, -]
 };
 
 // basis.cpp
