@@ -104,8 +104,8 @@ typedef struct tgba_basis tgba_basis;
  * runs on the host; the table is built by a device kernel on `stream`, and
  * the call synchronises that stream before returning.
  * Per sector the basis is listed NS block first, then R block, each ordered by
- * (E^(0), mask); a state is a uint64 mask over its sector's ascending mode
- * table (bit a = mode a).
+ * (M, E^(0), mask) with M the quasiparticle number; a state is a uint64 mask
+ * over its sector's ascending mode table (bit a = mode a).
  * Errors: TGBA_EINVAL (model/trunc), TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC
  * (vacuum-vacuum element |c0| below 1e-12, or the real-gauge check failed).
  */
@@ -181,6 +181,30 @@ int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks,
  * Errors: TGBA_EINVAL, TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC.
  */
 int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags, void *stream);
+
+/*
+ * Several sectors at once (all sectors of a model in one batched pass: the
+ * reduction of every sector advances column by column together).  n, A, lda, w
+ * are host arrays of nsec entries; each sector as in tgba_eig.
+ */
+int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
+                     void *stream);
+
+/*
+ * Stages of tgba_eig, exported for callers that need them separately.
+ * tgba_sytrd: A = Q T Q^T by Householder reflectors of the lower triangle;
+ *   d (n) and e (n-1) receive T, tau (n-1) the reflector scalars; on return
+ *   A[c+1][c] = 1 and A[c+2:, c] hold reflector c (Q = H_0 H_1 ... H_{n-2},
+ *   H_c = I - tau_c v_c v_c^T).  Device arrays.
+ * tgba_stebz: ascending eigenvalues w (n) of the symmetric tridiagonal (d, e)
+ *   by bisection on Sturm counts (device arrays).
+ * tgba_dgemm: C = alpha op(A) op(B) + beta C, column-major device matrices,
+ *   op = transpose when transA/transB != 0 (FP64 matrix cores).
+ */
+int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *e, double *tau, void *stream);
+int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream);
+int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+               const double *B, int64_t ldb, double beta, double *C, int64_t ldc, void *stream);
 
 /* ---- dynamic structure factor at k = 0 (DSF section, eq. 8) -------------- */
 

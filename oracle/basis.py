@@ -15,7 +15,8 @@ Truncation (Method section; DSF section; Appendix B):
 Energies are summed in ascending mode index with libm cosines (``math``),
 so that a C implementation doing the same arithmetic takes exactly the same
 integer decisions (inclusion, order).  Within a sector the kept states are
-listed NS block first, then R block, each ordered by (E^(0), mask).
+listed NS block first, then R block, each ordered by (M, E^(0), mask) -- the
+paper fixes no order; grouping by quasiparticle number M is a convention.
 """
 import math
 import numpy as np
@@ -123,13 +124,13 @@ def build_basis(N, h_perp, e_cut=None, chi=None, m_max=None, e_cut_pool=None):
         if chi is not None:
             c = chi if np.isscalar(chi) else chi[K]
             lst = lst[:c]
-        ns = sorted((e, m) for (e, s, m) in lst if s == model.NS)
-        r = sorted((e, m) for (e, s, m) in lst if s == model.R)
+        ns = sorted((popcount(m), e, m) for (e, s, m) in lst if s == model.NS)
+        r = sorted((popcount(m), e, m) for (e, s, m) in lst if s == model.R)
         out[K] = dict(
-            ns_masks=np.array([m for _, m in ns], dtype=np.uint64),
-            ns_e=np.array([e for e, _ in ns], dtype=np.float64),
-            r_masks=np.array([m for _, m in r], dtype=np.uint64),
-            r_e=np.array([e for e, _ in r], dtype=np.float64),
+            ns_masks=np.array([m for _, _, m in ns], dtype=np.uint64),
+            ns_e=np.array([e for _, e, _ in ns], dtype=np.float64),
+            r_masks=np.array([m for _, _, m in r], dtype=np.uint64),
+            r_e=np.array([e for _, e, _ in r], dtype=np.float64),
         )
     return out
 

@@ -129,6 +129,38 @@ def eig(A, w, flags=TGBA_EIG_FP64, stream=None):
     return w
 
 
+def eig_batched(As, ws, flags=TGBA_EIG_FP64, stream=None):
+    """Eigen-decomposition of several sectors in one batched pass (see eig)."""
+    k = len(As)
+    ns = np.array([w.shape[0] for w in ws], dtype=np.int64)
+    lds = np.array([_ld(A) for A in As], dtype=np.int64)
+    ap = (ctypes.c_void_p * k)(*[A.data_ptr() for A in As])
+    wp = (ctypes.c_void_p * k)(*[w.data_ptr() for w in ws])
+    _lib.check(_lib.load().tgba_eig_batched(k, _lib.ptr(ns), ap, _lib.ptr(lds), wp, int(flags),
+                                            _lib.stream_handle(stream)))
+    return ws
+
+
+def sytrd(A, d, e, tau, stream=None):
+    n = d.shape[0]
+    _lib.check(_lib.load().tgba_sytrd(int(n), _lib.ptr(A), _ld(A), _lib.ptr(d), _lib.ptr(e), _lib.ptr(tau),
+                                      _lib.stream_handle(stream)))
+
+
+def stebz(d, e, w, stream=None):
+    _lib.check(_lib.load().tgba_stebz(int(d.shape[0]), _lib.ptr(d), _lib.ptr(e), _lib.ptr(w),
+                                      _lib.stream_handle(stream)))
+    return w
+
+
+def dgemm(transA, transB, M, N, K, alpha, A, B, beta, C, stream=None):
+    """C = alpha op(A) op(B) + beta C; column-major device matrices stored as (ncols, ld) tensors."""
+    _lib.check(_lib.load().tgba_dgemm(int(transA), int(transB), int(M), int(N), int(K), float(alpha), _lib.ptr(A),
+                                      _ld(A), _lib.ptr(B), _ld(B), float(beta), _lib.ptr(C), _ld(C),
+                                      _lib.stream_handle(stream)))
+    return C
+
+
 def dsf(Z, w, G, N_sites, omega, eta, S, weights=None, stream=None):
     n = w.shape[0]
     _lib.check(_lib.load().tgba_dsf(int(n), _lib.ptr(Z), _ld(Z), _lib.ptr(w), _lib.ptr(G), _ld(G), int(N_sites),

@@ -22,7 +22,8 @@ EXPORTS = [
     "tgba_last_error", "tgba_version", "tgba_build_basis", "tgba_basis_free", "tgba_basis_sector_size",
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
-    "tgba_release_workspace", "tgba_basis_stats",
+    "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
+    "tgba_dgemm",
 ]
 
 
@@ -76,6 +77,11 @@ def load():
     L.tgba_quench_overlaps.argtypes = [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p]
     L.tgba_release_workspace.argtypes = []
     L.tgba_basis_stats.argtypes = [c_void_p, c_void_p]
+    L.tgba_eig_batched.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+    L.tgba_sytrd.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_stebz.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
+                             c_double, c_void_p, c_int64, c_void_p]
     for name in EXPORTS:
         if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free"):
             getattr(L, name).restype = c_int

@@ -30,6 +30,7 @@ SOURCES = {
     "tgba_runtime.cpp": [],
     "tgba_table.hip": [],
     "tgba_assemble.hip": [],
+    "tgba_blas.hip": [],
     "tgba_eig.hip": [],
     "tgba_spectral.hip": [],
 }

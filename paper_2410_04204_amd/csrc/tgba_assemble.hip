@@ -25,12 +25,14 @@
 // Output (column-major, ld): the sector's NS block first, then R block:
 //   H = [[diag E_NS, B], [B^T, diag E_R]]   (real gauge, double), or the
 //   complex Hermitian matrix of the paper's gauge (B -> (-i)^{m/2} B).
-// The workgroup writes its NS columns completely (NS x NS zeros + diagonal,
-// B^T part coalesced along b), unless TGBA_LOWER the B part as ROWS
-// consecutive entries per R column, and an equal share of the R columns'
-// R x R block (zeros + diagonal): one launch writes the whole matrix.
+// The rows kernel writes only coalesced runs: its NS columns (NS x NS zeros
+// + diagonal, and the B^T part along b) and an equal share of the R columns'
+// R x R block (zeros + diagonal) -- everything in the lower triangle.  Unless
+// TGBA_LOWER, a tiled LDS transpose then mirrors B^T into the upper block B
+// (writing B directly from the rows kernel would be ROWS-long strided runs).
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 
 #include "tgba_internal.h"
 
@@ -82,68 +84,35 @@ __device__ __forceinline__ double pf_rec(const double (&a)[10][10]) {
     }
 }
 
-// packed upper-triangular LDS table of an N x N skew matrix:
-// element (u, v), u < v, at rowoff(u) + v with rowoff(u) = u*N - u(u+1)/2 - u - 1
-__device__ __forceinline__ int rowoff(int u, int N) { return u * N - (u * (u + 1)) / 2 - u - 1; }
-
-__device__ __forceinline__ double skew_at(const double *tab, int N, int u, int v) {
-    return (u < v) ? tab[rowoff(u, N) + v] : -tab[rowoff(v, N) + u];
+__device__ __forceinline__ int sector_of(const SectorDesc *d, int nsec, int64_t blk) {
+    int lo = 0, hi = nsec - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].first_block <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
-// Pf(S[idx[0..M)]) for M in {0,2,4,6}; idx ascending; off[i] = rowoff(idx[i]).
-template <int M>
-__device__ __forceinline__ double pf_direct(const double *tab, const int *idx, const int *off) {
-    if constexpr (M == 0) {
-        return 1.0;
-    } else {
-        double a[10][10];
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int j = i + 1; j < M; ++j) a[i][j] = tab[off[i] + idx[j]];
-        return pf_rec<(1u << M) - 1u>(a);
+// quarter-turn phase (-i)^q applied to a real value: returns (re, im)
+__device__ __forceinline__ void phase_mi(int q, double v, double &re, double &im) {
+    switch (q & 3) {
+        case 0: re = v; im = 0.0; break;
+        case 1: re = 0.0; im = -v; break;
+        case 2: re = -v; im = 0.0; break;
+        default: re = 0.0; im = v; break;
     }
 }
 
-// Pf for M in {8, 10}: pivot the first row while gathering, then expand the rest.
-template <int M>
-__device__ __forceinline__ double pf_pivot_expand(const double *tab, int N, const int *idx, const int *off) {
-    double r0[M];
-#pragma unroll
-    for (int j = 1; j < M; ++j) r0[j] = tab[off[0] + idx[j]];
-    int p = 1;
-    double best = fabs(r0[1]);
-#pragma unroll
-    for (int j = 2; j < M; ++j) {
-        double v = fabs(r0[j]);
-        if (v > best) { best = v; p = j; }
-    }
-    if (best == 0.0) return 0.0;
-    double piv = r0[1];
-    int ip = idx[1];
-#pragma unroll
-    for (int j = 2; j < M; ++j)
-        if (p == j) { piv = r0[j]; ip = idx[j]; }
-    // remaining positions t -> original position (t+1 < p ? t+1 : t+2)
-    int ri[M - 2];
-    double y[M - 2], x[M - 2];
-#pragma unroll
-    for (int t = 0; t < M - 2; ++t) {
-        const bool lo = (t + 1 < p);
-        ri[t] = lo ? idx[t + 1] : idx[t + 2];
-        y[t] = lo ? r0[t + 1] : r0[t + 2];
-        x[t] = skew_at(tab, N, ip, ri[t]);
-    }
-    const double inv = 1.0 / piv;
-    double a[10][10];
-#pragma unroll
-    for (int t = 0; t < M - 2; ++t) {
-        const int ot = rowoff(ri[t], N);
-#pragma unroll
-        for (int u = t + 1; u < M - 2; ++u) a[t][u] = tab[ot + ri[u]] + (x[t] * y[u] - y[t] * x[u]) * inv;
-    }
-    const double sgn = (p & 1) ? 1.0 : -1.0;  // (-1)^(p-1)
-    return sgn * piv * pf_rec<(1u << (M - 2)) - 1u>(a);
+// Packed upper-triangular tables of the ROWS per-row Schur complements S_a
+// (N x N, skew) are interleaved in LDS: element (u, v), u < v, of row r sits at
+//     tabs[(rowoff(u) + v) * ROWS + r],   rowoff(u) = u*N - u(u+1)/2 - u - 1,
+// so one address computation serves all rows of the workgroup (the row is an
+// immediate offset of the LDS load).
+__device__ __forceinline__ int rowoff_of(int u, int N) { return u * N - (u * (u + 1)) / 2 - u - 1; }
+
+template <int ROWS>
+__device__ __forceinline__ double skew_at(const double *tabs, const int *s_rowoff, int r, int u, int v) {
+    return (u < v) ? tabs[(s_rowoff[u] + v) * ROWS + r] : -tabs[(s_rowoff[v] + u) * ROWS + r];
 }
 
 // Pfaffian of the M x M skew matrix in A (row-major, ld kGenMax), destroyed.
@@ -181,111 +150,126 @@ __device__ __noinline__ double pf_eliminate(double *A, int M) {
     return pf;
 }
 
-// Generic small-table Pfaffian (packed LDS S_a), any M <= kGenMax.
-__device__ __noinline__ double pf_generic_packed(const double *tab, int N, const int *idx, int M) {
-    double A[kGenMax * kGenMax];
-    for (int i = 0; i < M; ++i) {
-        A[i * kGenMax + i] = 0.0;
-        for (int j = i + 1; j < M; ++j) {
-            double v = tab[rowoff(idx[i], N) + idx[j]];
-            A[i * kGenMax + j] = v;
-            A[j * kGenMax + i] = -v;
-        }
-    }
-    return pf_eliminate(A, M);
-}
-
-// Direct Pf(R[I_a u I_b]) from the global real table (flagged rows).
-__device__ __noinline__ double pf_generic_full(const double *__restrict__ R, int N, uint64_t bra, const int *kidx, int Mb) {
+// Rare paths (private memory): a ket with more than 10 quasiparticles on the
+// row's Schur table, or a flagged row evaluated directly as Pf(R[I_a u I_b]).
+template <int ROWS>
+__device__ __noinline__ double element_generic(const double *tabs, const int *s_rowoff, int r, int N, uint64_t ket,
+                                               int flagged, uint64_t bra, const double *__restrict__ R,
+                                               unsigned long long *counters) {
     int g[kGenMax];
     int M = 0;
-    for (int a = N - 1; a >= 0; --a)
-        if ((bra >> a) & 1ULL) g[M++] = N - 1 - a;
-    for (int j = 0; j < Mb; ++j) g[M++] = N + kidx[j];
+    if (flagged) {
+        for (int a = N - 1; a >= 0; --a)
+            if ((bra >> a) & 1ULL) {
+                if (M == kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
+                g[M++] = N - 1 - a;
+            }
+    }
+    const int mb0 = M;
+    for (int q = 0; q < N; ++q)
+        if ((ket >> q) & 1ULL) {
+            if (M == kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
+            g[M++] = flagged ? N + q : q;
+        }
+    (void)mb0;
     double A[kGenMax * kGenMax];
     const int n2 = 2 * N;
     for (int i = 0; i < M; ++i) {
         A[i * kGenMax + i] = 0.0;
         for (int j = i + 1; j < M; ++j) {
-            double v = R[g[i] * n2 + g[j]];
+            const double v = flagged ? R[g[i] * n2 + g[j]] : tabs[(s_rowoff[g[i]] + g[j]) * ROWS + r];
             A[i * kGenMax + j] = v;
             A[j * kGenMax + i] = -v;
         }
     }
+    if (!flagged) atomicAdd(&counters[1], 1ULL);
     return pf_eliminate(A, M);
 }
 
-__device__ __forceinline__ int sector_of(const SectorDesc *d, int nsec, int64_t blk) {
-    int lo = 0, hi = nsec - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (d[mid].first_block <= blk) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// quarter-turn phase (-i)^q applied to a real value: returns (re, im)
-__device__ __forceinline__ void phase_mi(int q, double v, double &re, double &im) {
-    switch (q & 3) {
-        case 0: re = v; im = 0.0; break;
-        case 1: re = 0.0; im = -v; break;
-        case 2: re = -v; im = 0.0; break;
-        default: re = 0.0; im = v; break;
-    }
-}
-
-// Positions of the set bits of a ket mask, statically indexed (registers).
-template <int M>
-__device__ __forceinline__ void decode_ket(uint64_t x, int N, int (&idx)[M > 0 ? M : 1], int (&off)[M > 0 ? M : 1]) {
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        idx[j] = __ffsll((long long)x) - 1;
-        off[j] = rowoff(idx[j], N);
-        x &= x - 1ULL;
-    }
-}
-
-// Generic path for one element of a flagged row or a large ket (rare): decodes
-// into private memory.
-__device__ __noinline__ double element_generic(const double *tab, int N, uint64_t ket, int flagged, uint64_t bra,
-                                               const double *__restrict__ R, unsigned long long *counters) {
-    int kidx[kGenMax];
-    int m = 0;
-    for (int q = 0; q < N; ++q)
-        if ((ket >> q) & 1ULL) {
-            if (m == kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
-            kidx[m++] = q;
-        }
-    if (flagged) {
-        if (__popcll(bra) + m > kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
-        return pf_generic_full(R, N, bra, kidx, m);
-    }
-    atomicAdd(&counters[1], 1ULL);
-    return pf_generic_packed(tab, N, kidx, m);
-}
-
-// Pf(S_r[I_b]) times the row factor for every valid row r of the workgroup.
+// Pf(S_r[I_b]) * factor_r for all valid rows, for a ket of MB quasiparticles.
 template <int MB, int ROWS>
-__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, int ntab, int N, uint64_t ket,
-                                           int nvalid, const int *s_flag, const uint64_t *s_bra, const double *s_fac,
-                                           const double *__restrict__ R, unsigned long long *counters) {
-    int idx[MB > 0 ? MB : 1], off[MB > 0 ? MB : 1];
-    if constexpr (MB > 0) decode_ket<MB>(ket, N, idx, off);
+__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, const int *s_rowoff, int N,
+                                           uint64_t ket, int nvalid, const int *s_flag, const uint64_t *s_bra,
+                                           const double *s_fac, const double *__restrict__ R,
+                                           unsigned long long *counters) {
+    constexpr int MI = MB > 0 ? MB : 1;
+    int idx[MI], roff[MI];
+    if constexpr (MB > 0) {
+        uint64_t x = ket;
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            idx[j] = __ffsll((long long)x) - 1;
+            roff[j] = s_rowoff[idx[j]];
+            x &= x - 1ULL;
+        }
+    }
+    // bases of the pairs (i, j), i < j, shared by all rows
+    constexpr int NP = (MB >= 2 && MB <= 6) ? MB * (MB - 1) / 2 : ((MB >= 8 && MB <= 10) ? MB - 1 : 1);
+    int base[NP];
+    if constexpr (MB >= 2 && MB <= 6) {
+        int t = 0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < MB; ++j) base[t++] = (roff[i] + idx[j]) * ROWS;
+    } else if constexpr (MB >= 8 && MB <= 10) {
+#pragma unroll
+        for (int j = 1; j < MB; ++j) base[j - 1] = (roff[0] + idx[j]) * ROWS;
+    }
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         double pfv = 0.0;
         if (r < nvalid) {
-            const double *tab = tabs + r * ntab;
             if (MB < 0 || s_flag[r]) {
-                pfv = element_generic(tab, N, ket, s_flag[r], s_bra[r], R, counters);
+                pfv = element_generic<ROWS>(tabs, s_rowoff, r, N, ket, s_flag[r], s_bra[r], R, counters);
             } else if constexpr (MB == 0) {
                 pfv = 1.0;
-            } else if constexpr (MB == 2) {
-                pfv = tab[off[0] + idx[1]];
-            } else if constexpr (MB == 4 || MB == 6) {
-                pfv = pf_direct<MB>(tab, idx, off);
-            } else if constexpr (MB == 8 || MB == 10) {
-                pfv = pf_pivot_expand<MB>(tab, N, idx, off);
+            } else if constexpr (MB >= 2 && MB <= 6) {
+                double a[10][10];
+                int t = 0;
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < MB; ++j) a[i][j] = tabs[base[t++] + r];
+                pfv = pf_rec<(1u << MB) - 1u>(a);
+            } else if constexpr (MB >= 8 && MB <= 10) {
+                // one step of partial pivoting on the first row, then expansion
+                double r0[MB];
+#pragma unroll
+                for (int j = 1; j < MB; ++j) r0[j] = tabs[base[j - 1] + r];
+                int p = 1;
+                double best = fabs(r0[1]);
+#pragma unroll
+                for (int j = 2; j < MB; ++j) {
+                    const double v = fabs(r0[j]);
+                    if (v > best) { best = v; p = j; }
+                }
+                if (best != 0.0) {
+                    double piv = r0[1];
+                    int ip = idx[1];
+#pragma unroll
+                    for (int j = 2; j < MB; ++j)
+                        if (p == j) { piv = r0[j]; ip = idx[j]; }
+                    int ri[MB - 2], ro[MB - 2];
+                    double y[MB - 2], x[MB - 2];
+#pragma unroll
+                    for (int t = 0; t < MB - 2; ++t) {
+                        const bool lo = (t + 1 < p);
+                        ri[t] = lo ? idx[t + 1] : idx[t + 2];
+                        ro[t] = lo ? roff[t + 1] : roff[t + 2];
+                        y[t] = lo ? r0[t + 1] : r0[t + 2];
+                        x[t] = skew_at<ROWS>(tabs, s_rowoff, r, ip, ri[t]);
+                    }
+                    const double inv = 1.0 / piv;
+                    double a[10][10];
+#pragma unroll
+                    for (int t = 0; t < MB - 2; ++t)
+#pragma unroll
+                        for (int u = t + 1; u < MB - 2; ++u)
+                            a[t][u] = tabs[(ro[t] + ri[u]) * ROWS + r] + (x[t] * y[u] - y[t] * x[u]) * inv;
+                    const double sgn = (p & 1) ? 1.0 : -1.0;  // (-1)^(p-1)
+                    pfv = sgn * piv * pf_rec<(1u << (MB - 2)) - 1u>(a);
+                }
             }
         }
         val[r] = s_fac[r] * pfv;
@@ -299,19 +283,22 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
                      unsigned long long *__restrict__ counters) {
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;  // 64 x 4 thread grid for 2D loops
     const int s = sector_of(descs, nsec, blockIdx.x);
     const SectorDesc D = descs[s];
     const int64_t a0 = (int64_t)(blockIdx.x - D.first_block) * ROWS;
     const int ntab = N * (N - 1) / 2;
     const int wdim = D.max_m_bra + N;
-    double *tabs = lds;                          // ROWS packed S_a tables
-    double *W = lds + ROWS * ntab;               // dense scratch wdim x wdim
+    double *tabs = lds;                      // ntab x ROWS interleaved
+    double *W = lds + ROWS * ntab;           // dense scratch wdim x wdim
     __shared__ double s_fac[ROWS];
     __shared__ int s_flag[ROWS], s_mbra[ROWS];
     __shared__ uint64_t s_bra[ROWS];
     __shared__ int s_bidx[kGenMax];
+    __shared__ int s_rowoff[kMaxN];
     __shared__ int s_pp, s_pq;
     __shared__ double s_growth;
+    if (tid < N) s_rowoff[tid] = rowoff_of(tid, N);
 
     // ---- per-row Schur complement over the bra indices -------------------
     for (int r = 0; r < ROWS; ++r) {
@@ -332,11 +319,12 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         }
         __syncthreads();
         const int n = Ma + N;
-        for (int idx = tid; idx < n * n; idx += kThreads) {
-            const int i = idx / n, j = idx % n;
+        for (int i = ty; i < n; i += 4) {
             const int gi = (i < Ma) ? s_bidx[i] : N + (i - Ma);
-            const int gj = (j < Ma) ? s_bidx[j] : N + (j - Ma);
-            W[i * wdim + j] = R[gi * (2 * N) + gj];
+            for (int j = tx; j < n; j += 64) {
+                const int gj = (j < Ma) ? s_bidx[j] : N + (j - Ma);
+                W[i * wdim + j] = R[gi * (2 * N) + gj];
+            }
         }
         __syncthreads();
         double pf = 1.0;
@@ -344,13 +332,11 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             if (tid < 64) {  // complete pivot search over the remaining bra block
                 double best = -1.0;
                 int bp = k, bq = k + 1;
-                const int rem = Ma - k;
-                for (int e = tid; e < rem * rem; e += 64) {
-                    const int i = k + e / rem, j = k + e % rem;
-                    if (j <= i) continue;
-                    const double v = fabs(W[i * wdim + j]);
-                    if (v > best) { best = v; bp = i; bq = j; }
-                }
+                for (int i = k; i < Ma; ++i)
+                    for (int j = i + 1 + tid; j < Ma; j += 64) {
+                        const double v = fabs(W[i * wdim + j]);
+                        if (v > best) { best = v; bp = i; bq = j; }
+                    }
                 for (int off = 32; off > 0; off >>= 1) {
                     const double ob = __shfl_down(best, off, 64);
                     const int op = __shfl_down(bp, off, 64), oq = __shfl_down(bq, off, 64);
@@ -385,27 +371,25 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const double piv = W[k * wdim + k + 1];
             pf *= piv;
             const double inv = (piv != 0.0) ? 1.0 / piv : 0.0;
-            const int t0 = k + 2, nt = n - t0;
-            for (int e = tid; e < nt * nt; e += kThreads) {
-                const int i = t0 + e / nt, j = t0 + e % nt;
-                W[i * wdim + j] += (W[(k + 1) * wdim + i] * W[k * wdim + j] - W[k * wdim + i] * W[(k + 1) * wdim + j]) * inv;
+            for (int i = k + 2 + ty; i < n; i += 4) {
+                const double xi = W[(k + 1) * wdim + i], yi = W[k * wdim + i];
+                for (int j = k + 2 + tx; j < n; j += 64)
+                    W[i * wdim + j] += (xi * W[k * wdim + j] - yi * W[(k + 1) * wdim + j]) * inv;
             }
             __syncthreads();
         }
-        // pack the ket block into the row's table and measure its growth
+        // pack the ket block into the row's interleaved table and measure its growth
         double g = 0.0;
-        double *tab = tabs + r * ntab;
-        for (int e = tid; e < ntab; e += kThreads) {
-            // invert the packed index: row u with rowoff(u)+u+1 <= e < rowoff(u+1)+u+2
-            int u = 0;
-            while (rowoff(u + 1, N) + u + 2 <= e) ++u;
-            const int v = e - rowoff(u, N);
-            const double val = W[(Ma + u) * wdim + Ma + v];
-            tab[e] = val;
-            g = fmax(g, fabs(val));
+        for (int u = ty; u < N; u += 4) {
+            const int ro = s_rowoff[u];
+            for (int v = u + 1 + tx; v < N; v += 64) {
+                const double val = W[(Ma + u) * wdim + Ma + v];
+                tabs[(ro + v) * ROWS + r] = val;
+                g = fmax(g, fabs(val));
+            }
         }
         for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_down(g, off, 64));
-        if ((tid & 63) == 0) atomicMax((unsigned long long *)&s_growth, __double_as_longlong(g));
+        if (tx == 0) atomicMax((unsigned long long *)&s_growth, __double_as_longlong(g));
         __syncthreads();
         if (tid == 0) {
             const bool bad = !(pf != 0.0) || !(s_growth <= kGrowthLimit * r_max) || !isfinite(pf);
@@ -416,11 +400,12 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         __syncthreads();
     }
 
-    // ---- NS columns: zeros of the NS x NS block and the diagonal -----------
     const int64_t ld = D.ld;
-    for (int r = 0; r < ROWS; ++r) {
+    const int nvalid = (int)((D.n_ns - a0) < ROWS ? (D.n_ns - a0) : ROWS);
+
+    // ---- NS columns: zeros of the NS x NS block and the diagonal -----------
+    for (int r = 0; r < nvalid; ++r) {
         const int64_t a = a0 + r;
-        if (a >= D.n_ns) break;
         const int64_t i0 = lower ? a : 0;
         for (int64_t i = i0 + tid; i < D.n_ns; i += kThreads) {
             const double v = (i == a && with_diag) ? D.e[a] : 0.0;
@@ -452,47 +437,67 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     }
 
     // ---- B elements -------------------------------------------------------
-    const int nvalid = (int)((D.n_ns - a0) < ROWS ? (D.n_ns - a0) : ROWS);
+    using T = typename std::conditional<CPLX, double2, double>::type;
+    T *Hb = reinterpret_cast<T *>(D.H);
+    T *colA[ROWS];  // columns a0 + r (B^T part, coalesced along b)
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) colA[r] = Hb + (a0 + r) * ld + D.n_ns;
+    const uint64_t *kmask = D.masks + D.n_ns;
     for (int64_t b = tid; nvalid > 0 && b < D.n_r; b += kThreads) {
-        const uint64_t ket = D.masks[D.n_ns + b];
+        const uint64_t ket = kmask[b];
         const int Mb = __popcll(ket);
         double val[ROWS];
         switch (Mb) {
-            case 0: row_values<0>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 2: row_values<2>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 4: row_values<4>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 6: row_values<6>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 8: row_values<8>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 10: row_values<10>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            default: row_values<-1>(val, tabs, ntab, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 0: row_values<0, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 2: row_values<2, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 4: row_values<4, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 6: row_values<6, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 8: row_values<8, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 10: row_values<10, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            default: row_values<-1, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
         }
-        // B^T part: column a, row n_ns + b  (coalesced along b)
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             if (r >= nvalid) break;
-            const int64_t a = a0 + r;
             if constexpr (CPLX) {
                 double re, im;
                 phase_mi((s_mbra[r] + Mb) / 2, val[r], re, im);
-                reinterpret_cast<double2 *>(D.H)[D.n_ns + b + a * ld] = make_double2(re, -im);
+                colA[r][b] = make_double2(re, -im);
             } else {
-                reinterpret_cast<double *>(D.H)[D.n_ns + b + a * ld] = val[r];
+                colA[r][b] = val[r];
             }
         }
-        // B part: rows a0..a0+ROWS-1 of column n_ns + b (contiguous per thread)
-        if (!lower) {
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                if (r >= nvalid) break;
-                const int64_t a = a0 + r;
-                if constexpr (CPLX) {
-                    double re, im;
-                    phase_mi((s_mbra[r] + Mb) / 2, val[r], re, im);
-                    reinterpret_cast<double2 *>(D.H)[a + (D.n_ns + b) * ld] = make_double2(re, im);
-                } else {
-                    reinterpret_cast<double *>(D.H)[a + (D.n_ns + b) * ld] = val[r];
-                }
-            }
+    }
+}
+
+// Upper block B = (B^T)^H of every sector by 64 x 64 tiles staged in LDS, so
+// that both the read of the B^T block and the write of the B block are
+// coalesced.  Grid: flattened tiles of all sectors (first_block = first tile).
+template <bool CPLX>
+__global__ void __launch_bounds__(kThreads) mirror_upper_kernel(const SectorDesc *__restrict__ descs, int nsec) {
+    using T = typename std::conditional<CPLX, double2, double>::type;
+    __shared__ T tile[64][65];
+    const int s = sector_of(descs, nsec, blockIdx.x);
+    const SectorDesc D = descs[s];
+    const int64_t tiles_b = (D.n_r + 63) / 64;
+    const int64_t t = blockIdx.x - D.first_block;
+    const int64_t ta = t / tiles_b, tb = t % tiles_b;
+    const int64_t a0 = ta * 64, b0 = tb * 64;
+    T *H = reinterpret_cast<T *>(D.H);
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    // read B^T rows n_ns + b0.., columns a0..: element (n_ns + b, a) at H[n_ns + b + a ld]
+    for (int j = ty; j < 64; j += 4) {
+        const int64_t a = a0 + j, b = b0 + tx;
+        if (a < D.n_ns && b < D.n_r) tile[j][tx] = H[D.n_ns + b + a * D.ld];
+    }
+    __syncthreads();
+    // write B: element (a, n_ns + b) at H[a + (n_ns + b) ld]
+    for (int j = ty; j < 64; j += 4) {
+        const int64_t b = b0 + j, a = a0 + tx;
+        if (a < D.n_ns && b < D.n_r) {
+            T v = tile[tx][j];
+            if constexpr (CPLX) v.y = -v.y;
+            H[a + (D.n_ns + b) * D.ld] = v;
         }
     }
 }
@@ -571,6 +576,28 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
                       : launch_rows<2, false>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream);
         }
         if (rc) return rc;
+    }
+    if (!lower) {
+        // second descriptor set: tiles of the B block
+        std::vector<SectorDesc> tdesc = desc;
+        int64_t ntiles = 0;
+        for (auto &d : tdesc) {
+            d.first_block = ntiles;
+            ntiles += ((d.n_ns + 63) / 64) * ((d.n_r + 63) / 64);
+        }
+        if (ntiles > 0) {
+            void *ws2 = nullptr;
+            rc = workspace_get(desc_bytes, 1, &ws2);
+            if (rc) return rc;
+            TGBA_HIP(hipMemcpyAsync(ws2, tdesc.data(), desc_bytes, hipMemcpyHostToDevice, stream));
+            if (cplx)
+                hipLaunchKernelGGL(mirror_upper_kernel<true>, dim3((unsigned)ntiles), dim3(kThreads), 0, stream,
+                                   (const SectorDesc *)ws2, nsec);
+            else
+                hipLaunchKernelGGL(mirror_upper_kernel<false>, dim3((unsigned)ntiles), dim3(kThreads), 0, stream,
+                                   (const SectorDesc *)ws2, nsec);
+            TGBA_HIP(hipGetLastError());
+        }
     }
     return TGBA_OK;
 }

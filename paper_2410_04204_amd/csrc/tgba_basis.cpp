@@ -9,6 +9,8 @@
 //   vacuum, whose product skips k = pi, is annihilated by d_pi]
 // Energies are evaluated with libm in ascending mode order and compared with
 // the same expressions everywhere, so inclusion and order are reproducible.
+// Within a sector the NS block precedes the R block; each block is ordered by
+// (M, E^(0), mask) so that consecutive states share their quasiparticle number.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -204,14 +206,21 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
                 if ((int64_t)c.size() > keep) c.resize(keep);
             }
             Sector &sc = b.sec[K];
-            std::vector<std::pair<double, uint64_t>> ns, r;
-            for (auto &x : c) (x.s == kNS ? ns : r).push_back({x.e, x.mask});
-            std::sort(ns.begin(), ns.end());
-            std::sort(r.begin(), r.end());
+            // each parity block ordered by (M, E^(0), mask): waves see uniform M
+            struct Key { int M; double e; uint64_t mask; };
+            auto less = [](const Key &x, const Key &y) {
+                if (x.M != y.M) return x.M < y.M;
+                if (x.e != y.e) return x.e < y.e;
+                return x.mask < y.mask;
+            };
+            std::vector<Key> ns, r;
+            for (auto &x : c) (x.s == kNS ? ns : r).push_back({__builtin_popcountll(x.mask), x.e, x.mask});
+            std::sort(ns.begin(), ns.end(), less);
+            std::sort(r.begin(), r.end(), less);
             sc.n_ns = (int64_t)ns.size();
             sc.n_r = (int64_t)r.size();
-            for (auto &x : ns) { sc.masks.push_back(x.second); sc.e.push_back(x.first); }
-            for (auto &x : r) { sc.masks.push_back(x.second); sc.e.push_back(x.first); }
+            for (auto &x : ns) { sc.masks.push_back(x.mask); sc.e.push_back(x.e); }
+            for (auto &x : r) { sc.masks.push_back(x.mask); sc.e.push_back(x.e); }
         }
     } catch (const std::bad_alloc &) {
         delete hb;

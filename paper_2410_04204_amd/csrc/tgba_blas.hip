@@ -1,0 +1,162 @@
+// Dense FP64 products on the matrix cores (MFMA f64 16x16x4), batched over
+// descriptors so that the products of several sectors share one launch.
+//
+//   C = alpha op(A) op(B) + beta C     (column-major, op = N or T)
+//
+// Tiles of 128 x 128 per workgroup (4 waves, each a 64 x 64 sub-tile made of
+// 4 x 4 blocks of 16 x 16), K staged through LDS in steps of 16.  Lane layout
+// of v_mfma_f64_16x16x4: operand a of lane l is A[l%16][l/16], operand b is
+// B[l/16][l%16], and the 4 accumulator registers r hold D[4r + l/16][l%16].
+// With `lower` set only tiles touching the lower triangle are computed and
+// only elements with i >= j are written (symmetric rank-k updates).
+#include <cstdint>
+
+#include "tgba_internal.h"
+#include "tgba_blas.h"
+
+namespace tgba {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 128, TN = 128, TK = 16, LDS_STRIDE = TM + 4;
+
+__device__ __forceinline__ int gemm_desc_of(const GemmDesc *d, int nd, int64_t blk) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].first_tile <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
+    __shared__ double As[TK][LDS_STRIDE];  // As[k][i]
+    __shared__ double Bs[TK][LDS_STRIDE];  // Bs[k][j]
+    const GemmDesc G = descs[gemm_desc_of(descs, nd, blockIdx.x)];
+    const int64_t t = blockIdx.x - G.first_tile;
+    int64_t ti, tj;
+    if (G.lower) {  // lower-triangular tile enumeration: t = ti (ti + 1) / 2 + tj, tj <= ti
+        ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = t % G.tiles_m;
+        tj = t / G.tiles_m;
+    }
+    const int64_t m0 = ti * TM, n0 = tj * TN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t k0 = 0; k0 < G.K; k0 += TK) {
+        // op(A)[i][k], i in [m0, m0+128), k in [k0, k0+16): 2048 values, 8 per thread
+        if (!G.transA) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int i = tid & 127, k = (tid >> 7) + 2 * s;
+                const int64_t gi = m0 + i, gk = k0 + k;
+                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gi + gk * G.lda] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = tid & 15, i = (tid >> 4) + 16 * s;
+                const int64_t gi = m0 + i, gk = k0 + k;
+                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gk + gi * G.lda] : 0.0;
+            }
+        }
+        // op(B)[k][j]
+        if (!G.transB) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = tid & 15, j = (tid >> 4) + 16 * s;
+                const int64_t gj = n0 + j, gk = k0 + k;
+                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gk + gj * G.ldb] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int j = tid & 127, k = (tid >> 7) + 2 * s;
+                const int64_t gj = n0 + j, gk = k0 + k;
+                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gj + gk * G.ldb] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 4) {
+            double af[4], bf[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) af[a] = As[kk + (lane >> 4)][64 * wy + 16 * a + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bf[b] = Bs[kk + (lane >> 4)][64 * wx + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // epilogue: D[4r + l/16][l%16] of block (a, b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = m0 + 64 * wy + 16 * a + 4 * r + (lane >> 4);
+                const int64_t j = n0 + 64 * wx + 16 * b + (lane & 15);
+                if (i < G.M && j < G.N && (!G.lower || i >= j)) {
+                    double *c = G.C + i + j * G.ldc;
+                    const double v = G.alpha * acc[a][b][r];
+                    *c = (G.beta == 0.0) ? v : v + G.beta * (*c);
+                }
+            }
+}
+
+}  // namespace
+
+int64_t gemm_tiles(const GemmDesc &g) {
+    const int64_t tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
+    if (g.M <= 0 || g.N <= 0) return 0;
+    if (g.lower) return tm * (tm + 1) / 2;  // square lower: tm == tn
+    return tm * tn;
+}
+
+int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
+    int64_t total = 0;
+    for (auto &g : descs) {
+        g.tiles_m = (g.M + TM - 1) / TM;
+        g.first_tile = total;
+        total += gemm_tiles(g);
+    }
+    if (total == 0) return TGBA_OK;
+    void *ws = nullptr;
+    int rc = workspace_get(descs.size() * sizeof(GemmDesc), slot, &ws);
+    if (rc) return rc;
+    TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(dgemm_kernel, dim3((unsigned)total), dim3(256), 0, stream, (const GemmDesc *)ws, (int)descs.size());
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+}  // namespace tgba
+
+extern "C" int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                          int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc, void *stream) {
+    tgba::clear_error();
+    if (M < 0 || N < 0 || K < 0) return tgba::set_error(TGBA_EINVAL, "negative size");
+    if (M == 0 || N == 0) return TGBA_OK;
+    if (!C || (K > 0 && (!A || !B))) return tgba::set_error(TGBA_EINVAL, "NULL operand");
+    if (ldc < M) return tgba::set_error(TGBA_EINVAL, "bad leading dimension of C");
+    if (K > 0 && (lda < (transA ? K : M) || ldb < (transB ? N : K)))
+        return tgba::set_error(TGBA_EINVAL, "bad leading dimension of A or B");
+    std::vector<tgba::GemmDesc> d(1);
+    d[0] = tgba::GemmDesc{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, transA ? 1 : 0, transB ? 1 : 0, 0, 0, 0};
+    return tgba::dgemm_batched(d, 2, (hipStream_t)stream);
+}

@@ -1,7 +1,489 @@
-// Dense symmetric eigensolver (placeholder until the device solver lands).
+// Dense real symmetric eigensolver for the sector matrices (Method section:
+// the effective Hamiltonian of every symmetry sector is diagonalised).
+//
+// Stage 1  A = Q T Q^T, T tridiagonal: blocked Householder reduction of the
+//          lower triangle (panels of NB columns).  Per column the trailing
+//          symmetric matrix-vector product -- the memory-bound part -- is
+//          spread over every workgroup of every active sector; at the end of a
+//          panel the trailing matrix takes the rank-2NB update
+//          A22 -= V W^T + W V^T on the matrix cores (tgba_blas.hip).
+//          All sectors of a batched call advance column by column together,
+//          so the number of launches follows the largest sector, not the sum.
+// Stage 2  eigenvalues of T by bisection on Sturm counts, one thread per
+//          eigenvalue (all sectors in one launch);
+//          eigenvectors of T by divide and conquer (tgba_dc.hip);
+// Stage 3  Z = Q Z_T by compact-WY blocks of the panel reflectors.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <numeric>
+
+#include "tgba_blas.h"
+#include "tgba_eig.h"
 #include "tgba_internal.h"
 
+namespace tgba {
+namespace {
+
+constexpr int kNB = 64;       // panel width
+constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
+constexpr int kSymvG = 512;   // workgroups per active sector for the symmetric product
+
+// scal layout per sector
+constexpr int S_XN2 = 0, S_ALPHA = 1, S_TAU = 2, S_SCALE = 3, S_DOT = 4, S_T1 = 8, S_T2 = 8 + kNB, S_LEN = 8 + 2 * kNB;
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// K1: apply the panel's previous reflectors to column c, zero the y accumulator,
+//     record d[c], alpha = A[c+1][c], and accumulate |A[c+2:, c]|^2.
+__global__ void __launch_bounds__(256) tri_col_update(TriSec *secs, int c, int i, int j0) {
+    const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
+    TriSec S = secs[s];
+    if (c >= S.n) return;
+    __shared__ double wc[kNB], vc[kNB], red[4];
+    if (threadIdx.x < i) {
+        wc[threadIdx.x] = S.W[c + (int64_t)threadIdx.x * S.ldw];
+        vc[threadIdx.x] = S.A[c + (int64_t)(j0 + threadIdx.x) * S.lda];
+    }
+    if (lb == 0 && threadIdx.x < S_LEN && threadIdx.x >= S_DOT) S.scal[threadIdx.x] = 0.0;  // dot, t1, t2
+    __syncthreads();
+    double ss = 0.0;
+    for (int64_t r = c + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
+        double v = S.A[r + (int64_t)c * S.lda];
+        for (int t = 0; t < i; ++t)
+            v -= S.A[r + (int64_t)(j0 + t) * S.lda] * wc[t] + S.W[r + (int64_t)t * S.ldw] * vc[t];
+        if (i > 0) S.A[r + (int64_t)c * S.lda] = v;
+        if (r == c) S.d[c] = v;
+        if (r == c + 1) S.scal[S_ALPHA] = v;
+        if (r >= c + 2) ss += v * v;
+        if (r >= c + 1) S.W[r + (int64_t)i * S.ldw] = 0.0;
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0 && ss != 0.0) atomicAdd(&S.scal[S_XN2], ss);
+}
+
+// K2: Householder reflector of column c (one thread per sector).
+__global__ void tri_reflector(TriSec *secs, int nsec, int c) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsec) return;
+    TriSec S = secs[s];
+    if (c >= S.n - 1) return;
+    const double xn = sqrt(S.scal[S_XN2]);
+    const double alpha = S.scal[S_ALPHA];
+    double tau = 0.0, beta = alpha, scale = 1.0;
+    if (xn != 0.0) {
+        beta = -copysign(hypot(alpha, xn), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    S.e[c] = beta;
+    S.tau[c] = tau;
+    S.scal[S_TAU] = tau;
+    S.scal[S_SCALE] = scale;
+    S.scal[S_XN2] = 0.0;
+    S.A[c + 1 + (int64_t)c * S.lda] = 1.0;
+}
+
+// K3: y = A22 v (lower-stored trailing matrix, rows/cols c+1..n-1) into W[:, i]
+//     by atomics, and the panel corrections t1 = W^T v, t2 = V^T v.
+//     Work item = (64-column block J, 256-row chunk Q) of the lower triangle.
+__global__ void __launch_bounds__(256) tri_symv(TriSec *secs, int c, int i, int j0) {
+    const int s = blockIdx.x / kSymvG, lb = blockIdx.x % kSymvG;
+    TriSec S = secs[s];
+    const int64_t o = c + 1, n = S.n;
+    if (o >= n) return;
+    const int64_t m = n - o;
+    const int64_t nJ = (m + 63) / 64, nQ = (m + 255) / 256;
+    const double scale = S.scal[S_SCALE];
+    const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+    __shared__ double vcol[64], vrow[256], ypart[4][256];
+    for (int64_t item = lb; item < nJ * nQ; item += kSymvG) {
+        const int64_t J = item % nJ, Q = item / nJ;
+        const int64_t cb = o + 64 * J, rb = o + 256 * Q;
+        if (rb + 255 < cb) continue;  // entirely above the diagonal (uniform branch)
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int64_t cc = cb + threadIdx.x;
+            vcol[threadIdx.x] = (cc >= n) ? 0.0 : (cc == o ? 1.0 : S.A[cc + (int64_t)c * S.lda] * scale);
+        }
+        {
+            const int64_t r = rb + threadIdx.x;
+            vrow[threadIdx.x] = (r >= n) ? 0.0 : (r == o ? 1.0 : S.A[r + (int64_t)c * S.lda] * scale);
+        }
+        __syncthreads();
+        double acc[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+        double yr[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t c0 = cb + 16 * tc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = rb + tr + 64 * q;
+            if (r >= n) continue;
+            const double vr = vrow[tr + 64 * q];
+            const double *col = S.A + r;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int64_t cc = c0 + jj;
+                if (cc < n && r >= cc) {
+                    const double a = col[cc * S.lda];
+                    yr[q] += a * vcol[16 * tc + jj];
+                    if (r > cc) acc[jj] += a * vr;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ypart[tc][tr + 64 * q] = yr[q];
+        // column contributions: reduce over the 64 rows-lanes of this wave
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            double v = acc[jj];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            acc[jj] = v;
+        }
+        if (tr == 0) {
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int64_t cc = c0 + jj;
+                if (cc < n && acc[jj] != 0.0) atomicAdd(&S.W[cc + (int64_t)i * S.ldw], acc[jj]);
+            }
+        }
+        __syncthreads();
+        {
+            const int64_t r = rb + threadIdx.x;
+            if (r < n) {
+                const double y = ypart[0][threadIdx.x] + ypart[1][threadIdx.x] + ypart[2][threadIdx.x] + ypart[3][threadIdx.x];
+                if (y != 0.0) atomicAdd(&S.W[r + (int64_t)i * S.ldw], y);
+            }
+        }
+        // panel corrections from the first column block (covers every row once)
+        if (J == 0 && i > 0) {
+            for (int t = tc; t < i; t += 4) {
+                double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = rb + tr + 64 * q;
+                    if (r < n) {
+                        const double vr = vrow[tr + 64 * q];
+                        p1 += S.W[r + (int64_t)t * S.ldw] * vr;
+                        p2 += S.A[r + (int64_t)(j0 + t) * S.lda] * vr;
+                    }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    p1 += __shfl_down(p1, off, 64);
+                    p2 += __shfl_down(p2, off, 64);
+                }
+                if (tr == 0) {
+                    atomicAdd(&S.scal[S_T1 + t], p1);
+                    atomicAdd(&S.scal[S_T2 + t], p2);
+                }
+            }
+        }
+    }
+}
+
+// K4: w = tau (y - V t1 - W t2), write back the scaled reflector, dot(w, v).
+__global__ void __launch_bounds__(256) tri_w(TriSec *secs, int c, int i, int j0) {
+    const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
+    TriSec S = secs[s];
+    if (c + 1 >= S.n) return;
+    __shared__ double t1[kNB], t2[kNB], red[4];
+    if (threadIdx.x < i) {
+        t1[threadIdx.x] = S.scal[S_T1 + threadIdx.x];
+        t2[threadIdx.x] = S.scal[S_T2 + threadIdx.x];
+    }
+    __syncthreads();
+    const double tau = S.scal[S_TAU], scale = S.scal[S_SCALE];
+    double dot = 0.0;
+    for (int64_t r = c + 1 + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
+        double y = S.W[r + (int64_t)i * S.ldw];
+        for (int t = 0; t < i; ++t) y -= S.A[r + (int64_t)(j0 + t) * S.lda] * t1[t] + S.W[r + (int64_t)t * S.ldw] * t2[t];
+        const double w = tau * y;
+        double v = 1.0;
+        if (r >= c + 2) {
+            v = S.A[r + (int64_t)c * S.lda] * scale;
+            S.A[r + (int64_t)c * S.lda] = v;
+        }
+        S.W[r + (int64_t)i * S.ldw] = w;
+        dot += w * v;
+    }
+    dot = block_sum(dot, red);
+    if (threadIdx.x == 0 && dot != 0.0) atomicAdd(&S.scal[S_DOT], dot);
+}
+
+// K5: w += alpha2 v, alpha2 = -tau/2 (w . v).
+__global__ void __launch_bounds__(256) tri_finish(TriSec *secs, int c, int i) {
+    const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
+    TriSec S = secs[s];
+    if (c + 1 >= S.n) return;
+    const double alpha2 = -0.5 * S.scal[S_TAU] * S.scal[S_DOT];
+    for (int64_t r = c + 1 + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
+        const double v = (r == c + 1) ? 1.0 : S.A[r + (int64_t)c * S.lda];
+        S.W[r + (int64_t)i * S.ldw] += alpha2 * v;
+    }
+}
+
+__global__ void zero_kernel(double *p, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0.0;
+}
+
+// ---- bisection on Sturm counts (one thread per eigenvalue) ----------------
+struct BisSec {
+    const double *d, *e;  // diagonal (n), off-diagonal (n-1)
+    double *w;            // eigenvalues out (n)
+    int64_t n;
+    int64_t first;        // first global thread of this sector
+};
+
+__device__ __forceinline__ int64_t sturm_count(const double *d, const double *e, int64_t n, double x, double pivmin) {
+    int64_t cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+    for (int64_t k = 1; k < n; ++k) {
+        q = d[k] - x - e[k - 1] * e[k - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0);
+    }
+    return cnt;
+}
+
+__global__ void __launch_bounds__(256) bisect_kernel(const BisSec *secs, int nsec, const double *bounds) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int lo_s = 0, hi_s = nsec - 1;
+    while (lo_s < hi_s) {
+        int mid = (lo_s + hi_s + 1) >> 1;
+        if (secs[mid].first <= g) lo_s = mid; else hi_s = mid - 1;
+    }
+    const BisSec S = secs[lo_s];
+    const int64_t k = g - S.first;
+    if (k < 0 || k >= S.n) return;
+    double lo = bounds[3 * lo_s], hi = bounds[3 * lo_s + 1];
+    const double pivmin = bounds[3 * lo_s + 2];
+    // invariant: count(lo) <= k < count(hi)
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        if (sturm_count(S.d, S.e, S.n, mid, pivmin) > k) hi = mid; else lo = mid;
+    }
+    S.w[k] = 0.5 * (lo + hi);
+}
+
+// Gershgorin interval and pivmin per sector (one workgroup per sector).
+__global__ void __launch_bounds__(256) gersh_kernel(const BisSec *secs, double *bounds) {
+    const BisSec S = secs[blockIdx.x];
+    __shared__ double rlo[256], rhi[256], rmx[256];
+    double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
+    for (int64_t k = threadIdx.x; k < S.n; k += 256) {
+        const double el = (k > 0) ? fabs(S.e[k - 1]) : 0.0, er = (k + 1 < S.n) ? fabs(S.e[k]) : 0.0;
+        lo = fmin(lo, S.d[k] - el - er);
+        hi = fmax(hi, S.d[k] + el + er);
+        if (k + 1 < S.n) emax = fmax(emax, S.e[k] * S.e[k]);
+    }
+    rlo[threadIdx.x] = lo; rhi[threadIdx.x] = hi; rmx[threadIdx.x] = emax;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            rlo[threadIdx.x] = fmin(rlo[threadIdx.x], rlo[threadIdx.x + off]);
+            rhi[threadIdx.x] = fmax(rhi[threadIdx.x], rhi[threadIdx.x + off]);
+            rmx[threadIdx.x] = fmax(rmx[threadIdx.x], rmx[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double span = fmax(fabs(rlo[0]), fabs(rhi[0]));
+        const double pivmin = DBL_MIN * fmax(1.0, rmx[0]);
+        const double pad = 2.0 * DBL_EPSILON * span * (double)S.n + 2.0 * pivmin;
+        bounds[3 * blockIdx.x] = rlo[0] - pad;
+        bounds[3 * blockIdx.x + 1] = rhi[0] + pad;
+        bounds[3 * blockIdx.x + 2] = pivmin;
+    }
+}
+
+}  // namespace
+
+// ---- host drivers -------------------------------------------------------------
+
+int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
+    const int nsec = (int)secs.size();
+    if (nsec == 0) return TGBA_OK;
+    // sectors sorted by size, largest first: the active ones are always a prefix
+    std::vector<int> order(nsec);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return secs[a].n > secs[b].n; });
+    std::vector<TriSec> sorted(nsec);
+    for (int k = 0; k < nsec; ++k) sorted[k] = secs[order[k]];
+    void *ws = nullptr;
+    int rc = workspace_get(nsec * sizeof(TriSec), 3, &ws);
+    if (rc) return rc;
+    TriSec *d_secs = (TriSec *)ws;
+    TGBA_HIP(hipMemcpyAsync(d_secs, sorted.data(), nsec * sizeof(TriSec), hipMemcpyHostToDevice, stream));
+    for (auto &S : sorted) {
+        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, stream, S.scal, (int64_t)S_LEN);
+        TGBA_HIP(hipGetLastError());
+    }
+    const int64_t nmax = sorted[0].n;
+    auto active = [&](int64_t c) {  // sectors with c < n
+        int a = 0;
+        while (a < nsec && sorted[a].n > c) ++a;
+        return a;
+    };
+    for (int64_t j0 = 0; j0 < nmax; j0 += kNB) {
+        const int nb = (int)std::min<int64_t>(kNB, nmax - j0);
+        for (int i = 0; i < nb; ++i) {
+            const int64_t c = j0 + i;
+            const int act = active(c);
+            if (act == 0) break;
+            hipLaunchKernelGGL(tri_col_update, dim3(act * kG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+            const int actr = active(c + 1);  // sectors that need a reflector at column c
+            if (actr > 0) {
+                hipLaunchKernelGGL(tri_reflector, dim3((actr + 63) / 64), dim3(64), 0, stream, d_secs, actr, (int)c);
+                hipLaunchKernelGGL(tri_symv, dim3(actr * kSymvG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+                hipLaunchKernelGGL(tri_w, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+                hipLaunchKernelGGL(tri_finish, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i);
+            }
+            TGBA_HIP(hipGetLastError());
+        }
+        // trailing update A22 -= V W^T + W V^T for sectors extending beyond the panel
+        const int64_t t0 = j0 + nb;
+        std::vector<GemmDesc> g1, g2;
+        for (auto &S : sorted) {
+            if (S.n <= t0) continue;
+            const int64_t m = S.n - t0;
+            double *C = S.A + t0 + t0 * S.lda;
+            const double *V = S.A + t0 + j0 * S.lda;
+            const double *Wm = S.W + t0;
+            g1.push_back(GemmDesc{V, S.lda, Wm, S.ldw, C, S.lda, m, m, nb, -1.0, 1.0, 0, 1, 1, 0, 0, 0});
+            g2.push_back(GemmDesc{Wm, S.ldw, V, S.lda, C, S.lda, m, m, nb, -1.0, 1.0, 0, 1, 1, 0, 0, 0});
+        }
+        if (!g1.empty()) {
+            rc = dgemm_batched(g1, 4, stream);
+            if (rc) return rc;
+            rc = dgemm_batched(g2, 5, stream);
+            if (rc) return rc;
+        }
+    }
+    return TGBA_OK;
+}
+
+int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
+    const int nsec = (int)in.size();
+    if (nsec == 0) return TGBA_OK;
+    std::vector<BisSec> secs(nsec);
+    int64_t total = 0;
+    for (int k = 0; k < nsec; ++k) {
+        secs[k] = BisSec{in[k].d, in[k].e, in[k].w, in[k].n, total};
+        total += in[k].n;
+    }
+    void *ws = nullptr;
+    int rc = workspace_get(nsec * sizeof(BisSec) + nsec * 3 * sizeof(double) + 64, 6, &ws);
+    if (rc) return rc;
+    BisSec *d_secs = (BisSec *)ws;
+    double *bounds = (double *)((char *)ws + ((nsec * sizeof(BisSec) + 63) / 64) * 64);
+    TGBA_HIP(hipMemcpyAsync(d_secs, secs.data(), nsec * sizeof(BisSec), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(gersh_kernel, dim3(nsec), dim3(256), 0, stream, d_secs, bounds);
+    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, d_secs, nsec, bounds);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+}  // namespace tgba
+
+using namespace tgba;
+
+extern "C" int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *e, double *tau, void *stream) {
+    clear_error();
+    if (n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && (!A || !d || !e || !tau)))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    if (n == 0) return TGBA_OK;
+    hipStream_t st = (hipStream_t)stream;
+    void *ws = nullptr;
+    const size_t wbytes = sizeof(double) * ((size_t)n * kNB + S_LEN + 64);
+    int rc = workspace_get(wbytes, 7, &ws);
+    if (rc) return rc;
+    std::vector<TriSec> secs(1);
+    secs[0] = TriSec{A, lda, n, d, e, tau, (double *)ws + S_LEN + 64, n, (double *)ws};
+    return sytrd_batched(secs, st);
+}
+
+extern "C" int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!d || !w)) || (n > 1 && !e)) return set_error(TGBA_EINVAL, "bad arguments");
+    if (n == 0) return TGBA_OK;
+    std::vector<BisIn> in(1);
+    in[0] = BisIn{d, e, w, n};
+    return stebz_batched(in, (hipStream_t)stream);
+}
+
+// ---- public eigensolver calls --------------------------------------------------
+
+namespace tgba {
+
+// Eigen-decomposition of several sectors.  Eigenvalues only for now unless the
+// divide-and-conquer stage is available (stedc_and_backtransform).
+int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
+                hipStream_t stream) {
+    const bool novec = (flags & TGBA_EIG_NOVEC) != 0;
+    size_t total = 0;
+    for (int k = 0; k < nsec; ++k) {
+        if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
+            return set_error(TGBA_EINVAL, "bad eigensolver arguments");
+        total += (size_t)S_LEN + 64 + (size_t)n[k] * (kNB + 3);
+    }
+    void *ws = nullptr;
+    int rc = workspace_get(total * sizeof(double), 7, &ws);
+    if (rc) return rc;
+    double *p = (double *)ws;
+    std::vector<TriSec> secs;
+    std::vector<BisIn> bis;
+    for (int k = 0; k < nsec; ++k) {
+        if (n[k] == 0) continue;
+        TriSec S;
+        S.scal = p; p += S_LEN + 64;
+        S.W = p; p += n[k] * kNB;
+        S.d = p; p += n[k];
+        S.e = p; p += n[k];
+        S.tau = p; p += n[k];
+        S.A = A[k]; S.lda = lda[k]; S.n = n[k]; S.ldw = n[k];
+        secs.push_back(S);
+        bis.push_back(BisIn{S.d, S.e, w[k], n[k]});
+    }
+    rc = sytrd_batched(secs, stream);
+    if (rc) return rc;
+    if (novec) {
+        rc = stebz_batched(bis, stream);
+        if (rc) return rc;
+        TGBA_HIP(hipStreamSynchronize(stream));
+        return TGBA_OK;
+    }
+    return set_error(TGBA_EUNSUPPORTED, "eigenvectors need the divide-and-conquer stage (not built yet)");
+}
+
+}  // namespace tgba
+
 extern "C" int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags, void *stream) {
-    (void)n; (void)A; (void)lda; (void)w; (void)flags; (void)stream;
-    return tgba::set_error(TGBA_EUNSUPPORTED, "tgba_eig is not built yet");
+    clear_error();
+    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC)) return set_error(TGBA_EINVAL, "unknown flags");
+    double *As[1] = {A};
+    double *ws[1] = {w};
+    return eig_batched(1, &n, As, &lda, ws, flags, (hipStream_t)stream);
+}
+
+extern "C" int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,
+                                int flags, void *stream) {
+    clear_error();
+    if (nsec < 0 || (nsec > 0 && (!n || !A || !lda || !w))) return set_error(TGBA_EINVAL, "bad arguments");
+    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC)) return set_error(TGBA_EINVAL, "unknown flags");
+    return eig_batched(nsec, n, A, lda, w, flags, (hipStream_t)stream);
 }
