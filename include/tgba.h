@@ -203,6 +203,10 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
  */
 int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *e, double *tau, void *stream);
 int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream);
+/* tgba_stedc: eigenvalues (into d, ascending) and eigenvectors Z (n x n, ldz)
+ *   of the symmetric tridiagonal (d, e) by divide and conquer (device arrays;
+ *   e is not modified). */
+int tgba_stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *stream);
 int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
                const double *B, int64_t ldb, double beta, double *C, int64_t ldc, void *stream);
 

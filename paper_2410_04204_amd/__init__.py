@@ -153,6 +153,13 @@ def stebz(d, e, w, stream=None):
     return w
 
 
+def stedc(d, e, Z, stream=None):
+    """Eigenvalues (into d) and eigenvectors Z of the tridiagonal (d, e) by divide and conquer."""
+    _lib.check(_lib.load().tgba_stedc(int(d.shape[0]), _lib.ptr(d), _lib.ptr(e), _lib.ptr(Z), _ld(Z),
+                                      _lib.stream_handle(stream)))
+    return d
+
+
 def dgemm(transA, transB, M, N, K, alpha, A, B, beta, C, stream=None):
     """C = alpha op(A) op(B) + beta C; column-major device matrices stored as (ncols, ld) tensors."""
     _lib.check(_lib.load().tgba_dgemm(int(transA), int(transB), int(M), int(N), int(K), float(alpha), _lib.ptr(A),

@@ -23,7 +23,7 @@ EXPORTS = [
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
-    "tgba_dgemm",
+    "tgba_dgemm", "tgba_stedc",
 ]
 
 
@@ -80,6 +80,7 @@ def load():
     L.tgba_eig_batched.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
     L.tgba_sytrd.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     L.tgba_stebz.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_stedc.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]
     L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
                              c_double, c_void_p, c_int64, c_void_p]
     for name in EXPORTS:

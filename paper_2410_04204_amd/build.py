@@ -32,6 +32,7 @@ SOURCES = {
     "tgba_assemble.hip": [],
     "tgba_blas.hip": [],
     "tgba_eig.hip": [],
+    "tgba_dc.hip": [],
     "tgba_spectral.hip": [],
 }
 

@@ -29,5 +29,7 @@ struct BisIn {
 
 int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream);
 int stebz_batched(std::vector<BisIn> &in, hipStream_t stream);
+int ormtr(int64_t n, const double *A, int64_t lda, const double *tau, double *Z, int64_t ldz, double *scratch,
+          hipStream_t stream);
 
 }  // namespace tgba

@@ -19,6 +19,7 @@
 #include <numeric>
 
 #include "tgba_blas.h"
+#include "tgba_dc.h"
 #include "tgba_eig.h"
 #include "tgba_internal.h"
 
@@ -311,6 +312,55 @@ __global__ void __launch_bounds__(256) gersh_kernel(const BisSec *secs, double *
     }
 }
 
+
+// ---- back-transform Z <- Q Z with Q = H_0 ... H_{n-2} ------------------------
+
+// V (m x nbp, ld m) of panel columns j0..j0+nbp-1: row r <-> global row j0+1+r,
+// explicit zeros above the unit diagonal entry of each reflector.
+__global__ void extract_v_kernel(const double *A, int64_t lda, int64_t n, int64_t j0, int nbp, double *V) {
+    const int64_t m = n - j0 - 1;
+    const int64_t tot = m * nbp;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = k % m, t = k / m;
+        const int64_t R = j0 + 1 + r, c = j0 + t;
+        V[r + t * m] = (R < c + 1) ? 0.0 : ((R == c + 1) ? 1.0 : A[R + c * lda]);
+    }
+}
+
+// Upper triangular T of the compact WY form I - V T V^T of H_j0 ... H_j0+nbp-1
+// (forward, columnwise): T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) (V^T V)(0:i, i).
+__global__ void larft_kernel(const double *Sg, const double *tau, int nbp, double *T) {
+    __shared__ double Tl[64][65];
+    __shared__ double col[64];
+    const int j = threadIdx.x;
+    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < nbp; ++i) {
+        const double ti = tau[i];
+        if (j < i) {
+            double acc = 0.0;
+            for (int l = j; l < i; ++l) acc += Tl[j][l] * Sg[l + i * nbp];
+            col[j] = -ti * acc;
+        }
+        __syncthreads();
+        if (j < i) Tl[j][i] = col[j];
+        if (j == i) Tl[i][i] = ti;
+        __syncthreads();
+    }
+    for (int k = j; k < nbp * nbp; k += blockDim.x) {
+        const int r = k % nbp, c = k / nbp;
+        T[r + c * nbp] = Tl[r][c];
+    }
+}
+
+__global__ void copy_matrix_kernel(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m, int64_t n) {
+    const int64_t tot = m * n;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = k % m, j = k / m;
+        dst[i + j * ldd] = src[i + j * lds];
+    }
+}
+
 }  // namespace
 
 // ---- host drivers -------------------------------------------------------------
@@ -373,6 +423,45 @@ int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
             rc = dgemm_batched(g2, 5, stream);
             if (rc) return rc;
         }
+    }
+    return TGBA_OK;
+}
+
+
+// Z (n x n, ldz) <- Q Z with the reflectors of tgba_sytrd stored in A.
+// scratch: n*64 (V) + 3 n*64 (W1, W2) + 2*64*64 (S, T) doubles.
+int ormtr(int64_t n, const double *A, int64_t lda, const double *tau, double *Z, int64_t ldz, double *scratch,
+          hipStream_t stream) {
+    if (n < 2) return TGBA_OK;
+    double *V = scratch;
+    double *W1 = V + (size_t)n * kNB;
+    double *W2 = W1 + (size_t)n * kNB;
+    double *Sg = W2 + (size_t)n * kNB;
+    double *T = Sg + kNB * kNB;
+    const int64_t nref = n - 1;
+    const int64_t npan = (nref + kNB - 1) / kNB;
+    for (int64_t p = npan - 1; p >= 0; --p) {
+        const int64_t j0 = p * kNB;
+        const int nbp = (int)std::min<int64_t>(kNB, nref - j0);
+        const int64_t m = n - j0 - 1;
+        hipLaunchKernelGGL(extract_v_kernel, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nbp, V);
+        TGBA_HIP(hipGetLastError());
+        std::vector<GemmDesc> g(1);
+        g[0] = GemmDesc{V, m, V, m, Sg, nbp, nbp, nbp, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+        int rc = dgemm_batched(g, 11, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, T);
+        TGBA_HIP(hipGetLastError());
+        double *Zs = Z + (j0 + 1);
+        g[0] = GemmDesc{V, m, Zs, ldz, W1, nbp, nbp, n, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+        rc = dgemm_batched(g, 12, stream);
+        if (rc) return rc;
+        g[0] = GemmDesc{T, nbp, W1, nbp, W2, nbp, nbp, n, nbp, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+        rc = dgemm_batched(g, 13, stream);
+        if (rc) return rc;
+        g[0] = GemmDesc{V, m, W2, nbp, Zs, ldz, m, n, nbp, -1.0, 1.0, 0, 0, 0, 0, 0, 0};
+        rc = dgemm_batched(g, 14, stream);
+        if (rc) return rc;
     }
     return TGBA_OK;
 }
@@ -467,7 +556,26 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         TGBA_HIP(hipStreamSynchronize(stream));
         return TGBA_OK;
     }
-    return set_error(TGBA_EUNSUPPORTED, "eigenvectors need the divide-and-conquer stage (not built yet)");
+    // eigenvectors: divide and conquer on T, then the back-transform, per sector
+    for (size_t k = 0; k < secs.size(); ++k) {
+        TriSec &S = secs[k];
+        const int64_t nn = S.n;
+        void *zw = nullptr;
+        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + (size_t)nn * kNB + 3 * (size_t)nn * kNB + 2 * kNB * kNB + 1024);
+        rc = workspace_get(zbytes, 10, &zw);
+        if (rc) return rc;
+        double *Zt = (double *)zw;
+        double *scratch = Zt + (size_t)nn * nn;
+        rc = stedc(nn, S.d, S.e, Zt, nn, stream);
+        if (rc) return rc;
+        rc = ormtr(nn, S.A, S.lda, S.tau, Zt, nn, scratch, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(copy_matrix_kernel, dim3(4096), dim3(256), 0, stream, Zt, nn, S.A, S.lda, nn, nn);
+        TGBA_HIP(hipMemcpyAsync(bis[k].w, S.d, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        TGBA_HIP(hipGetLastError());
+    }
+    TGBA_HIP(hipStreamSynchronize(stream));
+    return TGBA_OK;
 }
 
 }  // namespace tgba

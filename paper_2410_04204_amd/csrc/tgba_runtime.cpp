@@ -7,7 +7,7 @@
 
 namespace tgba {
 namespace {
-constexpr int kSlots = 8;
+constexpr int kSlots = 32;
 constexpr int kDevices = 16;
 struct Buf {
     void *p = nullptr;

@@ -111,3 +111,84 @@ def test_eig_novec_n24_dsf_k0_full_size():
     ref = scipy.linalg.eigvalsh(Hn, driver="evd")
     print(f"n={n} max err {np.abs(wv.cpu().numpy() - ref).max():.3e}", flush=True)
     assert np.abs(wv.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def _tridiag(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        return rng.normal(size=n), rng.normal(size=max(n - 1, 0))
+    if kind == "split":  # zero couplings: exact deflation
+        e = rng.normal(size=max(n - 1, 0))
+        e[::7] = 0.0
+        return rng.normal(size=n), e
+    if kind == "cluster":  # tight clusters of equal diagonal values
+        return np.repeat(rng.normal(size=(n + 9) // 10), 10)[:n], 1e-9 * rng.normal(size=max(n - 1, 0))
+    if kind == "wilkinson":
+        m = (n - 1) / 2.0
+        return np.abs(np.arange(n) - m), np.ones(max(n - 1, 0))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["random", "split", "cluster", "wilkinson"])
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 101, 1000, 2500])
+def test_divide_and_conquer_tridiagonal(kind, n):
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    d, e = _tridiag(kind, n, n + len(kind))
+    dd = torch.as_tensor(d.copy(), device="cuda")
+    de = torch.as_tensor(e.copy() if n > 1 else np.zeros(1), device="cuda")
+    Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    tg.stedc(dd, de, Z)
+    torch.cuda.synchronize()
+    w = dd.cpu().numpy()
+    Zn = Z.cpu().numpy().T
+    T = np.diag(d) + (np.diag(e, 1) + np.diag(e, -1) if n > 1 else 0)
+    nrm = max(1.0, np.abs(np.linalg.eigvalsh(T)).max())
+    ref = np.linalg.eigvalsh(T)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - ref).max() <= 1e-12 * nrm * max(1, np.sqrt(n))
+    assert np.abs(T @ Zn - Zn * w).max() <= 1e-12 * nrm * max(1, np.sqrt(n))
+    assert np.abs(Zn.T @ Zn - np.eye(n)).max() <= 1e-12 * max(1, np.sqrt(n))
+
+
+@pytest.mark.parametrize("n", [1, 2, 65, 500, 2049])
+def test_eig_with_vectors_random(n):
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    A = _rand_sym(n, 3 * n)
+    dA = _cm(A)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg.eig(dA, w)
+    torch.cuda.synchronize()
+    Z = _np(dA)
+    wn = w.cpu().numpy()
+    ref = scipy.linalg.eigvalsh(A)
+    nrm = max(1.0, np.abs(ref).max())
+    assert np.abs(wn - ref).max() <= 1e-12 * nrm * np.sqrt(n)
+    assert np.abs(A @ Z - Z * wn).max() <= 1e-12 * nrm * np.sqrt(n)
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-12 * np.sqrt(n)
+
+
+def test_eig_with_vectors_heff_n24_k0():
+    """Full-size K = 0 sector of the N = 24 workload: eigenpairs against LAPACK."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    w = workloads.WORKLOADS["n24_dsf"]
+    B = tg.Basis(w["N"], w["h_perp"], w["h_par"], e_cut=w["e_cut"])
+    n = sum(B.sector_size(0))
+    H = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    tg.assemble_heff(B, 0, H, tg.TGBA_HEFF)
+    Hn = H.cpu().numpy().T.copy()
+    wv = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg.eig(H, wv)
+    torch.cuda.synchronize()
+    ref = scipy.linalg.eigvalsh(Hn, driver="evd")
+    wn = wv.cpu().numpy()
+    Z = H.cpu().numpy().T
+    nrm = np.abs(ref).max()
+    print(f"n={n} eig err {np.abs(wn - ref).max():.2e}", flush=True)
+    assert np.abs(wn - ref).max() <= 1e-10 * nrm
+    R = Hn @ Z - Z * wn
+    print(f"residual {np.abs(R).max():.2e} orth {np.abs(Z.T @ Z - np.eye(n)).max():.2e}", flush=True)
+    assert np.abs(R).max() <= 1e-10 * nrm
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-10
