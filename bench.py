@@ -10,8 +10,8 @@ that input, with the basis (host enumeration + contraction table) resident:
   2. eigen-decomposition of every sector (eigenvalues; eigenvectors of K = 0);
   3. gamma_1 matrix of K = 0 and the dynamic structure factor S(0, omega) on
      4096 frequencies;
-  4. quench from the K = 0 ground state of H0: <sigma^x>(t) on 1001 times.
-Stages that are not built yet are listed in "stages_missing" and skipped.
+  4. quench from the K = 0 ground state of H0: <sigma^x>(t) on 1001 times
+     (t = 0 .. 50, dt = 0.05).
 
 Prints ONE JSON line.  `value` = H_eff elements (sum_K chi_NS chi_R) per second
 of the whole step; per-stage times, the assembly roofline and the oracle's CPU
@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=2)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="n40_batched")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -83,31 +83,58 @@ def main():
     n = [a_ + b_ for a_, b_ in sizes]
     elements = int(sum(a_ * b_ for a_, b_ in sizes))
     Hs = [torch.empty((n[K], n[K]), dtype=torch.float64, device=dev) for K in range(N)]
+    ws = [torch.empty(n[K], dtype=torch.float64, device=dev) for K in range(N)]
     Ks = list(range(N))
-    stages_missing = ["eig", "dsf", "quench"]
+    n0 = n[0]
+    G0 = torch.empty((n0, n0), dtype=torch.float64, device=dev)
+    omega = torch.as_tensor(workloads.omega_grid(w["n_omega"], w["omega_max"]), device=dev)
+    S = torch.empty(w["n_omega"], dtype=torch.float64, device=dev)
+    nt, dt = 1001, 0.05
+    c0v = torch.empty(2 * n0, dtype=torch.float64, device=dev)
+    sx = torch.empty(nt, dtype=torch.float64, device=dev)
+    nrm = torch.empty(nt, dtype=torch.float64, device=dev)
+    stages = ["assemble", "eig", "dsf", "quench"]
 
     def step(ev=None):
-        if ev:
-            ev[0].record(stream)
+        def mark(k):
+            if ev is not None:
+                ev[k].record(stream)
+        mark(0)
         tg.assemble_heff_batched(B, Ks, Hs, tg.TGBA_HEFF | tg.TGBA_LOWER)
-        if ev:
-            ev[1].record(stream)
+        mark(1)
+        tg.eig_batched(Hs[1:], ws[1:], tg.TGBA_EIG_NOVEC)   # spectra of the K != 0 sectors
+        tg.eig(Hs[0], ws[0], tg.TGBA_EIG_FP64)               # eigenpairs of K = 0
+        mark(2)
+        tg.assemble_heff(B, 0, G0, tg.TGBA_GAMMA1)
+        tg.dsf(Hs[0], ws[0], G0, N, omega, w["eta"], S)
+        mark(3)
+        tg.quench_overlaps(B, 0, w["h_perp"], 0, c0v)         # Phi_0 = H0 ground state |0>_NS
+        tg.quench(Hs[0], ws[0], G0, c0v, 0.0, dt, nt, sx, nrm)
+        mark(4)
 
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        print(f"warmup step {i} done", file=sys.stderr, flush=True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        step(ev[i])
-    torch.cuda.synchronize()
+        step(evs[i])
+        torch.cuda.synchronize()
+        print(f"timed step {i} done", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
-    asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    stage_ms = {st: float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k, st in enumerate(stages)}
+    asm_ms = stage_ms["assemble"]
     ms_per_step = wall * 1000.0 / a.steps
     bytes_per_launch = float(sum(x * (x + 1) // 2 for x in n)) * 8.0  # lower triangle incl. diagonal
     achieved = bytes_per_launch / (asm_ms * 1e-3) / 1e9
+    # memory-bound part of the reduction: every column reads the trailing lower triangle once
+    symv_bytes = float(sum((x - 1) * x * (x + 1) // 6 for x in n)) * 8.0  # sum over columns of the trailing lower triangle
+    eig_gbs = symv_bytes / (stage_ms["eig"] * 1e-3) / 1e9
     stats = B.stats()
+    sxn = sx.cpu().numpy()
+    wn0 = ws[0].cpu().numpy()
 
     out = {
         "metric": "H_eff elements/s at N=40",
@@ -125,14 +152,18 @@ def main():
         "config": {"workload": a.workload, "N": N, "h_perp": w["h_perp"], "h_par": w["h_par"],
                    "sectors": N, "chi_min": int(min(n)), "chi_max": int(max(n)), "elements": elements,
                    "gauge": "real", "fill": "lower"},
-        "stages_ms": {"assemble": asm_ms},
-        "stages_missing": stages_missing,
+        "stages_ms": stage_ms,
         "assembly_elements_per_s": elements / (asm_ms * 1e-3),
         "basis_build_s": t_basis,
         "assembly_stats": {"flagged_rows": stats[0], "generic_elements": stats[1], "unsupported": stats[2]},
         "roofline": {"kernel": "assemble_rows_kernel<4,false>", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline_eig_phase": {"bound": "hbm", "achieved": eig_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": eig_gbs / HBM_PEAK_GBS, "algorithmic_bytes": symv_bytes,
+                               "note": "tridiagonal-reduction reads of the trailing lower triangle over the whole eig stage"},
+        "physics": {"E0_K0": float(wn0[0]), "gap_K0": float(wn0[1] - wn0[0]), "m2_over_m1": float((wn0[2] - wn0[0]) / (wn0[1] - wn0[0])),
+                    "sx_t0": float(sxn[0]), "sx_t50": float(sxn[-1]), "norm_drift": float(nrm.max() - nrm.min())},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, B, a.cpu_seconds)

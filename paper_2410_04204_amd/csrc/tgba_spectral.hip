@@ -1,14 +1,313 @@
-// Spectral sums (placeholder).
+// Spectral sums on the sector eigenpairs (real gauge).
+//
+// Dynamic structure factor at k = 0 (DSF section, eq. 8 and the amplitude
+// formula below it): with z_0 the ground state and G the gamma_1 matrix,
+//     b = Z^T (G z_0),   S(omega_j) = 2 pi N sum_a b_a^2 L_eta(omega_j - (w_a - w_0)),
+//     L_eta(x) = (eta/pi) / (x^2 + eta^2).
+// Two memory-bound matrix-vector products and a 4096 x n Lorentzian sum.
+//
+// Quench (Quench section, eq. 9): B(t) = Z diag(exp(-i w t)) Z^T c~,
+// <sigma^x>(t) = B^H G B / |c~|^2, |B(t)|.  The time points are the columns of
+// two FP64 GEMMs: B = Z U and G B, U_{a n} = exp(-i w_a t_n) y_a, y = Z^T c~.
+//
+// Overlaps of the pre-quench vacua with the post-quench Gaussian basis follow
+// the closed form of eq. S5 (pairs (-k, k) with amplitude i W(k), W(k) =
+// tan(Delta_k / 2), normalised by prod sqrt(1 + W^2), and the sign of
+// reordering the pair product into ascending momentum).
+#include <cmath>
+#include <vector>
+
+#include "tgba_blas.h"
 #include "tgba_internal.h"
 
-extern "C" int tgba_dsf(int64_t, const double *, int64_t, const double *, const double *, int64_t, int,
-                        const double *, int, double, double *, double *, void *) {
-    return tgba::set_error(TGBA_EUNSUPPORTED, "tgba_dsf is not built yet");
+namespace tgba {
+namespace {
+
+// y += A x on a 256-row x 256-column tile per workgroup (column-major A), atomics into y
+__global__ void __launch_bounds__(256) gemv_n_kernel(const double *A, int64_t lda, int64_t m, int64_t n,
+                                                     const double *x, double *y) {
+    const int64_t tiles_m = (m + 255) / 256;
+    const int64_t tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int64_t i = tm * 256 + threadIdx.x;
+    __shared__ double xs[256];
+    const int64_t j0 = tn * 256;
+    xs[threadIdx.x] = (j0 + threadIdx.x < n) ? x[j0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    if (i >= m) return;
+    double acc = 0.0;
+    const int64_t jn = (j0 + 256 < n) ? 256 : n - j0;
+    for (int64_t j = 0; j < jn; ++j) acc += A[i + (j0 + j) * lda] * xs[j];
+    atomicAdd(&y[i], acc);
 }
-extern "C" int tgba_quench(int64_t, const double *, int64_t, const double *, const double *, int64_t,
-                           const double *, double, double, int, double *, double *, double *, void *) {
-    return tgba::set_error(TGBA_EUNSUPPORTED, "tgba_quench is not built yet");
+
+// y = A^T x: one wave per column (coalesced column reads)
+__global__ void __launch_bounds__(256) gemv_t_kernel(const double *A, int64_t lda, int64_t m, int64_t n,
+                                                     const double *x, double *y) {
+    const int64_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int64_t i = lane; i < m; i += 64) acc += A[i + j * lda] * x[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) y[j] = acc;
 }
-extern "C" int tgba_quench_overlaps(const tgba_basis *, int, double, int, double *, void *) {
-    return tgba::set_error(TGBA_EUNSUPPORTED, "tgba_quench_overlaps is not built yet");
+
+__global__ void zero_kernel(double *p, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0.0;
+}
+
+__global__ void copy_col_kernel(const double *Z, double *x, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) x[k] = Z[k];
+}
+
+// S(omega_j): one thread per frequency, weights/energies staged through LDS
+__global__ void __launch_bounds__(256) lorentz_kernel(const double *b, const double *w, int64_t n, const double *omega,
+                                                      int n_omega, double eta, double pref, double *S, double *weights) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const double om = (j < n_omega) ? omega[j] : 0.0;
+    const double w0 = w[0];
+    __shared__ double sb[256], se[256];
+    double acc = 0.0;
+    const double e2 = eta * eta;
+    for (int64_t a0 = 0; a0 < n; a0 += 256) {
+        __syncthreads();
+        const int64_t a = a0 + threadIdx.x;
+        if (a < n) {
+            const double bb = b[a] * b[a];
+            sb[threadIdx.x] = bb;
+            se[threadIdx.x] = w[a] - w0;
+            if (weights && blockIdx.x == 0) weights[a] = bb;
+        } else {
+            sb[threadIdx.x] = 0.0;
+            se[threadIdx.x] = 0.0;
+        }
+        __syncthreads();
+        const int cnt = (n - a0 < 256) ? (int)(n - a0) : 256;
+        for (int t = 0; t < cnt; ++t) {
+            const double x = om - se[t];
+            acc += sb[t] / (x * x + e2);
+        }
+    }
+    if (j < n_omega) S[j] = pref * eta / M_PI * acc;
+}
+
+// quench: y = Z^T c (c complex interleaved): two real products through the GEMV
+__global__ void split_complex_kernel(const double *c, double *re, double *im, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        re[k] = c[2 * k];
+        im[k] = c[2 * k + 1];
+    }
+}
+
+// U (n x 2nt, ld n): columns [0, nt) real parts, [nt, 2nt) imaginary parts of exp(-i w t) y
+__global__ void phase_kernel(const double *w, const double *yr, const double *yi, int64_t n, double t0, double dt,
+                             int nt, double *U) {
+    const int64_t tot = n * (int64_t)nt;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = k % n, q = k / n;
+        const double t = t0 + dt * (double)q;
+        double s, c;
+        sincos(w[a] * t, &s, &c);  // exp(-i w t) = c - i s
+        const double re = yr[a], im = yi[a];
+        U[a + q * n] = c * re + s * im;
+        U[a + (q + nt) * n] = c * im - s * re;
+    }
+}
+
+// per time column: sx = (B_re . GB_re + B_im . GB_im) / |c|^2, nrm = |B|
+__global__ void __launch_bounds__(256) quench_reduce_kernel(const double *Bm, const double *GB, int64_t n, int nt,
+                                                            double inv_c2, double *sx, double *nrm, double *Bout) {
+    const int q = blockIdx.x;
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t a = threadIdx.x; a < n; a += 256) {
+        const double br = Bm[a + (int64_t)q * n], bi = Bm[a + (int64_t)(q + nt) * n];
+        a1 += br * GB[a + (int64_t)q * n] + bi * GB[a + (int64_t)(q + nt) * n];
+        a2 += br * br + bi * bi;
+        if (Bout) {
+            Bout[2 * (a + (int64_t)q * n)] = br;
+            Bout[2 * (a + (int64_t)q * n) + 1] = bi;
+        }
+    }
+    __shared__ double r1[4], r2[4];
+    for (int off = 32; off > 0; off >>= 1) {
+        a1 += __shfl_down(a1, off, 64);
+        a2 += __shfl_down(a2, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { r1[threadIdx.x >> 6] = a1; r2[threadIdx.x >> 6] = a2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sx[q] = (r1[0] + r1[1] + r1[2] + r1[3]) * inv_c2;
+        nrm[q] = sqrt(r2[0] + r2[1] + r2[2] + r2[3]);
+    }
+}
+
+__global__ void norm2_kernel(const double *c, int64_t n, double *out) {
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < 2 * n; k += 256) a += c[k] * c[k];
+    __shared__ double r[4];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = r[0] + r[1] + r[2] + r[3];
+}
+
+// CEF overlaps (eq. S5) in the real gauge: thread per basis state.
+// modes: [sector][a] = W(k_a) (0 for k <= 0 or k = pi), pair partner index, and k > 0 flag
+struct CefTab {
+    double W[2][kMaxN];
+    int partner[2][kMaxN];
+    int pos[2][kMaxN];     // 1 if 0 < k < pi
+    double inv_norm[2];    // 1 / prod sqrt(1 + W^2)
+    double weight[2];      // overall factor per parity sector (1/sqrt 2, s/sqrt 2, or 0/1)
+};
+
+__global__ void cef_overlap_kernel(const uint64_t *masks, int64_t n_ns, int64_t n, int N, CefTab tab, double *c) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (i < n_ns) ? 0 : 1;
+        const uint64_t m = masks[i];
+        double re = 0.0, im = 0.0;
+        bool ok = tab.weight[s] != 0.0;
+        // pair state: every occupied mode has 0 < |k| < pi and its partner occupied
+        for (int a = 0; a < N && ok; ++a) {
+            if (!((m >> a) & 1ULL)) continue;
+            const int p = tab.partner[s][a];
+            if (p < 0 || !((m >> p) & 1ULL)) ok = false;
+        }
+        if (ok) {
+            // amplitude prod (i W) over the k > 0 members; phase i^{npairs}
+            double amp = tab.inv_norm[s] * tab.weight[s];
+            int npairs = 0;
+            for (int a = 0; a < N; ++a)
+                if (((m >> a) & 1ULL) && tab.pos[s][a]) { amp *= tab.W[s][a]; ++npairs; }
+            // sign of reordering prod_{k>0 ascending} (d^dag_{-k} d^dag_k) into ascending modes
+            int seq[kMaxN];
+            int L = 0;
+            for (int a = 0; a < N; ++a)
+                if (((m >> a) & 1ULL) && tab.pos[s][a]) { seq[L++] = tab.partner[s][a]; seq[L++] = a; }
+            int inv = 0;
+            for (int x = 0; x < L; ++x)
+                for (int y = x + 1; y < L; ++y) inv += (seq[x] > seq[y]);
+            if (inv & 1) amp = -amp;
+            // paper-gauge value i^{npairs} amp; real gauge multiplies by conj(g),
+            // g = (-i)^{M/2} (NS) or i^{M/2} (R), M/2 = npairs
+            const int q = (s == 0) ? (npairs + npairs) : 0;  // i^{npairs} * i^{npairs} for NS, i^{npairs} (-i)^{npairs} = 1 for R
+            switch (q & 3) {
+                case 0: re = amp; break;
+                case 1: im = amp; break;
+                case 2: re = -amp; break;
+                default: im = -amp; break;
+            }
+        }
+        c[2 * i] = re;
+        c[2 * i + 1] = im;
+    }
+}
+
+}  // namespace
+
+}  // namespace tgba
+
+using namespace tgba;
+
+extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+                        int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
+                        void *stream) {
+    clear_error();
+    if (n <= 0 || !Z || !w || !G || !S || !omega || n_omega <= 0 || ldz < n || ldg < n || !(eta > 0.0))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    void *ws = nullptr;
+    int rc = workspace_get(sizeof(double) * 3 * (size_t)n + 256, 15, &ws);
+    if (rc) return rc;
+    double *z0 = (double *)ws, *gz = z0 + n, *b = gz + n;
+    hipLaunchKernelGGL(copy_col_kernel, dim3(256), dim3(256), 0, st, Z, z0, n);
+    hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, gz, n);
+    const int64_t tm = (n + 255) / 256;
+    hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)(tm * tm)), dim3(256), 0, st, G, ldg, n, n, z0, gz);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, gz, b);
+    hipLaunchKernelGGL(lorentz_kernel, dim3((n_omega + 255) / 256), dim3(256), 0, st, b, w, n, omega, n_omega, eta,
+                       2.0 * M_PI * (double)N_sites, S, weights);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+extern "C" int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+                           const double *c, double t0, double dt, int nt, double *sx, double *nrm, double *B_out,
+                           void *stream) {
+    clear_error();
+    if (n <= 0 || nt <= 0 || !Z || !w || !G || !c || !sx || !nrm || ldz < n || ldg < n)
+        return set_error(TGBA_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cols = 2 * (size_t)nt;
+    void *ws = nullptr;
+    int rc = workspace_get(sizeof(double) * (4 * (size_t)n + 3 * (size_t)n * cols + 64), 16, &ws);
+    if (rc) return rc;
+    double *cr = (double *)ws, *ci = cr + n, *yr = ci + n, *yi = yr + n;
+    double *U = yi + n, *Bm = U + n * cols, *GB = Bm + n * cols;
+    double *c2 = GB + n * cols;
+    hipLaunchKernelGGL(split_complex_kernel, dim3(256), dim3(256), 0, st, c, cr, ci, n);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, cr, yr);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, ci, yi);
+    hipLaunchKernelGGL(phase_kernel, dim3(4096), dim3(256), 0, st, w, yr, yi, n, t0, dt, nt, U);
+    hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(256), 0, st, c, n, c2);
+    TGBA_HIP(hipGetLastError());
+    std::vector<GemmDesc> g(1);
+    g[0] = GemmDesc{Z, ldz, U, n, Bm, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+    rc = dgemm_batched(g, 17, st);
+    if (rc) return rc;
+    g[0] = GemmDesc{G, ldg, Bm, n, GB, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+    rc = dgemm_batched(g, 18, st);
+    if (rc) return rc;
+    double c2h = 0.0;
+    TGBA_HIP(hipMemcpyAsync(&c2h, c2, sizeof(double), hipMemcpyDeviceToHost, st));
+    TGBA_HIP(hipStreamSynchronize(st));
+    if (!(c2h > 0.0)) return set_error(TGBA_EINVAL, "initial state has zero overlap with the basis");
+    hipLaunchKernelGGL(quench_reduce_kernel, dim3(nt), dim3(256), 0, st, Bm, GB, n, nt, 1.0 / c2h, sx, nrm, B_out);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+extern "C" int tgba_quench_overlaps(const tgba_basis *hb, int K, double h_perp_pre, int s, double *c, void *stream) {
+    clear_error();
+    if (!hb || K < 0 || K >= hb->b.N || !c || !(h_perp_pre > 0.0) || s < -1 || s > 1)
+        return set_error(TGBA_EINVAL, "bad arguments");
+    const Basis &b = hb->b;
+    const Sector &sc = b.sec[K];
+    const int64_t n = sc.n_ns + sc.n_r;
+    if (n == 0) return TGBA_OK;
+    const int N = b.N;
+    double kk[2][kMaxN], ep[2][kMaxN], thp[2][kMaxN];
+    mode_tables(N, h_perp_pre, kk, ep, thp);
+    CefTab tab{};
+    for (int sec = 0; sec < 2; ++sec) {
+        double norm2 = 1.0;
+        for (int a = 0; a < N; ++a) {
+            const double k = b.k[sec][a];
+            const bool pos = (k > 1e-12 && k < M_PI - 1e-12);
+            const bool neg = (k < -1e-12 && k > -M_PI + 1e-12);
+            tab.pos[sec][a] = pos ? 1 : 0;
+            tab.partner[sec][a] = -1;
+            if (pos || neg) {
+                for (int q = 0; q < N; ++q)
+                    if (std::fabs(b.k[sec][q] + k) < 1e-12) tab.partner[sec][a] = q;
+            }
+            tab.W[sec][a] = pos ? std::tan(0.5 * (b.th[sec][a] - thp[sec][a])) : 0.0;
+            if (pos) norm2 *= 1.0 + tab.W[sec][a] * tab.W[sec][a];
+        }
+        tab.inv_norm[sec] = 1.0 / std::sqrt(norm2);
+    }
+    if (s == 0) {  // Phi_0 = |0, post>_NS: only the NS vacuum state, amplitude 1 (W = 0)
+        for (int sec = 0; sec < 2; ++sec)
+            for (int a = 0; a < N; ++a) tab.W[sec][a] = 0.0;
+        tab.inv_norm[0] = 1.0;
+        tab.weight[0] = 1.0;
+        tab.weight[1] = 0.0;
+    } else {
+        tab.weight[0] = M_SQRT1_2;
+        tab.weight[1] = (double)s * M_SQRT1_2;
+    }
+    hipLaunchKernelGGL(cef_overlap_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream, sc.d_masks, sc.n_ns, n, N,
+                       tab, c);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
 }
