@@ -5,7 +5,8 @@ Usage: python -m paper_2410_04204_amd.build   (or __graft_entry__.build()).
 Every source is compiled with hipcc for gfx950 only, code object v5.  The
 library binds to the HIP runtime that torch has already loaded (same soname),
 so that device memory, streams and kernels share one runtime.  Packed FP32 VALU
-instructions are disabled for all device code.  The host-only basis code is
+instructions are disabled for all device code.  Floating-point atomics use the
+hardware instructions (all atomics target hipMalloc'ed device memory).  The host-only basis code is
 compiled without floating-point contraction so that its energy sums (which
 decide cutoff inclusion and ordering) are plain IEEE additions.
 """
@@ -24,7 +25,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-I", os.path.join(ROOT, "include"),
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
-          "-Wno-unused-result"]
+          "-Wno-unused-result", "-munsafe-fp-atomics"]
 SOURCES = {
     "tgba_basis.cpp": ["-ffp-contract=off"],
     "tgba_runtime.cpp": [],

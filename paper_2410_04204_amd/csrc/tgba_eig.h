@@ -18,8 +18,12 @@ struct TriSec {
     double *tau;  // reflector scalars (n-1)
     double *W;    // panel workspace, n x 64, leading dimension ldw
     int64_t ldw;
-    double *scal; // per-column scalars and panel dot products (8 + 2*64)
+    double *scal; // per-column scalars, two sets of 8 (by column parity)
+    double *P;    // partial sums of the symmetric product, symv_partials(n) doubles
 };
+
+// Doubles of partial-sum workspace one sector of order n needs.
+int64_t symv_partials(int64_t n);
 
 struct BisIn {
     const double *d, *e;

@@ -26,12 +26,21 @@
 namespace tgba {
 namespace {
 
+// Pointers known to live in global memory (device buffers): loads through them
+// compile to global (not flat) instructions with a scalar base and a 32-bit
+// per-lane offset.
+typedef const char __attribute__((address_space(1))) gchar;
+typedef const double __attribute__((address_space(1))) gdouble;
+
 constexpr int kNB = 64;       // panel width
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
-constexpr int kSymvG = 512;   // workgroups per active sector for the symmetric product
+constexpr int kSymvG = 1024;  // workgroups per active sector for the symmetric product
 
-// scal layout per sector
-constexpr int S_XN2 = 0, S_ALPHA = 1, S_TAU = 2, S_SCALE = 3, S_DOT = 4, S_T1 = 8, S_T2 = 8 + kNB, S_LEN = 8 + 2 * kNB;
+// Per-sector scalars, double-buffered by column parity p = c & 1 so that a
+// kernel may read the previous column's values while the current column's
+// accumulators are being filled:  base(p) = p * S_SET.
+constexpr int S_XN2 = 0, S_ALPHA = 1, S_TAU = 2, S_SCALE = 3, S_DOT = 4;
+constexpr int S_SET = 8, S_LEN = 2 * S_SET;
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -45,189 +54,323 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;  // valid in thread 0
 }
 
-// K1: apply the panel's previous reflectors to column c, zero the y accumulator,
-//     record d[c], alpha = A[c+1][c], and accumulate |A[c+2:, c]|^2.
-__global__ void __launch_bounds__(256) tri_col_update(TriSec *secs, int c, int i, int j0) {
-    const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
-    TriSec S = secs[s];
-    if (c >= S.n) return;
-    __shared__ double wc[kNB], vc[kNB], red[4];
-    if (threadIdx.x < i) {
-        wc[threadIdx.x] = S.W[c + (int64_t)threadIdx.x * S.ldw];
-        vc[threadIdx.x] = S.A[c + (int64_t)(j0 + threadIdx.x) * S.lda];
-    }
-    if (lb == 0 && threadIdx.x < S_LEN && threadIdx.x >= S_DOT) S.scal[threadIdx.x] = 0.0;  // dot, t1, t2
-    __syncthreads();
-    double ss = 0.0;
-    for (int64_t r = c + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
-        double v = S.A[r + (int64_t)c * S.lda];
-        for (int t = 0; t < i; ++t)
-            v -= S.A[r + (int64_t)(j0 + t) * S.lda] * wc[t] + S.W[r + (int64_t)t * S.ldw] * vc[t];
-        if (i > 0) S.A[r + (int64_t)c * S.lda] = v;
-        if (r == c) S.d[c] = v;
-        if (r == c + 1) S.scal[S_ALPHA] = v;
-        if (r >= c + 2) ss += v * v;
-        if (r >= c + 1) S.W[r + (int64_t)i * S.ldw] = 0.0;
-    }
-    ss = block_sum(ss, red);
-    if (threadIdx.x == 0 && ss != 0.0) atomicAdd(&S.scal[S_XN2], ss);
-}
-
-// K2: Householder reflector of column c (one thread per sector).
-__global__ void tri_reflector(TriSec *secs, int nsec, int c) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsec) return;
-    TriSec S = secs[s];
-    if (c >= S.n - 1) return;
-    const double xn = sqrt(S.scal[S_XN2]);
-    const double alpha = S.scal[S_ALPHA];
-    double tau = 0.0, beta = alpha, scale = 1.0;
+// Householder scalars of column c from |x|^2 and alpha (dlarfg without rescaling).
+__device__ __forceinline__ void reflector_scalars(double xn2, double alpha, double &tau, double &beta, double &scale) {
+    const double xn = sqrt(xn2);
+    tau = 0.0;
+    beta = alpha;
+    scale = 1.0;
     if (xn != 0.0) {
         beta = -copysign(hypot(alpha, xn), alpha);
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
     }
-    S.e[c] = beta;
-    S.tau[c] = tau;
-    S.scal[S_TAU] = tau;
-    S.scal[S_SCALE] = scale;
-    S.scal[S_XN2] = 0.0;
-    S.A[c + 1 + (int64_t)c * S.lda] = 1.0;
 }
 
-// K3: y = A22 v (lower-stored trailing matrix, rows/cols c+1..n-1) into W[:, i]
-//     by atomics, and the panel corrections t1 = W^T v, t2 = V^T v.
-//     Work item = (64-column block J, 256-row chunk Q) of the lower triangle.
-__global__ void __launch_bounds__(256) tri_symv(TriSec *secs, int c, int i, int j0) {
+// K1: finish w_{i-1} of the previous column (w += alpha2 v), apply the panel's
+//     previous reflectors to column c, record d[c], alpha = A[c+1][c] and
+//     |A[c+2:, c]|^2; clear this column's dot accumulator.  A workgroup takes
+//     64 rows at a time; its 16 waves split the panel terms of every row and
+//     wave 0 sums the shares in a fixed order.
+constexpr int kWGroups = 16;
+__global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSec *secs, int c, int i, int j0, int nblk) {
+    const int s = blockIdx.x / nblk, lb = blockIdx.x % nblk;
+    TriSec S = secs[s];
+    if (c >= S.n) return;
+    const int64_t n = S.n;
+    const int p = c & 1, q = p ^ 1;
+    double *sc = S.scal + p * S_SET;
+    const double *sq = S.scal + q * S_SET;
+    __shared__ double wc[kNB], vc[kNB];
+    __shared__ double part[kWGroups][64];
+    // pending correction of w_{i-1}: alpha2 = -tau/2 (w . v) of column c-1
+    const double alpha2 = (i > 0) ? -0.5 * sq[S_TAU] * sq[S_DOT] : 0.0;
+    if ((int)threadIdx.x < i) {
+        double wv = S.W[c + (int64_t)threadIdx.x * S.ldw];
+        if ((int)threadIdx.x == i - 1) wv += alpha2;  // v_{c-1}[c] = 1
+        wc[threadIdx.x] = wv;
+        vc[threadIdx.x] = S.A[c + (int64_t)(j0 + threadIdx.x) * S.lda];
+    }
+    if (lb == 0 && threadIdx.x == 0) sc[S_DOT] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    double ss = 0.0;
+    for (int64_t rb0 = c + 64 * (int64_t)lb; rb0 < n; rb0 += 64 * (int64_t)nblk) {  // uniform per block
+        const int64_t r = rb0 + lane;
+        double acc = 0.0;
+        if (r < n)
+            for (int t = grp; t + 1 < i; t += kWGroups)
+                acc += S.A[r + (int64_t)(j0 + t) * S.lda] * wc[t] + S.W[r + (int64_t)t * S.ldw] * vc[t];
+        part[grp][lane] = acc;
+        __syncthreads();
+        if (grp == 0 && r < n) {
+            // finish w_{i-1}: v_{c-1}[r] = A[r][c-1] (1 at r = c).  Row c of W is
+            // not read from memory again (other workgroups hold it in LDS), so
+            // only rows below c are written back.
+            double v = S.A[r + (int64_t)c * S.lda];
+            if (i > 0) {
+                const double wlast = S.W[r + (int64_t)(i - 1) * S.ldw] + alpha2 * S.A[r + (int64_t)(c - 1) * S.lda];
+                if (r > c) S.W[r + (int64_t)(i - 1) * S.ldw] = wlast;
+                double pt = 0.0;
+#pragma unroll
+                for (int g = 0; g < kWGroups; ++g) pt += part[g][lane];
+                v -= pt;
+                v -= S.A[r + (int64_t)(j0 + i - 1) * S.lda] * wc[i - 1] + wlast * vc[i - 1];
+                S.A[r + (int64_t)c * S.lda] = v;
+            }
+            if (r == c) S.d[c] = v;
+            if (r == c + 1) sc[S_ALPHA] = v;
+            if (r >= c + 2) ss += v * v;
+        }
+        __syncthreads();
+    }
+    if (grp == 0) {
+        for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
+        if (lane == 0 && ss != 0.0) atomicAdd(&sc[S_XN2], ss);
+    }
+}
+
+// K2: reflector of column c (every block derives it; block 0 stores it) and
+//     the partial sums of y = A22 v (lower-stored trailing matrix, rows/cols
+//     c+1..n-1) and of the panel corrections t1 = W^T v, t2 = V^T v.
+//     Work item = a kSeg-row segment g of a 64-column strip J of the lower
+//     triangle; wave wv owns the 16 columns cb + 16 wv + jj and streams the
+//     segment 128 rows at a time (lane = row), all 32 loads of an iteration in
+//     flight before any is used.  Every item stores its own partials (no
+//     atomics), which tri_w sums in a fixed order:
+//       Prow[J][r]  sum over the strip's columns cc <= r of A[r][cc] v[cc]
+//       Pcol[g][cc] sum over the segment's rows r > cc of A[r][cc] v[r]
+//       Pt[g][t], Pt[g][64 + t]   the share of t1[t], t2[t] of row segment g
+//                                 (separate items, same streaming pattern)
+//     Rows and columns are indexed absolutely with stride n.
+constexpr int kSeg = 512;
+
+__host__ __device__ __forceinline__ int64_t symv_strips(int64_t n) { return (n + 63) / 64; }
+__host__ __device__ __forceinline__ int64_t symv_segments(int64_t n) { return (n + kSeg - 1) / kSeg; }
+
+// Raw buffer access to a column-major block: base = the block's first element,
+// `bytes` = how far the matrix extends from there (clamped to 32 bits).
+// Offsets past the end read 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const double *base, int64_t bytes) {
+    const int nrec = (int)(uint32_t)(bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nrec, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// bytes from element (r0, c0) to the end of an n x n column-major matrix
+__device__ __forceinline__ int64_t bytes_to_end(int64_t n, int64_t lda, int64_t r0, int64_t c0) {
+    return ((n - 1 - c0) * lda + (n - r0)) * (int64_t)sizeof(double);
+}
+
+__global__ void __launch_bounds__(256, 2) tri_symv(TriSec *secs, int c, int i, int j0) {
     const int s = blockIdx.x / kSymvG, lb = blockIdx.x % kSymvG;
     TriSec S = secs[s];
     const int64_t o = c + 1, n = S.n;
     if (o >= n) return;
+    double *sc = S.scal + (c & 1) * S_SET;
+    double tau, beta, scale;
+    reflector_scalars(sc[S_XN2], sc[S_ALPHA], tau, beta, scale);
+    if (lb == 0 && threadIdx.x == 0) {
+        S.e[c] = beta;
+        S.tau[c] = tau;
+        sc[S_TAU] = tau;
+        sc[S_SCALE] = scale;
+        S.A[o + (int64_t)c * S.lda] = 1.0;
+    }
     const int64_t m = n - o;
-    const int64_t nJ = (m + 63) / 64, nQ = (m + 255) / 256;
-    const double scale = S.scal[S_SCALE];
-    const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
-    __shared__ double vcol[64], vrow[256], ypart[4][256];
-    for (int64_t item = lb; item < nJ * nQ; item += kSymvG) {
-        const int64_t J = item % nJ, Q = item / nJ;
-        const int64_t cb = o + 64 * J, rb = o + 256 * Q;
-        if (rb + 255 < cb) continue;  // entirely above the diagonal (uniform branch)
+    const int64_t nJ = (m + 63) / 64, nG = (m + kSeg - 1) / kSeg;
+    double *Prow = S.P;
+    double *Pcol = Prow + symv_strips(n) * n;
+    double *Pt = Pcol + symv_segments(n) * n;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const gdouble *vsrc = (const gdouble *)(S.A + (int64_t)c * S.lda);  // v[r] = A[r][c] * scale (r > o), 1 at r = o
+    const uint32_t ldb = (uint32_t)(S.lda * (int64_t)sizeof(double));
+    __shared__ double vcol[64];
+    __shared__ double ypart[4][kSeg];
+    const int64_t nmat = nJ * nG, nitem = nmat + (i > 0 ? 2 * nG : 0);
+    for (int64_t item = lb; item < nitem; item += kSymvG) {
+        if (item >= nmat) {
+            // panel item: segment g of t1 = W^T v (kind 0) or t2 = V^T v (kind 1);
+            // wave wv owns the panel columns t = 16 wv + jj
+            const int64_t kind = (item - nmat) / nG, g = (item - nmat) % nG;
+            const int64_t rs = o + (int64_t)kSeg * g, re = (rs + kSeg < n) ? rs + kSeg : n;
+            const double *B = kind ? S.A + rs + (int64_t)j0 * S.lda : S.W + rs;
+            const int64_t ldB = kind ? S.lda : S.ldw;
+            const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(B, (i * ldB) * (int64_t)sizeof(double));
+            const uint32_t ldBb = (uint32_t)(ldB * (int64_t)sizeof(double));
+            double acc[16];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+#pragma unroll 1
+            for (int64_t r = rs + lane; r < re; r += 64) {
+                const double vr = (r == o) ? 1.0 : vsrc[r] * scale;
+                const uint32_t voff = (uint32_t)((r - rs) * (int64_t)sizeof(double));
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int t = 16 * wv + jj;
+                    const double x = buf_ld(rsrc, voff, (uint32_t)t * ldBb);
+                    acc[jj] += (t < i) ? x * vr : 0.0;
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                double v = acc[jj];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                acc[jj] = v;
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int t = 16 * wv + jj;
+                    if (t < i) Pt[g * 2 * kNB + kind * kNB + t] = acc[jj];
+                }
+            }
+            continue;
+        }
+        const int64_t J = item % nJ, g = item / nJ;
+        const int64_t cb = o + 64 * J;
+        const int64_t rs = cb + (int64_t)kSeg * g;
+        if (rs >= n) continue;  // uniform
+        const int64_t re = (rs + kSeg < n) ? rs + kSeg : n;
         __syncthreads();
         if (threadIdx.x < 64) {
             const int64_t cc = cb + threadIdx.x;
-            vcol[threadIdx.x] = (cc >= n) ? 0.0 : (cc == o ? 1.0 : S.A[cc + (int64_t)c * S.lda] * scale);
-        }
-        {
-            const int64_t r = rb + threadIdx.x;
-            vrow[threadIdx.x] = (r >= n) ? 0.0 : (r == o ? 1.0 : S.A[r + (int64_t)c * S.lda] * scale);
+            vcol[threadIdx.x] = (cc >= n) ? 0.0 : (cc == o ? 1.0 : vsrc[cc] * scale);
         }
         __syncthreads();
         double acc[16];
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-        double yr[4] = {0.0, 0.0, 0.0, 0.0};
-        const int64_t c0 = cb + 16 * tc;
+        const int64_t c0 = cb + 16 * wv;  // this wave's first column
+        // the wave's 16 columns from row cb: column jj at scalar offset jj * lda
+        const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(S.A + cb + c0 * S.lda, bytes_to_end(n, S.lda, cb, c0));
+        const bool full_cols = (cb + 64 <= n);
+#pragma unroll 1
+        for (int64_t rb = rs; rb < re; rb += 128) {
+            const bool interior = full_cols && (rb >= cb + 64) && (rb + 128 <= re);
+            double a[2][16], vr[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t r = rb + tr + 64 * q;
-            if (r >= n) continue;
-            const double vr = vrow[tr + 64 * q];
-            const double *col = S.A + r;
+            for (int q = 0; q < 2; ++q) {
+                const int64_t r = rb + lane + 64 * q;
+                const bool rin = r < re;
+                const double vx = vsrc[rin ? r : o];
+                vr[q] = (!rin) ? 0.0 : ((r == o) ? 1.0 : vx * scale);
+                const uint32_t voff = (uint32_t)((r - cb) * (int64_t)sizeof(double));
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const int64_t cc = c0 + jj;
-                if (cc < n && r >= cc) {
-                    const double a = col[cc * S.lda];
-                    yr[q] += a * vcol[16 * tc + jj];
-                    if (r > cc) acc[jj] += a * vr;
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int64_t cc = c0 + jj;
+                    const bool ok = interior || (rin && r >= cc);  // cc >= n reads 0
+                    const double x = buf_ld(rsrc, voff, (uint32_t)jj * ldb);
+                    a[q][jj] = ok ? x : 0.0;
                 }
             }
-        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ypart[tc][tr + 64 * q] = yr[q];
-        // column contributions: reduce over the 64 rows-lanes of this wave
+            for (int q = 0; q < 2; ++q) {
+                const int64_t r = rb + lane + 64 * q;
+                double yr = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int64_t cc = c0 + jj;
+                    yr += a[q][jj] * vcol[16 * wv + jj];
+                    acc[jj] += (interior || r > cc) ? a[q][jj] * vr[q] : 0.0;
+                }
+                if (r < re) ypart[wv][r - rs] = yr;
+            }
+        }
+        // column sums: reduce over the 64 row-lanes of this wave
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             double v = acc[jj];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
             acc[jj] = v;
         }
-        if (tr == 0) {
+        if (lane == 0) {
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
                 const int64_t cc = c0 + jj;
-                if (cc < n && acc[jj] != 0.0) atomicAdd(&S.W[cc + (int64_t)i * S.ldw], acc[jj]);
+                if (cc < n) Pcol[g * n + cc] = acc[jj];
             }
         }
         __syncthreads();
-        {
-            const int64_t r = rb + threadIdx.x;
-            if (r < n) {
-                const double y = ypart[0][threadIdx.x] + ypart[1][threadIdx.x] + ypart[2][threadIdx.x] + ypart[3][threadIdx.x];
-                if (y != 0.0) atomicAdd(&S.W[r + (int64_t)i * S.ldw], y);
-            }
-        }
-        // panel corrections from the first column block (covers every row once)
-        if (J == 0 && i > 0) {
-            for (int t = tc; t < i; t += 4) {
-                double p1 = 0.0, p2 = 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t r = rb + tr + 64 * q;
-                    if (r < n) {
-                        const double vr = vrow[tr + 64 * q];
-                        p1 += S.W[r + (int64_t)t * S.ldw] * vr;
-                        p2 += S.A[r + (int64_t)(j0 + t) * S.lda] * vr;
-                    }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    p1 += __shfl_down(p1, off, 64);
-                    p2 += __shfl_down(p2, off, 64);
-                }
-                if (tr == 0) {
-                    atomicAdd(&S.scal[S_T1 + t], p1);
-                    atomicAdd(&S.scal[S_T2 + t], p2);
-                }
-            }
+        for (int64_t k = threadIdx.x; k < re - rs; k += 256) {
+            Prow[J * n + rs + k] = ((ypart[0][k] + ypart[1][k]) + ypart[2][k]) + ypart[3][k];
         }
     }
 }
 
-// K4: w = tau (y - V t1 - W t2), write back the scaled reflector, dot(w, v).
-__global__ void __launch_bounds__(256) tri_w(TriSec *secs, int c, int i, int j0) {
-    const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
+// K3: y from the partial sums, w = tau (y - V t1 - W t2), write back the
+//     scaled reflector, dot(w, v); clears |x|^2 of this parity for column c + 2.
+//     A workgroup takes 64 rows at a time; its 16 waves split the terms of
+//     every row (strip partials, segment partials, panel corrections) so that
+//     many independent loads are in flight, then wave 0 sums the 16 shares in
+//     a fixed order.
+__global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSec *secs, int c, int i, int j0, int nblk) {
+    const int s = blockIdx.x / nblk, lb = blockIdx.x % nblk;
     TriSec S = secs[s];
-    if (c + 1 >= S.n) return;
-    __shared__ double t1[kNB], t2[kNB], red[4];
-    if (threadIdx.x < i) {
-        t1[threadIdx.x] = S.scal[S_T1 + threadIdx.x];
-        t2[threadIdx.x] = S.scal[S_T2 + threadIdx.x];
+    const int64_t o = c + 1, n = S.n;
+    if (o >= n) return;
+    double *sc = S.scal + (c & 1) * S_SET;
+    const double *Prow = S.P;
+    const double *Pcol = Prow + symv_strips(n) * n;
+    const double *Pt = Pcol + symv_segments(n) * n;
+    const int64_t nG = symv_segments(n - o);
+    __shared__ double t12[2 * kNB];
+    __shared__ double part[kWGroups][64];
+    if ((int)threadIdx.x < 2 * i) {
+        const int idx = ((int)threadIdx.x < i) ? threadIdx.x : kNB + threadIdx.x - i;
+        double a = 0.0;
+        for (int64_t g = 0; g < nG; ++g) a += Pt[g * 2 * kNB + idx];
+        t12[idx] = a;
     }
     __syncthreads();
-    const double tau = S.scal[S_TAU], scale = S.scal[S_SCALE];
+    const double tau = sc[S_TAU], scale = sc[S_SCALE];
+    if (lb == 0 && threadIdx.x == 0) sc[S_XN2] = 0.0;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
     double dot = 0.0;
-    for (int64_t r = c + 1 + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
-        double y = S.W[r + (int64_t)i * S.ldw];
-        for (int t = 0; t < i; ++t) y -= S.A[r + (int64_t)(j0 + t) * S.lda] * t1[t] + S.W[r + (int64_t)t * S.ldw] * t2[t];
-        const double w = tau * y;
-        double v = 1.0;
-        if (r >= c + 2) {
-            v = S.A[r + (int64_t)c * S.lda] * scale;
-            S.A[r + (int64_t)c * S.lda] = v;
+    for (int64_t rb0 = o + 64 * (int64_t)lb; rb0 < n; rb0 += 64 * (int64_t)nblk) {  // uniform per block
+        const int64_t r = rb0 + lane;
+        const int64_t Jr = (rb0 - o) / 64, cb = o + 64 * Jr;  // the strip of these 64 rows
+        const int64_t nGr = (n - cb + kSeg - 1) / kSeg;
+        double y = 0.0;
+        if (r < n) {
+#pragma unroll 4
+            for (int64_t J = grp; J <= Jr; J += kWGroups) y += Prow[J * n + r];
+            for (int64_t g = grp; g < nGr; g += kWGroups) y += Pcol[g * n + r];
+            for (int t = grp; t < i; t += kWGroups)
+                y -= S.A[r + (int64_t)(j0 + t) * S.lda] * t12[t] + S.W[r + (int64_t)t * S.ldw] * t12[kNB + t];
         }
-        S.W[r + (int64_t)i * S.ldw] = w;
-        dot += w * v;
+        part[grp][lane] = y;
+        __syncthreads();
+        if (grp == 0 && r < n) {
+            double yy = 0.0;
+#pragma unroll
+            for (int q = 0; q < kWGroups; ++q) yy += part[q][lane];
+            const double w = tau * yy;
+            double v = 1.0;
+            if (r >= c + 2) {
+                v = S.A[r + (int64_t)c * S.lda] * scale;
+                S.A[r + (int64_t)c * S.lda] = v;
+            }
+            S.W[r + (int64_t)i * S.ldw] = w;
+            dot += w * v;
+        }
+        __syncthreads();
     }
-    dot = block_sum(dot, red);
-    if (threadIdx.x == 0 && dot != 0.0) atomicAdd(&S.scal[S_DOT], dot);
+    if (grp == 0) {
+        for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
+        if (lane == 0 && dot != 0.0) atomicAdd(&sc[S_DOT], dot);
+    }
 }
 
-// K5: w += alpha2 v, alpha2 = -tau/2 (w . v).
+// K4 (panel end only): w += alpha2 v for the panel's last column.
 __global__ void __launch_bounds__(256) tri_finish(TriSec *secs, int c, int i) {
     const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
     TriSec S = secs[s];
     if (c + 1 >= S.n) return;
-    const double alpha2 = -0.5 * S.scal[S_TAU] * S.scal[S_DOT];
+    const double *sc = S.scal + (c & 1) * S_SET;
+    const double alpha2 = -0.5 * sc[S_TAU] * sc[S_DOT];
     for (int64_t r = c + 1 + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
         const double v = (r == c + 1) ? 1.0 : S.A[r + (int64_t)c * S.lda];
         S.W[r + (int64_t)i * S.ldw] += alpha2 * v;
@@ -365,6 +508,8 @@ __global__ void copy_matrix_kernel(const double *src, int64_t lds, double *dst, 
 
 // ---- host drivers -------------------------------------------------------------
 
+int64_t symv_partials(int64_t n) { return (symv_strips(n) + symv_segments(n)) * n + symv_segments(n) * 2 * kNB; }
+
 int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
     const int nsec = (int)secs.size();
     if (nsec == 0) return TGBA_OK;
@@ -395,13 +540,19 @@ int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
             const int64_t c = j0 + i;
             const int act = active(c);
             if (act == 0) break;
-            hipLaunchKernelGGL(tri_col_update, dim3(act * kG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+            const int nblk_u = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nmax - c + 63) / 64));
+            hipLaunchKernelGGL(tri_col_update, dim3(act * nblk_u), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i,
+                               (int)j0, nblk_u);
             const int actr = active(c + 1);  // sectors that need a reflector at column c
             if (actr > 0) {
-                hipLaunchKernelGGL(tri_reflector, dim3((actr + 63) / 64), dim3(64), 0, stream, d_secs, actr, (int)c);
                 hipLaunchKernelGGL(tri_symv, dim3(actr * kSymvG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
-                hipLaunchKernelGGL(tri_w, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
-                hipLaunchKernelGGL(tri_finish, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i);
+                const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nmax - c - 1 + 63) / 64));
+                hipLaunchKernelGGL(tri_w, dim3(actr * nblk), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i, (int)j0,
+                                   nblk);
+                // the last column of a panel is finished before the trailing update;
+                // the others are finished by the next column's update kernel
+                if (i == nb - 1)
+                    hipLaunchKernelGGL(tri_finish, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i);
             }
             TGBA_HIP(hipGetLastError());
         }
@@ -498,11 +649,12 @@ extern "C" int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *
     if (n == 0) return TGBA_OK;
     hipStream_t st = (hipStream_t)stream;
     void *ws = nullptr;
-    const size_t wbytes = sizeof(double) * ((size_t)n * kNB + S_LEN + 64);
+    const size_t wbytes = sizeof(double) * ((size_t)n * kNB + S_LEN + 64 + (size_t)symv_partials(n));
     int rc = workspace_get(wbytes, 7, &ws);
     if (rc) return rc;
     std::vector<TriSec> secs(1);
-    secs[0] = TriSec{A, lda, n, d, e, tau, (double *)ws + S_LEN + 64, n, (double *)ws};
+    double *base = (double *)ws;
+    secs[0] = TriSec{A, lda, n, d, e, tau, base + S_LEN + 64, n, base, base + S_LEN + 64 + (size_t)n * kNB};
     return sytrd_batched(secs, st);
 }
 
@@ -528,7 +680,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
     for (int k = 0; k < nsec; ++k) {
         if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
             return set_error(TGBA_EINVAL, "bad eigensolver arguments");
-        total += (size_t)S_LEN + 64 + (size_t)n[k] * (kNB + 3);
+        total += (size_t)S_LEN + 64 + (size_t)n[k] * (kNB + 3) + (size_t)symv_partials(n[k]);
     }
     void *ws = nullptr;
     int rc = workspace_get(total * sizeof(double), 7, &ws);
@@ -544,6 +696,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         S.d = p; p += n[k];
         S.e = p; p += n[k];
         S.tau = p; p += n[k];
+        S.P = p; p += symv_partials(n[k]);
         S.A = A[k]; S.lda = lda[k]; S.n = n[k]; S.ldw = n[k];
         secs.push_back(S);
         bis.push_back(BisIn{S.d, S.e, w[k], n[k]});
