@@ -249,6 +249,20 @@ int tgba_quench_overlaps(const tgba_basis *basis, int K, double h_perp_pre, int 
 
 /* ---- bookkeeping -------------------------------------------------------- */
 
+/*
+ * Opt-in timing of the eigensolver's dominant kernel, the symmetric
+ * matrix-vector product of the tridiagonal reduction (one launch per column
+ * and batch).  While enabled, every such launch is bracketed by two HIP events
+ * on its stream and its algorithmic bytes are recorded: the trailing lower
+ * triangle read once plus the reflector read and the product written,
+ * 8 (m (m + 1) / 2 + 2 m) bytes per sector with a trailing order m.
+ * tgba_timing_read waits for the recorded events and returns the summed
+ * kernel milliseconds, the number of launches and the summed bytes since the
+ * previous read, then starts over.  Host-side state shared by all devices.
+ */
+int tgba_timing_enable(int on);
+int tgba_timing_read(double *ms, int64_t *launches, double *bytes);
+
 /* Free the cached device workspace of the current device. */
 int tgba_release_workspace(void);
 

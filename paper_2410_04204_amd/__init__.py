@@ -16,7 +16,7 @@ from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_GAMMA1, T
 
 __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "dsf", "quench", "quench_overlaps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
-           "TGBA_EIG_NOVEC", "TgbaError", "version"]
+           "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read"]
 
 
 def version():
@@ -188,3 +188,15 @@ def quench_overlaps(basis, K, h_perp_pre, s, c, stream=None):
     _lib.check(_lib.load().tgba_quench_overlaps(basis.handle, int(K), float(h_perp_pre), int(s), _lib.ptr(c),
                                                 _lib.stream_handle(stream)))
     return c
+
+
+def timing_enable(on=True):
+    """Start (or stop) event timing of the reduction's symmetric-product launches."""
+    _lib.check(_lib.load().tgba_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """(kernel ms, launches, algorithmic bytes) since the previous read; waits for the events."""
+    ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _lib.check(_lib.load().tgba_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+    return ms.value, n.value, by.value

@@ -23,7 +23,7 @@ EXPORTS = [
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
-    "tgba_dgemm", "tgba_stedc",
+    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read",
 ]
 
 
@@ -83,6 +83,8 @@ def load():
     L.tgba_stedc.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]
     L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
                              c_double, c_void_p, c_int64, c_void_p]
+    L.tgba_timing_enable.argtypes = [c_int]
+    L.tgba_timing_read.argtypes = [ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
     for name in EXPORTS:
         if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free"):
             getattr(L, name).restype = c_int

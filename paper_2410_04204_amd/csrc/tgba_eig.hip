@@ -545,7 +545,18 @@ int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
                                (int)j0, nblk_u);
             const int actr = active(c + 1);  // sectors that need a reflector at column c
             if (actr > 0) {
+                hipEvent_t ta = nullptr, tb = nullptr;
+                const bool timed = timing_on();
+                if (timed && (rc = timing_begin(stream, &ta, &tb))) return rc;
                 hipLaunchKernelGGL(tri_symv, dim3(actr * kSymvG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+                if (timed) {
+                    double bytes = 0.0;
+                    for (int k = 0; k < actr; ++k) {
+                        const double m = (double)(sorted[k].n - c - 1);
+                        bytes += 8.0 * (m * (m + 1.0) / 2.0 + 2.0 * m);
+                    }
+                    if ((rc = timing_end(stream, ta, tb, bytes))) return rc;
+                }
                 const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nmax - c - 1 + 63) / 64));
                 hipLaunchKernelGGL(tri_w, dim3(actr * nblk), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i, (int)j0,
                                    nblk);

@@ -58,6 +58,12 @@ int build_contraction_table(Basis *b, hipStream_t stream);
 int workspace_get(size_t bytes, int slot, void **out);
 int release_all_workspace();
 
+// Opt-in event timing (tgba_timing_enable): bracket one launch with two events
+// from a recycled pool and record its algorithmic bytes.
+bool timing_on();
+int timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b);
+int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double bytes);
+
 }  // namespace tgba
 
 struct tgba_basis {

@@ -56,3 +56,13 @@ def test_null_arguments_are_rejected():
     L = _lib.load()
     assert L.tgba_assemble_heff(None, 0, None, 1, 0, None) == -1
     assert L.tgba_basis_sector_size(None, 0, None, None) == -1
+
+
+def test_timing_hook_without_launches():
+    """Enabling, reading and disabling the kernel timing needs no device."""
+    import paper_2410_04204_amd as tg
+    from paper_2410_04204_amd import _lib
+    tg.timing_enable(True)
+    assert tg.timing_read() == (0.0, 0, 0.0)
+    tg.timing_enable(False)
+    assert _lib.load().tgba_timing_read(None, None, None) == -1
