@@ -74,6 +74,7 @@ typedef struct tgba_model {
 
 #define TGBA_TRUNC_ECUT 0 /* keep E^(0) - E0 <= e_cut (E0 = min vacuum energy)          */
 #define TGBA_TRUNC_CHI 1  /* keep chi[K] lowest per sector, order (E^(0), NS<R, mask)   */
+#define TGBA_TRUNC_LEARNED 2 /* keep chi[K] best-scored by the network (tgba_mlp_*)     */
 
 /*
  * Truncation of the Gaussian basis (Method section; Appendix B).
@@ -81,10 +82,17 @@ typedef struct tgba_model {
  *   e_cut  ECUT: the cutoff.  CHI: cutoff of the candidate pool (< 0: the pool
  *          is the whole space, only sensible for small N).
  *   m_max  keep only M <= m_max quasiparticles (<= 0: no cap)
- *   chi    CHI: host array of N per-sector dimensions, or NULL to use chi_all
+ *   chi    CHI, LEARNED: host array of N per-sector dimensions, or NULL to use
+ *          chi_all
+ *   mlp    LEARNED: device array of TGBA_MLP_PARAMS floats (the network of
+ *          tgba_mlp_*); ignored otherwise
  * Cutoffs are inclusive with an absolute slack of 1e-9.  Energies are sums of
  * libm-evaluated mode energies in ascending mode order, so inclusion and order
  * decisions are reproducible bit for bit by any implementation doing the same.
+ * LEARNED (not in the paper, which orders by E^(0) or by the overlap with the
+ * initial state): the pool is the e_cut / m_max set; per sector the chi[K]
+ * states with the largest BF16 score of tgba_mlp_score on their features
+ * (tgba_mlp_features) are kept, equal scores in the order (E^(0), NS<R, mask).
  */
 typedef struct tgba_trunc {
     int mode;
@@ -92,6 +100,7 @@ typedef struct tgba_trunc {
     int m_max;
     const int64_t *chi;
     int64_t chi_all;
+    const float *mlp;
 } tgba_trunc;
 
 typedef struct tgba_basis tgba_basis;
@@ -246,6 +255,67 @@ int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double *w, const 
  * s = 0, Phi_0 = |0,post>_NS (the H0 ground state at h_perp = 1).
  */
 int tgba_quench_overlaps(const tgba_basis *basis, int K, double h_perp_pre, int s, double *c, void *stream);
+
+/* ---- learned truncation (not in the paper; replaces the E^(0) order) ---- */
+
+/*
+ * A 32 -> 256 -> 256 -> 256 -> 1 network with ReLU after each hidden layer and
+ * a linear output scores candidate Gaussian states; its parameters are one
+ * device array of TGBA_MLP_PARAMS floats: W0 (32 x 256, row-major, row =
+ * input), b0 (256), W1 (256 x 256), b1, W2 (256 x 256), b2, w3 (256), b3 (1).
+ * Feature rows are 32 floats (row-major, leading dimension ldx >= 32):
+ *   0..9   |k|/pi of the occupied modes, ascending, zero padded
+ *   10..19 eps_k / (2 (1 + h_perp)) of the occupied modes, ascending, zero padded
+ *   20 sector (0 NS, 1 R)  21 M/10  22 (E - E0)/10  23 occupied (k,-k) pairs / 5
+ *   24 1 if every occupied mode has its -k partner occupied  25 mean |k|/pi
+ *   26 min and 27 max of eps/eps_max (0 when M = 0)  28 1/(1 + E - E0)
+ *   29 (E - E0)^2 / 100  30 h_perp  31 N / 64
+ * Training uses FP32 matrix-core products, the mean-squared error and Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8); inference uses BF16 operands with FP32
+ * accumulation.  All arrays are device arrays unless stated.
+ */
+#define TGBA_MLP_IN 32
+#define TGBA_MLP_HIDDEN 256
+#define TGBA_MLP_PARAMS 140289
+
+/* Features of every state of sector K of a basis (n_ns + n_r rows, basis order). */
+int tgba_mlp_features(const tgba_basis *basis, int K, float *F, int64_t ldf, void *stream);
+
+/* FP32 forward pass of B rows: y (B) and the hidden pre-activations acts
+ * (3 x B x 256: Z1, Z2, Z3, kept for the backward pass). */
+int tgba_mlp_forward(int64_t B, const float *X, int64_t ldx, const float *params, float *acts, float *y,
+                     void *stream);
+
+/* Gradient (packed like params) of sum_b dy[b] y[b] for the forward pass whose
+ * activations are in acts. */
+int tgba_mlp_backward(int64_t B, const float *X, int64_t ldx, const float *params, const float *acts,
+                      const float *dy, float *grads, void *stream);
+
+/* One Adam update of params with moments m, v (TGBA_MLP_PARAMS each); step >= 1. */
+int tgba_mlp_adam(float *params, const float *grads, float *m, float *v, int64_t step, float lr, void *stream);
+
+/*
+ * Minibatch Adam on the mean-squared error over n rows (X, labels) for
+ * `epochs` passes over consecutive batches of `batch` rows (the last one may
+ * be shorter); Adam steps are numbered from step0 + 1.  epoch_loss (epochs
+ * floats, may be NULL) receives the mean batch loss of every epoch.
+ */
+int tgba_mlp_train(int64_t n, const float *X, int64_t ldx, const float *labels, float *params, float *m, float *v,
+                   int64_t step0, int epochs, int64_t batch, float lr, float *epoch_loss, void *stream);
+
+/* BF16 inference: scores y (n) of n feature rows. */
+int tgba_mlp_score(int64_t n, const float *X, int64_t ldx, const float *params, float *y, void *stream);
+
+/* Training labels log10(sum_{v < nvec} Z[a][v]^2 + 1e-30) for the n basis states
+ * (Z column-major n x >= nvec, ldz >= n): the weight of each state in the lowest
+ * nvec eigenvectors of a large-cutoff run. */
+int tgba_mlp_labels(int64_t n, const double *Z, int64_t ldz, int nvec, float *labels, void *stream);
+
+/* Positions (host array, ascending) of the `keep` largest of n device scores;
+ * equal scores are taken in position order.  *n_selected = min(keep, n).
+ * Synchronises the stream. */
+int tgba_mlp_select(int64_t n, const float *scores, int64_t keep, int64_t *selected, int64_t *n_selected,
+                    void *stream);
 
 /* ---- bookkeeping -------------------------------------------------------- */
 

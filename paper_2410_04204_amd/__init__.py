@@ -16,7 +16,11 @@ from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_GAMMA1, T
 
 __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "dsf", "quench", "quench_overlaps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
-           "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read"]
+           "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
+           "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
+           "mlp_select"]
+
+MLP_IN, MLP_HIDDEN, MLP_PARAMS = 32, 256, 140289
 
 
 def version():
@@ -28,10 +32,12 @@ class Basis:
 
     Exactly one of e_cut (energy cutoff) or chi (int or per-sector list) selects
     the truncation; with chi, pool_e_cut bounds the candidate pool (None: whole
-    space, small N only).  m_max caps the quasiparticle number.
+    space, small N only).  m_max caps the quasiparticle number.  With mlp (a
+    device tensor of TGBA_MLP_PARAMS floats) the chi states of every sector
+    with the best network score are kept instead of the lowest in energy.
     """
 
-    def __init__(self, N, h_perp, h_par, e_cut=None, chi=None, m_max=None, pool_e_cut=None, stream=None):
+    def __init__(self, N, h_perp, h_par, e_cut=None, chi=None, m_max=None, pool_e_cut=None, mlp=None, stream=None):
         L = _lib.load()
         self.N, self.h_perp, self.h_par = int(N), float(h_perp), float(h_par)
         model = _lib.Model(self.N, self.h_perp, self.h_par)
@@ -42,12 +48,13 @@ class Basis:
             tr = _lib.Trunc(_lib.TGBA_TRUNC_ECUT, float(e_cut), int(m_max or 0), None, 0)
         else:
             pool = -1.0 if pool_e_cut is None else float(pool_e_cut)
+            mode = _lib.TGBA_TRUNC_CHI if mlp is None else _lib.TGBA_TRUNC_LEARNED
             if np.isscalar(chi):
-                tr = _lib.Trunc(_lib.TGBA_TRUNC_CHI, pool, int(m_max or 0), None, int(chi))
+                tr = _lib.Trunc(mode, pool, int(m_max or 0), None, int(chi), _lib.ptr(mlp))
             else:
                 self._chi_buf = np.ascontiguousarray(np.asarray(chi, dtype=np.int64))
-                tr = _lib.Trunc(_lib.TGBA_TRUNC_CHI, pool, int(m_max or 0),
-                                self._chi_buf.ctypes.data_as(_lib.P_i64), 0)
+                tr = _lib.Trunc(mode, pool, int(m_max or 0), self._chi_buf.ctypes.data_as(_lib.P_i64), 0,
+                                _lib.ptr(mlp))
         h = ctypes.c_void_p()
         _lib.check(L.tgba_build_basis(ctypes.byref(model), ctypes.byref(tr), _lib.stream_handle(stream),
                                       ctypes.byref(h)))
@@ -200,3 +207,64 @@ def timing_read():
     ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
     _lib.check(_lib.load().tgba_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
     return ms.value, n.value, by.value
+
+
+# ---- learned truncation ---------------------------------------------------------
+# Feature rows, activations and parameters are float32 device tensors; X is
+# (rows, >= 32) row-major, its leading dimension is X.stride(0).
+
+def _ldx(X):
+    return X.stride(0) if X.dim() == 2 else MLP_IN
+
+
+def mlp_features(basis, K, F, stream=None):
+    _lib.check(_lib.load().tgba_mlp_features(basis.handle, int(K), _lib.ptr(F), _ldx(F), _lib.stream_handle(stream)))
+    return F
+
+
+def mlp_forward(X, params, acts, y, stream=None):
+    _lib.check(_lib.load().tgba_mlp_forward(X.shape[0], _lib.ptr(X), _ldx(X), _lib.ptr(params), _lib.ptr(acts),
+                                            _lib.ptr(y), _lib.stream_handle(stream)))
+    return y
+
+
+def mlp_backward(X, params, acts, dy, grads, stream=None):
+    _lib.check(_lib.load().tgba_mlp_backward(X.shape[0], _lib.ptr(X), _ldx(X), _lib.ptr(params), _lib.ptr(acts),
+                                             _lib.ptr(dy), _lib.ptr(grads), _lib.stream_handle(stream)))
+    return grads
+
+
+def mlp_adam(params, grads, m, v, step, lr, stream=None):
+    _lib.check(_lib.load().tgba_mlp_adam(_lib.ptr(params), _lib.ptr(grads), _lib.ptr(m), _lib.ptr(v), int(step),
+                                         float(lr), _lib.stream_handle(stream)))
+
+
+def mlp_train(X, labels, params, m, v, step0, epochs, batch, lr, epoch_loss=None, stream=None):
+    _lib.check(_lib.load().tgba_mlp_train(X.shape[0], _lib.ptr(X), _ldx(X), _lib.ptr(labels), _lib.ptr(params),
+                                          _lib.ptr(m), _lib.ptr(v), int(step0), int(epochs), int(batch), float(lr),
+                                          _lib.ptr(epoch_loss), _lib.stream_handle(stream)))
+    return int(step0) + int(epochs) * ((X.shape[0] + min(int(batch), X.shape[0]) - 1) // min(int(batch), X.shape[0]))
+
+
+def mlp_score(X, params, y, stream=None):
+    _lib.check(_lib.load().tgba_mlp_score(X.shape[0], _lib.ptr(X), _ldx(X), _lib.ptr(params), _lib.ptr(y),
+                                          _lib.stream_handle(stream)))
+    return y
+
+
+def mlp_labels(Z, nvec, labels, stream=None):
+    """Labels of the Z.shape[1] basis states (Z: eigenvector tensor shaped (ncols, ld), column-major)."""
+    n = labels.shape[0]
+    _lib.check(_lib.load().tgba_mlp_labels(n, _lib.ptr(Z), Z.shape[1], int(nvec), _lib.ptr(labels),
+                                           _lib.stream_handle(stream)))
+    return labels
+
+
+def mlp_select(scores, keep, stream=None):
+    """Ascending positions of the `keep` largest device scores (ties in position order)."""
+    n = scores.shape[0]
+    out = np.zeros(max(min(int(keep), n), 1), dtype=np.int64)
+    cnt = ctypes.c_int64()
+    _lib.check(_lib.load().tgba_mlp_select(n, _lib.ptr(scores), int(keep), _lib.ptr(out), ctypes.byref(cnt),
+                                           _lib.stream_handle(stream)))
+    return out[:cnt.value]

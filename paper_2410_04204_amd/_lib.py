@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtgba.so")
 TGBA_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
 
-TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI = 0, 1
+TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED = 0, 1, 2
 TGBA_HEFF, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_LOWER = 0x0, 0x1, 0x2, 0x4
 TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC = 0x0, 0x1, 0x2
 
@@ -23,7 +23,9 @@ EXPORTS = [
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
-    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read",
+    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_mlp_features",
+    "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
+    "tgba_mlp_select",
 ]
 
 
@@ -39,7 +41,7 @@ class Model(ctypes.Structure):
 
 class Trunc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("e_cut", ctypes.c_double), ("m_max", ctypes.c_int),
-                ("chi", ctypes.POINTER(ctypes.c_int64)), ("chi_all", ctypes.c_int64)]
+                ("chi", ctypes.POINTER(ctypes.c_int64)), ("chi_all", ctypes.c_int64), ("mlp", ctypes.c_void_p)]
 
 
 _lib = None
@@ -84,6 +86,15 @@ def load():
     L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
                              c_double, c_void_p, c_int64, c_void_p]
     L.tgba_timing_enable.argtypes = [c_int]
+    L.tgba_mlp_features.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p]
+    L.tgba_mlp_forward.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_mlp_backward.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p]
+    L.tgba_mlp_train.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int,
+                                 c_int64, ctypes.c_float, c_void_p, c_void_p]
+    L.tgba_mlp_score.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    L.tgba_mlp_labels.argtypes = [c_int64, c_void_p, c_int64, c_int, c_void_p, c_void_p]
+    L.tgba_mlp_select.argtypes = [c_int64, c_void_p, c_int64, c_void_p, P_i64, c_void_p]
     L.tgba_timing_read.argtypes = [ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
     for name in EXPORTS:
         if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free"):

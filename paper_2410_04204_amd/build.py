@@ -35,6 +35,7 @@ SOURCES = {
     "tgba_eig.hip": [],
     "tgba_dc.hip": [],
     "tgba_spectral.hip": [],
+    "tgba_mlp.hip": [],
 }
 
 

@@ -18,6 +18,7 @@
 #include <new>
 
 #include "tgba_internal.h"
+#include "tgba_mlp.h"
 
 namespace tgba {
 
@@ -120,11 +121,13 @@ static int validate(const tgba_model *m, const tgba_trunc *t) {
         return set_error(TGBA_EINVAL, "N must be even with 2 <= N <= 64");
     if (!(m->h_perp > 0.0) || !std::isfinite(m->h_perp) || !std::isfinite(m->h_par))
         return set_error(TGBA_EINVAL, "h_perp must be > 0 and fields finite");
-    if (t->mode != TGBA_TRUNC_ECUT && t->mode != TGBA_TRUNC_CHI)
+    if (t->mode != TGBA_TRUNC_ECUT && t->mode != TGBA_TRUNC_CHI && t->mode != TGBA_TRUNC_LEARNED)
         return set_error(TGBA_EINVAL, "unknown truncation mode");
+    if (t->mode == TGBA_TRUNC_LEARNED && (!t->mlp || !(t->e_cut >= 0.0)))
+        return set_error(TGBA_EINVAL, "LEARNED mode needs the network parameters and a pool cutoff e_cut >= 0");
     if (t->mode == TGBA_TRUNC_ECUT && !(t->e_cut >= 0.0))
         return set_error(TGBA_EINVAL, "e_cut must be >= 0 in ECUT mode");
-    if (t->mode == TGBA_TRUNC_CHI) {
+    if (t->mode == TGBA_TRUNC_CHI || t->mode == TGBA_TRUNC_LEARNED) {
         if (t->chi) {
             for (int K = 0; K < m->N; ++K)
                 if (t->chi[K] < 0) return set_error(TGBA_EINVAL, "chi must be >= 0");
@@ -157,6 +160,44 @@ static void free_device(Basis &b) {
 using namespace tgba;
 
 extern "C" const char *tgba_last_error(void) { return g_last_error.c_str(); }
+
+// Keep the `keep` candidates with the largest network score (device features,
+// BF16 inference, radix selection); c is replaced by the kept subset, order kept.
+static int learned_keep(const Basis &b, std::vector<Cand> &c, int64_t keep, const float *params, hipStream_t st) {
+    const int64_t n = (int64_t)c.size();
+    std::vector<uint64_t> mk(n);
+    std::vector<double> e(n);
+    std::vector<uint8_t> sec(n);
+    for (int64_t a = 0; a < n; ++a) {
+        mk[a] = c[a].mask;
+        e[a] = c[a].e;
+        sec[a] = (uint8_t)c[a].s;
+    }
+    void *ws = nullptr;
+    const size_t bytes = (size_t)n * (sizeof(uint64_t) + sizeof(double) + kMlpIn * sizeof(float) + sizeof(float)) +
+                         (size_t)n + 1024;
+    int rc = workspace_get(bytes, 24, &ws);
+    if (rc) return rc;
+    uint64_t *d_mk = (uint64_t *)ws;
+    double *d_e = (double *)(d_mk + n);
+    float *d_F = (float *)(d_e + n);
+    float *d_y = d_F + n * kMlpIn;
+    uint8_t *d_sec = (uint8_t *)(d_y + n);
+    TGBA_HIP(hipMemcpyAsync(d_mk, mk.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    TGBA_HIP(hipMemcpyAsync(d_e, e.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    TGBA_HIP(hipMemcpyAsync(d_sec, sec.data(), n, hipMemcpyHostToDevice, st));
+    MlpTab tab;
+    mlp_tab_from_basis(b, tab);
+    if ((rc = mlp_features(tab, n, d_mk, d_e, d_sec, 0, d_F, kMlpIn, st))) return rc;
+    if ((rc = mlp_score_bf16(n, d_F, kMlpIn, params, d_y, st))) return rc;
+    std::vector<int64_t> sel;
+    if ((rc = mlp_select_top(n, d_y, keep, sel, st))) return rc;
+    std::vector<Cand> kept;
+    kept.reserve(sel.size());
+    for (int64_t a : sel) kept.push_back(c[a]);
+    c.swap(kept);
+    return TGBA_OK;
+}
 
 extern "C" const char *tgba_version(void) { return "tgba-mi355x 0.1 (gfx950)"; }
 
@@ -204,6 +245,16 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
             if (t->mode == TGBA_TRUNC_CHI) {
                 int64_t keep = t->chi ? t->chi[K] : t->chi_all;
                 if ((int64_t)c.size() > keep) c.resize(keep);
+            } else if (t->mode == TGBA_TRUNC_LEARNED) {
+                int64_t keep = t->chi ? t->chi[K] : t->chi_all;
+                if ((int64_t)c.size() > keep) {
+                    // c is in tie-break order (E, NS<R, mask): equal scores keep that order
+                    rc = learned_keep(b, c, keep, t->mlp, (hipStream_t)stream);
+                    if (rc) {
+                        delete hb;
+                        return rc;
+                    }
+                }
             }
             Sector &sc = b.sec[K];
             // each parity block ordered by (M, E^(0), mask): waves see uniform M

@@ -1,0 +1,183 @@
+"""Device parity of the learned truncation (features, FP32 training, BF16
+inference, selection, LEARNED basis) against the FP64 oracle in oracle/mlp.py.
+
+Tolerances follow from the arithmetic: FP32 products of at most 256 terms
+give relative errors far below 1e-4 of the output scale; BF16 operands (8-bit
+significand, 3 layers) give a few percent; Adam moves every parameter by at
+most about lr per step, so FP32-vs-FP64 differences in a gradient whose sign is
+decided by rounding are bounded by that step.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import basis as obasis
+from oracle import mlp as omlp
+from oracle import model as omodel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_04204_amd as m
+    return m
+
+
+def dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda", dtype=dtype)
+
+
+def f32(x):
+    import torch
+    return dev(np.asarray(x, dtype=np.float32), torch.float32)
+
+
+def test_features_match_oracle(tg):
+    import torch
+    N, h = 12, 0.8
+    B = tg.Basis(N, h, 0.1, e_cut=8.0)
+    ob = obasis.build_basis(N, h, e_cut=8.0)
+    e0 = B.constants()["e0"]
+    for K in (0, 3, 6):
+        n = sum(B.sector_size(K))
+        F = torch.empty((n, 40), dtype=torch.float32, device="cuda")  # ld 40 > 32
+        tg.mlp_features(B, K, F)
+        want = omlp.sector_features(N, h, ob[K], e0)
+        np.testing.assert_allclose(F[:, :32].cpu().numpy(), want, rtol=0, atol=2e-6)
+
+
+def _fwd_bwd(tg, X, p, dyv):
+    import torch
+    n = X.shape[0]
+    acts = torch.empty(3 * n * 256, dtype=torch.float32, device="cuda")
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    tg.mlp_forward(X, p, acts, y)
+    g = torch.empty(tg.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    tg.mlp_backward(X, p, acts, dyv, g)
+    return y.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1, 63, 300])
+def test_forward_backward_fp32(tg, n):
+    rng = np.random.default_rng(21 + n)
+    X = rng.normal(size=(n, 32))
+    p = workloads.mlp_params(1)
+    dy = rng.normal(size=n)
+    y, g = _fwd_bwd(tg, f32(X), f32(p), f32(dy))
+    # the oracle sees the same float32-rounded inputs
+    X32, p32, dy32 = (np.asarray(a, np.float32).astype(np.float64) for a in (X, p, dy))
+    yo, cache = omlp.forward(X32, p32)
+    go = omlp.backward(X32, p32, cache, dy32)
+    assert np.abs(y - yo).max() <= 1e-4 * max(1.0, np.abs(yo).max())
+    o = 0
+    for name, shp in omlp.SHAPES:
+        k = int(np.prod(shp))
+        d = np.abs(g[o:o + k] - go[o:o + k]).max()
+        assert d <= 1e-4 * max(1e-6, np.abs(go[o:o + k]).max()) + 1e-9, (name, d)
+        o += k
+
+
+def test_adam_step(tg):
+    rng = np.random.default_rng(5)
+    n = omlp.N_PARAMS
+    p, g, m = rng.normal(size=n), rng.normal(size=n), rng.normal(size=n) * 0.1
+    v = rng.random(size=n) * 0.01
+    vals = [np.asarray(a, np.float32).astype(np.float64) for a in (p, g, m, v)]
+    dp, dg, dm, dv = (f32(a) for a in vals)
+    tg.mlp_adam(dp, dg, dm, dv, 3, 1e-3)
+    po, mo, vo = vals[0].copy(), vals[2].copy(), vals[3].copy()
+    omlp.adam_step(po, vals[1], mo, vo, 3, 1e-3)
+    np.testing.assert_allclose(dm.cpu().numpy(), mo, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(dv.cpu().numpy(), vo, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(dp.cpu().numpy(), po, rtol=1e-6, atol=2e-6)
+
+
+def test_training_matches_oracle(tg):
+    import torch
+    rng = np.random.default_rng(31)
+    n, batch, epochs, lr = 1000, 256, 3, 1e-3     # last batch of every epoch: 232 rows
+    X = rng.normal(size=(n, 32))
+    t = np.tanh(X[:, 0]) + 0.3 * X[:, 5] ** 2
+    p0 = workloads.mlp_params(2)
+    X32, t32, p32 = (np.asarray(a, np.float32).astype(np.float64) for a in (X, t, p0))
+    dp = f32(p32)
+    dm = torch.zeros(omlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    dv = torch.zeros_like(dm)
+    loss = torch.empty(epochs, dtype=torch.float32, device="cuda")
+    steps = tg.mlp_train(f32(X32), f32(t32), dp, dm, dv, 0, epochs, batch, lr, loss)
+    po = p32.copy()
+    lo, so = omlp.train(X32, t32, po, epochs, batch, lr)
+    assert steps == so == 12
+    np.testing.assert_allclose(loss.cpu().numpy(), lo, rtol=1e-3)
+    d = np.abs(dp.cpu().numpy() - po)
+    assert d.max() <= 12 * lr * 1.01          # no parameter further than the Adam step bound
+    assert np.quantile(d, 0.999) <= 1e-4        # and almost all of them agree closely
+
+
+@pytest.mark.parametrize("n", [1, 64, 1000])
+def test_bf16_scores(tg, n):
+    rng = np.random.default_rng(41 + n)
+    X = rng.normal(size=(n, 32))
+    p = workloads.mlp_params(3)
+    y = f32(np.zeros(n))
+    tg.mlp_score(f32(X), f32(p), y)
+    yo, _ = omlp.forward(np.asarray(X, np.float32).astype(np.float64), np.asarray(p, np.float32).astype(np.float64))
+    scale = max(1.0, np.abs(yo).max())
+    assert np.abs(y.cpu().numpy() - yo).max() <= 3e-2 * scale
+
+
+@pytest.mark.parametrize("keep", [0, 1, 137, 4999, 5000, 6000])
+def test_select_top_bit_exact(tg, keep):
+    rng = np.random.default_rng(51)
+    s = rng.integers(-40, 40, size=5000).astype(np.float32) * 0.25   # many equal scores
+    s[7] = -0.0
+    s[8] = 0.0
+    sel = tg.mlp_select(f32(s), keep)
+    order = np.lexsort((np.arange(5000), -s.astype(np.float64)))  # score desc, then position
+    np.testing.assert_array_equal(sel, np.sort(order[:min(keep, 5000)]))
+
+
+def test_labels(tg):
+    Q, _ = np.linalg.qr(np.random.default_rng(61).normal(size=(300, 300)))
+    Z = dev(Q.T.copy())  # (ncols, ld) column-major view of Q
+    import torch
+    lab = torch.empty(300, dtype=torch.float32, device="cuda")
+    tg.mlp_labels(Z, 3, lab)
+    np.testing.assert_allclose(lab.cpu().numpy(), omlp.importance_labels(Q, 3), rtol=1e-6, atol=1e-6)
+
+
+def test_learned_basis_matches_oracle_selection(tg):
+    """Every state the oracle's FP64 scores put clearly inside (outside) the kept
+    set is kept (dropped) on the device; the rest is a valid completion."""
+    N, h, pool, chi = 16, 1.0, 8.0, 30
+    p = workloads.mlp_params(4)
+    p32 = np.asarray(p, np.float32).astype(np.float64)
+    B = tg.Basis(N, h, 0.1, chi=chi, pool_e_cut=pool, mlp=f32(p32))
+    ob = obasis.build_basis(N, h, e_cut=pool)
+    e0 = B.constants()["e0"]
+    for K in range(N):
+        sec = ob[K]
+        cand = [(0, m, e) for m, e in zip(sec["ns_masks"], sec["ns_e"])] + \
+               [(1, m, e) for m, e in zip(sec["r_masks"], sec["r_e"])]
+        F = np.array([omlp.features(N, h, s, m, e, e0) for s, m, e in cand]).reshape(-1, 32)
+        sc, _ = omlp.forward(np.asarray(F, np.float32).astype(np.float64), p32)
+        masks, _ = B.sector(K)
+        n_ns, n_r = B.sector_size(K)
+        got = {(0, int(m)) for m in masks[:n_ns]} | {(1, int(m)) for m in masks[n_ns:]}
+        keep = min(chi, len(cand))
+        assert len(got) == keep
+        if keep == len(cand):
+            assert got == {(s, int(m)) for s, m, _ in cand}
+            continue
+        thr = np.sort(sc)[::-1][keep - 1]
+        tol = 3e-2 * max(1.0, np.abs(sc).max())
+        for (s, m, _), v in zip(cand, sc):
+            if v > thr + tol:
+                assert (s, int(m)) in got
+            elif v < thr - tol:
+                assert (s, int(m)) not in got

@@ -60,3 +60,21 @@ def random_vector(n, seed, complex_=True):
     if complex_:
         v = v + 1j * rng.normal(size=n)
     return v
+
+
+MLP_SHAPES = [(32, 256), (256,), (256, 256), (256,), (256, 256), (256,), (256,), (1,)]
+
+
+def mlp_params(seed, bias_scale=0.1):
+    """Seeded network parameters in the packed order W0, b0, W1, b1, W2, b2, w3, b3:
+    weights ~ N(0, 2 / fan_in), biases ~ N(0, bias_scale^2)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shp in MLP_SHAPES:
+        if len(shp) == 2:
+            parts.append(rng.normal(size=shp).ravel() * np.sqrt(2.0 / shp[0]))
+        elif shp == (256,) and len(parts) == 6:
+            parts.append(rng.normal(size=shp) * np.sqrt(2.0 / 256))   # w3: the output weights
+        else:
+            parts.append(rng.normal(size=shp) * bias_scale)
+    return np.concatenate(parts)
