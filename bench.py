@@ -18,7 +18,11 @@ of the whole step.  `roofline` is that of the step's dominant kernel, the
 symmetric matrix-vector product of the tridiagonal reduction (HBM bound): its
 algorithmic bytes and launch durations come from the library's own HIP-event
 timing of every launch in the timed steps.  Per-stage times, the assembly
-kernel's roofline and the oracle's CPU baseline are reported beside it.
+kernel's roofline and the oracle's CPU baseline are reported beside it, and,
+after the timed steps, the second half of the metric: the K = 0 basis
+dimension at which the N = 40 gap is within 1e-6 of the pool's, for the energy
+cutoff and for the learned selection (network trained on the device at
+N = 16..24).
 """
 import argparse
 import json
@@ -44,6 +48,8 @@ def parse():
     p.add_argument("--workload", default="n40_batched")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-gap-metric", action="store_true",
+                   help="skip the learned-versus-cutoff basis dimension (second half of the metric)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (5 times), the reference for "
                         "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -78,6 +84,34 @@ def cpu_baseline(w, B, seconds):
     return {"value": done / dt, "unit": "H_eff elements/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} seeded (row, col) pairs of the K=0 sector ({n_ns}x{n_r} NS x R block), "
                       f"literal Wick-Pfaffian of size 2N+m, {dt:.1f} s"}
+
+
+GAP_TRAIN_RUNS = [(16, 1.0, 14.0), (20, 1.0, 12.0), (20, 0.9, 12.0), (20, 1.1, 12.0), (22, 1.0, 11.0), (24, 1.0, 10.0)]
+
+
+def gap_metric(tol=1e-6):
+    """Basis dimension (K = 0, N = 40) for a gap error <= tol, energy cutoff vs learned.
+
+    The network is trained on the device on the K = 0 eigenvector weights of
+    large-cutoff runs at N = 16..24 (never on N = 40), then selects from the
+    N = 40 E_cut = 10.85 pool (about 20k states), whose own gap is the
+    reference (self-referenced).  Dimensions are searched on a sqrt(2) grid.
+    """
+    import torch
+    from paper_2410_04204_amd import learned
+    t0 = time.perf_counter()
+    F, L = learned.training_data(GAP_TRAIN_RUNS)
+    p0 = torch.as_tensor(workloads.mlp_params(0).astype(np.float32), device="cuda")
+    p, loss = learned.train(F, L, p0, epochs=300)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    grid = [int(round(1000 * 2 ** (j / 2))) for j in range(9)]
+    r = learned.dim_for_gap(40, 1.0, 10.85, grid, p, tol=tol)
+    return {"tol": tol, "workload": "N=40 K=0, h_perp=1, h_par=0.1, pool E_cut=10.85 (reference = whole pool)",
+            "dim_cutoff": r["cutoff"]["dim"], "dim_learned": r["learned"]["dim"], "grid": grid,
+            "gap_err_cutoff": r["cutoff"]["gap_err"], "gap_err_learned": r["learned"]["gap_err"],
+            "train_rows": int(F.shape[0]), "train_loss": [float(loss[0]), float(loss[-1])],
+            "train_s": t_train, "sweep_s": r["seconds"]}
 
 
 def main():
@@ -162,7 +196,7 @@ def main():
     wn0 = ws[0].cpu().numpy()
 
     out = {
-        "metric": "H_eff elements/s at N=40",
+        "metric": "H_eff elements/s at N=40; basis dim for 1e-6 gap error, learned vs cutoff",
         "value": elements / (ms_per_step * 1e-3),
         "unit": "elements/s",
         "n_gpus": 1,
@@ -191,6 +225,10 @@ def main():
         "physics": {"E0_K0": float(wn0[0]), "gap_K0": float(wn0[1] - wn0[0]), "m2_over_m1": float((wn0[2] - wn0[0]) / (wn0[1] - wn0[0])),
                     "sx_t0": float(sxn[0]), "sx_t50": float(sxn[-1]), "norm_drift": float(nrm.max() - nrm.min())},
     }
+    if not a.no_gap_metric:
+        Hs.clear()  # free the N=40 sector matrices before the sweep
+        torch.cuda.empty_cache()
+        out["basis_dim_for_1e-6_gap"] = gap_metric()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, B, a.cpu_seconds)
     print(json.dumps(out), flush=True)
