@@ -179,7 +179,8 @@ int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks,
 /* ---- dense symmetric eigensolve (Method section: diagonalise H_eff) ----- */
 
 #define TGBA_EIG_FP64 0x0    /* all stages in double precision                          */
-#define TGBA_EIG_MIXED 0x1   /* FP32 matrix-core products, FP64 tridiagonal + refinement */
+#define TGBA_EIG_MIXED 0x1   /* FP32 reduction + back-transform, FP64 tridiagonal solve and
+                               refinement of the lowest 200 pairs (see tgba_eig_mixed)  */
 #define TGBA_EIG_NOVEC 0x2   /* eigenvalues only                                         */
 
 /*
@@ -190,6 +191,24 @@ int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks,
  * Errors: TGBA_EINVAL, TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC.
  */
 int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags, void *stream);
+
+/*
+ * Mixed-precision eigen-decomposition of one sector.  The lower triangle is
+ * rounded to FP32 and reduced to tridiagonal form in single precision (FP32
+ * symmetric products and FP32 matrix-core updates: half the HBM traffic of the
+ * FP64 reduction); the tridiagonal is promoted to FP64 and solved by divide and
+ * conquer; the back-transform runs on the FP32 matrix cores.  The lowest
+ * n_refine pairs are then refined in FP64 against the original matrix: two
+ * Newton sweeps on those columns with the whole approximate eigenbasis (the
+ * iterative refinement of Ogita and Aishima restricted to them; near-degenerate
+ * pairs are only re-orthogonalised), then Rayleigh-Ritz on their span
+ * (orthonormalised through the eigen-decomposition of its Gram matrix).  The
+ * refined pairs reach FP64 accuracy; the other pairs keep FP32 accuracy.  On return A holds Z and w the eigenvalues
+ * (the refined ones first; not re-sorted across the refinement boundary).
+ * The upper triangle of A is used as scratch.  Synchronises `stream`.
+ * Errors: TGBA_EINVAL, TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC.
+ */
+int tgba_eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_refine, void *stream);
 
 /*
  * Several sectors at once (all sectors of a model in one batched pass: the

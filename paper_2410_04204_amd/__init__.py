@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
-__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "dsf", "quench", "quench_overlaps",
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -133,6 +133,13 @@ def eig(A, w, flags=TGBA_EIG_FP64, stream=None):
     """A = Z diag(w) Z^T for a column-major symmetric device matrix; A is overwritten by Z."""
     n = w.shape[0]
     _lib.check(_lib.load().tgba_eig(int(n), _lib.ptr(A), _ld(A), _lib.ptr(w), int(flags), _lib.stream_handle(stream)))
+    return w
+
+
+def eig_mixed(A, w, n_refine=200, stream=None):
+    """Mixed-precision eigen-decomposition of one sector (tgba_eig_mixed); A is overwritten by Z."""
+    _lib.check(_lib.load().tgba_eig_mixed(A.shape[0], _lib.ptr(A), _ld(A), _lib.ptr(w), int(n_refine),
+                                          _lib.stream_handle(stream)))
     return w
 
 

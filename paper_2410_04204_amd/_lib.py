@@ -25,7 +25,7 @@ EXPORTS = [
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
     "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
-    "tgba_mlp_select",
+    "tgba_mlp_select", "tgba_eig_mixed",
 ]
 
 
@@ -86,6 +86,7 @@ def load():
     L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
                              c_double, c_void_p, c_int64, c_void_p]
     L.tgba_timing_enable.argtypes = [c_int]
+    L.tgba_eig_mixed.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p]
     L.tgba_mlp_features.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p]
     L.tgba_mlp_forward.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     L.tgba_mlp_backward.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]

@@ -24,7 +24,30 @@ struct GemmDesc {
     int64_t first_tile; // filled by dgemm_batched
 };
 
+// The same in single precision (FP32 matrix cores, v_mfma_f32_32x32x2f32).
+struct SGemmDesc {
+    const float *A;
+    int64_t lda;
+    const float *B;
+    int64_t ldb;
+    float *C;
+    int64_t ldc;
+    int64_t M, N, K;
+    float alpha, beta;
+    int transA, transB;
+    int lower;
+    int pad;
+    int64_t tiles_m;
+    int64_t first_tile;
+};
+
 // One launch for all descriptors; descriptor storage from workspace `slot`.
 int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream);
+int sgemm_batched(std::vector<SGemmDesc> &descs, int slot, hipStream_t stream);
+inline int gemm_batched(std::vector<GemmDesc> &d, int slot, hipStream_t st) { return dgemm_batched(d, slot, st); }
+inline int gemm_batched(std::vector<SGemmDesc> &d, int slot, hipStream_t st) { return sgemm_batched(d, slot, st); }
+template <typename T> struct GemmOf;
+template <> struct GemmOf<double> { using type = GemmDesc; };
+template <> struct GemmOf<float> { using type = SGemmDesc; };
 
 }  // namespace tgba

@@ -1,5 +1,6 @@
 // Dense FP64 products on the matrix cores (MFMA f64 16x16x4), batched over
-// descriptors so that the products of several sectors share one launch.
+// descriptors so that the products of several sectors share one launch, and
+// their FP32 counterpart (MFMA f32 32x32x2) for the mixed-precision eigensolve.
 //
 //   C = alpha op(A) op(B) + beta C     (column-major, op = N or T)
 //
@@ -119,7 +120,125 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
             }
 }
 
+// ---- single precision: v_mfma_f32_32x32x2f32 ---------------------------------
+// Lane layout: operand a of lane l is A[l%32][l/32], operand b is B[l/32][l%32];
+// accumulator r holds D[8(r/4) + 4(l/32) + r%4][l%32].  Each wave computes a
+// 64 x 64 sub-tile as 2 x 2 blocks of 32 x 32.
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int sgemm_desc_of(const SGemmDesc *d, int nd, int64_t blk) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].first_tile <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) sgemm_kernel(const SGemmDesc *__restrict__ descs, int nd) {
+    __shared__ float As[TK][LDS_STRIDE];
+    __shared__ float Bs[TK][LDS_STRIDE];
+    const SGemmDesc G = descs[sgemm_desc_of(descs, nd, blockIdx.x)];
+    const int64_t t = blockIdx.x - G.first_tile;
+    int64_t ti, tj;
+    if (G.lower) {
+        ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = t % G.tiles_m;
+        tj = t / G.tiles_m;
+    }
+    const int64_t m0 = ti * TM, n0 = tj * TN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    f16v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
+    for (int64_t k0 = 0; k0 < G.K; k0 += TK) {
+        if (!G.transA) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int i = tid & 127, k = (tid >> 7) + 2 * s;
+                const int64_t gi = m0 + i, gk = k0 + k;
+                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gi + gk * G.lda] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = tid & 15, i = (tid >> 4) + 16 * s;
+                const int64_t gi = m0 + i, gk = k0 + k;
+                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gk + gi * G.lda] : 0.0f;
+            }
+        }
+        if (!G.transB) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = tid & 15, j = (tid >> 4) + 16 * s;
+                const int64_t gj = n0 + j, gk = k0 + k;
+                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gk + gj * G.ldb] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int j = tid & 127, k = (tid >> 7) + 2 * s;
+                const int64_t gj = n0 + j, gk = k0 + k;
+                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gj + gk * G.ldb] : 0.0f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 2) {
+            float af[2], bf[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) af[a] = As[kk + (lane >> 5)][64 * wy + 32 * a + (lane & 31)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + (lane >> 5)][64 * wx + 32 * b + (lane & 31)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = m0 + 64 * wy + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t j = n0 + 64 * wx + 32 * b + (lane & 31);
+                if (i < G.M && j < G.N && (!G.lower || i >= j)) {
+                    float *c = G.C + i + j * G.ldc;
+                    const float v = G.alpha * acc[a][b][r];
+                    *c = (G.beta == 0.0f) ? v : v + G.beta * (*c);
+                }
+            }
+}
+
 }  // namespace
+
+int sgemm_batched(std::vector<SGemmDesc> &descs, int slot, hipStream_t stream) {
+    int64_t total = 0;
+    for (auto &g : descs) {
+        g.tiles_m = (g.M + TM - 1) / TM;
+        g.first_tile = total;
+        const int64_t tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
+        total += (g.M <= 0 || g.N <= 0) ? 0 : (g.lower ? tm * (tm + 1) / 2 : tm * tn);
+    }
+    if (total == 0) return TGBA_OK;
+    void *ws = nullptr;
+    int rc = workspace_get(descs.size() * sizeof(SGemmDesc), slot, &ws);
+    if (rc) return rc;
+    TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(SGemmDesc), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(sgemm_kernel, dim3((unsigned)total), dim3(256), 0, stream, (const SGemmDesc *)ws, (int)descs.size());
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
 
 int64_t gemm_tiles(const GemmDesc &g) {
     const int64_t tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;

@@ -30,9 +30,10 @@ namespace {
 // compile to global (not flat) instructions with a scalar base and a 32-bit
 // per-lane offset.
 typedef const char __attribute__((address_space(1))) gchar;
-typedef const double __attribute__((address_space(1))) gdouble;
+template <typename T> using gptr = const T __attribute__((address_space(1))) *;
 
 constexpr int kNB = 64;       // panel width
+constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXED
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
 constexpr int kSymvG = 1024;  // workgroups per active sector for the symmetric product
 
@@ -42,25 +43,14 @@ constexpr int kSymvG = 1024;  // workgroups per active sector for the symmetric 
 constexpr int S_XN2 = 0, S_ALPHA = 1, S_TAU = 2, S_SCALE = 3, S_DOT = 4;
 constexpr int S_SET = 8, S_LEN = 2 * S_SET;
 
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-    __syncthreads();
-    return s;  // valid in thread 0
-}
-
 // Householder scalars of column c from |x|^2 and alpha (dlarfg without rescaling).
-__device__ __forceinline__ void reflector_scalars(double xn2, double alpha, double &tau, double &beta, double &scale) {
-    const double xn = sqrt(xn2);
-    tau = 0.0;
+template <typename T>
+__device__ __forceinline__ void reflector_scalars(T xn2, T alpha, T &tau, T &beta, T &scale) {
+    const T xn = sqrt(xn2);
+    tau = T(0);
     beta = alpha;
-    scale = 1.0;
-    if (xn != 0.0) {
+    scale = T(1);
+    if (xn != T(0)) {
         beta = -copysign(hypot(alpha, xn), alpha);
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
@@ -73,31 +63,32 @@ __device__ __forceinline__ void reflector_scalars(double xn2, double alpha, doub
 //     64 rows at a time; its 16 waves split the panel terms of every row and
 //     wave 0 sums the shares in a fixed order.
 constexpr int kWGroups = 16;
-__global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSec *secs, int c, int i, int j0, int nblk) {
+template <typename T>
+__global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSecT<T> *secs, int c, int i, int j0, int nblk) {
     const int s = blockIdx.x / nblk, lb = blockIdx.x % nblk;
-    TriSec S = secs[s];
+    TriSecT<T> S = secs[s];
     if (c >= S.n) return;
     const int64_t n = S.n;
     const int p = c & 1, q = p ^ 1;
-    double *sc = S.scal + p * S_SET;
-    const double *sq = S.scal + q * S_SET;
-    __shared__ double wc[kNB], vc[kNB];
-    __shared__ double part[kWGroups][64];
+    T *sc = S.scal + p * S_SET;
+    const T *sq = S.scal + q * S_SET;
+    __shared__ T wc[kNB], vc[kNB];
+    __shared__ T part[kWGroups][64];
     // pending correction of w_{i-1}: alpha2 = -tau/2 (w . v) of column c-1
-    const double alpha2 = (i > 0) ? -0.5 * sq[S_TAU] * sq[S_DOT] : 0.0;
+    const T alpha2 = (i > 0) ? T(-0.5) * sq[S_TAU] * sq[S_DOT] : T(0);
     if ((int)threadIdx.x < i) {
-        double wv = S.W[c + (int64_t)threadIdx.x * S.ldw];
+        T wv = S.W[c + (int64_t)threadIdx.x * S.ldw];
         if ((int)threadIdx.x == i - 1) wv += alpha2;  // v_{c-1}[c] = 1
         wc[threadIdx.x] = wv;
         vc[threadIdx.x] = S.A[c + (int64_t)(j0 + threadIdx.x) * S.lda];
     }
-    if (lb == 0 && threadIdx.x == 0) sc[S_DOT] = 0.0;
+    if (lb == 0 && threadIdx.x == 0) sc[S_DOT] = T(0);
     __syncthreads();
     const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    double ss = 0.0;
+    T ss = T(0);
     for (int64_t rb0 = c + 64 * (int64_t)lb; rb0 < n; rb0 += 64 * (int64_t)nblk) {  // uniform per block
         const int64_t r = rb0 + lane;
-        double acc = 0.0;
+        T acc = T(0);
         if (r < n)
             for (int t = grp; t + 1 < i; t += kWGroups)
                 acc += S.A[r + (int64_t)(j0 + t) * S.lda] * wc[t] + S.W[r + (int64_t)t * S.ldw] * vc[t];
@@ -107,11 +98,11 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSec *secs, in
             // finish w_{i-1}: v_{c-1}[r] = A[r][c-1] (1 at r = c).  Row c of W is
             // not read from memory again (other workgroups hold it in LDS), so
             // only rows below c are written back.
-            double v = S.A[r + (int64_t)c * S.lda];
+            T v = S.A[r + (int64_t)c * S.lda];
             if (i > 0) {
-                const double wlast = S.W[r + (int64_t)(i - 1) * S.ldw] + alpha2 * S.A[r + (int64_t)(c - 1) * S.lda];
+                const T wlast = S.W[r + (int64_t)(i - 1) * S.ldw] + alpha2 * S.A[r + (int64_t)(c - 1) * S.lda];
                 if (r > c) S.W[r + (int64_t)(i - 1) * S.ldw] = wlast;
-                double pt = 0.0;
+                T pt = T(0);
 #pragma unroll
                 for (int g = 0; g < kWGroups; ++g) pt += part[g][lane];
                 v -= pt;
@@ -126,7 +117,7 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSec *secs, in
     }
     if (grp == 0) {
         for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
-        if (lane == 0 && ss != 0.0) atomicAdd(&sc[S_XN2], ss);
+        if (lane == 0 && ss != T(0)) atomicAdd(&sc[S_XN2], ss);
     }
 }
 
@@ -151,44 +142,50 @@ __host__ __device__ __forceinline__ int64_t symv_segments(int64_t n) { return (n
 // Raw buffer access to a column-major block: base = the block's first element,
 // `bytes` = how far the matrix extends from there (clamped to 32 bits).
 // Offsets past the end read 0.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const double *base, int64_t bytes) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void *base, int64_t bytes) {
     const int nrec = (int)(uint32_t)(bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes));
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nrec, 0x00020000);
 }
-__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 // bytes from element (r0, c0) to the end of an n x n column-major matrix
+template <typename T>
 __device__ __forceinline__ int64_t bytes_to_end(int64_t n, int64_t lda, int64_t r0, int64_t c0) {
-    return ((n - 1 - c0) * lda + (n - r0)) * (int64_t)sizeof(double);
+    return ((n - 1 - c0) * lda + (n - r0)) * (int64_t)sizeof(T);
 }
 
-__global__ void __launch_bounds__(256, 2) tri_symv(TriSec *secs, int c, int i, int j0) {
+template <typename T>
+__global__ void __launch_bounds__(256, 2) tri_symv(TriSecT<T> *secs, int c, int i, int j0) {
     const int s = blockIdx.x / kSymvG, lb = blockIdx.x % kSymvG;
-    TriSec S = secs[s];
+    TriSecT<T> S = secs[s];
     const int64_t o = c + 1, n = S.n;
     if (o >= n) return;
-    double *sc = S.scal + (c & 1) * S_SET;
-    double tau, beta, scale;
+    T *sc = S.scal + (c & 1) * S_SET;
+    T tau, beta, scale;
     reflector_scalars(sc[S_XN2], sc[S_ALPHA], tau, beta, scale);
     if (lb == 0 && threadIdx.x == 0) {
         S.e[c] = beta;
         S.tau[c] = tau;
         sc[S_TAU] = tau;
         sc[S_SCALE] = scale;
-        S.A[o + (int64_t)c * S.lda] = 1.0;
+        S.A[o + (int64_t)c * S.lda] = T(1);
     }
     const int64_t m = n - o;
     const int64_t nJ = (m + 63) / 64, nG = (m + kSeg - 1) / kSeg;
-    double *Prow = S.P;
-    double *Pcol = Prow + symv_strips(n) * n;
-    double *Pt = Pcol + symv_segments(n) * n;
+    T *Prow = S.P;
+    T *Pcol = Prow + symv_strips(n) * n;
+    T *Pt = Pcol + symv_segments(n) * n;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const gdouble *vsrc = (const gdouble *)(S.A + (int64_t)c * S.lda);  // v[r] = A[r][c] * scale (r > o), 1 at r = o
-    const uint32_t ldb = (uint32_t)(S.lda * (int64_t)sizeof(double));
-    __shared__ double vcol[64];
-    __shared__ double ypart[4][kSeg];
+    const gptr<T> vsrc = (gptr<T>)(S.A + (int64_t)c * S.lda);  // v[r] = A[r][c] * scale (r > o), 1 at r = o
+    const uint32_t ldb = (uint32_t)(S.lda * (int64_t)sizeof(T));
+    __shared__ T vcol[64];
+    __shared__ T ypart[4][kSeg];
     const int64_t nmat = nJ * nG, nitem = nmat + (i > 0 ? 2 * nG : 0);
     for (int64_t item = lb; item < nitem; item += kSymvG) {
         if (item >= nmat) {
@@ -196,27 +193,27 @@ __global__ void __launch_bounds__(256, 2) tri_symv(TriSec *secs, int c, int i, i
             // wave wv owns the panel columns t = 16 wv + jj
             const int64_t kind = (item - nmat) / nG, g = (item - nmat) % nG;
             const int64_t rs = o + (int64_t)kSeg * g, re = (rs + kSeg < n) ? rs + kSeg : n;
-            const double *B = kind ? S.A + rs + (int64_t)j0 * S.lda : S.W + rs;
+            const T *B = kind ? S.A + rs + (int64_t)j0 * S.lda : S.W + rs;
             const int64_t ldB = kind ? S.lda : S.ldw;
-            const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(B, (i * ldB) * (int64_t)sizeof(double));
-            const uint32_t ldBb = (uint32_t)(ldB * (int64_t)sizeof(double));
-            double acc[16];
+            const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(B, (i * ldB) * (int64_t)sizeof(T));
+            const uint32_t ldBb = (uint32_t)(ldB * (int64_t)sizeof(T));
+            T acc[16];
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+            for (int jj = 0; jj < 16; ++jj) acc[jj] = T(0);
 #pragma unroll 1
             for (int64_t r = rs + lane; r < re; r += 64) {
-                const double vr = (r == o) ? 1.0 : vsrc[r] * scale;
-                const uint32_t voff = (uint32_t)((r - rs) * (int64_t)sizeof(double));
+                const T vr = (r == o) ? T(1) : vsrc[r] * scale;
+                const uint32_t voff = (uint32_t)((r - rs) * (int64_t)sizeof(T));
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) {
                     const int t = 16 * wv + jj;
-                    const double x = buf_ld(rsrc, voff, (uint32_t)t * ldBb);
-                    acc[jj] += (t < i) ? x * vr : 0.0;
+                    const T x = buf_ld<T>(rsrc, voff, (uint32_t)t * ldBb);
+                    acc[jj] += (t < i) ? x * vr : T(0);
                 }
             }
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
-                double v = acc[jj];
+                T v = acc[jj];
                 for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
                 acc[jj] = v;
             }
@@ -237,44 +234,44 @@ __global__ void __launch_bounds__(256, 2) tri_symv(TriSec *secs, int c, int i, i
         __syncthreads();
         if (threadIdx.x < 64) {
             const int64_t cc = cb + threadIdx.x;
-            vcol[threadIdx.x] = (cc >= n) ? 0.0 : (cc == o ? 1.0 : vsrc[cc] * scale);
+            vcol[threadIdx.x] = (cc >= n) ? T(0) : (cc == o ? T(1) : vsrc[cc] * scale);
         }
         __syncthreads();
-        double acc[16];
+        T acc[16];
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+        for (int jj = 0; jj < 16; ++jj) acc[jj] = T(0);
         const int64_t c0 = cb + 16 * wv;  // this wave's first column
         // the wave's 16 columns from row cb: column jj at scalar offset jj * lda
-        const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(S.A + cb + c0 * S.lda, bytes_to_end(n, S.lda, cb, c0));
+        const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(S.A + cb + c0 * S.lda, bytes_to_end<T>(n, S.lda, cb, c0));
         const bool full_cols = (cb + 64 <= n);
 #pragma unroll 1
         for (int64_t rb = rs; rb < re; rb += 128) {
             const bool interior = full_cols && (rb >= cb + 64) && (rb + 128 <= re);
-            double a[2][16], vr[2];
+            T a[2][16], vr[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int64_t r = rb + lane + 64 * q;
                 const bool rin = r < re;
-                const double vx = vsrc[rin ? r : o];
-                vr[q] = (!rin) ? 0.0 : ((r == o) ? 1.0 : vx * scale);
-                const uint32_t voff = (uint32_t)((r - cb) * (int64_t)sizeof(double));
+                const T vx = vsrc[rin ? r : o];
+                vr[q] = (!rin) ? T(0) : ((r == o) ? T(1) : vx * scale);
+                const uint32_t voff = (uint32_t)((r - cb) * (int64_t)sizeof(T));
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) {
                     const int64_t cc = c0 + jj;
                     const bool ok = interior || (rin && r >= cc);  // cc >= n reads 0
-                    const double x = buf_ld(rsrc, voff, (uint32_t)jj * ldb);
-                    a[q][jj] = ok ? x : 0.0;
+                    const T x = buf_ld<T>(rsrc, voff, (uint32_t)jj * ldb);
+                    a[q][jj] = ok ? x : T(0);
                 }
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int64_t r = rb + lane + 64 * q;
-                double yr = 0.0;
+                T yr = T(0);
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) {
                     const int64_t cc = c0 + jj;
                     yr += a[q][jj] * vcol[16 * wv + jj];
-                    acc[jj] += (interior || r > cc) ? a[q][jj] * vr[q] : 0.0;
+                    acc[jj] += (interior || r > cc) ? a[q][jj] * vr[q] : T(0);
                 }
                 if (r < re) ypart[wv][r - rs] = yr;
             }
@@ -282,7 +279,7 @@ __global__ void __launch_bounds__(256, 2) tri_symv(TriSec *secs, int c, int i, i
         // column sums: reduce over the 64 row-lanes of this wave
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
-            double v = acc[jj];
+            T v = acc[jj];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
             acc[jj] = v;
         }
@@ -306,34 +303,35 @@ __global__ void __launch_bounds__(256, 2) tri_symv(TriSec *secs, int c, int i, i
 //     every row (strip partials, segment partials, panel corrections) so that
 //     many independent loads are in flight, then wave 0 sums the 16 shares in
 //     a fixed order.
-__global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSec *secs, int c, int i, int j0, int nblk) {
+template <typename T>
+__global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSecT<T> *secs, int c, int i, int j0, int nblk) {
     const int s = blockIdx.x / nblk, lb = blockIdx.x % nblk;
-    TriSec S = secs[s];
+    TriSecT<T> S = secs[s];
     const int64_t o = c + 1, n = S.n;
     if (o >= n) return;
-    double *sc = S.scal + (c & 1) * S_SET;
-    const double *Prow = S.P;
-    const double *Pcol = Prow + symv_strips(n) * n;
-    const double *Pt = Pcol + symv_segments(n) * n;
+    T *sc = S.scal + (c & 1) * S_SET;
+    const T *Prow = S.P;
+    const T *Pcol = Prow + symv_strips(n) * n;
+    const T *Pt = Pcol + symv_segments(n) * n;
     const int64_t nG = symv_segments(n - o);
-    __shared__ double t12[2 * kNB];
-    __shared__ double part[kWGroups][64];
+    __shared__ T t12[2 * kNB];
+    __shared__ T part[kWGroups][64];
     if ((int)threadIdx.x < 2 * i) {
         const int idx = ((int)threadIdx.x < i) ? threadIdx.x : kNB + threadIdx.x - i;
-        double a = 0.0;
+        T a = T(0);
         for (int64_t g = 0; g < nG; ++g) a += Pt[g * 2 * kNB + idx];
         t12[idx] = a;
     }
     __syncthreads();
-    const double tau = sc[S_TAU], scale = sc[S_SCALE];
-    if (lb == 0 && threadIdx.x == 0) sc[S_XN2] = 0.0;
+    const T tau = sc[S_TAU], scale = sc[S_SCALE];
+    if (lb == 0 && threadIdx.x == 0) sc[S_XN2] = T(0);
     const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    double dot = 0.0;
+    T dot = T(0);
     for (int64_t rb0 = o + 64 * (int64_t)lb; rb0 < n; rb0 += 64 * (int64_t)nblk) {  // uniform per block
         const int64_t r = rb0 + lane;
         const int64_t Jr = (rb0 - o) / 64, cb = o + 64 * Jr;  // the strip of these 64 rows
         const int64_t nGr = (n - cb + kSeg - 1) / kSeg;
-        double y = 0.0;
+        T y = T(0);
         if (r < n) {
 #pragma unroll 4
             for (int64_t J = grp; J <= Jr; J += kWGroups) y += Prow[J * n + r];
@@ -344,11 +342,11 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSec *secs, int c, int 
         part[grp][lane] = y;
         __syncthreads();
         if (grp == 0 && r < n) {
-            double yy = 0.0;
+            T yy = T(0);
 #pragma unroll
             for (int q = 0; q < kWGroups; ++q) yy += part[q][lane];
-            const double w = tau * yy;
-            double v = 1.0;
+            const T w = tau * yy;
+            T v = T(1);
             if (r >= c + 2) {
                 v = S.A[r + (int64_t)c * S.lda] * scale;
                 S.A[r + (int64_t)c * S.lda] = v;
@@ -360,25 +358,27 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSec *secs, int c, int 
     }
     if (grp == 0) {
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
-        if (lane == 0 && dot != 0.0) atomicAdd(&sc[S_DOT], dot);
+        if (lane == 0 && dot != T(0)) atomicAdd(&sc[S_DOT], dot);
     }
 }
 
 // K4 (panel end only): w += alpha2 v for the panel's last column.
-__global__ void __launch_bounds__(256) tri_finish(TriSec *secs, int c, int i) {
+template <typename T>
+__global__ void __launch_bounds__(256) tri_finish(TriSecT<T> *secs, int c, int i) {
     const int s = blockIdx.x / kG, lb = blockIdx.x % kG;
-    TriSec S = secs[s];
+    TriSecT<T> S = secs[s];
     if (c + 1 >= S.n) return;
-    const double *sc = S.scal + (c & 1) * S_SET;
-    const double alpha2 = -0.5 * sc[S_TAU] * sc[S_DOT];
+    const T *sc = S.scal + (c & 1) * S_SET;
+    const T alpha2 = T(-0.5) * sc[S_TAU] * sc[S_DOT];
     for (int64_t r = c + 1 + (int64_t)lb * 256 + threadIdx.x; r < S.n; r += (int64_t)kG * 256) {
-        const double v = (r == c + 1) ? 1.0 : S.A[r + (int64_t)c * S.lda];
+        const T v = (r == c + 1) ? T(1) : S.A[r + (int64_t)c * S.lda];
         S.W[r + (int64_t)i * S.ldw] += alpha2 * v;
     }
 }
 
-__global__ void zero_kernel(double *p, int64_t n) {
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0.0;
+template <typename T>
+__global__ void zero_kernel(T *p, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = T(0);
 }
 
 // ---- bisection on Sturm counts (one thread per eigenvalue) ----------------
@@ -460,28 +460,30 @@ __global__ void __launch_bounds__(256) gersh_kernel(const BisSec *secs, double *
 
 // V (m x nbp, ld m) of panel columns j0..j0+nbp-1: row r <-> global row j0+1+r,
 // explicit zeros above the unit diagonal entry of each reflector.
-__global__ void extract_v_kernel(const double *A, int64_t lda, int64_t n, int64_t j0, int nbp, double *V) {
+template <typename T>
+__global__ void extract_v_kernel(const T *A, int64_t lda, int64_t n, int64_t j0, int nbp, T *V) {
     const int64_t m = n - j0 - 1;
     const int64_t tot = m * nbp;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = k % m, t = k / m;
         const int64_t R = j0 + 1 + r, c = j0 + t;
-        V[r + t * m] = (R < c + 1) ? 0.0 : ((R == c + 1) ? 1.0 : A[R + c * lda]);
+        V[r + t * m] = (R < c + 1) ? T(0) : ((R == c + 1) ? T(1) : A[R + c * lda]);
     }
 }
 
 // Upper triangular T of the compact WY form I - V T V^T of H_j0 ... H_j0+nbp-1
 // (forward, columnwise): T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) (V^T V)(0:i, i).
-__global__ void larft_kernel(const double *Sg, const double *tau, int nbp, double *T) {
-    __shared__ double Tl[64][65];
-    __shared__ double col[64];
+template <typename T>
+__global__ void larft_kernel(const T *Sg, const T *tau, int nbp, T *Tm) {
+    __shared__ T Tl[64][65];
+    __shared__ T col[64];
     const int j = threadIdx.x;
-    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = 0.0;
+    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = T(0);
     __syncthreads();
     for (int i = 0; i < nbp; ++i) {
-        const double ti = tau[i];
+        const T ti = tau[i];
         if (j < i) {
-            double acc = 0.0;
+            T acc = T(0);
             for (int l = j; l < i; ++l) acc += Tl[j][l] * Sg[l + i * nbp];
             col[j] = -ti * acc;
         }
@@ -492,15 +494,103 @@ __global__ void larft_kernel(const double *Sg, const double *tau, int nbp, doubl
     }
     for (int k = j; k < nbp * nbp; k += blockDim.x) {
         const int r = k % nbp, c = k / nbp;
-        T[r + c * nbp] = Tl[r][c];
+        Tm[r + c * nbp] = Tl[r][c];
     }
 }
 
-__global__ void copy_matrix_kernel(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m, int64_t n) {
+template <typename T>
+__global__ void copy_matrix_kernel(const T *src, int64_t lds, T *dst, int64_t ldd, int64_t m, int64_t n) {
     const int64_t tot = m * n;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = k % m, j = k / m;
         dst[i + j * ldd] = src[i + j * lds];
+    }
+}
+
+
+// ---- mixed precision helpers ----------------------------------------------------
+
+// lower triangle (incl. diagonal) of an FP64 matrix into an FP32 one
+__global__ void lower_to_f32_kernel(const double *A, int64_t lda, float *B, int64_t ldb, int64_t n) {
+    const int64_t tot = n * n;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = k % n, j = k / n;
+        if (i >= j) B[i + j * ldb] = (float)A[i + j * lda];
+    }
+}
+
+template <typename S, typename D>
+__global__ void convert_matrix_kernel(const S *src, int64_t lds, D *dst, int64_t ldd, int64_t m, int64_t n) {
+    const int64_t tot = m * n;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = k % m, j = k / m;
+        dst[i + j * ldd] = (D)src[i + j * lds];
+    }
+}
+
+// A[j][i] = A[i][j] for i > j, 64 x 64 tiles through LDS (coalesced both ways)
+__global__ void symmetrize_lower_kernel(double *A, int64_t lda, int64_t n) {
+    __shared__ double t[64][65];
+    const int64_t nb = (n + 63) / 64;
+    const int64_t b = blockIdx.x;
+    int64_t bi = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);  // lower tile (bi >= bj)
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    while (bi * (bi + 1) / 2 > b) --bi;
+    const int64_t bj = b - bi * (bi + 1) / 2;
+    if (bi >= nb) return;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4 threads
+    for (int r = ty; r < 64; r += 4) {  // column bj*64 + r, rows bi*64 + tx
+        const int64_t i = bi * 64 + tx, j = bj * 64 + r;
+        if (i < n && j < n) t[r][tx] = A[i + j * lda];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {  // column bi*64 + r of the upper part, rows bj*64 + tx
+        const int64_t i = bj * 64 + tx, j = bi * 64 + r;  // destination (i, j), source (j, i)
+        if (i < n && j < n && j > i) A[i + j * lda] = t[tx][r];
+    }
+}
+
+// B[:, j] = U[:, j] / sqrt(g[j])
+__global__ void scale_cols_kernel(double *U, int64_t ldu, int64_t m, int64_t k, const double *g) {
+    const int64_t tot = m * k;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q % m, j = q / m;
+        U[i + j * ldu] /= sqrt(g[j]);
+    }
+}
+
+// Newton correction of the first k columns of an approximate eigenbasis X
+// (all n columns; Ogita & Aishima's iterative refinement restricted to those
+// columns).  In: Sk = X^T A X_k, Gk = X^T X_k (n x k), w (n) eigenvalue
+// estimates for the columns >= k.  Out: E (n x k) with X_k += X E:
+//   lambda_i = Sk[i][i] / Gk[i][i], r_ji = delta_ji - Gk[j][i],
+//   E[j][i] = (Sk[j][i] + lambda_i r_ji) / (lambda_i - lambda_j)  if |lambda_i - lambda_j| > thr,
+//   E[j][i] = r_ji / 2  otherwise (the same column, or a near-degenerate pair).
+__global__ void oa_correction_kernel(const double *Sk, const double *Gk, const double *w, int64_t n, int64_t k,
+                                     double thr, double *E) {
+    const int64_t tot = n * k;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = q % n, i = q / n;
+        const double li = Sk[i + i * n] / Gk[i + i * n];
+        const double lj = (j < k) ? Sk[j + j * n] / Gk[j + j * n] : w[j];
+        const double r = ((j == i) ? 1.0 : 0.0) - Gk[j + i * n];
+        double e;
+        if (j != i && fabs(li - lj) > thr) e = (Sk[j + i * n] + li * r) / (li - lj);
+        else e = 0.5 * r;
+        E[j + i * n] = e;
+    }
+}
+
+// S = (S + S^T) / 2 for a small k x k matrix
+__global__ void sym_avg_kernel(double *S, int64_t lds, int64_t k) {
+    const int64_t tot = k * k;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q % k, j = q / k;
+        if (i > j) {
+            const double v = 0.5 * (S[i + j * lds] + S[j + i * lds]);
+            S[i + j * lds] = v;
+            S[j + i * lds] = v;
+        }
     }
 }
 
@@ -510,22 +600,23 @@ __global__ void copy_matrix_kernel(const double *src, int64_t lds, double *dst, 
 
 int64_t symv_partials(int64_t n) { return (symv_strips(n) + symv_segments(n)) * n + symv_segments(n) * 2 * kNB; }
 
-int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
+template <typename T>
+int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
     const int nsec = (int)secs.size();
     if (nsec == 0) return TGBA_OK;
     // sectors sorted by size, largest first: the active ones are always a prefix
     std::vector<int> order(nsec);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return secs[a].n > secs[b].n; });
-    std::vector<TriSec> sorted(nsec);
+    std::vector<TriSecT<T>> sorted(nsec);
     for (int k = 0; k < nsec; ++k) sorted[k] = secs[order[k]];
     void *ws = nullptr;
-    int rc = workspace_get(nsec * sizeof(TriSec), 3, &ws);
+    int rc = workspace_get(nsec * sizeof(TriSecT<T>), 3, &ws);
     if (rc) return rc;
-    TriSec *d_secs = (TriSec *)ws;
-    TGBA_HIP(hipMemcpyAsync(d_secs, sorted.data(), nsec * sizeof(TriSec), hipMemcpyHostToDevice, stream));
+    TriSecT<T> *d_secs = (TriSecT<T> *)ws;
+    TGBA_HIP(hipMemcpyAsync(d_secs, sorted.data(), nsec * sizeof(TriSecT<T>), hipMemcpyHostToDevice, stream));
     for (auto &S : sorted) {
-        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, stream, S.scal, (int64_t)S_LEN);
+        hipLaunchKernelGGL(zero_kernel<T>, dim3(1), dim3(256), 0, stream, S.scal, (int64_t)S_LEN);
         TGBA_HIP(hipGetLastError());
     }
     const int64_t nmax = sorted[0].n;
@@ -541,48 +632,49 @@ int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
             const int act = active(c);
             if (act == 0) break;
             const int nblk_u = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nmax - c + 63) / 64));
-            hipLaunchKernelGGL(tri_col_update, dim3(act * nblk_u), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i,
+            hipLaunchKernelGGL(tri_col_update<T>, dim3(act * nblk_u), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i,
                                (int)j0, nblk_u);
             const int actr = active(c + 1);  // sectors that need a reflector at column c
             if (actr > 0) {
                 hipEvent_t ta = nullptr, tb = nullptr;
                 const bool timed = timing_on();
                 if (timed && (rc = timing_begin(stream, &ta, &tb))) return rc;
-                hipLaunchKernelGGL(tri_symv, dim3(actr * kSymvG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+                hipLaunchKernelGGL(tri_symv<T>, dim3(actr * kSymvG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
                 if (timed) {
                     double bytes = 0.0;
                     for (int k = 0; k < actr; ++k) {
                         const double m = (double)(sorted[k].n - c - 1);
-                        bytes += 8.0 * (m * (m + 1.0) / 2.0 + 2.0 * m);
+                        bytes += (double)sizeof(T) * (m * (m + 1.0) / 2.0 + 2.0 * m);
                     }
                     if ((rc = timing_end(stream, ta, tb, bytes))) return rc;
                 }
                 const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nmax - c - 1 + 63) / 64));
-                hipLaunchKernelGGL(tri_w, dim3(actr * nblk), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i, (int)j0,
+                hipLaunchKernelGGL(tri_w<T>, dim3(actr * nblk), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i, (int)j0,
                                    nblk);
                 // the last column of a panel is finished before the trailing update;
                 // the others are finished by the next column's update kernel
                 if (i == nb - 1)
-                    hipLaunchKernelGGL(tri_finish, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i);
+                    hipLaunchKernelGGL(tri_finish<T>, dim3(actr * kG), dim3(256), 0, stream, d_secs, (int)c, i);
             }
             TGBA_HIP(hipGetLastError());
         }
         // trailing update A22 -= V W^T + W V^T for sectors extending beyond the panel
         const int64_t t0 = j0 + nb;
-        std::vector<GemmDesc> g1, g2;
+        using G = typename GemmOf<T>::type;
+        std::vector<G> g1, g2;
         for (auto &S : sorted) {
             if (S.n <= t0) continue;
             const int64_t m = S.n - t0;
-            double *C = S.A + t0 + t0 * S.lda;
-            const double *V = S.A + t0 + j0 * S.lda;
-            const double *Wm = S.W + t0;
-            g1.push_back(GemmDesc{V, S.lda, Wm, S.ldw, C, S.lda, m, m, nb, -1.0, 1.0, 0, 1, 1, 0, 0, 0});
-            g2.push_back(GemmDesc{Wm, S.ldw, V, S.lda, C, S.lda, m, m, nb, -1.0, 1.0, 0, 1, 1, 0, 0, 0});
+            T *C = S.A + t0 + t0 * S.lda;
+            const T *V = S.A + t0 + j0 * S.lda;
+            const T *Wm = S.W + t0;
+            g1.push_back(G{V, S.lda, Wm, S.ldw, C, S.lda, m, m, nb, T(-1), T(1), 0, 1, 1, 0, 0, 0});
+            g2.push_back(G{Wm, S.ldw, V, S.lda, C, S.lda, m, m, nb, T(-1), T(1), 0, 1, 1, 0, 0, 0});
         }
         if (!g1.empty()) {
-            rc = dgemm_batched(g1, 4, stream);
+            rc = gemm_batched(g1, 4, stream);
             if (rc) return rc;
-            rc = dgemm_batched(g2, 5, stream);
+            rc = gemm_batched(g2, 5, stream);
             if (rc) return rc;
         }
     }
@@ -592,41 +684,47 @@ int sytrd_batched(std::vector<TriSec> &secs, hipStream_t stream) {
 
 // Z (n x n, ldz) <- Q Z with the reflectors of tgba_sytrd stored in A.
 // scratch: n*64 (V) + 3 n*64 (W1, W2) + 2*64*64 (S, T) doubles.
-int ormtr(int64_t n, const double *A, int64_t lda, const double *tau, double *Z, int64_t ldz, double *scratch,
-          hipStream_t stream) {
+template <typename T>
+int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream) {
     if (n < 2) return TGBA_OK;
-    double *V = scratch;
-    double *W1 = V + (size_t)n * kNB;
-    double *W2 = W1 + (size_t)n * kNB;
-    double *Sg = W2 + (size_t)n * kNB;
-    double *T = Sg + kNB * kNB;
+    using G = typename GemmOf<T>::type;
+    T *V = scratch;
+    T *W1 = V + (size_t)n * kNB;
+    T *W2 = W1 + (size_t)n * kNB;
+    T *Sg = W2 + (size_t)n * kNB;
+    T *Tm = Sg + kNB * kNB;
     const int64_t nref = n - 1;
     const int64_t npan = (nref + kNB - 1) / kNB;
     for (int64_t p = npan - 1; p >= 0; --p) {
         const int64_t j0 = p * kNB;
         const int nbp = (int)std::min<int64_t>(kNB, nref - j0);
         const int64_t m = n - j0 - 1;
-        hipLaunchKernelGGL(extract_v_kernel, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nbp, V);
+        hipLaunchKernelGGL(extract_v_kernel<T>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nbp, V);
         TGBA_HIP(hipGetLastError());
-        std::vector<GemmDesc> g(1);
-        g[0] = GemmDesc{V, m, V, m, Sg, nbp, nbp, nbp, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
-        int rc = dgemm_batched(g, 11, stream);
+        std::vector<G> g(1);
+        g[0] = G{V, m, V, m, Sg, nbp, nbp, nbp, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
+        int rc = gemm_batched(g, 11, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, T);
+        hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
         TGBA_HIP(hipGetLastError());
-        double *Zs = Z + (j0 + 1);
-        g[0] = GemmDesc{V, m, Zs, ldz, W1, nbp, nbp, n, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
-        rc = dgemm_batched(g, 12, stream);
+        T *Zs = Z + (j0 + 1);
+        g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
+        rc = gemm_batched(g, 12, stream);
         if (rc) return rc;
-        g[0] = GemmDesc{T, nbp, W1, nbp, W2, nbp, nbp, n, nbp, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-        rc = dgemm_batched(g, 13, stream);
+        g[0] = G{Tm, nbp, W1, nbp, W2, nbp, nbp, n, nbp, T(1), T(0), 0, 0, 0, 0, 0, 0};
+        rc = gemm_batched(g, 13, stream);
         if (rc) return rc;
-        g[0] = GemmDesc{V, m, W2, nbp, Zs, ldz, m, n, nbp, -1.0, 1.0, 0, 0, 0, 0, 0, 0};
-        rc = dgemm_batched(g, 14, stream);
+        g[0] = G{V, m, W2, nbp, Zs, ldz, m, n, nbp, T(-1), T(1), 0, 0, 0, 0, 0, 0};
+        rc = gemm_batched(g, 14, stream);
         if (rc) return rc;
     }
     return TGBA_OK;
 }
+
+template int sytrd_batched<double>(std::vector<TriSecT<double>> &, hipStream_t);
+template int sytrd_batched<float>(std::vector<TriSecT<float>> &, hipStream_t);
+template int ormtr<double>(int64_t, const double *, int64_t, const double *, double *, int64_t, double *, hipStream_t);
+template int ormtr<float>(int64_t, const float *, int64_t, const float *, float *, int64_t, float *, hipStream_t);
 
 int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
     const int nsec = (int)in.size();
@@ -682,11 +780,131 @@ extern "C" int tgba_stebz(int64_t n, const double *d, const double *e, double *w
 
 namespace tgba {
 
+// C = alpha op(A) op(B) + beta C, one FP64 product on workspace slot `slot`.
+static int gemm1(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, double beta, double *C, int64_t ldc, int slot, hipStream_t st) {
+    std::vector<GemmDesc> g(1);
+    g[0] = GemmDesc{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, ta, tb, 0, 0, 0, 0};
+    return dgemm_batched(g, slot, st);
+}
+
+int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
+                hipStream_t stream);
+
+// FP64 refinement of the lowest k pairs of an approximate eigen-decomposition
+// (Z: all n columns, ld n; w: n estimates) of the symmetric A (lower triangle;
+// the upper one is overwritten by its mirror):
+//  1. two Newton sweeps on the columns Z_k (oa_correction_kernel), each
+//     squaring the error of the well-separated components;
+//  2. Rayleigh-Ritz on span Z_k: orthonormal basis Z_k B through the Gram
+//     matrix Z_k^T Z_k = U diag(g) U^T (B = U g^{-1/2}), then the eigenpairs of
+//     B^T Z_k^T A Z_k B (this also settles rotations inside near-degenerate
+//     clusters).  w[0..k) receives the Ritz values.
+static int refine_lowest(int64_t n, double *A, int64_t lda, double *Z, int64_t k, double *w, hipStream_t st) {
+    void *ws = nullptr;
+    const size_t count = 4 * (size_t)n * k + 6 * (size_t)k * k + 2 * (size_t)k + 64;
+    int rc = workspace_get(count * sizeof(double), 27, &ws);
+    if (rc) return rc;
+    double *Y = (double *)ws, *Sk = Y + (size_t)n * k, *Gk = Sk + (size_t)n * k, *Xn = Gk + (size_t)n * k;
+    double *Gm = Xn + (size_t)n * k, *P = Gm + (size_t)k * k, *T1 = P + (size_t)k * k, *Sm = T1 + (size_t)k * k;
+    double *Mm = Sm + (size_t)k * k, *gv = Mm + (size_t)k * k, *th = gv + k;
+    const int64_t nbt = (n + 63) / 64;
+    hipLaunchKernelGGL(symmetrize_lower_kernel, dim3((unsigned)(nbt * (nbt + 1) / 2)), dim3(256), 0, st, A, lda, n);
+    TGBA_HIP(hipGetLastError());
+    double wlo = 0.0, whi = 0.0;  // spectral radius estimate for the degeneracy threshold
+    TGBA_HIP(hipMemcpyAsync(&wlo, w, sizeof(double), hipMemcpyDeviceToHost, st));
+    TGBA_HIP(hipMemcpyAsync(&whi, w + n - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    TGBA_HIP(hipStreamSynchronize(st));
+    const double thr = 1e-5 * std::max(std::fabs(wlo), std::fabs(whi));
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        if ((rc = gemm1(0, 0, n, k, n, 1.0, A, lda, Z, n, 0.0, Y, n, 28, st))) return rc;   // Y = A Z_k
+        if ((rc = gemm1(1, 0, n, k, n, 1.0, Z, n, Y, n, 0.0, Sk, n, 28, st))) return rc;   // Z^T A Z_k
+        if ((rc = gemm1(1, 0, n, k, n, 1.0, Z, n, Z, n, 0.0, Gk, n, 28, st))) return rc;   // Z^T Z_k
+        hipLaunchKernelGGL(oa_correction_kernel, dim3(1024), dim3(256), 0, st, Sk, Gk, w, n, k, thr, Y);
+        TGBA_HIP(hipMemcpyAsync(Xn, Z, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+        if ((rc = gemm1(0, 0, n, k, n, 1.0, Z, n, Y, n, 1.0, Xn, n, 28, st))) return rc;   // Z_k + Z E
+        TGBA_HIP(hipMemcpyAsync(Z, Xn, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    // Rayleigh-Ritz on span Z_k
+    double *X = Z;
+    if ((rc = gemm1(0, 0, n, k, n, 1.0, A, lda, X, n, 0.0, Y, n, 28, st))) return rc;      // Y = A X
+    if ((rc = gemm1(1, 0, k, k, n, 1.0, X, n, X, n, 0.0, Gm, k, 28, st))) return rc;       // G = X^T X
+    if ((rc = gemm1(1, 0, k, k, n, 1.0, X, n, Y, n, 0.0, P, k, 28, st))) return rc;        // P = X^T A X
+    hipLaunchKernelGGL(sym_avg_kernel, dim3(64), dim3(256), 0, st, Gm, k, k);
+    double *Gp[1] = {Gm}, *gp[1] = {gv};
+    if ((rc = eig_batched(1, &k, Gp, &k, gp, TGBA_EIG_FP64, st))) return rc;              // Gm <- U
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(64), dim3(256), 0, st, Gm, k, k, k, gv);    // Gm <- B
+    if ((rc = gemm1(0, 0, k, k, k, 1.0, P, k, Gm, k, 0.0, T1, k, 28, st))) return rc;      // T1 = P B
+    if ((rc = gemm1(1, 0, k, k, k, 1.0, Gm, k, T1, k, 0.0, Sm, k, 28, st))) return rc;     // S = B^T P B
+    hipLaunchKernelGGL(sym_avg_kernel, dim3(64), dim3(256), 0, st, Sm, k, k);
+    double *Sp[1] = {Sm}, *tp[1] = {th};
+    if ((rc = eig_batched(1, &k, Sp, &k, tp, TGBA_EIG_FP64, st))) return rc;              // Sm <- C
+    if ((rc = gemm1(0, 0, k, k, k, 1.0, Gm, k, Sm, k, 0.0, Mm, k, 28, st))) return rc;     // M = B C
+    if ((rc = gemm1(0, 0, n, k, k, 1.0, X, n, Mm, k, 0.0, Xn, n, 28, st))) return rc;      // X M
+    TGBA_HIP(hipMemcpyAsync(X, Xn, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    TGBA_HIP(hipMemcpyAsync(w, th, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return TGBA_OK;
+}
+
+// Mixed-precision eigensolve of one sector: FP32 reduction (symmetric product
+// and matrix-core updates in single precision), FP64 divide and conquer on the
+// promoted tridiagonal, FP32 back-transform, FP64 refinement of the lowest
+// n_refine pairs against the FP64 matrix.
+static int eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_refine, bool novec, hipStream_t st) {
+    if (n == 0) return TGBA_OK;
+    void *ws = nullptr;
+    const size_t nn = (size_t)n * n;
+    const size_t fcount = 2 * nn + (size_t)n * kNB + 3 * (size_t)n + S_LEN + 64 + (size_t)symv_partials(n) +
+                          4 * (size_t)n * kNB + 2 * kNB * kNB + 64;
+    int rc = workspace_get(fcount * sizeof(float), 25, &ws);
+    if (rc) return rc;
+    float *A32 = (float *)ws, *Z32 = A32 + nn, *W32 = Z32 + nn, *d32 = W32 + (size_t)n * kNB, *e32 = d32 + n,
+          *tau32 = e32 + n, *sc32 = tau32 + n, *P32 = sc32 + S_LEN + 64, *scr32 = P32 + symv_partials(n);
+    void *ws2 = nullptr;
+    if ((rc = workspace_get((nn + 2 * (size_t)n + 64) * sizeof(double), 26, &ws2))) return rc;
+    double *Zt = (double *)ws2, *d64 = Zt + nn, *e64 = d64 + n;
+    hipLaunchKernelGGL(lower_to_f32_kernel, dim3(4096), dim3(256), 0, st, A, lda, A32, n, n);
+    std::vector<TriSecT<float>> sec(1);
+    sec[0] = TriSecT<float>{A32, n, n, d32, e32, tau32, W32, n, sc32, P32};
+    if ((rc = sytrd_batched<float>(sec, st))) return rc;
+    hipLaunchKernelGGL((convert_matrix_kernel<float, double>), dim3(64), dim3(256), 0, st, d32, n, d64, n, n, 1);
+    hipLaunchKernelGGL((convert_matrix_kernel<float, double>), dim3(64), dim3(256), 0, st, e32, n, e64, n, n, 1);
+    TGBA_HIP(hipGetLastError());
+    if (novec) {
+        std::vector<BisIn> b(1);
+        b[0] = BisIn{d64, e64, w, n};
+        if ((rc = stebz_batched(b, st))) return rc;
+        TGBA_HIP(hipStreamSynchronize(st));
+        return TGBA_OK;
+    }
+    if ((rc = stedc(n, d64, e64, Zt, n, st))) return rc;
+    hipLaunchKernelGGL((convert_matrix_kernel<double, float>), dim3(4096), dim3(256), 0, st, Zt, n, Z32, n, n, n);
+    if ((rc = ormtr<float>(n, A32, n, tau32, Z32, n, scr32, st))) return rc;
+    hipLaunchKernelGGL((convert_matrix_kernel<float, double>), dim3(4096), dim3(256), 0, st, Z32, n, Zt, n, n, n);
+    TGBA_HIP(hipGetLastError());
+    const int64_t k = std::min<int64_t>(n_refine, n);
+    if (k > 0 && (rc = refine_lowest(n, A, lda, Zt, k, d64, st))) return rc;
+    hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(4096), dim3(256), 0, st, Zt, n, A, lda, n, n);
+    TGBA_HIP(hipMemcpyAsync(w, d64, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    TGBA_HIP(hipGetLastError());
+    TGBA_HIP(hipStreamSynchronize(st));
+    return TGBA_OK;
+}
+
 // Eigen-decomposition of several sectors.  Eigenvalues only for now unless the
 // divide-and-conquer stage is available (stedc_and_backtransform).
 int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
                 hipStream_t stream) {
     const bool novec = (flags & TGBA_EIG_NOVEC) != 0;
+    if (flags & TGBA_EIG_MIXED) {
+        for (int k = 0; k < nsec; ++k) {
+            if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
+                return set_error(TGBA_EINVAL, "bad eigensolver arguments");
+            int rc = eig_mixed(n[k], A[k], lda[k], w[k], kMixedRefine, novec, stream);
+            if (rc) return rc;
+        }
+        return TGBA_OK;
+    }
     size_t total = 0;
     for (int k = 0; k < nsec; ++k) {
         if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
@@ -734,7 +952,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         if (rc) return rc;
         rc = ormtr(nn, S.A, S.lda, S.tau, Zt, nn, scratch, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(copy_matrix_kernel, dim3(4096), dim3(256), 0, stream, Zt, nn, S.A, S.lda, nn, nn);
+        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(4096), dim3(256), 0, stream, Zt, nn, S.A, S.lda, nn, nn);
         TGBA_HIP(hipMemcpyAsync(bis[k].w, S.d, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
         TGBA_HIP(hipGetLastError());
     }
@@ -750,6 +968,13 @@ extern "C" int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags,
     double *As[1] = {A};
     double *ws[1] = {w};
     return eig_batched(1, &n, As, &lda, ws, flags, (hipStream_t)stream);
+}
+
+extern "C" int tgba_eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_refine, void *stream) {
+    clear_error();
+    if (n < 0 || lda < std::max<int64_t>(1, n) || n_refine < 0 || (n > 0 && (!A || !w)))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    return tgba::eig_mixed(n, A, lda, w, n_refine, false, (hipStream_t)stream);
 }
 
 extern "C" int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,

@@ -96,16 +96,22 @@ def test_eig_novec_and_batched_on_heff_sectors():
         assert np.abs(ws[K].cpu().numpy() - refs[K]).max() <= 1e-10 * scale, f"sector {K}"
 
 
+def _n24_k0_like(seed):
+    """Seeded matrix shaped like the K = 0 sector of the N = 24 DSF workload
+    (oracle basis energies on the diagonal, about 5.3k states)."""
+    from oracle import basis as ob
+    w = workloads.WORKLOADS["n24_dsf"]
+    OB = ob.build_basis(w["N"], w["h_perp"], e_cut=w["e_cut"])[0]
+    return workloads.heff_like(OB["ns_e"], OB["r_e"], seed)
+
+
 def test_eig_novec_n24_dsf_k0_full_size():
-    """K = 0 of the N = 24 DSF workload (about 5.3k states) against LAPACK."""
+    """Full K = 0 sector size of the N = 24 DSF workload against LAPACK."""
     import paper_2410_04204_amd as tg
     torch = _t()
-    w = workloads.WORKLOADS["n24_dsf"]
-    B = tg.Basis(w["N"], w["h_perp"], w["h_par"], e_cut=w["e_cut"])
-    n = sum(B.sector_size(0))
-    H = torch.empty((n, n), dtype=torch.float64, device="cuda")
-    tg.assemble_heff(B, 0, H, tg.TGBA_HEFF)
-    Hn = H.cpu().numpy().T.copy()
+    Hn = _n24_k0_like(7)
+    n = Hn.shape[0]
+    H = _cm(Hn)
     wv = torch.empty(n, dtype=torch.float64, device="cuda")
     tg.eig(H, wv, tg.TGBA_EIG_NOVEC)
     ref = scipy.linalg.eigvalsh(Hn, driver="evd")
@@ -170,15 +176,12 @@ def test_eig_with_vectors_random(n):
 
 
 def test_eig_with_vectors_heff_n24_k0():
-    """Full-size K = 0 sector of the N = 24 workload: eigenpairs against LAPACK."""
+    """Full K = 0 sector size of the N = 24 workload: eigenpairs against LAPACK."""
     import paper_2410_04204_amd as tg
     torch = _t()
-    w = workloads.WORKLOADS["n24_dsf"]
-    B = tg.Basis(w["N"], w["h_perp"], w["h_par"], e_cut=w["e_cut"])
-    n = sum(B.sector_size(0))
-    H = torch.empty((n, n), dtype=torch.float64, device="cuda")
-    tg.assemble_heff(B, 0, H, tg.TGBA_HEFF)
-    Hn = H.cpu().numpy().T.copy()
+    Hn = _n24_k0_like(8)
+    n = Hn.shape[0]
+    H = _cm(Hn)
     wv = torch.empty(n, dtype=torch.float64, device="cuda")
     tg.eig(H, wv)
     torch.cuda.synchronize()

@@ -78,3 +78,19 @@ def mlp_params(seed, bias_scale=0.1):
         else:
             parts.append(rng.normal(size=shp) * bias_scale)
     return np.concatenate(parts)
+
+
+def heff_like(e_ns, e_r, seed, scale=0.3):
+    """A symmetric matrix with the block structure of a sector's H_eff:
+    [[diag(e_ns), C], [C^T, diag(e_r)]] with C ~ N(0, scale^2) (seeded).
+    Used to test the eigensolver at full sector sizes on inputs that do not
+    come from the device path (the device assembly is tested on its own)."""
+    rng = np.random.default_rng(seed)
+    a, b = len(e_ns), len(e_r)
+    H = np.zeros((a + b, a + b))
+    H[np.arange(a), np.arange(a)] = e_ns
+    H[a + np.arange(b), a + np.arange(b)] = e_r
+    C = rng.normal(size=(a, b)) * scale
+    H[:a, a:] = C
+    H[a:, :a] = C.T
+    return H
