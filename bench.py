@@ -22,7 +22,8 @@ kernel's roofline and the oracle's CPU baseline are reported beside it, and,
 after the timed steps, the second half of the metric: the K = 0 basis
 dimension at which the N = 40 gap is within 1e-6 of the pool's, for the energy
 cutoff and for the learned selection (network trained on the device at
-N = 16..24).
+N = 16..24), and the FP64-versus-mixed-precision eigensolve of the N = 40
+K = 0 sector at E_cut = 10.85.
 """
 import argparse
 import json
@@ -50,6 +51,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-gap-metric", action="store_true",
                    help="skip the learned-versus-cutoff basis dimension (second half of the metric)")
+    p.add_argument("--no-mixed", action="store_true",
+                   help="skip the mixed-precision eigensolve measurement (N=40 K=0, E_cut 10.85)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (5 times), the reference for "
                         "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -112,6 +115,48 @@ def gap_metric(tol=1e-6):
             "gap_err_cutoff": r["cutoff"]["gap_err"], "gap_err_learned": r["learned"]["gap_err"],
             "train_rows": int(F.shape[0]), "train_loss": [float(loss[0]), float(loss[-1])],
             "train_s": t_train, "sweep_s": r["seconds"]}
+
+
+def mixed_precision(n_refine=200):
+    """FP64 versus mixed-precision eigen-decomposition (with vectors) of the
+    N = 40 K = 0 sector at E_cut = 10.85: wall times, the difference of the
+    lowest n_refine eigenvalues, the largest unrefined difference and that of
+    S(0, omega) computed from each set of eigenvectors."""
+    import torch
+    import paper_2410_04204_amd as tg
+    w = workloads.WORKLOADS["n40_mixed"]
+    N = w["N"]
+    B = tg.Basis(N, w["h_perp"], w["h_par"], chi=[10 ** 9 if K == 0 else 0 for K in range(N)], pool_e_cut=w["e_cut"])
+    n = sum(B.sector_size(0))
+    H = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    G = torch.empty_like(H)
+    tg.assemble_heff(B, 0, H, tg.TGBA_HEFF | tg.TGBA_LOWER)
+    tg.assemble_heff(B, 0, G, tg.TGBA_GAMMA1)
+    omega = torch.as_tensor(workloads.omega_grid(4096, 8.0), device="cuda")
+    out = {}
+    for name in ("fp64", "mixed"):
+        A = H.clone()
+        ev = torch.empty(n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if name == "fp64":
+            tg.eig(A, ev, tg.TGBA_EIG_FP64)
+        else:
+            tg.eig_mixed(A, ev, n_refine)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        S = torch.empty(4096, dtype=torch.float64, device="cuda")
+        tg.dsf(A, ev, G, N, omega, 0.02, S)
+        out[name] = (ev.cpu().numpy(), S.cpu().numpy(), dt)
+        del A
+    wf, Sf, tf = out["fp64"]
+    wm, Sm, tm = out["mixed"]
+    return {"workload": f"N=40 K=0, E_cut={w['e_cut']}, n={n}, eigenvectors", "n_refine": n_refine,
+            "fp64_s": tf, "mixed_s": tm, "speedup": tf / tm,
+            "lowest_refined_max_abs_diff": float(np.abs(wm[:n_refine] - wf[:n_refine]).max()),
+            "unrefined_max_abs_diff": float(np.abs(np.sort(wm) - wf).max()),
+            "dsf_max_rel_diff": float(np.abs(Sm - Sf).max() / np.abs(Sf).max()),
+            "max_abs_eigenvalue": float(np.abs(wf).max())}
 
 
 def main():
@@ -229,6 +274,10 @@ def main():
         Hs.clear()  # free the N=40 sector matrices before the sweep
         torch.cuda.empty_cache()
         out["basis_dim_for_1e-6_gap"] = gap_metric()
+    if not a.no_mixed:
+        Hs.clear()
+        torch.cuda.empty_cache()
+        out["mixed_precision"] = mixed_precision()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, B, a.cpu_seconds)
     print(json.dumps(out), flush=True)
