@@ -176,6 +176,23 @@ int tgba_assemble_heff(const tgba_basis *basis, int K, void *H, int64_t ld, int 
 int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks, void *const *H,
                                const int64_t *ld, int flags, void *stream);
 
+/*
+ * Assembly plan: the launches of one batched assembly (the same arguments as
+ * tgba_assemble_heff_batched) captured once into a hipGraph whose nodes are
+ * kernels only; the sector descriptors live in device memory the plan owns.
+ * tgba_plan_launch replays the whole assembly of every listed sector on
+ * `stream` with one graph launch (no host work per sector); the output
+ * matrices, the basis and its contraction table must stay alive and in place
+ * while the plan is used.  The launch shape is the autotuner's pick for this
+ * assembly class if one was made (see tgba_autotune_enable), else the default.
+ * Errors: as tgba_assemble_heff_batched; TGBA_EDEVICE if capture fails.
+ */
+typedef struct tgba_plan tgba_plan;
+int tgba_assembly_plan_create(const tgba_basis *basis, int nsec, const int *Ks, void *const *H, const int64_t *ld,
+                              int flags, tgba_plan **out);
+int tgba_plan_launch(tgba_plan *plan, void *stream);
+void tgba_plan_free(tgba_plan *plan);
+
 /* ---- dense symmetric eigensolve (Method section: diagonalise H_eff) ----- */
 
 #define TGBA_EIG_FP64 0x0    /* all stages in double precision                          */
@@ -337,6 +354,24 @@ int tgba_mlp_select(int64_t n, const float *scores, int64_t keep, int64_t *selec
                     void *stream);
 
 /* ---- bookkeeping -------------------------------------------------------- */
+
+/*
+ * Autotuner of launch shapes.  On the first call with a new shape class the
+ * library times every candidate launch shape of a kernel on the live data
+ * (HIP events; the timed launches repeat an idempotent launch, so results do
+ * not change) and keeps the fastest for the rest of the process:
+ *   tri_symv (symmetric product of the reduction): minimum waves per SIMD
+ *     {2, 3} x workgroups per sector {512, 1024, 2048}, keyed by precision,
+ *     number of sectors and log2 of the largest order;
+ *   assemble_rows (H_eff rows): 2 or 4 bra rows per workgroup, keyed by N,
+ *     gauge and log2 of the element count (calls of >= 1e6 elements).
+ * tgba_autotune_enable(1) turns tuning on (the default), 0 off (fixed default
+ * shapes), -1 forgets every decision and keeps tuning on.  tgba_autotune_report
+ * writes a JSON object {key: {"pick": i, "ms": [...]}} of the decisions into
+ * buf (cap bytes, NUL terminated); *len receives its full length.
+ */
+int tgba_autotune_enable(int on);
+int tgba_autotune_report(char *buf, int64_t cap, int64_t *len);
 
 /*
  * Opt-in timing of the eigensolver's dominant kernel, the symmetric

@@ -18,7 +18,7 @@ __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "eig_mixed"
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
-           "mlp_select"]
+           "mlp_select", "autotune_enable", "autotune_report", "AssemblyPlan"]
 
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 32, 256, 140289
 
@@ -134,6 +134,36 @@ def eig(A, w, flags=TGBA_EIG_FP64, stream=None):
     n = w.shape[0]
     _lib.check(_lib.load().tgba_eig(int(n), _lib.ptr(A), _ld(A), _lib.ptr(w), int(flags), _lib.stream_handle(stream)))
     return w
+
+
+class AssemblyPlan:
+    """A batched assembly captured once in a hipGraph (tgba_assembly_plan_create);
+    launch() replays it.  Keeps references to the basis and the output tensors."""
+
+    def __init__(self, basis, Ks, Hs, flags=TGBA_HEFF):
+        self._keep = (basis, list(Hs))
+        nsec = len(Ks)
+        self._k = (ctypes.c_int * nsec)(*[int(K) for K in Ks])
+        self._h = (ctypes.c_void_p * nsec)(*[H.data_ptr() for H in Hs])
+        self._ld = (ctypes.c_int64 * nsec)(*[_ld(H) for H in Hs])
+        p = ctypes.c_void_p()
+        _lib.check(_lib.load().tgba_assembly_plan_create(basis.handle, nsec, self._k, self._h, self._ld, int(flags),
+                                                         ctypes.byref(p)))
+        self._p = p
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().tgba_plan_launch(self._p, _lib.stream_handle(stream)))
+
+    def free(self):
+        if getattr(self, "_p", None):
+            _lib.load().tgba_plan_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def eig_mixed(A, w, n_refine=200, stream=None):
@@ -275,3 +305,18 @@ def mlp_select(scores, keep, stream=None):
     _lib.check(_lib.load().tgba_mlp_select(n, _lib.ptr(scores), int(keep), _lib.ptr(out), ctypes.byref(cnt),
                                            _lib.stream_handle(stream)))
     return out[:cnt.value]
+
+
+def autotune_enable(on=True):
+    """1 / True: tune launch shapes on first use (default); 0: fixed defaults; -1: forget decisions."""
+    _lib.check(_lib.load().tgba_autotune_enable(int(on)))
+
+
+def autotune_report():
+    """Decisions of the autotuner: {key: {"pick": i, "ms": [per candidate]}}."""
+    import json
+    n = ctypes.c_int64()
+    _lib.check(_lib.load().tgba_autotune_report(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _lib.check(_lib.load().tgba_autotune_report(buf, n.value + 1, ctypes.byref(n)))
+    return json.loads(buf.value.decode())

@@ -25,7 +25,8 @@ EXPORTS = [
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
     "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
-    "tgba_mlp_select", "tgba_eig_mixed",
+    "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
+    "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free",
 ]
 
 
@@ -86,6 +87,13 @@ def load():
     L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
                              c_double, c_void_p, c_int64, c_void_p]
     L.tgba_timing_enable.argtypes = [c_int]
+    L.tgba_autotune_enable.argtypes = [c_int]
+    L.tgba_assembly_plan_create.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int,
+                                            ctypes.POINTER(c_void_p)]
+    L.tgba_plan_launch.argtypes = [c_void_p, c_void_p]
+    L.tgba_plan_free.argtypes = [c_void_p]
+    L.tgba_plan_free.restype = None
+    L.tgba_autotune_report.argtypes = [ctypes.c_char_p, c_int64, P_i64]
     L.tgba_eig_mixed.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p]
     L.tgba_mlp_features.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p]
     L.tgba_mlp_forward.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
@@ -98,7 +106,7 @@ def load():
     L.tgba_mlp_select.argtypes = [c_int64, c_void_p, c_int64, c_void_p, P_i64, c_void_p]
     L.tgba_timing_read.argtypes = [ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
     for name in EXPORTS:
-        if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free"):
+        if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free", "tgba_plan_free"):
             getattr(L, name).restype = c_int
     _lib = L
     return L

@@ -504,9 +504,11 @@ __global__ void __launch_bounds__(kThreads) mirror_upper_kernel(const SectorDesc
 
 template <int ROWS, bool CPLX>
 int launch_rows(const SectorDesc *d_desc, int nsec, int64_t nblocks, size_t lds, const Basis *b, double r_max,
-                double scale, int with_diag, int lower, unsigned long long *counters, hipStream_t stream) {
+                double scale, int with_diag, int lower, unsigned long long *counters, hipStream_t stream,
+                bool set_attr = true) {
     auto kern = assemble_rows_kernel<ROWS, CPLX>;
-    if (lds > 65536) TGBA_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (set_attr && lds > 65536)
+        TGBA_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kThreads), lds, stream, d_desc, nsec, b->N, b->d_table, r_max,
                        b->c0, scale, with_diag, lower, counters);
     TGBA_HIP(hipGetLastError());
@@ -515,20 +517,29 @@ int launch_rows(const SectorDesc *d_desc, int nsec, int64_t nblocks, size_t lds,
 
 }  // namespace
 
-// Rows per workgroup as a function of N and the LDS budget (chosen by tuning).
-static int rows_for(int N) { return N <= 48 ? 4 : 2; }
+// Rows per workgroup: the autotuner times 2 and 4 (each row's arithmetic is
+// the same either way); without tuning, a rule from the LDS budget.
+static int rows_default(int N) { return N <= 48 ? 4 : 2; }
+constexpr int kRowChoices[2] = {2, 4};
 
-int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, const int64_t *ld, int flags,
-                     hipStream_t stream) {
-    const bool cplx = (flags & TGBA_GAUGE_PAPER) != 0;
-    const int lower = (flags & TGBA_LOWER) ? 1 : 0;
-    const int with_diag = (flags & TGBA_GAMMA1) ? 0 : 1;
-    const double scale = (flags & TGBA_GAMMA1) ? 1.0 : -(double)b->N * b->h_par;
-    const int N = b->N;
-    const int rows = rows_for(N);
-    std::vector<SectorDesc> desc;
-    int64_t nblocks = 0;
+namespace {
+
+// Validated per-call state of an assembly (shared by eager calls and plans).
+struct AsmSetup {
+    std::vector<SectorDesc> desc;  // one per sector, block layout not yet set
     int max_m = 0;
+    double elements = 0.0;
+    bool cplx = false;
+    int lower = 0, with_diag = 1;
+    double scale = 0.0;
+};
+
+int asm_setup(const Basis *b, int nsec, const int *Ks, void *const *H, const int64_t *ld, int flags, AsmSetup &o) {
+    o.cplx = (flags & TGBA_GAUGE_PAPER) != 0;
+    o.lower = (flags & TGBA_LOWER) ? 1 : 0;
+    o.with_diag = (flags & TGBA_GAMMA1) ? 0 : 1;
+    o.scale = (flags & TGBA_GAMMA1) ? 1.0 : -(double)b->N * b->h_par;
+    const int N = b->N;
     for (int i = 0; i < nsec; ++i) {
         const int K = Ks[i];
         if (K < 0 || K >= N) return set_error(TGBA_EINVAL, "sector index out of range");
@@ -546,62 +557,214 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
         d.ld = ld[i];
         d.n_ns = sc.n_ns;
         d.n_r = sc.n_r;
+        o.desc.push_back(d);
+        o.max_m = std::max(o.max_m, mb);
+        o.elements += (double)sc.n_ns * (double)sc.n_r;
+    }
+    // all descriptors with the same LDS layout: pad max_m_bra to the global maximum
+    for (auto &d : o.desc) d.max_m_bra = o.max_m;
+    return TGBA_OK;
+}
+
+// Block layout for `rows` bra rows per workgroup; returns the grid size and LDS bytes.
+int64_t asm_blocks(const AsmSetup &o, int N, int rows, std::vector<SectorDesc> &dd, size_t &lds) {
+    dd = o.desc;
+    int64_t nblocks = 0;
+    for (auto &d : dd) {
         d.first_block = nblocks;
-        d.nblk = (sc.n_ns + rows - 1) / rows;
-        if (d.nblk == 0 && sc.n_r > 0) d.nblk = 1;  // R-only sector: one block fills the R x R block
-        d.max_m_bra = mb;
-        desc.push_back(d);
+        d.nblk = (d.n_ns + rows - 1) / rows;
+        if (d.nblk == 0 && d.n_r > 0) d.nblk = 1;  // R-only sector: one block fills the R x R block
         nblocks += d.nblk;
-        max_m = std::max(max_m, mb);
     }
     // R x R blocks may exist even for sectors without NS states
-    const size_t lds = sizeof(double) * ((size_t)rows * N * (N - 1) / 2 + (size_t)(max_m + N) * (max_m + N));
-    // all descriptors with the same LDS layout: pad max_m_bra to the global maximum
-    for (auto &d : desc) d.max_m_bra = max_m;
-    void *ws = nullptr;
-    const size_t desc_bytes = desc.size() * sizeof(SectorDesc);
-    int rc = workspace_get(desc_bytes, 0, &ws);
-    if (rc) return rc;
-    SectorDesc *d_desc = (SectorDesc *)ws;
-    unsigned long long *d_cnt = b->d_counters;
-    TGBA_HIP(hipMemcpyAsync(d_desc, desc.data(), desc_bytes, hipMemcpyHostToDevice, stream));
-    // the matrix's absolute scale for the growth check
-    const double r_max = 1.0;  // R entries are O(1): contractions of normalised operators
-    if (nblocks > 0) {
-        if (rows == 4) {
-            rc = cplx ? launch_rows<4, true>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream)
-                      : launch_rows<4, false>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream);
-        } else {
-            rc = cplx ? launch_rows<2, true>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream)
-                      : launch_rows<2, false>(d_desc, nsec, nblocks, lds, b, r_max, scale, with_diag, lower, d_cnt, stream);
-        }
-        if (rc) return rc;
+    lds = sizeof(double) * ((size_t)rows * N * (N - 1) / 2 + (size_t)(o.max_m + N) * (o.max_m + N));
+    return nblocks;
+}
+
+// Tile layout of the mirror pass (full-matrix mode).
+int64_t asm_tiles(const AsmSetup &o, std::vector<SectorDesc> &td) {
+    td = o.desc;
+    int64_t ntiles = 0;
+    for (auto &d : td) {
+        d.first_block = ntiles;
+        ntiles += ((d.n_ns + 63) / 64) * ((d.n_r + 63) / 64);
     }
-    if (!lower) {
-        // second descriptor set: tiles of the B block
-        std::vector<SectorDesc> tdesc = desc;
-        int64_t ntiles = 0;
-        for (auto &d : tdesc) {
-            d.first_block = ntiles;
-            ntiles += ((d.n_ns + 63) / 64) * ((d.n_r + 63) / 64);
+    return ntiles;
+}
+
+int asm_launch_rows(const Basis *b, const AsmSetup &o, int rows, const SectorDesc *d_desc, int nsec, int64_t nblocks,
+                    size_t lds, hipStream_t stream, bool set_attr) {
+    if (nblocks == 0) return TGBA_OK;
+    const double r_max = 1.0;  // R entries are O(1): contractions of normalised operators
+    unsigned long long *cnt = b->d_counters;
+    if (rows == 4)
+        return o.cplx ? launch_rows<4, true>(d_desc, nsec, nblocks, lds, b, r_max, o.scale, o.with_diag, o.lower, cnt,
+                                             stream, set_attr)
+                      : launch_rows<4, false>(d_desc, nsec, nblocks, lds, b, r_max, o.scale, o.with_diag, o.lower, cnt,
+                                              stream, set_attr);
+    return o.cplx ? launch_rows<2, true>(d_desc, nsec, nblocks, lds, b, r_max, o.scale, o.with_diag, o.lower, cnt,
+                                         stream, set_attr)
+                  : launch_rows<2, false>(d_desc, nsec, nblocks, lds, b, r_max, o.scale, o.with_diag, o.lower, cnt,
+                                          stream, set_attr);
+}
+
+int asm_launch_mirror(const AsmSetup &o, const SectorDesc *d_tdesc, int nsec, int64_t ntiles, hipStream_t stream) {
+    if (ntiles == 0) return TGBA_OK;
+    if (o.cplx)
+        hipLaunchKernelGGL(mirror_upper_kernel<true>, dim3((unsigned)ntiles), dim3(kThreads), 0, stream, d_tdesc, nsec);
+    else
+        hipLaunchKernelGGL(mirror_upper_kernel<false>, dim3((unsigned)ntiles), dim3(kThreads), 0, stream, d_tdesc, nsec);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+std::string asm_key(int N, const AsmSetup &o) {
+    int lg = 0;
+    while (std::ldexp(1.0, lg + 1) <= o.elements) ++lg;
+    return "assemble_rows/N=" + std::to_string(N) + (o.cplx ? "/complex" : "/real") + "/log2elements=" +
+           std::to_string(lg);
+}
+
+}  // namespace
+
+int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, const int64_t *ld, int flags,
+                     hipStream_t stream) {
+    AsmSetup o;
+    int rc = asm_setup(b, nsec, Ks, H, ld, flags, o);
+    if (rc) return rc;
+    const int N = b->N;
+    const size_t desc_bytes = o.desc.size() * sizeof(SectorDesc);
+    void *ws = nullptr;
+    if ((rc = workspace_get(desc_bytes, 0, &ws))) return rc;
+    SectorDesc *d_desc = (SectorDesc *)ws;
+    auto run = [&](int cand) -> int {
+        const int rows = kRowChoices[cand];
+        std::vector<SectorDesc> dd;
+        size_t lds = 0;
+        const int64_t nblocks = asm_blocks(o, N, rows, dd, lds);
+        TGBA_HIP(hipMemcpyAsync(d_desc, dd.data(), desc_bytes, hipMemcpyHostToDevice, stream));
+        return asm_launch_rows(b, o, rows, d_desc, nsec, nblocks, lds, stream, true);
+    };
+    const int fallback = rows_default(N) == 4 ? 1 : 0;
+    int pick = fallback;
+    if (o.elements >= 1e6) {  // worth timing: tuning runs are repeats of the same (idempotent) launch
+        const std::string key = asm_key(N, o);
+        if (autotune_known(key)) {
+            if ((rc = autotune(key, 2, fallback, run, stream, &pick))) return rc;  // cached pick, nothing runs
+        } else {
+            // keep the diagnostic counters of the basis out of the tuning runs
+            unsigned long long saved[4];
+            TGBA_HIP(hipMemcpyAsync(saved, b->d_counters, sizeof(saved), hipMemcpyDeviceToHost, stream));
+            TGBA_HIP(hipStreamSynchronize(stream));
+            if ((rc = autotune(key, 2, fallback, run, stream, &pick))) return rc;
+            TGBA_HIP(hipMemcpyAsync(b->d_counters, saved, sizeof(saved), hipMemcpyHostToDevice, stream));
+            TGBA_HIP(hipStreamSynchronize(stream));
         }
+    }
+    if ((rc = run(pick))) return rc;
+    if (!o.lower) {
+        std::vector<SectorDesc> td;
+        const int64_t ntiles = asm_tiles(o, td);
         if (ntiles > 0) {
             void *ws2 = nullptr;
-            rc = workspace_get(desc_bytes, 1, &ws2);
-            if (rc) return rc;
-            TGBA_HIP(hipMemcpyAsync(ws2, tdesc.data(), desc_bytes, hipMemcpyHostToDevice, stream));
-            if (cplx)
-                hipLaunchKernelGGL(mirror_upper_kernel<true>, dim3((unsigned)ntiles), dim3(kThreads), 0, stream,
-                                   (const SectorDesc *)ws2, nsec);
-            else
-                hipLaunchKernelGGL(mirror_upper_kernel<false>, dim3((unsigned)ntiles), dim3(kThreads), 0, stream,
-                                   (const SectorDesc *)ws2, nsec);
-            TGBA_HIP(hipGetLastError());
+            if ((rc = workspace_get(desc_bytes, 1, &ws2))) return rc;
+            TGBA_HIP(hipMemcpyAsync(ws2, td.data(), desc_bytes, hipMemcpyHostToDevice, stream));
+            if ((rc = asm_launch_mirror(o, (const SectorDesc *)ws2, nsec, ntiles, stream))) return rc;
         }
     }
     return TGBA_OK;
 }
 
+}  // namespace tgba
+
+// ---- assembly plan: the launches of a batched assembly captured in a hipGraph ----
+
+struct tgba_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *d_desc = nullptr, *d_tdesc = nullptr;
+};
+
+extern "C" void tgba_plan_free(tgba_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_desc) (void)hipFree(p->d_desc);
+    if (p->d_tdesc) (void)hipFree(p->d_tdesc);
+    delete p;
+}
+
+extern "C" int tgba_assembly_plan_create(const tgba_basis *hb, int nsec, const int *Ks, void *const *H,
+                                         const int64_t *ld, int flags, tgba_plan **out) {
+    using namespace tgba;
+    clear_error();
+    if (!out) return set_error(TGBA_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    if (!hb || nsec <= 0 || !Ks || !H || !ld) return set_error(TGBA_EINVAL, "bad arguments");
+    if (flags & ~(TGBA_GAMMA1 | TGBA_GAUGE_PAPER | TGBA_LOWER)) return set_error(TGBA_EINVAL, "unknown flags");
+    const Basis *b = &hb->b;
+    AsmSetup o;
+    int rc = asm_setup(b, nsec, Ks, H, ld, flags, o);
+    if (rc) return rc;
+    const int N = b->N;
+    // the launch shape: the autotuner's pick if this class was tuned, else the default
+    int pick = rows_default(N) == 4 ? 1 : 0;
+    if (o.elements >= 1e6 && autotune_known(asm_key(N, o))) {
+        auto none = [](int) { return TGBA_OK; };
+        if ((rc = autotune(asm_key(N, o), 2, pick, none, nullptr, &pick))) return rc;
+    }
+    const int rows = kRowChoices[pick];
+    std::vector<SectorDesc> dd, td;
+    size_t lds = 0;
+    const int64_t nblocks = asm_blocks(o, N, rows, dd, lds);
+    const int64_t ntiles = o.lower ? 0 : asm_tiles(o, td);
+    tgba_plan *p = new (std::nothrow) tgba_plan();
+    if (!p) return set_error(TGBA_ENOMEM, "host allocation failed");
+    const size_t bytes = dd.size() * sizeof(SectorDesc);
+    hipStream_t cs = nullptr;
+    auto fail = [&](int code, const char *msg) {
+        if (cs) (void)hipStreamDestroy(cs);
+        tgba_plan_free(p);
+        return set_error(code, msg);
+    };
+    if (hipMalloc(&p->d_desc, bytes) != hipSuccess || (ntiles > 0 && hipMalloc(&p->d_tdesc, bytes) != hipSuccess))
+        return fail(TGBA_ENOMEM, "plan descriptor allocation failed");
+    if (hipMemcpy(p->d_desc, dd.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        (ntiles > 0 && hipMemcpy(p->d_tdesc, td.data(), bytes, hipMemcpyHostToDevice) != hipSuccess))
+        return fail(TGBA_EDEVICE, "plan descriptor upload failed");
+    // kernel attributes are set outside the capture
+    if (lds > 65536) {
+        const void *k = rows == 4 ? (o.cplx ? (const void *)assemble_rows_kernel<4, true> : (const void *)assemble_rows_kernel<4, false>)
+                                  : (o.cplx ? (const void *)assemble_rows_kernel<2, true> : (const void *)assemble_rows_kernel<2, false>);
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return fail(TGBA_EDEVICE, "kernel attribute failed");
+    }
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(TGBA_EDEVICE, "stream creation failed");
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(TGBA_EDEVICE, "capture failed");
+    rc = asm_launch_rows(b, o, rows, (const SectorDesc *)p->d_desc, nsec, nblocks, lds, cs, false);
+    if (!rc && ntiles > 0) rc = asm_launch_mirror(o, (const SectorDesc *)p->d_tdesc, nsec, ntiles, cs);
+    const hipError_t ec = hipStreamEndCapture(cs, &p->graph);
+    if (rc) {
+        std::string msg = tgba_last_error();
+        fail(rc, "capture of the assembly launches failed");
+        return set_error(rc, msg.c_str());
+    }
+    if (ec != hipSuccess || !p->graph) return fail(TGBA_EDEVICE, "capture failed");
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(TGBA_EDEVICE, "graph instantiation failed");
+    (void)hipStreamDestroy(cs);
+    *out = p;
+    return TGBA_OK;
+}
+
+extern "C" int tgba_plan_launch(tgba_plan *p, void *stream) {
+    tgba::clear_error();
+    if (!p || !p->exec) return tgba::set_error(TGBA_EINVAL, "bad plan");
+    TGBA_HIP(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return TGBA_OK;
+}
+
+namespace tgba {
 }  // namespace tgba
 
 extern "C" int tgba_assemble_heff(const tgba_basis *hb, int K, void *H, int64_t ld, int flags, void *stream) {

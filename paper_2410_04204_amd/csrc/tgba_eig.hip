@@ -35,7 +35,11 @@ template <typename T> using gptr = const T __attribute__((address_space(1))) *;
 constexpr int kNB = 64;       // panel width
 constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXED
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
-constexpr int kSymvG = 1024;  // workgroups per active sector for the symmetric product
+// Launch shapes of the symmetric product the autotuner chooses from:
+// (minimum waves per SIMD, workgroups per active sector).
+constexpr int kSymvOcc[2] = {2, 3};
+constexpr int kSymvGrid[3] = {512, 1024, 2048};
+constexpr int kSymvDefault = 1;  // occupancy 2, 1024 workgroups
 
 // Per-sector scalars, double-buffered by column parity p = c & 1 so that a
 // kernel may read the previous column's values while the current column's
@@ -159,9 +163,9 @@ __device__ __forceinline__ int64_t bytes_to_end(int64_t n, int64_t lda, int64_t 
     return ((n - 1 - c0) * lda + (n - r0)) * (int64_t)sizeof(T);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256, 2) tri_symv(TriSecT<T> *secs, int c, int i, int j0) {
-    const int s = blockIdx.x / kSymvG, lb = blockIdx.x % kSymvG;
+template <typename T, int OCC>
+__global__ void __launch_bounds__(256, OCC) tri_symv(TriSecT<T> *secs, int c, int i, int j0, int G) {
+    const int s = blockIdx.x / G, lb = blockIdx.x % G;
     TriSecT<T> S = secs[s];
     const int64_t o = c + 1, n = S.n;
     if (o >= n) return;
@@ -187,7 +191,7 @@ __global__ void __launch_bounds__(256, 2) tri_symv(TriSecT<T> *secs, int c, int 
     __shared__ T vcol[64];
     __shared__ T ypart[4][kSeg];
     const int64_t nmat = nJ * nG, nitem = nmat + (i > 0 ? 2 * nG : 0);
-    for (int64_t item = lb; item < nitem; item += kSymvG) {
+    for (int64_t item = lb; item < nitem; item += G) {
         if (item >= nmat) {
             // panel item: segment g of t1 = W^T v (kind 0) or t2 = V^T v (kind 1);
             // wave wv owns the panel columns t = 16 wv + jj
@@ -598,6 +602,18 @@ __global__ void sym_avg_kernel(double *S, int64_t lds, int64_t k) {
 
 // ---- host drivers -------------------------------------------------------------
 
+// Launch shape cand = occupancy index * 3 + grid index.
+template <typename T>
+static int launch_symv(int cand, TriSecT<T> *d_secs, int actr, int c, int i, int j0, hipStream_t st) {
+    const int G = kSymvGrid[cand % 3];
+    if (cand / 3 == 0)
+        hipLaunchKernelGGL((tri_symv<T, 2>), dim3(actr * G), dim3(256), 0, st, d_secs, c, i, j0, G);
+    else
+        hipLaunchKernelGGL((tri_symv<T, 3>), dim3(actr * G), dim3(256), 0, st, d_secs, c, i, j0, G);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
 int64_t symv_partials(int64_t n) { return (symv_strips(n) + symv_segments(n)) * n + symv_segments(n) * 2 * kNB; }
 
 template <typename T>
@@ -620,6 +636,7 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
         TGBA_HIP(hipGetLastError());
     }
     const int64_t nmax = sorted[0].n;
+    int symv_pick = -1;
     auto active = [&](int64_t c) {  // sectors with c < n
         int a = 0;
         while (a < nsec && sorted[a].n > c) ++a;
@@ -636,10 +653,20 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
                                (int)j0, nblk_u);
             const int actr = active(c + 1);  // sectors that need a reflector at column c
             if (actr > 0) {
+                if (symv_pick < 0) {
+                    // first column of the call: time every launch shape on it (the
+                    // product at a fixed column is idempotent) unless already known
+                    auto run = [&](int cand) { return launch_symv<T>(cand, d_secs, actr, (int)c, i, (int)j0, stream); };
+                    int lg = 0;
+                    while ((int64_t(1) << (lg + 1)) <= nmax) ++lg;
+                    const std::string key = std::string("tri_symv/") + (sizeof(T) == 8 ? "f64" : "f32") +
+                                            "/sectors=" + std::to_string(actr) + "/log2n=" + std::to_string(lg);
+                    if ((rc = autotune(key, 6, kSymvDefault, run, stream, &symv_pick))) return rc;
+                }
                 hipEvent_t ta = nullptr, tb = nullptr;
                 const bool timed = timing_on();
                 if (timed && (rc = timing_begin(stream, &ta, &tb))) return rc;
-                hipLaunchKernelGGL(tri_symv<T>, dim3(actr * kSymvG), dim3(256), 0, stream, d_secs, (int)c, i, (int)j0);
+                if ((rc = launch_symv<T>(symv_pick, d_secs, actr, (int)c, i, (int)j0, stream))) return rc;
                 if (timed) {
                     double bytes = 0.0;
                     for (int k = 0; k < actr; ++k) {

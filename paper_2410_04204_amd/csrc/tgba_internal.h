@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,15 @@ int build_contraction_table(Basis *b, hipStream_t stream);
 // Device workspace cache (grow-only, per device and slot).
 int workspace_get(size_t bytes, int slot, void **out);
 int release_all_workspace();
+
+// Autotuner: on first use of `key`, time run(c) for every candidate c (one
+// warm-up and two timed launches each, HIP events on `st`, host wait) and keep
+// the fastest; later calls return the cached pick.  run(c) must be idempotent.
+// With tuning off (tgba_autotune_enable(0)) the fallback is returned.
+int autotune(const std::string &key, int ncand, int fallback, const std::function<int(int)> &run, hipStream_t st,
+             int *pick);
+// True when autotune(key, ...) would run nothing (tuning off or key decided).
+bool autotune_known(const std::string &key);
 
 // Opt-in event timing (tgba_timing_enable): bracket one launch with two events
 // from a recycled pool and record its algorithmic bytes.

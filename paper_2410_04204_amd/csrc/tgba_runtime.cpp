@@ -1,7 +1,12 @@
 // Device workspace cache: grow-only buffers per (device, slot), released on
 // request.  Kernels that need scratch memory (descriptors, counters, panel
 // buffers) take it from here so that repeated calls do not allocate.
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "tgba_internal.h"
@@ -88,7 +93,109 @@ int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double bytes) {
     return TGBA_OK;
 }
 
+// ---- autotuner --------------------------------------------------------------------
+namespace {
+struct Choice {
+    int pick;
+    std::vector<double> ms;  // per candidate (best of the timed runs)
+};
+std::mutex g_amu;
+bool g_autotune = true;
+std::map<std::string, Choice> g_choices;
+}  // namespace
+
+int autotune(const std::string &key, int ncand, int fallback, const std::function<int(int)> &run, hipStream_t st,
+             int *pick) {
+    {
+        std::lock_guard<std::mutex> lk(g_amu);
+        if (!g_autotune || ncand <= 1) {
+            *pick = fallback;
+            return TGBA_OK;
+        }
+        auto it = g_choices.find(key);
+        if (it != g_choices.end()) {
+            *pick = it->second.pick;
+            return TGBA_OK;
+        }
+    }
+    hipEvent_t a, b;
+    TGBA_HIP(hipEventCreate(&a));
+    TGBA_HIP(hipEventCreate(&b));
+    Choice ch{fallback, std::vector<double>(ncand, 0.0)};
+    double best = 1e300;
+    int rc = TGBA_OK;
+    for (int c = 0; c < ncand && rc == TGBA_OK; ++c) {
+        if ((rc = run(c))) break;  // warm-up (first launch of a variant)
+        double m = 1e300;
+        for (int rep = 0; rep < 2 && rc == TGBA_OK; ++rep) {
+            if (hipEventRecord(a, st) != hipSuccess) { rc = set_error(TGBA_EDEVICE, "event record failed"); break; }
+            if ((rc = run(c))) break;
+            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                rc = set_error(TGBA_EDEVICE, "event wait failed");
+                break;
+            }
+            float e = 0.0f;
+            (void)hipEventElapsedTime(&e, a, b);
+            m = std::min(m, (double)e);
+        }
+        ch.ms[c] = m;
+        if (m < best) {
+            best = m;
+            ch.pick = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_amu);
+    g_choices[key] = ch;
+    *pick = ch.pick;
+    return TGBA_OK;
+}
+
+bool autotune_known(const std::string &key) {
+    std::lock_guard<std::mutex> lk(g_amu);
+    return !g_autotune || g_choices.count(key) > 0;
+}
+
 }  // namespace tgba
+
+extern "C" int tgba_autotune_enable(int on) {
+    tgba::clear_error();
+    std::lock_guard<std::mutex> lk(tgba::g_amu);
+    tgba::g_autotune = (on != 0);
+    if (on < 0) tgba::g_choices.clear();  // forget every decision (and keep tuning on)
+    if (on < 0) tgba::g_autotune = true;
+    return TGBA_OK;
+}
+
+extern "C" int tgba_autotune_report(char *buf, int64_t cap, int64_t *len) {
+    tgba::clear_error();
+    std::string out = "{";
+    {
+        std::lock_guard<std::mutex> lk(tgba::g_amu);
+        bool first = true;
+        for (auto &kv : tgba::g_choices) {
+            char tmp[64];
+            out += first ? "\"" : ", \"";
+            first = false;
+            out += kv.first + "\": {\"pick\": " + std::to_string(kv.second.pick) + ", \"ms\": [";
+            for (size_t i = 0; i < kv.second.ms.size(); ++i) {
+                std::snprintf(tmp, sizeof(tmp), "%s%.4f", i ? ", " : "", kv.second.ms[i]);
+                out += tmp;
+            }
+            out += "]}";
+        }
+    }
+    out += "}";
+    if (len) *len = (int64_t)out.size();
+    if (buf && cap > 0) {
+        const size_t n = std::min<size_t>((size_t)cap - 1, out.size());
+        std::memcpy(buf, out.data(), n);
+        buf[n] = 0;
+    }
+    return TGBA_OK;
+}
 
 extern "C" int tgba_timing_enable(int on) {
     tgba::clear_error();

@@ -66,3 +66,11 @@ def test_timing_hook_without_launches():
     assert tg.timing_read() == (0.0, 0, 0.0)
     tg.timing_enable(False)
     assert _lib.load().tgba_timing_read(None, None, None) == -1
+
+
+def test_autotune_switches_and_empty_report():
+    import paper_2410_04204_amd as tg
+    tg.autotune_enable(-1)
+    assert tg.autotune_report() == {}
+    tg.autotune_enable(False)
+    tg.autotune_enable(True)
