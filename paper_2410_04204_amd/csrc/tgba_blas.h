@@ -22,6 +22,13 @@ struct GemmDesc {
     int pad;
     int64_t tiles_m;    // filled by dgemm_batched
     int64_t first_tile; // filled by dgemm_batched
+    // optional second part of the product: C = alpha (op(A) op(B) + op(A2) op(B2)) + beta C,
+    // op(A2) M x K2, op(B2) K2 x N, same transposition flags; K must be a multiple of 16
+    const double *A2 = nullptr;
+    int64_t lda2 = 0;
+    const double *B2 = nullptr;
+    int64_t ldb2 = 0;
+    int64_t K2 = 0;
 };
 
 // The same in single precision (FP32 matrix cores, v_mfma_f32_32x32x2f32).

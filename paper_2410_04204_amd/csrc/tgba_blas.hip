@@ -31,6 +31,101 @@ __device__ __forceinline__ int gemm_desc_of(const GemmDesc *d, int nd, int64_t b
     return lo;
 }
 
+// Raw buffer access: base = first element of the operand tile, `bytes` = how far
+// the operand extends from there (clamped to 32 bits); reads past it return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t op_rsrc(const double *base, int64_t bytes) {
+    const int nrec = (int)(uint32_t)(bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nrec, 0x00020000);
+}
+__device__ __forceinline__ double op_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// One K-tile (16) of op(A) (128 x 16) and op(B) (16 x 128) into registers:
+// thread t holds 8 values of each.  Entries with k >= K are zeroed explicitly;
+// rows/columns beyond M/N only feed outputs that are never stored, and reads
+// beyond an operand's extent return 0, so no access leaves the operands.
+struct TileRegs {
+    double a[8], b[8];
+};
+
+__device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_t n0, int64_t kt, int tid, TileRegs &r) {
+    // tiles with kt >= K come from the second part (A2, B2)
+    GemmDesc G = G0;
+    int64_t k0 = kt;
+    if (kt >= G0.K) {
+        G.A = G0.A2;
+        G.lda = G0.lda2;
+        G.B = G0.B2;
+        G.ldb = G0.ldb2;
+        G.K = G0.K2;
+        k0 = kt - G0.K;
+    }
+    const uint32_t la = (uint32_t)(G.lda * (int64_t)sizeof(double)), lb = (uint32_t)(G.ldb * (int64_t)sizeof(double));
+    if (!G.transA) {  // op(A)[i][k] = A[i + k lda]; i = tid & 127, k = (tid >> 7) + 2 s
+        const double *base = G.A + m0 + k0 * G.lda;
+        const auto rs = op_rsrc(base, ((G.M - m0) + (G.K - 1 - k0) * G.lda) * (int64_t)sizeof(double));
+        const int i = tid & 127, kq = tid >> 7;
+        const uint32_t voff = (uint32_t)i * 8u + (uint32_t)kq * la;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double x = op_ld(rs, voff, (uint32_t)(2 * s) * la);
+            r.a[s] = (k0 + kq + 2 * s < G.K) ? x : 0.0;
+        }
+    } else {  // op(A)[i][k] = A[k + i lda]; k = tid & 15, i = (tid >> 4) + 16 s
+        const double *base = G.A + k0 + m0 * G.lda;
+        const auto rs = op_rsrc(base, ((G.K - k0) + (G.M - 1 - m0) * G.lda) * (int64_t)sizeof(double));
+        const int k = tid & 15, iq = tid >> 4;
+        const uint32_t voff = (uint32_t)k * 8u + (uint32_t)iq * la;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double x = op_ld(rs, voff, (uint32_t)(16 * s) * la);
+            r.a[s] = (k0 + k < G.K) ? x : 0.0;
+        }
+    }
+    if (!G.transB) {  // op(B)[k][j] = B[k + j ldb]; k = tid & 15, j = (tid >> 4) + 16 s
+        const double *base = G.B + k0 + n0 * G.ldb;
+        const auto rs = op_rsrc(base, ((G.K - k0) + (G.N - 1 - n0) * G.ldb) * (int64_t)sizeof(double));
+        const int k = tid & 15, jq = tid >> 4;
+        const uint32_t voff = (uint32_t)k * 8u + (uint32_t)jq * lb;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double x = op_ld(rs, voff, (uint32_t)(16 * s) * lb);
+            r.b[s] = (k0 + k < G.K) ? x : 0.0;
+        }
+    } else {  // op(B)[k][j] = B[j + k ldb]; j = tid & 127, k = (tid >> 7) + 2 s
+        const double *base = G.B + n0 + k0 * G.ldb;
+        const auto rs = op_rsrc(base, ((G.N - n0) + (G.K - 1 - k0) * G.ldb) * (int64_t)sizeof(double));
+        const int j = tid & 127, kq = tid >> 7;
+        const uint32_t voff = (uint32_t)j * 8u + (uint32_t)kq * lb;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double x = op_ld(rs, voff, (uint32_t)(2 * s) * lb);
+            r.b[s] = (k0 + kq + 2 * s < G.K) ? x : 0.0;
+        }
+    }
+}
+
+__device__ __forceinline__ void store_tile(const GemmDesc &G, int tid, const TileRegs &r, double (*As)[LDS_STRIDE],
+                                           double (*Bs)[LDS_STRIDE]) {
+    if (!G.transA) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) As[(tid >> 7) + 2 * s][tid & 127] = r.a[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) As[tid & 15][(tid >> 4) + 16 * s] = r.a[s];
+    }
+    if (!G.transB) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) Bs[tid & 15][(tid >> 4) + 16 * s] = r.b[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) Bs[(tid >> 7) + 2 * s][tid & 127] = r.b[s];
+    }
+}
+
+// Software pipeline: the next K-tile's global loads are in flight while the
+// matrix cores work on the current one from LDS.
 __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
     __shared__ double As[TK][LDS_STRIDE];  // As[k][i]
     __shared__ double Bs[TK][LDS_STRIDE];  // Bs[k][j]
@@ -55,40 +150,14 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t k0 = 0; k0 < G.K; k0 += TK) {
-        // op(A)[i][k], i in [m0, m0+128), k in [k0, k0+16): 2048 values, 8 per thread
-        if (!G.transA) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int i = tid & 127, k = (tid >> 7) + 2 * s;
-                const int64_t gi = m0 + i, gk = k0 + k;
-                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gi + gk * G.lda] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int k = tid & 15, i = (tid >> 4) + 16 * s;
-                const int64_t gi = m0 + i, gk = k0 + k;
-                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gk + gi * G.lda] : 0.0;
-            }
-        }
-        // op(B)[k][j]
-        if (!G.transB) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int k = tid & 15, j = (tid >> 4) + 16 * s;
-                const int64_t gj = n0 + j, gk = k0 + k;
-                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gk + gj * G.ldb] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int j = tid & 127, k = (tid >> 7) + 2 * s;
-                const int64_t gj = n0 + j, gk = k0 + k;
-                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gj + gk * G.ldb] : 0.0;
-            }
-        }
+    TileRegs r;
+    const int64_t Ktot = G.K + G.K2;
+    if (Ktot > 0) load_tile(G, m0, n0, 0, tid, r);
+    for (int64_t k0 = 0; k0 < Ktot; k0 += TK) {
+        __syncthreads();  // the previous tile's readers are done
+        store_tile(G, tid, r, As, Bs);
         __syncthreads();
+        if (k0 + TK < Ktot) load_tile(G, m0, n0, k0 + TK, tid, r);
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
             double af[4], bf[4];
@@ -101,7 +170,6 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
     }
     // epilogue: D[4r + l/16][l%16] of block (a, b)
 #pragma unroll
@@ -109,16 +177,20 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = m0 + 64 * wy + 16 * a + 4 * r + (lane >> 4);
+            for (int rr = 0; rr < 4; ++rr) {
+                const int64_t i = m0 + 64 * wy + 16 * a + 4 * rr + (lane >> 4);
                 const int64_t j = n0 + 64 * wx + 16 * b + (lane & 15);
                 if (i < G.M && j < G.N && (!G.lower || i >= j)) {
                     double *c = G.C + i + j * G.ldc;
-                    const double v = G.alpha * acc[a][b][r];
+                    const double v = G.alpha * acc[a][b][rr];
                     *c = (G.beta == 0.0) ? v : v + G.beta * (*c);
                 }
             }
 }
+
+}  // namespace
+
+namespace {
 
 // ---- single precision: v_mfma_f32_32x32x2f32 ---------------------------------
 // Lane layout: operand a of lane l is A[l%32][l/32], operand b is B[l/32][l%32];

@@ -699,10 +699,23 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
             g2.push_back(G{Wm, S.ldw, V, S.lda, C, S.lda, m, m, nb, T(-1), T(1), 0, 1, 1, 0, 0, 0});
         }
         if (!g1.empty()) {
-            rc = gemm_batched(g1, 4, stream);
-            if (rc) return rc;
-            rc = gemm_batched(g2, 5, stream);
-            if (rc) return rc;
+            if constexpr (sizeof(T) == 8) {
+                // one product of depth 2 nb: C -= [V W] [W V]^T (C read and written once)
+                for (size_t q = 0; q < g1.size(); ++q) {
+                    g1[q].A2 = g2[q].A;
+                    g1[q].lda2 = g2[q].lda;
+                    g1[q].B2 = g2[q].B;
+                    g1[q].ldb2 = g2[q].ldb;
+                    g1[q].K2 = g2[q].K;
+                }
+                rc = gemm_batched(g1, 4, stream);
+                if (rc) return rc;
+            } else {
+                rc = gemm_batched(g1, 4, stream);
+                if (rc) return rc;
+                rc = gemm_batched(g2, 5, stream);
+                if (rc) return rc;
+            }
         }
     }
     return TGBA_OK;
