@@ -36,10 +36,10 @@ constexpr int kNB = 64;       // panel width
 constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXED
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
 // Launch shapes of the symmetric product the autotuner chooses from:
-// (minimum waves per SIMD, workgroups per active sector).
+// (minimum waves per SIMD, cap on the number of workgroups).
 constexpr int kSymvOcc[2] = {2, 3};
-constexpr int kSymvGrid[3] = {512, 1024, 2048};
-constexpr int kSymvDefault = 1;  // occupancy 2, 1024 workgroups
+constexpr int kSymvGrid[3] = {4096, 16384, 65536};  // caps on the total workgroup count
+constexpr int kSymvDefault = 1;  // occupancy 2, up to 16384 workgroups
 
 // Per-sector scalars, double-buffered by column parity p = c & 1 so that a
 // kernel may read the previous column's values while the current column's
@@ -163,35 +163,60 @@ __device__ __forceinline__ int64_t bytes_to_end(int64_t n, int64_t lda, int64_t 
     return ((n - 1 - c0) * lda + (n - r0)) * (int64_t)sizeof(T);
 }
 
-template <typename T, int OCC>
-__global__ void __launch_bounds__(256, OCC) tri_symv(TriSecT<T> *secs, int c, int i, int j0, int G) {
-    const int s = blockIdx.x / G, lb = blockIdx.x % G;
-    TriSecT<T> S = secs[s];
-    const int64_t o = c + 1, n = S.n;
-    if (o >= n) return;
-    T *sc = S.scal + (c & 1) * S_SET;
-    T tau, beta, scale;
-    reflector_scalars(sc[S_XN2], sc[S_ALPHA], tau, beta, scale);
-    if (lb == 0 && threadIdx.x == 0) {
-        S.e[c] = beta;
-        S.tau[c] = tau;
-        sc[S_TAU] = tau;
-        sc[S_SCALE] = scale;
-        S.A[o + (int64_t)c * S.lda] = T(1);
-    }
-    const int64_t m = n - o;
+// Work items of one sector at column c (trailing order m): nJ * nG matrix items
+// and, inside a panel (i > 0), 2 nG panel items.
+__host__ __device__ __forceinline__ int64_t symv_items(int64_t n, int64_t c, int i) {
+    const int64_t m = n - c - 1;
+    if (m <= 0) return 0;
     const int64_t nJ = (m + 63) / 64, nG = (m + kSeg - 1) / kSeg;
-    T *Prow = S.P;
-    T *Pcol = Prow + symv_strips(n) * n;
-    T *Pt = Pcol + symv_segments(n) * n;
+    return nJ * nG + (i > 0 ? 2 * nG : 0);
+}
+
+constexpr int kSymvMaxSecs = 255;  // sectors a flat launch indexes through LDS
+
+template <typename T, int OCC>
+__global__ void __launch_bounds__(256, OCC) tri_symv(TriSecT<T> *secs, int nact, int c, int i, int j0) {
+    const int64_t o = c + 1;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const gptr<T> vsrc = (gptr<T>)(S.A + (int64_t)c * S.lda);  // v[r] = A[r][c] * scale (r > o), 1 at r = o
-    const uint32_t ldb = (uint32_t)(S.lda * (int64_t)sizeof(T));
     __shared__ T vcol[64];
     __shared__ T ypart[4][kSeg];
-    const int64_t nmat = nJ * nG, nitem = nmat + (i > 0 ? 2 * nG : 0);
-    for (int64_t item = lb; item < nitem; item += G) {
+    __shared__ int64_t pref[kSymvMaxSecs + 1];  // items of sectors < s (launches have nact <= kSymvMaxSecs)
+    if ((int)threadIdx.x <= nact) {
+        int64_t acc = 0;
+        for (int q = 0; q < (int)threadIdx.x; ++q) acc += symv_items(secs[q].n, c, i);
+        pref[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    const int64_t total = pref[nact];
+    // the items of all active sectors form one list; workgroups stride through it
+    for (int64_t gitem = blockIdx.x; gitem < total; gitem += gridDim.x) {
+        int lo = 0, hi = nact - 1;  // sector of this item: pref[s] <= gitem < pref[s + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pref[mid] <= gitem) lo = mid; else hi = mid - 1;
+        }
+        const int64_t item = gitem - pref[lo];
+        const TriSecT<T> S = secs[lo];
+        T *sc = S.scal + (c & 1) * S_SET;
+        T tau, beta, scale;
+        reflector_scalars(sc[S_XN2], sc[S_ALPHA], tau, beta, scale);
+        const int64_t n = S.n;
+        if (item == 0 && threadIdx.x == 0) {  // one writer per sector
+            S.e[c] = beta;
+            S.tau[c] = tau;
+            sc[S_TAU] = tau;
+            sc[S_SCALE] = scale;
+            S.A[o + (int64_t)c * S.lda] = T(1);
+        }
+        const int64_t m = n - o;
+        const int64_t nJ = (m + 63) / 64, nG = (m + kSeg - 1) / kSeg;
+        T *Prow = S.P;
+        T *Pcol = Prow + symv_strips(n) * n;
+        T *Pt = Pcol + symv_segments(n) * n;
+        const gptr<T> vsrc = (gptr<T>)(S.A + (int64_t)c * S.lda);  // v[r] = A[r][c] * scale (r > o), 1 at r = o
+        const uint32_t ldb = (uint32_t)(S.lda * (int64_t)sizeof(T));
+        const int64_t nmat = nJ * nG;
         if (item >= nmat) {
             // panel item: segment g of t1 = W^T v (kind 0) or t2 = V^T v (kind 1);
             // wave wv owns the panel columns t = 16 wv + jj
@@ -602,14 +627,20 @@ __global__ void sym_avg_kernel(double *S, int64_t lds, int64_t k) {
 
 // ---- host drivers -------------------------------------------------------------
 
-// Launch shape cand = occupancy index * 3 + grid index.
+// Launch shape cand = occupancy index * 3 + grid-cap index; the grid covers
+// the items of all active sectors (capped), each workgroup striding through them.
 template <typename T>
-static int launch_symv(int cand, TriSecT<T> *d_secs, int actr, int c, int i, int j0, hipStream_t st) {
-    const int G = kSymvGrid[cand % 3];
+static int launch_symv(int cand, TriSecT<T> *d_secs, const std::vector<TriSecT<T>> &sorted, int actr, int c, int i,
+                       int j0, hipStream_t st) {
+    if (actr > kSymvMaxSecs) return set_error(TGBA_EUNSUPPORTED, "more than 255 sectors in one batched reduction");
+    int64_t items = 0;
+    for (int k = 0; k < actr; ++k) items += symv_items(sorted[k].n, c, i);
+    if (items == 0) return TGBA_OK;
+    const unsigned grid = (unsigned)std::min<int64_t>(items, kSymvGrid[cand % 3]);
     if (cand / 3 == 0)
-        hipLaunchKernelGGL((tri_symv<T, 2>), dim3(actr * G), dim3(256), 0, st, d_secs, c, i, j0, G);
+        hipLaunchKernelGGL((tri_symv<T, 2>), dim3(grid), dim3(256), 0, st, d_secs, actr, c, i, j0);
     else
-        hipLaunchKernelGGL((tri_symv<T, 3>), dim3(actr * G), dim3(256), 0, st, d_secs, c, i, j0, G);
+        hipLaunchKernelGGL((tri_symv<T, 3>), dim3(grid), dim3(256), 0, st, d_secs, actr, c, i, j0);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }
@@ -656,7 +687,7 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
                 if (symv_pick < 0) {
                     // first column of the call: time every launch shape on it (the
                     // product at a fixed column is idempotent) unless already known
-                    auto run = [&](int cand) { return launch_symv<T>(cand, d_secs, actr, (int)c, i, (int)j0, stream); };
+                    auto run = [&](int cand) { return launch_symv<T>(cand, d_secs, sorted, actr, (int)c, i, (int)j0, stream); };
                     int lg = 0;
                     while ((int64_t(1) << (lg + 1)) <= nmax) ++lg;
                     const std::string key = std::string("tri_symv/") + (sizeof(T) == 8 ? "f64" : "f32") +
@@ -666,7 +697,7 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
                 hipEvent_t ta = nullptr, tb = nullptr;
                 const bool timed = timing_on();
                 if (timed && (rc = timing_begin(stream, &ta, &tb))) return rc;
-                if ((rc = launch_symv<T>(symv_pick, d_secs, actr, (int)c, i, (int)j0, stream))) return rc;
+                if ((rc = launch_symv<T>(symv_pick, d_secs, sorted, actr, (int)c, i, (int)j0, stream))) return rc;
                 if (timed) {
                     double bytes = 0.0;
                     for (int k = 0; k < actr; ++k) {

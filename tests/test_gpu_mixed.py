@@ -6,6 +6,7 @@ Bars:
   residual |A x - theta x| <= 1e-10 ||A||, orthonormal to 1e-12;
 * unrefined eigenvalues: FP32 backward stability of the reduction,
   |lambda - lambda_LAPACK| <= 2e-6 ||A||_2 (u32 = 6e-8 times a modest growth in n);
+  unrefined eigenvectors orthonormal to n u32 (1e-4 at n = 1500);
 * S(omega) from the mixed eigenvectors: 1e-7 relative to max S (the weight
   sits on the refined low-lying states; measured 1e-9).
 Matrices are seeded and synthetic: random symmetric ones and ones shaped like
@@ -68,7 +69,8 @@ def test_mixed_refined_pairs_random(n, k):
         assert np.abs(A @ X - X * wn[:k]).max() <= 1e-10 * nrm
         assert np.abs(X.T @ X - np.eye(k)).max() <= 1e-12
     assert np.abs(np.sort(wn) - ref).max() <= 2e-6 * nrm
-    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-5
+    # FP32 back-transform: orthogonality error of order n u32 (9e-5 at n = 1500)
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-4
 
 
 def test_mixed_heff_like_n24_k0_lowest_200_and_dsf():
