@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--workload", default="n40_batched")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--chi-ref", type=int, default=45000, help="reference dimension of the n64_learned workload")
     p.add_argument("--no-gap-metric", action="store_true",
                    help="skip the learned-versus-cutoff basis dimension (second half of the metric)")
     p.add_argument("--no-mixed", action="store_true",
@@ -159,6 +160,36 @@ def mixed_precision(n_refine=200):
             "max_abs_eigenvalue": float(np.abs(wf).max())}
 
 
+def n64_learned(a):
+    """The N=64 learned-basis quench workload (one JSON line): the network is
+    trained on the device on quench weights of K = 0 runs at N = 16..24, picks
+    chi = 30000 states of the K = 0 pool (E_cut 11.5, M <= 10, about 1.06e6
+    candidates), and <sigma^x>(t) for t = 0..50 (dt 0.05) after the quench from
+    the H0 ground state is compared with the energy cutoff of the same dimension,
+    both against the energy cutoff of dimension 45000 as reference."""
+    import torch
+    from paper_2410_04204_amd import learned
+    w = workloads.WORKLOADS["n64_learned"]
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    F, L = learned.training_data(GAP_TRAIN_RUNS, target="quench")
+    p0 = torch.as_tensor(workloads.mlp_params(0).astype(np.float32), device="cuda")
+    p, loss = learned.train(F, L, p0, epochs=300)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained on {F.shape[0]} rows in {t_train:.1f} s")
+    nt = int(round(w["t_max"] / w["dt"])) + 1
+    r = learned.quench_comparison(w["N"], 1.0, w["pool_e_cut"], w["m_max"], w["chi"], a.chi_ref, p, nt=nt,
+                                  dt=w["dt"], h_par=0.1, log=log)
+    out = {"metric": "max_t |<sigma^x>(t) - reference| at equal basis dimension, learned vs cutoff",
+           "value": r["learned"]["max_abs_dev_sx"], "unit": "abs", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "n64_learned", "N": w["N"], "chi": w["chi"], "chi_reference": a.chi_ref,
+                      "pool_e_cut": w["pool_e_cut"], "m_max": w["m_max"], "t_max": w["t_max"], "dt": w["dt"]},
+           "cutoff_value": r["cutoff"]["max_abs_dev_sx"], "train_s": t_train, "runs": r}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -166,6 +197,9 @@ def main():
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "n64_learned":
+        n64_learned(a)
         return
     import torch
     import paper_2410_04204_amd as tg

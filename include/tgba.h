@@ -284,6 +284,13 @@ int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double *w, const 
                 void *stream);
 
 /*
+ * Spectral weights of an initial state: w_a = |(Z^T c~)_a|^2 (n, device) for the
+ * real-gauge eigenvectors Z and overlaps c~ of tgba_quench (Quench section: the
+ * time average of |B_b(t)|^2 is sum_a Z[b][a]^2 w_a without degeneracies).
+ */
+int tgba_quench_weights(int64_t n, const double *Z, int64_t ldz, const double *c, double *w, void *stream);
+
+/*
  * Overlaps <phi_a(post)|Phi_0> of a sector's basis with the initial state
  * Phi_0 = (|0,pre>_NS + s |0,pre>_R)/sqrt(2) (s = +1 or -1), the vacua of H0 at
  * the pre-quench transverse field h_perp_pre (closed form of eq. S5), written
@@ -342,10 +349,13 @@ int tgba_mlp_train(int64_t n, const float *X, int64_t ldx, const float *labels, 
 /* BF16 inference: scores y (n) of n feature rows. */
 int tgba_mlp_score(int64_t n, const float *X, int64_t ldx, const float *params, float *y, void *stream);
 
-/* Training labels log10(sum_{v < nvec} Z[a][v]^2 + 1e-30) for the n basis states
- * (Z column-major n x >= nvec, ldz >= n): the weight of each state in the lowest
- * nvec eigenvectors of a large-cutoff run. */
-int tgba_mlp_labels(int64_t n, const double *Z, int64_t ldz, int nvec, float *labels, void *stream);
+/* Training labels log10(sum_{v < nvec} w_v Z[a][v]^2 + 1e-30) for the n basis
+ * states (Z column-major n x >= nvec, ldz >= n; weights w (nvec, device) or NULL
+ * for w_v = 1): with unit weights, the weight of each state in the lowest nvec
+ * eigenvectors of a large-cutoff run; with w = tgba_quench_weights and nvec = n,
+ * its time-averaged weight in a quench (diagonal ensemble). */
+int tgba_mlp_labels(int64_t n, const double *Z, int64_t ldz, int64_t nvec, const double *weights, float *labels,
+                    void *stream);
 
 /* Positions (host array, ascending) of the `keep` largest of n device scores;
  * equal scores are taken in position order.  *n_selected = min(keep, n).

@@ -15,8 +15,9 @@ below is the plain definition, written for legibility:
 * mean-squared-error loss, its gradient by the chain rule, and Adam
   (Kingma & Ba 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8;
 * training over consecutive minibatches in the given sample order;
-* importance labels log10(sum_{v < nvec} Z[a, v]^2 + 1e-30) of the basis
-  states a in the lowest nvec eigenvectors;
+* importance labels log10(sum_{v < nvec} w_v Z[a, v]^2 + 1e-30) of the basis
+  states a in the lowest nvec eigenvectors (w_v = 1, or the spectral weights
+  of a quench's initial state: the diagonal ensemble);
 * the top-chi selection rule: largest score first, ties by (E, NS before R,
   mask).
 
@@ -183,9 +184,11 @@ def train(X, t, p, epochs, batch, lr, m=None, v=None, step0=0):
     return losses, step
 
 
-def importance_labels(Z, nvec):
-    """log10 of the weight of every basis state in the lowest nvec eigenvectors."""
-    w = (Z[:, :nvec] ** 2).sum(axis=1)
+def importance_labels(Z, nvec, weights=None):
+    """log10 of the weight of every basis state in the lowest nvec eigenvectors
+    (each eigenvector v weighted by weights[v] when given)."""
+    wv = np.ones(nvec) if weights is None else np.asarray(weights)[:nvec]
+    w = (Z[:, :nvec] ** 2 * wv[None, :]).sum(axis=1)
     return np.log10(w + LABEL_FLOOR)
 
 

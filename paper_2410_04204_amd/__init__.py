@@ -18,7 +18,7 @@ __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "eig_mixed"
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
-           "mlp_select", "autotune_enable", "autotune_report", "AssemblyPlan"]
+           "mlp_select", "quench_weights", "autotune_enable", "autotune_report", "AssemblyPlan"]
 
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 32, 256, 140289
 
@@ -289,12 +289,19 @@ def mlp_score(X, params, y, stream=None):
     return y
 
 
-def mlp_labels(Z, nvec, labels, stream=None):
-    """Labels of the Z.shape[1] basis states (Z: eigenvector tensor shaped (ncols, ld), column-major)."""
+def mlp_labels(Z, nvec, labels, weights=None, stream=None):
+    """Labels of the labels.shape[0] basis states (Z: eigenvector tensor shaped (ncols, ld), column-major)."""
     n = labels.shape[0]
-    _lib.check(_lib.load().tgba_mlp_labels(n, _lib.ptr(Z), Z.shape[1], int(nvec), _lib.ptr(labels),
-                                           _lib.stream_handle(stream)))
+    _lib.check(_lib.load().tgba_mlp_labels(n, _lib.ptr(Z), Z.shape[1], int(nvec), _lib.ptr(weights),
+                                           _lib.ptr(labels), _lib.stream_handle(stream)))
     return labels
+
+
+def quench_weights(Z, c, w, stream=None):
+    """w_a = |(Z^T c)_a|^2 for real-gauge eigenvectors Z and interleaved complex overlaps c."""
+    _lib.check(_lib.load().tgba_quench_weights(w.shape[0], _lib.ptr(Z), _ld(Z), _lib.ptr(c), _lib.ptr(w),
+                                               _lib.stream_handle(stream)))
+    return w
 
 
 def mlp_select(scores, keep, stream=None):

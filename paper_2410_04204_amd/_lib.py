@@ -26,7 +26,7 @@ EXPORTS = [
     "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
     "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
-    "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free",
+    "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free", "tgba_quench_weights",
 ]
 
 
@@ -102,7 +102,8 @@ def load():
     L.tgba_mlp_train.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int,
                                  c_int64, ctypes.c_float, c_void_p, c_void_p]
     L.tgba_mlp_score.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
-    L.tgba_mlp_labels.argtypes = [c_int64, c_void_p, c_int64, c_int, c_void_p, c_void_p]
+    L.tgba_mlp_labels.argtypes = [c_int64, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_void_p]
+    L.tgba_quench_weights.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
     L.tgba_mlp_select.argtypes = [c_int64, c_void_p, c_int64, c_void_p, P_i64, c_void_p]
     L.tgba_timing_read.argtypes = [ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
     for name in EXPORTS:

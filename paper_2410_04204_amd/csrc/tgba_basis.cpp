@@ -235,7 +235,9 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
             for (uint64_t mk : masks) {
                 double e = state_energy(b.evac[s], b.eps[s], mk);
                 if (!unlimited && !(e - b.e0 <= cut + slack)) continue;
-                cand[momentum_index(N, s, mk)].push_back({e, s, mk});
+                const int K = momentum_index(N, s, mk);
+                if (t->mode != TGBA_TRUNC_ECUT && (t->chi ? t->chi[K] : t->chi_all) == 0) continue;  // sector kept empty
+                cand[K].push_back({e, s, mk});
             }
         }
         b.sec.resize(N);
@@ -247,7 +249,9 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
                 if ((int64_t)c.size() > keep) c.resize(keep);
             } else if (t->mode == TGBA_TRUNC_LEARNED) {
                 int64_t keep = t->chi ? t->chi[K] : t->chi_all;
-                if ((int64_t)c.size() > keep) {
+                if (keep == 0) {
+                    c.clear();
+                } else if ((int64_t)c.size() > keep) {
                     // c is in tie-break order (E, NS<R, mask): equal scores keep that order
                     rc = learned_keep(b, c, keep, t->mlp, (hipStream_t)stream);
                     if (rc) {

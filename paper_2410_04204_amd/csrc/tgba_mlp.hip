@@ -232,13 +232,13 @@ __global__ void adam_kernel(int64_t n, float *p, const float *g, float *m, float
     p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
 }
 
-__global__ void labels_kernel(int64_t n, const double *Z, int64_t ldz, int nvec, float *out) {
+__global__ void labels_kernel(int64_t n, const double *Z, int64_t ldz, int64_t nvec, const double *wts, float *out) {
     const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (a >= n) return;
     double s = 0.0;
-    for (int v = 0; v < nvec; ++v) {
-        const double z = Z[a + (int64_t)v * ldz];
-        s += z * z;
+    for (int64_t v = 0; v < nvec; ++v) {
+        const double z = Z[a + v * ldz];
+        s += (wts ? wts[v] : 1.0) * z * z;
     }
     out[a] = (float)log10(s + 1e-30);
 }
@@ -581,11 +581,13 @@ extern "C" int tgba_mlp_score(int64_t n, const float *X, int64_t ldx, const floa
     return mlp_score_bf16(n, X, ldx, params, y, (hipStream_t)stream);
 }
 
-extern "C" int tgba_mlp_labels(int64_t n, const double *Z, int64_t ldz, int nvec, float *labels, void *stream) {
+extern "C" int tgba_mlp_labels(int64_t n, const double *Z, int64_t ldz, int64_t nvec, const double *weights,
+                               float *labels, void *stream) {
     clear_error();
     if (n < 0 || nvec < 1 || (n > 0 && (!Z || !labels || ldz < n))) return set_error(TGBA_EINVAL, "bad arguments");
     if (n == 0) return TGBA_OK;
-    hipLaunchKernelGGL(labels_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, n, Z, ldz, nvec, labels);
+    hipLaunchKernelGGL(labels_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, n, Z, ldz, nvec,
+                       weights, labels);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }

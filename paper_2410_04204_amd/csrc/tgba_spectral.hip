@@ -141,6 +141,12 @@ __global__ void __launch_bounds__(256) quench_reduce_kernel(const double *Bm, co
     }
 }
 
+// w = re^2 + im^2
+__global__ void abs2_kernel(const double *re, const double *im, double *w, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        w[k] = re[k] * re[k] + im[k] * im[k];
+}
+
 __global__ void norm2_kernel(const double *c, int64_t n, double *out) {
     double a = 0.0;
     for (int64_t k = threadIdx.x; k < 2 * n; k += 256) a += c[k] * c[k];
@@ -263,6 +269,22 @@ extern "C" int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double
     TGBA_HIP(hipStreamSynchronize(st));
     if (!(c2h > 0.0)) return set_error(TGBA_EINVAL, "initial state has zero overlap with the basis");
     hipLaunchKernelGGL(quench_reduce_kernel, dim3(nt), dim3(256), 0, st, Bm, GB, n, nt, 1.0 / c2h, sx, nrm, B_out);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+extern "C" int tgba_quench_weights(int64_t n, const double *Z, int64_t ldz, const double *c, double *w, void *stream) {
+    clear_error();
+    if (n <= 0 || !Z || !c || !w || ldz < n) return set_error(TGBA_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    void *ws = nullptr;
+    int rc = workspace_get(sizeof(double) * 4 * (size_t)n + 256, 19, &ws);
+    if (rc) return rc;
+    double *cr = (double *)ws, *ci = cr + n, *yr = ci + n, *yi = yr + n;
+    hipLaunchKernelGGL(split_complex_kernel, dim3(256), dim3(256), 0, st, c, cr, ci, n);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, cr, yr);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, ci, yi);
+    hipLaunchKernelGGL(abs2_kernel, dim3(256), dim3(256), 0, st, yr, yi, w, n);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }

@@ -16,8 +16,8 @@ import time
 
 import numpy as np
 
-from . import (TGBA_EIG_FP64, TGBA_EIG_NOVEC, TGBA_HEFF, TGBA_LOWER, Basis, assemble_heff, eig, eig_batched,
-               mlp_features, mlp_labels, mlp_train)
+from . import (TGBA_EIG_FP64, TGBA_EIG_NOVEC, TGBA_GAMMA1, TGBA_HEFF, TGBA_LOWER, Basis, assemble_heff, eig,
+               eig_batched, mlp_features, mlp_labels, mlp_train, quench, quench_overlaps, quench_weights)
 
 
 def _k0_matrix(B, dev):
@@ -29,19 +29,32 @@ def _k0_matrix(B, dev):
     return H
 
 
-def training_data(runs, h_par=0.1, nvec=2, dev="cuda"):
-    """Features and labels of the K = 0 sector of every (N, h_perp, e_cut) run."""
+def training_data(runs, h_par=0.1, nvec=2, dev="cuda", target="gap"):
+    """Features and labels of the K = 0 sector of every (N, h_perp, e_cut) run.
+
+    target "gap": weight of each state in the lowest nvec eigenvectors;
+    target "quench": its time-averaged weight after a quench from the NS
+    vacuum (diagonal ensemble, sum_a Z[b][a]^2 |(Z^T c)_a|^2).
+    """
     import torch
     Fs, Ls = [], []
     for N, h, ec in runs:
         B = Basis(N, h, h_par, e_cut=ec)
         Z = _k0_matrix(B, dev)
-        w = torch.empty(Z.shape[0], dtype=torch.float64, device=dev)
+        n = Z.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=dev)
         eig(Z, w, TGBA_EIG_FP64)
-        F = torch.empty((Z.shape[0], 32), dtype=torch.float32, device=dev)
+        F = torch.empty((n, 32), dtype=torch.float32, device=dev)
         mlp_features(B, 0, F)
-        lab = torch.empty(Z.shape[0], dtype=torch.float32, device=dev)
-        mlp_labels(Z, nvec, lab)
+        lab = torch.empty(n, dtype=torch.float32, device=dev)
+        if target == "quench":
+            c = torch.empty(2 * n, dtype=torch.float64, device=dev)
+            quench_overlaps(B, 0, h, 0, c)
+            wt = torch.empty(n, dtype=torch.float64, device=dev)
+            quench_weights(Z, c, wt)
+            mlp_labels(Z, n, lab, wt)
+        else:
+            mlp_labels(Z, nvec, lab)
         Fs.append(F)
         Ls.append(lab)
         B.free()
@@ -86,4 +99,53 @@ def dim_for_gap(N, h, pool, grid, mlp, tol=1e-6, h_par=0.1, m_max=None, dev="cud
         ok = [c for c, e in zip(grid, err) if e <= tol]
         out[name] = {"dim": (min(ok) if ok else None), "gap_err": err, "E1_err": e1}
     out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def k0_quench(B, h_perp, nt, dt, dev="cuda"):
+    """<sigma^x>(t_n), t_n = n dt, of the K = 0 sector after a quench from the NS
+    vacuum (FP64 eigenpairs; tgba_quench)."""
+    import torch
+    n = sum(B.sector_size(0))
+    Z = torch.empty((n, n), dtype=torch.float64, device=dev)
+    G = torch.empty_like(Z)
+    assemble_heff(B, 0, Z, TGBA_HEFF | TGBA_LOWER)
+    assemble_heff(B, 0, G, TGBA_GAMMA1)
+    w = torch.empty(n, dtype=torch.float64, device=dev)
+    eig(Z, w, TGBA_EIG_FP64)
+    c = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    quench_overlaps(B, 0, h_perp, 0, c)
+    sx = torch.empty(nt, dtype=torch.float64, device=dev)
+    nrm = torch.empty(nt, dtype=torch.float64, device=dev)
+    quench(Z, w, G, c, 0.0, dt, nt, sx, nrm)
+    out = sx.cpu().numpy()
+    del Z, G
+    torch.cuda.empty_cache()
+    return out, float(w[0].item())
+
+
+def quench_comparison(N, h, pool, m_max, chi, chi_ref, mlp, nt=1001, dt=0.05, h_par=0.1, log=None, dev="cuda"):
+    """<sigma^x>(t) from the learned basis of dimension chi, the energy cutoff of
+    the same dimension and the energy cutoff of dimension chi_ref (reference),
+    all K = 0 from the same candidate pool."""
+    import numpy as np
+    res = {}
+    for name, dim, p in (("learned", chi, mlp), ("cutoff", chi, None), ("reference", chi_ref, None)):
+        t0 = time.perf_counter()
+        B = Basis(N, h, h_par, chi=[dim if K == 0 else 0 for K in range(N)], pool_e_cut=pool, m_max=m_max, mlp=p)
+        tb = time.perf_counter() - t0
+        sx, e1 = k0_quench(B, h, nt, dt, dev)
+        res[name] = {"dim": sum(B.sector_size(0)), "sx": sx, "E1": e1, "basis_s": tb,
+                     "total_s": time.perf_counter() - t0}
+        B.free()
+        if log:
+            log(f"{name}: dim {res[name]['dim']}, E1 {e1:.8f}, {res[name]['total_s']:.1f} s")
+    ref = res["reference"]["sx"]
+    out = {k: {kk: vv for kk, vv in v.items() if kk != "sx"} for k, v in res.items()}
+    for k in ("learned", "cutoff"):
+        d = np.abs(res[k]["sx"] - ref)
+        out[k]["max_abs_dev_sx"] = float(d.max())
+        out[k]["mean_abs_dev_sx"] = float(d.mean())
+        out[k]["E1_minus_ref"] = res[k]["E1"] - res["reference"]["E1"]
+    out["sx_ref_t50"] = float(ref[-1])
     return out

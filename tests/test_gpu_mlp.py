@@ -149,6 +149,21 @@ def test_labels(tg):
     lab = torch.empty(300, dtype=torch.float32, device="cuda")
     tg.mlp_labels(Z, 3, lab)
     np.testing.assert_allclose(lab.cpu().numpy(), omlp.importance_labels(Q, 3), rtol=1e-6, atol=1e-6)
+    w = np.random.default_rng(62).random(300)
+    tg.mlp_labels(Z, 300, lab, dev(w))
+    np.testing.assert_allclose(lab.cpu().numpy(), omlp.importance_labels(Q, 300, w), rtol=1e-6, atol=1e-6)
+
+
+def test_quench_weights(tg):
+    import torch
+    rng = np.random.default_rng(63)
+    Q, _ = np.linalg.qr(rng.normal(size=(257, 257)))
+    c = rng.normal(size=257) + 1j * rng.normal(size=257)
+    w = torch.empty(257, dtype=torch.float64, device="cuda")
+    tg.quench_weights(dev(Q.T.copy()), dev(c.view(np.float64)), w)
+    want = np.abs(Q.T @ c) ** 2                       # the definition
+    np.testing.assert_allclose(w.cpu().numpy(), want, rtol=1e-12, atol=1e-13)
+    assert abs(want.sum() - np.vdot(c, c).real) <= 1e-10 * want.sum()  # Parseval (Q orthogonal)
 
 
 def test_learned_basis_matches_oracle_selection(tg):

@@ -144,6 +144,16 @@ def test_importance_labels_of_orthogonal_vectors():
     np.testing.assert_allclose(lab, [0, 0, -30, -30, -30], atol=1e-12)
 
 
+def test_weighted_labels_sum_to_the_total_weight():
+    # completeness of an orthogonal Z: sum_a Z[a, v]^2 = 1, so sum_a 10^label_a = sum_v w_v
+    rng = np.random.default_rng(13)
+    Q, _ = np.linalg.qr(rng.normal(size=(40, 40)))
+    w = rng.random(40)
+    lab = mlp.importance_labels(Q, 40, w)
+    assert abs((10.0 ** lab).sum() - w.sum()) <= 1e-12 * w.sum()
+    np.testing.assert_allclose(mlp.importance_labels(Q, 7, np.ones(40)), mlp.importance_labels(Q, 7), rtol=1e-15)
+
+
 def test_select_top_distinct_and_ties():
     s = np.random.default_rng(11).permutation(50).astype(float)
     E = np.zeros(50)
