@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSecT<T> *secs
 //       Pt[g][t], Pt[g][64 + t]   the share of t1[t], t2[t] of row segment g
 //                                 (separate items, same streaming pattern)
 //     Rows and columns are indexed absolutely with stride n.
-constexpr int kSeg = 512;
+constexpr int kSeg = 1024;
 
 __host__ __device__ __forceinline__ int64_t symv_strips(int64_t n) { return (n + 63) / 64; }
 __host__ __device__ __forceinline__ int64_t symv_segments(int64_t n) { return (n + kSeg - 1) / kSeg; }
@@ -273,36 +273,37 @@ __global__ void __launch_bounds__(256, OCC) tri_symv(TriSecT<T> *secs, int nact,
         // the wave's 16 columns from row cb: column jj at scalar offset jj * lda
         const __amdgpu_buffer_rsrc_t rsrc = block_rsrc(S.A + cb + c0 * S.lda, bytes_to_end<T>(n, S.lda, cb, c0));
         const bool full_cols = (cb + 64 <= n);
+        // row and column positions relative to the strip corner (32-bit; uniform ones in SGPRs)
+        const gptr<T> vstrip = vsrc + cb;
+        const int rs_r = (int)(rs - cb), re_r = (int)(re - cb), o_r = (int)(o - cb), c0_r = 16 * wv;
 #pragma unroll 1
-        for (int64_t rb = rs; rb < re; rb += 128) {
-            const bool interior = full_cols && (rb >= cb + 64) && (rb + 128 <= re);
+        for (int rb = rs_r; rb < re_r; rb += 128) {
+            const bool interior = full_cols && (rb >= 64) && (rb + 128 <= re_r);
             T a[2][16], vr[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const int64_t r = rb + lane + 64 * q;
-                const bool rin = r < re;
-                const T vx = vsrc[rin ? r : o];
-                vr[q] = (!rin) ? T(0) : ((r == o) ? T(1) : vx * scale);
-                const uint32_t voff = (uint32_t)((r - cb) * (int64_t)sizeof(T));
+                const int r = rb + lane + 64 * q;
+                const bool rin = r < re_r;
+                const T vx = vstrip[rin ? r : o_r];
+                vr[q] = (!rin) ? T(0) : ((r == o_r) ? T(1) : vx * scale);
+                const uint32_t voff = (uint32_t)r * (uint32_t)sizeof(T);
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) {
-                    const int64_t cc = c0 + jj;
-                    const bool ok = interior || (rin && r >= cc);  // cc >= n reads 0
+                    const bool ok = interior || (rin && r >= c0_r + jj);  // columns >= n read 0
                     const T x = buf_ld<T>(rsrc, voff, (uint32_t)jj * ldb);
                     a[q][jj] = ok ? x : T(0);
                 }
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const int64_t r = rb + lane + 64 * q;
+                const int r = rb + lane + 64 * q;
                 T yr = T(0);
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) {
-                    const int64_t cc = c0 + jj;
-                    yr += a[q][jj] * vcol[16 * wv + jj];
-                    acc[jj] += (interior || r > cc) ? a[q][jj] * vr[q] : T(0);
+                    yr += a[q][jj] * vcol[c0_r + jj];
+                    acc[jj] += (interior || r > c0_r + jj) ? a[q][jj] * vr[q] : T(0);
                 }
-                if (r < re) ypart[wv][r - rs] = yr;
+                if (r < re_r) ypart[wv][r - rs_r] = yr;
             }
         }
         // column sums: reduce over the 64 row-lanes of this wave
