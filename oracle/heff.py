@@ -48,3 +48,19 @@ def heff(N, h_perp, h_par, sec, G=None):
     e = np.concatenate([sec["ns_e"], sec["r_e"]])
     H[np.diag_indices_from(H)] = e
     return H
+
+
+def gamma1_cross(N, h_perp, sec_rows, sec_cols):
+    """X[j, i] = <phi_j^(rows)| gamma_1 |phi_i^(cols)> between two sectors.
+
+    gamma_1 = sigma^x_1 is not translation invariant, so it connects every pair
+    of momentum sectors; it flips the fermion parity, so only the NS x R and
+    R x NS blocks are nonzero.  gamma_1 is Hermitian: the R x NS block is the
+    conjugate transpose of <NS^(cols)| gamma_1 |R^(rows)>.
+    """
+    nr_ns, nr_r = len(sec_rows["ns_masks"]), len(sec_rows["r_masks"])
+    nc_ns, nc_r = len(sec_cols["ns_masks"]), len(sec_cols["r_masks"])
+    X = np.zeros((nr_ns + nr_r, nc_ns + nc_r), dtype=np.complex128)
+    X[:nr_ns, nc_ns:] = gamma1_block(N, h_perp, sec_rows["ns_masks"], sec_cols["r_masks"])
+    X[nr_ns:, :nc_ns] = gamma1_block(N, h_perp, sec_cols["ns_masks"], sec_rows["r_masks"]).conj().T
+    return X

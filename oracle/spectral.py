@@ -38,3 +38,14 @@ def dsf(N, E, Z, G, omega, eta):
 def masses(E, n=3):
     """m_i = E_{i+1} - E_1 for the lowest K = 0 levels (DSF section, Table I)."""
     return np.asarray(E[1:n + 1]) - E[0]
+
+
+def dsf_cross(N, Ek, Zk, E0, Z0, X, omega, eta):
+    """S(k, omega_j) from sector k's eigenpairs (Ek, Zk), the K = 0 ground state
+    Z0[:, 0] with energy E0[0] and X[j, i] = <phi_j^(k)|gamma_1|phi_i^(0)>:
+    b = Zk^H X z_1, weights |b_a|^2 at the poles Ek_a - E0_0 (eq. 8 at k != 0;
+    translation invariance turns sum_j e^{-ikj} sigma^x_j into N gamma_1)."""
+    b = Zk.conj().T @ (X @ Z0[:, 0])
+    x = np.asarray(omega)[:, None] - (Ek[None, :] - E0[0])
+    lor = (eta / np.pi) / (x * x + eta * eta)
+    return 2.0 * np.pi * N * (lor @ np.abs(b) ** 2)

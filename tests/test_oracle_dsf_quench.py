@@ -33,6 +33,42 @@ def test_dsf_full_basis_equals_spin_space_lehmann_sum(N, h, hp):
     assert np.abs(E - Ek).max() < 1e-11
 
 
+@pytest.mark.parametrize("N,h,hp,K", [(8, 1.0, 0.1, 1), (8, 0.7, 0.3, 4), (10, 1.0, 0.1, 3)])
+def test_dsf_k_full_basis_equals_spin_space_lehmann_sum(N, h, hp, K):
+    """S(k, omega) at k = 2 pi K / N: the cross-sector gamma_1 matrix with the full
+    basis against (2 pi / N) |<alpha_K| sum_j e^{+-ikj} sigma^x_j |psi_0>|^2 in the
+    2^N spin space (one of the two signs connects K = 0 to sector K)."""
+    B = basis.build_basis(N, h)
+    E0, Z0 = spectral.eigh(heff.heff(N, h, hp, B[0]))
+    Ek, Zk = spectral.eigh(heff.heff(N, h, hp, B[K]))
+    X = heff.gamma1_cross(N, h, B[K], B[0])
+    omega = np.linspace(0, 8, 257)
+    eta = 0.02
+    S = spectral.dsf_cross(N, Ek, Zk, E0, Z0, X, omega, eta)
+    e0, v0 = brute.ed_sector(N, h, hp, 0, vectors=True)
+    eK, vK = brute.ed_sector(N, h, hp, K, vectors=True)
+    _, sx_sites = _site_sigma_x(N)
+    w = np.zeros(len(eK))
+    for sgn in ({1, -1} if 2 * K != N else {1}):
+        op = sum(np.exp(sgn * 2j * np.pi * K * j / N) * sx_sites[j] for j in range(N))
+        w += np.abs(vK.conj().T @ (op @ v0[:, 0])) ** 2 / N
+    Sref = 2 * np.pi * (_lorentz(omega[:, None] - (eK[None, :] - e0[0]), eta) @ w)
+    assert np.abs(S - Sref).max() < 1e-9 * np.abs(Sref).max()
+    assert np.abs(Ek - eK).max() < 1e-11
+
+
+def _site_sigma_x(N):
+    """sigma^x on every site of the 2^N spin space (site j <-> bit j), dense."""
+    D = 1 << N
+    ops = []
+    for j in range(N):
+        M = np.zeros((D, D))
+        for x in range(D):
+            M[x ^ (1 << j), x] = 1.0
+        ops.append(M)
+    return None, ops
+
+
 def test_dsf_sum_rule():
     N, h, hp = 10, 1.0, 0.1
     B = basis.build_basis(N, h, e_cut=8.0)
