@@ -293,7 +293,8 @@ def main():
         "stages_ms": stage_ms,
         "assembly_elements_per_s": elements / (asm_ms * 1e-3),
         "basis_build_s": t_basis,
-        "assembly_stats": {"flagged_rows": stats[0], "generic_elements": stats[1], "unsupported": stats[2]},
+        "assembly_stats": {"flagged_rows": stats[0], "generic_elements": stats[1], "unsupported": stats[2],
+                           "deflated_rows": stats[3]},
         "roofline": {"kernel": "tri_symv", "bound": "hbm", "achieved": symv_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": symv_gbs / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": symv_avg_bytes, "avg_launch_ms": symv_avg_ms,

@@ -141,12 +141,14 @@ int tgba_basis_constants(const tgba_basis *basis, double *c0, double *e_vac_ns, 
 int tgba_basis_gauge(const tgba_basis *basis, int K, int8_t *q);
 
 /*
- * Diagnostic counters of all assembly calls on this basis so far (host,
- * synchronises the device): stats[0] rows whose bra elimination grew too much
- * and were evaluated by direct pivoted elimination; stats[1] elements taken by
- * the generic pivoted path (more than 10 ket quasiparticles); stats[2]
- * elements beyond the generic path's 24 quasiparticles (written as 0: any
- * nonzero value means the result is incomplete).
+ * Diagnostic counters of all assembly calls on this basis so far (host array
+ * of 4, synchronises the device): stats[0] rows evaluated by direct pivoted
+ * elimination of Pf(R[I_a u I_b]) (more than 4 deflated bra indices, or
+ * growth beyond 1e12); stats[1] elements taken by a generic pivoted path (more
+ * than 10 indices in the small Pfaffian); stats[2] elements beyond the generic
+ * path's 24 quasiparticles (written as 0: any nonzero value means the result
+ * is incomplete); stats[3] deflated rows (bra pivots that would grow the Schur
+ * complement by more than 1e3 max|R| left in each element's Pfaffian).
  */
 int tgba_basis_stats(const tgba_basis *basis, int64_t *stats);
 
@@ -175,6 +177,21 @@ int tgba_assemble_heff(const tgba_basis *basis, int K, void *H, int64_t ld, int 
  */
 int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks, void *const *H,
                                const int64_t *ld, int flags, void *stream);
+
+/*
+ * Cross-sector matrix of gamma_1 for the dynamic structure factor at k != 0
+ * (DSF section: S(k, omega) needs <E_a^(k)| sigma^x(k) |E_1^(0)>, and by
+ * translation invariance sum_j e^{-ikj} sigma^x_j connects sector 0 to sector
+ * k with the same single-site operator gamma_1 = sigma^x_1 as eq. S4).
+ * X (device, n_rows x n_cols, column-major, ld >= n_rows) receives the real
+ * matrix with <phi_j^(K_rows)| gamma_1 |phi_i^(K_cols)> = e^{2 pi i (K_cols -
+ * K_rows)/N} X[j][i] in the real gauge of both sectors (the bra and ket total
+ * momenta leave this one constant phase, which cancels in S(k, omega)):
+ * Pfaffians of the contraction table (Appendix A) for the NS x R and R x NS
+ * blocks, zeros for the same-parity blocks.
+ * Errors: TGBA_EINVAL, TGBA_EUNSUPPORTED, TGBA_EDEVICE.
+ */
+int tgba_assemble_cross(const tgba_basis *basis, int K_rows, int K_cols, double *X, int64_t ld, void *stream);
 
 /*
  * Assembly plan: the launches of one batched assembly (the same arguments as
@@ -266,6 +283,16 @@ int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double a
 int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
              int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
              void *stream);
+
+/*
+ * S(k, omega_j) = 2 pi N sum_a |b_a|^2 (eta/pi) / ((omega_j - (wk_a - w0_0))^2 + eta^2),
+ * b = Zk^T (X z0): the eigenpairs (Zk, wk) of sector k, the K = 0 ground state z0
+ * (n0) with energy w0[0] (device), and X = tgba_assemble_cross(k, 0) (nk x n0).
+ * weights (nk, may be NULL) receives |b_a|^2.
+ */
+int tgba_dsf_cross(int64_t nk, const double *Zk, int64_t ldz, const double *wk, int64_t n0, const double *z0,
+                   const double *w0, const double *X, int64_t ldx, int N_sites, const double *omega, int n_omega,
+                   double eta, double *S, double *weights, void *stream);
 
 /* ---- quench (Quench section, eq. 9, eq. 10, Appendix B eqs. S5-S6) ------- */
 

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
-__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps",
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -90,8 +90,8 @@ class Basis:
         return q
 
     def stats(self):
-        """(flagged rows, generic-path elements, unsupported elements) over all assembly calls."""
-        out = np.zeros(3, dtype=np.int64)
+        """(flagged rows, generic-path elements, unsupported elements, deflated rows) over all assembly calls."""
+        out = np.zeros(4, dtype=np.int64)
         _lib.check(_lib.load().tgba_basis_stats(self._h, _lib.ptr(out)))
         return tuple(int(x) for x in out)
 
@@ -217,6 +217,22 @@ def dsf(Z, w, G, N_sites, omega, eta, S, weights=None, stream=None):
     _lib.check(_lib.load().tgba_dsf(int(n), _lib.ptr(Z), _ld(Z), _lib.ptr(w), _lib.ptr(G), _ld(G), int(N_sites),
                                     _lib.ptr(omega), int(omega.shape[0]), float(eta), _lib.ptr(S),
                                     _lib.ptr(weights), _lib.stream_handle(stream)))
+    return S
+
+
+def assemble_cross(basis, K_rows, K_cols, X, stream=None):
+    """X[j][i] = <phi_j^(K_rows)|gamma_1|phi_i^(K_cols)> (real gauge; X shaped (n_cols, ld), column-major)."""
+    _lib.check(_lib.load().tgba_assemble_cross(basis.handle, int(K_rows), int(K_cols), _lib.ptr(X), _ld(X),
+                                               _lib.stream_handle(stream)))
+    return X
+
+
+def dsf_cross(Zk, wk, z0, w0, X, N_sites, omega, eta, S, weights=None, stream=None):
+    """S(k, omega) from sector k's eigenpairs, the K = 0 ground state z0 (energy w0[0]) and X = assemble_cross(k, 0)."""
+    nk, n0 = wk.shape[0], z0.shape[0]
+    _lib.check(_lib.load().tgba_dsf_cross(nk, _lib.ptr(Zk), _ld(Zk), _lib.ptr(wk), n0, _lib.ptr(z0), _lib.ptr(w0),
+                                          _lib.ptr(X), _ld(X), int(N_sites), _lib.ptr(omega), omega.shape[0],
+                                          float(eta), _lib.ptr(S), _lib.ptr(weights), _lib.stream_handle(stream)))
     return S
 
 

@@ -19,8 +19,16 @@
 //   M_b = 8,10 one step of partial pivoting done while gathering from LDS,
 //              then the expansion of the remaining 6 or 8,
 //   M_b > 10   pivoted elimination in private memory (rare).
-// A row whose bra elimination shows large element growth is flagged and its
-// elements are evaluated directly as Pf(R[I_a u I_b]) by pivoted elimination.
+// Numerical safeguard: when R[I_a] is nearly singular, S_a has entries far
+// above max|R| (a rank-2 term x y^T / a of a tiny pivot a) and the small
+// Pfaffians of S_a cancel them, losing digits in proportion.  The bra
+// elimination therefore stops before any pivot whose update would exceed
+// kGrowthStep max|R| (deflated row).  With two bra indices left, each element
+// is recovered exactly from two Pfaffians of size M_b with bounded entries (an
+// identity of rank-2 updates, see deflated_value); with four left, by pivoted
+// elimination of Pf(S_a[J u I_b]).  A row with more than kMaxDefl indices left,
+// or with growth beyond kGrowthLimit anyway, is flagged and its elements are
+// evaluated directly as Pf(R[I_a u I_b]) by pivoted elimination.
 //
 // Output (column-major, ld): the sector's NS block first, then R block:
 //   H = [[diag E_NS, B], [B^T, diag E_R]]   (real gauge, double), or the
@@ -30,6 +38,7 @@
 // R x R block (zeros + diagonal) -- everything in the lower triangle.  Unless
 // TGBA_LOWER, a tiled LDS transpose then mirrors B^T into the upper block B
 // (writing B directly from the rows kernel would be ROWS-long strided runs).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <type_traits>
@@ -48,7 +57,9 @@ struct SectorDesc {
     int64_t first_block;    // first workgroup index of this sector
     int64_t nblk;           // workgroups of this sector
     int max_m_bra;          // largest M among the sector's NS states
-    int pad;
+    int mode;               // 0: a sector's own matrix; 1, 2: a block of a cross-sector matrix
+    const uint64_t *ket;    // the ket (R) masks: masks + n_ns for mode 0
+    int64_t row_off;        // output row of ket 0: n_ns for mode 0
 };
 
 namespace {
@@ -56,6 +67,14 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kGenMax = 24;          // largest Pfaffian of the generic path
 constexpr double kGrowthLimit = 1e12; // flag a row whose Schur complement is (near) singular
+// A bra pivot a whose rank-2 update x y^T / a would add more than kGrowthStep
+// (relative to max|R|) to the Schur complement is not taken: the remaining
+// d <= kMaxDefl bra indices stay in every element's Pfaffian (deflation).
+// While more than two bra indices remain, pivots up to kGrowthForce are still
+// taken, so that rows almost always stop with d = 2 (the fast identity).
+constexpr double kGrowthStep = 1e4;
+constexpr double kGrowthForce = 1e6;
+constexpr int kMaxDefl = 4;
 
 // ---- small Pfaffians by expansion along the first remaining index ------------
 template <unsigned MASK>
@@ -186,98 +205,221 @@ __device__ __noinline__ double element_generic(const double *tabs, const int *s_
     return pf_eliminate(A, M);
 }
 
-// Pf(S_r[I_b]) * factor_r for all valid rows, for a ket of MB quasiparticles.
-template <int MB, int ROWS>
-__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, const int *s_rowoff, int N,
-                                           uint64_t ket, int nvalid, const int *s_flag, const uint64_t *s_bra,
-                                           const double *s_fac, const double *__restrict__ R,
-                                           unsigned long long *counters) {
-    constexpr int MI = MB > 0 ? MB : 1;
-    int idx[MI], roff[MI];
-    if constexpr (MB > 0) {
-        uint64_t x = ket;
+// ---- one small Pfaffian per (row, ket) ----------------------------------------
+// Ket positions of a ket with MB quasiparticles: idx[j] = its j-th table
+// index, roff[j] = rowoff(idx[j]); base[] = the shared LDS offsets of the pairs
+// read first (all pairs for MB <= 6, the first row for MB = 8, 10).
+template <int MB>
+struct KetIdx {
+    static constexpr int MI = MB > 0 ? MB : 1;
+    static constexpr int NP = (MB >= 2 && MB <= 6) ? MB * (MB - 1) / 2 : ((MB >= 8 && MB <= 10) ? MB - 1 : 1);
+    int idx[MI], roff[MI], base[NP];
+
+    template <int ROWS>
+    __device__ __forceinline__ void init(uint64_t ket, const int *s_rowoff) {
+        if constexpr (MB > 0) {
+            uint64_t x = ket;
 #pragma unroll
-        for (int j = 0; j < MB; ++j) {
-            idx[j] = __ffsll((long long)x) - 1;
-            roff[j] = s_rowoff[idx[j]];
-            x &= x - 1ULL;
+            for (int j = 0; j < MB; ++j) {
+                idx[j] = __ffsll((long long)x) - 1;
+                roff[j] = s_rowoff[idx[j]];
+                x &= x - 1ULL;
+            }
+        }
+        if constexpr (MB >= 2 && MB <= 6) {
+            int t = 0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = i + 1; j < MB; ++j) base[t++] = (roff[i] + idx[j]) * ROWS;
+        } else if constexpr (MB >= 8 && MB <= 10) {
+#pragma unroll
+            for (int j = 1; j < MB; ++j) base[j - 1] = (roff[0] + idx[j]) * ROWS;
         }
     }
-    // bases of the pairs (i, j), i < j, shared by all rows
-    constexpr int NP = (MB >= 2 && MB <= 6) ? MB * (MB - 1) / 2 : ((MB >= 8 && MB <= 10) ? MB - 1 : 1);
-    int base[NP];
-    if constexpr (MB >= 2 && MB <= 6) {
+};
+
+// Pf(T[I_b]) of row r's table, where T = S_r, or (MOD) T = S_r + (X Y^T - Y X^T) * inv
+// with X[j], Y[j] the rank-2 vectors at the ket's positions j.
+//   MB <= 6   expansion along the first index (division free);
+//   MB = 8,10 one step of partial pivoting while gathering from LDS, then the
+//             expansion of the remaining 6 or 8.
+template <int MB, int ROWS, bool MOD>
+__device__ __forceinline__ double pf_ket(const double *tabs, const int *s_rowoff, int r, const KetIdx<MB> &K,
+                                         const double *X, const double *Y, double inv) {
+    auto md = [&](int i, int j) -> double { return MOD ? (X[i] * Y[j] - Y[i] * X[j]) * inv : 0.0; };
+    if constexpr (MB == 0) {
+        return 1.0;
+    } else if constexpr (MB >= 2 && MB <= 6) {
+        double a[10][10];
         int t = 0;
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = i + 1; j < MB; ++j) base[t++] = (roff[i] + idx[j]) * ROWS;
+            for (int j = i + 1; j < MB; ++j) a[i][j] = tabs[K.base[t++] + r] + md(i, j);
+        return pf_rec<(1u << MB) - 1u>(a);
     } else if constexpr (MB >= 8 && MB <= 10) {
+        double r0[MB];
 #pragma unroll
-        for (int j = 1; j < MB; ++j) base[j - 1] = (roff[0] + idx[j]) * ROWS;
+        for (int j = 1; j < MB; ++j) r0[j] = tabs[K.base[j - 1] + r] + md(0, j);
+        int p = 1;
+        double best = fabs(r0[1]);
+#pragma unroll
+        for (int j = 2; j < MB; ++j) {
+            const double v = fabs(r0[j]);
+            if (v > best) { best = v; p = j; }
+        }
+        if (best == 0.0) return 0.0;
+        double piv = r0[1], Xp = MOD ? X[1] : 0.0, Yp = MOD ? Y[1] : 0.0;
+        int ip = K.idx[1];
+#pragma unroll
+        for (int j = 2; j < MB; ++j)
+            if (p == j) {
+                piv = r0[j];
+                ip = K.idx[j];
+                if constexpr (MOD) { Xp = X[j]; Yp = Y[j]; }
+            }
+        int ri[MB - 2], ro[MB - 2];
+        double y[MB - 2], x[MB - 2], Xr[MB - 2], Yr[MB - 2];
+#pragma unroll
+        for (int t = 0; t < MB - 2; ++t) {
+            const bool lo = (t + 1 < p);
+            ri[t] = lo ? K.idx[t + 1] : K.idx[t + 2];
+            ro[t] = lo ? K.roff[t + 1] : K.roff[t + 2];
+            y[t] = lo ? r0[t + 1] : r0[t + 2];
+            if constexpr (MOD) {
+                Xr[t] = lo ? X[t + 1] : X[t + 2];
+                Yr[t] = lo ? Y[t + 1] : Y[t + 2];
+            } else {
+                Xr[t] = Yr[t] = 0.0;
+            }
+            x[t] = skew_at<ROWS>(tabs, s_rowoff, r, ip, ri[t]) + (MOD ? (Xp * Yr[t] - Yp * Xr[t]) * inv : 0.0);
+        }
+        const double ipiv = 1.0 / piv;
+        double a[10][10];
+#pragma unroll
+        for (int t = 0; t < MB - 2; ++t)
+#pragma unroll
+            for (int u = t + 1; u < MB - 2; ++u)
+                a[t][u] = tabs[(ro[t] + ri[u]) * ROWS + r] + (MOD ? (Xr[t] * Yr[u] - Yr[t] * Xr[u]) * inv : 0.0) +
+                          (x[t] * y[u] - y[t] * x[u]) * ipiv;
+        const double sgn = (p & 1) ? 1.0 : -1.0;  // (-1)^(p-1)
+        return sgn * piv * pf_rec<(1u << (MB - 2)) - 1u>(a);
+    } else {
+        return 0.0;  // not used: other sizes take a generic path
     }
+}
+
+// Pf(S_r[I_b]) * factor_r for all valid rows that are neither flagged nor
+// deflated, for a ket of MB quasiparticles (MB < 0: more than 10, generic).
+template <int MB, int ROWS>
+__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, const int *s_rowoff, int N,
+                                           uint64_t ket, int nvalid, const int *s_flag, const int *s_defl,
+                                           const uint64_t *s_bra, const double *s_fac, const double *__restrict__ R,
+                                           unsigned long long *counters) {
+    constexpr int MK = MB > 0 ? MB : 0;
+    KetIdx<MK> K;
+    if constexpr (MB >= 0) K.template init<ROWS>(ket, s_rowoff);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         double pfv = 0.0;
-        if (r < nvalid) {
+        if (r < nvalid && !s_defl[r]) {
             if (MB < 0 || s_flag[r]) {
                 pfv = element_generic<ROWS>(tabs, s_rowoff, r, N, ket, s_flag[r], s_bra[r], R, counters);
-            } else if constexpr (MB == 0) {
-                pfv = 1.0;
-            } else if constexpr (MB >= 2 && MB <= 6) {
-                double a[10][10];
-                int t = 0;
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int j = i + 1; j < MB; ++j) a[i][j] = tabs[base[t++] + r];
-                pfv = pf_rec<(1u << MB) - 1u>(a);
-            } else if constexpr (MB >= 8 && MB <= 10) {
-                // one step of partial pivoting on the first row, then expansion
-                double r0[MB];
-#pragma unroll
-                for (int j = 1; j < MB; ++j) r0[j] = tabs[base[j - 1] + r];
-                int p = 1;
-                double best = fabs(r0[1]);
-#pragma unroll
-                for (int j = 2; j < MB; ++j) {
-                    const double v = fabs(r0[j]);
-                    if (v > best) { best = v; p = j; }
-                }
-                if (best != 0.0) {
-                    double piv = r0[1];
-                    int ip = idx[1];
-#pragma unroll
-                    for (int j = 2; j < MB; ++j)
-                        if (p == j) { piv = r0[j]; ip = idx[j]; }
-                    int ri[MB - 2], ro[MB - 2];
-                    double y[MB - 2], x[MB - 2];
-#pragma unroll
-                    for (int t = 0; t < MB - 2; ++t) {
-                        const bool lo = (t + 1 < p);
-                        ri[t] = lo ? idx[t + 1] : idx[t + 2];
-                        ro[t] = lo ? roff[t + 1] : roff[t + 2];
-                        y[t] = lo ? r0[t + 1] : r0[t + 2];
-                        x[t] = skew_at<ROWS>(tabs, s_rowoff, r, ip, ri[t]);
-                    }
-                    const double inv = 1.0 / piv;
-                    double a[10][10];
-#pragma unroll
-                    for (int t = 0; t < MB - 2; ++t)
-#pragma unroll
-                        for (int u = t + 1; u < MB - 2; ++u)
-                            a[t][u] = tabs[(ro[t] + ri[u]) * ROWS + r] + (x[t] * y[u] - y[t] * x[u]) * inv;
-                    const double sgn = (p & 1) ? 1.0 : -1.0;  // (-1)^(p-1)
-                    pfv = sgn * piv * pf_rec<(1u << (MB - 2)) - 1u>(a);
-                }
+            } else {
+                pfv = pf_ket<MK, ROWS, false>(tabs, s_rowoff, r, K, nullptr, nullptr, 0.0);
             }
         }
         val[r] = s_fac[r] * pfv;
     }
 }
 
+// ---- deflated rows --------------------------------------------------------
+// A deflated row stopped its bra elimination with two bra indices J0, J1 left
+// (their pivot delta = S[J0, J1] would have grown the Schur complement too
+// much).  With y = S[J0, kets], x = S[J1, kets] and S the ket block, its
+// element is the Pfaffian of [[0, delta, y^T], [-delta, 0, x^T], [-y, -x, S]]
+// over J u I_b, which eliminating the pair would give as
+//     delta * Pf(S + (x y^T - y x^T) / delta).
+// Pf(S + t (x y^T - y x^T)) is affine in t (the update has rank 2), so for
+// any Delta the same value is
+//     Delta * Pf(S + (x y^T - y x^T) / Delta) - (Delta - delta) * Pf(S),
+// two Pfaffians of size M_b with entries of the size of S: with Delta = max|R|
+// no large entry is ever formed.  The row stores x and y in dk (rows 1, 0 of
+// its kMaxDefl x N block) and delta in dd.  Rows with four bra indices left
+// take the pivoted elimination of Pf(S[J u I_b]) (rare).
+__device__ __forceinline__ constexpr int dd_pair(int i, int j) {
+    return i * (2 * kMaxDefl - i - 1) / 2 + (j - i - 1);
+}
+
+template <int MB, int ROWS>
+__device__ __forceinline__ double defl2_value(const double *tabs, const int *s_rowoff, const double *dk, int r,
+                                              int N, uint64_t ket, double delta, double Delta) {
+    KetIdx<MB> K;
+    K.template init<ROWS>(ket, s_rowoff);
+    double X[KetIdx<MB>::MI], Y[KetIdx<MB>::MI];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        Y[j] = dk[(r * kMaxDefl + 0) * N + K.idx[j]];
+        X[j] = dk[(r * kMaxDefl + 1) * N + K.idx[j]];
+    }
+    const double p0 = pf_ket<MB, ROWS, false>(tabs, s_rowoff, r, K, X, Y, 0.0);
+    const double p1 = pf_ket<MB, ROWS, true>(tabs, s_rowoff, r, K, X, Y, 1.0 / Delta);
+    return Delta * p1 - (Delta - delta) * p0;
+}
+
+// Pf(S_r[J u I_b]) by pivoted elimination in private memory (four kept bra
+// indices, or a ket of more than 10 quasiparticles).
+template <int ROWS>
+__device__ __noinline__ double defl_generic(const double *tabs, const int *s_rowoff, const double *dk,
+                                            const double *dd, int r, int N, uint64_t ket, int d,
+                                            unsigned long long *counters) {
+    int g[kGenMax];
+    int M = d;
+    for (int q = 0; q < N; ++q)
+        if ((ket >> q) & 1ULL) {
+            if (M == kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
+            g[M++] = q;
+        }
+    double A[kGenMax * kGenMax];
+    for (int i = 0; i < M; ++i) {
+        A[i * kGenMax + i] = 0.0;
+        for (int j = i + 1; j < M; ++j) {
+            double v;
+            if (j < d) v = dd[dd_pair(i, j)];
+            else if (i < d) v = dk[(r * kMaxDefl + i) * N + g[j]];
+            else v = tabs[(s_rowoff[g[i]] + g[j]) * ROWS + r];
+            A[i * kGenMax + j] = v;
+            A[j * kGenMax + i] = -v;
+        }
+    }
+    atomicAdd(&counters[1], 1ULL);
+    return pf_eliminate(A, M);
+}
+
+template <int ROWS>
+__device__ __forceinline__ double deflated_value(const double *tabs, const int *s_rowoff, const double *dk,
+                                                 const double *dd, int r, int N, uint64_t ket, int Mb, int d,
+                                                 double Delta, unsigned long long *counters) {
+    if (d == 2) {
+        const double delta = dd[0];
+        switch (Mb) {
+            case 0: return delta;
+            case 2: return defl2_value<2, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
+            case 4: return defl2_value<4, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
+            case 6: return defl2_value<6, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
+            case 8: return defl2_value<8, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
+            case 10: return defl2_value<10, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
+            default: break;
+        }
+    }
+    return defl_generic<ROWS>(tabs, s_rowoff, dk, dd, r, N, ket, d, counters);
+}
+
+// 3 waves per SIMD (<= 168 VGPRs): the LDS of a workgroup at N = 40 allows 3
+// workgroups of 4 waves per CU anyway.
 template <int ROWS, bool CPLX>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, const double *__restrict__ R,
                      double r_max, double c0, double scale, int with_diag, int lower,
                      unsigned long long *__restrict__ counters) {
@@ -291,20 +433,24 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     const int wdim = D.max_m_bra + N;
     double *tabs = lds;                      // ntab x ROWS interleaved
     double *W = lds + ROWS * ntab;           // dense scratch wdim x wdim
+    double *dk = W + wdim * wdim;            // deflated rows: ROWS x kMaxDefl x N
     __shared__ double s_fac[ROWS];
-    __shared__ int s_flag[ROWS], s_mbra[ROWS];
+    __shared__ double s_dd[ROWS][kMaxDefl * (kMaxDefl - 1) / 2];
+    __shared__ int s_flag[ROWS], s_defl[ROWS], s_mbra[ROWS];
+    __shared__ int s_stop, s_anydefl;
     __shared__ uint64_t s_bra[ROWS];
     __shared__ int s_bidx[kGenMax];
     __shared__ int s_rowoff[kMaxN];
     __shared__ int s_pp, s_pq;
     __shared__ double s_growth;
     if (tid < N) s_rowoff[tid] = rowoff_of(tid, N);
+    if (tid == 0) s_anydefl = 0;
 
     // ---- per-row Schur complement over the bra indices -------------------
     for (int r = 0; r < ROWS; ++r) {
         const int64_t a = a0 + r;
         if (a >= D.n_ns) {
-            if (tid == 0) { s_fac[r] = 0.0; s_flag[r] = 0; s_mbra[r] = 0; s_bra[r] = 0; }
+            if (tid == 0) { s_fac[r] = 0.0; s_flag[r] = 0; s_defl[r] = 0; s_mbra[r] = 0; s_bra[r] = 0; }
             continue;
         }
         const uint64_t bra = D.masks[a];
@@ -328,6 +474,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         }
         __syncthreads();
         double pf = 1.0;
+        int kstop = Ma;  // bra positions kstop.. stay (deflated)
         for (int k = 0; k < Ma; k += 2) {
             if (tid < 64) {  // complete pivot search over the remaining bra block
                 double best = -1.0;
@@ -342,9 +489,33 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
                     const int op = __shfl_down(bp, off, 64), oq = __shfl_down(bq, off, 64);
                     if (ob > best || (ob == best && (op < bp || (op == bp && oq < bq)))) { best = ob; bp = op; bq = oq; }
                 }
-                if (tid == 0) { s_pp = bp; s_pq = bq; }
+                best = __shfl(best, 0, 64);
+                bp = __shfl(bp, 0, 64);
+                bq = __shfl(bq, 0, 64);
+                // size of the rank-2 update this pivot would make: max|W[p, c]| max|W[q, c]| / |W[p, q]|
+                double xm = 0.0, ym = 0.0;
+                for (int c = k + tid; c < n; c += 64)
+                    if (c != bp && c != bq) {
+                        xm = fmax(xm, fabs(W[bp * wdim + c]));
+                        ym = fmax(ym, fabs(W[bq * wdim + c]));
+                    }
+                for (int off = 32; off > 0; off >>= 1) {
+                    xm = fmax(xm, __shfl_down(xm, off, 64));
+                    ym = fmax(ym, __shfl_down(ym, off, 64));
+                }
+                if (tid == 0) {
+                    s_pp = bp;
+                    s_pq = bq;
+                    const double upd = xm * ym;  // |update| <= upd / best
+                    s_stop = !(best > 0.0) ||
+                             (!(upd <= kGrowthStep * r_max * best) && (Ma - k <= 2 || !(upd <= kGrowthForce * r_max * best)));
+                }
             }
             __syncthreads();
+            if (s_stop) {
+                kstop = k;
+                break;
+            }
             const int p = s_pp, q = s_pq;
             if (p != k) {  // swap index p -> k
                 for (int c = tid; c < n; c += kThreads) {
@@ -378,7 +549,10 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             }
             __syncthreads();
         }
-        // pack the ket block into the row's interleaved table and measure its growth
+        // pack the ket block into the row's interleaved table (and the kept bra
+        // indices' rows of a deflated row) and measure the growth
+        const int d = Ma - kstop;
+        const bool keep_d = (d <= kMaxDefl) && !(d & 1);
         double g = 0.0;
         for (int u = ty; u < N; u += 4) {
             const int ro = s_rowoff[u];
@@ -388,14 +562,31 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
                 g = fmax(g, fabs(val));
             }
         }
+        if (keep_d) {
+            for (int i = ty; i < d; i += 4)
+                for (int v = tx; v < N; v += 64) {
+                    const double val = W[(kstop + i) * wdim + Ma + v];
+                    dk[(r * kMaxDefl + i) * N + v] = val;
+                    g = fmax(g, fabs(val));
+                }
+            if (tid < d * d) {
+                const int i = tid / d, j = tid % d;
+                if (i < j) s_dd[r][dd_pair(i, j)] = W[(kstop + i) * wdim + kstop + j];
+            }
+        }
         for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_down(g, off, 64));
         if (tx == 0) atomicMax((unsigned long long *)&s_growth, __double_as_longlong(g));
         __syncthreads();
         if (tid == 0) {
-            const bool bad = !(pf != 0.0) || !(s_growth <= kGrowthLimit * r_max) || !isfinite(pf);
+            const bool bad = !keep_d || !(pf != 0.0) || !(s_growth <= kGrowthLimit * r_max) || !isfinite(pf);
             s_flag[r] = bad ? 1 : 0;
+            s_defl[r] = bad ? 0 : d;
             s_fac[r] = bad ? c0 * scale : c0 * scale * pf;
             if (bad) atomicAdd(&counters[0], 1ULL);
+            if (!bad && d > 0) {
+                s_anydefl = 1;
+                atomicAdd(&counters[3], 1ULL);
+            }
         }
         __syncthreads();
     }
@@ -404,7 +595,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     const int nvalid = (int)((D.n_ns - a0) < ROWS ? (D.n_ns - a0) : ROWS);
 
     // ---- NS columns: zeros of the NS x NS block and the diagonal -----------
-    for (int r = 0; r < nvalid; ++r) {
+    for (int r = 0; r < nvalid && D.mode == 0; ++r) {
         const int64_t a = a0 + r;
         const int64_t i0 = lower ? a : 0;
         for (int64_t i = i0 + tid; i < D.n_ns; i += kThreads) {
@@ -418,7 +609,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     }
 
     // ---- this workgroup's share of the R x R block: zeros and the diagonal --
-    {
+    if (D.mode == 0) {
         const int64_t w = blockIdx.x - D.first_block;
         const int64_t per = (D.n_r + D.nblk - 1) / D.nblk;
         const int64_t c0c = w * per, c1c = (c0c + per < D.n_r) ? c0c + per : D.n_r;
@@ -441,30 +632,48 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     T *Hb = reinterpret_cast<T *>(D.H);
     T *colA[ROWS];  // columns a0 + r (B^T part, coalesced along b)
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) colA[r] = Hb + (a0 + r) * ld + D.n_ns;
-    const uint64_t *kmask = D.masks + D.n_ns;
+    for (int r = 0; r < ROWS; ++r) colA[r] = Hb + (a0 + r) * ld + D.row_off;
+    const uint64_t *kmask = D.ket;
     for (int64_t b = tid; nvalid > 0 && b < D.n_r; b += kThreads) {
         const uint64_t ket = kmask[b];
         const int Mb = __popcll(ket);
         double val[ROWS];
         switch (Mb) {
-            case 0: row_values<0, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 2: row_values<2, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 4: row_values<4, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 6: row_values<6, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 8: row_values<8, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            case 10: row_values<10, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
-            default: row_values<-1, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_bra, s_fac, R, counters); break;
+            case 0: row_values<0, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 2: row_values<2, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 4: row_values<4, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 6: row_values<6, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 8: row_values<8, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 10: row_values<10, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            default: row_values<-1, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
         }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             if (r >= nvalid) break;
+            if (s_defl[r]) continue;
             if constexpr (CPLX) {
                 double re, im;
                 phase_mi((s_mbra[r] + Mb) / 2, val[r], re, im);
                 colA[r][b] = make_double2(re, -im);
             } else {
-                colA[r][b] = val[r];
+                if (D.mode == 2) Hb[(a0 + r) + (D.row_off + b) * ld] = val[r];  // bra row, ket column
+                else colA[r][b] = val[r];
+            }
+        }
+        if (s_anydefl) {  // deflated rows, one at a time (the row is uniform over the workgroup)
+#pragma unroll 1
+            for (int r = 0; r < nvalid; ++r) {
+                const int d = s_defl[r];
+                if (!d) continue;
+                const double v = s_fac[r] * deflated_value<ROWS>(tabs, s_rowoff, dk, s_dd[r], r, N, ket, Mb, d, r_max, counters);
+                if constexpr (CPLX) {
+                    double re, im;
+                    phase_mi((s_mbra[r] + Mb) / 2, v, re, im);
+                    Hb[(a0 + r) * ld + D.row_off + b] = make_double2(re, -im);
+                } else {
+                    if (D.mode == 2) Hb[(a0 + r) + (D.row_off + b) * ld] = v;
+                    else Hb[(a0 + r) * ld + D.row_off + b] = v;
+                }
             }
         }
     }
@@ -557,13 +766,29 @@ int asm_setup(const Basis *b, int nsec, const int *Ks, void *const *H, const int
         d.ld = ld[i];
         d.n_ns = sc.n_ns;
         d.n_r = sc.n_r;
+        d.mode = 0;
+        d.ket = sc.d_masks ? sc.d_masks + sc.n_ns : nullptr;
+        d.row_off = sc.n_ns;
         o.desc.push_back(d);
         o.max_m = std::max(o.max_m, mb);
         o.elements += (double)sc.n_ns * (double)sc.n_r;
     }
     // all descriptors with the same LDS layout: pad max_m_bra to the global maximum
     for (auto &d : o.desc) d.max_m_bra = o.max_m;
+    // longest processing time first: the grid lays out sectors by decreasing
+    // NS x R element count, so the largest sectors' blocks are dispatched first
+    // and the small ones fill the tail
+    std::stable_sort(o.desc.begin(), o.desc.end(), [](const SectorDesc &x, const SectorDesc &y) {
+        return (double)x.n_ns * (double)x.n_r > (double)y.n_ns * (double)y.n_r;
+    });
     return TGBA_OK;
+}
+
+// Dynamic LDS of the rows kernel: the ROWS interleaved N x N tables, the
+// elimination scratch (max_m + N)^2 and the deflated rows' kMaxDefl x N blocks.
+size_t asm_lds(int rows, int N, int max_m) {
+    return sizeof(double) * ((size_t)rows * N * (N - 1) / 2 + (size_t)(max_m + N) * (max_m + N) +
+                             (size_t)rows * kMaxDefl * N);
 }
 
 // Block layout for `rows` bra rows per workgroup; returns the grid size and LDS bytes.
@@ -577,7 +802,7 @@ int64_t asm_blocks(const AsmSetup &o, int N, int rows, std::vector<SectorDesc> &
         nblocks += d.nblk;
     }
     // R x R blocks may exist even for sectors without NS states
-    lds = sizeof(double) * ((size_t)rows * N * (N - 1) / 2 + (size_t)(o.max_m + N) * (o.max_m + N));
+    lds = asm_lds(rows, N, o.max_m);
     return nblocks;
 }
 
@@ -675,7 +900,70 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
     return TGBA_OK;
 }
 
+namespace {
+__global__ void fill_zero_kernel(double *X, int64_t ld, int64_t m, int64_t n) {
+    const int64_t tot = m * n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x)
+        X[q % m + (q / m) * ld] = 0.0;
+}
+}  // namespace
+
+// X[j][i] = <phi^{Kr}_j| gamma_1 |phi^{Kc}_i> (real gauge): two blocks of the
+// same Pfaffian kernel, the same-parity blocks are zero.
+int assemble_cross(const Basis *b, int Kr, int Kc, double *X, int64_t ld, hipStream_t stream) {
+    const int N = b->N;
+    if (Kr < 0 || Kr >= N || Kc < 0 || Kc >= N) return set_error(TGBA_EINVAL, "sector index out of range");
+    const Sector &sr = b->sec[Kr], &sc = b->sec[Kc];
+    const int64_t nr = sr.n_ns + sr.n_r, nc = sc.n_ns + sc.n_r;
+    if (nr == 0 || nc == 0) return TGBA_OK;
+    if (!X || ld < nr) return set_error(TGBA_EINVAL, "bad output matrix");
+    int mb = 0;
+    for (int64_t a = 0; a < sc.n_ns; ++a) mb = std::max(mb, __builtin_popcountll(sc.masks[a]));
+    for (int64_t a = 0; a < sr.n_ns; ++a) mb = std::max(mb, __builtin_popcountll(sr.masks[a]));
+    if (mb > kGenMax) return set_error(TGBA_EUNSUPPORTED, "bra states with more than 24 quasiparticles");
+    const int rows = rows_default(N);
+    std::vector<SectorDesc> d(2);
+    // block (R of Kr) x (NS of Kc): bra NS(Kc), ket R(Kr), natural (ket row, bra column) layout
+    d[0] = SectorDesc{};
+    d[0].masks = sc.d_masks; d[0].e = sc.d_e; d[0].H = X; d[0].ld = ld;
+    d[0].n_ns = sc.n_ns; d[0].n_r = sr.n_r; d[0].mode = 1;
+    d[0].ket = sr.d_masks ? sr.d_masks + sr.n_ns : nullptr; d[0].row_off = sr.n_ns;
+    // block (NS of Kr) x (R of Kc): bra NS(Kr), ket R(Kc), written as (bra row, ket column)
+    d[1] = SectorDesc{};
+    d[1].masks = sr.d_masks; d[1].e = sr.d_e; d[1].H = X; d[1].ld = ld;
+    d[1].n_ns = sr.n_ns; d[1].n_r = sc.n_r; d[1].mode = 2;
+    d[1].ket = sc.d_masks ? sc.d_masks + sc.n_ns : nullptr; d[1].row_off = sc.n_ns;
+    int64_t nblocks = 0;
+    for (auto &x : d) {
+        x.max_m_bra = mb;
+        x.first_block = nblocks;
+        x.nblk = (x.n_r > 0) ? (x.n_ns + rows - 1) / rows : 0;
+        nblocks += x.nblk;
+    }
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, stream, X, ld, nr, nc);
+    TGBA_HIP(hipGetLastError());
+    if (nblocks == 0) return TGBA_OK;
+    void *ws = nullptr;
+    int rc = workspace_get(2 * sizeof(SectorDesc), 29, &ws);
+    if (rc) return rc;
+    TGBA_HIP(hipMemcpyAsync(ws, d.data(), 2 * sizeof(SectorDesc), hipMemcpyHostToDevice, stream));
+    AsmSetup o;
+    o.cplx = false;
+    o.lower = 0;
+    o.with_diag = 0;
+    o.scale = 1.0;
+    o.max_m = mb;
+    const size_t lds = asm_lds(rows, N, mb);
+    return asm_launch_rows(b, o, rows, (const SectorDesc *)ws, 2, nblocks, lds, stream, true);
+}
+
 }  // namespace tgba
+
+extern "C" int tgba_assemble_cross(const tgba_basis *hb, int K_rows, int K_cols, double *X, int64_t ld, void *stream) {
+    tgba::clear_error();
+    if (!hb) return tgba::set_error(TGBA_EINVAL, "NULL basis");
+    return tgba::assemble_cross(&hb->b, K_rows, K_cols, X, ld, (hipStream_t)stream);
+}
 
 // ---- assembly plan: the launches of a batched assembly captured in a hipGraph ----
 

@@ -362,6 +362,6 @@ extern "C" int tgba_basis_stats(const tgba_basis *hb, int64_t *stats) {
     unsigned long long c[4] = {0, 0, 0, 0};
     TGBA_HIP(hipDeviceSynchronize());
     TGBA_HIP(hipMemcpy(c, hb->b.d_counters, sizeof(c), hipMemcpyDeviceToHost));
-    for (int i = 0; i < 3; ++i) stats[i] = (int64_t)c[i];
+    for (int i = 0; i < 4; ++i) stats[i] = (int64_t)c[i];
     return TGBA_OK;
 }

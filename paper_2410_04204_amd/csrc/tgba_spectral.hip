@@ -62,10 +62,11 @@ __global__ void copy_col_kernel(const double *Z, double *x, int64_t n) {
 
 // S(omega_j): one thread per frequency, weights/energies staged through LDS
 __global__ void __launch_bounds__(256) lorentz_kernel(const double *b, const double *w, int64_t n, const double *omega,
-                                                      int n_omega, double eta, double pref, double *S, double *weights) {
+                                                      int n_omega, double eta, double pref, double *S, double *weights,
+                                                      const double *wref) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     const double om = (j < n_omega) ? omega[j] : 0.0;
-    const double w0 = w[0];
+    const double w0 = wref[0];  // poles at w_a - (reference energy)
     __shared__ double sb[256], se[256];
     double acc = 0.0;
     const double e2 = eta * eta;
@@ -232,7 +233,29 @@ extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w
     hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)(tm * tm)), dim3(256), 0, st, G, ldg, n, n, z0, gz);
     hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, gz, b);
     hipLaunchKernelGGL(lorentz_kernel, dim3((n_omega + 255) / 256), dim3(256), 0, st, b, w, n, omega, n_omega, eta,
-                       2.0 * M_PI * (double)N_sites, S, weights);
+                       2.0 * M_PI * (double)N_sites, S, weights, w);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+extern "C" int tgba_dsf_cross(int64_t nk, const double *Zk, int64_t ldz, const double *wk, int64_t n0, const double *z0,
+                              const double *w0, const double *X, int64_t ldx, int N_sites, const double *omega,
+                              int n_omega, double eta, double *S, double *weights, void *stream) {
+    clear_error();
+    if (nk <= 0 || n0 <= 0 || !Zk || !wk || !z0 || !w0 || !X || !S || !omega || n_omega <= 0 || ldz < nk || ldx < nk ||
+        !(eta > 0.0))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    void *ws = nullptr;
+    int rc = workspace_get(sizeof(double) * 2 * (size_t)nk + 256, 18, &ws);
+    if (rc) return rc;
+    double *gz = (double *)ws, *b = gz + nk;
+    hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, gz, nk);
+    const int64_t tm = (nk + 255) / 256, tn = (n0 + 255) / 256;
+    hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, st, X, ldx, nk, n0, z0, gz);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((nk + 3) / 4)), dim3(256), 0, st, Zk, ldz, nk, nk, gz, b);
+    hipLaunchKernelGGL(lorentz_kernel, dim3((n_omega + 255) / 256), dim3(256), 0, st, b, wk, nk, omega, n_omega, eta,
+                       2.0 * M_PI * (double)N_sites, S, weights, w0);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }

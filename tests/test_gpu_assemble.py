@@ -133,6 +133,65 @@ def test_real_gauge_equals_gauge_transformed_oracle(N, h, hp, e_cut):
         assert np.abs(Gr - Gt).max() <= TOL * max(np.abs(Go).max(), 1e-300)
 
 
+def test_full_basis_gamma1_against_its_own_scale():
+    """gamma_1 matrices of every sector of the full 2^10 space, error relative to
+    max|G| (not max|H|, which the diagonal energies dominate).  States with most
+    modes occupied have nearly singular bra blocks R[I_a]: their rows are
+    deflated, none may fall back to the direct path or be left incomplete."""
+    import paper_2410_04204_amd as tg
+    from oracle import heff
+    N, h = 10, 1.0
+    B = _basis(N, h, 0.1, chi=1 << N)
+    OB = _oracle_basis(N, h)
+    worst = 0.0
+    for K in range(N):
+        Gr = _assemble(B, K, tg.TGBA_GAMMA1)
+        g = _gauge_phase(B, K)
+        Go = heff.gamma1_matrix(N, h, OB[K])
+        Gt = ((g.conj()[:, None] * Go) * g[None, :]).real
+        err = np.abs(Gr - Gt).max() / np.abs(Go).max()
+        print(f"sector {K}: max err / max|G| = {err:.2e}", flush=True)
+        worst = max(worst, err)
+    assert worst <= TOL
+    flagged, _, unsupported, deflated = B.stats()
+    assert deflated > 0 and flagged == 0 and unsupported == 0
+
+
+def test_n40_most_occupied_rows_sampled():
+    """Rows of the N=40 workload with the most quasiparticles (the worst
+    conditioned bra blocks), against the V block's own scale."""
+    import paper_2410_04204_amd as tg
+    from oracle import heff
+    torch = _torch()
+    w = workloads.WORKLOADS["n40_batched"]
+    chi = workloads.sector_chis(w["N"], w["chi_lo"], w["chi_hi"], w["chi_seed"])
+    N, hp = w["N"], w["h_par"]
+    B = _basis(N, w["h_perp"], hp, chi=chi, pool=w["pool_e_cut"])
+    rng = np.random.default_rng(17)
+    for K in (0, 13, 27):
+        n_ns, n_r = B.sector_size(K)
+        n = n_ns + n_r
+        masks, _ = B.sector(K)
+        pc = np.array([bin(int(m)).count("1") for m in masks[:n_ns]])
+        top = np.argsort(-pc, kind="stable")[:48]
+        rows = np.concatenate([np.repeat(top, 16), rng.integers(0, n_ns, 400)])
+        cols = rng.integers(0, n_r, rows.size)
+        print(f"n40 sector {K}: {n_ns} x {n_r}, max M of the bra rows {pc.max()}", flush=True)
+        H = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        tg.assemble_heff(B, K, H, tg.TGBA_HEFF | tg.TGBA_LOWER)
+        # lower triangle: element (n_ns + b, a) of the column-major matrix is H[a, n_ns + b] here
+        got = H[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols + n_ns, device="cuda")].cpu().numpy()
+        del H
+        ref = -N * hp * heff.gamma1_pairs(N, w["h_perp"], masks[rows], masks[n_ns + cols])
+        g = (1j) ** B.gauge(K).astype(np.int64)
+        ref_real = (g[rows].conj() * ref * g[n_ns + cols]).real
+        scale = np.abs(ref).max()
+        err = np.abs(got - ref_real).max() / scale
+        print(f"  max err / max|V| = {err:.2e}", flush=True)
+        assert err <= TOL
+    assert B.stats()[0] == 0 and B.stats()[2] == 0
+
+
 def test_lower_mode_writes_only_the_lower_triangle():
     import paper_2410_04204_amd as tg
     torch = _torch()

@@ -119,3 +119,95 @@ def test_quench_matches_oracle(hpre, s, e_cut):
     assert np.abs(sx.cpu().numpy() - sxo).max() <= TOL * max(1e-3, np.abs(sxo).max())
     assert np.abs(nrm.cpu().numpy() - nrmo).max() <= TOL
     assert np.abs(nrm.cpu().numpy() - np.linalg.norm(co)).max() <= 1e-11  # norm is time independent
+
+
+def _real_gauge(M, g_rows, g_cols, N=None, Kr=0, Kc=0):
+    """Per-state quarter turns of the real gauge; across sectors a constant block
+    phase e^{2 pi i (Kc - Kr) / N} remains (the bra and ket total momenta differ),
+    which the device matrix leaves out (it cancels in |b|^2)."""
+    out = g_rows.conj()[:, None] * M * g_cols[None, :]
+    return out if N is None else out * np.exp(-2j * np.pi * (Kc - Kr) / N)
+
+
+@pytest.mark.parametrize("N,e_cut,pairs", [(10, None, [(1, 0), (3, 0), (0, 4), (5, 5), (7, 2)]),
+                                          (12, 7.0, [(1, 0), (6, 0), (0, 11)])])
+def test_cross_matrix_matches_oracle(N, e_cut, pairs):
+    import paper_2410_04204_amd as tg
+    from oracle import basis as ob, heff
+    torch = _t()
+    h = 1.0
+    B = tg.Basis(N, h, 0.1, e_cut=e_cut) if e_cut else tg.Basis(N, h, 0.1, chi=1 << N)
+    OB = ob.build_basis(N, h, e_cut=e_cut)
+    for Kr, Kc in pairs:
+        nr, nc = sum(B.sector_size(Kr)), sum(B.sector_size(Kc))
+        X = torch.full((nc, nr + 2), float("nan"), dtype=torch.float64, device="cuda")  # ld = nr + 2
+        tg.assemble_cross(B, Kr, Kc, X)
+        Xg = X.cpu().numpy().T[:nr, :]
+        Xo = _real_gauge(heff.gamma1_cross(N, h, OB[Kr], OB[Kc]), (1j) ** B.gauge(Kr).astype(np.int64),
+                         (1j) ** B.gauge(Kc).astype(np.int64), N, Kr, Kc)
+        scale = max(np.abs(Xo).max(), 1e-300)
+        assert np.abs(Xo.imag).max() <= 1e-12 * scale
+        assert np.abs(Xg - Xo.real).max() <= TOL * scale, (Kr, Kc)
+        assert np.all(np.isnan(X.cpu().numpy().T[nr:, :]))  # rows beyond n untouched
+
+
+def test_cross_matrix_full_size_n24_sampled():
+    """Sampled elements of the N = 24 cross matrix (sectors 5 and 0) against the literal Wick-Pfaffian."""
+    import paper_2410_04204_amd as tg
+    from oracle import heff
+    torch = _t()
+    wl = workloads.WORKLOADS["n24_dsf"]
+    N, h = wl["N"], wl["h_perp"]
+    B = tg.Basis(N, h, wl["h_par"], e_cut=wl["e_cut"])
+    Kr, Kc = 5, 0
+    (rns, rr), (cns, cr) = B.sector_size(Kr), B.sector_size(Kc)
+    nr, nc = rns + rr, cns + cr
+    X = torch.empty((nc, nr), dtype=torch.float64, device="cuda")
+    tg.assemble_cross(B, Kr, Kc, X)
+    Xn = X.cpu().numpy().T
+    mr, _ = B.sector(Kr)
+    mc, _ = B.sector(Kc)
+    gr = (1j) ** B.gauge(Kr).astype(np.int64)
+    gc = (1j) ** B.gauge(Kc).astype(np.int64)
+    ph = np.exp(-2j * np.pi * (Kc - Kr) / N)  # block phase left out by the device matrix
+    # block NS(rows) x R(cols) and block R(rows) x NS(cols), 300 seeded samples each
+    a, b = workloads.element_sample(rns, cr, 300)
+    ref = heff.gamma1_pairs(N, h, mr[a], mc[cns + b])
+    got = Xn[a, cns + b]
+    want = ph * gr[a].conj() * ref * gc[cns + b]
+    assert np.abs(want.imag).max() <= 1e-12 * max(1.0, np.abs(want).max())
+    assert np.abs(got - want.real).max() <= TOL * max(1.0, np.abs(want).max())
+    a, b = workloads.element_sample(cns, rr, 300, seed=999)
+    ref = heff.gamma1_pairs(N, h, mc[a], mr[rns + b])          # <NS_cols| gamma_1 |R_rows>
+    got = Xn[rns + b, a]
+    want = ph * gr[rns + b].conj() * ref.conj() * gc[a]         # <R_rows| gamma_1 |NS_cols>
+    assert np.abs(want.imag).max() <= 1e-12 * max(1.0, np.abs(want).max())
+    assert np.abs(got - want.real).max() <= TOL * max(1.0, np.abs(want).max())
+    assert np.all(Xn[:rns, :cns] == 0) and np.all(Xn[rns:, cns:] == 0)
+
+
+@pytest.mark.parametrize("K", [1, 3, 5])
+def test_dsf_k_matches_oracle(K):
+    import paper_2410_04204_amd as tg
+    from oracle import basis as ob, heff, spectral
+    torch = _t()
+    N, h, hp = 10, 1.0, 0.1
+    B = tg.Basis(N, h, hp, chi=1 << N)
+    OB = ob.build_basis(N, h)
+    Z0, w0, _ = _sector_eig(tg, B, 0)
+    Zk, wk, _ = _sector_eig(tg, B, K)
+    nk, n0 = wk.shape[0], w0.shape[0]
+    X = torch.empty((n0, nk), dtype=torch.float64, device="cuda")
+    tg.assemble_cross(B, K, 0, X)
+    omega = workloads.omega_grid(4096, 8.0)
+    S = torch.empty(4096, dtype=torch.float64, device="cuda")
+    wt = torch.empty(nk, dtype=torch.float64, device="cuda")
+    tg.dsf_cross(Zk, wk, Z0[0].contiguous(), w0, X, N, torch.as_tensor(omega, device="cuda"), 0.02, S, wt)
+    E0, Zo0 = spectral.eigh(heff.heff(N, h, hp, OB[0]))
+    Ek, Zok = spectral.eigh(heff.heff(N, h, hp, OB[K]))
+    So = spectral.dsf_cross(N, Ek, Zok, E0, Zo0, heff.gamma1_cross(N, h, OB[K], OB[0]), omega, 0.02)
+    assert np.abs(S.cpu().numpy() - So).max() <= TOL * np.abs(So).max()
+    # sum rule: the weights add up to |X z_0|^2
+    Xn = X.cpu().numpy().T
+    z0 = Z0.cpu().numpy()[0]
+    assert abs(wt.sum().item() - np.linalg.norm(Xn @ z0) ** 2) <= 1e-12 * max(1e-300, np.linalg.norm(Xn @ z0) ** 2)
