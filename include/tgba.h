@@ -216,11 +216,16 @@ void tgba_plan_free(tgba_plan *plan);
 #define TGBA_EIG_MIXED 0x1   /* FP32 reduction + back-transform, FP64 tridiagonal solve and
                                refinement of the lowest 200 pairs (see tgba_eig_mixed)  */
 #define TGBA_EIG_NOVEC 0x2   /* eigenvalues only                                         */
+#define TGBA_EIG_ONESTAGE 0x4 /* with TGBA_EIG_NOVEC: the one-stage reduction of the vector path
+                                instead of the two-stage one (comparison and testing)     */
 
 /*
  * Eigen-decomposition A = Z diag(w) Z^T of a real symmetric n x n device
  * matrix (lower triangle referenced).  On return A holds Z (unless
  * TGBA_EIG_NOVEC) and w (device, n doubles) the ascending eigenvalues.
+ * Eigenvalues only (TGBA_EIG_NOVEC) take the two-stage reduction of
+ * tgba_sytrd_2stage, then bisection; A is overwritten.  With vectors, the
+ * one-stage reduction, divide and conquer and the back-transform.
  * The call synchronises `stream`.
  * Errors: TGBA_EINVAL, TGBA_ENOMEM, TGBA_EDEVICE, TGBA_ENUMERIC.
  */
@@ -264,6 +269,13 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
  *   op = transpose when transA/transB != 0 (FP64 matrix cores).
  */
 int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *e, double *tau, void *stream);
+/* tgba_sytrd_2stage: a tridiagonal (d: n, e: n-1, device) similar to the
+ *   symmetric A (lower triangle read; A is overwritten), by reduction to a band
+ *   of half-bandwidth 64 (panel QR and two-sided blocked updates on the FP64
+ *   matrix cores) and bulge chasing.  The reflectors are not kept (eigenvalues
+ *   only).  n <= 65536.  Stream-ordered; does not synchronise.
+ *   Errors: TGBA_EINVAL, TGBA_EUNSUPPORTED (n > 65536), TGBA_ENOMEM. */
+int tgba_sytrd_2stage(int64_t n, double *A, int64_t lda, double *d, double *e, void *stream);
 int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream);
 /* tgba_stedc: eigenvalues (into d, ascending) and eigenvectors Z (n x n, ldz)
  *   of the symmetric tridiagonal (d, e) by divide and conquer (device arrays;

@@ -11,12 +11,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
+from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
 __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
-           "TGBA_EIG_NOVEC", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
+           "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
            "mlp_select", "quench_weights", "autotune_enable", "autotune_report", "AssemblyPlan"]
 
@@ -189,6 +189,13 @@ def sytrd(A, d, e, tau, stream=None):
     n = d.shape[0]
     _lib.check(_lib.load().tgba_sytrd(int(n), _lib.ptr(A), _ld(A), _lib.ptr(d), _lib.ptr(e), _lib.ptr(tau),
                                       _lib.stream_handle(stream)))
+
+
+def sytrd_2stage(A, d, e, stream=None):
+    """Tridiagonal (d, e) similar to A by the two-stage reduction (tgba_sytrd_2stage); A is overwritten."""
+    n = d.shape[0]
+    _lib.check(_lib.load().tgba_sytrd_2stage(int(n), _lib.ptr(A), _ld(A), _lib.ptr(d), _lib.ptr(e),
+                                             _lib.stream_handle(stream)))
 
 
 def stebz(d, e, w, stream=None):

@@ -16,13 +16,13 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUP
 
 TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED = 0, 1, 2
 TGBA_HEFF, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_LOWER = 0x0, 0x1, 0x2, 0x4
-TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC = 0x0, 0x1, 0x2
+TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE = 0x0, 0x1, 0x2, 0x4
 
 EXPORTS = [
     "tgba_last_error", "tgba_version", "tgba_build_basis", "tgba_basis_free", "tgba_basis_sector_size",
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
-    "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_stebz",
+    "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_sytrd_2stage", "tgba_stebz",
     "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
     "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
@@ -84,6 +84,7 @@ def load():
     L.tgba_eig_batched.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
     L.tgba_sytrd.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     L.tgba_stebz.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_sytrd_2stage.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
     L.tgba_stedc.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]
     L.tgba_dgemm.argtypes = [c_int, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p, c_int64,
                              c_double, c_void_p, c_int64, c_void_p]

@@ -33,6 +33,7 @@ SOURCES = {
     "tgba_assemble.hip": [],
     "tgba_blas.hip": [],
     "tgba_eig.hip": [],
+    "tgba_band.hip": [],
     "tgba_dc.hip": [],
     "tgba_spectral.hip": [],
     "tgba_mlp.hip": [],

@@ -1,0 +1,562 @@
+// Two-stage tridiagonal reduction of real symmetric matrices (eigenvalues of
+// the Method section's "diagonalise each sector"), batched over sectors.
+//
+// Stage 1, dense -> band of half-bandwidth BW = 64 (the lower triangle is
+// read and updated).  For every panel of BW columns j0.. with m = n - j0 - BW
+// rows below it:
+//   * QR of the m x BW panel by Householder reflectors H_q = I - tau_q v_q v_q^T,
+//     column by column (qr_dots: norm and dot products of the column with the
+//     panel in one pass; qr_update: the reflector and its application).  R
+//     stays in the panel as the band's subdiagonal block.
+//   * compact WY: Q = I - V T V^T (T from the Gram matrix V^T V, larft);
+//   * the two-sided update of the trailing matrix A22 <- Q^T A22 Q as
+//         X = A22 V T,   W = X - 1/2 V (T^T V^T X),   A22 -= V W^T + W V^T,
+//     all on FP64 MFMA: A22 V from its lower triangle as tril(A22) V +
+//     stril(A22)^T V with K split over workgroups, the update on the lower
+//     tiles only.
+// That reads the trailing matrix once per panel instead of once per column,
+// which is what makes the one-stage reduction HBM bound.
+//
+// Stage 2, band -> tridiagonal by bulge chasing, in band storage of 2 BW
+// rows (B[(i - j) + j * 2BW], the band plus room for the bulge).  Sweep i
+// annihilates column i below the subdiagonal; task (i, k) works on rows
+// r = i + 1 + k BW .. r + BW - 1:
+//   * a reflector from column i (k = 0) or from the first column r - BW of the
+//     bulge left by task (i, k - 1), which it annihilates;
+//   * applied from the left to the rest of that bulge block, from both sides
+//     to the diagonal block, from the right to the block below (the next
+//     bulge).
+// Task (i, k) runs at step t = 4 i + k.  Tasks of one step touch index ranges
+// [r - BW, r + 2 BW) that are 4 BW - 1 apart, and every conflicting pair of
+// tasks keeps the order of the sequential algorithm, so each step is one
+// launch with one workgroup per task of every sector.
+//
+// The tridiagonal (d, e) then goes to the bisection of tgba_stebz.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "tgba_internal.h"
+#include "tgba_blas.h"
+#include "tgba_band.h"
+
+namespace tgba {
+namespace {
+
+constexpr int BW = kBandWidth;     // half-bandwidth of stage 1
+constexpr int LDB = 2 * BW;        // rows of the band storage
+constexpr int QCH = 1024;          // panel rows per workgroup of the panel QR
+constexpr int kQrMaxBlk = 64;      // partial-sum rows of the panel QR (>= ceil(n / QCH) for n <= 65536)
+constexpr int QP = BW + 1;         // partial sums per block: BW dot products + the norm
+
+// workspace slots of this file
+constexpr int kSlotSecs = 30, kSlotWork = 31, kSlotParts = 32, kSlotGemm = 33, kSlotRed = 34;
+
+struct BandSec {
+    double *A;
+    int64_t lda, n;
+    double *tau;    // n
+    double *qpart;  // kQrMaxBlk x QP partial sums, then the panel's top row (BW)
+    double *V;      // n x BW (ld n): the panel's reflectors, unit lower trapezoidal
+    double *X;      // n x BW (ld n)
+    double *W;      // n x BW (ld n)
+    double *S, *T, *Y, *M;  // BW x BW each (ld BW)
+    double *band;   // LDB x n
+    double *d, *e;  // n, n
+    int64_t first_wg;  // stage 2: first workgroup of this sector in a step launch
+    int64_t cap;       // stage 2: workgroups of this sector per step
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---- stage 1: panel QR ----------------------------------------------------------
+// Panel of sector s at column j0: P[r + c lda] = A[(j0 + BW + r) + (j0 + c) lda],
+// r < m = n - j0 - BW, c < BW.  Column q's reflector acts on rows q .. m-1.
+
+// One pass over rows q.. of the panel: sum_{r > q} P[r][q]^2 and
+// sum_{r >= q} P[r][q] P[r][j] for j > q, per block of QCH rows; block 0 also
+// saves the row q of the panel (read by every block of qr_update).
+__global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict__ secs, int64_t j0, int q, int maxblk) {
+    const int s = blockIdx.x / maxblk, blk = blockIdx.x % maxblk;
+    const BandSec S = secs[s];
+    const int64_t m = S.n - j0 - BW;
+    if (m < 2) return;
+    const int nref = (int)(m - 1 < BW ? m - 1 : BW);
+    if (q >= nref) return;
+    const int64_t nblk = (m - q + QCH - 1) / QCH;
+    if (blk >= nblk) return;
+    const double *P = S.A + (j0 + BW) + j0 * S.lda;
+    const int64_t lda = S.lda;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double acc[BW];
+#pragma unroll
+    for (int j = 0; j < BW; ++j) acc[j] = 0.0;
+    double nrm = 0.0;
+    for (int it = 0; it < QCH / 256; ++it) {
+        const int64_t r = q + (int64_t)blk * QCH + it * 256 + tid;
+        if (r < m) {
+            const double x = P[r + q * lda];
+            if (r > q) nrm += x * x;
+#pragma unroll
+            for (int j = 0; j < BW; ++j)
+                if (j > q) acc[j] += x * P[r + j * lda];
+        }
+    }
+    __shared__ double red[4][QP];
+#pragma unroll
+    for (int j = 0; j < BW; ++j) {
+        if (j > q) {  // q is uniform: the branch is too
+            const double v = wave_sum(acc[j]);
+            if (lane == 0) red[wave][j] = v;
+        }
+    }
+    nrm = wave_sum(nrm);
+    if (lane == 0) red[wave][BW] = nrm;
+    __syncthreads();
+    double *out = S.qpart + (int64_t)blk * QP;
+    if (tid < QP && (tid > q || tid == BW)) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (blk == 0 && tid < BW && tid >= q) S.qpart[kQrMaxBlk * QP + tid] = P[q + tid * lda];
+}
+
+// Reflector of column q from the partial sums, then its application to rows
+// q.. of columns q+1.. (and the reflector stored below the diagonal of column q).
+__global__ void __launch_bounds__(256) qr_update_kernel(const BandSec *__restrict__ secs, int64_t j0, int q, int maxblk) {
+    const int s = blockIdx.x / maxblk, blk = blockIdx.x % maxblk;
+    const BandSec S = secs[s];
+    const int64_t m = S.n - j0 - BW;
+    if (m < 2) return;
+    const int nref = (int)(m - 1 < BW ? m - 1 : BW);
+    if (q >= nref) return;
+    const int64_t nblk = (m - q + QCH - 1) / QCH;
+    if (blk >= nblk) return;
+    double *P = S.A + (j0 + BW) + j0 * S.lda;
+    const int64_t lda = S.lda;
+    const int tid = threadIdx.x;
+    __shared__ double sums[QP], w[BW], par[3];
+    const double *top = S.qpart + kQrMaxBlk * QP;
+    if (tid < QP && (tid > q || tid == BW)) {
+        double a = 0.0;
+        for (int64_t b = 0; b < nblk; ++b) a += S.qpart[b * QP + tid];
+        sums[tid] = a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double alpha = top[q], sig = sums[BW];
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (sig != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        par[0] = tau;
+        par[1] = beta;
+        par[2] = scale;
+        if (blk == 0) S.tau[j0 + q] = tau;
+    }
+    __syncthreads();
+    const double tau = par[0], beta = par[1], scale = par[2];
+    // w_j = v^T P[:, j] = P[q][j] + scale (sum_{r >= q} x_r P[r][j] - alpha P[q][j])
+    if (tid < BW && tid > q) w[tid] = top[tid] + scale * (sums[tid] - top[q] * top[tid]);
+    __syncthreads();
+    for (int it = 0; it < QCH / 256; ++it) {
+        const int64_t r = q + (int64_t)blk * QCH + it * 256 + tid;
+        if (r >= m) continue;
+        if (r == q) {
+            for (int j = q + 1; j < BW; ++j) P[q + j * lda] -= tau * w[j];
+            P[q + q * lda] = beta;
+        } else {
+            const double v = P[r + q * lda] * scale;
+            P[r + q * lda] = v;
+            for (int j = q + 1; j < BW; ++j) P[r + j * lda] -= tau * v * w[j];
+        }
+    }
+}
+
+// V (m x BW, ld n): unit lower trapezoidal reflectors of the panel, zero columns
+// beyond the panel's nref reflectors (whose tau is set to 0).
+__global__ void extract_panel_v_kernel(const BandSec *__restrict__ secs, int64_t j0) {
+    const BandSec S = secs[blockIdx.y];
+    const int64_t m = S.n - j0 - BW;
+    if (m < 2) return;
+    const int64_t nref = m - 1 < BW ? m - 1 : BW;
+    const double *P = S.A + (j0 + BW) + j0 * S.lda;
+    const int64_t tot = m * BW;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = k % m, c = k / m;
+        double v = 0.0;
+        if (c < nref) v = (r < c) ? 0.0 : ((r == c) ? 1.0 : P[r + c * S.lda]);
+        S.V[r + c * S.n] = v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < BW && threadIdx.x >= nref) S.tau[j0 + threadIdx.x] = 0.0;
+}
+
+// T (BW x BW, upper) of Q = I - V T V^T from the Gram matrix S = V^T V:
+// T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) S(0:i, i).  One workgroup per sector.
+__global__ void larft_panel_kernel(const BandSec *__restrict__ secs, int64_t j0) {
+    const BandSec S = secs[blockIdx.x];
+    if (S.n - j0 - BW < 2) return;
+    __shared__ double Tl[BW][BW + 1];
+    __shared__ double col[BW];
+    const int j = threadIdx.x;  // BW threads
+    for (int k = 0; k < BW; ++k) Tl[j][k] = 0.0;
+    __syncthreads();
+    const double *tau = S.tau + j0;
+    for (int i = 0; i < BW; ++i) {
+        const double ti = tau[i];
+        if (j < i) {
+            double acc = 0.0;
+            for (int l = j; l < i; ++l) acc += Tl[j][l] * S.S[l + i * BW];
+            col[j] = -ti * acc;
+        }
+        __syncthreads();
+        if (j < i) Tl[j][i] = col[j];
+        if (j == i) Tl[i][i] = ti;
+        __syncthreads();
+    }
+    for (int r = 0; r < BW; ++r) S.T[r + j * BW] = Tl[r][j];
+}
+
+// Band storage from the reduced matrix: B[(i - j) + j LDB] = A[i][j] for
+// 0 <= i - j <= BW (the panels' R blocks included, their reflectors not), 0 up to LDB.
+__global__ void band_extract_kernel(const BandSec *__restrict__ secs) {
+    const BandSec S = secs[blockIdx.y];
+    const int64_t tot = S.n * LDB;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t dlt = k % LDB, j = k / LDB, i = j + dlt;
+        S.band[k] = (dlt <= BW && i < S.n) ? S.A[i + j * S.lda] : 0.0;
+    }
+}
+
+// ---- stage 2: bulge chasing -----------------------------------------------------
+__device__ __forceinline__ double &bat(double *B, int64_t row, int64_t c) { return B[(row - c) + c * LDB]; }
+
+__global__ void __launch_bounds__(256) sb2st_step_kernel(const BandSec *__restrict__ secs, int nsec, int64_t t) {
+    __shared__ double Ds[BW][BW + 1];
+    __shared__ double vs[BW], ps[BW], wsv[BW], qs[BW];
+    __shared__ double par[3];
+    int s = 0;
+    while (s + 1 < nsec && secs[s + 1].first_wg <= (int64_t)blockIdx.x) ++s;
+    const BandSec S = secs[s];
+    const int64_t slot = blockIdx.x - S.first_wg;
+    const int64_t n = S.n;
+    if (slot >= S.cap || n < 3) return;
+    const int64_t i = t / 4 - slot, k = t % 4 + 4 * slot;
+    if (i < 0 || i > n - 3 || k > (n - 3 - i) / BW) return;
+    const int64_t r = i + 1 + k * BW;
+    const int ln = (int)(n - r < BW ? n - r : BW);              // >= 2
+    const int64_t rest = n - r - ln;
+    const int ln2 = (int)(rest < 0 ? 0 : (rest < BW ? rest : BW));
+    const int64_t col = (k == 0) ? i : r - BW;
+    double *B = S.band;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // reflector from column col, rows r .. r+ln-1
+    if (wave == 0) {
+        const double x = (lane < ln) ? bat(B, r + lane, col) : 0.0;
+        const double sig = wave_sum(lane > 0 ? x * x : 0.0);
+        const double alpha = __shfl(x, 0, 64);
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (sig != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        vs[lane] = (lane == 0) ? 1.0 : ((lane < ln) ? x * scale : 0.0);
+        if (lane < ln) bat(B, r + lane, col) = (lane == 0) ? beta : 0.0;
+        if (lane == 0) par[0] = tau;
+    }
+    // diagonal block (symmetric, from its lower triangle)
+    for (int e = tid; e < BW * BW; e += 256) {
+        const int a = e % BW, b = e / BW;
+        if (a < ln && b < ln && a >= b) {
+            const double v = bat(B, r + a, r + b);
+            Ds[a][b] = v;
+            Ds[b][a] = v;
+        }
+    }
+    __syncthreads();
+    const double tau = par[0];
+    if (tau == 0.0) return;  // identity reflector: nothing else changes (uniform)
+
+    // left application to the rest of the bulge block: columns col+1 .. r-1, rows r..
+    if (k > 0) {
+        for (int cc = wave; cc < BW - 1; cc += 4) {
+            const int64_t c = col + 1 + cc;
+            double e = (lane < ln) ? bat(B, r + lane, c) : 0.0;
+            const double wc = wave_sum(vs[lane] * e);
+            if (lane < ln) bat(B, r + lane, c) = e - tau * vs[lane] * wc;
+        }
+    }
+    // two-sided application to the diagonal block: p = tau D v, w = p - (tau/2)(p.v) v
+    if (tid < BW) {
+        double acc = 0.0;
+        if (tid < ln)
+            for (int b = 0; b < ln; ++b) acc += Ds[tid][b] * vs[b];
+        ps[tid] = tau * acc;
+    }
+    // right application to the block below: q = F v
+    if (tid >= BW && tid < 2 * BW) {
+        const int a2 = tid - BW;
+        double acc = 0.0;
+        if (a2 < ln2)
+            for (int a = 0; a < ln; ++a) acc += bat(B, r + ln + a2, r + a) * vs[a];
+        qs[a2] = acc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const double kk = 0.5 * tau * wave_sum(ps[lane] * vs[lane]);
+        wsv[lane] = ps[lane] - kk * vs[lane];
+    }
+    __syncthreads();
+    for (int e = tid; e < BW * BW; e += 256) {
+        const int a = e % BW, b = e / BW;
+        if (a < ln && b < ln && a >= b) bat(B, r + a, r + b) = Ds[a][b] - vs[a] * wsv[b] - wsv[a] * vs[b];
+    }
+    for (int e = tid; e < BW * BW; e += 256) {
+        const int a2 = e % BW, a = e / BW;
+        if (a2 < ln2 && a < ln) {
+            double &f = bat(B, r + ln + a2, r + a);
+            f -= tau * qs[a2] * vs[a];
+        }
+    }
+}
+
+__global__ void band_tridiag_kernel(const BandSec *__restrict__ secs) {
+    const BandSec S = secs[blockIdx.y];
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < S.n; j += (int64_t)gridDim.x * blockDim.x) {
+        S.d[j] = S.band[j * LDB];
+        if (j + 1 < S.n) S.e[j] = S.band[1 + j * LDB];
+    }
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+size_t band_workspace_doubles(int64_t n) {
+    return (size_t)n * (3 * BW + LDB + 1) + (size_t)kQrMaxBlk * QP + BW + 4 * BW * BW + 64;
+}
+
+int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
+    const int nsec = (int)in.size();
+    if (nsec == 0) return TGBA_OK;
+    for (auto &x : in)
+        if (x.n > (int64_t)kQrMaxBlk * QCH) return set_error(TGBA_EUNSUPPORTED, "two-stage reduction: order above 65536");
+    // sectors by decreasing order: the sectors a panel needs are a prefix
+    std::vector<int> order(nsec);
+    for (int k = 0; k < nsec; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return in[a].n > in[b].n; });
+    size_t total = 0;
+    for (auto &x : in) total += band_workspace_doubles(x.n);
+    void *wsp = nullptr;
+    int rc = workspace_get(total * sizeof(double), kSlotWork, &wsp);
+    if (rc) return rc;
+    double *p = (double *)wsp;
+    std::vector<BandSec> secs(nsec);
+    int64_t wg = 0;
+    for (int q = 0; q < nsec; ++q) {
+        const BandIn &x = in[order[q]];
+        BandSec &S = secs[q];
+        S.A = x.A;
+        S.lda = x.lda;
+        S.n = x.n;
+        S.d = x.d;
+        S.e = x.e;
+        S.tau = p; p += x.n;
+        S.V = p; p += (size_t)x.n * BW;
+        S.X = p; p += (size_t)x.n * BW;
+        S.W = p; p += (size_t)x.n * BW;
+        S.band = p; p += (size_t)x.n * LDB;
+        S.qpart = p; p += (size_t)kQrMaxBlk * QP + BW;
+        S.S = p; p += BW * BW;
+        S.T = p; p += BW * BW;
+        S.Y = p; p += BW * BW;
+        S.M = p; p += BW * BW;
+        S.first_wg = wg;
+        S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / 4 + 2 : 0;
+        wg += S.cap;
+    }
+    void *wsd = nullptr;
+    if ((rc = workspace_get(nsec * sizeof(BandSec), kSlotSecs, &wsd))) return rc;
+    BandSec *d_secs = (BandSec *)wsd;
+    TGBA_HIP(hipMemcpyAsync(d_secs, secs.data(), nsec * sizeof(BandSec), hipMemcpyHostToDevice, stream));
+
+    // split-K partial buffers: size for the largest panel call
+    const int64_t nmax = secs[0].n;
+    auto active = [&](int64_t j0) {  // sectors whose panel at j0 has m >= 2 rows
+        int a = 0;
+        while (a < nsec && secs[a].n - j0 - BW >= 2) ++a;
+        return a;
+    };
+    // K split per sector: enough workgroups for the chip, chunks of >= 512
+    auto splits = [&](int act, int64_t j0, std::vector<int> &sym, std::vector<int> &gram) {
+        int64_t base = 0;
+        for (int q = 0; q < act; ++q) base += 2 * ceil_div(secs[q].n - j0 - BW, 128);
+        sym.assign(act, 1);
+        gram.assign(act, 1);
+        for (int q = 0; q < act; ++q) {
+            const int64_t m = secs[q].n - j0 - BW;
+            int64_t ks = std::max<int64_t>(1, ceil_div(2048, std::max<int64_t>(base, 1)));
+            ks = std::min<int64_t>({ks, 32, std::max<int64_t>(1, m / 512)});
+            sym[q] = (int)ks;
+            gram[q] = (int)std::min<int64_t>(64, std::max<int64_t>(1, m / 512));
+        }
+    };
+    size_t part_max = 0;
+    for (int64_t j0 = 0; j0 < nmax; j0 += BW) {
+        const int act = active(j0);
+        if (act == 0) break;
+        std::vector<int> sym, gram;
+        splits(act, j0, sym, gram);
+        size_t need = 0;
+        for (int q = 0; q < act; ++q) {
+            const int64_t m = secs[q].n - j0 - BW;
+            need += (size_t)2 * sym[q] * m * BW + (size_t)gram[q] * BW * BW;
+        }
+        part_max = std::max(part_max, need);
+    }
+    double *parts = nullptr;
+    if (part_max) {
+        void *wpp = nullptr;
+        if ((rc = workspace_get(part_max * sizeof(double), kSlotParts, &wpp))) return rc;
+        parts = (double *)wpp;
+    }
+
+    // ---- stage 1 ----
+    for (int64_t j0 = 0; j0 < nmax; j0 += BW) {
+        const int act = active(j0);
+        if (act == 0) break;
+        const int64_t m0 = secs[0].n - j0 - BW;
+        for (int q = 0; q < BW; ++q) {
+            if (q >= m0 - 1) break;  // no sector has a reflector q (sector 0 has the most rows)
+            const int maxblk = (int)ceil_div(m0 - q, QCH);
+            hipLaunchKernelGGL(qr_dots_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
+            hipLaunchKernelGGL(qr_update_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
+        }
+        hipLaunchKernelGGL(extract_panel_v_kernel, dim3(512, act), dim3(256), 0, stream, d_secs, j0);
+        TGBA_HIP(hipGetLastError());
+        std::vector<int> sym, gram;
+        splits(act, j0, sym, gram);
+        // Gram S = V^T V (split K) -> larft
+        std::vector<GemmDesc> g;
+        std::vector<ReduceDesc> red;
+        double *pp = parts;
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            const int64_t m = S.n - j0 - BW;
+            GemmDesc G{S.V, S.n, S.V, S.n, S.S, BW, BW, BW, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+            G.ksplit = gram[q];
+            G.Cpart = pp;
+            g.push_back(G);
+            red.push_back(ReduceDesc{S.S, BW, BW, BW, pp, gram[q], 0.0, 0});
+            pp += (size_t)gram[q] * BW * BW;
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+        hipLaunchKernelGGL(larft_panel_kernel, dim3(act), dim3(BW), 0, stream, d_secs, j0);
+        TGBA_HIP(hipGetLastError());
+        // X = A22 V = tril(A22) V + stril(A22)^T V (split K) into X
+        g.clear();
+        red.clear();
+        pp = parts;
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            const int64_t m = S.n - j0 - BW, t0 = j0 + BW;
+            const double *A22 = S.A + t0 + t0 * S.lda;
+            GemmDesc G1{A22, S.lda, S.V, S.n, S.X, S.n, m, BW, m, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+            G1.amask = 1;
+            G1.ksplit = sym[q];
+            G1.Cpart = pp;
+            GemmDesc G2 = G1;
+            G2.transA = 1;
+            G2.amask = 2;
+            G2.Cpart = pp + (size_t)sym[q] * m * BW;
+            g.push_back(G1);
+            g.push_back(G2);
+            red.push_back(ReduceDesc{S.X, S.n, m, BW, pp, 2 * sym[q], 0.0, 0});
+            pp += (size_t)2 * sym[q] * m * BW;
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+        // W = X T
+        g.clear();
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            const int64_t m = S.n - j0 - BW;
+            g.push_back(GemmDesc{S.X, S.n, S.T, BW, S.W, S.n, m, BW, BW, 1.0, 0.0, 0, 0, 0, 0, 0, 0});
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        // Y = V^T W (split K)
+        g.clear();
+        red.clear();
+        pp = parts;
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            const int64_t m = S.n - j0 - BW;
+            GemmDesc G{S.V, S.n, S.W, S.n, S.Y, BW, BW, BW, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+            G.ksplit = gram[q];
+            G.Cpart = pp;
+            g.push_back(G);
+            red.push_back(ReduceDesc{S.Y, BW, BW, BW, pp, gram[q], 0.0, 0});
+            pp += (size_t)gram[q] * BW * BW;
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+        // M = T^T Y
+        g.clear();
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            g.push_back(GemmDesc{S.T, BW, S.Y, BW, S.M, BW, BW, BW, BW, 1.0, 0.0, 1, 0, 0, 0, 0, 0});
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        // W -= 1/2 V M
+        g.clear();
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            const int64_t m = S.n - j0 - BW;
+            g.push_back(GemmDesc{S.V, S.n, S.M, BW, S.W, S.n, m, BW, BW, -0.5, 1.0, 0, 0, 0, 0, 0, 0});
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        // A22 -= V W^T + W V^T (lower tiles; one product of depth 2 BW)
+        g.clear();
+        for (int q = 0; q < act; ++q) {
+            const BandSec &S = secs[q];
+            const int64_t m = S.n - j0 - BW, t0 = j0 + BW;
+            double *A22 = S.A + t0 + t0 * S.lda;
+            GemmDesc G{S.V, S.n, S.W, S.n, A22, S.lda, m, m, BW, -1.0, 1.0, 0, 1, 1, 0, 0, 0};
+            G.A2 = S.W;
+            G.lda2 = S.n;
+            G.B2 = S.V;
+            G.ldb2 = S.n;
+            G.K2 = BW;
+            g.push_back(G);
+        }
+        if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+    }
+    hipLaunchKernelGGL(band_extract_kernel, dim3(256, nsec), dim3(256), 0, stream, d_secs);
+    TGBA_HIP(hipGetLastError());
+
+    // ---- stage 2 ----
+    const int64_t n0 = secs[0].n;
+    if (n0 >= 3 && wg > 0) {
+        // the last task of a sector of order n is sweep n-3 at k = 0: step 4 (n - 3)
+        const int64_t tmax = 4 * (n0 - 3);
+        int act = nsec;
+        for (int64_t t = 0; t <= tmax; ++t) {
+            // sectors with tasks left at step t are a prefix (decreasing order)
+            while (act > 0 && (secs[act - 1].n < 3 || 4 * (secs[act - 1].n - 3) < t)) --act;
+            const int64_t grid = secs[act - 1].first_wg + secs[act - 1].cap;
+            hipLaunchKernelGGL(sb2st_step_kernel, dim3((unsigned)grid), dim3(256), 0, stream, d_secs, act, t);
+        }
+        TGBA_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(band_tridiag_kernel, dim3(64, nsec), dim3(256), 0, stream, d_secs);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+}  // namespace tgba

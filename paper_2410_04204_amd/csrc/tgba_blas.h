@@ -29,6 +29,25 @@ struct GemmDesc {
     const double *B2 = nullptr;
     int64_t ldb2 = 0;
     int64_t K2 = 0;
+    // optional triangular mask of A in its storage coordinates (r, c): 1 keeps r >= c, 2 keeps
+    // r > c, entries outside are read as 0 (products with one triangle of a symmetric matrix)
+    int amask = 0;
+    // split of K over ksplit workgroups per output tile.  With Cpart set (any ksplit), each
+    // writes alpha * (its partial product) to Cpart + kc * M * N (column-major, ld M); C
+    // is not touched and a ReduceDesc sums the parts (requires lower == 0 and K2 == 0)
+    int ksplit = 1;
+    double *Cpart = nullptr;
+    int64_t ntile = 0;  // output tiles (filled by dgemm_batched)
+};
+
+// C = beta C + sum_{p < nparts} parts[p] (each M x N, ld M), in a fixed order.
+struct ReduceDesc {
+    double *C;
+    int64_t ldc, M, N;
+    const double *parts;
+    int nparts;
+    double beta;
+    int64_t first;  // filled by splitk_reduce
 };
 
 // The same in single precision (FP32 matrix cores, v_mfma_f32_32x32x2f32).
@@ -50,6 +69,7 @@ struct SGemmDesc {
 
 // One launch for all descriptors; descriptor storage from workspace `slot`.
 int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream);
+int splitk_reduce(std::vector<ReduceDesc> &descs, int slot, hipStream_t stream);
 int sgemm_batched(std::vector<SGemmDesc> &descs, int slot, hipStream_t stream);
 inline int gemm_batched(std::vector<GemmDesc> &d, int slot, hipStream_t st) { return dgemm_batched(d, slot, st); }
 inline int gemm_batched(std::vector<SGemmDesc> &d, int slot, hipStream_t st) { return sgemm_batched(d, slot, st); }

@@ -9,7 +9,12 @@
 // of v_mfma_f64_16x16x4: operand a of lane l is A[l%16][l/16], operand b is
 // B[l/16][l%16], and the 4 accumulator registers r hold D[4r + l/16][l%16].
 // With `lower` set only tiles touching the lower triangle are computed and
-// only elements with i >= j are written (symmetric rank-k updates).
+// only elements with i >= j are written (symmetric rank-k updates).  `amask`
+// reads A as one of its triangles (a product with a symmetric matrix stored
+// in its lower triangle is tril(A) B + stril(A)^T B); each output tile then
+// skips the K range that is zero.  `ksplit` divides K over several workgroups
+// per output tile, which write partial products for splitk_reduce.
+#include <algorithm>
 #include <cstdint>
 
 #include "tgba_internal.h"
@@ -49,11 +54,17 @@ struct TileRegs {
     double a[8], b[8];
 };
 
-__device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_t n0, int64_t kt, int tid, TileRegs &r) {
-    // tiles with kt >= K come from the second part (A2, B2)
+__device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_t n0, int64_t kt, int64_t kend, int tid,
+                                          TileRegs &r) {
+    // tiles with kt >= K come from the second part (A2, B2); the first part is
+    // read for k < kend only (kend <= K: a split or masked K range)
     GemmDesc G = G0;
     int64_t k0 = kt;
+    G.K = kend;
+    const int moff = G0.amask == 2 ? 1 : 0;
+    bool mask = G0.amask != 0;
     if (kt >= G0.K) {
+        mask = false;
         G.A = G0.A2;
         G.lda = G0.lda2;
         G.B = G0.B2;
@@ -70,7 +81,8 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const double x = op_ld(rs, voff, (uint32_t)(2 * s) * la);
-            r.a[s] = (k0 + kq + 2 * s < G.K) ? x : 0.0;
+            const int64_t k = k0 + kq + 2 * s;  // storage (m0 + i, k)
+            r.a[s] = (k < G.K && (!mask || m0 + i - k >= moff)) ? x : 0.0;
         }
     } else {  // op(A)[i][k] = A[k + i lda]; k = tid & 15, i = (tid >> 4) + 16 s
         const double *base = G.A + k0 + m0 * G.lda;
@@ -80,7 +92,8 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const double x = op_ld(rs, voff, (uint32_t)(16 * s) * la);
-            r.a[s] = (k0 + k < G.K) ? x : 0.0;
+            const int64_t ii = m0 + iq + 16 * s;  // storage (k0 + k, ii)
+            r.a[s] = (k0 + k < G.K && (!mask || k0 + k - ii >= moff)) ? x : 0.0;
         }
     }
     if (!G.transB) {  // op(B)[k][j] = B[k + j ldb]; k = tid & 15, j = (tid >> 4) + 16 s
@@ -130,7 +143,8 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
     __shared__ double As[TK][LDS_STRIDE];  // As[k][i]
     __shared__ double Bs[TK][LDS_STRIDE];  // Bs[k][j]
     const GemmDesc G = descs[gemm_desc_of(descs, nd, blockIdx.x)];
-    const int64_t t = blockIdx.x - G.first_tile;
+    const int64_t tl = blockIdx.x - G.first_tile;
+    const int64_t kc = tl / G.ntile, t = tl - kc * G.ntile;
     int64_t ti, tj;
     if (G.lower) {  // lower-triangular tile enumeration: t = ti (ti + 1) / 2 + tj, tj <= ti
         ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -151,13 +165,25 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
         for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
     TileRegs r;
-    const int64_t Ktot = G.K + G.K2;
-    if (Ktot > 0) load_tile(G, m0, n0, 0, tid, r);
-    for (int64_t k0 = 0; k0 < Ktot; k0 += TK) {
+    // K range of this workgroup: [kbeg, kstop); the first part is read below kend
+    int64_t kbeg = 0, kend = G.K, kstop = G.K + G.K2;
+    if (G.amask || G.Cpart) {
+        const int moff = G.amask == 2 ? 1 : 0;
+        if (G.amask && !G.transA) kend = min(kend, m0 + TM - moff);  // needs k <= i - moff
+        if (G.amask && G.transA) kbeg = max(kbeg, m0 + moff);        // needs k >= i + moff
+        if (G.Cpart) {
+            const int64_t Kc = ((G.K + G.ksplit - 1) / G.ksplit + TK - 1) / TK * TK;
+            kbeg = max(kbeg, kc * Kc);
+            kend = min(kend, (kc + 1) * Kc);
+        }
+        kstop = kend;
+    }
+    if (kbeg < kstop) load_tile(G, m0, n0, kbeg, kend, tid, r);
+    for (int64_t k0 = kbeg; k0 < kstop; k0 += TK) {
         __syncthreads();  // the previous tile's readers are done
         store_tile(G, tid, r, As, Bs);
         __syncthreads();
-        if (k0 + TK < Ktot) load_tile(G, m0, n0, k0 + TK, tid, r);
+        if (k0 + TK < kstop) load_tile(G, m0, n0, k0 + TK, kend, tid, r);
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
             double af[4], bf[4];
@@ -172,6 +198,20 @@ __global__ void __launch_bounds__(256) dgemm_kernel(const GemmDesc *__restrict__
         }
     }
     // epilogue: D[4r + l/16][l%16] of block (a, b)
+    if (G.Cpart) {
+        double *P = G.Cpart + kc * G.M * G.N;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int64_t i = m0 + 64 * wy + 16 * a + 4 * rr + (lane >> 4);
+                    const int64_t j = n0 + 64 * wx + 16 * b + (lane & 15);
+                    if (i < G.M && j < G.N) P[i + j * G.M] = G.alpha * acc[a][b][rr];
+                }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -322,9 +362,13 @@ int64_t gemm_tiles(const GemmDesc &g) {
 int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
     int64_t total = 0;
     for (auto &g : descs) {
+        if (g.ksplit < 1) g.ksplit = 1;
+        if ((g.ksplit > 1 && !g.Cpart) || (g.Cpart && (g.lower || g.K2)) || (g.amask && g.K2))
+            return set_error(TGBA_EINVAL, "split or masked product with unsupported options");
         g.tiles_m = (g.M + TM - 1) / TM;
         g.first_tile = total;
-        total += gemm_tiles(g);
+        g.ntile = gemm_tiles(g);
+        total += g.ntile * g.ksplit;
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
@@ -332,6 +376,43 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
     if (rc) return rc;
     TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(dgemm_kernel, dim3((unsigned)total), dim3(256), 0, stream, (const GemmDesc *)ws, (int)descs.size());
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+namespace {
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(const ReduceDesc *__restrict__ d, int nd, int64_t total) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].first <= e) lo = mid; else hi = mid - 1;
+        }
+        const ReduceDesc D = d[lo];
+        const int64_t loc = e - D.first, mn = D.M * D.N;
+        const int64_t i = loc % D.M, j = loc / D.M;
+        double acc = 0.0;
+        for (int p = 0; p < D.nparts; ++p) acc += D.parts[p * mn + loc];
+        double *c = D.C + i + j * D.ldc;
+        *c = (D.beta == 0.0) ? acc : acc + D.beta * (*c);
+    }
+}
+}  // namespace
+
+int splitk_reduce(std::vector<ReduceDesc> &descs, int slot, hipStream_t stream) {
+    int64_t total = 0;
+    for (auto &r : descs) {
+        r.first = total;
+        total += (r.M > 0 && r.N > 0) ? r.M * r.N : 0;
+    }
+    if (total == 0) return TGBA_OK;
+    void *ws = nullptr;
+    int rc = workspace_get(descs.size() * sizeof(ReduceDesc), slot, &ws);
+    if (rc) return rc;
+    TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(ReduceDesc), hipMemcpyHostToDevice, stream));
+    const int64_t grid = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)grid), dim3(256), 0, stream, (const ReduceDesc *)ws,
+                       (int)descs.size(), total);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }

@@ -21,6 +21,7 @@
 #include "tgba_blas.h"
 #include "tgba_dc.h"
 #include "tgba_eig.h"
+#include "tgba_band.h"
 #include "tgba_internal.h"
 
 namespace tgba {
@@ -839,6 +840,15 @@ extern "C" int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *
     return sytrd_batched(secs, st);
 }
 
+extern "C" int tgba_sytrd_2stage(int64_t n, double *A, int64_t lda, double *d, double *e, void *stream) {
+    tgba::clear_error();
+    if (n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && (!A || !d || (n > 1 && !e))))
+        return tgba::set_error(TGBA_EINVAL, "bad two-stage reduction arguments");
+    if (n == 0) return TGBA_OK;
+    std::vector<tgba::BandIn> in{tgba::BandIn{A, lda, n, d, e}};
+    return tgba::sytrd_2stage_batched(in, (hipStream_t)stream);
+}
+
 extern "C" int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream) {
     clear_error();
     if (n < 0 || (n > 0 && (!d || !w)) || (n > 1 && !e)) return set_error(TGBA_EINVAL, "bad arguments");
@@ -1002,6 +1012,15 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         secs.push_back(S);
         bis.push_back(BisIn{S.d, S.e, w[k], n[k]});
     }
+    if (novec && !(flags & TGBA_EIG_ONESTAGE)) {
+        std::vector<BandIn> bin;
+        for (auto &S : secs) bin.push_back(BandIn{S.A, S.lda, S.n, S.d, S.e});
+        if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
+        rc = stebz_batched(bis, stream);
+        if (rc) return rc;
+        TGBA_HIP(hipStreamSynchronize(stream));
+        return TGBA_OK;
+    }
     rc = sytrd_batched(secs, stream);
     if (rc) return rc;
     if (novec) {
@@ -1036,7 +1055,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
 
 extern "C" int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags, void *stream) {
     clear_error();
-    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC)) return set_error(TGBA_EINVAL, "unknown flags");
+    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC | TGBA_EIG_ONESTAGE)) return set_error(TGBA_EINVAL, "unknown flags");
     double *As[1] = {A};
     double *ws[1] = {w};
     return eig_batched(1, &n, As, &lda, ws, flags, (hipStream_t)stream);
@@ -1053,6 +1072,6 @@ extern "C" int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, co
                                 int flags, void *stream) {
     clear_error();
     if (nsec < 0 || (nsec > 0 && (!n || !A || !lda || !w))) return set_error(TGBA_EINVAL, "bad arguments");
-    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC)) return set_error(TGBA_EINVAL, "unknown flags");
+    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC | TGBA_EIG_ONESTAGE)) return set_error(TGBA_EINVAL, "unknown flags");
     return eig_batched(nsec, n, A, lda, w, flags, (hipStream_t)stream);
 }

@@ -13,7 +13,7 @@
 
 namespace tgba {
 namespace {
-constexpr int kSlots = 32;
+constexpr int kSlots = 48;
 constexpr int kDevices = 16;
 struct Buf {
     void *p = nullptr;

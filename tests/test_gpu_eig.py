@@ -74,6 +74,66 @@ def test_tridiagonal_reduction_and_bisection_eigenvalues(n):
         assert np.abs(ref_t - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max()) * np.sqrt(n)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 65, 66, 67, 129, 130, 200, 1000, 2049, 4500])
+def test_two_stage_reduction_and_bisection_eigenvalues(n):
+    """Band reduction (several 64-column panels and a ragged tail) + bulge chasing."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    A = _rand_sym(n, n + 11)
+    dA = _cm(A)
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device="cuda")
+    print(f"two-stage n={n}", flush=True)
+    tg.sytrd_2stage(dA, d, e)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg.stebz(d, e, w)
+    torch.cuda.synchronize()
+    ref = scipy.linalg.eigvalsh(A)
+    err = np.abs(w.cpu().numpy() - ref).max()
+    print(f"  max err {err:.2e} (max|lambda| {np.abs(ref).max():.1f})", flush=True)
+    assert err <= 1e-12 * max(1.0, np.abs(ref).max()) * np.sqrt(n)
+
+
+def test_two_stage_batched_uneven_sectors_match_lapack_and_one_stage():
+    """Uneven sector sizes in one batched call (the sectors finish their panels
+    and their sweeps at different steps), two-stage vs one-stage vs LAPACK."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    sizes = [700, 3, 1, 1500, 64, 257, 130, 2]
+    As = [_rand_sym(n, 100 + n) for n in sizes]
+    got = {}
+    for name, fl in (("two", tg.TGBA_EIG_NOVEC), ("one", tg.TGBA_EIG_NOVEC | tg.TGBA_EIG_ONESTAGE)):
+        mats = [_cm(A) for A in As]
+        ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+        tg.eig_batched(mats, ws, fl)
+        got[name] = [w.cpu().numpy() for w in ws]
+    for A, w2, w1 in zip(As, got["two"], got["one"]):
+        ref = scipy.linalg.eigvalsh(A)
+        tol = 1e-12 * max(1.0, np.abs(ref).max()) * np.sqrt(A.shape[0])
+        assert np.abs(w2 - ref).max() <= tol
+        assert np.abs(w1 - ref).max() <= tol
+
+
+def test_masked_split_k_symmetric_product():
+    """tril(A) V + stril(A)^T V (the first stage's product with the trailing
+    matrix, from its lower triangle) equals A V; exercised through the
+    two-stage reduction of a matrix whose upper triangle holds garbage."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    n = 1537
+    A = _rand_sym(n, 77)
+    G = A.copy()
+    G[np.triu_indices(n, 1)] = 1e6  # never read
+    dA = _cm(G)
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    e = torch.empty(n - 1, dtype=torch.float64, device="cuda")
+    tg.sytrd_2stage(dA, d, e)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg.stebz(d, e, w)
+    ref = scipy.linalg.eigvalsh(A)
+    assert np.abs(w.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max() * np.sqrt(n)
+
+
 def test_eig_novec_and_batched_on_heff_sectors():
     import paper_2410_04204_amd as tg
     from oracle import basis as ob, heff, spectral

@@ -61,7 +61,7 @@ def test_autotuned_shapes_give_default_results():
         tg.assemble_heff(B, 0, H[mode], tg.TGBA_HEFF | tg.TGBA_LOWER)
         A = H[mode].clone()
         w[mode] = torch.empty(n, dtype=torch.float64, device="cuda")
-        tg.eig(A, w[mode], tg.TGBA_EIG_NOVEC)
+        tg.eig(A, w[mode], tg.TGBA_EIG_NOVEC | tg.TGBA_EIG_ONESTAGE)  # the tuned symmetric product
     rep = tg.autotune_report()
     print(rep, flush=True)
     assert any(k.startswith("assemble_rows/N=24") for k in rep)
