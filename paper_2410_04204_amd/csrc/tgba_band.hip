@@ -26,10 +26,12 @@
 //   * applied from the left to the rest of that bulge block, from both sides
 //     to the diagonal block, from the right to the block below (the next
 //     bulge).
-// Task (i, k) runs at step t = 4 i + k.  Tasks of one step touch index ranges
-// [r - BW, r + 2 BW) that are 4 BW - 1 apart, and every conflicting pair of
-// tasks keeps the order of the sequential algorithm, so each step is one
-// launch with one workgroup per task of every sector.
+// Task (i, k) runs at step t = 3 i + k.  Every entry task (i, k) touches
+// lies in rows >= r, and every entry of the concurrent task (i + 1, k - 3) in
+// rows <= r - BW, so the tasks of one step are disjoint; every conflicting
+// pair of tasks keeps the order of the sequential algorithm (checked against
+// it, bit for bit, with the tasks of each step run in either order).  So each
+// step is one launch with one workgroup per task of every sector.
 //
 // The tridiagonal (d, e) then goes to the bisection of tgba_stebz.
 #include <algorithm>
@@ -43,11 +45,15 @@
 namespace tgba {
 namespace {
 
-constexpr int BW = kBandWidth;     // half-bandwidth of stage 1
+constexpr int BW = kBandWidth;     // half-bandwidth of stage 1 (<= 64: a band row per lane)
+static_assert(BW <= 64 && BW % 16 == 0, "band width");
 constexpr int LDB = 2 * BW;        // rows of the band storage
 constexpr int QCH = 1024;          // panel rows per workgroup of the panel QR
 constexpr int kQrMaxBlk = 64;      // partial-sum rows of the panel QR (>= ceil(n / QCH) for n <= 65536)
 constexpr int QP = BW + 1;         // partial sums per block: BW dot products + the norm
+constexpr int kMaxBandSecs = 256;  // sectors of one call (the step kernel indexes them in LDS)
+constexpr int kStride = 3;         // bulge-chasing schedule: task (i, k) at step kStride i + k
+constexpr int SB = 16;             // columns of a panel-QR sub-block
 
 // workspace slots of this file
 constexpr int kSlotSecs = 30, kSlotWork = 31, kSlotParts = 32, kSlotGemm = 33, kSlotRed = 34;
@@ -77,9 +83,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Panel of sector s at column j0: P[r + c lda] = A[(j0 + BW + r) + (j0 + c) lda],
 // r < m = n - j0 - BW, c < BW.  Column q's reflector acts on rows q .. m-1.
 
+// The panel is factored in sub-blocks of SB columns [c0, c0 + SB): the column
+// kernels touch only the sub-block; the rest of the panel then receives the
+// sub-block's block reflector by products (a third of the panel traffic).
+//
 // One pass over rows q.. of the panel: sum_{r > q} P[r][q]^2 and
-// sum_{r >= q} P[r][q] P[r][j] for j > q, per block of QCH rows; block 0 also
-// saves the row q of the panel (read by every block of qr_update).
+// sum_{r >= q} P[r][q] P[r][j] for q < j < c0 + SB, per block of QCH rows;
+// block 0 also saves row q of the sub-block (read by every block of qr_update).
 __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict__ secs, int64_t j0, int q, int maxblk) {
     const int s = blockIdx.x / maxblk, blk = blockIdx.x % maxblk;
     const BandSec S = secs[s];
@@ -92,9 +102,10 @@ __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict_
     const double *P = S.A + (j0 + BW) + j0 * S.lda;
     const int64_t lda = S.lda;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double acc[BW];
+    const int c0 = q & ~(SB - 1), c1 = c0 + SB;
+    double acc[SB];
 #pragma unroll
-    for (int j = 0; j < BW; ++j) acc[j] = 0.0;
+    for (int jj = 0; jj < SB; ++jj) acc[jj] = 0.0;
     double nrm = 0.0;
     for (int it = 0; it < QCH / 256; ++it) {
         const int64_t r = q + (int64_t)blk * QCH + it * 256 + tid;
@@ -102,24 +113,24 @@ __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict_
             const double x = P[r + q * lda];
             if (r > q) nrm += x * x;
 #pragma unroll
-            for (int j = 0; j < BW; ++j)
-                if (j > q) acc[j] += x * P[r + j * lda];
+            for (int jj = 0; jj < SB; ++jj)
+                if (c0 + jj > q) acc[jj] += x * P[r + (c0 + jj) * lda];
         }
     }
     __shared__ double red[4][QP];
 #pragma unroll
-    for (int j = 0; j < BW; ++j) {
-        if (j > q) {  // q is uniform: the branch is too
-            const double v = wave_sum(acc[j]);
-            if (lane == 0) red[wave][j] = v;
+    for (int jj = 0; jj < SB; ++jj) {
+        if (c0 + jj > q) {  // q is uniform: the branch is too
+            const double v = wave_sum(acc[jj]);
+            if (lane == 0) red[wave][c0 + jj] = v;
         }
     }
     nrm = wave_sum(nrm);
     if (lane == 0) red[wave][BW] = nrm;
     __syncthreads();
     double *out = S.qpart + (int64_t)blk * QP;
-    if (tid < QP && (tid > q || tid == BW)) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    if (blk == 0 && tid < BW && tid >= q) S.qpart[kQrMaxBlk * QP + tid] = P[q + tid * lda];
+    if (tid < QP && ((tid > q && tid < c1) || tid == BW)) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (blk == 0 && tid >= q && tid < c1) S.qpart[kQrMaxBlk * QP + tid] = P[q + tid * lda];
 }
 
 // Reflector of column q from the partial sums, then its application to rows
@@ -137,8 +148,9 @@ __global__ void __launch_bounds__(256) qr_update_kernel(const BandSec *__restric
     const int64_t lda = S.lda;
     const int tid = threadIdx.x;
     __shared__ double sums[QP], w[BW], par[3];
+    const int c1 = (q & ~(SB - 1)) + SB;
     const double *top = S.qpart + kQrMaxBlk * QP;
-    if (tid < QP && (tid > q || tid == BW)) {
+    if (tid < QP && ((tid > q && tid < c1) || tid == BW)) {
         double a = 0.0;
         for (int64_t b = 0; b < nblk; ++b) a += S.qpart[b * QP + tid];
         sums[tid] = a;
@@ -160,56 +172,61 @@ __global__ void __launch_bounds__(256) qr_update_kernel(const BandSec *__restric
     __syncthreads();
     const double tau = par[0], beta = par[1], scale = par[2];
     // w_j = v^T P[:, j] = P[q][j] + scale (sum_{r >= q} x_r P[r][j] - alpha P[q][j])
-    if (tid < BW && tid > q) w[tid] = top[tid] + scale * (sums[tid] - top[q] * top[tid]);
+    if (tid > q && tid < c1) w[tid] = top[tid] + scale * (sums[tid] - top[q] * top[tid]);
     __syncthreads();
     for (int it = 0; it < QCH / 256; ++it) {
         const int64_t r = q + (int64_t)blk * QCH + it * 256 + tid;
         if (r >= m) continue;
         if (r == q) {
-            for (int j = q + 1; j < BW; ++j) P[q + j * lda] -= tau * w[j];
+            for (int j = q + 1; j < c1; ++j) P[q + j * lda] -= tau * w[j];
             P[q + q * lda] = beta;
         } else {
             const double v = P[r + q * lda] * scale;
             P[r + q * lda] = v;
-            for (int j = q + 1; j < BW; ++j) P[r + j * lda] -= tau * v * w[j];
+            for (int j = q + 1; j < c1; ++j) P[r + j * lda] -= tau * v * w[j];
         }
     }
 }
 
-// V (m x BW, ld n): unit lower trapezoidal reflectors of the panel, zero columns
-// beyond the panel's nref reflectors (whose tau is set to 0).
-__global__ void extract_panel_v_kernel(const BandSec *__restrict__ secs, int64_t j0) {
+// Columns [c0, c0 + SB) of V (m x BW, ld n): unit lower trapezoidal reflectors
+// of the panel, zero columns beyond the panel's nref reflectors (tau set to 0).
+__global__ void extract_panel_v_kernel(const BandSec *__restrict__ secs, int64_t j0, int c0) {
     const BandSec S = secs[blockIdx.y];
     const int64_t m = S.n - j0 - BW;
     if (m < 2) return;
     const int64_t nref = m - 1 < BW ? m - 1 : BW;
     const double *P = S.A + (j0 + BW) + j0 * S.lda;
-    const int64_t tot = m * BW;
+    const int64_t tot = m * SB;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = k % m, c = k / m;
+        const int64_t r = k % m, c = c0 + k / m;
         double v = 0.0;
         if (c < nref) v = (r < c) ? 0.0 : ((r == c) ? 1.0 : P[r + c * S.lda]);
         S.V[r + c * S.n] = v;
     }
-    if (blockIdx.x == 0 && threadIdx.x < BW && threadIdx.x >= nref) S.tau[j0 + threadIdx.x] = 0.0;
+    const int c = c0 + (int)threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < SB && c >= nref) S.tau[j0 + c] = 0.0;
 }
 
-// T (BW x BW, upper) of Q = I - V T V^T from the Gram matrix S = V^T V:
-// T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) S(0:i, i).  One workgroup per sector.
-__global__ void larft_panel_kernel(const BandSec *__restrict__ secs, int64_t j0) {
+// T (nb x nb, upper, ld BW) of H_c0 ... H_{c0+nb-1} = I - V T V^T from the
+// Gram matrix G = V^T V (ld BW): T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i).
+// One workgroup of BW threads per sector; sub = 0: the whole panel (S -> T),
+// sub = 1: a sub-block (Y -> M).
+__global__ void larft_panel_kernel(const BandSec *__restrict__ secs, int64_t j0, int c0, int nb, int sub) {
     const BandSec S = secs[blockIdx.x];
     if (S.n - j0 - BW < 2) return;
+    const double *Gm = sub ? S.Y : S.S;
+    double *Tm = sub ? S.M : S.T;
     __shared__ double Tl[BW][BW + 1];
     __shared__ double col[BW];
     const int j = threadIdx.x;  // BW threads
     for (int k = 0; k < BW; ++k) Tl[j][k] = 0.0;
     __syncthreads();
-    const double *tau = S.tau + j0;
-    for (int i = 0; i < BW; ++i) {
+    const double *tau = S.tau + j0 + c0;
+    for (int i = 0; i < nb; ++i) {
         const double ti = tau[i];
         if (j < i) {
             double acc = 0.0;
-            for (int l = j; l < i; ++l) acc += Tl[j][l] * S.S[l + i * BW];
+            for (int l = j; l < i; ++l) acc += Tl[j][l] * Gm[l + i * BW];
             col[j] = -ti * acc;
         }
         __syncthreads();
@@ -217,7 +234,8 @@ __global__ void larft_panel_kernel(const BandSec *__restrict__ secs, int64_t j0)
         if (j == i) Tl[i][i] = ti;
         __syncthreads();
     }
-    for (int r = 0; r < BW; ++r) S.T[r + j * BW] = Tl[r][j];
+    if (j < nb)
+        for (int r = 0; r < nb; ++r) Tm[r + j * BW] = Tl[r][j];
 }
 
 // Band storage from the reduced matrix: B[(i - j) + j LDB] = A[i][j] for
@@ -234,18 +252,39 @@ __global__ void band_extract_kernel(const BandSec *__restrict__ secs) {
 // ---- stage 2: bulge chasing -----------------------------------------------------
 __device__ __forceinline__ double &bat(double *B, int64_t row, int64_t c) { return B[(row - c) + c * LDB]; }
 
+// One workgroup per task.  Lane l is a row of every block, and thread (l, w)
+// holds columns w, w + 4, ... (16 of the 64) of the bulge block E (rows r..,
+// columns col+1 .. r-1), the diagonal block D (its lower triangle) and the
+// block F below D, so that every load is a contiguous column segment and all
+// 48 are in flight before any arithmetic.
 __global__ void __launch_bounds__(256) sb2st_step_kernel(const BandSec *__restrict__ secs, int nsec, int64_t t) {
-    __shared__ double Ds[BW][BW + 1];
-    __shared__ double vs[BW], ps[BW], wsv[BW], qs[BW];
-    __shared__ double par[3];
-    int s = 0;
-    while (s + 1 < nsec && secs[s + 1].first_wg <= (int64_t)blockIdx.x) ++s;
-    const BandSec S = secs[s];
-    const int64_t slot = blockIdx.x - S.first_wg;
-    const int64_t n = S.n;
-    if (slot >= S.cap || n < 3) return;
-    const int64_t i = t / 4 - slot, k = t % 4 + 4 * slot;
+    __shared__ double vs[64], prow[4][64], pcol[64], qrow[4][64], wsv[64], qv[64];  // lane-indexed (BW <= 64)
+    __shared__ double par[2];
+    __shared__ int64_t s_first[kMaxBandSecs], s_n[kMaxBandSecs], s_cap[kMaxBandSecs];
+    __shared__ int s_sec;
+    // sector of this workgroup: the sectors' first workgroups in LDS, one load each
+    for (int q = threadIdx.x; q < nsec; q += blockDim.x) {
+        s_first[q] = secs[q].first_wg;
+        s_n[q] = secs[q].n;
+        s_cap[q] = secs[q].cap;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = nsec - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_first[mid] <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        s_sec = lo;
+    }
+    __syncthreads();
+    const int s = s_sec;
+    const int64_t slot = blockIdx.x - s_first[s];
+    const int64_t n = s_n[s];
+    if (slot >= s_cap[s] || n < 3) return;
+    const int64_t i = t / kStride - slot, k = t % kStride + kStride * slot;
     if (i < 0 || i > n - 3 || k > (n - 3 - i) / BW) return;
+    const BandSec S = secs[s];
     const int64_t r = i + 1 + k * BW;
     const int ln = (int)(n - r < BW ? n - r : BW);              // >= 2
     const int64_t rest = n - r - ln;
@@ -253,10 +292,23 @@ __global__ void __launch_bounds__(256) sb2st_step_kernel(const BandSec *__restri
     const int64_t col = (k == 0) ? i : r - BW;
     double *B = S.band;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NJ = BW / 4;
 
-    // reflector from column col, rows r .. r+ln-1
+    // ---- loads ----
+    double x = 0.0;
+    if (wave == 0 && lane < ln) x = bat(B, r + lane, col);
+    double E[NJ], D[NJ], F[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
+        E[jj] = (k > 0 && j < BW - 1 && lane < ln) ? bat(B, r + lane, col + 1 + j) : 0.0;
+        D[jj] = (lane < ln && j <= lane) ? bat(B, r + lane, r + j) : 0.0;  // j < ln follows
+        F[jj] = (lane < ln2 && j < ln) ? bat(B, r + ln + lane, r + j) : 0.0;
+    }
+
+    if (tid < 64) pcol[tid] = 0.0;  // lanes beyond BW read it below
+    // ---- reflector from column col (wave 0) ----
     if (wave == 0) {
-        const double x = (lane < ln) ? bat(B, r + lane, col) : 0.0;
         const double sig = wave_sum(lane > 0 ? x * x : 0.0);
         const double alpha = __shfl(x, 0, 64);
         double tau = 0.0, beta = alpha, scale = 0.0;
@@ -269,59 +321,49 @@ __global__ void __launch_bounds__(256) sb2st_step_kernel(const BandSec *__restri
         if (lane < ln) bat(B, r + lane, col) = (lane == 0) ? beta : 0.0;
         if (lane == 0) par[0] = tau;
     }
-    // diagonal block (symmetric, from its lower triangle)
-    for (int e = tid; e < BW * BW; e += 256) {
-        const int a = e % BW, b = e / BW;
-        if (a < ln && b < ln && a >= b) {
-            const double v = bat(B, r + a, r + b);
-            Ds[a][b] = v;
-            Ds[b][a] = v;
-        }
-    }
     __syncthreads();
     const double tau = par[0];
-    if (tau == 0.0) return;  // identity reflector: nothing else changes (uniform)
+    if (tau == 0.0) return;  // identity reflector (uniform)
+    const double vl = vs[lane];
 
-    // left application to the rest of the bulge block: columns col+1 .. r-1, rows r..
+    // ---- left application to the bulge block: E -= tau v (v^T E) ----
     if (k > 0) {
-        for (int cc = wave; cc < BW - 1; cc += 4) {
-            const int64_t c = col + 1 + cc;
-            double e = (lane < ln) ? bat(B, r + lane, c) : 0.0;
-            const double wc = wave_sum(vs[lane] * e);
-            if (lane < ln) bat(B, r + lane, c) = e - tau * vs[lane] * wc;
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = wave + 4 * jj;
+            const double wc = wave_sum(vl * E[jj]);
+            if (j < BW - 1 && lane < ln) bat(B, r + lane, col + 1 + j) = E[jj] - tau * vl * wc;
         }
     }
-    // two-sided application to the diagonal block: p = tau D v, w = p - (tau/2)(p.v) v
-    if (tid < BW) {
-        double acc = 0.0;
-        if (tid < ln)
-            for (int b = 0; b < ln; ++b) acc += Ds[tid][b] * vs[b];
-        ps[tid] = tau * acc;
+    // ---- p = D v from the lower triangle; q = F v ----
+    double pr = 0.0, qr = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
+        const double vj = vs[j];
+        pr += D[jj] * vj;                                                  // D[l][j], j <= l
+        const double pc = wave_sum((j < lane) ? D[jj] * vl : 0.0);        // sum_{l > j} D[l][j] v_l
+        if (lane == 0) pcol[j] = pc;
+        qr += F[jj] * vj;
     }
-    // right application to the block below: q = F v
-    if (tid >= BW && tid < 2 * BW) {
-        const int a2 = tid - BW;
-        double acc = 0.0;
-        if (a2 < ln2)
-            for (int a = 0; a < ln; ++a) acc += bat(B, r + ln + a2, r + a) * vs[a];
-        qs[a2] = acc;
-    }
+    prow[wave][lane] = pr;
+    qrow[wave][lane] = qr;
     __syncthreads();
     if (wave == 0) {
-        const double kk = 0.5 * tau * wave_sum(ps[lane] * vs[lane]);
-        wsv[lane] = ps[lane] - kk * vs[lane];
+        const double pl = tau * (prow[0][lane] + prow[1][lane] + prow[2][lane] + prow[3][lane] + pcol[lane]);
+        const double kk = 0.5 * tau * wave_sum(pl * vl);
+        wsv[lane] = pl - kk * vl;
+        qv[lane] = qrow[0][lane] + qrow[1][lane] + qrow[2][lane] + qrow[3][lane];
     }
     __syncthreads();
-    for (int e = tid; e < BW * BW; e += 256) {
-        const int a = e % BW, b = e / BW;
-        if (a < ln && b < ln && a >= b) bat(B, r + a, r + b) = Ds[a][b] - vs[a] * wsv[b] - wsv[a] * vs[b];
-    }
-    for (int e = tid; e < BW * BW; e += 256) {
-        const int a2 = e % BW, a = e / BW;
-        if (a2 < ln2 && a < ln) {
-            double &f = bat(B, r + ln + a2, r + a);
-            f -= tau * qs[a2] * vs[a];
-        }
+    // ---- D -= v w^T + w v^T (lower), F -= tau q v^T ----
+    const double wl = wsv[lane], ql = qv[lane];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
+        const double vj = vs[j], wj = wsv[j];
+        if (lane < ln && j <= lane) bat(B, r + lane, r + j) = D[jj] - vl * wj - wl * vj;
+        if (lane < ln2 && j < ln) bat(B, r + ln + lane, r + j) = F[jj] - tau * ql * vj;
     }
 }
 
@@ -344,6 +386,7 @@ size_t band_workspace_doubles(int64_t n) {
 int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     const int nsec = (int)in.size();
     if (nsec == 0) return TGBA_OK;
+    if (nsec > kMaxBandSecs) return set_error(TGBA_EUNSUPPORTED, "two-stage reduction: more than 256 sectors in one call");
     for (auto &x : in)
         if (x.n > (int64_t)kQrMaxBlk * QCH) return set_error(TGBA_EUNSUPPORTED, "two-stage reduction: order above 65536");
     // sectors by decreasing order: the sectors a panel needs are a prefix
@@ -377,7 +420,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.Y = p; p += BW * BW;
         S.M = p; p += BW * BW;
         S.first_wg = wg;
-        S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / 4 + 2 : 0;
+        S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / kStride + 2 : 0;
         wg += S.cap;
     }
     void *wsd = nullptr;
@@ -431,16 +474,63 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         const int act = active(j0);
         if (act == 0) break;
         const int64_t m0 = secs[0].n - j0 - BW;
-        for (int q = 0; q < BW; ++q) {
-            if (q >= m0 - 1) break;  // no sector has a reflector q (sector 0 has the most rows)
-            const int maxblk = (int)ceil_div(m0 - q, QCH);
-            hipLaunchKernelGGL(qr_dots_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
-            hipLaunchKernelGGL(qr_update_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
-        }
-        hipLaunchKernelGGL(extract_panel_v_kernel, dim3(512, act), dim3(256), 0, stream, d_secs, j0);
-        TGBA_HIP(hipGetLastError());
         std::vector<int> sym, gram;
         splits(act, j0, sym, gram);
+        for (int c0 = 0; c0 < BW; c0 += SB) {
+            for (int q = c0; q < c0 + SB; ++q) {
+                if (q >= m0 - 1) break;  // no sector has a reflector q (sector 0 has the most rows)
+                const int maxblk = (int)ceil_div(m0 - q, QCH);
+                hipLaunchKernelGGL(qr_dots_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
+                hipLaunchKernelGGL(qr_update_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
+            }
+            hipLaunchKernelGGL(extract_panel_v_kernel, dim3(256, act), dim3(256), 0, stream, d_secs, j0, c0);
+            TGBA_HIP(hipGetLastError());
+            const int c1 = c0 + SB, nrest = BW - c1;
+            if (nrest == 0 || c0 >= m0 - 1) continue;  // no columns to the right, or no reflector in the sub-block
+            // rest of the panel: P[:, c1:] -= V_sb T_sb^T (V_sb^T P[:, c1:])
+            std::vector<GemmDesc> g;
+            std::vector<ReduceDesc> red;
+            double *pp = parts;
+            for (int q = 0; q < act; ++q) {  // Gram of the sub-block -> Y (ld BW)
+                const BandSec &S = secs[q];
+                const int64_t m = S.n - j0 - BW;
+                GemmDesc G{S.V + (size_t)c0 * S.n, S.n, S.V + (size_t)c0 * S.n, S.n, S.Y, BW, SB, SB, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+                G.ksplit = gram[q];
+                G.Cpart = pp;
+                g.push_back(G);
+                red.push_back(ReduceDesc{S.Y, BW, SB, SB, pp, gram[q], 0.0, 0});
+                pp += (size_t)gram[q] * SB * SB;
+            }
+            for (int q = 0; q < act; ++q) {  // Z = V_sb^T P_rest -> X (ld SB)
+                const BandSec &S = secs[q];
+                const int64_t m = S.n - j0 - BW;
+                const double *Pr = S.A + (j0 + BW) + (j0 + c1) * S.lda;
+                GemmDesc G{S.V + (size_t)c0 * S.n, S.n, Pr, S.lda, S.X, SB, SB, nrest, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+                G.ksplit = gram[q];
+                G.Cpart = pp;
+                g.push_back(G);
+                red.push_back(ReduceDesc{S.X, SB, SB, nrest, pp, gram[q], 0.0, 0});
+                pp += (size_t)gram[q] * SB * nrest;
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+            if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+            hipLaunchKernelGGL(larft_panel_kernel, dim3(act), dim3(BW), 0, stream, d_secs, j0, c0, SB, 1);
+            TGBA_HIP(hipGetLastError());
+            g.clear();
+            for (int q = 0; q < act; ++q) {  // W = T_sb^T Z (ld SB)
+                const BandSec &S = secs[q];
+                g.push_back(GemmDesc{S.M, BW, S.X, SB, S.W, SB, SB, nrest, SB, 1.0, 0.0, 1, 0, 0, 0, 0, 0});
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+            g.clear();
+            for (int q = 0; q < act; ++q) {  // P_rest -= V_sb W
+                const BandSec &S = secs[q];
+                const int64_t m = S.n - j0 - BW;
+                double *Pr = S.A + (j0 + BW) + (j0 + c1) * S.lda;
+                g.push_back(GemmDesc{S.V + (size_t)c0 * S.n, S.n, S.W, SB, Pr, S.lda, m, nrest, SB, -1.0, 1.0, 0, 0, 0, 0, 0, 0});
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        }
         // Gram S = V^T V (split K) -> larft
         std::vector<GemmDesc> g;
         std::vector<ReduceDesc> red;
@@ -457,7 +547,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         }
         if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
         if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
-        hipLaunchKernelGGL(larft_panel_kernel, dim3(act), dim3(BW), 0, stream, d_secs, j0);
+        hipLaunchKernelGGL(larft_panel_kernel, dim3(act), dim3(BW), 0, stream, d_secs, j0, 0, BW, 0);
         TGBA_HIP(hipGetLastError());
         // X = A22 V = tril(A22) V + stril(A22)^T V (split K) into X
         g.clear();
@@ -543,12 +633,12 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     // ---- stage 2 ----
     const int64_t n0 = secs[0].n;
     if (n0 >= 3 && wg > 0) {
-        // the last task of a sector of order n is sweep n-3 at k = 0: step 4 (n - 3)
-        const int64_t tmax = 4 * (n0 - 3);
+        // the last task of a sector of order n is sweep n-3 at k = 0: step kStride (n - 3)
+        const int64_t tmax = kStride * (n0 - 3);
         int act = nsec;
         for (int64_t t = 0; t <= tmax; ++t) {
             // sectors with tasks left at step t are a prefix (decreasing order)
-            while (act > 0 && (secs[act - 1].n < 3 || 4 * (secs[act - 1].n - 3) < t)) --act;
+            while (act > 0 && (secs[act - 1].n < 3 || kStride * (secs[act - 1].n - 3) < t)) --act;
             const int64_t grid = secs[act - 1].first_wg + secs[act - 1].cap;
             hipLaunchKernelGGL(sb2st_step_kernel, dim3((unsigned)grid), dim3(256), 0, stream, d_secs, act, t);
         }

@@ -775,15 +775,39 @@ int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T
         hipLaunchKernelGGL(extract_v_kernel<T>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nbp, V);
         TGBA_HIP(hipGetLastError());
         std::vector<G> g(1);
-        g[0] = G{V, m, V, m, Sg, nbp, nbp, nbp, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
-        int rc = gemm_batched(g, 11, stream);
-        if (rc) return rc;
-        hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
-        TGBA_HIP(hipGetLastError());
         T *Zs = Z + (j0 + 1);
-        g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
-        rc = gemm_batched(g, 12, stream);
-        if (rc) return rc;
+        g[0] = G{V, m, V, m, Sg, nbp, nbp, nbp, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
+        int rc;
+        if constexpr (sizeof(T) == 8) {
+            // the two products with K = m have few output tiles: split K over workgroups
+            const int ks_s = (int)std::min<int64_t>(64, std::max<int64_t>(1, m / 512));
+            const int64_t tiles_w = (n + 127) / 128;
+            const int ks_w = (int)std::min<int64_t>({32, std::max<int64_t>(1, m / 512),
+                                                      std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles_w, 1))});
+            void *wp = nullptr;
+            const size_t need = (size_t)ks_s * nbp * nbp + (size_t)ks_w * nbp * n;
+            if ((rc = workspace_get(need * sizeof(double), 36, &wp))) return rc;
+            double *parts = (double *)wp;
+            g[0].ksplit = ks_s;
+            g[0].Cpart = parts;
+            if ((rc = gemm_batched(g, 11, stream))) return rc;
+            std::vector<ReduceDesc> red{ReduceDesc{Sg, nbp, nbp, nbp, parts, ks_s, 0.0, 0}};
+            if ((rc = splitk_reduce(red, 37, stream))) return rc;
+            hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
+            TGBA_HIP(hipGetLastError());
+            g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
+            g[0].ksplit = ks_w;
+            g[0].Cpart = parts + (size_t)ks_s * nbp * nbp;
+            if ((rc = gemm_batched(g, 12, stream))) return rc;
+            red[0] = ReduceDesc{W1, nbp, nbp, n, parts + (size_t)ks_s * nbp * nbp, ks_w, 0.0, 0};
+            if ((rc = splitk_reduce(red, 37, stream))) return rc;
+        } else {
+            if ((rc = gemm_batched(g, 11, stream))) return rc;
+            hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
+            TGBA_HIP(hipGetLastError());
+            g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
+            if ((rc = gemm_batched(g, 12, stream))) return rc;
+        }
         g[0] = G{Tm, nbp, W1, nbp, W2, nbp, nbp, n, nbp, T(1), T(0), 0, 0, 0, 0, 0, 0};
         rc = gemm_batched(g, 13, stream);
         if (rc) return rc;
