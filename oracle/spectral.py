@@ -10,6 +10,9 @@ w = G z_1 and b = Z^H w.  Then
     S(0, omega) = 2 pi N sum_a |b_a|^2 delta(omega - (E_a - E_1)),
 the delta replaced by a Lorentzian of half-width eta: (eta/pi) / (x^2 + eta^2).
 The sum runs over a = 1..chi including the elastic a = 1 term.
+
+Power spectrum (power-spectrum appendix): |<sigma^x>(omega)|^2 of the quench
+signal over a finite window, trapezoidal rule (power_spectrum).
 """
 import numpy as np
 import scipy.linalg
@@ -49,3 +52,20 @@ def dsf_cross(N, Ek, Zk, E0, Z0, X, omega, eta):
     x = np.asarray(omega)[:, None] - (Ek[None, :] - E0[0])
     lor = (eta / np.pi) / (x * x + eta * eta)
     return 2.0 * np.pi * N * (lor @ np.abs(b) ** 2)
+
+
+def power_spectrum(t0, dt, sx, omega):
+    """|<sigma^x>(omega)|^2 with <sigma^x>(omega) = int dt e^{-i omega t} <sigma^x>(t)
+    (power-spectrum appendix), the integral taken over the sampled window
+    t_n = t0 + n dt, n = 0 .. nt-1, by the trapezoidal rule (weights dt, and
+    dt / 2 at both ends); no window function and no mean subtraction."""
+    sx = np.asarray(sx, dtype=np.float64)
+    nt = sx.size
+    t = t0 + dt * np.arange(nt)
+    wts = np.full(nt, dt)
+    if nt >= 2:
+        wts[0] = wts[-1] = 0.5 * dt
+    elif nt == 1:
+        wts[0] = 0.0  # a single sample spans no interval
+    F = np.exp(-1j * np.outer(np.asarray(omega, dtype=np.float64), t)) @ (wts * sx)
+    return np.abs(F) ** 2

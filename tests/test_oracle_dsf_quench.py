@@ -154,3 +154,38 @@ def test_eps_metric_nested_and_identical():
     Bs = Bl[:4] + 0.1
     direct = np.sqrt(np.max(np.sum(np.abs(Bs - Bl[:4]) ** 2, axis=0) + np.sum(np.abs(Bl[4:]) ** 2, axis=0)))
     assert quench.eps_metric(keys[:4], Bs, keys, Bl) == pytest.approx(direct, rel=1e-14)
+
+
+def _trap_exp_sum(a, t0, dt, nt):
+    """sum_n w_n e^{i a t_n} (trapezoid weights) in closed form: a geometric series."""
+    z = np.exp(1j * a * dt)
+    if abs(1.0 - z) < 1e-14:
+        return dt * (nt - 1) * np.exp(1j * a * t0)
+    geo = (1.0 - z ** nt) / (1.0 - z)
+    return dt * np.exp(1j * a * t0) * (geo - 0.5 * (1.0 + z ** (nt - 1)))
+
+
+@pytest.mark.parametrize("t0,dt,nt", [(0.0, 0.05, 9601), (0.3, 0.05, 2001), (1.0, 0.1, 7)])
+def test_power_spectrum_of_a_cosine_equals_the_geometric_series(t0, dt, nt):
+    """cos(W t) = (e^{iWt} + e^{-iWt}) / 2: the trapezoid sum of each exponential
+    is a geometric series with its two half-weight ends."""
+    W = 1.7
+    omega = np.array([0.0, 0.5, W, 1.71, 3.4, 7.9])
+    t = t0 + dt * np.arange(nt)
+    got = spectral.power_spectrum(t0, dt, np.cos(W * t), omega)
+    want = np.abs(0.5 * (np.array([_trap_exp_sum(W - w, t0, dt, nt) for w in omega])
+                         + np.array([_trap_exp_sum(-W - w, t0, dt, nt) for w in omega]))) ** 2
+    np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-12 * want.max())
+
+
+def test_power_spectrum_special_cases():
+    # a constant is integrated exactly by the trapezoid rule: |F(0)|^2 = T^2
+    dt, nt = 0.05, 9601
+    T = dt * (nt - 1)
+    P = spectral.power_spectrum(0.0, dt, np.full(nt, 0.4), np.array([0.0]))
+    assert abs(P[0] - (0.4 * T) ** 2) <= 1e-12 * (0.4 * T) ** 2
+    # a peak at the signal's frequency: |F(W)|^2 -> (T / 2)^2 for a long window
+    W = 2.0
+    t = dt * np.arange(nt)
+    P = spectral.power_spectrum(0.0, dt, np.cos(W * t), np.array([W, W + 0.5]))
+    assert abs(np.sqrt(P[0]) - T / 2) <= 0.01 * T and P[1] < 1e-3 * P[0]
