@@ -284,6 +284,20 @@ int tgba_stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, vo
 int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
                const double *B, int64_t ldb, double beta, double *C, int64_t ldc, void *stream);
 
+/* ---- power spectrum of the quench signal (power-spectrum appendix) ------- */
+
+/*
+ * P_j = |X(omega_j)|^2 with X(omega) = int dt e^{-i omega t} x(t) (the Fourier
+ * transform of <sigma^x>(t) after the quench, whose modulus squared shows the
+ * E8 masses and their differences), the integral taken over the sampled window
+ * t_n = t0 + n dt, n < nt, by the trapezoidal rule (weights dt, dt/2 at both
+ * ends; no window function, no mean subtraction).  x (nt), omega (n_omega) and
+ * P (n_omega) are device arrays.  Stream-ordered.
+ * Errors: TGBA_EINVAL (nt < 1, n_omega < 1, dt <= 0, NULL).
+ */
+int tgba_power_spectrum(int64_t nt, double t0, double dt, const double *x, int n_omega, const double *omega, double *P,
+                        void *stream);
+
 /* ---- dynamic structure factor at k = 0 (DSF section, eq. 8) -------------- */
 
 /*
@@ -435,6 +449,15 @@ int tgba_autotune_report(char *buf, int64_t cap, int64_t *len);
  */
 int tgba_timing_enable(int on);
 int tgba_timing_read(double *ms, int64_t *launches, double *bytes);
+/*
+ * The same per channel: channel 0 is the symmetric product above (units =
+ * bytes), channel 1 every FP64 matrix-core product launch (tgba_dgemm and the
+ * eigensolver's own: the reductions' updates, the back-transform, divide and
+ * conquer), units = algorithmic flops: 2 M N K, counting only the stored
+ * triangle for lower-only updates and for products with one triangle of a
+ * symmetric operand.  Reading a channel consumes only that channel's records.
+ */
+int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units);
 
 /* Free the cached device workspace of the current device. */
 int tgba_release_workspace(void);

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
-__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps",
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps", "power_spectrum",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -257,16 +257,25 @@ def quench_overlaps(basis, K, h_perp_pre, s, c, stream=None):
     return c
 
 
+def power_spectrum(x, t0, dt, omega, P, stream=None):
+    """|int dt e^{-i omega t} x(t)|^2 of the sampled signal x (trapezoid rule; tgba_power_spectrum)."""
+    _lib.check(_lib.load().tgba_power_spectrum(int(x.shape[0]), float(t0), float(dt), _lib.ptr(x), int(omega.shape[0]),
+                                               _lib.ptr(omega), _lib.ptr(P), _lib.stream_handle(stream)))
+    return P
+
+
 def timing_enable(on=True):
-    """Start (or stop) event timing of the reduction's symmetric-product launches."""
+    """Start (or stop) event timing of the symmetric-product and FP64 matrix-core launches."""
     _lib.check(_lib.load().tgba_timing_enable(1 if on else 0))
 
 
-def timing_read():
-    """(kernel ms, launches, algorithmic bytes) since the previous read; waits for the events."""
-    ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-    _lib.check(_lib.load().tgba_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
-    return ms.value, n.value, by.value
+def timing_read(channel=0):
+    """(kernel ms, launches, algorithmic units) of one channel since its previous read:
+    channel 0 the symmetric product (bytes), channel 1 the FP64 products (flops)."""
+    ms, n, un = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _lib.check(_lib.load().tgba_timing_read_channel(int(channel), ctypes.byref(ms), ctypes.byref(n),
+                                                    ctypes.byref(un)))
+    return ms.value, n.value, un.value
 
 
 # ---- learned truncation ---------------------------------------------------------

@@ -72,7 +72,7 @@ bool autotune_known(const std::string &key);
 // from a recycled pool and record its algorithmic bytes.
 bool timing_on();
 int timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b);
-int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double bytes);
+int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double units, int ch = 0);
 
 }  // namespace tgba
 

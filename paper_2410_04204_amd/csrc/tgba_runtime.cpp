@@ -62,7 +62,8 @@ int release_all_workspace() {
 namespace {
 struct Timed {
     hipEvent_t a, b;
-    double bytes;
+    double units;  // bytes (channel 0) or flops (channel 1)
+    int ch;
 };
 std::mutex g_tmu;
 bool g_timing = false;
@@ -86,10 +87,10 @@ int timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b) {
     return TGBA_OK;
 }
 
-int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double bytes) {
+int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double units, int ch) {
     TGBA_HIP(hipEventRecord(b, st));
     std::lock_guard<std::mutex> lk(g_tmu);
-    g_pending.push_back(Timed{a, b, bytes});
+    g_pending.push_back(Timed{a, b, units, ch});
     return TGBA_OK;
 }
 
@@ -204,25 +205,37 @@ extern "C" int tgba_timing_enable(int on) {
     return TGBA_OK;
 }
 
-extern "C" int tgba_timing_read(double *ms, int64_t *launches, double *bytes) {
+extern "C" int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units) {
     tgba::clear_error();
-    if (!ms || !launches || !bytes) return tgba::set_error(TGBA_EINVAL, "NULL output");
+    if (!ms || !launches || !units) return tgba::set_error(TGBA_EINVAL, "NULL output");
+    if (channel < 0 || channel > 1) return tgba::set_error(TGBA_EINVAL, "unknown timing channel");
     std::lock_guard<std::mutex> lk(tgba::g_tmu);
-    double tot = 0.0, by = 0.0;
+    double tot = 0.0, un = 0.0;
+    int64_t cnt = 0;
+    std::vector<tgba::Timed> keep;
     for (auto &t : tgba::g_pending) {
+        if (t.ch != channel) {
+            keep.push_back(t);
+            continue;
+        }
         TGBA_HIP(hipEventSynchronize(t.b));
         float e = 0.0f;
         TGBA_HIP(hipEventElapsedTime(&e, t.a, t.b));
         tot += e;
-        by += t.bytes;
+        un += t.units;
+        ++cnt;
         tgba::g_pool.push_back(t.a);
         tgba::g_pool.push_back(t.b);
     }
     *ms = tot;
-    *launches = (int64_t)tgba::g_pending.size();
-    *bytes = by;
-    tgba::g_pending.clear();
+    *launches = cnt;
+    *units = un;
+    tgba::g_pending.swap(keep);
     return TGBA_OK;
+}
+
+extern "C" int tgba_timing_read(double *ms, int64_t *launches, double *bytes) {
+    return tgba_timing_read_channel(0, ms, launches, bytes);
 }
 
 extern "C" int tgba_release_workspace(void) {

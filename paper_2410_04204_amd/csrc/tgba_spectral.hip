@@ -238,6 +238,45 @@ extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w
     return TGBA_OK;
 }
 
+// ---- power spectrum of the quench signal (power-spectrum appendix) -------------
+// P_j = |sum_n w_n e^{-i omega_j t_n} x_n|^2, t_n = t0 + n dt, trapezoid weights
+// (dt, dt/2 at both ends).  One wave per frequency, lanes stride over the
+// samples; each phase is formed from t_n directly (no recurrence, so no drift
+// over long windows).
+__global__ void __launch_bounds__(256) power_spectrum_kernel(int64_t nt, double t0, double dt, const double *__restrict__ x,
+                                                             int n_omega, const double *__restrict__ omega,
+                                                             double *__restrict__ P) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n_omega) return;
+    const double om = omega[j];
+    double re = 0.0, im = 0.0;
+    for (int64_t k = lane; k < nt; k += 64) {
+        const double wk = (nt > 1 && (k == 0 || k == nt - 1)) ? 0.5 * dt : (nt > 1 ? dt : 0.0);
+        double sn, cs;
+        sincos(om * (t0 + dt * (double)k), &sn, &cs);
+        const double v = wk * x[k];
+        re += v * cs;
+        im -= v * sn;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) P[j] = re * re + im * im;
+}
+
+extern "C" int tgba_power_spectrum(int64_t nt, double t0, double dt, const double *x, int n_omega,
+                                   const double *omega, double *P, void *stream) {
+    clear_error();
+    if (nt < 1 || n_omega < 1 || !x || !omega || !P || !(dt > 0.0)) return set_error(TGBA_EINVAL, "bad arguments");
+    hipLaunchKernelGGL(power_spectrum_kernel, dim3((unsigned)((n_omega + 3) / 4)), dim3(256), 0, (hipStream_t)stream, nt,
+                       t0, dt, x, n_omega, omega, P);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
 extern "C" int tgba_dsf_cross(int64_t nk, const double *Zk, int64_t ldz, const double *wk, int64_t n0, const double *z0,
                               const double *w0, const double *X, int64_t ldx, int N_sites, const double *omega,
                               int n_omega, double eta, double *S, double *weights, void *stream) {

@@ -211,3 +211,50 @@ def test_dsf_k_matches_oracle(K):
     Xn = X.cpu().numpy().T
     z0 = Z0.cpu().numpy()[0]
     assert abs(wt.sum().item() - np.linalg.norm(Xn @ z0) ** 2) <= 1e-12 * max(1e-300, np.linalg.norm(Xn @ z0) ** 2)
+
+
+@pytest.mark.parametrize("nt,n_omega", [(9601, 4096), (2, 3), (1, 1), (257, 1000)])
+def test_power_spectrum_matches_oracle(nt, n_omega):
+    import paper_2410_04204_amd as tg
+    from oracle import spectral
+    torch = _t()
+    rng = np.random.default_rng(nt + n_omega)
+    x = rng.normal(size=nt) * np.exp(-0.001 * np.arange(nt))
+    omega = np.linspace(0.0, 8.0, n_omega)
+    P = torch.empty(n_omega, dtype=torch.float64, device="cuda")
+    tg.power_spectrum(torch.as_tensor(x, device="cuda"), 0.3, 0.05, torch.as_tensor(omega, device="cuda"), P)
+    want = spectral.power_spectrum(0.3, 0.05, x, omega)
+    got = P.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-10 * max(want.max(), 1e-300) + (0.0 if nt > 1 else 1e-300)
+
+
+def test_power_spectrum_of_a_quench_to_t480():
+    """f3 end to end at N = 10: the device quench (h_perp 0.5 -> 1, h_par 0.1,
+    paper's initial state) to t = 480 and its power spectrum, against the
+    oracle's quench and power spectrum of the same model."""
+    import paper_2410_04204_amd as tg
+    from oracle import spectral
+    torch = _t()
+    N, hpre, hpost, hp, s = 10, 0.5, 1.0, 0.1, 1
+    B = tg.Basis(N, hpost, hp, chi=1 << N)
+    Z, w, G = _sector_eig(tg, B, 0)
+    n = w.shape[0]
+    c = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    tg.quench_overlaps(B, 0, hpre, s, c)
+    nt, dt = 9601, 0.05
+    sx = torch.empty(nt, dtype=torch.float64, device="cuda")
+    nrm = torch.empty(nt, dtype=torch.float64, device="cuda")
+    tg.quench(Z, w, G, c, 0.0, dt, nt, sx, nrm)
+    omega = np.linspace(0.0, 8.0, 4096)
+    P = torch.empty(4096, dtype=torch.float64, device="cuda")
+    tg.power_spectrum(sx, 0.0, dt, torch.as_tensor(omega, device="cuda"), P)
+    times = dt * np.arange(nt)
+    _, sxo, _ = _oracle_quench(N, hpre, hpost, hp, None, s, times)
+    want = spectral.power_spectrum(0.0, dt, sxo, omega)
+    got = P.cpu().numpy()
+    # signal parity (1e-10) propagates through a sum of nt terms of weight dt
+    assert np.abs(sx.cpu().numpy() - sxo).max() <= TOL * max(1e-3, np.abs(sxo).max())
+    assert np.abs(got - want).max() <= 1e-8 * want.max()
+    # the peaks away from omega = 0 sit at the same frequencies
+    lo = omega > 0.2
+    assert omega[lo][np.argmax(got[lo])] == omega[lo][np.argmax(want[lo])]
