@@ -92,3 +92,28 @@ def eps_metric(keys_small, B_small, keys_large, B_large):
         rows.append(B_small[i])
     diff = np.array(rows)
     return float(np.sqrt(np.max(np.sum(np.abs(diff) ** 2, axis=0))))
+
+
+def initial_overlaps(N, h_pre, h_post, s, sec):
+    """<phi|Phi_0> for the states of one sector (oracle.basis layout: NS block, then R
+    block), Phi_0 = |0,pre>_NS (s = 0) or (|0,pre>_NS + s |0,pre>_R) / sqrt(2) (s = +-1,
+    Appendix B eqs. S5-S6)."""
+    ns = cef_overlaps(N, h_pre, h_post, model.NS, sec["ns_masks"])
+    r = cef_overlaps(N, h_pre, h_post, model.R, sec["r_masks"])
+    if s == 0:
+        return np.concatenate([ns, np.zeros(len(r), dtype=np.complex128)])
+    return np.concatenate([ns, s * r]) / np.sqrt(2.0)
+
+
+def select_by_overlap(N, h_pre, h_post, s, sec, chi, ov_min=0.0):
+    """Overlap-ranked truncation (Quench section): the candidates of one sector
+    ordered by |<phi|Phi_0>| (largest first), equal magnitudes by (E^(0), NS before
+    R, mask); the first chi are kept, and with ov_min > 0 only those with
+    |<phi|Phi_0>| >= ov_min.  Returns the kept candidate indices (ascending)."""
+    ov = np.abs(initial_overlaps(N, h_pre, h_post, s, sec))
+    E = np.concatenate([sec["ns_e"], sec["r_e"]])
+    par = np.concatenate([np.zeros(len(sec["ns_e"]), int), np.ones(len(sec["r_e"]), int)])
+    masks = np.concatenate([sec["ns_masks"], sec["r_masks"]])
+    order = sorted(range(len(ov)), key=lambda a: (-ov[a], E[a], par[a], int(masks[a])))
+    keep = [a for a in order[:chi] if ov[a] >= ov_min or ov_min <= 0.0]
+    return sorted(keep)

@@ -189,3 +189,32 @@ def test_power_spectrum_special_cases():
     t = dt * np.arange(nt)
     P = spectral.power_spectrum(0.0, dt, np.cos(W * t), np.array([W, W + 0.5]))
     assert abs(np.sqrt(P[0]) - T / 2) <= 0.01 * T and P[1] < 1e-3 * P[0]
+
+
+@pytest.mark.parametrize("N,hpre,s", [(8, 0.5, 1), (10, 0.5, -1), (10, 2.0, 0)])
+def test_overlap_coverage_of_the_full_basis_is_one(N, hpre, s):
+    """Phi_0 lies in the span of the post-quench pair states of K = 0, so the
+    full basis captures it exactly: sum |<phi|Phi_0>|^2 = <Phi_0|Phi_0> = 1,
+    and every truncation covers less (Quench section)."""
+    B = basis.build_basis(N, 1.0)
+    c = quench.initial_overlaps(N, hpre, 1.0, s, B[0])
+    assert abs(np.vdot(c, c).real - 1.0) <= 1e-13
+    for K in range(1, N):  # pair states carry zero momentum
+        assert np.abs(quench.initial_overlaps(N, hpre, 1.0, s, B[K])).max() == 0.0
+    keep = quench.select_by_overlap(N, hpre, 1.0, s, B[0], 12)
+    cov = np.vdot(c[keep], c[keep]).real
+    assert cov < 1.0 and cov >= np.sort(np.abs(c) ** 2)[::-1][:12].sum() - 1e-15
+
+
+def test_overlap_selection_order_and_ties():
+    sec = {"ns_masks": np.array([0b11, 0b1100, 0b1], dtype=np.uint64), "ns_e": np.array([2.0, 1.0, 0.5]),
+           "r_masks": np.array([0b110], dtype=np.uint64), "r_e": np.array([0.7])}
+    # fake overlaps through a monkeypatched initial_overlaps: two equal magnitudes and two zeros
+    orig = quench.initial_overlaps
+    quench.initial_overlaps = lambda *a, **k: np.array([0.5, -0.5j, 0.0, 0.0])
+    try:
+        assert quench.select_by_overlap(4, 0.5, 1.0, 1, sec, 1) == [1]         # tie 0.5: lower E first
+        assert quench.select_by_overlap(4, 0.5, 1.0, 1, sec, 3) == [0, 1, 2]   # zeros: NS E=0.5 before R E=0.7
+        assert quench.select_by_overlap(4, 0.5, 1.0, 1, sec, 4, ov_min=0.1) == [0, 1]
+    finally:
+        quench.initial_overlaps = orig
