@@ -23,11 +23,13 @@ and launch durations come from the library's own HIP-event timing of every
 launch in the timed steps; the other family is reported as `roofline_other`.
 Per-stage times, the assembly kernel's roofline and the oracle's CPU baseline
 are reported beside it, and,
-after the timed steps, the second half of the metric: the K = 0 basis
-dimension at which the N = 40 gap is within 1e-6 of the pool's, for the energy
-cutoff and for the learned selection (network trained on the device at
-N = 16..24), and the FP64-versus-mixed-precision eigensolve of the N = 40
-K = 0 sector at E_cut = 10.85.
+after the timed steps: the power spectrum of the K = 0 quench to t = 480; the
+overlap-ranked truncation's convergence (eps(chi', chi), eq. 10, over a chi
+sweep); the second half of the metric: the K = 0 basis dimension at which the
+N = 40 gap is within 1e-6 of the pool's, for the energy cutoff and for the
+learned selection (network trained on the device at N = 16..24); and the
+FP64-versus-mixed-precision eigensolve of the N = 40 K = 0 sector at
+E_cut = 10.85.
 """
 import argparse
 import json
@@ -57,6 +59,10 @@ def parse():
     p.add_argument("--chi-ref", type=int, default=45000, help="reference dimension of the n64_learned workload")
     p.add_argument("--no-gap-metric", action="store_true",
                    help="skip the learned-versus-cutoff basis dimension (second half of the metric)")
+    p.add_argument("--no-power-spectrum", action="store_true",
+                   help="skip the power spectrum of the K = 0 quench to t = 480 (after the timed steps)")
+    p.add_argument("--no-overlap-study", action="store_true",
+                   help="skip the overlap-ranked truncation convergence study (N=40 K=0, chi 2000..8000)")
     p.add_argument("--no-mixed", action="store_true",
                    help="skip the mixed-precision eigensolve measurement (N=40 K=0, E_cut 10.85)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -121,6 +127,83 @@ def gap_metric(tol=1e-6):
             "gap_err_cutoff": r["cutoff"]["gap_err"], "gap_err_learned": r["learned"]["gap_err"],
             "train_rows": int(F.shape[0]), "train_loss": [float(loss[0]), float(loss[-1])],
             "train_s": t_train, "sweep_s": r["seconds"]}
+
+
+def power_spectrum_run(tg, B, Z, w, G, h_pre=0.5, s=1, t_max=480.0, dt=0.05, n_omega=4096, omega_max=8.0):
+    """Power spectrum of <sigma^x>(t) after the quench (h_perp, h_par) = (h_pre, 0) -> the
+    workload's, initial state (|0>_NS + s |0>_R)/sqrt(2) at h_pre (Appendix B), K = 0
+    sector, t = 0 .. t_max: the device quench and tgba_power_spectrum; the strongest
+    peaks above omega = 0.5 (below it the omega = 0 peak of the untransformed mean has
+    side lobes every 2 pi / t_max) against the sector's lowest gaps m_a = E_{a+1} - E_1."""
+    import torch
+    n = w.shape[0]
+    nt = int(round(t_max / dt)) + 1
+    c = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    sx = torch.empty(nt, dtype=torch.float64, device="cuda")
+    nrm = torch.empty(nt, dtype=torch.float64, device="cuda")
+    omega = torch.as_tensor(np.linspace(0.0, omega_max, n_omega), device="cuda")
+    P = torch.empty(n_omega, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tg.quench_overlaps(B, 0, h_pre, s, c)
+    tg.quench(Z, w, G, c, 0.0, dt, nt, sx, nrm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tg.power_spectrum(sx, 0.0, dt, omega, P)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    Pn, om, wn = P.cpu().numpy(), omega.cpu().numpy(), w.cpu().numpy()
+    peaks = [j for j in range(1, n_omega - 1) if om[j] > 0.5 and Pn[j] >= Pn[j - 1] and Pn[j] >= Pn[j + 1]]
+    peaks.sort(key=lambda j: -Pn[j])
+    top = [float(om[j]) for j in peaks[:6]]
+    m = [float(wn[a] - wn[0]) for a in (1, 2, 3)]
+    return {"quench": f"(h_perp, h_par) = ({h_pre}, 0) -> workload, initial state s = {s}, K = 0 (n = {n})",
+            "t_max": t_max, "dt": dt, "samples": nt, "omega": [0.0, omega_max, n_omega],
+            "quench_s": t1 - t0, "power_spectrum_ms": (t2 - t1) * 1e3,
+            "top_peaks_omega": top, "m1_m2_m3": m, "m2_over_m1": m[1] / m[0],
+            "nearest_peak_to_m1": min(top, key=lambda x: abs(x - m[0])) if top else None,
+            "nearest_peak_to_m2": min(top, key=lambda x: abs(x - m[1])) if top else None}
+
+
+def overlap_study(chis=(2000, 4000, 8000), pool=10.85, h_pre=0.5, s=1, t_max=60.0, dt=0.05):
+    """Overlap-ranked truncation and its convergence (Quench section, eq. 10): N = 40 K = 0,
+    the chi states with the largest |<phi|Phi_0>| from the E_cut = pool candidates, the
+    quench (h_pre, 0) -> (1, 0.1) from (|0>_NS + s |0>_R)/sqrt(2), B(t) to t_max, and
+    eps(chi', chi) between successive dimensions; also the coverage sum |<phi|Phi_0>|^2
+    and <sigma^x>(t_max)."""
+    import torch
+    import paper_2410_04204_amd as tg
+    w = workloads.WORKLOADS["n40_batched"]
+    N = w["N"]
+    nt = int(round(t_max / dt)) + 1
+    prev, rows = None, []
+    t0 = time.perf_counter()
+    for chi in chis:
+        B = tg.Basis(N, w["h_perp"], w["h_par"], chi=[chi if K == 0 else 0 for K in range(N)], pool_e_cut=pool,
+                     overlap=(h_pre, s))
+        n = sum(B.sector_size(0))
+        H = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        G = torch.empty_like(H)
+        tg.assemble_heff(B, 0, H, tg.TGBA_HEFF | tg.TGBA_LOWER)
+        tg.assemble_heff(B, 0, G, tg.TGBA_GAMMA1)
+        ev = torch.empty(n, dtype=torch.float64, device="cuda")
+        tg.eig(H, ev, tg.TGBA_EIG_FP64)
+        c = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        tg.quench_overlaps(B, 0, h_pre, s, c)
+        sx = torch.empty(nt, dtype=torch.float64, device="cuda")
+        nrm = torch.empty(nt, dtype=torch.float64, device="cuda")
+        Bt = torch.empty(2 * n * nt, dtype=torch.float64, device="cuda")
+        tg.quench(H, ev, G, c, 0.0, dt, nt, sx, nrm, Bt)
+        row = {"chi": n, "coverage": float((c * c).sum().item()), "sx_tmax": float(sx[-1].item())}
+        if prev is not None:
+            eps, _ = tg.quench_eps(prev[0], 0, prev[1], B, 0, Bt, nt)
+            row["eps_vs_previous"] = float(eps.item())
+        del H, G
+        prev = (B, Bt)
+        rows.append(row)
+    torch.cuda.synchronize()
+    return {"workload": f"N=40 K=0, pool E_cut={pool}, quench ({h_pre}, 0) -> (1.0, {w['h_par']}), s={s}, "
+                        f"t_max={t_max}", "rows": rows, "seconds": time.perf_counter() - t0}
 
 
 def mixed_precision(n_refine=200):
@@ -325,8 +408,14 @@ def main():
         "physics": {"E0_K0": float(wn0[0]), "gap_K0": float(wn0[1] - wn0[0]), "m2_over_m1": float((wn0[2] - wn0[0]) / (wn0[1] - wn0[0])),
                     "sx_t0": float(sxn[0]), "sx_t50": float(sxn[-1]), "norm_drift": float(nrm.max() - nrm.min())},
     }
+    if not a.no_power_spectrum:
+        out["power_spectrum"] = power_spectrum_run(tg, B, Hs[0], ws[0], G0)
+    if not a.no_gap_metric or not a.no_overlap_study:
+        Hs.clear()  # free the N=40 sector matrices before the sweeps
+        torch.cuda.empty_cache()
+    if not a.no_overlap_study:
+        out["overlap_truncation"] = overlap_study()
     if not a.no_gap_metric:
-        Hs.clear()  # free the N=40 sector matrices before the sweep
         torch.cuda.empty_cache()
         out["basis_dim_for_1e-6_gap"] = gap_metric()
     if not a.no_mixed:

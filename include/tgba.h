@@ -75,6 +75,7 @@ typedef struct tgba_model {
 #define TGBA_TRUNC_ECUT 0 /* keep E^(0) - E0 <= e_cut (E0 = min vacuum energy)          */
 #define TGBA_TRUNC_CHI 1  /* keep chi[K] lowest per sector, order (E^(0), NS<R, mask)   */
 #define TGBA_TRUNC_LEARNED 2 /* keep chi[K] best-scored by the network (tgba_mlp_*)     */
+#define TGBA_TRUNC_OVERLAP 3 /* keep chi[K] with the largest |<phi|Phi_0>| (Quench section) */
 
 /*
  * Truncation of the Gaussian basis (Method section; Appendix B).
@@ -86,6 +87,11 @@ typedef struct tgba_model {
  *          chi_all
  *   mlp    LEARNED: device array of TGBA_MLP_PARAMS floats (the network of
  *          tgba_mlp_*); ignored otherwise
+ *   h_pre, s, ov_min   OVERLAP: the quench's initial state Phi_0 is the
+ *          pre-quench vacuum at transverse field h_pre, |0,h_pre>_NS (s = 0) or
+ *          (|0,h_pre>_NS + s |0,h_pre>_R) / sqrt(2) (s = +1 or -1; Appendix B
+ *          eqs. S5-S6); states with |<phi|Phi_0>| < ov_min are dropped
+ *          (ov_min <= 0: none); ignored otherwise
  * Cutoffs are inclusive with an absolute slack of 1e-9.  Energies are sums of
  * libm-evaluated mode energies in ascending mode order, so inclusion and order
  * decisions are reproducible bit for bit by any implementation doing the same.
@@ -93,6 +99,12 @@ typedef struct tgba_model {
  * initial state): the pool is the e_cut / m_max set; per sector the chi[K]
  * states with the largest BF16 score of tgba_mlp_score on their features
  * (tgba_mlp_features) are kept, equal scores in the order (E^(0), NS<R, mask).
+ * OVERLAP (Quench section: order the states by the magnitude of their overlap
+ * with the initial state, not by their energy): the pool is the e_cut / m_max
+ * set; per sector the candidates are ordered by |<phi|Phi_0>| from the closed
+ * form of eq. S5 (largest first; equal magnitudes, in particular the zero
+ * overlaps of all states that are not (k, -k) pair states and of all sectors
+ * K != 0, in the order (E^(0), NS<R, mask)) and the first chi[K] are kept.
  */
 typedef struct tgba_trunc {
     int mode;
@@ -101,6 +113,9 @@ typedef struct tgba_trunc {
     const int64_t *chi;
     int64_t chi_all;
     const float *mlp;
+    double h_pre;
+    int s;
+    double ov_min;
 } tgba_trunc;
 
 typedef struct tgba_basis tgba_basis;
@@ -351,6 +366,29 @@ int tgba_quench_weights(int64_t n, const double *Z, int64_t ldz, const double *c
  * s = 0, Phi_0 = |0,post>_NS (the H0 ground state at h_perp = 1).
  */
 int tgba_quench_overlaps(const tgba_basis *basis, int K, double h_perp_pre, int s, double *c, void *stream);
+
+/*
+ * Alignment of two truncations of one model for the convergence metric
+ * (Quench section, eq. 10): states are identified by (parity, mask).  Host
+ * outputs: small_of_large (n of the large sector) = index of the same state in
+ * the small sector or -1; missing_small (capacity n of the small sector) = the
+ * small sector's states absent from the large one, *n_missing of them.
+ */
+int tgba_basis_align(const tgba_basis *small, int Ks, const tgba_basis *large, int Kl, int64_t *small_of_large,
+                     int64_t *missing_small, int64_t *n_missing);
+
+/*
+ * Convergence metric eq. 10: dist[t] = || Psi^chi(t) - Psi^chi'(t) || =
+ * sqrt(sum over the large basis |B'_a(t) - B_a(t)|^2 (B_a = 0 for a state the
+ * small basis lacks) + sum over the small-only states |B_a(t)|^2) for every
+ * time column, and eps[0] = max_t dist[t].  B_small (n_small x nt) and B_large
+ * (n_large x nt) are the interleaved complex coefficients written by
+ * tgba_quench (B_out); small_of_large and missing_small come from
+ * tgba_basis_align (device copies).  Device arrays; stream-ordered.
+ */
+int tgba_quench_eps(int64_t n_small, const double *B_small, int64_t n_large, const double *B_large,
+                    const int64_t *small_of_large, int64_t n_missing, const int64_t *missing_small, int64_t nt,
+                    double *dist, double *eps, void *stream);
 
 /* ---- learned truncation (not in the paper; replaces the E^(0) order) ---- */
 

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
-__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps", "power_spectrum",
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -35,9 +35,12 @@ class Basis:
     space, small N only).  m_max caps the quasiparticle number.  With mlp (a
     device tensor of TGBA_MLP_PARAMS floats) the chi states of every sector
     with the best network score are kept instead of the lowest in energy.
+    With overlap=(h_pre, s[, ov_min]) the chi states with the largest overlap
+    with the quench's initial state are kept (TGBA_TRUNC_OVERLAP).
     """
 
-    def __init__(self, N, h_perp, h_par, e_cut=None, chi=None, m_max=None, pool_e_cut=None, mlp=None, stream=None):
+    def __init__(self, N, h_perp, h_par, e_cut=None, chi=None, m_max=None, pool_e_cut=None, mlp=None, overlap=None,
+                 stream=None):
         L = _lib.load()
         self.N, self.h_perp, self.h_par = int(N), float(h_perp), float(h_par)
         model = _lib.Model(self.N, self.h_perp, self.h_par)
@@ -49,12 +52,18 @@ class Basis:
         else:
             pool = -1.0 if pool_e_cut is None else float(pool_e_cut)
             mode = _lib.TGBA_TRUNC_CHI if mlp is None else _lib.TGBA_TRUNC_LEARNED
+            if overlap is not None:
+                mode = _lib.TGBA_TRUNC_OVERLAP
             if np.isscalar(chi):
                 tr = _lib.Trunc(mode, pool, int(m_max or 0), None, int(chi), _lib.ptr(mlp))
             else:
                 self._chi_buf = np.ascontiguousarray(np.asarray(chi, dtype=np.int64))
                 tr = _lib.Trunc(mode, pool, int(m_max or 0), self._chi_buf.ctypes.data_as(_lib.P_i64), 0,
                                 _lib.ptr(mlp))
+        if overlap is not None:
+            tr.h_pre = float(overlap[0])
+            tr.s = int(overlap[1])
+            tr.ov_min = float(overlap[2]) if len(overlap) > 2 else 0.0
         h = ctypes.c_void_p()
         _lib.check(L.tgba_build_basis(ctypes.byref(model), ctypes.byref(tr), _lib.stream_handle(stream),
                                       ctypes.byref(h)))
@@ -255,6 +264,28 @@ def quench_overlaps(basis, K, h_perp_pre, s, c, stream=None):
     _lib.check(_lib.load().tgba_quench_overlaps(basis.handle, int(K), float(h_perp_pre), int(s), _lib.ptr(c),
                                                 _lib.stream_handle(stream)))
     return c
+
+
+def quench_eps(small, Ks, B_small, large, Kl, B_large, nt, stream=None):
+    """eps(chi', chi) of eq. 10 and the distance per time (device tensors) for the
+    coefficients B (interleaved complex, n x nt) of two truncations (tgba_basis_align,
+    tgba_quench_eps)."""
+    import torch
+    n_s, n_l = sum(small.sector_size(Ks)), sum(large.sector_size(Kl))
+    idx = np.zeros(max(n_l, 1), dtype=np.int64)
+    miss = np.zeros(max(n_s, 1), dtype=np.int64)
+    nm = ctypes.c_int64()
+    _lib.check(_lib.load().tgba_basis_align(small.handle, int(Ks), large.handle, int(Kl), _lib.ptr(idx), _lib.ptr(miss),
+                                            ctypes.byref(nm)))
+    dev = B_large.device
+    d_idx = torch.as_tensor(idx, device=dev)
+    d_miss = torch.as_tensor(miss, device=dev)
+    dist = torch.empty(int(nt), dtype=torch.float64, device=dev)
+    eps = torch.empty(1, dtype=torch.float64, device=dev)
+    _lib.check(_lib.load().tgba_quench_eps(int(n_s), _lib.ptr(B_small), int(n_l), _lib.ptr(B_large), _lib.ptr(d_idx),
+                                           nm.value, _lib.ptr(d_miss), int(nt), _lib.ptr(dist), _lib.ptr(eps),
+                                           _lib.stream_handle(stream)))
+    return eps, dist
 
 
 def power_spectrum(x, t0, dt, omega, P, stream=None):

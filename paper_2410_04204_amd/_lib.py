@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtgba.so")
 TGBA_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
 
-TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED = 0, 1, 2
+TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED, TGBA_TRUNC_OVERLAP = 0, 1, 2, 3
 TGBA_HEFF, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_LOWER = 0x0, 0x1, 0x2, 0x4
 TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE = 0x0, 0x1, 0x2, 0x4
 
@@ -23,7 +23,7 @@ EXPORTS = [
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_sytrd", "tgba_sytrd_2stage", "tgba_stebz",
-    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_timing_read_channel", "tgba_power_spectrum", "tgba_mlp_features",
+    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_timing_read_channel", "tgba_power_spectrum", "tgba_basis_align", "tgba_quench_eps", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
     "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
     "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free", "tgba_quench_weights",
@@ -43,7 +43,8 @@ class Model(ctypes.Structure):
 
 class Trunc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("e_cut", ctypes.c_double), ("m_max", ctypes.c_int),
-                ("chi", ctypes.POINTER(ctypes.c_int64)), ("chi_all", ctypes.c_int64), ("mlp", ctypes.c_void_p)]
+                ("chi", ctypes.POINTER(ctypes.c_int64)), ("chi_all", ctypes.c_int64), ("mlp", ctypes.c_void_p),
+                ("h_pre", ctypes.c_double), ("s", ctypes.c_int), ("ov_min", ctypes.c_double)]
 
 
 _lib = None
@@ -111,6 +112,9 @@ def load():
     L.tgba_quench_weights.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
     L.tgba_mlp_select.argtypes = [c_int64, c_void_p, c_int64, c_void_p, P_i64, c_void_p]
     L.tgba_timing_read.argtypes = [ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
+    L.tgba_basis_align.argtypes = [c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p, P_i64]
+    L.tgba_quench_eps.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                  c_void_p, c_void_p]
     L.tgba_power_spectrum.argtypes = [c_int64, c_double, c_double, c_void_p, c_int, c_void_p, c_void_p, c_void_p]
     L.tgba_timing_read_channel.argtypes = [c_int, ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
     for name in EXPORTS:

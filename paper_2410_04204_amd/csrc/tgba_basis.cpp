@@ -121,13 +121,17 @@ static int validate(const tgba_model *m, const tgba_trunc *t) {
         return set_error(TGBA_EINVAL, "N must be even with 2 <= N <= 64");
     if (!(m->h_perp > 0.0) || !std::isfinite(m->h_perp) || !std::isfinite(m->h_par))
         return set_error(TGBA_EINVAL, "h_perp must be > 0 and fields finite");
-    if (t->mode != TGBA_TRUNC_ECUT && t->mode != TGBA_TRUNC_CHI && t->mode != TGBA_TRUNC_LEARNED)
+    if (t->mode != TGBA_TRUNC_ECUT && t->mode != TGBA_TRUNC_CHI && t->mode != TGBA_TRUNC_LEARNED &&
+        t->mode != TGBA_TRUNC_OVERLAP)
         return set_error(TGBA_EINVAL, "unknown truncation mode");
+    if (t->mode == TGBA_TRUNC_OVERLAP &&
+        (!(t->h_pre > 0.0) || !std::isfinite(t->h_pre) || t->s < -1 || t->s > 1 || !(t->e_cut >= 0.0)))
+        return set_error(TGBA_EINVAL, "OVERLAP mode needs h_pre > 0, s in {-1, 0, 1} and a pool cutoff e_cut >= 0");
     if (t->mode == TGBA_TRUNC_LEARNED && (!t->mlp || !(t->e_cut >= 0.0)))
         return set_error(TGBA_EINVAL, "LEARNED mode needs the network parameters and a pool cutoff e_cut >= 0");
     if (t->mode == TGBA_TRUNC_ECUT && !(t->e_cut >= 0.0))
         return set_error(TGBA_EINVAL, "e_cut must be >= 0 in ECUT mode");
-    if (t->mode == TGBA_TRUNC_CHI || t->mode == TGBA_TRUNC_LEARNED) {
+    if (t->mode == TGBA_TRUNC_CHI || t->mode == TGBA_TRUNC_LEARNED || t->mode == TGBA_TRUNC_OVERLAP) {
         if (t->chi) {
             for (int K = 0; K < m->N; ++K)
                 if (t->chi[K] < 0) return set_error(TGBA_EINVAL, "chi must be >= 0");
@@ -199,6 +203,47 @@ static int learned_keep(const Basis &b, std::vector<Cand> &c, int64_t keep, cons
     return TGBA_OK;
 }
 
+// |<phi|Phi_0>| of a candidate (eq. S5): only states made of (k, -k) pairs with
+// 0 < |k| < pi overlap the pre-quench vacuum of their parity; the magnitude is
+// prod_{occupied k > 0} |W(k)| / prod_{0 < k < pi} sqrt(1 + W(k)^2), W(k) =
+// tan((theta_k(post) - theta_k(pre)) / 2), times the weight of that parity's
+// vacuum in Phi_0 (1, or 1/sqrt(2) each for s = +-1; R states 0 for s = 0).
+struct OverlapTab {
+    double W[2][kMaxN], norm[2], wt[2];
+    int partner[2][kMaxN];  // mode of -k, -1 for k = 0 and k = pi
+    bool pos[2][kMaxN];     // 0 < k < pi
+};
+
+static void overlap_tab(const Basis &b, double h_pre, int s, OverlapTab &o) {
+    double kp[2][kMaxN], ep[2][kMaxN], thp[2][kMaxN];
+    mode_tables(b.N, h_pre, kp, ep, thp);
+    const int N = b.N;
+    for (int sec = 0; sec < 2; ++sec) {
+        o.norm[sec] = 1.0;
+        for (int a = 0; a < N; ++a) {
+            const double k = b.k[sec][a];
+            o.pos[sec][a] = (k > 1e-12 && k < M_PI - 1e-12);
+            o.W[sec][a] = std::tan(0.5 * (b.th[sec][a] - thp[sec][a]));
+            if (o.pos[sec][a]) o.norm[sec] *= std::sqrt(1.0 + o.W[sec][a] * o.W[sec][a]);
+            if (sec == kNS) o.partner[sec][a] = N - 1 - a;
+            else o.partner[sec][a] = (a == N / 2 - 1 || a == N - 1) ? -1 : N - 2 - a;
+        }
+    }
+    o.wt[kNS] = (s == 0) ? 1.0 : 1.0 / std::sqrt(2.0);
+    o.wt[kR] = (s == 0) ? 0.0 : 1.0 / std::sqrt(2.0);
+}
+
+static double overlap_abs(const OverlapTab &o, int N, int sec, uint64_t mask) {
+    double amp = 1.0;
+    for (int a = 0; a < N; ++a) {
+        if (!((mask >> a) & 1ULL)) continue;
+        const int p = o.partner[sec][a];
+        if (p < 0 || !((mask >> p) & 1ULL)) return 0.0;
+        if (o.pos[sec][a]) amp *= std::fabs(o.W[sec][a]);
+    }
+    return o.wt[sec] * amp / o.norm[sec];
+}
+
 extern "C" const char *tgba_version(void) { return "tgba-mi355x 0.1 (gfx950)"; }
 
 extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *stream, tgba_basis **out) {
@@ -247,6 +292,21 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
             if (t->mode == TGBA_TRUNC_CHI) {
                 int64_t keep = t->chi ? t->chi[K] : t->chi_all;
                 if ((int64_t)c.size() > keep) c.resize(keep);
+            } else if (t->mode == TGBA_TRUNC_OVERLAP) {
+                int64_t keep = t->chi ? t->chi[K] : t->chi_all;
+                OverlapTab ot;
+                overlap_tab(b, t->h_pre, t->s, ot);
+                std::vector<std::pair<double, int64_t>> ov(c.size());
+                for (size_t a = 0; a < c.size(); ++a) ov[a] = {overlap_abs(ot, N, c[a].s, c[a].mask), (int64_t)a};
+                // c is in (E, NS<R, mask) order: a stable sort by decreasing |overlap| keeps it for ties
+                std::stable_sort(ov.begin(), ov.end(), [](const std::pair<double, int64_t> &x,
+                                                          const std::pair<double, int64_t> &y) { return x.first > y.first; });
+                std::vector<Cand> kept;
+                for (size_t a = 0; a < ov.size() && (int64_t)kept.size() < keep; ++a) {
+                    if (t->ov_min > 0.0 && !(ov[a].first >= t->ov_min)) break;
+                    kept.push_back(c[ov[a].second]);
+                }
+                c.swap(kept);
             } else if (t->mode == TGBA_TRUNC_LEARNED) {
                 int64_t keep = t->chi ? t->chi[K] : t->chi_all;
                 if (keep == 0) {
@@ -343,6 +403,34 @@ extern "C" int tgba_basis_constants(const tgba_basis *hb, double *c0, double *ev
     if (evns) *evns = hb->b.evac[kNS];
     if (evr) *evr = hb->b.evac[kR];
     if (e0) *e0 = hb->b.e0;
+    return TGBA_OK;
+}
+
+extern "C" int tgba_basis_align(const tgba_basis *small, int Ks, const tgba_basis *large, int Kl,
+                                int64_t *small_of_large, int64_t *missing_small, int64_t *n_missing) {
+    clear_error();
+    if (!small || !large || !small_of_large || !missing_small || !n_missing || Ks < 0 || Ks >= small->b.N || Kl < 0 ||
+        Kl >= large->b.N || small->b.N != large->b.N)
+        return set_error(TGBA_EINVAL, "bad bases, sectors or outputs");
+    const Sector &S = small->b.sec[Ks], &L = large->b.sec[Kl];
+    std::vector<std::pair<std::pair<int, uint64_t>, int64_t>> key(S.n_ns + S.n_r);
+    for (int64_t i = 0; i < S.n_ns + S.n_r; ++i) key[i] = {{i < S.n_ns ? 0 : 1, S.masks[i]}, i};
+    std::sort(key.begin(), key.end());
+    std::vector<char> used(key.size(), 0);
+    for (int64_t j = 0; j < L.n_ns + L.n_r; ++j) {
+        const std::pair<int, uint64_t> kj{j < L.n_ns ? 0 : 1, L.masks[j]};
+        auto it = std::lower_bound(key.begin(), key.end(), std::make_pair(kj, (int64_t)-1));
+        if (it != key.end() && it->first == kj) {
+            small_of_large[j] = it->second;
+            used[it - key.begin()] = 1;
+        } else {
+            small_of_large[j] = -1;
+        }
+    }
+    int64_t m = 0;
+    for (size_t a = 0; a < key.size(); ++a)
+        if (!used[a]) missing_small[m++] = key[a].second;
+    *n_missing = m;
     return TGBA_OK;
 }
 

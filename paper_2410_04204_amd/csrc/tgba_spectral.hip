@@ -299,6 +299,70 @@ extern "C" int tgba_dsf_cross(int64_t nk, const double *Zk, int64_t ldz, const d
     return TGBA_OK;
 }
 
+// ---- convergence metric of two truncations (eq. 10) ------------------------------
+// dist[t] = || Psi^chi(t) - Psi^chi'(t) || from the coefficients B (interleaved
+// complex, n x nt, column t) of the two bases, aligned by small_of_large; the
+// states of the smaller basis missing from the larger one add their |B|^2.
+__global__ void __launch_bounds__(256) quench_dist_kernel(int64_t ns, const double *__restrict__ Bs, int64_t nl,
+                                                          const double *__restrict__ Bl, const int64_t *__restrict__ idx,
+                                                          int64_t nmiss, const int64_t *__restrict__ miss, int64_t nt,
+                                                          double *__restrict__ dist) {
+    const int64_t t = blockIdx.x;
+    if (t >= nt) return;
+    const double2 *bs = reinterpret_cast<const double2 *>(Bs) + t * ns;
+    const double2 *bl = reinterpret_cast<const double2 *>(Bl) + t * nl;
+    double acc = 0.0;
+    for (int64_t j = threadIdx.x; j < nl; j += blockDim.x) {
+        double2 d = bl[j];
+        const int64_t i = idx[j];
+        if (i >= 0) {
+            d.x -= bs[i].x;
+            d.y -= bs[i].y;
+        }
+        acc += d.x * d.x + d.y * d.y;
+    }
+    for (int64_t m = threadIdx.x; m < nmiss; m += blockDim.x) {
+        const double2 d = bs[miss[m]];
+        acc += d.x * d.x + d.y * d.y;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dist[t] = sqrt(red[0]);
+}
+
+__global__ void __launch_bounds__(256) max_kernel(const double *__restrict__ x, int64_t n, double *__restrict__ out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, x[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+extern "C" int tgba_quench_eps(int64_t n_small, const double *B_small, int64_t n_large, const double *B_large,
+                               const int64_t *small_of_large, int64_t n_missing, const int64_t *missing_small,
+                               int64_t nt, double *dist, double *eps, void *stream) {
+    clear_error();
+    if (n_small < 0 || n_large < 0 || n_missing < 0 || n_missing > n_small || nt < 1 || !dist || !eps ||
+        (n_small > 0 && !B_small) || (n_large > 0 && (!B_large || !small_of_large)) || (n_missing > 0 && !missing_small))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(quench_dist_kernel, dim3((unsigned)nt), dim3(256), 0, st, n_small, B_small, n_large, B_large,
+                       small_of_large, n_missing, missing_small, nt, dist);
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, dist, nt, eps);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
 extern "C" int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
                            const double *c, double t0, double dt, int nt, double *sx, double *nrm, double *B_out,
                            void *stream) {

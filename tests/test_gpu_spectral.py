@@ -258,3 +258,79 @@ def test_power_spectrum_of_a_quench_to_t480():
     # the peaks away from omega = 0 sit at the same frequencies
     lo = omega > 0.2
     assert omega[lo][np.argmax(got[lo])] == omega[lo][np.argmax(want[lo])]
+
+
+def _oracle_sub(sec, keep):
+    """The oracle sector dict restricted to the kept candidate indices (NS block, then R)."""
+    n_ns = len(sec["ns_masks"])
+    ki = np.asarray(keep, dtype=np.int64)
+    ns, r = ki[ki < n_ns], ki[ki >= n_ns] - n_ns
+    return {"ns_masks": sec["ns_masks"][ns], "ns_e": sec["ns_e"][ns],
+            "r_masks": sec["r_masks"][r], "r_e": sec["r_e"][r]}
+
+
+@pytest.mark.parametrize("N,pool,hpre,s,chi", [(10, 9.0, 0.5, 1, 30), (12, 8.0, 0.5, -1, 60), (12, 8.0, 2.0, 0, 25)])
+def test_overlap_basis_matches_oracle_selection(N, pool, hpre, s, chi):
+    import paper_2410_04204_amd as tg
+    from oracle import basis as ob, quench
+    B = tg.Basis(N, 1.0, 0.1, chi=[chi if K == 0 else 0 for K in range(N)], pool_e_cut=pool, overlap=(hpre, s))
+    sec = ob.build_basis(N, 1.0, e_cut=pool)[0]
+    ov = np.abs(quench.initial_overlaps(N, hpre, 1.0, s, sec))
+    keep = quench.select_by_overlap(N, hpre, 1.0, s, sec, chi)
+    masks, _ = B.sector(0)
+    n_ns, _ = B.sector_size(0)
+    got = {(0, int(m)) for m in masks[:n_ns]} | {(1, int(m)) for m in masks[n_ns:]}
+    cand = [(0, int(m)) for m in sec["ns_masks"]] + [(1, int(m)) for m in sec["r_masks"]]
+    want = {cand[a] for a in keep}
+    assert len(got) == len(want) == min(chi, len(cand))
+    thr = np.sort(ov)[::-1][min(chi, len(ov)) - 1]
+    for a, key in enumerate(cand):  # clear decisions must agree; near-ties only within rounding
+        if abs(ov[a] - thr) > 1e-12 * max(thr, 1e-300) and ov[a] > 0:
+            assert (key in got) == (key in want), key
+    if thr > 0:  # the cut falls inside the nonzero overlaps: the sets agree up to near-ties
+        assert len(got ^ want) <= 2
+    else:        # zero-overlap completion by (E, NS<R, mask), decided bit-exactly
+        assert got == want
+
+
+def test_quench_eps_matches_oracle():
+    """eps(chi', chi) of eq. 10 between two overlap-ranked K = 0 truncations at
+    N = 10: device quench coefficients + tgba_quench_eps against the oracle's
+    evolution and eps_metric (gauge invariant: the gauge of a state is the same
+    in both bases)."""
+    import paper_2410_04204_amd as tg
+    from oracle import basis as ob, heff, quench, spectral
+    torch = _t()
+    N, pool, hpre, s, hp = 10, 9.0, 0.5, 1, 0.1
+    nt, dt = 201, 0.05
+    times = dt * np.arange(nt)
+    sec = ob.build_basis(N, 1.0, e_cut=pool)[0]
+    Bdev, Borc, keys, bases = [], [], [], []
+    for chi in (12, 40):
+        Bb = tg.Basis(N, 1.0, hp, chi=[chi if K == 0 else 0 for K in range(N)], pool_e_cut=pool, overlap=(hpre, s))
+        Z, w, G = _sector_eig(tg, Bb, 0)
+        n = w.shape[0]
+        c = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        tg.quench_overlaps(Bb, 0, hpre, s, c)
+        sx = torch.empty(nt, dtype=torch.float64, device="cuda")
+        nrm = torch.empty(nt, dtype=torch.float64, device="cuda")
+        Bo = torch.empty(2 * n * nt, dtype=torch.float64, device="cuda")
+        tg.quench(Z, w, G, c, 0.0, dt, nt, sx, nrm, Bo)
+        Bdev.append(Bo)
+        bases.append(Bb)
+        sub = _oracle_sub(sec, quench.select_by_overlap(N, hpre, 1.0, s, sec, chi))
+        H = heff.heff(N, 1.0, hp, sub)
+        E, Zo = spectral.eigh(H)
+        co = quench.initial_overlaps(N, hpre, 1.0, s, sub)
+        Borc.append(quench.evolve(E, Zo, co, times))
+        keys.append([(0, int(m)) for m in sub["ns_masks"]] + [(1, int(m)) for m in sub["r_masks"]])
+    # the device basis lists the same states as the oracle's selection (clear ranking here)
+    for Bb, k in zip(bases, keys):
+        m, _ = Bb.sector(0)
+        n_ns, _ = Bb.sector_size(0)
+        assert {(0, int(x)) for x in m[:n_ns]} | {(1, int(x)) for x in m[n_ns:]} == set(k)
+    eps, dist = tg.quench_eps(bases[0], 0, Bdev[0], bases[1], 0, Bdev[1], nt)
+    want = quench.eps_metric(keys[0], Borc[0], keys[1], Borc[1])
+    got = float(eps.item())
+    assert abs(got - want) <= 1e-9 * max(want, 1e-12), (got, want)
+    assert abs(float(dist.max().item()) - got) == 0.0
