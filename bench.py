@@ -165,9 +165,10 @@ def power_spectrum_run(tg, B, Z, w, G, h_pre=0.5, s=1, t_max=480.0, dt=0.05, n_o
             "nearest_peak_to_m2": min(top, key=lambda x: abs(x - m[1])) if top else None}
 
 
-def overlap_study(chis=(2000, 4000, 8000), pool=10.85, h_pre=0.5, s=1, t_max=60.0, dt=0.05):
+def overlap_study(chis=(1000, 2000, 4000, 8000), pool=14.0, m_max=6, h_pre=0.5, s=1, t_max=60.0, dt=0.05):
     """Overlap-ranked truncation and its convergence (Quench section, eq. 10): N = 40 K = 0,
-    the chi states with the largest |<phi|Phi_0>| from the E_cut = pool candidates, the
+    the chi states with the largest |<phi|Phi_0>| among the candidates with at most m_max
+    quasiparticles and E - E0 <= pool (the paper first caps the quasiparticle number), the
     quench (h_pre, 0) -> (1, 0.1) from (|0>_NS + s |0>_R)/sqrt(2), B(t) to t_max, and
     eps(chi', chi) between successive dimensions; also the coverage sum |<phi|Phi_0>|^2
     and <sigma^x>(t_max)."""
@@ -180,7 +181,7 @@ def overlap_study(chis=(2000, 4000, 8000), pool=10.85, h_pre=0.5, s=1, t_max=60.
     t0 = time.perf_counter()
     for chi in chis:
         B = tg.Basis(N, w["h_perp"], w["h_par"], chi=[chi if K == 0 else 0 for K in range(N)], pool_e_cut=pool,
-                     overlap=(h_pre, s))
+                     m_max=m_max, overlap=(h_pre, s))
         n = sum(B.sector_size(0))
         H = torch.empty((n, n), dtype=torch.float64, device="cuda")
         G = torch.empty_like(H)
@@ -202,7 +203,7 @@ def overlap_study(chis=(2000, 4000, 8000), pool=10.85, h_pre=0.5, s=1, t_max=60.
         prev = (B, Bt)
         rows.append(row)
     torch.cuda.synchronize()
-    return {"workload": f"N=40 K=0, pool E_cut={pool}, quench ({h_pre}, 0) -> (1.0, {w['h_par']}), s={s}, "
+    return {"workload": f"N=40 K=0, pool M<={m_max} E_cut={pool}, quench ({h_pre}, 0) -> (1.0, {w['h_par']}), s={s}, "
                         f"t_max={t_max}", "rows": rows, "seconds": time.perf_counter() - t0}
 
 
