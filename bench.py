@@ -324,8 +324,9 @@ def main():
         mark(0)
         tg.assemble_heff_batched(B, Ks, Hs, tg.TGBA_HEFF | tg.TGBA_LOWER)
         mark(1)
-        tg.eig_batched(Hs[1:], ws[1:], tg.TGBA_EIG_NOVEC)   # spectra of the K != 0 sectors
-        tg.eig(Hs[0], ws[0], tg.TGBA_EIG_FP64)               # eigenpairs of K = 0
+        # spectra of the K != 0 sectors (two-stage) and the eigenpairs of K = 0 (one-stage,
+        # with vectors) in one call: the two groups run concurrently on two streams
+        tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))])
         mark(2)
         tg.assemble_heff(B, 0, G0, tg.TGBA_GAMMA1)
         tg.dsf(Hs[0], ws[0], G0, N, omega, w["eta"], S)

@@ -273,6 +273,18 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
                      void *stream);
 
 /*
+ * Several sectors, some with eigenvectors: want_vectors (host, nsec) marks the
+ * sectors whose A is to be overwritten by Z; the others get eigenvalues only
+ * (A overwritten).  The eigenvalue-only sectors take the two-stage path on
+ * `stream`; the vector sectors run at the same time on a second stream of the
+ * device (ordered after the work already queued on `stream`), from a second
+ * host thread, so that the latency-bound parts of each path overlap the other.
+ * Returns when both are done.  Errors: as tgba_eig_batched.
+ */
+int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,
+                         const int *want_vectors, void *stream);
+
+/*
  * Stages of tgba_eig, exported for callers that need them separately.
  * tgba_sytrd: A = Q T Q^T by Householder reflectors of the lower triangle;
  *   d (n) and e (n-1) receive T, tau (n-1) the reflector scalars; on return

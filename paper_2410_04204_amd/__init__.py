@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
-__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -191,6 +191,20 @@ def eig_batched(As, ws, flags=TGBA_EIG_FP64, stream=None):
     wp = (ctypes.c_void_p * k)(*[w.data_ptr() for w in ws])
     _lib.check(_lib.load().tgba_eig_batched(k, _lib.ptr(ns), ap, _lib.ptr(lds), wp, int(flags),
                                             _lib.stream_handle(stream)))
+    return ws
+
+
+def eig_batched_vec(As, ws, want_vectors, stream=None):
+    """Several sectors, eigenvectors for those flagged in want_vectors (A overwritten by Z),
+    eigenvalues only for the others; the two groups run concurrently (tgba_eig_batched_vec)."""
+    k = len(As)
+    ns = np.array([w.shape[0] for w in ws], dtype=np.int64)
+    lds = np.array([_ld(A) for A in As], dtype=np.int64)
+    wv = np.array([1 if v else 0 for v in want_vectors], dtype=np.int32)
+    ap = (ctypes.c_void_p * k)(*[A.data_ptr() for A in As])
+    wp = (ctypes.c_void_p * k)(*[w.data_ptr() for w in ws])
+    _lib.check(_lib.load().tgba_eig_batched_vec(k, _lib.ptr(ns), ap, _lib.ptr(lds), wp, _lib.ptr(wv),
+                                                _lib.stream_handle(stream)))
     return ws
 
 

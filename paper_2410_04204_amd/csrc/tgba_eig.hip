@@ -17,6 +17,8 @@
 #include <cfloat>
 #include <cmath>
 #include <numeric>
+#include <string>
+#include <thread>
 
 #include "tgba_blas.h"
 #include "tgba_dc.h"
@@ -997,11 +999,39 @@ static int eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_ref
     return TGBA_OK;
 }
 
-// Eigen-decomposition of several sectors.  Eigenvalues only for now unless the
-// divide-and-conquer stage is available (stedc_and_backtransform).
+// Eigen-decomposition of several sectors: eigenvalues only by the two-stage
+// reduction and bisection, with vectors by the one-stage reduction, divide and
+// conquer and the back-transform.  The two paths use disjoint workspace slots
+// (the eigenvalue path: 6, 30-35, 38), so they may run at the same time on two
+// streams from two host threads (tgba_eig_batched_vec).
 int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
                 hipStream_t stream) {
     const bool novec = (flags & TGBA_EIG_NOVEC) != 0;
+    if (novec && !(flags & (TGBA_EIG_ONESTAGE | TGBA_EIG_MIXED))) {
+        size_t tot = 0;
+        for (int k = 0; k < nsec; ++k) {
+            if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
+                return set_error(TGBA_EINVAL, "bad eigensolver arguments");
+            tot += 2 * (size_t)n[k] + 8;
+        }
+        void *ws = nullptr;
+        int rc = workspace_get(tot * sizeof(double), 38, &ws);
+        if (rc) return rc;
+        double *p = (double *)ws;
+        std::vector<BandIn> bin;
+        std::vector<BisIn> bis;
+        for (int k = 0; k < nsec; ++k) {
+            if (n[k] == 0) continue;
+            double *d = p, *e = p + n[k];
+            p += 2 * n[k] + 8;
+            bin.push_back(BandIn{A[k], lda[k], n[k], d, e});
+            bis.push_back(BisIn{d, e, w[k], n[k]});
+        }
+        if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
+        if ((rc = stebz_batched(bis, stream))) return rc;
+        TGBA_HIP(hipStreamSynchronize(stream));
+        return TGBA_OK;
+    }
     if (flags & TGBA_EIG_MIXED) {
         for (int k = 0; k < nsec; ++k) {
             if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
@@ -1035,15 +1065,6 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         S.A = A[k]; S.lda = lda[k]; S.n = n[k]; S.ldw = n[k];
         secs.push_back(S);
         bis.push_back(BisIn{S.d, S.e, w[k], n[k]});
-    }
-    if (novec && !(flags & TGBA_EIG_ONESTAGE)) {
-        std::vector<BandIn> bin;
-        for (auto &S : secs) bin.push_back(BandIn{S.A, S.lda, S.n, S.d, S.e});
-        if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
-        rc = stebz_batched(bis, stream);
-        if (rc) return rc;
-        TGBA_HIP(hipStreamSynchronize(stream));
-        return TGBA_OK;
     }
     rc = sytrd_batched(secs, stream);
     if (rc) return rc;
@@ -1090,6 +1111,55 @@ extern "C" int tgba_eig_mixed(int64_t n, double *A, int64_t lda, double *w, int6
     if (n < 0 || lda < std::max<int64_t>(1, n) || n_refine < 0 || (n > 0 && (!A || !w)))
         return set_error(TGBA_EINVAL, "bad arguments");
     return tgba::eig_mixed(n, A, lda, w, n_refine, false, (hipStream_t)stream);
+}
+
+extern "C" int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A, const int64_t *lda,
+                                    double *const *w, const int *want_vectors, void *stream) {
+    tgba::clear_error();
+    if (nsec < 0 || (nsec > 0 && (!n || !A || !lda || !w || !want_vectors)))
+        return tgba::set_error(TGBA_EINVAL, "bad arguments");
+    std::vector<int64_t> nv, nn, lv, ln;
+    std::vector<double *> av, an, wv, wn;
+    for (int k = 0; k < nsec; ++k) {
+        if (want_vectors[k]) {
+            nv.push_back(n[k]); av.push_back(A[k]); lv.push_back(lda[k]); wv.push_back(w[k]);
+        } else {
+            nn.push_back(n[k]); an.push_back(A[k]); ln.push_back(lda[k]); wn.push_back(w[k]);
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (nv.empty() || nn.empty()) {
+        if (!nv.empty()) return tgba::eig_batched((int)nv.size(), nv.data(), av.data(), lv.data(), wv.data(), 0, st);
+        return tgba::eig_batched((int)nn.size(), nn.data(), an.data(), ln.data(), wn.data(), TGBA_EIG_NOVEC, st);
+    }
+    // the vector sectors on a second stream of this device, ordered after the
+    // work already queued on `stream`, from a second host thread
+    hipStream_t s2 = nullptr;
+    int rc = tgba::side_stream(&s2);
+    if (rc) return rc;
+    hipEvent_t ev = nullptr;
+    TGBA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    TGBA_HIP(hipEventRecord(ev, st));
+    TGBA_HIP(hipStreamWaitEvent(s2, ev, 0));
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    int rc2 = TGBA_OK;
+    std::string err2;
+    std::thread th([&] {
+        if (hipSetDevice(dev) != hipSuccess) {
+            rc2 = TGBA_EDEVICE;
+            err2 = "hipSetDevice failed in the vector thread";
+            return;
+        }
+        rc2 = tgba::eig_batched((int)nv.size(), nv.data(), av.data(), lv.data(), wv.data(), 0, s2);
+        if (rc2) err2 = tgba_last_error();
+    });
+    rc = tgba::eig_batched((int)nn.size(), nn.data(), an.data(), ln.data(), wn.data(), TGBA_EIG_NOVEC, st);
+    th.join();
+    (void)hipEventDestroy(ev);
+    if (rc) return rc;
+    if (rc2) return tgba::set_error(rc2, err2);
+    return TGBA_OK;
 }
 
 extern "C" int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,

@@ -57,6 +57,8 @@ int build_contraction_table(Basis *b, hipStream_t stream);
 
 // Device workspace cache (grow-only, per device and slot).
 int workspace_get(size_t bytes, int slot, void **out);
+// A second stream of the current device (created once, default priority).
+int side_stream(hipStream_t *out);
 int release_all_workspace();
 
 // Autotuner: on first use of `key`, time run(c) for every candidate c (one

@@ -58,6 +58,21 @@ int release_all_workspace() {
     return TGBA_OK;
 }
 
+namespace {
+hipStream_t g_side[kDevices] = {};
+std::mutex g_smu;
+}  // namespace
+
+int side_stream(hipStream_t *out) {
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kDevices) return set_error(TGBA_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_smu);
+    if (!g_side[dev]) TGBA_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+    *out = g_side[dev];
+    return TGBA_OK;
+}
+
 // ---- opt-in event timing of the reduction's symmetric product ------------------
 namespace {
 struct Timed {

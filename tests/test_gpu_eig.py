@@ -134,6 +134,32 @@ def test_masked_split_k_symmetric_product():
     assert np.abs(w.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max() * np.sqrt(n)
 
 
+def test_eig_batched_vec_concurrent_groups():
+    """Sectors with and without eigenvectors in one call (two streams, two host
+    threads): eigenvalues against LAPACK, and A Z = Z diag(w), Z^T Z = 1 for the
+    vector sectors."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    sizes = [1500, 700, 2049, 65, 900, 3]
+    want = [True, False, False, True, False, True]
+    As = [_rand_sym(n, 300 + n) for n in sizes]
+    mats = [_cm(A) for A in As]
+    ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+    for rep in range(2):  # twice: the second call reuses the workspace and the side stream
+        mats = [_cm(A) for A in As]
+        tg.eig_batched_vec(mats, ws, want)
+        for A, M, w, v in zip(As, mats, ws, want):
+            ref = scipy.linalg.eigvalsh(A)
+            n = A.shape[0]
+            tol = 1e-12 * max(1.0, np.abs(ref).max()) * np.sqrt(n)
+            wn = w.cpu().numpy()
+            assert np.abs(np.sort(wn) - ref).max() <= tol
+            if v:
+                Z = _np(M)
+                assert np.abs(A @ Z - Z * wn[None, :]).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+                assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-10
+
+
 def test_eig_novec_and_batched_on_heff_sectors():
     import paper_2410_04204_amd as tg
     from oracle import basis as ob, heff, spectral
