@@ -65,6 +65,9 @@ def parse():
                    help="skip the overlap-ranked truncation convergence study (N=40 K=0, chi 2000..8000)")
     p.add_argument("--no-mixed", action="store_true",
                    help="skip the mixed-precision eigensolve measurement (N=40 K=0, E_cut 10.85)")
+    p.add_argument("--no-isolated", action="store_true",
+                   help="skip the extra step with the two eigensolve groups serialised (per-kernel rates "
+                        "without the other stream's kernels beside them)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (5 times), the reference for "
                         "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -317,16 +320,21 @@ def main():
     nrm = torch.empty(nt, dtype=torch.float64, device=dev)
     stages = ["assemble", "eig", "dsf", "quench"]
 
-    def step(ev=None):
+    def step(ev=None, serial=False):
         def mark(k):
             if ev is not None:
                 ev[k].record(stream)
         mark(0)
         tg.assemble_heff_batched(B, Ks, Hs, tg.TGBA_HEFF | tg.TGBA_LOWER)
         mark(1)
-        # spectra of the K != 0 sectors (two-stage) and the eigenpairs of K = 0 (one-stage,
-        # with vectors) in one call: the two groups run concurrently on two streams
-        tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))])
+        if serial:
+            # the same two groups one after the other on one stream (kernel-quality view)
+            tg.eig_batched(Hs[1:], ws[1:], tg.TGBA_EIG_NOVEC)
+            tg.eig_batched(Hs[:1], ws[:1], tg.TGBA_EIG_FP64)
+        else:
+            # spectra of the K != 0 sectors (two-stage) and the eigenpairs of K = 0 (one-stage,
+            # with vectors) in one call: the two groups run concurrently on two streams
+            tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))])
         mark(2)
         tg.assemble_heff(B, 0, G0, tg.TGBA_GAMMA1)
         tg.dsf(Hs[0], ws[0], G0, N, omega, w["eta"], S)
@@ -377,6 +385,30 @@ def main():
                  "launches": gemm_launches, "share_of_step": gemm_ms / a.steps / ms_per_step}
     dominant, other = (roof_gemm, roof_symv) if roof_gemm["share_of_step"] >= roof_symv["share_of_step"] \
         else (roof_symv, roof_gemm)
+    # One more (untimed for the metric) step with the two eigensolve groups serialised: inside the
+    # timed steps the two streams share the chip, so the per-launch durations above include the
+    # other group's kernels running beside them.  This pass shows each kernel on its own.
+    isolated = {}
+    if not a.no_isolated:
+        tg.timing_enable(True)
+        ev_iso = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        step(ev_iso, serial=True)
+        torch.cuda.synchronize()
+        tg.timing_enable(False)
+        print("isolated step done", file=sys.stderr, flush=True)
+        i_sm, i_sl, i_sb = tg.timing_read(0)
+        i_gm, i_gl, i_gf = tg.timing_read(1)
+        i_eig = ev_iso[1].elapsed_time(ev_iso[2])
+        isolated = {
+            "eig_ms": i_eig,
+            "dgemm_kernel": {"achieved": i_gf / (i_gm * 1e-3) / 1e12 if i_gm > 0 else 0.0, "unit": "TFLOP/s",
+                             "peak": FP64_MFMA_PEAK_TFS, "avg_launch_ms": i_gm / max(i_gl, 1),
+                             "launches": i_gl, "frac": (i_gf / (i_gm * 1e-3) / 1e12 if i_gm > 0 else 0.0)
+                             / FP64_MFMA_PEAK_TFS},
+            "tri_symv": {"achieved": i_sb / (i_sm * 1e-3) / 1e9 if i_sm > 0 else 0.0, "unit": "GB/s",
+                         "peak": HBM_PEAK_GBS, "avg_launch_ms": i_sm / max(i_sl, 1), "launches": i_sl,
+                         "frac": (i_sb / (i_sm * 1e-3) / 1e9 if i_sm > 0 else 0.0) / HBM_PEAK_GBS},
+        }
     stats = B.stats()
     sxn = sx.cpu().numpy()
     wn0 = ws[0].cpu().numpy()
@@ -404,6 +436,7 @@ def main():
                            "deflated_rows": stats[3]},
         "roofline": dominant,
         "roofline_other": other,
+        "roofline_isolated": isolated,
         "roofline_assembly": {"kernel": "assemble_rows_kernel<4,false>", "bound": "hbm", "achieved": achieved,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                               "algorithmic_bytes_per_launch": bytes_per_launch},
