@@ -16,6 +16,8 @@ Everything here is plain double precision, written for legibility:
 * ``heff``     the truncated effective Hamiltonian (eq. 2, eq. S4)
 * ``spectral`` LAPACK eigensolve and the dynamic structure factor (eq. 8)
 * ``quench``   overlaps (eqs. S5-S6), B(t) (eq. 9), <sigma^x>(t), eps (eq. 10)
+* ``corr``     sigma^x_1 sigma^x_{j+1} matrices and connected correlators after a
+               quench (appendix on correlation functions)
 * ``mlp``      plain forward/backward pass of the basis-scoring network
 
 Functions whose result has no independent pin say "parity unpinned" in their

@@ -183,6 +183,88 @@ int oracle_wick_elements(int N, const double *bra_k, const double *bra_th, int b
     return fail ? -1 : 0;
 }
 
+/*
+ * <phi_bra| X_1 X_2 ... X_m |phi_ket> for a middle string of m operators that
+ * are each linear in the site fermions, X_r = sum_j mu[r][j] c_j^dag + mv[r][j] c_j
+ * (mu, mv: m x N complex, row r = operator r in string order).  Same literal
+ * string as element(): bra vacuum product, bra excitations, the middle string,
+ * ket excitations, ket vacuum product, all relative to |0>_c (eqs. S1-S2).
+ */
+static cplx element_string(int N, const side_t *bra, uint64_t bmask, const side_t *ket, uint64_t kmask,
+                           int nmid, const cplx *mu, const cplx *mv, cplx *U, cplx *V, cplx *A)
+{
+    int n = 0;
+    for (int a = N - 1; a >= 0; --a) {
+        if (bra->is_r && is_pi(bra->k[a])) continue;
+        op_ddag(N, bra->k[a], bra->th[a], U + (size_t)n * N, V + (size_t)n * N); ++n;
+    }
+    for (int a = N - 1; a >= 0; --a)
+        if ((bmask >> a) & 1ULL) { op_d(N, bra->k[a], bra->th[a], U + (size_t)n * N, V + (size_t)n * N); ++n; }
+    for (int r = 0; r < nmid; ++r) {
+        for (int j = 0; j < N; ++j) { U[(size_t)n * N + j] = mu[(size_t)r * N + j]; V[(size_t)n * N + j] = mv[(size_t)r * N + j]; }
+        ++n;
+    }
+    for (int a = 0; a < N; ++a)
+        if ((kmask >> a) & 1ULL) { op_ddag(N, ket->k[a], ket->th[a], U + (size_t)n * N, V + (size_t)n * N); ++n; }
+    for (int a = 0; a < N; ++a) {
+        if (ket->is_r && is_pi(ket->k[a])) continue;
+        op_d(N, ket->k[a], ket->th[a], U + (size_t)n * N, V + (size_t)n * N); ++n;
+    }
+    if (n & 1) return 0.0;
+    for (int m = 0; m < n; ++m) {
+        A[(size_t)m * n + m] = 0.0;
+        for (int q = m + 1; q < n; ++q) {
+            cplx acc = 0.0;
+            const cplx *vm = V + (size_t)m * N, *uq = U + (size_t)q * N;
+            for (int j = 0; j < N; ++j) acc += vm[j] * uq[j];
+            A[(size_t)m * n + q] = acc;
+            A[(size_t)q * n + m] = -acc;
+        }
+    }
+    return pfaffian(A, n) / (vac_norm(N, bra) * vac_norm(N, ket));
+}
+
+/*
+ * Batched entry of element_string: mid_uv holds mu then mv, each nmid x N
+ * complex interleaved (re, im).  out[2*i], out[2*i+1] = Re, Im of element i.
+ */
+int oracle_wick_string_elements(int N, const double *bra_k, const double *bra_th, int bra_is_r,
+                                const double *ket_k, const double *ket_th, int ket_is_r, int nmid,
+                                const double *mid_uv, long npairs, const uint64_t *bra_masks,
+                                const uint64_t *ket_masks, double *out)
+{
+    side_t bra = {bra_k, bra_th, bra_is_r}, ket = {ket_k, ket_th, ket_is_r};
+    cplx *mu = malloc(sizeof(cplx) * (size_t)(nmid > 0 ? nmid : 1) * N);
+    cplx *mv = malloc(sizeof(cplx) * (size_t)(nmid > 0 ? nmid : 1) * N);
+    if (!mu || !mv) { free(mu); free(mv); return -1; }
+    for (long i = 0; i < (long)nmid * N; ++i) {
+        mu[i] = mid_uv[2 * i] + I * mid_uv[2 * i + 1];
+        mv[i] = mid_uv[2 * ((long)nmid * N + i)] + I * mid_uv[2 * ((long)nmid * N + i) + 1];
+    }
+    int fail = 0;
+#pragma omp parallel
+    {
+        int nmax = 4 * N + nmid + 2;
+        cplx *U = malloc(sizeof(cplx) * (size_t)nmax * N);
+        cplx *V = malloc(sizeof(cplx) * (size_t)nmax * N);
+        cplx *A = malloc(sizeof(cplx) * (size_t)nmax * nmax);
+        if (!U || !V || !A) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (long i = 0; i < npairs; ++i) {
+                cplx v = element_string(N, &bra, bra_masks[i], &ket, ket_masks[i], nmid, mu, mv, U, V, A);
+                out[2 * i] = creal(v);
+                out[2 * i + 1] = cimag(v);
+            }
+        }
+        free(U); free(V); free(A);
+    }
+    free(mu); free(mv);
+    return fail ? -1 : 0;
+}
+
 /* Pfaffian of one dense complex skew matrix (row-major, copied). */
 int oracle_pfaffian(int n, const double *a_re_im, double *out)
 {
