@@ -209,6 +209,26 @@ int tgba_assemble_heff_batched(const tgba_basis *basis, int nsec, const int *Ks,
 int tgba_assemble_cross(const tgba_basis *basis, int K_rows, int K_cols, double *X, int64_t ld, void *stream);
 
 /*
+ * Equal-time correlator strings (appendix on correlation functions, Fig. S1;
+ * the Jordan-Wigner form of sigma^x_j in the notes):
+ *   O_j = sigma^x_1 sigma^x_{j+1} = B_1 A_2 B_2 ... B_j A_{j+1},
+ * A_l = c_l^dag + c_l, B_l = c_l^dag - c_l, for every j = js[i], 1 <= j <= N-1.
+ * O[i] (device, n x n, column-major, ld[i] >= n, n = n_ns + n_r of sector K)
+ * receives O_js[i] on the sector basis in the real gauge of its H_eff: the
+ * NS x NS and R x R blocks (Wick-Pfaffians of the 2j-operator string between
+ * the basis states, Appendix A), zeros in the NS x R blocks (O_j conserves the
+ * fermion parity).  The matrix is real and symmetric.  Inside a momentum
+ * sector the elements of sigma^x_i sigma^x_{i+j} do not depend on i, so O_j is
+ * the translation-averaged correlator.  js, O and ld are host arrays of nj
+ * entries; the library owns nothing of the outputs.
+ * Errors: TGBA_EINVAL (sector, j or output), TGBA_EUNSUPPORTED (states with
+ * more than 22 quasiparticles), TGBA_ENUMERIC (the real form of a table
+ * failed), TGBA_EDEVICE.
+ */
+int tgba_assemble_corr(const tgba_basis *basis, int K, int nj, const int *js, double *const *O, const int64_t *ld,
+                       void *stream);
+
+/*
  * Assembly plan: the launches of one batched assembly (the same arguments as
  * tgba_assemble_heff_batched) captured once into a hipGraph whose nodes are
  * kernels only; the sector descriptors live in device memory the plan owns.
@@ -371,11 +391,27 @@ int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double *w, const 
 int tgba_quench_weights(int64_t n, const double *Z, int64_t ldz, const double *c, double *w, void *stream);
 
 /*
+ * Correlators after a quench (appendix on correlation functions, Fig. S1):
+ * with B(t_n) = Z diag(exp(-i w t_n)) Z^T c~ as in tgba_quench (same Z, w, c~,
+ * t0, dt, nt), for every matrix O[i] (device, n x n, ld ldo[i]; e.g. from
+ * tgba_assemble_corr):
+ *   out[i * nt + n] = B^H O_i B / (c~^H c~) - (sx ? sx[n]^2 : 0)
+ * (device, nj x nt).  With sx the <sigma^x>(t) of tgba_quench this is the
+ * connected correlator <sigma^x_1 sigma^x_{j+1}> - <sigma^x_1><sigma^x_{j+1}> of a
+ * K = 0 state.  O, ldo are host arrays of nj entries; sx may be NULL.
+ * Errors: TGBA_EINVAL (sizes, pointers, or c~ = 0), TGBA_ENOMEM, TGBA_EDEVICE.
+ */
+int tgba_quench_corr(int64_t n, const double *Z, int64_t ldz, const double *w, const double *c, double t0, double dt,
+                     int nt, int nj, const double *const *O, const int64_t *ldo, const double *sx, double *out,
+                     void *stream);
+
+/*
  * Overlaps <phi_a(post)|Phi_0> of a sector's basis with the initial state
  * Phi_0 = (|0,pre>_NS + s |0,pre>_R)/sqrt(2) (s = +1 or -1), the vacua of H0 at
- * the pre-quench transverse field h_perp_pre (closed form of eq. S5), written
- * in the real gauge to c (device, interleaved complex, n_ns + n_r).  With
- * s = 0, Phi_0 = |0,post>_NS (the H0 ground state at h_perp = 1).
+ * the pre-quench transverse field h_perp_pre >= 0 (closed form of eq. S5),
+ * written in the real gauge to c (device, interleaved complex, n_ns + n_r).
+ * With s = 0, Phi_0 = |0,pre>_NS alone (the paramagnetic ground state; for
+ * h_perp_pre = h_perp the post-quench NS vacuum itself).
  */
 int tgba_quench_overlaps(const tgba_basis *basis, int K, double h_perp_pre, int s, double *c, void *stream);
 

@@ -14,7 +14,8 @@ from . import _lib
 from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
-__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
+__all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "assemble_corr",
+           "quench_corr", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -272,6 +273,30 @@ def quench(Z, w, G, c, t0, dt, nt, sx, nrm, B=None, stream=None):
                                        float(t0), float(dt), int(nt), _lib.ptr(sx), _lib.ptr(nrm), _lib.ptr(B),
                                        _lib.stream_handle(stream)))
     return sx
+
+
+def assemble_corr(basis, K, js, Os, stream=None):
+    """O_j = <phi|sigma^x_1 sigma^x_{j+1}|phi> on sector K (real gauge, symmetric; NS x NS and
+    R x R blocks, zero NS x R blocks) for every j in js, into the (n, ld) device tensors Os."""
+    js = np.ascontiguousarray(np.asarray(js, dtype=np.int32))
+    k = js.size
+    lds = np.array([_ld(O) for O in Os], dtype=np.int64)
+    op = (ctypes.c_void_p * k)(*[O.data_ptr() for O in Os])
+    _lib.check(_lib.load().tgba_assemble_corr(basis.handle, int(K), int(k), _lib.ptr(js), op, _lib.ptr(lds),
+                                              _lib.stream_handle(stream)))
+    return Os
+
+
+def quench_corr(Z, w, c, t0, dt, nt, Os, out, sx=None, stream=None):
+    """out[i, n] = <O_i>(t_n) = B^H O_i B / |c|^2 with B(t) as in quench (minus sx(t)^2, the
+    connected correlator, when the magnetisation series sx is given)."""
+    n, k = w.shape[0], len(Os)
+    lds = np.array([_ld(O) for O in Os], dtype=np.int64)
+    op = (ctypes.c_void_p * k)(*[O.data_ptr() for O in Os])
+    _lib.check(_lib.load().tgba_quench_corr(int(n), _lib.ptr(Z), _ld(Z), _lib.ptr(w), _lib.ptr(c), float(t0),
+                                            float(dt), int(nt), int(k), op, _lib.ptr(lds), _lib.ptr(sx),
+                                            _lib.ptr(out), _lib.stream_handle(stream)))
+    return out
 
 
 def quench_overlaps(basis, K, h_perp_pre, s, c, stream=None):

@@ -27,7 +27,7 @@ EXPORTS = [
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
     "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
     "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free", "tgba_quench_weights",
-    "tgba_assemble_cross", "tgba_dsf_cross",
+    "tgba_assemble_cross", "tgba_dsf_cross", "tgba_assemble_corr", "tgba_quench_corr",
 ]
 
 
@@ -93,6 +93,9 @@ def load():
     L.tgba_timing_enable.argtypes = [c_int]
     L.tgba_autotune_enable.argtypes = [c_int]
     L.tgba_assemble_cross.argtypes = [c_void_p, c_int, c_int, c_void_p, c_int64, c_void_p]
+    L.tgba_assemble_corr.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_quench_corr.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_double, c_double, c_int, c_int,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.tgba_dsf_cross.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64,
                                  c_int, c_void_p, c_int, c_double, c_void_p, c_void_p, c_void_p]
     L.tgba_assembly_plan_create.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int,

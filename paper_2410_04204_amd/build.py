@@ -28,6 +28,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}", "-mcode-object
           "-Wno-unused-result", "-munsafe-fp-atomics"]
 SOURCES = {
     "tgba_basis.cpp": ["-ffp-contract=off"],
+    "tgba_corr.cpp": [],
     "tgba_runtime.cpp": [],
     "tgba_table.hip": [],
     "tgba_assemble.hip": [],

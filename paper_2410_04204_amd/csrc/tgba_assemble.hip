@@ -60,6 +60,11 @@ struct SectorDesc {
     int mode;               // 0: a sector's own matrix; 1, 2: a block of a cross-sector matrix
     const uint64_t *ket;    // the ket (R) masks: masks + n_ns for mode 0
     int64_t row_off;        // output row of ket 0: n_ns for mode 0
+    // correlator strings only (kernel instances with a common index prefix):
+    const double *tab;      // this block's table, order 2N + 2, row-major
+    double fac, rmax;       // its prefactor and max |entry|
+    const double *rsign;    // per-state signs of the bra rows and of the ket columns
+    const double *csign;
 };
 
 namespace {
@@ -171,13 +176,14 @@ __device__ __noinline__ double pf_eliminate(double *A, int M) {
 
 // Rare paths (private memory): a ket with more than 10 quasiparticles on the
 // row's Schur table, or a flagged row evaluated directly as Pf(R[I_a u I_b]).
-template <int ROWS>
+template <int ROWS, int NJ>
 __device__ __noinline__ double element_generic(const double *tabs, const int *s_rowoff, int r, int N, uint64_t ket,
                                                int flagged, uint64_t bra, const double *__restrict__ R,
                                                unsigned long long *counters) {
     int g[kGenMax];
     int M = 0;
     if (flagged) {
+        for (int q = 0; q < NJ; ++q) g[M++] = 2 * N + q;  // common prefix (correlator strings)
         for (int a = N - 1; a >= 0; --a)
             if ((bra >> a) & 1ULL) {
                 if (M == kGenMax) { atomicAdd(&counters[2], 1ULL); return 0.0; }
@@ -192,7 +198,7 @@ __device__ __noinline__ double element_generic(const double *tabs, const int *s_
         }
     (void)mb0;
     double A[kGenMax * kGenMax];
-    const int n2 = 2 * N;
+    const int n2 = 2 * N + NJ;
     for (int i = 0; i < M; ++i) {
         A[i * kGenMax + i] = 0.0;
         for (int j = i + 1; j < M; ++j) {
@@ -312,7 +318,7 @@ __device__ __forceinline__ double pf_ket(const double *tabs, const int *s_rowoff
 
 // Pf(S_r[I_b]) * factor_r for all valid rows that are neither flagged nor
 // deflated, for a ket of MB quasiparticles (MB < 0: more than 10, generic).
-template <int MB, int ROWS>
+template <int MB, int ROWS, int NJ>
 __device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, const int *s_rowoff, int N,
                                            uint64_t ket, int nvalid, const int *s_flag, const int *s_defl,
                                            const uint64_t *s_bra, const double *s_fac, const double *__restrict__ R,
@@ -325,7 +331,7 @@ __device__ __forceinline__ void row_values(double (&val)[ROWS], const double *ta
         double pfv = 0.0;
         if (r < nvalid && !s_defl[r]) {
             if (MB < 0 || s_flag[r]) {
-                pfv = element_generic<ROWS>(tabs, s_rowoff, r, N, ket, s_flag[r], s_bra[r], R, counters);
+                pfv = element_generic<ROWS, NJ>(tabs, s_rowoff, r, N, ket, s_flag[r], s_bra[r], R, counters);
             } else {
                 pfv = pf_ket<MK, ROWS, false>(tabs, s_rowoff, r, K, nullptr, nullptr, 0.0);
             }
@@ -418,16 +424,24 @@ __device__ __forceinline__ double deflated_value(const double *tabs, const int *
 
 // 3 waves per SIMD (<= 168 VGPRs): the LDS of a workgroup at N = 40 allows 3
 // workgroups of 4 waves per CU anyway.
-template <int ROWS, bool CPLX>
+// NJ = 0: H_eff and gamma_1 blocks (one model table R, factor c0).  NJ = 2:
+// correlator strings (tgba_corr.cpp): every element carries the two table
+// indices 2N, 2N+1 in front of its bra indices, and each descriptor brings its
+// own table (order 2N + 2), factor, max|entry| and per-state signs.
+template <int ROWS, bool CPLX, int NJ>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
-assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, const double *__restrict__ R,
-                     double r_max, double c0, double scale, int with_diag, int lower,
+assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, const double *__restrict__ R_model,
+                     double r_max_model, double c0_model, double scale, int with_diag, int lower,
                      unsigned long long *__restrict__ counters) {
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;  // 64 x 4 thread grid for 2D loops
     const int s = sector_of(descs, nsec, blockIdx.x);
     const SectorDesc D = descs[s];
+    const double *__restrict__ R = NJ ? D.tab : R_model;
+    const double r_max = NJ ? D.rmax : r_max_model;
+    const double c0 = NJ ? D.fac : c0_model;
+    const int ts = 2 * N + NJ;  // table row stride
     const int64_t a0 = (int64_t)(blockIdx.x - D.first_block) * ROWS;
     const int ntab = N * (N - 1) / 2;
     const int wdim = D.max_m_bra + N;
@@ -454,13 +468,14 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             continue;
         }
         const uint64_t bra = D.masks[a];
-        const int Ma = __popcll(bra);
+        const int Ma = __popcll(bra) + NJ;  // eliminated block: the common prefix, then the bra indices
         if (tid == 0) {
             int m = 0;
+            for (int q = 0; q < NJ; ++q) s_bidx[m++] = 2 * N + q;
             for (int q = N - 1; q >= 0; --q)
                 if ((bra >> q) & 1ULL) s_bidx[m++] = N - 1 - q;  // ascending table index
             s_bra[r] = bra;
-            s_mbra[r] = Ma;
+            s_mbra[r] = Ma - NJ;
             s_growth = 0.0;
         }
         __syncthreads();
@@ -469,7 +484,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const int gi = (i < Ma) ? s_bidx[i] : N + (i - Ma);
             for (int j = tx; j < n; j += 64) {
                 const int gj = (j < Ma) ? s_bidx[j] : N + (j - Ma);
-                W[i * wdim + j] = R[gi * (2 * N) + gj];
+                W[i * wdim + j] = R[gi * ts + gj];
             }
         }
         __syncthreads();
@@ -581,7 +596,8 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const bool bad = !keep_d || !(pf != 0.0) || !(s_growth <= kGrowthLimit * r_max) || !isfinite(pf);
             s_flag[r] = bad ? 1 : 0;
             s_defl[r] = bad ? 0 : d;
-            s_fac[r] = bad ? c0 * scale : c0 * scale * pf;
+            const double rs = (NJ && D.rsign) ? D.rsign[a] : 1.0;
+            s_fac[r] = bad ? c0 * scale * rs : c0 * scale * pf * rs;
             if (bad) atomicAdd(&counters[0], 1ULL);
             if (!bad && d > 0) {
                 s_anydefl = 1;
@@ -639,13 +655,18 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         const int Mb = __popcll(ket);
         double val[ROWS];
         switch (Mb) {
-            case 0: row_values<0, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 2: row_values<2, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 4: row_values<4, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 6: row_values<6, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 8: row_values<8, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 10: row_values<10, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            default: row_values<-1, ROWS>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 0: row_values<0, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 2: row_values<2, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 4: row_values<4, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 6: row_values<6, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 8: row_values<8, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 10: row_values<10, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            default: row_values<-1, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+        }
+        if constexpr (NJ > 0) {
+            const double cs = D.csign ? D.csign[b] : 1.0;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) val[r] *= cs;
         }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -665,7 +686,8 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             for (int r = 0; r < nvalid; ++r) {
                 const int d = s_defl[r];
                 if (!d) continue;
-                const double v = s_fac[r] * deflated_value<ROWS>(tabs, s_rowoff, dk, s_dd[r], r, N, ket, Mb, d, r_max, counters);
+                double v = s_fac[r] * deflated_value<ROWS>(tabs, s_rowoff, dk, s_dd[r], r, N, ket, Mb, d, r_max, counters);
+                if constexpr (NJ > 0) v *= D.csign ? D.csign[b] : 1.0;
                 if constexpr (CPLX) {
                     double re, im;
                     phase_mi((s_mbra[r] + Mb) / 2, v, re, im);
@@ -711,11 +733,11 @@ __global__ void __launch_bounds__(kThreads) mirror_upper_kernel(const SectorDesc
     }
 }
 
-template <int ROWS, bool CPLX>
+template <int ROWS, bool CPLX, int NJ = 0>
 int launch_rows(const SectorDesc *d_desc, int nsec, int64_t nblocks, size_t lds, const Basis *b, double r_max,
                 double scale, int with_diag, int lower, unsigned long long *counters, hipStream_t stream,
                 bool set_attr = true) {
-    auto kern = assemble_rows_kernel<ROWS, CPLX>;
+    auto kern = assemble_rows_kernel<ROWS, CPLX, NJ>;
     if (set_attr && lds > 65536)
         TGBA_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kThreads), lds, stream, d_desc, nsec, b->N, b->d_table, r_max,
@@ -957,7 +979,101 @@ int assemble_cross(const Basis *b, int Kr, int Kc, double *X, int64_t ld, hipStr
     return asm_launch_rows(b, o, rows, (const SectorDesc *)ws, 2, nblocks, lds, stream, true);
 }
 
+// O_j[b][a] = <phi_a| sigma^x_1 sigma^x_{j+1} |phi_b> (real gauge) of sector K for
+// every j of the list, in one launch: the NS x NS and R x R blocks of each j
+// are two descriptors of the rows kernel with the common J prefix (NJ = 2),
+// each with its own table; the NS x R blocks are zero.  O_j is symmetric.
+int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O, const int64_t *ld,
+                  hipStream_t stream) {
+    const int N = b->N;
+    if (K < 0 || K >= N) return set_error(TGBA_EINVAL, "sector index out of range");
+    if (nj < 0 || (nj > 0 && (!js || !O || !ld))) return set_error(TGBA_EINVAL, "bad arguments");
+    const Sector &sc = b->sec[K];
+    const int64_t nn = sc.n_ns, nr = sc.n_r, n = nn + nr;
+    for (int i = 0; i < nj; ++i) {
+        if (js[i] < 1 || js[i] > N - 1) return set_error(TGBA_EINVAL, "correlator distance j must be in [1, N-1]");
+        if (n > 0 && (!O[i] || ld[i] < n)) return set_error(TGBA_EINVAL, "bad output matrix");
+    }
+    if (nj == 0 || n == 0) return TGBA_OK;
+    int mb = 0;
+    for (int64_t a = 0; a < n; ++a) mb = std::max(mb, __builtin_popcountll(sc.masks[a]));
+    if (mb + 2 > kGenMax) return set_error(TGBA_EUNSUPPORTED, "states with more than 22 quasiparticles");
+    const int ts = 2 * N + 2;
+    const size_t tsz = (size_t)ts * ts;
+    // host: tables (two per j), signs (one per state and j), descriptors
+    std::vector<double> htab(2 * (size_t)nj * tsz), hsign((size_t)nj * n);
+    std::vector<double> hfac(2 * nj), hrmax(2 * nj);
+    std::vector<double> t;
+    for (int i = 0; i < nj; ++i)
+        for (int p = 0; p < 2; ++p) {
+            double res = 0.0;
+            int rc = corr_table(b, p == 0 ? kNS : kR, js[i], t, hfac[2 * i + p], hrmax[2 * i + p], res);
+            if (rc) return rc;
+            if (!(res < 1e-9)) return set_error(TGBA_ENUMERIC, "correlator table is not real in the real gauge");
+            std::copy(t.begin(), t.end(), htab.begin() + (2 * (size_t)i + p) * tsz);
+            for (int64_t a = 0; a < n; ++a)
+                if ((a < nn) == (p == 0)) hsign[(size_t)i * n + a] = corr_sign(b, p == 0 ? kNS : kR, js[i], sc.masks[a]);
+        }
+    const size_t ndesc = 2 * (size_t)nj;
+    const size_t bytes = sizeof(double) * (htab.size() + hsign.size()) + ndesc * sizeof(SectorDesc) + 256;
+    void *ws = nullptr;
+    int rc = workspace_get(bytes, 39, &ws);
+    if (rc) return rc;
+    double *d_tab = (double *)ws, *d_sign = d_tab + htab.size();
+    SectorDesc *d_desc = (SectorDesc *)(((uintptr_t)(d_sign + hsign.size()) + 255) & ~(uintptr_t)255);
+    const int rows = rows_default(N);
+    std::vector<SectorDesc> d(ndesc);
+    int64_t nblocks = 0;
+    for (int i = 0; i < nj; ++i)
+        for (int p = 0; p < 2; ++p) {
+            SectorDesc &x = d[2 * i + p];
+            x = SectorDesc{};
+            const int64_t off = p == 0 ? 0 : nn, cnt = p == 0 ? nn : nr;
+            x.masks = sc.d_masks + off;
+            x.ket = sc.d_masks + off;
+            x.e = nullptr;
+            x.H = O[i] + off * ld[i];  // column off + bra, row off + ket
+            x.ld = ld[i];
+            x.n_ns = cnt;
+            x.n_r = cnt;
+            x.mode = 1;
+            x.row_off = off;
+            x.max_m_bra = mb + 2;
+            x.tab = d_tab + (2 * (size_t)i + p) * tsz;
+            x.fac = hfac[2 * i + p];
+            x.rmax = hrmax[2 * i + p];
+            x.rsign = d_sign + (size_t)i * n + off;
+            x.csign = x.rsign;
+            x.first_block = nblocks;
+            x.nblk = (cnt + rows - 1) / rows;
+            nblocks += x.nblk;
+        }
+    TGBA_HIP(hipMemcpyAsync(d_tab, htab.data(), sizeof(double) * htab.size(), hipMemcpyHostToDevice, stream));
+    TGBA_HIP(hipMemcpyAsync(d_sign, hsign.data(), sizeof(double) * hsign.size(), hipMemcpyHostToDevice, stream));
+    TGBA_HIP(hipMemcpyAsync(d_desc, d.data(), ndesc * sizeof(SectorDesc), hipMemcpyHostToDevice, stream));
+    for (int i = 0; i < nj; ++i)  // the parity-changing blocks
+        if (nn > 0 && nr > 0) {
+            hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, stream, O[i] + nn, ld[i], nr, nn);
+            hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, stream, O[i] + nn * ld[i], ld[i], nn, nr);
+        }
+    TGBA_HIP(hipGetLastError());
+    if (nblocks == 0) return TGBA_OK;
+    const size_t lds = asm_lds(rows, N, mb + 2);
+    // hipMemcpyAsync from pageable host memory returns once the data is staged,
+    // so the host vectors may go out of scope after this point
+    if (rows == 4)
+        return launch_rows<4, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream);
+    return launch_rows<2, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream);
+}
+
 }  // namespace tgba
+
+extern "C" int tgba_assemble_corr(const tgba_basis *hb, int K, int nj, const int *js, double *const *O,
+                                  const int64_t *ld, void *stream) {
+    tgba::clear_error();
+    if (!hb) return tgba::set_error(TGBA_EINVAL, "NULL basis");
+    return tgba::assemble_corr(&hb->b, K, nj, js, O, ld, (hipStream_t)stream);
+}
 
 extern "C" int tgba_assemble_cross(const tgba_basis *hb, int K_rows, int K_cols, double *X, int64_t ld, void *stream) {
     tgba::clear_error();
@@ -1022,8 +1138,8 @@ extern "C" int tgba_assembly_plan_create(const tgba_basis *hb, int nsec, const i
         return fail(TGBA_EDEVICE, "plan descriptor upload failed");
     // kernel attributes are set outside the capture
     if (lds > 65536) {
-        const void *k = rows == 4 ? (o.cplx ? (const void *)assemble_rows_kernel<4, true> : (const void *)assemble_rows_kernel<4, false>)
-                                  : (o.cplx ? (const void *)assemble_rows_kernel<2, true> : (const void *)assemble_rows_kernel<2, false>);
+        const void *k = rows == 4 ? (o.cplx ? (const void *)assemble_rows_kernel<4, true, 0> : (const void *)assemble_rows_kernel<4, false, 0>)
+                                  : (o.cplx ? (const void *)assemble_rows_kernel<2, true, 0> : (const void *)assemble_rows_kernel<2, false, 0>);
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return fail(TGBA_EDEVICE, "kernel attribute failed");
     }

@@ -125,8 +125,8 @@ static int validate(const tgba_model *m, const tgba_trunc *t) {
         t->mode != TGBA_TRUNC_OVERLAP)
         return set_error(TGBA_EINVAL, "unknown truncation mode");
     if (t->mode == TGBA_TRUNC_OVERLAP &&
-        (!(t->h_pre > 0.0) || !std::isfinite(t->h_pre) || t->s < -1 || t->s > 1 || !(t->e_cut >= 0.0)))
-        return set_error(TGBA_EINVAL, "OVERLAP mode needs h_pre > 0, s in {-1, 0, 1} and a pool cutoff e_cut >= 0");
+        (!(t->h_pre >= 0.0) || !std::isfinite(t->h_pre) || t->s < -1 || t->s > 1 || !(t->e_cut >= 0.0)))
+        return set_error(TGBA_EINVAL, "OVERLAP mode needs h_pre >= 0, s in {-1, 0, 1} and a pool cutoff e_cut >= 0");
     if (t->mode == TGBA_TRUNC_LEARNED && (!t->mlp || !(t->e_cut >= 0.0)))
         return set_error(TGBA_EINVAL, "LEARNED mode needs the network parameters and a pool cutoff e_cut >= 0");
     if (t->mode == TGBA_TRUNC_ECUT && !(t->e_cut >= 0.0))

@@ -55,6 +55,14 @@ int momentum_index(int N, int sector, uint64_t mask);
 // table.hip: real contraction table of the common string and c0.
 int build_contraction_table(Basis *b, hipStream_t stream);
 
+// corr.cpp: real table (order 2N + 2, [bra, ket, J pair]) of the correlator
+// string sigma^x_1 sigma^x_{j+1} in parity sector `sector`, its prefactor, its
+// max |entry| and the relative imaginary residual of the real form; and the
+// per-state sign of the real-gauge matrix elements.
+int corr_table(const Basis *b, int sector, int j, std::vector<double> &tab, double &fac, double &rmax,
+               double &residual);
+double corr_sign(const Basis *b, int sector, int j, uint64_t mask);
+
 // Device workspace cache (grow-only, per device and slot).
 int workspace_get(size_t bytes, int slot, void **out);
 // A second stream of the current device (created once, default priority).

@@ -14,6 +14,7 @@
 // the closed form of eq. S5 (pairs (-k, k) with amplitude i W(k), W(k) =
 // tan(Delta_k / 2), normalised by prod sqrt(1 + W^2), and the sign of
 // reordering the pair product into ascending momentum).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -207,6 +208,27 @@ __global__ void cef_overlap_kernel(const uint64_t *masks, int64_t n_ns, int64_t 
         }
         c[2 * i] = re;
         c[2 * i + 1] = im;
+    }
+}
+
+// per (time column q, string i): <O_i>(t_q) = (B_re . W_re + B_im . W_im) / |c|^2,
+// minus sx(t_q)^2 when sx is given (connected correlator)
+__global__ void __launch_bounds__(256) corr_reduce_kernel(const double *Bm, const double *W, int64_t n, int nt,
+                                                          double inv_c2, const double *sx, double *out) {
+    const int q = blockIdx.x, i = blockIdx.y;
+    const double *Wi = W + (int64_t)i * n * 2 * nt;
+    double acc = 0.0;
+    for (int64_t a = threadIdx.x; a < n; a += 256)
+        acc += Bm[a + (int64_t)q * n] * Wi[a + (int64_t)q * n] +
+               Bm[a + (int64_t)(q + nt) * n] * Wi[a + (int64_t)(q + nt) * n];
+    __shared__ double r[4];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = (r[0] + r[1] + r[2] + r[3]) * inv_c2;
+        if (sx) v -= sx[q] * sx[q];
+        out[(int64_t)i * nt + q] = v;
     }
 }
 
@@ -417,7 +439,7 @@ extern "C" int tgba_quench_weights(int64_t n, const double *Z, int64_t ldz, cons
 
 extern "C" int tgba_quench_overlaps(const tgba_basis *hb, int K, double h_perp_pre, int s, double *c, void *stream) {
     clear_error();
-    if (!hb || K < 0 || K >= hb->b.N || !c || !(h_perp_pre > 0.0) || s < -1 || s > 1)
+    if (!hb || K < 0 || K >= hb->b.N || !c || !(h_perp_pre >= 0.0) || !std::isfinite(h_perp_pre) || s < -1 || s > 1)
         return set_error(TGBA_EINVAL, "bad arguments");
     const Basis &b = hb->b;
     const Sector &sc = b.sec[K];
@@ -444,10 +466,7 @@ extern "C" int tgba_quench_overlaps(const tgba_basis *hb, int K, double h_perp_p
         }
         tab.inv_norm[sec] = 1.0 / std::sqrt(norm2);
     }
-    if (s == 0) {  // Phi_0 = |0, post>_NS: only the NS vacuum state, amplitude 1 (W = 0)
-        for (int sec = 0; sec < 2; ++sec)
-            for (int a = 0; a < N; ++a) tab.W[sec][a] = 0.0;
-        tab.inv_norm[0] = 1.0;
+    if (s == 0) {  // Phi_0 = |0, pre>_NS alone (the post-quench NS vacuum when h_perp_pre = h_perp)
         tab.weight[0] = 1.0;
         tab.weight[1] = 0.0;
     } else {
@@ -457,5 +476,52 @@ extern "C" int tgba_quench_overlaps(const tgba_basis *hb, int K, double h_perp_p
     hipLaunchKernelGGL(cef_overlap_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream, sc.d_masks, sc.n_ns, n, N,
                        tab, c);
     TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+// Equal-time correlators after a quench (appendix on correlation functions):
+// B(t) as in tgba_quench, then W_i = O_i B for each string matrix (FP64 MFMA
+// products, in chunks that keep W within 2 GiB) and one reduction per (t, i).
+extern "C" int tgba_quench_corr(int64_t n, const double *Z, int64_t ldz, const double *w, const double *c, double t0,
+                                double dt, int nt, int nj, const double *const *O, const int64_t *ldo,
+                                const double *sx, double *out, void *stream) {
+    clear_error();
+    if (n <= 0 || nt <= 0 || nj < 0 || !Z || !w || !c || ldz < n || (nj > 0 && (!O || !ldo || !out)))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    for (int i = 0; i < nj; ++i)
+        if (!O[i] || ldo[i] < n) return set_error(TGBA_EINVAL, "bad string matrix");
+    if (nj == 0) return TGBA_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cols = 2 * (size_t)nt;
+    const size_t per = (size_t)n * cols;
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nj, ((size_t)1 << 28) / per));
+    void *ws = nullptr;
+    int rc = workspace_get(sizeof(double) * (4 * (size_t)n + 2 * per + (size_t)chunk * per + 64), 40, &ws);
+    if (rc) return rc;
+    double *cr = (double *)ws, *ci = cr + n, *yr = ci + n, *yi = yr + n;
+    double *U = yi + n, *Bm = U + per, *W = Bm + per, *c2 = W + (size_t)chunk * per;
+    hipLaunchKernelGGL(split_complex_kernel, dim3(256), dim3(256), 0, st, c, cr, ci, n);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, cr, yr);
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, ldz, n, n, ci, yi);
+    hipLaunchKernelGGL(phase_kernel, dim3(4096), dim3(256), 0, st, w, yr, yi, n, t0, dt, nt, U);
+    hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(256), 0, st, c, n, c2);
+    TGBA_HIP(hipGetLastError());
+    std::vector<GemmDesc> g(1);
+    g[0] = GemmDesc{Z, ldz, U, n, Bm, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+    if ((rc = dgemm_batched(g, 41, st))) return rc;
+    double c2h = 0.0;
+    TGBA_HIP(hipMemcpyAsync(&c2h, c2, sizeof(double), hipMemcpyDeviceToHost, st));
+    TGBA_HIP(hipStreamSynchronize(st));
+    if (!(c2h > 0.0)) return set_error(TGBA_EINVAL, "initial state has zero overlap with the basis");
+    for (int i0 = 0; i0 < nj; i0 += chunk) {
+        const int cnt = std::min(chunk, nj - i0);
+        g.assign(cnt, GemmDesc{});
+        for (int i = 0; i < cnt; ++i)
+            g[i] = GemmDesc{O[i0 + i], ldo[i0 + i], Bm, n, W + (size_t)i * per, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+        if ((rc = dgemm_batched(g, 42, st))) return rc;
+        hipLaunchKernelGGL(corr_reduce_kernel, dim3((unsigned)nt, (unsigned)cnt), dim3(256), 0, st, Bm, W, n, nt,
+                           1.0 / c2h, sx, out + (size_t)i0 * nt);
+        TGBA_HIP(hipGetLastError());
+    }
     return TGBA_OK;
 }
