@@ -65,6 +65,9 @@ def parse():
                    help="skip the overlap-ranked truncation convergence study (N=40 K=0, chi 2000..8000)")
     p.add_argument("--no-mixed", action="store_true",
                    help="skip the mixed-precision eigensolve measurement (N=40 K=0, E_cut 10.85)")
+    p.add_argument("--no-correlators", action="store_true",
+                   help="skip the equal-time correlator study (N=60, chi=2000, the two quenches of the "
+                        "appendix's correlator figure, j = 1..30, t <= 20)")
     p.add_argument("--no-isolated", action="store_true",
                    help="skip the extra step with the two eigensolve groups serialised (per-kernel rates "
                         "without the other stream's kernels beside them)")
@@ -166,6 +169,95 @@ def power_spectrum_run(tg, B, Z, w, G, h_pre=0.5, s=1, t_max=480.0, dt=0.05, n_o
             "top_peaks_omega": top, "m1_m2_m3": m, "m2_over_m1": m[1] / m[0],
             "nearest_peak_to_m1": min(top, key=lambda x: abs(x - m[0])) if top else None,
             "nearest_peak_to_m2": min(top, key=lambda x: abs(x - m[1])) if top else None}
+
+
+def correlator_study(N=60, chi=2000, m_max=6, js=tuple(range(1, 31)), t_max=20.0, dt=0.05, h_par=0.05,
+                     quenches=((0.0, 0.25, 1, 10.0), (2.0, 1.75, 0, 12.0))):
+    """Equal-time connected correlators <sigma^x_1 sigma^x_{j+1}> - <sigma^x>^2 after the two
+    quenches of the appendix's correlator figure, (h_pre, 0) -> (h_post, 0.05) at N = 60 with
+    chi = 2000 K = 0 states of at most m_max quasiparticles (lowest E^(0) among those with
+    E - E0 <= pool): the K = 0 H_eff and its eigenpairs, the CEF overlaps, the strings O_j for
+    j = 1..30 (tgba_assemble_corr) and their time series to t_max (tgba_quench_corr).  Per
+    quench: stage times, the rows kernel's rate (HIP events, bytes it writes), the products'
+    rate (algorithmic flops), and where the correlations spread (the first time |C_j| > 1e-3)."""
+    import torch
+    import paper_2410_04204_amd as tg
+    out = []
+    nt = int(round(t_max / dt)) + 1
+    for h_pre, h_post, s, pool in quenches:
+        chis = [chi] + [0] * (N - 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B = tg.Basis(N, h_post, h_par, chi=chis, m_max=m_max, pool_e_cut=pool)
+        t_basis = time.perf_counter() - t0
+        nn, nr = B.sector_size(0)
+        n = nn + nr
+        H = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        G = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        c = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        sx = torch.empty(nt, dtype=torch.float64, device="cuda")
+        nrm = torch.empty(nt, dtype=torch.float64, device="cuda")
+        Os = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in js]
+        C = torch.empty((len(js), nt), dtype=torch.float64, device="cuda")
+        stages = {}
+        for rep in range(2):  # the first pass warms up (autotuned launch shapes, workspaces)
+            for ch in (0, 1, 2):
+                tg.timing_read(ch)
+            tg.timing_enable(rep == 1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            tg.assemble_heff(B, 0, H, tg.TGBA_HEFF)
+            tg.assemble_heff(B, 0, G, tg.TGBA_GAMMA1)
+            tg.eig(H, w)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            tg.quench_overlaps(B, 0, h_pre, s, c)
+            tg.quench(H, w, G, c, 0.0, dt, nt, sx, nrm)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            tg.assemble_corr(B, 0, list(js), Os)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            tg.timing_read(1)  # products of the eigensolve and of the quench
+            tg.quench_corr(H, w, c, 0.0, dt, nt, Os, C, sx=sx)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            tg.timing_enable(False)
+            stages = {"heff_gamma1_eig": (t2 - t1) * 1e3, "overlaps_quench": (t3 - t2) * 1e3,
+                      "assemble_corr": (t4 - t3) * 1e3, "quench_corr": (t5 - t4) * 1e3}
+        wall = sum(stages.values()) * 1e-3
+        g_ms, g_l, g_f = tg.timing_read(1)
+        a_ms, a_l, a_b = tg.timing_read(2)
+        tg.timing_read(0)
+        Cn, sxn = C.cpu().numpy(), sx.cpu().numpy()
+        times = dt * np.arange(nt)
+        front = {}
+        for jj in (1, 5, 10, 15, 20, 25, 30):
+            if jj in js:
+                hit = np.where(np.abs(Cn[list(js).index(jj)]) > 1e-3)[0]
+                front[str(jj)] = float(times[hit[0]]) if hit.size else None
+        kk = np.linspace(-np.pi, np.pi, 20001)
+        eps = 2.0 * np.sqrt((h_post - 1.0) ** 2 + 4.0 * h_post * np.cos(kk / 2) ** 2)
+        vmax = float(np.max(np.abs(np.gradient(eps, kk))))
+        corr_elems = len(js) * (nn * nn + nr * nr)
+        out.append({
+            "quench": f"(h_perp, h_par) = ({h_pre}, 0) -> ({h_post}, {h_par}), initial state s = {s}",
+            "N": N, "chi_K0": n, "n_ns": nn, "n_r": nr, "m_max": m_max, "pool_e_cut": pool, "js": [min(js), max(js)],
+            "t_max": t_max, "samples": nt, "basis_build_s": t_basis, "wall_s": wall,
+            "stages_ms": stages,
+            "corr_rows_kernel": {"elements": corr_elems, "ms": a_ms, "launches": a_l,
+                                 "elements_per_s": corr_elems / (a_ms * 1e-3) if a_ms > 0 else None,
+                                 "achieved_GBs": a_b / (a_ms * 1e-3) / 1e9 if a_ms > 0 else None,
+                                 "frac_hbm": a_b / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if a_ms > 0 else None},
+            "quench_corr_products": {"ms": g_ms, "launches": g_l, "flops": g_f,
+                                     "TFs": g_f / (g_ms * 1e-3) / 1e12 if g_ms > 0 else None},
+            "C_1_at_t": {str(t): float(Cn[0][int(round(t / dt))]) for t in (0.0, 5.0, 10.0, 20.0) if t <= t_max},
+            "first_time_abs_C_j_above_1e-3": front, "max_group_velocity": vmax,
+            "sx_t0_t_max": [float(sxn[0]), float(sxn[-1])]})
+        del H, G, Os, C
+        torch.cuda.empty_cache()
+    return out
 
 
 def overlap_study(chis=(1000, 2000, 4000, 8000), pool=14.0, m_max=6, h_pre=0.5, s=1, t_max=60.0, dt=0.05):
@@ -445,11 +537,13 @@ def main():
     }
     if not a.no_power_spectrum:
         out["power_spectrum"] = power_spectrum_run(tg, B, Hs[0], ws[0], G0)
-    if not a.no_gap_metric or not a.no_overlap_study:
+    if not a.no_gap_metric or not a.no_overlap_study or not a.no_correlators:
         Hs.clear()  # free the N=40 sector matrices before the sweeps
         torch.cuda.empty_cache()
     if not a.no_overlap_study:
         out["overlap_truncation"] = overlap_study()
+    if not a.no_correlators:
+        out["correlators"] = correlator_study()
     if not a.no_gap_metric:
         torch.cuda.empty_cache()
         out["basis_dim_for_1e-6_gap"] = gap_metric()

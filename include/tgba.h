@@ -541,7 +541,9 @@ int tgba_timing_read(double *ms, int64_t *launches, double *bytes);
  * eigensolver's own: the reductions' updates, the back-transform, divide and
  * conquer), units = algorithmic flops: 2 M N K, counting only the stored
  * triangle for lower-only updates and for products with one triangle of a
- * symmetric operand.  Reading a channel consumes only that channel's records.
+ * symmetric operand.  Channel 2 is the rows kernel of tgba_assemble_corr,
+ * units = bytes it writes (8 per element of the NS x NS and R x R blocks).
+ * Reading a channel consumes only that channel's records.
  */
 int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units);
 

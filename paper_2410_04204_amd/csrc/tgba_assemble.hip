@@ -39,8 +39,10 @@
 // TGBA_LOWER, a tiled LDS transpose then mirrors B^T into the upper block B
 // (writing B directly from the rows kernel would be ROWS-long strided runs).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <thread>
 #include <type_traits>
 
 #include "tgba_internal.h"
@@ -1002,18 +1004,33 @@ int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O
     const size_t tsz = (size_t)ts * ts;
     // host: tables (two per j), signs (one per state and j), descriptors
     std::vector<double> htab(2 * (size_t)nj * tsz), hsign((size_t)nj * n);
-    std::vector<double> hfac(2 * nj), hrmax(2 * nj);
-    std::vector<double> t;
-    for (int i = 0; i < nj; ++i)
-        for (int p = 0; p < 2; ++p) {
-            double res = 0.0;
-            int rc = corr_table(b, p == 0 ? kNS : kR, js[i], t, hfac[2 * i + p], hrmax[2 * i + p], res);
-            if (rc) return rc;
-            if (!(res < 1e-9)) return set_error(TGBA_ENUMERIC, "correlator table is not real in the real gauge");
-            std::copy(t.begin(), t.end(), htab.begin() + (2 * (size_t)i + p) * tsz);
-            for (int64_t a = 0; a < n; ++a)
-                if ((a < nn) == (p == 0)) hsign[(size_t)i * n + a] = corr_sign(b, p == 0 ? kNS : kR, js[i], sc.masks[a]);
-        }
+    std::vector<double> hfac(2 * nj), hrmax(2 * nj), hres(2 * nj);
+    std::vector<int> hrc(2 * nj, TGBA_OK);
+    // the 2 nj tables are independent host computations: split them over threads
+    auto work = [&](int task) {
+        const int i = task / 2, p = task % 2;
+        std::vector<double> t;
+        hrc[task] = corr_table(b, p == 0 ? kNS : kR, js[i], t, hfac[task], hrmax[task], hres[task]);
+        if (hrc[task]) return;
+        std::copy(t.begin(), t.end(), htab.begin() + (size_t)task * tsz);
+        for (int64_t a = 0; a < n; ++a)
+            if ((a < nn) == (p == 0)) hsign[(size_t)i * n + a] = corr_sign(b, p == 0 ? kNS : kR, js[i], sc.masks[a]);
+    };
+    const int ntask = 2 * nj;
+    const int nthr = std::max(1, std::min({ntask, 16, (int)std::thread::hardware_concurrency()}));
+    {
+        std::atomic<int> next{0};
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nthr; ++w)
+            pool.emplace_back([&] { for (int t; (t = next++) < ntask;) work(t); });
+        for (int t; (t = next++) < ntask;) work(t);
+        for (auto &th : pool) th.join();
+    }
+    for (int task = 0; task < ntask; ++task) {
+        if (hrc[task] == TGBA_EINVAL) return set_error(TGBA_EINVAL, "correlator distance j must be in [1, N-1]");
+        if (hrc[task]) return set_error(hrc[task], "correlator table: singular string block or transform");
+        if (!(hres[task] < 1e-9)) return set_error(TGBA_ENUMERIC, "correlator table is not real in the real gauge");
+    }
     const size_t ndesc = 2 * (size_t)nj;
     const size_t bytes = sizeof(double) * (htab.size() + hsign.size()) + ndesc * sizeof(SectorDesc) + 256;
     void *ws = nullptr;
@@ -1061,9 +1078,17 @@ int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O
     const size_t lds = asm_lds(rows, N, mb + 2);
     // hipMemcpyAsync from pageable host memory returns once the data is staged,
     // so the host vectors may go out of scope after this point
-    if (rows == 4)
-        return launch_rows<4, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream);
-    return launch_rows<2, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream);
+    hipEvent_t ta = nullptr, tb = nullptr;
+    if (timing_on() && (rc = timing_begin(stream, &ta, &tb))) return rc;
+    rc = (rows == 4)
+             ? launch_rows<4, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream)
+             : launch_rows<2, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream);
+    if (rc) return rc;
+    if (ta) {  // channel 2: bytes written by the rows kernel (the two parity blocks of every j)
+        const double written = 8.0 * (double)nj * ((double)nn * nn + (double)nr * nr);
+        if ((rc = timing_end(stream, ta, tb, written, 2))) return rc;
+    }
+    return TGBA_OK;
 }
 
 }  // namespace tgba

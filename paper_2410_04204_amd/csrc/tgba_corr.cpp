@@ -21,8 +21,8 @@
 // each other's conjugates; their sum and difference (a 2 x 2 transform L per
 // pair) are real.  R = diag(L, D) K diag(L, D)^T is real, and for states of one
 // momentum sector
-//     O_real[a][b] = fac * sigma_a * sigma_b * Pf(R[O u I_a u I_b]),
-//     fac = 1 / det L,   sigma = (-1)^{M/2 [NS only] + j m},
+//     O_real[a][b] = sigma_a * sigma_b * Pf(R[O u I_a u I_b]) / det L,
+//     sigma = (-1)^{M/2 [NS only] + j m},
 // where m is the integer with sum of the state's momenta = K + 2 pi m and
 // O_real is the matrix in the gauge of the real H_eff (NS: (-i)^{M/2},
 // R: i^{M/2} per state).
@@ -32,9 +32,10 @@
 // of size 1 / Pf(R_OO) into the table.  The block is therefore eliminated by
 // complete pivoting except for its last pair J: the table handed to the
 // device is the Schur complement over the other 2j - 2 Majoranas, of order
-// 2N + 2, and every element is fac' * Pf(T[J u I_a u I_b]) with bounded
-// entries (the small pivot stays inside each element's Pfaffian, where the
-// assembly kernel treats it like a nearly singular bra block).
+// 2N + 2, and every element is fac * sigma_a * sigma_b * Pf(T[J u I_a u I_b]),
+// fac = (product of the eliminated pivots, with the signs of the swaps) / det L,
+// with bounded entries (the small pivot stays inside each element's Pfaffian,
+// where the assembly kernel treats it like a nearly singular bra block).
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -147,27 +148,32 @@ int corr_table(const Basis *b, int sector, int j, std::vector<double> &tab, doub
         L[(size_t)(2 * r + 1) * no + pa] = -I;
         L[(size_t)(2 * r + 1) * no + pb] = I / rho;
     }
-    // R = T K T^T with T = diag(L, D); keep the real part, record the imaginary one
-    std::vector<double> R((size_t)n * n, 0.0);
-    auto tk = [&](int p, int q) -> cplx {  // (T K)[p][q]
-        if (p >= no) return D[p - no] * K[(size_t)p * n + q];
-        cplx acc = 0.0;
-        for (int t = 0; t < no; ++t) acc += L[(size_t)p * no + t] * K[(size_t)t * n + q];
-        return acc;
-    };
+    // R = T K T^T with T = diag(L, D); every row of L has two entries (at pa and pb of
+    // its pair), so both products are applied sparsely.  Keep the real part and
+    // record the imaginary one.
+    std::vector<int> lc0(no), lc1(no);
+    std::vector<cplx> lv0(no), lv1(no);
+    for (int r = 0; r < j; ++r) {
+        const int l = r + 2, pa = 2 * l - 3, pb = 2 * j + 2 - 2 * l;
+        for (int u = 0; u < 2; ++u) {
+            const int row = 2 * r + u;
+            lc0[row] = pa;
+            lc1[row] = pb;
+            lv0[row] = L[(size_t)row * no + pa];
+            lv1[row] = L[(size_t)row * no + pb];
+        }
+    }
     std::vector<cplx> TK((size_t)n * n);
     for (int p = 0; p < n; ++p)
-        for (int q = 0; q < n; ++q) TK[(size_t)p * n + q] = tk(p, q);
+        for (int q = 0; q < n; ++q)
+            TK[(size_t)p * n + q] = (p >= no) ? D[p - no] * K[(size_t)p * n + q]
+                                              : lv0[p] * K[(size_t)lc0[p] * n + q] + lv1[p] * K[(size_t)lc1[p] * n + q];
+    std::vector<double> R((size_t)n * n, 0.0);
     double imag = 0.0, mag = 0.0;
     for (int p = 0; p < n; ++p)
         for (int q = 0; q < n; ++q) {
-            cplx v;
-            if (q >= no) {
-                v = TK[(size_t)p * n + q] * D[q - no];
-            } else {
-                v = 0.0;
-                for (int t = 0; t < no; ++t) v += TK[(size_t)p * n + t] * L[(size_t)q * no + t];
-            }
+            const cplx v = (q >= no) ? TK[(size_t)p * n + q] * D[q - no]
+                                     : TK[(size_t)p * n + lc0[q]] * lv0[q] + TK[(size_t)p * n + lc1[q]] * lv1[q];
             R[(size_t)p * n + q] = v.real();
             imag = std::max(imag, std::fabs(v.imag()));
             mag = std::max(mag, std::abs(v));
