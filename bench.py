@@ -53,7 +53,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=2)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="n40_batched")
+    p.add_argument("--workload", default="n40_batched",
+                   help="n40_batched (the timed step), n64_learned (learned quench basis), n60_corr (only the "
+                        "correlator study)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--chi-ref", type=int, default=45000, help="reference dimension of the n64_learned workload")
@@ -381,6 +383,10 @@ def main():
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "n60_corr":
+        print(json.dumps({"workload": "n60_corr", "data": "synthetic", "dtype": "f64",
+                          "correlators": correlator_study()}), flush=True)
         return
     if a.workload == "n64_learned":
         n64_learned(a)

@@ -16,9 +16,9 @@
 //   3. each remaining root lambda_m of the secular equation
 //          f(lambda) = 1 + rho' sum_j z_j^2 / (d_j - lambda) = 0
 //      lies strictly between consecutive poles (the last above the last pole);
-//      it is found by bisection on tau = lambda - d_o from the nearer pole d_o,
-//      so that every difference d_j - lambda = (d_j - d_o) - tau is formed
-//      without cancellation;
+//      it is found on tau = lambda - d_o from the nearer pole d_o, so that every
+//      difference d_j - lambda = (d_j - d_o) - tau is formed without
+//      cancellation, by a safeguarded rational iteration (see dc_roots);
 //   4. the vector z is recomputed from the roots (Gu-Eisenstat):
 //          zhat_i^2 = prod_j (lambda_j - d_i) / (rho' prod_{j != i} (d_j - d_i)),
 //      which makes the eigenvectors v_m = zhat / (d - lambda_m) numerically
@@ -59,6 +59,7 @@ struct DCScratch {
     int64_t *code;     // final position q -> root m (>= 0) or deflated t (-1 - t)
     int64_t *counts;   // per merge: [k', ndefl, nrot, -]
     double *rho;       // per merge
+    double *cd, *cw;   // nondeflated poles d and weights rho z^2 in order, at lo + m
 };
 
 __global__ void tear_kernel(double *d, const double *e, const int64_t *splits, int nsplit) {
@@ -177,19 +178,32 @@ __device__ __forceinline__ int merge_of(const int64_t *first, int nm, int64_t g)
     return lo;
 }
 
-// secular function from origin o: 1 + rho sum z_j^2 / ((d_j - d_o) - tau)
-__device__ __forceinline__ double secular(const double *ds, const double *zs, const int64_t *nd, int64_t lo, int64_t kp,
-                                          double rho, double dorg, double tau) {
-    double f = 0.0;
-    for (int64_t j = 0; j < kp; ++j) {
-        const int64_t p = nd[lo + j];
-        const double z = zs[lo + p];
-        f += z * z / ((ds[lo + p] - dorg) - tau);
-    }
-    return 1.0 + rho * f;
+// 3a: the nondeflated poles and weights rho z_j^2 as contiguous arrays (thread per (merge, m))
+__global__ void __launch_bounds__(256) dc_compact(const Merge *merges, const int64_t *first, int nm, DCScratch S) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int mi = merge_of(first, nm, g);
+    const Merge M = merges[mi];
+    const int64_t m = g - first[mi];
+    const int64_t kp = S.counts[4 * mi];
+    if (m < 0 || m >= kp) return;
+    const int64_t lo = M.lo, p = S.nd[lo + m];
+    const double z = S.zs[lo + p];
+    S.cd[lo + m] = S.ds[lo + p];
+    S.cw[lo + m] = S.rho[mi] * z * z;
 }
 
-// 3: one thread per (merge, root); `first` = prefix of merge sizes k (thread slots)
+// 3b: one thread per (merge, root m).  Root m lies between the poles m and m+1
+// (the last root above the last pole, below it plus rho |z|^2); its origin is
+// the nearer pole, decided by the sign of f at the midpoint.  Safeguarded
+// rational iteration (the secular-equation model of Bunch, Nielsen and
+// Sorensen): at the current t the sum over the poles at or below the bracket
+// (psi, negative) and the sum over the poles above it (phi, positive) are each
+// replaced by a constant plus one pole term at the bracket's pole, matching
+// value and slope at t; the model's root inside the bracket is the next t, and
+// a bisection step is taken whenever it falls outside.  The bracket follows the
+// sign of f (f increases between its poles).  Stops when |f| is at the level of
+// its rounding error, when the step no longer changes t, or when the bracket
+// has no interior point.
 __global__ void __launch_bounds__(256) dc_roots(const Merge *merges, const int64_t *first, int nm, DCScratch S) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int mi = merge_of(first, nm, g);
@@ -198,31 +212,69 @@ __global__ void __launch_bounds__(256) dc_roots(const Merge *merges, const int64
     const int64_t kp = S.counts[4 * mi];
     if (m < 0 || m >= kp) return;
     const int64_t lo = M.lo;
-    const double rho = S.rho[mi];
-    const double dm = S.ds[lo + S.nd[lo + m]];
+    const double *cd = S.cd + lo, *cw = S.cw + lo;
+    const bool last = (m + 1 >= kp);
     int64_t o;
     double tlo, thi;
-    if (m + 1 < kp) {
-        const double dn = S.ds[lo + S.nd[lo + m + 1]];
-        const double half = 0.5 * (dn - dm);
-        const double fmid = secular(S.ds, S.zs, S.nd, lo, kp, rho, dm, half);
+    if (!last) {
+        const double dm = cd[m], half = 0.5 * (cd[m + 1] - dm);
+        double fmid = 1.0;
+        for (int64_t j = 0; j < kp; ++j) fmid += cw[j] / ((cd[j] - dm) - half);
         if (fmid > 0.0) { o = m; tlo = 0.0; thi = half; }
         else { o = m + 1; tlo = -half; thi = 0.0; }
     } else {
-        double zz = 0.0;
-        for (int64_t j = 0; j < kp; ++j) { const double z = S.zs[lo + S.nd[lo + j]]; zz += z * z; }
-        o = m; tlo = 0.0; thi = rho * zz;
+        double ww = 0.0;
+        for (int64_t j = 0; j < kp; ++j) ww += cw[j];
+        o = m; tlo = 0.0; thi = ww;
     }
-    const double dorg = S.ds[lo + S.nd[lo + o]];
-    for (int it = 0; it < 400; ++it) {
-        const double t = 0.5 * (tlo + thi);
-        if (t <= tlo || t >= thi) break;
-        if (thi - tlo <= 2.0 * DBL_EPSILON * fmax(fabs(tlo), fabs(thi))) break;
-        const double f = secular(S.ds, S.zs, S.nd, lo, kp, rho, dorg, t);
+    const double dorg = cd[o];
+    const double dL = cd[m] - dorg;                   // lower pole of the bracket (0 when o == m)
+    const double dU = last ? 0.0 : cd[m + 1] - dorg;  // upper pole (0 when o == m + 1)
+    double t = 0.5 * (tlo + thi);
+    for (int it = 0; it < 200; ++it) {
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        for (int64_t j = 0; j <= m; ++j) {
+            const double r = 1.0 / ((cd[j] - dorg) - t), w = cw[j] * r;
+            psi += w;
+            dpsi += w * r;
+        }
+        for (int64_t j = m + 1; j < kp; ++j) {
+            const double r = 1.0 / ((cd[j] - dorg) - t), w = cw[j] * r;
+            phi += w;
+            dphi += w * r;
+        }
+        const double f = 1.0 + psi + phi;
         if (f > 0.0) thi = t; else tlo = t;
+        if (fabs(f) <= 8.0 * DBL_EPSILON * (1.0 + phi - psi)) break;
+        if (thi - tlo <= 2.0 * DBL_EPSILON * fmax(fabs(tlo), fabs(thi))) break;
+        const double q = dpsi * (dL - t) * (dL - t), p = psi - dpsi * (dL - t);
+        double tn;
+        if (last) {  // 1 + p + q / (dL - x) = 0
+            const double A = 1.0 + p;
+            tn = dL + q / A;
+        } else {     // 1 + p + r + q / (dL - x) + s / (dU - x) = 0: one root in (dL, dU)
+            const double s = dphi * (dU - t) * (dU - t), r = phi - dphi * (dU - t);
+            const double A = 1.0 + p + r, Del = dU - dL;
+            // with y = x - dL:  A y^2 - b y + q Del = 0,  b = A Del + q + s,
+            // with y = dU - x:  A y^2 - c y - s Del = 0,  c = A Del - q - s,
+            // one root each in (0, Del); both discriminants are X^2 + 4 q s.
+            // Each root is taken in the form without cancellation for the sign
+            // of b or c (s or q can be far below the other terms).
+            const double X = A * Del - q + s, sq = sqrt(X * X + 4.0 * q * s);
+            if (o == m) {  // distance above the lower pole
+                const double b = A * Del + q + s;
+                tn = dL + ((b >= 0.0) ? 2.0 * q * Del / (b + sq) : (b - sq) / (2.0 * A));
+            } else {       // distance below the upper pole
+                const double c = A * Del - q - s;
+                tn = dU - ((c > 0.0) ? (c + sq) / (2.0 * A) : 2.0 * s * Del / (sq - c));
+            }
+        }
+        if (!(tn > tlo && tn < thi)) tn = 0.5 * (tlo + thi);
+        if (fabs(tn - t) <= 2.0 * DBL_EPSILON * fabs(t)) { t = tn; break; }
+        t = tn;
     }
     S.org[lo + m] = o;
-    S.tau[lo + m] = 0.5 * (tlo + thi);
+    S.tau[lo + m] = t;
 }
 
 // 4: zhat_i for each nondeflated index i (thread per (merge, i))
@@ -235,14 +287,15 @@ __global__ void __launch_bounds__(256) dc_zhat(const Merge *merges, const int64_
     if (i < 0 || i >= kp) return;
     const int64_t lo = M.lo;
     const double rho = S.rho[mi];
-    const double di = S.ds[lo + S.nd[lo + i]];
+    const double *cd = S.cd + lo;
+    const double di = cd[i];
     double prod = 1.0;
     for (int64_t j = 0; j < kp; ++j) {
-        const double lam_minus_di = (S.ds[lo + S.nd[lo + S.org[lo + j]]] - di) + S.tau[lo + j];
+        const double lam_minus_di = (cd[S.org[lo + j]] - di) + S.tau[lo + j];
         if (j < i) {
-            prod *= lam_minus_di / (S.ds[lo + S.nd[lo + j]] - di);
+            prod *= lam_minus_di / (cd[j] - di);
         } else if (j + 1 < kp) {
-            prod *= lam_minus_di / (S.ds[lo + S.nd[lo + j + 1]] - di);
+            prod *= lam_minus_di / (cd[j + 1] - di);
         } else {
             prod *= lam_minus_di / rho;
         }
@@ -260,10 +313,11 @@ __global__ void __launch_bounds__(256) dc_norms(const Merge *merges, const int64
     const int64_t kp = S.counts[4 * mi];
     if (m < 0 || m >= kp) return;
     const int64_t lo = M.lo;
-    const double dorg = S.ds[lo + S.nd[lo + S.org[lo + m]]], tau = S.tau[lo + m];
+    const double *cd = S.cd + lo;
+    const double dorg = cd[S.org[lo + m]], tau = S.tau[lo + m];
     double s = 0.0;
     for (int64_t i = 0; i < kp; ++i) {
-        const double v = S.zhat[lo + i] / ((S.ds[lo + S.nd[lo + i]] - dorg) - tau);
+        const double v = S.zhat[lo + i] / ((cd[i] - dorg) - tau);
         s += v * v;
     }
     S.inorm[lo + m] = 1.0 / sqrt(s);
@@ -374,10 +428,10 @@ int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStre
     const int H = build(0, n);
     // workspace
     const size_t nn = (size_t)n;
-    // carve-outs below: 2 n^2 + 11 n doubles, 15 n + 1 int64 and 4 n doubles of descriptors,
-    // each rounded up to 256 bytes (at most 30 carve-outs)
-    const size_t bytes = sizeof(double) * (2 * nn * nn + 11 * nn) + sizeof(int64_t) * (15 * nn + 1) +
-                         sizeof(double) * 4 * nn + 30 * 256;
+    // carve-outs below: 2 n^2 + 13 n doubles, 15 n + 1 int64 and 4 n doubles of descriptors,
+    // each rounded up to 256 bytes (at most 32 carve-outs)
+    const size_t bytes = sizeof(double) * (2 * nn * nn + 13 * nn) + sizeof(int64_t) * (15 * nn + 1) +
+                         sizeof(double) * 4 * nn + 32 * 256;
     void *ws = nullptr;
     int rc = workspace_get(bytes, 8, &ws);
     if (rc) return rc;
@@ -387,7 +441,7 @@ int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStre
     double *Qtmp = takeD(nn * n), *V = takeD(nn * n);
     DCScratch S;
     S.ds = takeD(nn); S.zs = takeD(nn); S.dval = takeD(nn); S.tau = takeD(nn); S.zhat = takeD(nn);
-    S.inorm = takeD(nn); S.rcs = takeD(2 * nn); S.rho = takeD(nn);
+    S.inorm = takeD(nn); S.rcs = takeD(2 * nn); S.rho = takeD(nn); S.cd = takeD(nn); S.cw = takeD(nn);
     double *Dalt = takeD(nn);
     S.perm = takeI(nn); S.nd = takeI(nn); S.ndinv = takeI(nn); S.dpos = takeI(nn); S.org = takeI(nn);
     S.code = takeI(nn); S.rij = takeI(2 * nn); S.counts = takeI(4 * nn);
@@ -423,6 +477,7 @@ int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStre
         // the same range is also copied so that Dnext holds the untouched entries of other blocks
         TGBA_HIP(hipMemcpyAsync(Dnext, Dcur, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
         hipLaunchKernelGGL(dc_prepare, dim3(nm), dim3(256), 0, stream, d_merges, Dcur, Z, ldz, S);
+        hipLaunchKernelGGL(dc_compact, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, S);
         hipLaunchKernelGGL(dc_roots, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, S);
         hipLaunchKernelGGL(dc_zhat, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, S);
         hipLaunchKernelGGL(dc_norms, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, S);
