@@ -71,6 +71,7 @@ struct BandSec {
     double *d, *e;  // n, n
     int64_t first_wg;  // stage 2: first workgroup of this sector in a step launch
     int64_t cap;       // stage 2: workgroups of this sector per step
+    double *Q;      // n x 4 BW (ld n): a panel pair's [V1' V2 W1' W2] for the rank-4 BW update
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -380,8 +381,26 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 }  // namespace
 
 size_t band_workspace_doubles(int64_t n) {
-    return (size_t)n * (3 * BW + LDB + 1) + (size_t)kQrMaxBlk * QP + BW + 4 * BW * BW + 64;
+    return (size_t)n * (7 * BW + LDB + 1) + (size_t)kQrMaxBlk * QP + BW + 4 * BW * BW + 64;
 }
+
+namespace {
+// Q[:, col0 .. col0 + BW) of every active sector <- rows [off, off + m) of its V
+// (which = 0) or W (which = 1), m = n - j0p - BW (the geometry of the panel at j0p)
+__global__ void __launch_bounds__(256) pair_copy_kernel(const BandSec *__restrict__ secs, int64_t j0p, int which,
+                                                        int64_t off, int col0) {
+    const BandSec &S = secs[blockIdx.y];
+    const int64_t m = S.n - j0p - BW;
+    if (m <= 0) return;
+    const double *src = (which ? S.W : S.V) + off;
+    double *dst = S.Q + (size_t)col0 * S.n;
+    const int64_t tot = m * BW;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < tot; i += (int64_t)gridDim.x * 256) {
+        const int64_t r = i % m, c = i / m;
+        dst[r + c * S.n] = src[r + c * S.n];
+    }
+}
+}  // namespace
 
 int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     const int nsec = (int)in.size();
@@ -419,6 +438,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.T = p; p += BW * BW;
         S.Y = p; p += BW * BW;
         S.M = p; p += BW * BW;
+        S.Q = p; p += (size_t)x.n * 4 * BW;
         S.first_wg = wg;
         S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / kStride + 2 : 0;
         wg += S.cap;
@@ -470,12 +490,12 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     }
 
     // ---- stage 1 ----
-    for (int64_t j0 = 0; j0 < nmax; j0 += BW) {
-        const int act = active(j0);
-        if (act == 0) break;
-        const int64_t m0 = secs[0].n - j0 - BW;
+    // One panel of every active sector at column j0: QR (sub-blocks) and T.
+    auto factor = [&](int64_t j0, int act) -> int {
+        int rc = TGBA_OK;
         std::vector<int> sym, gram;
         splits(act, j0, sym, gram);
+        const int64_t m0 = secs[0].n - j0 - BW;
         for (int c0 = 0; c0 < BW; c0 += SB) {
             for (int q = c0; q < c0 + SB; ++q) {
                 if (q >= m0 - 1) break;  // no sector has a reflector q (sector 0 has the most rows)
@@ -549,10 +569,17 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
         hipLaunchKernelGGL(larft_panel_kernel, dim3(act), dim3(BW), 0, stream, d_secs, j0, 0, BW, 0);
         TGBA_HIP(hipGetLastError());
+        return TGBA_OK;
+    };
+    // X = A22 V of the panel at j0
+    auto symx = [&](int64_t j0, int act) -> int {
+        int rc = TGBA_OK;
+        std::vector<int> sym, gram;
+        splits(act, j0, sym, gram);
+        std::vector<GemmDesc> g;
+        std::vector<ReduceDesc> red;
+        double *pp = parts;
         // X = A22 V = tril(A22) V + stril(A22)^T V (split K) into X
-        g.clear();
-        red.clear();
-        pp = parts;
         for (int q = 0; q < act; ++q) {
             const BandSec &S = secs[q];
             const int64_t m = S.n - j0 - BW, t0 = j0 + BW;
@@ -572,6 +599,16 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         }
         if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
         if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+        return TGBA_OK;
+    };
+    // W = X T - 1/2 V (T^T V^T X T) of the panel at j0
+    auto makew = [&](int64_t j0, int act) -> int {
+        int rc = TGBA_OK;
+        std::vector<int> sym, gram;
+        splits(act, j0, sym, gram);
+        std::vector<GemmDesc> g;
+        std::vector<ReduceDesc> red;
+        double *pp = parts;
         // W = X T
         g.clear();
         for (int q = 0; q < act; ++q) {
@@ -611,9 +648,14 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
             g.push_back(GemmDesc{S.V, S.n, S.M, BW, S.W, S.n, m, BW, BW, -0.5, 1.0, 0, 0, 0, 0, 0, 0});
         }
         if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        return TGBA_OK;
+    };
+    // A22 -= V W^T + W V^T for the sectors [qa, qb) (their panel at j0 alone)
+    auto syr2k = [&](int64_t j0, int qa, int qb) -> int {
+        int rc = TGBA_OK;
+        std::vector<GemmDesc> g;
         // A22 -= V W^T + W V^T (lower tiles; one product of depth 2 BW)
-        g.clear();
-        for (int q = 0; q < act; ++q) {
+        for (int q = qa; q < qb; ++q) {
             const BandSec &S = secs[q];
             const int64_t m = S.n - j0 - BW, t0 = j0 + BW;
             double *A22 = S.A + t0 + t0 * S.lda;
@@ -626,6 +668,109 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
             g.push_back(G);
         }
         if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        return TGBA_OK;
+    };
+    // Panels are taken in pairs (j0, j1 = j0 + BW).  Panel j0's two-sided update
+    // is applied at once only to the next panel's block column; panel j1 is
+    // factored on that, its product X2 = A22 V2 is corrected for panel j0's
+    // pending update (A22 = A22_old - V1 W1^T - W1 V1^T on the rows from
+    // j1 + BW: X2 = A22_old V2 - V1' (W1'^T V2) - W1' (V1'^T V2)), and both
+    // updates of the trailing matrix are one lower product of depth 4 BW,
+    // A22_old -= [V1' V2][W1' W2]^T + [W1' W2][V1' V2]^T, which reads and writes
+    // the trailing matrix once per two panels.
+    for (int64_t j0 = 0; j0 < nmax;) {
+        const int act1 = active(j0);
+        if (act1 == 0) break;
+        const int64_t j1 = j0 + BW;
+        const int act2 = active(j1);
+        if ((rc = factor(j0, act1)) || (rc = symx(j0, act1)) || (rc = makew(j0, act1))) return rc;
+        if (act2 < act1 && (rc = syr2k(j0, act2, act1))) return rc;  // no next panel: update alone
+        if (act2 == 0) {
+            j0 = j1;
+            continue;
+        }
+        const unsigned cb = (unsigned)std::min<int64_t>(1024, ceil_div((secs[0].n - j1 - BW) * BW, 256));
+        // V1', W1': rows of panel j0's V, W from j1 + BW on -> Q[:, 0:BW), Q[:, 2BW:3BW)
+        hipLaunchKernelGGL(pair_copy_kernel, dim3(cb, act2), dim3(256), 0, stream, d_secs, j1, 0, (int64_t)BW, 0);
+        hipLaunchKernelGGL(pair_copy_kernel, dim3(cb, act2), dim3(256), 0, stream, d_secs, j1, 1, (int64_t)BW, 2 * BW);
+        TGBA_HIP(hipGetLastError());
+        {  // A[j1.., j1..j1+BW) -= V1 W1[0:BW)^T + W1 V1[0:BW)^T (the next panel's block column)
+            std::vector<GemmDesc> g;
+            for (int q = 0; q < act2; ++q) {
+                const BandSec &S = secs[q];
+                const int64_t m1 = S.n - j0 - BW;
+                double *C = S.A + j1 + j1 * S.lda;
+                GemmDesc G{S.V, S.n, S.W, S.n, C, S.lda, m1, BW, BW, -1.0, 1.0, 0, 1, 0, 0, 0, 0};
+                G.A2 = S.W;
+                G.lda2 = S.n;
+                G.B2 = S.V;
+                G.ldb2 = S.n;
+                G.K2 = BW;
+                g.push_back(G);
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        }
+        if ((rc = factor(j1, act2)) || (rc = symx(j1, act2))) return rc;
+        {  // X2 -= V1' (W1'^T V2) + W1' (V1'^T V2): the two BW x BW factors by split K into Y and S
+            std::vector<int> sym, gram;
+            splits(act2, j1, sym, gram);
+            std::vector<GemmDesc> g;
+            std::vector<ReduceDesc> red;
+            double *pp = parts;
+            for (int q = 0; q < act2; ++q) {
+                const BandSec &S = secs[q];
+                const int64_t m2 = S.n - j1 - BW;
+                GemmDesc G1{S.Q + (size_t)2 * BW * S.n, S.n, S.V, S.n, S.Y, BW, BW, BW, m2, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+                G1.ksplit = gram[q];
+                G1.Cpart = pp;
+                red.push_back(ReduceDesc{S.Y, BW, BW, BW, pp, gram[q], 0.0, 0});
+                pp += (size_t)gram[q] * BW * BW;
+                GemmDesc G2{S.Q, S.n, S.V, S.n, S.S, BW, BW, BW, m2, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+                G2.ksplit = gram[q];
+                G2.Cpart = pp;
+                red.push_back(ReduceDesc{S.S, BW, BW, BW, pp, gram[q], 0.0, 0});
+                pp += (size_t)gram[q] * BW * BW;
+                g.push_back(G1);
+                g.push_back(G2);
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+            if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+            g.clear();
+            for (int q = 0; q < act2; ++q) {
+                const BandSec &S = secs[q];
+                const int64_t m2 = S.n - j1 - BW;
+                GemmDesc G{S.Q, S.n, S.Y, BW, S.X, S.n, m2, BW, BW, -1.0, 1.0, 0, 0, 0, 0, 0, 0};
+                G.A2 = S.Q + (size_t)2 * BW * S.n;
+                G.lda2 = S.n;
+                G.B2 = S.S;
+                G.ldb2 = BW;
+                G.K2 = BW;
+                g.push_back(G);
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        }
+        if ((rc = makew(j1, act2))) return rc;
+        // V2, W2 -> Q[:, BW:2BW), Q[:, 3BW:4BW)
+        hipLaunchKernelGGL(pair_copy_kernel, dim3(cb, act2), dim3(256), 0, stream, d_secs, j1, 0, (int64_t)0, BW);
+        hipLaunchKernelGGL(pair_copy_kernel, dim3(cb, act2), dim3(256), 0, stream, d_secs, j1, 1, (int64_t)0, 3 * BW);
+        TGBA_HIP(hipGetLastError());
+        {  // A22 -= [V1' V2][W1' W2]^T + [W1' W2][V1' V2]^T (lower tiles, depth 4 BW)
+            std::vector<GemmDesc> g;
+            for (int q = 0; q < act2; ++q) {
+                const BandSec &S = secs[q];
+                const int64_t m2 = S.n - j1 - BW, t0 = j1 + BW;
+                double *A22 = S.A + t0 + t0 * S.lda;
+                GemmDesc G{S.Q, S.n, S.Q + (size_t)2 * BW * S.n, S.n, A22, S.lda, m2, m2, 2 * BW, -1.0, 1.0, 0, 1, 1, 0, 0, 0};
+                G.A2 = S.Q + (size_t)2 * BW * S.n;
+                G.lda2 = S.n;
+                G.B2 = S.Q;
+                G.ldb2 = S.n;
+                G.K2 = 2 * BW;
+                g.push_back(G);
+            }
+            if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
+        }
+        j0 += 2 * BW;
     }
     hipLaunchKernelGGL(band_extract_kernel, dim3(256, nsec), dim3(256), 0, stream, d_secs);
     TGBA_HIP(hipGetLastError());
