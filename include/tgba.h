@@ -523,10 +523,11 @@ int tgba_autotune_enable(int on);
 int tgba_autotune_report(char *buf, int64_t cap, int64_t *len);
 
 /*
- * Opt-in timing of the eigensolver's dominant kernel, the symmetric
- * matrix-vector product of the tridiagonal reduction (one launch per column
- * and batch).  While enabled, every such launch is bracketed by two HIP events
- * on its stream and its algorithmic bytes are recorded: the trailing lower
+ * Opt-in timing of the symmetric matrix-vector product of the one-stage
+ * tridiagonal reduction (one launch per column and batch).  While enabled,
+ * every such launch carries two HIP events that the runtime stamps when the
+ * kernel itself starts and ends (hipExtLaunchKernelGGL), so waiting for the
+ * launch is not counted, and its algorithmic bytes are recorded: the trailing lower
  * triangle read once plus the reflector read and the product written,
  * 8 (m (m + 1) / 2 + 2 m) bytes per sector with a trailing order m.
  * tgba_timing_read waits for the recorded events and returns the summed

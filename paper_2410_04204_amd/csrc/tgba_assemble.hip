@@ -738,12 +738,17 @@ __global__ void __launch_bounds__(kThreads) mirror_upper_kernel(const SectorDesc
 template <int ROWS, bool CPLX, int NJ = 0>
 int launch_rows(const SectorDesc *d_desc, int nsec, int64_t nblocks, size_t lds, const Basis *b, double r_max,
                 double scale, int with_diag, int lower, unsigned long long *counters, hipStream_t stream,
-                bool set_attr = true) {
+                bool set_attr = true, hipEvent_t ta = nullptr, hipEvent_t tb = nullptr) {
     auto kern = assemble_rows_kernel<ROWS, CPLX, NJ>;
     if (set_attr && lds > 65536)
         TGBA_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kThreads), lds, stream, d_desc, nsec, b->N, b->d_table, r_max,
-                       b->c0, scale, with_diag, lower, counters);
+    if (ta)
+        hipExtLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kThreads), (std::uint32_t)lds, stream, ta, tb, 0, d_desc,
+                              nsec, b->N, (const double *)b->d_table, r_max, (double)b->c0, scale, with_diag, lower,
+                              counters);
+    else
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kThreads), lds, stream, d_desc, nsec, b->N, b->d_table,
+                           r_max, b->c0, scale, with_diag, lower, counters);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }
@@ -1079,14 +1084,16 @@ int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O
     // hipMemcpyAsync from pageable host memory returns once the data is staged,
     // so the host vectors may go out of scope after this point
     hipEvent_t ta = nullptr, tb = nullptr;
-    if (timing_on() && (rc = timing_begin(stream, &ta, &tb))) return rc;
+    if (timing_on() && (rc = timing_events(&ta, &tb))) return rc;
     rc = (rows == 4)
-             ? launch_rows<4, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream)
-             : launch_rows<2, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream);
+             ? launch_rows<4, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream,
+                                        true, ta, tb)
+             : launch_rows<2, false, 2>(d_desc, (int)ndesc, nblocks, lds, b, 0.0, 1.0, 0, 0, b->d_counters, stream,
+                                        true, ta, tb);
     if (rc) return rc;
     if (ta) {  // channel 2: bytes written by the rows kernel (the two parity blocks of every j)
         const double written = 8.0 * (double)nj * ((double)nn * nn + (double)nr * nr);
-        if ((rc = timing_end(stream, ta, tb, written, 2))) return rc;
+        if ((rc = timing_push(ta, tb, written, 2))) return rc;
     }
     return TGBA_OK;
 }

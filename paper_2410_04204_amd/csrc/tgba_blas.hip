@@ -396,13 +396,13 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
     TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, stream));
     hipEvent_t ta = nullptr, tb = nullptr;
     const bool timed = timing_on();
-    if (timed && (rc = timing_begin(stream, &ta, &tb))) return rc;
+    if (timed && (rc = timing_events(&ta, &tb))) return rc;
     if (narrow)
-        hipLaunchKernelGGL(dgemm_kernel<64>, dim3((unsigned)total), dim3(256), 0, stream, (const GemmDesc *)ws,
-                           (int)descs.size());
+        hipExtLaunchKernelGGL(dgemm_kernel<64>, dim3((unsigned)total), dim3(256), 0, stream, ta, tb, 0,
+                              (const GemmDesc *)ws, (int)descs.size());
     else
-        hipLaunchKernelGGL(dgemm_kernel<TN>, dim3((unsigned)total), dim3(256), 0, stream, (const GemmDesc *)ws,
-                           (int)descs.size());
+        hipExtLaunchKernelGGL(dgemm_kernel<TN>, dim3((unsigned)total), dim3(256), 0, stream, ta, tb, 0,
+                              (const GemmDesc *)ws, (int)descs.size());
     if (timed) {
         // algorithmic flops: the stored triangle of a lower-only update, the stored
         // triangle of a masked (symmetric) operand, else the full product
@@ -413,7 +413,7 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
             else if (g.amask) fl += 2.0 * N * (g.amask == 1 ? M * (M + 1.0) / 2.0 : M * (M - 1.0) / 2.0);
             else fl += 2.0 * M * N * K;
         }
-        if ((rc = timing_end(stream, ta, tb, fl, 1))) return rc;
+        if ((rc = timing_push(ta, tb, fl, 1))) return rc;
     }
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;

@@ -635,16 +635,16 @@ __global__ void sym_avg_kernel(double *S, int64_t lds, int64_t k) {
 // the items of all active sectors (capped), each workgroup striding through them.
 template <typename T>
 static int launch_symv(int cand, TriSecT<T> *d_secs, const std::vector<TriSecT<T>> &sorted, int actr, int c, int i,
-                       int j0, hipStream_t st) {
+                       int j0, hipStream_t st, hipEvent_t ta = nullptr, hipEvent_t tb = nullptr) {
     if (actr > kSymvMaxSecs) return set_error(TGBA_EUNSUPPORTED, "more than 255 sectors in one batched reduction");
     int64_t items = 0;
     for (int k = 0; k < actr; ++k) items += symv_items(sorted[k].n, c, i);
     if (items == 0) return TGBA_OK;
     const unsigned grid = (unsigned)std::min<int64_t>(items, kSymvGrid[cand % 3]);
     if (cand / 3 == 0)
-        hipLaunchKernelGGL((tri_symv<T, 2>), dim3(grid), dim3(256), 0, st, d_secs, actr, c, i, j0);
+        hipExtLaunchKernelGGL((tri_symv<T, 2>), dim3(grid), dim3(256), 0, st, ta, tb, 0, d_secs, actr, c, i, j0);
     else
-        hipLaunchKernelGGL((tri_symv<T, 3>), dim3(grid), dim3(256), 0, st, d_secs, actr, c, i, j0);
+        hipExtLaunchKernelGGL((tri_symv<T, 3>), dim3(grid), dim3(256), 0, st, ta, tb, 0, d_secs, actr, c, i, j0);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }
@@ -700,15 +700,15 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
                 }
                 hipEvent_t ta = nullptr, tb = nullptr;
                 const bool timed = timing_on();
-                if (timed && (rc = timing_begin(stream, &ta, &tb))) return rc;
-                if ((rc = launch_symv<T>(symv_pick, d_secs, sorted, actr, (int)c, i, (int)j0, stream))) return rc;
+                if (timed && (rc = timing_events(&ta, &tb))) return rc;
+                if ((rc = launch_symv<T>(symv_pick, d_secs, sorted, actr, (int)c, i, (int)j0, stream, ta, tb))) return rc;
                 if (timed) {
                     double bytes = 0.0;
                     for (int k = 0; k < actr; ++k) {
                         const double m = (double)(sorted[k].n - c - 1);
                         bytes += (double)sizeof(T) * (m * (m + 1.0) / 2.0 + 2.0 * m);
                     }
-                    if ((rc = timing_end(stream, ta, tb, bytes))) return rc;
+                    if ((rc = timing_push(ta, tb, bytes))) return rc;
                 }
                 const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nmax - c - 1 + 63) / 64));
                 hipLaunchKernelGGL(tri_w<T>, dim3(actr * nblk), dim3(64 * kWGroups), 0, stream, d_secs, (int)c, i, (int)j0,

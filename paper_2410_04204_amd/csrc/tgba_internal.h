@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -78,11 +79,14 @@ int autotune(const std::string &key, int ncand, int fallback, const std::functio
 // True when autotune(key, ...) would run nothing (tuning off or key decided).
 bool autotune_known(const std::string &key);
 
-// Opt-in event timing (tgba_timing_enable): bracket one launch with two events
-// from a recycled pool and record its algorithmic bytes.
+// Opt-in event timing (tgba_timing_enable): two events from a recycled pool,
+// handed to hipExtLaunchKernelGGL so that they are stamped when the kernel
+// itself starts and ends (not when the stream reaches them, which would count
+// the time the GPU waits for the launch), then recorded with the launch's
+// algorithmic units.
 bool timing_on();
-int timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b);
-int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double units, int ch = 0);
+int timing_events(hipEvent_t *a, hipEvent_t *b);
+int timing_push(hipEvent_t a, hipEvent_t b, double units, int ch = 0);
 
 }  // namespace tgba
 

@@ -88,7 +88,7 @@ std::vector<hipEvent_t> g_pool;
 
 bool timing_on() { return g_timing; }
 
-int timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b) {
+int timing_events(hipEvent_t *a, hipEvent_t *b) {
     std::lock_guard<std::mutex> lk(g_tmu);
     for (hipEvent_t *e : {a, b}) {
         if (!g_pool.empty()) {
@@ -98,12 +98,10 @@ int timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b) {
             TGBA_HIP(hipEventCreate(e));
         }
     }
-    TGBA_HIP(hipEventRecord(*a, st));
     return TGBA_OK;
 }
 
-int timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b, double units, int ch) {
-    TGBA_HIP(hipEventRecord(b, st));
+int timing_push(hipEvent_t a, hipEvent_t b, double units, int ch) {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_pending.push_back(Timed{a, b, units, ch});
     return TGBA_OK;
