@@ -23,7 +23,7 @@ struct GemmDesc {
     int64_t tiles_m;    // filled by dgemm_batched
     int64_t first_tile; // filled by dgemm_batched
     // optional second part of the product: C = alpha (op(A) op(B) + op(A2) op(B2)) + beta C,
-    // op(A2) M x K2, op(B2) K2 x N, same transposition flags; K must be a multiple of 16
+    // op(A2) M x K2, op(B2) K2 x N, same transposition flags; K must be a multiple of 32
     const double *A2 = nullptr;
     int64_t lda2 = 0;
     const double *B2 = nullptr;

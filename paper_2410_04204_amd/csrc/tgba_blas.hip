@@ -5,7 +5,8 @@
 //   C = alpha op(A) op(B) + beta C     (column-major, op = N or T)
 //
 // Tiles of 128 x 128 per workgroup (4 waves, each a 64 x 64 sub-tile made of
-// 4 x 4 blocks of 16 x 16), K staged through LDS in steps of 16.  Lane layout
+// 4 x 4 blocks of 16 x 16), K staged through LDS in steps of 32 (FP64) or 16
+// (FP32).  Lane layout
 // of v_mfma_f64_16x16x4: operand a of lane l is A[l%16][l/16], operand b is
 // B[l/16][l%16], and the 4 accumulator registers r hold D[4r + l/16][l%16].
 // Each block is computed transposed, D = B^T A^T (the B fragment as operand a,
@@ -30,6 +31,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 128, TN = 128, TK = 16, LDS_STRIDE = TM + 4;
+constexpr int TKD = 32;  // K-tile depth of the FP64 kernel
 // TNV: output-tile width, 128, or 64 for products with N <= 64 (panel products)
 
 __device__ __forceinline__ int gemm_desc_of(const GemmDesc *d, int nd, int64_t blk) {
@@ -51,12 +53,12 @@ __device__ __forceinline__ double op_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff,
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
-// One K-tile (16) of op(A) (128 x 16) and op(B) (16 x 128) into registers:
-// thread t holds 8 values of each.  Entries with k >= K are zeroed explicitly;
+// One K-tile (32) of op(A) (128 x 32) and op(B) (32 x TNV) into registers:
+// thread t holds 16 values of A and TNV / 8 of B.  Entries with k >= K are zeroed explicitly;
 // rows/columns beyond M/N only feed outputs that are never stored, and reads
 // beyond an operand's extent return 0, so no access leaves the operands.
 struct TileRegs {
-    double a[8], b[8];
+    double a[16], b[16];
 };
 
 template <int TNV>
@@ -85,32 +87,32 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
         const int i = tid & 127, kq = tid >> 7;
         const uint32_t voff = (uint32_t)i * 8u + (uint32_t)kq * la;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < 16; ++s) {
             const double x = op_ld(rs, voff, (uint32_t)(2 * s) * la);
             const int64_t k = k0 + kq + 2 * s;  // storage (m0 + i, k)
             r.a[s] = (k < G.K && (!mask || m0 + i - k >= moff)) ? x : 0.0;
         }
-    } else {  // op(A)[i][k] = A[k + i lda]; k = tid & 15, i = (tid >> 4) + 16 s
+    } else {  // op(A)[i][k] = A[k + i lda]; k = tid & 31, i = (tid >> 5) + 8 s
         const double *base = G.A + k0 + m0 * G.lda;
         const auto rs = op_rsrc(base, ((G.K - k0) + (G.M - 1 - m0) * G.lda) * (int64_t)sizeof(double));
-        const int k = tid & 15, iq = tid >> 4;
+        const int k = tid & 31, iq = tid >> 5;
         const uint32_t voff = (uint32_t)k * 8u + (uint32_t)iq * la;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const double x = op_ld(rs, voff, (uint32_t)(16 * s) * la);
-            const int64_t ii = m0 + iq + 16 * s;  // storage (k0 + k, ii)
+        for (int s = 0; s < 16; ++s) {
+            const double x = op_ld(rs, voff, (uint32_t)(8 * s) * la);
+            const int64_t ii = m0 + iq + 8 * s;  // storage (k0 + k, ii)
             r.a[s] = (k0 + k < G.K && (!mask || k0 + k - ii >= moff)) ? x : 0.0;
         }
     }
-    constexpr int NS = TNV / 16, KST = 256 / TNV;  // B values per thread; k stride of the transposed load
-    if (!G.transB) {  // op(B)[k][j] = B[k + j ldb]; k = tid & 15, j = (tid >> 4) + 16 s
+    constexpr int NS = TNV / 8, KST = 256 / TNV;  // B values per thread; k stride of the transposed load
+    if (!G.transB) {  // op(B)[k][j] = B[k + j ldb]; k = tid & 31, j = (tid >> 5) + 8 s
         const double *base = G.B + k0 + n0 * G.ldb;
         const auto rs = op_rsrc(base, ((G.K - k0) + (G.N - 1 - n0) * G.ldb) * (int64_t)sizeof(double));
-        const int k = tid & 15, jq = tid >> 4;
+        const int k = tid & 31, jq = tid >> 5;
         const uint32_t voff = (uint32_t)k * 8u + (uint32_t)jq * lb;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double x = op_ld(rs, voff, (uint32_t)(16 * s) * lb);
+            const double x = op_ld(rs, voff, (uint32_t)(8 * s) * lb);
             r.b[s] = (k0 + k < G.K) ? x : 0.0;
         }
     } else {  // op(B)[k][j] = B[j + k ldb]; j = tid % TNV, k = tid / TNV + KST s
@@ -129,17 +131,17 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
 template <int TNV>
 __device__ __forceinline__ void store_tile(const GemmDesc &G, int tid, const TileRegs &r, double (*As)[LDS_STRIDE],
                                            double (*Bs)[TNV + 4]) {
-    constexpr int NS = TNV / 16, KST = 256 / TNV;
+    constexpr int NS = TNV / 8, KST = 256 / TNV;
     if (!G.transA) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) As[(tid >> 7) + 2 * s][tid & 127] = r.a[s];
+        for (int s = 0; s < 16; ++s) As[(tid >> 7) + 2 * s][tid & 127] = r.a[s];
     } else {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) As[tid & 15][(tid >> 4) + 16 * s] = r.a[s];
+        for (int s = 0; s < 16; ++s) As[tid & 31][(tid >> 5) + 8 * s] = r.a[s];
     }
     if (!G.transB) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) Bs[tid & 15][(tid >> 4) + 16 * s] = r.b[s];
+        for (int s = 0; s < NS; ++s) Bs[tid & 31][(tid >> 5) + 8 * s] = r.b[s];
     } else {
 #pragma unroll
         for (int s = 0; s < NS; ++s) Bs[tid / TNV + KST * s][tid & (TNV - 1)] = r.b[s];
@@ -155,8 +157,8 @@ template <int TNV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
     constexpr int WN = TNV / 2, NB = WN / 16;
-    __shared__ double As[TK][LDS_STRIDE];  // As[k][i]
-    __shared__ double Bs[TK][TNV + 4];     // Bs[k][j]
+    __shared__ double As[TKD][LDS_STRIDE];  // As[k][i]
+    __shared__ double Bs[TKD][TNV + 4];     // Bs[k][j]
     const GemmDesc G = descs[gemm_desc_of(descs, nd, blockIdx.x)];
     const int64_t tl = blockIdx.x - G.first_tile;
     const int64_t kc = tl / G.ntile, t = tl - kc * G.ntile;
@@ -187,20 +189,20 @@ dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
         if (G.amask && !G.transA) kend = min(kend, m0 + TM - moff);  // needs k <= i - moff
         if (G.amask && G.transA) kbeg = max(kbeg, m0 + moff);        // needs k >= i + moff
         if (G.Cpart) {
-            const int64_t Kc = ((G.K + G.ksplit - 1) / G.ksplit + TK - 1) / TK * TK;
+            const int64_t Kc = ((G.K + G.ksplit - 1) / G.ksplit + TKD - 1) / TKD * TKD;
             kbeg = max(kbeg, kc * Kc);
             kend = min(kend, (kc + 1) * Kc);
         }
         kstop = kend;
     }
     if (kbeg < kstop) load_tile<TNV>(G, m0, n0, kbeg, kend, tid, r);
-    for (int64_t k0 = kbeg; k0 < kstop; k0 += TK) {
+    for (int64_t k0 = kbeg; k0 < kstop; k0 += TKD) {
         __syncthreads();  // the previous tile's readers are done
         store_tile<TNV>(G, tid, r, As, Bs);
         __syncthreads();
-        if (k0 + TK < kstop) load_tile<TNV>(G, m0, n0, k0 + TK, kend, tid, r);
+        if (k0 + TKD < kstop) load_tile<TNV>(G, m0, n0, k0 + TKD, kend, tid, r);
 #pragma unroll
-        for (int kk = 0; kk < TK; kk += 4) {
+        for (int kk = 0; kk < TKD; kk += 4) {
             double af[4], bf[NB];
 #pragma unroll
             for (int a = 0; a < 4; ++a) af[a] = As[kk + (lane >> 4)][64 * wy + 16 * a + (lane & 15)];
@@ -384,6 +386,8 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
         if (g.ksplit < 1) g.ksplit = 1;
         if ((g.ksplit > 1 && !g.Cpart) || (g.Cpart && (g.lower || g.K2)) || (g.amask && g.K2))
             return set_error(TGBA_EINVAL, "split or masked product with unsupported options");
+        if (g.K2 && (g.K % TKD))  // the second part starts at a K-tile boundary
+            return set_error(TGBA_EINVAL, "two-part product: the first part's K must be a multiple of 32");
         g.tiles_m = (g.M + TM - 1) / TM;
         g.first_tile = total;
         g.ntile = gemm_tiles(g, tnv);
