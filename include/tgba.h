@@ -229,6 +229,24 @@ int tgba_assemble_corr(const tgba_basis *basis, int K, int nj, const int *js, do
                        void *stream);
 
 /*
+ * Host utilities behind tgba_assemble_corr (no device memory, no GPU needed),
+ * exposed so that the real form of the correlator tables can be checked on
+ * the CPU.  tgba_corr_table writes the table of sigma^x_1 sigma^x_{j+1} in
+ * parity sector `sector` (0 NS, 1 R) at transverse field h_perp >= 0 to tab
+ * (host, (2N + 2)^2 doubles, row-major, indices [bra 0..N-1 (mode N-1-i),
+ * ket N..2N-1 (mode a), kept Majorana pair 2N, 2N+1]), its prefactor, its
+ * max |entry| and the relative imaginary residual of the real form.  An
+ * element between states a, b of one momentum sector is then
+ *   fac * sign_a * sign_b * Pf(tab[J u I_a u I_b])
+ * with J = (2N, 2N+1), I_a the bra indices ascending, I_b the ket indices
+ * ascending; tgba_corr_signs writes sign_x for `count` masks (host arrays).
+ * Errors: TGBA_EINVAL, TGBA_ENUMERIC.
+ */
+int tgba_corr_table(int N, double h_perp, int sector, int j, double *tab, double *fac, double *rmax,
+                    double *residual);
+int tgba_corr_signs(int N, int sector, int j, int64_t count, const uint64_t *masks, double *signs);
+
+/*
  * Assembly plan: the launches of one batched assembly (the same arguments as
  * tgba_assemble_heff_batched) captured once into a hipGraph whose nodes are
  * kernels only; the sector descriptors live in device memory the plan owns.

@@ -15,7 +15,7 @@ from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONEST
                    TGBA_LOWER, TgbaError)
 
 __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "assemble_corr",
-           "quench_corr", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
+           "quench_corr", "corr_table", "corr_signs", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
            "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
@@ -285,6 +285,24 @@ def assemble_corr(basis, K, js, Os, stream=None):
     _lib.check(_lib.load().tgba_assemble_corr(basis.handle, int(K), int(k), _lib.ptr(js), op, _lib.ptr(lds),
                                               _lib.stream_handle(stream)))
     return Os
+
+
+def corr_table(N, h_perp, sector, j):
+    """Host table of the correlator string (tgba_corr_table): (tab (2N+2, 2N+2), fac, rmax, residual)."""
+    n = 2 * N + 2
+    tab = np.zeros((n, n))
+    fac, rmax, res = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().tgba_corr_table(int(N), float(h_perp), int(sector), int(j), _lib.ptr(tab),
+                                           ctypes.byref(fac), ctypes.byref(rmax), ctypes.byref(res)))
+    return tab, fac.value, rmax.value, res.value
+
+
+def corr_signs(N, sector, j, masks):
+    """Per-state signs of the real-gauge correlator elements (tgba_corr_signs)."""
+    m = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
+    out = np.zeros(m.size)
+    _lib.check(_lib.load().tgba_corr_signs(int(N), int(sector), int(j), int(m.size), _lib.ptr(m), _lib.ptr(out)))
+    return out
 
 
 def quench_corr(Z, w, c, t0, dt, nt, Os, out, sx=None, stream=None):

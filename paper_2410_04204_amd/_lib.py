@@ -28,6 +28,7 @@ EXPORTS = [
     "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
     "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free", "tgba_quench_weights",
     "tgba_assemble_cross", "tgba_dsf_cross", "tgba_assemble_corr", "tgba_quench_corr",
+    "tgba_corr_table", "tgba_corr_signs",
 ]
 
 
@@ -94,6 +95,8 @@ def load():
     L.tgba_autotune_enable.argtypes = [c_int]
     L.tgba_assemble_cross.argtypes = [c_void_p, c_int, c_int, c_void_p, c_int64, c_void_p]
     L.tgba_assemble_corr.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_corr_table.argtypes = [c_int, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.tgba_corr_signs.argtypes = [c_int, c_int, c_int, c_int64, c_void_p, c_void_p]
     L.tgba_quench_corr.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_double, c_double, c_int, c_int,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.tgba_dsf_cross.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64,

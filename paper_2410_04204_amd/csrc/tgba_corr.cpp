@@ -36,6 +36,7 @@
 // fac = (product of the eliminated pivots, with the signs of the swaps) / det L,
 // with bounded entries (the small pivot stays inside each element's Pfaffian,
 // where the assembly kernel treats it like a nearly singular bra block).
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -241,3 +242,33 @@ double corr_sign(const Basis *b, int sector, int j, uint64_t mask) {
 }
 
 }  // namespace tgba
+
+extern "C" int tgba_corr_table(int N, double h_perp, int sector, int j, double *tab, double *fac, double *rmax,
+                               double *residual) {
+    tgba::clear_error();
+    if (N < 2 || N > tgba::kMaxN || (N & 1)) return tgba::set_error(TGBA_EINVAL, "N must be even, 2 <= N <= 64");
+    if (!(h_perp >= 0.0) || !std::isfinite(h_perp)) return tgba::set_error(TGBA_EINVAL, "h_perp must be >= 0");
+    if (sector != 0 && sector != 1) return tgba::set_error(TGBA_EINVAL, "sector must be 0 (NS) or 1 (R)");
+    if (!tab || !fac || !rmax || !residual) return tgba::set_error(TGBA_EINVAL, "NULL output");
+    tgba::Basis b;
+    b.N = N;
+    b.h_perp = h_perp;
+    tgba::mode_tables(N, h_perp, b.k, b.eps, b.th);
+    std::vector<double> t;
+    const int rc = tgba::corr_table(&b, sector, j, t, *fac, *rmax, *residual);
+    if (rc) return rc;
+    std::copy(t.begin(), t.end(), tab);
+    return TGBA_OK;
+}
+
+extern "C" int tgba_corr_signs(int N, int sector, int j, int64_t count, const uint64_t *masks, double *signs) {
+    tgba::clear_error();
+    if (N < 2 || N > tgba::kMaxN || (N & 1) || (sector != 0 && sector != 1) || j < 1 || j > N - 1 || count < 0 ||
+        (count > 0 && (!masks || !signs)))
+        return tgba::set_error(TGBA_EINVAL, "bad arguments");
+    tgba::Basis b;
+    b.N = N;
+    for (int64_t a = 0; a < count; ++a) signs[a] = tgba::corr_sign(&b, sector, j, masks[a]);
+    return TGBA_OK;
+}
+
