@@ -45,18 +45,29 @@ __device__ __forceinline__ int gemm_desc_of(const GemmDesc *d, int nd, int64_t b
 
 // Raw buffer access: base = first element of the operand tile, `bytes` = how far
 // the operand extends from there (clamped to 32 bits); reads past it return 0.
+// The base and extent are the same for every lane of the workgroup (they depend
+// on the descriptor, the tile origin and the K offset only); reading them from
+// the first lane keeps the resource in scalar registers.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t op_rsrc(const double *base, int64_t bytes) {
     const int nrec = (int)(uint32_t)(bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes));
-    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nrec, 0x00020000);
+    const uint64_t b = (uint64_t)base;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(lo | (hi << 32)), (short)0, __builtin_amdgcn_readfirstlane(nrec),
+                                             0x00020000);
 }
 __device__ __forceinline__ double op_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
 // One K-tile (32) of op(A) (128 x 32) and op(B) (32 x TNV) into registers:
-// thread t holds 16 values of A and TNV / 8 of B.  Entries with k >= K are zeroed explicitly;
-// rows/columns beyond M/N only feed outputs that are never stored, and reads
-// beyond an operand's extent return 0, so no access leaves the operands.
+// thread t holds 16 values of A and TNV / 8 of B.  The loads are issued
+// unconditionally; entries with k >= K (or outside the stored triangle of a
+// masked operand) are zeroed by mask_tile just before the tile is written to
+// LDS, so that no select on a loaded value sits between the loads and the
+// matrix-core work that hides their latency.  Rows/columns beyond M/N only feed
+// outputs that are never stored, and reads beyond an operand's extent return 0,
+// so no access leaves the operands.
 struct TileRegs {
     double a[16], b[16];
 };
@@ -69,10 +80,7 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
     GemmDesc G = G0;
     int64_t k0 = kt;
     G.K = kend;
-    const int moff = G0.amask == 2 ? 1 : 0;
-    bool mask = G0.amask != 0;
     if (kt >= G0.K) {
-        mask = false;
         G.A = G0.A2;
         G.lda = G0.lda2;
         G.B = G0.B2;
@@ -88,9 +96,7 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
         const uint32_t voff = (uint32_t)i * 8u + (uint32_t)kq * la;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const double x = op_ld(rs, voff, (uint32_t)(2 * s) * la);
-            const int64_t k = k0 + kq + 2 * s;  // storage (m0 + i, k)
-            r.a[s] = (k < G.K && (!mask || m0 + i - k >= moff)) ? x : 0.0;
+            r.a[s] = op_ld(rs, voff, (uint32_t)(2 * s) * la);  // storage (m0 + i, k0 + kq + 2 s)
         }
     } else {  // op(A)[i][k] = A[k + i lda]; k = tid & 31, i = (tid >> 5) + 8 s
         const double *base = G.A + k0 + m0 * G.lda;
@@ -99,9 +105,7 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
         const uint32_t voff = (uint32_t)k * 8u + (uint32_t)iq * la;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const double x = op_ld(rs, voff, (uint32_t)(8 * s) * la);
-            const int64_t ii = m0 + iq + 8 * s;  // storage (k0 + k, ii)
-            r.a[s] = (k0 + k < G.K && (!mask || k0 + k - ii >= moff)) ? x : 0.0;
+            r.a[s] = op_ld(rs, voff, (uint32_t)(8 * s) * la);  // storage (k0 + k, m0 + iq + 8 s)
         }
     }
     constexpr int NS = TNV / 8, KST = 256 / TNV;  // B values per thread; k stride of the transposed load
@@ -111,20 +115,57 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
         const int k = tid & 31, jq = tid >> 5;
         const uint32_t voff = (uint32_t)k * 8u + (uint32_t)jq * lb;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const double x = op_ld(rs, voff, (uint32_t)(8 * s) * lb);
-            r.b[s] = (k0 + k < G.K) ? x : 0.0;
-        }
+        for (int s = 0; s < NS; ++s) r.b[s] = op_ld(rs, voff, (uint32_t)(8 * s) * lb);
     } else {  // op(B)[k][j] = B[j + k ldb]; j = tid % TNV, k = tid / TNV + KST s
         const double *base = G.B + n0 + k0 * G.ldb;
         const auto rs = op_rsrc(base, ((G.N - n0) + (G.K - 1 - k0) * G.ldb) * (int64_t)sizeof(double));
         const int j = tid & (TNV - 1), kq = tid / TNV;
         const uint32_t voff = (uint32_t)j * 8u + (uint32_t)kq * lb;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const double x = op_ld(rs, voff, (uint32_t)(KST * s) * lb);
-            r.b[s] = (k0 + kq + KST * s < G.K) ? x : 0.0;
+        for (int s = 0; s < NS; ++s) r.b[s] = op_ld(rs, voff, (uint32_t)(KST * s) * lb);
+    }
+}
+
+// Zeroes the entries of a loaded K-tile (the one load_tile read at kt) that lie
+// at k >= K of their part (or at or beyond kend in the first part) or, for a
+// masked operand, outside its stored triangle.  A tile inside K with no
+// triangle, the common case, returns at once (a decision uniform over the
+// workgroup).
+template <int TNV>
+__device__ __forceinline__ void mask_tile(const GemmDesc &G, int64_t m0, int64_t kt, int64_t kend, int tid, TileRegs &r) {
+    int64_t k0 = kt, K = kend;
+    const int moff = G.amask == 2 ? 1 : 0;
+    bool mask = G.amask != 0;
+    if (kt >= G.K) {
+        mask = false;
+        K = G.K2;
+        k0 = kt - G.K;
+    }
+    if (!mask && k0 + TKD <= K) return;
+    if (!G.transA) {
+        const int64_t i = m0 + (tid & 127), kq = k0 + (tid >> 7);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int64_t k = kq + 2 * s;
+            if (!(k < K && (!mask || i - k >= moff))) r.a[s] = 0.0;
         }
+    } else {
+        const int64_t k = k0 + (tid & 31), iq = m0 + (tid >> 5);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            if (!(k < K && (!mask || k - (iq + 8 * s) >= moff))) r.a[s] = 0.0;
+    }
+    constexpr int NS = TNV / 8, KST = 256 / TNV;
+    if (!G.transB) {
+        const bool keep = k0 + (tid & 31) < K;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (!keep) r.b[s] = 0.0;
+    } else {
+        const int64_t kq = k0 + tid / TNV;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (!(kq + KST * s < K)) r.b[s] = 0.0;
     }
 }
 
@@ -198,6 +239,7 @@ dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
     if (kbeg < kstop) load_tile<TNV>(G, m0, n0, kbeg, kend, tid, r);
     for (int64_t k0 = kbeg; k0 < kstop; k0 += TKD) {
         __syncthreads();  // the previous tile's readers are done
+        mask_tile<TNV>(G, m0, k0, kend, tid, r);
         store_tile<TNV>(G, tid, r, As, Bs);
         __syncthreads();
         if (k0 + TKD < kstop) load_tile<TNV>(G, m0, n0, k0 + TKD, kend, tid, r);
