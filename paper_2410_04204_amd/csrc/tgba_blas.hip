@@ -306,9 +306,104 @@ __device__ __forceinline__ int sgemm_desc_of(const SGemmDesc *d, int nd, int64_t
     return lo;
 }
 
+constexpr int TKS = 32;  // K-tile depth of the FP32 kernel
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t op_rsrc_f(const float *base, int64_t elems) {
+    const int64_t bytes = elems * (int64_t)sizeof(float);
+    const int nrec = (int)(uint32_t)(bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes));
+    const uint64_t b = (uint64_t)base;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(lo | (hi << 32)), (short)0, __builtin_amdgcn_readfirstlane(nrec),
+                                             0x00020000);
+}
+__device__ __forceinline__ float op_ld_f(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// One K-tile (32) of op(A) (128 x 32) and op(B) (32 x 128): 16 values of each per
+// thread, loaded unconditionally (reads beyond an operand's extent return 0;
+// rows/columns beyond M/N only feed outputs that are never stored).  Entries
+// with k >= K are zeroed by smask_tile when the tile is written to LDS, so the
+// loads stay in flight through the previous tile's matrix-core work.
+struct STileRegs {
+    float a[16], b[16];
+};
+
+__device__ __forceinline__ void sload_tile(const SGemmDesc &G, int64_t m0, int64_t n0, int64_t k0, int tid,
+                                           STileRegs &r) {
+    const uint32_t la = (uint32_t)(G.lda * (int64_t)sizeof(float)), lb = (uint32_t)(G.ldb * (int64_t)sizeof(float));
+    if (!G.transA) {  // op(A)[i][k] = A[i + k lda]; i = tid & 127, k = (tid >> 7) + 2 s
+        const auto rs = op_rsrc_f(G.A + m0 + k0 * G.lda, (G.M - m0) + (G.K - 1 - k0) * G.lda);
+        const uint32_t voff = (uint32_t)(tid & 127) * 4u + (uint32_t)(tid >> 7) * la;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) r.a[s] = op_ld_f(rs, voff, (uint32_t)(2 * s) * la);
+    } else {  // op(A)[i][k] = A[k + i lda]; k = tid & 31, i = (tid >> 5) + 8 s
+        const auto rs = op_rsrc_f(G.A + k0 + m0 * G.lda, (G.K - k0) + (G.M - 1 - m0) * G.lda);
+        const uint32_t voff = (uint32_t)(tid & 31) * 4u + (uint32_t)(tid >> 5) * la;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) r.a[s] = op_ld_f(rs, voff, (uint32_t)(8 * s) * la);
+    }
+    if (!G.transB) {  // op(B)[k][j] = B[k + j ldb]; k = tid & 31, j = (tid >> 5) + 8 s
+        const auto rs = op_rsrc_f(G.B + k0 + n0 * G.ldb, (G.K - k0) + (G.N - 1 - n0) * G.ldb);
+        const uint32_t voff = (uint32_t)(tid & 31) * 4u + (uint32_t)(tid >> 5) * lb;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) r.b[s] = op_ld_f(rs, voff, (uint32_t)(8 * s) * lb);
+    } else {  // op(B)[k][j] = B[j + k ldb]; j = tid & 127, k = (tid >> 7) + 2 s
+        const auto rs = op_rsrc_f(G.B + n0 + k0 * G.ldb, (G.N - n0) + (G.K - 1 - k0) * G.ldb);
+        const uint32_t voff = (uint32_t)(tid & 127) * 4u + (uint32_t)(tid >> 7) * lb;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) r.b[s] = op_ld_f(rs, voff, (uint32_t)(2 * s) * lb);
+    }
+}
+
+__device__ __forceinline__ void smask_tile(const SGemmDesc &G, int64_t k0, int tid, STileRegs &r) {
+    if (k0 + TKS <= G.K) return;  // interior tile (uniform over the workgroup)
+    if (!G.transA) {
+        const int64_t kq = k0 + (tid >> 7);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            if (!(kq + 2 * s < G.K)) r.a[s] = 0.0f;
+    } else {
+        const bool keep = k0 + (tid & 31) < G.K;
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            if (!keep) r.a[s] = 0.0f;
+    }
+    if (!G.transB) {
+        const bool keep = k0 + (tid & 31) < G.K;
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            if (!keep) r.b[s] = 0.0f;
+    } else {
+        const int64_t kq = k0 + (tid >> 7);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            if (!(kq + 2 * s < G.K)) r.b[s] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ void sstore_tile(const SGemmDesc &G, int tid, const STileRegs &r, float (*As)[LDS_STRIDE],
+                                            float (*Bs)[LDS_STRIDE]) {
+    if (!G.transA) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) As[(tid >> 7) + 2 * s][tid & 127] = r.a[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) As[tid & 31][(tid >> 5) + 8 * s] = r.a[s];
+    }
+    if (!G.transB) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) Bs[tid & 31][(tid >> 5) + 8 * s] = r.b[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) Bs[(tid >> 7) + 2 * s][tid & 127] = r.b[s];
+    }
+}
+
 __global__ void __launch_bounds__(256) sgemm_kernel(const SGemmDesc *__restrict__ descs, int nd) {
-    __shared__ float As[TK][LDS_STRIDE];
-    __shared__ float Bs[TK][LDS_STRIDE];
+    __shared__ float As[TKS][LDS_STRIDE];  // As[k][i]
+    __shared__ float Bs[TKS][LDS_STRIDE];  // Bs[k][j]
     const SGemmDesc G = descs[sgemm_desc_of(descs, nd, blockIdx.x)];
     const int64_t t = blockIdx.x - G.first_tile;
     int64_t ti, tj;
@@ -329,40 +424,16 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SGemmDesc *__restrict_
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
-    for (int64_t k0 = 0; k0 < G.K; k0 += TK) {
-        if (!G.transA) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int i = tid & 127, k = (tid >> 7) + 2 * s;
-                const int64_t gi = m0 + i, gk = k0 + k;
-                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gi + gk * G.lda] : 0.0f;
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int k = tid & 15, i = (tid >> 4) + 16 * s;
-                const int64_t gi = m0 + i, gk = k0 + k;
-                As[k][i] = (gi < G.M && gk < G.K) ? G.A[gk + gi * G.lda] : 0.0f;
-            }
-        }
-        if (!G.transB) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int k = tid & 15, j = (tid >> 4) + 16 * s;
-                const int64_t gj = n0 + j, gk = k0 + k;
-                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gk + gj * G.ldb] : 0.0f;
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int j = tid & 127, k = (tid >> 7) + 2 * s;
-                const int64_t gj = n0 + j, gk = k0 + k;
-                Bs[k][j] = (gj < G.N && gk < G.K) ? G.B[gj + gk * G.ldb] : 0.0f;
-            }
-        }
+    STileRegs r;
+    if (G.K > 0) sload_tile(G, m0, n0, 0, tid, r);
+    for (int64_t k0 = 0; k0 < G.K; k0 += TKS) {
+        __syncthreads();  // the previous tile's readers are done
+        smask_tile(G, k0, tid, r);
+        sstore_tile(G, tid, r, As, Bs);
         __syncthreads();
+        if (k0 + TKS < G.K) sload_tile(G, m0, n0, k0 + TKS, tid, r);
 #pragma unroll
-        for (int kk = 0; kk < TK; kk += 2) {
+        for (int kk = 0; kk < TKS; kk += 2) {
             float af[2], bf[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) af[a] = As[kk + (lane >> 5)][64 * wy + 32 * a + (lane & 31)];
@@ -373,7 +444,6 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SGemmDesc *__restrict_
 #pragma unroll
                 for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
