@@ -5,9 +5,11 @@
 // read and updated).  For every panel of BW columns j0.. with m = n - j0 - BW
 // rows below it:
 //   * QR of the m x BW panel by Householder reflectors H_q = I - tau_q v_q v_q^T,
-//     column by column (qr_dots: norm and dot products of the column with the
-//     panel in one pass; qr_update: the reflector and its application).  R
-//     stays in the panel as the band's subdiagonal block.
+//     column by column in sub-blocks of SB columns (qr_dots: norm and dot
+//     products of a sub-block's first column in one pass; qr_step: the
+//     reflector of column q, its application, and the next column's norm and
+//     dot products from the updated values).  R stays in the panel as the
+//     band's subdiagonal block.
 //   * compact WY: Q = I - V T V^T (T from the Gram matrix V^T V, larft);
 //   * the two-sided update of the trailing matrix A22 <- Q^T A22 Q as
 //         X = A22 V T,   W = X - 1/2 V (T^T V^T X),   A22 -= V W^T + W V^T,
@@ -54,6 +56,7 @@ constexpr int QP = BW + 1;         // partial sums per block: BW dot products + 
 constexpr int kMaxBandSecs = 256;  // sectors of one call (the step kernel indexes them in LDS)
 constexpr int kStride = 3;         // bulge-chasing schedule: task (i, k) at step kStride i + k
 constexpr int SB = 16;             // columns of a panel-QR sub-block
+constexpr int QB = kQrMaxBlk * QP + BW;  // one partial-sum buffer of the panel QR (column q uses buffer q & 1)
 
 // workspace slots of this file
 constexpr int kSlotSecs = 30, kSlotWork = 31, kSlotParts = 32, kSlotGemm = 33, kSlotRed = 34;
@@ -62,7 +65,7 @@ struct BandSec {
     double *A;
     int64_t lda, n;
     double *tau;    // n
-    double *qpart;  // kQrMaxBlk x QP partial sums, then the panel's top row (BW)
+    double *qpart;  // two buffers of QB doubles: kQrMaxBlk x QP partial sums, then the top row (BW)
     double *V;      // n x BW (ld n): the panel's reflectors, unit lower trapezoidal
     double *X;      // n x BW (ld n)
     double *W;      // n x BW (ld n)
@@ -90,7 +93,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 //
 // One pass over rows q.. of the panel: sum_{r > q} P[r][q]^2 and
 // sum_{r >= q} P[r][q] P[r][j] for q < j < c0 + SB, per block of QCH rows;
-// block 0 also saves row q of the sub-block (read by every block of qr_update).
+// block 0 also saves row q of the sub-block (read by every block of qr_step).
+// Launched for the first column q = c0 of a sub-block (buffer c0 & 1 = 0); the
+// row blocks q + blk QCH are the ones qr_step keeps for the whole sub-block.
 __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict__ secs, int64_t j0, int q, int maxblk) {
     const int s = blockIdx.x / maxblk, blk = blockIdx.x % maxblk;
     const BandSec S = secs[s];
@@ -134,26 +139,36 @@ __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict_
     if (blk == 0 && tid >= q && tid < c1) S.qpart[kQrMaxBlk * QP + tid] = P[q + tid * lda];
 }
 
-// Reflector of column q from the partial sums, then its application to rows
-// q.. of columns q+1.. (and the reflector stored below the diagonal of column q).
-__global__ void __launch_bounds__(256) qr_update_kernel(const BandSec *__restrict__ secs, int64_t j0, int q, int maxblk) {
+// Column q of the sub-block [c0, c0 + SB): the reflector from the partial sums of
+// column q (buffer q & 1, summed by every workgroup), its application to this
+// block's rows >= q of columns q+1 .. c0+SB-1 (and the reflector stored below the
+// diagonal of column q), then -- unless q + 1 ends the sub-block or the sector's
+// reflectors -- column q + 1's partial sums over the same rows from the updated
+// values still in registers, and row q + 1 of the sub-block (buffer (q + 1) & 1).
+// The row blocks c0 + blk QCH are fixed for the sub-block, so a workgroup reads
+// only rows it updates itself; other workgroups' results arrive through the
+// buffers, written in one launch and read in the next.
+__global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict__ secs, int64_t j0, int q, int maxblk) {
     const int s = blockIdx.x / maxblk, blk = blockIdx.x % maxblk;
     const BandSec S = secs[s];
     const int64_t m = S.n - j0 - BW;
     if (m < 2) return;
     const int nref = (int)(m - 1 < BW ? m - 1 : BW);
     if (q >= nref) return;
-    const int64_t nblk = (m - q + QCH - 1) / QCH;
+    const int c0 = q & ~(SB - 1), c1 = c0 + SB;
+    const int64_t nblk = (m - c0 + QCH - 1) / QCH;
     if (blk >= nblk) return;
     double *P = S.A + (j0 + BW) + j0 * S.lda;
     const int64_t lda = S.lda;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double *qin = S.qpart + (q & 1) * QB;
+    double *qout = S.qpart + ((q + 1) & 1) * QB;
     __shared__ double sums[QP], w[BW], par[3];
-    const int c1 = (q & ~(SB - 1)) + SB;
-    const double *top = S.qpart + kQrMaxBlk * QP;
+    __shared__ double red[4][QP];
+    const double *top = qin + kQrMaxBlk * QP;
     if (tid < QP && ((tid > q && tid < c1) || tid == BW)) {
         double a = 0.0;
-        for (int64_t b = 0; b < nblk; ++b) a += S.qpart[b * QP + tid];
+        for (int64_t b = 0; b < nblk; ++b) a += qin[b * QP + tid];
         sums[tid] = a;
     }
     __syncthreads();
@@ -175,18 +190,49 @@ __global__ void __launch_bounds__(256) qr_update_kernel(const BandSec *__restric
     // w_j = v^T P[:, j] = P[q][j] + scale (sum_{r >= q} x_r P[r][j] - alpha P[q][j])
     if (tid > q && tid < c1) w[tid] = top[tid] + scale * (sums[tid] - top[q] * top[tid]);
     __syncthreads();
+    const int qn = q + 1;
+    const bool next = qn < c1 && qn < nref;  // uniform
+    double acc[SB];
+#pragma unroll
+    for (int jj = 0; jj < SB; ++jj) acc[jj] = 0.0;
+    double nrm = 0.0;
     for (int it = 0; it < QCH / 256; ++it) {
-        const int64_t r = q + (int64_t)blk * QCH + it * 256 + tid;
-        if (r >= m) continue;
+        const int64_t r = c0 + (int64_t)blk * QCH + it * 256 + tid;
+        if (r >= m || r < q) continue;
         if (r == q) {
             for (int j = q + 1; j < c1; ++j) P[q + j * lda] -= tau * w[j];
             P[q + q * lda] = beta;
-        } else {
-            const double v = P[r + q * lda] * scale;
-            P[r + q * lda] = v;
-            for (int j = q + 1; j < c1; ++j) P[r + j * lda] -= tau * v * w[j];
+            continue;
+        }
+        const double v = P[r + q * lda] * scale;
+        P[r + q * lda] = v;
+        double x = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < SB; ++jj) {
+            const int j = c0 + jj;
+            if (j > q) {  // uniform
+                const double y = P[r + j * lda] - tau * v * w[j];
+                P[r + j * lda] = y;
+                if (j == qn) x = y;                    // column qn of this row (qn < any later j)
+                if (next && j > qn) acc[jj] += x * y;  // sum_{r >= qn} P[r][qn] P[r][j]
+                if (next && r == qn) qout[kQrMaxBlk * QP + j] = y;  // row qn, read by the next launch
+            }
+        }
+        if (next && r > qn) nrm += x * x;  // sum_{r > qn} P[r][qn]^2
+    }
+    if (!next) return;
+#pragma unroll
+    for (int jj = 0; jj < SB; ++jj) {
+        if (c0 + jj > qn) {  // uniform
+            const double v = wave_sum(acc[jj]);
+            if (lane == 0) red[wave][c0 + jj] = v;
         }
     }
+    nrm = wave_sum(nrm);
+    if (lane == 0) red[wave][BW] = nrm;
+    __syncthreads();
+    double *out = qout + (int64_t)blk * QP;
+    if (tid < QP && ((tid > qn && tid < c1) || tid == BW)) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
 // Columns [c0, c0 + SB) of V (m x BW, ld n): unit lower trapezoidal reflectors
@@ -381,7 +427,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 }  // namespace
 
 size_t band_workspace_doubles(int64_t n) {
-    return (size_t)n * (7 * BW + LDB + 1) + (size_t)kQrMaxBlk * QP + BW + 4 * BW * BW + 64;
+    return (size_t)n * (7 * BW + LDB + 1) + 2 * (size_t)QB + 4 * BW * BW + 64;
 }
 
 namespace {
@@ -433,7 +479,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.X = p; p += (size_t)x.n * BW;
         S.W = p; p += (size_t)x.n * BW;
         S.band = p; p += (size_t)x.n * LDB;
-        S.qpart = p; p += (size_t)kQrMaxBlk * QP + BW;
+        S.qpart = p; p += 2 * (size_t)QB;
         S.S = p; p += BW * BW;
         S.T = p; p += BW * BW;
         S.Y = p; p += BW * BW;
@@ -497,11 +543,13 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         splits(act, j0, sym, gram);
         const int64_t m0 = secs[0].n - j0 - BW;
         for (int c0 = 0; c0 < BW; c0 += SB) {
+            // the sub-block's row blocks c0 + blk QCH (every sector), kept by qr_step
+            const int maxblk = (int)ceil_div(m0 - c0, QCH);
+            if (c0 < m0 - 1)
+                hipLaunchKernelGGL(qr_dots_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, c0, maxblk);
             for (int q = c0; q < c0 + SB; ++q) {
                 if (q >= m0 - 1) break;  // no sector has a reflector q (sector 0 has the most rows)
-                const int maxblk = (int)ceil_div(m0 - q, QCH);
-                hipLaunchKernelGGL(qr_dots_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
-                hipLaunchKernelGGL(qr_update_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
+                hipLaunchKernelGGL(qr_step_kernel, dim3(act * maxblk), dim3(256), 0, stream, d_secs, j0, q, maxblk);
             }
             hipLaunchKernelGGL(extract_panel_v_kernel, dim3(256, act), dim3(256), 0, stream, d_secs, j0, c0);
             TGBA_HIP(hipGetLastError());
