@@ -331,7 +331,11 @@ int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A, const int
  * tgba_stebz: ascending eigenvalues w (n) of the symmetric tridiagonal (d, e)
  *   by bisection on Sturm counts (device arrays).
  * tgba_dgemm: C = alpha op(A) op(B) + beta C, column-major device matrices,
- *   op = transpose when transA/transB != 0 (FP64 matrix cores).
+ *   op = transpose when transA/transB != 0 (FP64 matrix cores).  transA = 2:
+ *   op(A) is the symmetric matrix whose lower triangle A holds (M == K; the
+ *   strict upper triangle of A is never read), the product of the band
+ *   reduction's panel step.  Errors: TGBA_EINVAL (sizes, leading dimensions,
+ *   transA outside 0..2).
  */
 int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *e, double *tau, void *stream);
 /* tgba_sytrd_2stage: a tridiagonal (d: n, e: n-1, device) similar to the

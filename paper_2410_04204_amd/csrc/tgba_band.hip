@@ -13,9 +13,10 @@
 //   * compact WY: Q = I - V T V^T (T from the Gram matrix V^T V, larft);
 //   * the two-sided update of the trailing matrix A22 <- Q^T A22 Q as
 //         X = A22 V T,   W = X - 1/2 V (T^T V^T X),   A22 -= V W^T + W V^T,
-//     all on FP64 MFMA: A22 V from its lower triangle as tril(A22) V +
-//     stril(A22)^T V with K split over workgroups, the update on the lower
-//     tiles only.
+//     all on FP64 MFMA: A22 V from its lower triangle in one pass over K per
+//     output tile (stored entries left of the tile's diagonal block, mirrored
+//     ones right of it; K split over workgroups when the sectors give too few
+//     tiles), the update on the lower tiles only.
 // That reads the trailing matrix once per panel instead of once per column,
 // which is what makes the one-stage reduction HBM bound.
 //
@@ -504,7 +505,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     // K split per sector: enough workgroups for the chip, chunks of >= 512
     auto splits = [&](int act, int64_t j0, std::vector<int> &sym, std::vector<int> &gram) {
         int64_t base = 0;
-        for (int q = 0; q < act; ++q) base += 2 * ceil_div(secs[q].n - j0 - BW, 128);
+        for (int q = 0; q < act; ++q) base += ceil_div(secs[q].n - j0 - BW, 128);
         sym.assign(act, 1);
         gram.assign(act, 1);
         for (int q = 0; q < act; ++q) {
@@ -627,26 +628,24 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         std::vector<GemmDesc> g;
         std::vector<ReduceDesc> red;
         double *pp = parts;
-        // X = A22 V = tril(A22) V + stril(A22)^T V (split K) into X
+        // X = A22 V from the lower triangle of A22 (symmetric operand: one pass over
+        // K per output tile; K split only when the sectors give too few tiles)
         for (int q = 0; q < act; ++q) {
             const BandSec &S = secs[q];
             const int64_t m = S.n - j0 - BW, t0 = j0 + BW;
             const double *A22 = S.A + t0 + t0 * S.lda;
-            GemmDesc G1{A22, S.lda, S.V, S.n, S.X, S.n, m, BW, m, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-            G1.amask = 1;
-            G1.ksplit = sym[q];
-            G1.Cpart = pp;
-            GemmDesc G2 = G1;
-            G2.transA = 1;
-            G2.amask = 2;
-            G2.Cpart = pp + (size_t)sym[q] * m * BW;
-            g.push_back(G1);
-            g.push_back(G2);
-            red.push_back(ReduceDesc{S.X, S.n, m, BW, pp, 2 * sym[q], 0.0, 0});
-            pp += (size_t)2 * sym[q] * m * BW;
+            GemmDesc G{A22, S.lda, S.V, S.n, S.X, S.n, m, BW, m, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+            G.symm = 1;
+            if (sym[q] > 1) {
+                G.ksplit = sym[q];
+                G.Cpart = pp;
+                red.push_back(ReduceDesc{S.X, S.n, m, BW, pp, sym[q], 0.0, 0});
+                pp += (size_t)sym[q] * m * BW;
+            }
+            g.push_back(G);
         }
         if ((rc = dgemm_batched(g, kSlotGemm, stream))) return rc;
-        if ((rc = splitk_reduce(red, kSlotRed, stream))) return rc;
+        if (!red.empty() && (rc = splitk_reduce(red, kSlotRed, stream))) return rc;
         return TGBA_OK;
     };
     // W = X T - 1/2 V (T^T V^T X T) of the panel at j0

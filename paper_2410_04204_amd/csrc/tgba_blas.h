@@ -32,6 +32,10 @@ struct GemmDesc {
     // optional triangular mask of A in its storage coordinates (r, c): 1 keeps r >= c, 2 keeps
     // r > c, entries outside are read as 0 (products with one triangle of a symmetric matrix)
     int amask = 0;
+    // optional symmetric A: op(A) is the symmetric matrix whose lower triangle A stores
+    // (entries (i, k) with i >= k at A[i + k lda], the others mirrored); needs M == K,
+    // no second part, no amask and no lower-only output; transA is ignored
+    int symm = 0;
     // split of K over ksplit workgroups per output tile.  With Cpart set (any ksplit), each
     // writes alpha * (its partial product) to Cpart + kc * M * N (column-major, ld M); C
     // is not touched and a ReduceDesc sums the parts (requires lower == 0 and K2 == 0)

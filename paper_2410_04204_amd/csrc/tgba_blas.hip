@@ -5,8 +5,7 @@
 //   C = alpha op(A) op(B) + beta C     (column-major, op = N or T)
 //
 // Tiles of 128 x 128 per workgroup (4 waves, each a 64 x 64 sub-tile made of
-// 4 x 4 blocks of 16 x 16), K staged through LDS in steps of 32 (FP64) or 16
-// (FP32).  Lane layout
+// 4 x 4 blocks of 16 x 16), K staged through LDS in steps of 32.  Lane layout
 // of v_mfma_f64_16x16x4: operand a of lane l is A[l%16][l/16], operand b is
 // B[l/16][l%16], and the 4 accumulator registers r hold D[4r + l/16][l%16].
 // Each block is computed transposed, D = B^T A^T (the B fragment as operand a,
@@ -17,8 +16,13 @@
 // only elements with i >= j are written (symmetric rank-k updates).  `amask`
 // reads A as one of its triangles (a product with a symmetric matrix stored
 // in its lower triangle is tril(A) B + stril(A)^T B); each output tile then
-// skips the K range that is zero.  `ksplit` divides K over several workgroups
-// per output tile, which write partial products for splitk_reduce.
+// skips the K range that is zero.  `symm` reads A as the whole symmetric matrix
+// its lower triangle stores, in one pass over K per output tile (stored entries
+// left of the tile's diagonal block, mirrored ones right of it): every tile then
+// does the same work, where the two masked halves leave the tiles at one end of
+// each half with the full K and those at the other end with almost none.
+// `ksplit` divides K over several workgroups per output tile, which write
+// partial products for splitk_reduce.
 #include <algorithm>
 #include <cstdint>
 
@@ -72,7 +76,21 @@ struct TileRegs {
     double a[16], b[16];
 };
 
-template <int TNV>
+// Storage order of the K-tile of op(A) at kt for the row tile at m0: 0 = A[i + k lda]
+// (op(A) = A), 1 = A[k + i lda] (op(A) = A^T), 2 = element by element (the
+// K-tiles of a symmetric operand that meet the row tile's diagonal block: the
+// stored lower entry A[i + k lda] for i >= k, its mirror A[k + i lda] above).
+// A symmetric operand reads its stored triangle as is left of the row tile and
+// mirrored right of it.  Uniform over the workgroup.
+template <bool SYM>
+__device__ __forceinline__ int a_order(const GemmDesc &G, int64_t m0, int64_t kt) {
+    if (!SYM || !G.symm) return G.transA;
+    if (kt + TKD <= m0) return 0;
+    if (kt >= m0 + TM) return 1;
+    return 2;
+}
+
+template <int TNV, bool SYM>
 __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_t n0, int64_t kt, int64_t kend, int tid,
                                           TileRegs &r) {
     // tiles with kt >= K come from the second part (A2, B2); the first part is
@@ -89,7 +107,20 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
         k0 = kt - G0.K;
     }
     const uint32_t la = (uint32_t)(G.lda * (int64_t)sizeof(double)), lb = (uint32_t)(G.ldb * (int64_t)sizeof(double));
-    if (!G.transA) {  // op(A)[i][k] = A[i + k lda]; i = tid & 127, k = (tid >> 7) + 2 s
+    const int ord = a_order<SYM>(G0, m0, kt);
+    if (SYM && ord == 2) {  // op(A)[i][k] = A[max(i,k) + min(i,k) lda]; i = tid & 127, k = (tid >> 7) + 2 s
+        // both entries lie in rows and columns >= kb, and i, k < kb + 256 (the
+        // tile spans TM rows and TKD columns within TKD of them): 32-bit offsets
+        const int64_t kb = m0 < k0 ? m0 : k0;
+        const double *base = G.A + kb + kb * G.lda;
+        const auto rs = op_rsrc(base, ((G.M - kb) + (G.M - 1 - kb) * G.lda) * (int64_t)sizeof(double));
+        const uint32_t i = (uint32_t)(m0 - kb) + (uint32_t)(tid & 127), kq = (uint32_t)(k0 - kb) + (uint32_t)(tid >> 7);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const uint32_t k = kq + 2u * s;
+            r.a[s] = op_ld(rs, (i >= k) ? i * 8u + k * la : k * 8u + i * la, 0u);
+        }
+    } else if (ord == 0) {  // op(A)[i][k] = A[i + k lda]; i = tid & 127, k = (tid >> 7) + 2 s
         const double *base = G.A + m0 + k0 * G.lda;
         const auto rs = op_rsrc(base, ((G.M - m0) + (G.K - 1 - k0) * G.lda) * (int64_t)sizeof(double));
         const int i = tid & 127, kq = tid >> 7;
@@ -131,7 +162,7 @@ __device__ __forceinline__ void load_tile(const GemmDesc &G0, int64_t m0, int64_
 // masked operand, outside its stored triangle.  A tile inside K with no
 // triangle, the common case, returns at once (a decision uniform over the
 // workgroup).
-template <int TNV>
+template <int TNV, bool SYM>
 __device__ __forceinline__ void mask_tile(const GemmDesc &G, int64_t m0, int64_t kt, int64_t kend, int tid, TileRegs &r) {
     int64_t k0 = kt, K = kend;
     const int moff = G.amask == 2 ? 1 : 0;
@@ -142,7 +173,7 @@ __device__ __forceinline__ void mask_tile(const GemmDesc &G, int64_t m0, int64_t
         k0 = kt - G.K;
     }
     if (!mask && k0 + TKD <= K) return;
-    if (!G.transA) {
+    if (a_order<SYM>(G, m0, kt) != 1) {
         const int64_t i = m0 + (tid & 127), kq = k0 + (tid >> 7);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
@@ -169,11 +200,11 @@ __device__ __forceinline__ void mask_tile(const GemmDesc &G, int64_t m0, int64_t
     }
 }
 
-template <int TNV>
-__device__ __forceinline__ void store_tile(const GemmDesc &G, int tid, const TileRegs &r, double (*As)[LDS_STRIDE],
+template <int TNV, bool SYM>
+__device__ __forceinline__ void store_tile(const GemmDesc &G, int64_t m0, int64_t kt, int tid, const TileRegs &r, double (*As)[LDS_STRIDE],
                                            double (*Bs)[TNV + 4]) {
     constexpr int NS = TNV / 8, KST = 256 / TNV;
-    if (!G.transA) {
+    if (a_order<SYM>(G, m0, kt) != 1) {
 #pragma unroll
         for (int s = 0; s < 16; ++s) As[(tid >> 7) + 2 * s][tid & 127] = r.a[s];
     } else {
@@ -194,7 +225,7 @@ __device__ __forceinline__ void store_tile(const GemmDesc &G, int tid, const Til
 // Waves: 2 x 2 of 64 x (TNV / 2) sub-tiles, each 4 x NB blocks of 16 x 16.
 // Two waves per SIMD (the accumulators then live in VGPRs): 1.75x the
 // throughput of one wave per SIMD with accumulation registers on 8192^3.
-template <int TNV>
+template <int TNV, bool SYM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
     constexpr int WN = TNV / 2, NB = WN / 16;
@@ -236,13 +267,13 @@ dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
         }
         kstop = kend;
     }
-    if (kbeg < kstop) load_tile<TNV>(G, m0, n0, kbeg, kend, tid, r);
+    if (kbeg < kstop) load_tile<TNV, SYM>(G, m0, n0, kbeg, kend, tid, r);
     for (int64_t k0 = kbeg; k0 < kstop; k0 += TKD) {
         __syncthreads();  // the previous tile's readers are done
-        mask_tile<TNV>(G, m0, k0, kend, tid, r);
-        store_tile<TNV>(G, tid, r, As, Bs);
+        mask_tile<TNV, SYM>(G, m0, k0, kend, tid, r);
+        store_tile<TNV, SYM>(G, m0, k0, tid, r, As, Bs);
         __syncthreads();
-        if (k0 + TKD < kstop) load_tile<TNV>(G, m0, n0, k0 + TKD, kend, tid, r);
+        if (k0 + TKD < kstop) load_tile<TNV, SYM>(G, m0, n0, k0 + TKD, kend, tid, r);
 #pragma unroll
         for (int kk = 0; kk < TKD; kk += 4) {
             double af[4], bf[NB];
@@ -498,6 +529,8 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
         if (g.ksplit < 1) g.ksplit = 1;
         if ((g.ksplit > 1 && !g.Cpart) || (g.Cpart && (g.lower || g.K2)) || (g.amask && g.K2))
             return set_error(TGBA_EINVAL, "split or masked product with unsupported options");
+        if (g.symm && (g.M != g.K || g.K2 || g.amask || g.lower))
+            return set_error(TGBA_EINVAL, "symmetric operand: needs M == K and no second part, mask or lower-only output");
         if (g.K2 && (g.K % TKD))  // the second part starts at a K-tile boundary
             return set_error(TGBA_EINVAL, "two-part product: the first part's K must be a multiple of 32");
         g.tiles_m = (g.M + TM - 1) / TM;
@@ -513,12 +546,21 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
     hipEvent_t ta = nullptr, tb = nullptr;
     const bool timed = timing_on();
     if (timed && (rc = timing_events(&ta, &tb))) return rc;
-    if (narrow)
-        hipExtLaunchKernelGGL(dgemm_kernel<64>, dim3((unsigned)total), dim3(256), 0, stream, ta, tb, 0,
-                              (const GemmDesc *)ws, (int)descs.size());
+    // products with a symmetric operand take their own instantiation, so that the
+    // element-by-element diagonal tiles cost the plain ones no registers
+    bool sym = false;
+    for (auto &g : descs) sym = sym || g.symm;
+    const dim3 grid((unsigned)total), blk(256);
+    const GemmDesc *dd = (const GemmDesc *)ws;
+    const int nd = (int)descs.size();
+    if (narrow && sym)
+        hipExtLaunchKernelGGL(dgemm_kernel<64, true>, grid, blk, 0, stream, ta, tb, 0, dd, nd);
+    else if (narrow)
+        hipExtLaunchKernelGGL(dgemm_kernel<64, false>, grid, blk, 0, stream, ta, tb, 0, dd, nd);
+    else if (sym)
+        hipExtLaunchKernelGGL(dgemm_kernel<TN, true>, grid, blk, 0, stream, ta, tb, 0, dd, nd);
     else
-        hipExtLaunchKernelGGL(dgemm_kernel<TN>, dim3((unsigned)total), dim3(256), 0, stream, ta, tb, 0,
-                              (const GemmDesc *)ws, (int)descs.size());
+        hipExtLaunchKernelGGL(dgemm_kernel<TN, false>, grid, blk, 0, stream, ta, tb, 0, dd, nd);
     if (timed) {
         // algorithmic flops: the stored triangle of a lower-only update, the stored
         // triangle of a masked (symmetric) operand, else the full product
@@ -581,9 +623,12 @@ extern "C" int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t 
     if (M == 0 || N == 0) return TGBA_OK;
     if (!C || (K > 0 && (!A || !B))) return tgba::set_error(TGBA_EINVAL, "NULL operand");
     if (ldc < M) return tgba::set_error(TGBA_EINVAL, "bad leading dimension of C");
-    if (K > 0 && (lda < (transA ? K : M) || ldb < (transB ? N : K)))
+    if (transA < 0 || transA > 2) return tgba::set_error(TGBA_EINVAL, "transA must be 0, 1 or 2");
+    if (transA == 2 && M != K) return tgba::set_error(TGBA_EINVAL, "symmetric A (transA = 2) needs M == K");
+    if (K > 0 && (lda < (transA == 1 ? K : M) || ldb < (transB ? N : K)))
         return tgba::set_error(TGBA_EINVAL, "bad leading dimension of A or B");
     std::vector<tgba::GemmDesc> d(1);
-    d[0] = tgba::GemmDesc{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, transA ? 1 : 0, transB ? 1 : 0, 0, 0, 0};
+    d[0] = tgba::GemmDesc{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, transA == 1 ? 1 : 0, transB ? 1 : 0, 0, 0, 0};
+    d[0].symm = transA == 2;
     return tgba::dgemm_batched(d, 2, (hipStream_t)stream);
 }

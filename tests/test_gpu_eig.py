@@ -281,3 +281,40 @@ def test_eig_with_vectors_heff_n24_k0():
     print(f"residual {np.abs(R).max():.2e} orth {np.abs(Z.T @ Z - np.eye(n)).max():.2e}", flush=True)
     assert np.abs(R).max() <= 1e-10 * nrm
     assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-10
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (31, 5), (128, 64), (161, 64), (300, 17), (1000, 64), (777, 100), (2049, 130)])
+def test_symmetric_operand_product(M, N):
+    """tgba_dgemm with transA = 2: op(A) is the symmetric matrix stored in A's lower
+    triangle, read in one pass (stored entries left of each row tile's diagonal block,
+    mirrored ones right of it, element by element on the diagonal K-tiles); the upper
+    triangle holds garbage that must never be read.  Ragged M (several row tiles and a
+    tail), narrow (N <= 64) and wide (N > 64) output tiles, beta != 0."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    rng = np.random.default_rng(M * 1000 + N)
+    S = rng.standard_normal((M, M))
+    S = S + S.T
+    G = S.copy()
+    G[np.triu_indices(M, 1)] = np.nan  # never read
+    Bm = rng.standard_normal((M, N))
+    Cm = rng.standard_normal((M, N))
+    dA, dB, dC = _cm(G), _cm(Bm), _cm(Cm)
+    tg.dgemm(2, 0, M, N, M, 0.75, dA, dB, -0.5, dC)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().T
+    ref = 0.75 * (S @ Bm) - 0.5 * Cm
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(M)
+
+
+def test_symmetric_operand_rejects_non_square():
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    A = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
+    B = torch.zeros((4, 8), dtype=torch.float64, device="cuda")
+    C = torch.zeros((4, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(tg.TgbaError):
+        tg.dgemm(2, 0, 8, 4, 7, 1.0, A, B, 0.0, C)
+    with pytest.raises(tg.TgbaError):
+        tg.dgemm(3, 0, 8, 4, 8, 1.0, A, B, 0.0, C)
