@@ -34,7 +34,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 128, TN = 128, TK = 16, LDS_STRIDE = TM + 4;
+constexpr int TM = 128, TN = 128, LDS_STRIDE = TM + 4;
 constexpr int TKD = 32;  // K-tile depth of the FP64 kernel
 // TNV: output-tile width, 128, or 64 for products with N <= 64 (panel products)
 
