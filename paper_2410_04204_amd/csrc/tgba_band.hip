@@ -29,12 +29,13 @@
 //   * applied from the left to the rest of that bulge block, from both sides
 //     to the diagonal block, from the right to the block below (the next
 //     bulge).
-// Task (i, k) runs at step t = 3 i + k.  Every entry task (i, k) touches
-// lies in rows >= r, and every entry of the concurrent task (i + 1, k - 3) in
-// rows <= r - BW, so the tasks of one step are disjoint; every conflicting
+// One workgroup runs the pair of tasks (i, 2 kap), (i, 2 kap + 1) in order, at
+// step t = 2 i + kap.  Every entry the pair touches lies in rows >= r(i, 2 kap),
+// and every entry of the concurrent pair (i + 1, kap - 2) in rows
+// <= r(i, 2 kap) - BW, so the pairs of one step are disjoint; every conflicting
 // pair of tasks keeps the order of the sequential algorithm (checked against
-// it, bit for bit, with the tasks of each step run in either order).  So each
-// step is one launch with one workgroup per task of every sector.
+// it, bit for bit, with the pairs of each step run in either order).  So each
+// step is one launch with one workgroup per pair of every sector.
 //
 // The tridiagonal (d, e) then goes to the bisection of tgba_stebz.
 #include <algorithm>
@@ -55,7 +56,7 @@ constexpr int QCH = 1024;          // panel rows per workgroup of the panel QR
 constexpr int kQrMaxBlk = 64;      // partial-sum rows of the panel QR (>= ceil(n / QCH) for n <= 65536)
 constexpr int QP = BW + 1;         // partial sums per block: BW dot products + the norm
 constexpr int kMaxBandSecs = 256;  // sectors of one call (the step kernel indexes them in LDS)
-constexpr int kStride = 3;         // bulge-chasing schedule: task (i, k) at step kStride i + k
+constexpr int kStride = 2;         // bulge-chasing schedule: pair (i, kap) at step kStride i + kap
 constexpr int SB = 16;             // columns of a panel-QR sub-block
 constexpr int QB = kQrMaxBlk * QP + BW;  // one partial-sum buffer of the panel QR (column q uses buffer q & 1)
 
@@ -300,13 +301,19 @@ __global__ void band_extract_kernel(const BandSec *__restrict__ secs) {
 // ---- stage 2: bulge chasing -----------------------------------------------------
 __device__ __forceinline__ double &bat(double *B, int64_t row, int64_t c) { return B[(row - c) + c * LDB]; }
 
-// One workgroup per task.  Lane l is a row of every block, and thread (l, w)
-// holds columns w, w + 4, ... (16 of the 64) of the bulge block E (rows r..,
-// columns col+1 .. r-1), the diagonal block D (its lower triangle) and the
-// block F below D, so that every load is a contiguous column segment and all
-// 48 are in flight before any arithmetic.
-__global__ void __launch_bounds__(256) sb2st_step_kernel(const BandSec *__restrict__ secs, int nsec, int64_t t) {
-    __shared__ double vs[64], prow[4][64], pcol[64], qrow[4][64], wsv[64], qv[64];  // lane-indexed (BW <= 64)
+// One workgroup of 8 waves per pair of consecutive tasks (i, 2 kap) and
+// (i, 2 kap + 1) of a sweep.  Lane l is a row of every block, and thread (l, w)
+// holds columns w, w + 8, ... (8 of the 64) of the bulge block E (rows r..,
+// columns col .. col+63: column col is the one the reflector annihilates), the
+// diagonal block D (its lower triangle) and the block F below D, so that every
+// load is a contiguous column segment and all 24 are in flight before any
+// arithmetic.  F after the first task is exactly the second task's E (rows
+// r + BW.., columns r .. r+63, held by the same threads): it stays in
+// registers, which saves a store and a load of a 64 x 64 block per pair.
+constexpr int kPairWaves = 8;
+__global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(4))) sb2st_pair_kernel(const BandSec *__restrict__ secs, int nsec, int64_t t) {
+    constexpr int NW = kPairWaves, NJ = BW / NW;
+    __shared__ double vs[64], prow[NW][64], pcol[64], qrow[NW][64], wsv[64], qv[64];  // lane-indexed (BW <= 64)
     __shared__ double par[2];
     __shared__ int64_t s_first[kMaxBandSecs], s_n[kMaxBandSecs], s_cap[kMaxBandSecs];
     __shared__ int s_sec;
@@ -330,88 +337,112 @@ __global__ void __launch_bounds__(256) sb2st_step_kernel(const BandSec *__restri
     const int64_t slot = blockIdx.x - s_first[s];
     const int64_t n = s_n[s];
     if (slot >= s_cap[s] || n < 3) return;
-    const int64_t i = t / kStride - slot, k = t % kStride + kStride * slot;
-    if (i < 0 || i > n - 3 || k > (n - 3 - i) / BW) return;
+    const int64_t i = t / kStride - slot, kap = t % kStride + kStride * slot;
+    if (i < 0 || i > n - 3) return;
+    const int64_t kmax = (n - 3 - i) / BW;  // tasks k = 0 .. kmax of sweep i
+    if (2 * kap > kmax) return;
     const BandSec S = secs[s];
-    const int64_t r = i + 1 + k * BW;
-    const int ln = (int)(n - r < BW ? n - r : BW);              // >= 2
-    const int64_t rest = n - r - ln;
-    const int ln2 = (int)(rest < 0 ? 0 : (rest < BW ? rest : BW));
-    const int64_t col = (k == 0) ? i : r - BW;
     double *B = S.band;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NJ = BW / 4;
-
-    // ---- loads ----
-    double x = 0.0;
-    if (wave == 0 && lane < ln) x = bat(B, r + lane, col);
     double E[NJ], D[NJ], F[NJ];
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        const int j = wave + 4 * jj;
-        E[jj] = (k > 0 && j < BW - 1 && lane < ln) ? bat(B, r + lane, col + 1 + j) : 0.0;
-        D[jj] = (lane < ln && j <= lane) ? bat(B, r + lane, r + j) : 0.0;  // j < ln follows
-        F[jj] = (lane < ln2 && j < ln) ? bat(B, r + ln + lane, r + j) : 0.0;
-    }
 
-    if (tid < 64) pcol[tid] = 0.0;  // lanes beyond BW read it below
-    // ---- reflector from column col (wave 0) ----
-    if (wave == 0) {
-        const double sig = wave_sum(lane > 0 ? x * x : 0.0);
-        const double alpha = __shfl(x, 0, 64);
-        double tau = 0.0, beta = alpha, scale = 0.0;
-        if (sig != 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        vs[lane] = (lane == 0) ? 1.0 : ((lane < ln) ? x * scale : 0.0);
-        if (lane < ln) bat(B, r + lane, col) = (lane == 0) ? beta : 0.0;
-        if (lane == 0) par[0] = tau;
-    }
-    __syncthreads();
-    const double tau = par[0];
-    if (tau == 0.0) return;  // identity reflector (uniform)
-    const double vl = vs[lane];
+#pragma nounroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t k = 2 * kap + h;
+        if (k > kmax) break;  // uniform
+        const bool more = k + 1 <= kmax && h == 0;  // the next task takes F from registers
+        const int64_t r = i + 1 + k * BW;
+        const int ln = (int)(n - r < BW ? n - r : BW);  // >= 2
+        const int64_t rest = n - r - ln;
+        const int ln2 = (int)(rest < 0 ? 0 : (rest < BW ? rest : BW));
+        const int64_t col = (k == 0) ? i : r - BW;
+        if (h == 1) __syncthreads();  // the first task's readers of vs, wsv, qv, pcol are done
 
-    // ---- left application to the bulge block: E -= tau v (v^T E) ----
-    if (k > 0) {
+        // ---- loads (E of the second task: the first task's F) ----
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
-            const int j = wave + 4 * jj;
-            const double wc = wave_sum(vl * E[jj]);
-            if (j < BW - 1 && lane < ln) bat(B, r + lane, col + 1 + j) = E[jj] - tau * vl * wc;
+            const int j = wave + NW * jj;
+            if (h == 0) E[jj] = (lane < ln && (k > 0 || j == 0)) ? bat(B, r + lane, col + j) : 0.0;
+            else E[jj] = F[jj];
+            D[jj] = (lane < ln && j <= lane) ? bat(B, r + lane, r + j) : 0.0;  // j < ln follows
+            F[jj] = (lane < ln2 && j < ln) ? bat(B, r + ln + lane, r + j) : 0.0;
         }
-    }
-    // ---- p = D v from the lower triangle; q = F v ----
-    double pr = 0.0, qr = 0.0;
+
+        if (tid < 64) pcol[tid] = 0.0;  // lanes beyond BW read it below
+        // ---- reflector from column col (wave 0: E[0] is column col) ----
+        if (wave == 0) {
+            const double x = E[0];
+            const double sig = wave_sum(lane > 0 ? x * x : 0.0);
+            const double alpha = __shfl(x, 0, 64);
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (sig != 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            vs[lane] = (lane == 0) ? 1.0 : ((lane < ln) ? x * scale : 0.0);
+            if (lane < ln) bat(B, r + lane, col) = (lane == 0) ? beta : 0.0;
+            if (lane == 0) par[0] = tau;
+        }
+        __syncthreads();
+        const double tau = par[0];
+        const bool act = tau != 0.0;  // uniform; an identity reflector changes nothing
+        const double vl = vs[lane];
+
+        // ---- left application to the bulge block: E -= tau v (v^T E), columns col+1.. ----
+        // (stored when changed, and always in the second task, whose E came from registers)
+        if (k > 0 && (act || h == 1)) {
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        const int j = wave + 4 * jj;
-        const double vj = vs[j];
-        pr += D[jj] * vj;                                                  // D[l][j], j <= l
-        const double pc = wave_sum((j < lane) ? D[jj] * vl : 0.0);        // sum_{l > j} D[l][j] v_l
-        if (lane == 0) pcol[j] = pc;
-        qr += F[jj] * vj;
-    }
-    prow[wave][lane] = pr;
-    qrow[wave][lane] = qr;
-    __syncthreads();
-    if (wave == 0) {
-        const double pl = tau * (prow[0][lane] + prow[1][lane] + prow[2][lane] + prow[3][lane] + pcol[lane]);
-        const double kk = 0.5 * tau * wave_sum(pl * vl);
-        wsv[lane] = pl - kk * vl;
-        qv[lane] = qrow[0][lane] + qrow[1][lane] + qrow[2][lane] + qrow[3][lane];
-    }
-    __syncthreads();
-    // ---- D -= v w^T + w v^T (lower), F -= tau q v^T ----
-    const double wl = wsv[lane], ql = qv[lane];
+            for (int jj = 0; jj < NJ; ++jj) {
+                const int j = wave + NW * jj;
+                if (j == 0) continue;  // column col: the reflector's own column, stored above
+                const double wc = act ? wave_sum(vl * E[jj]) : 0.0;
+                if (lane < ln) bat(B, r + lane, col + j) = E[jj] - tau * vl * wc;
+            }
+        }
+        if (!act) {
+            if (h == 0) continue;  // D, F unchanged; F is the next task's E as loaded
+            break;
+        }
+        // ---- p = D v from the lower triangle; q = F v ----
+        double pr = 0.0, qr = 0.0;
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        const int j = wave + 4 * jj;
-        const double vj = vs[j], wj = wsv[j];
-        if (lane < ln && j <= lane) bat(B, r + lane, r + j) = D[jj] - vl * wj - wl * vj;
-        if (lane < ln2 && j < ln) bat(B, r + ln + lane, r + j) = F[jj] - tau * ql * vj;
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = wave + NW * jj;
+            const double vj = vs[j];
+            pr += D[jj] * vj;                                                  // D[l][j], j <= l
+            const double pc = wave_sum((j < lane) ? D[jj] * vl : 0.0);        // sum_{l > j} D[l][j] v_l
+            if (lane == 0) pcol[j] = pc;
+            qr += F[jj] * vj;
+        }
+        prow[wave][lane] = pr;
+        qrow[wave][lane] = qr;
+        __syncthreads();
+        if (wave == 0) {
+            double ps = pcol[lane], qs = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                ps += prow[w][lane];
+                qs += qrow[w][lane];
+            }
+            const double pl = tau * ps;
+            const double kk = 0.5 * tau * wave_sum(pl * vl);
+            wsv[lane] = pl - kk * vl;
+            qv[lane] = qs;
+        }
+        __syncthreads();
+        // ---- D -= v w^T + w v^T (lower), F -= tau q v^T ----
+        const double wl = wsv[lane], ql = qv[lane];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = wave + NW * jj;
+            const double vj = vs[j], wj = wsv[j];
+            if (lane < ln && j <= lane) bat(B, r + lane, r + j) = D[jj] - vl * wj - wl * vj;
+            if (lane < ln2 && j < ln) {
+                F[jj] -= tau * ql * vj;
+                if (!more) bat(B, r + ln + lane, r + j) = F[jj];
+            }
+        }
     }
 }
 
@@ -487,7 +518,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.M = p; p += BW * BW;
         S.Q = p; p += (size_t)x.n * 4 * BW;
         S.first_wg = wg;
-        S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / kStride + 2 : 0;
+        S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / (2 * kStride) + 2 : 0;  // pairs of one step, per sector
         wg += S.cap;
     }
     void *wsd = nullptr;
@@ -825,14 +856,14 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     // ---- stage 2 ----
     const int64_t n0 = secs[0].n;
     if (n0 >= 3 && wg > 0) {
-        // the last task of a sector of order n is sweep n-3 at k = 0: step kStride (n - 3)
+        // the last pair of a sector of order n is sweep n-3 at kap = 0: step kStride (n - 3)
         const int64_t tmax = kStride * (n0 - 3);
         int act = nsec;
         for (int64_t t = 0; t <= tmax; ++t) {
             // sectors with tasks left at step t are a prefix (decreasing order)
             while (act > 0 && (secs[act - 1].n < 3 || kStride * (secs[act - 1].n - 3) < t)) --act;
             const int64_t grid = secs[act - 1].first_wg + secs[act - 1].cap;
-            hipLaunchKernelGGL(sb2st_step_kernel, dim3((unsigned)grid), dim3(256), 0, stream, d_secs, act, t);
+            hipLaunchKernelGGL(sb2st_pair_kernel, dim3((unsigned)grid), dim3(64 * kPairWaves), 0, stream, d_secs, act, t);
         }
         TGBA_HIP(hipGetLastError());
     }
