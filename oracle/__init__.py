@@ -12,6 +12,7 @@ Everything here is plain double precision, written for legibility:
 * ``model``    mode tables and vacuum energies (Example section, eqs. 4-6)
 * ``basis``    Gaussian basis enumeration, momentum labels, truncation
 * ``brute``    explicit 2^N state vectors and exact diagonalisation (N <= 12)
+* ``lanczos``  sparse exact diagonalisation of the zero-momentum sector (N <= 24)
 * ``wick``     literal generalized Wick theorem -> Pfaffian (Appendix A)
 * ``heff``     the truncated effective Hamiltonian (eq. 2, eq. S4)
 * ``spectral`` LAPACK eigensolve and the dynamic structure factor (eq. 8)
