@@ -263,6 +263,34 @@ int tgba_assembly_plan_create(const tgba_basis *basis, int nsec, const int *Ks, 
 int tgba_plan_launch(tgba_plan *plan, void *stream);
 void tgba_plan_free(tgba_plan *plan);
 
+/*
+ * Whole-step plans.  The Method section diagonalises every momentum sector
+ * independently; a plan records a sequence of library calls -- for the N = 40
+ * step: the all-sector assembly, tgba_eig_batched_vec over all sectors (the
+ * eigenvalue-only sectors and the K = 0 sector with vectors on two branches),
+ * the K = 0 gamma_1 matrix, tgba_dsf, tgba_quench_overlaps and tgba_quench --
+ * into one hipGraph that tgba_plan_launch replays with one launch.
+ *
+ * tgba_capture_begin(stream) starts recording the calls this host thread then
+ * makes on `stream` (a created stream, not NULL); they queue nothing and return
+ * the usual error codes for bad arguments.  While recording, calls never wait
+ * on or read from the device: launch descriptors go to plan-owned device memory
+ * (filled once at the end), workspace comes from plan-owned buffers (one per
+ * use), the autotuner returns decided shapes or the defaults without timing,
+ * and tgba_quench skips its host check of |c|^2 > 0 (a zero overlap then gives
+ * non-finite sx).  tgba_capture_end(stream, &plan) ends the recording and
+ * returns the plan (TGBA_EDEVICE if the capture failed; the recording is then
+ * discarded).  Every input and output buffer named in the recorded calls must
+ * stay alive and in place while the plan is used; each replay recomputes all
+ * outputs from the inputs.  tgba_plan_info reports the graph's node count and
+ * the plan-owned device bytes.  Only calls on the step's path are recordable:
+ * the basis build, the correlator, overlap-study and learned-selection calls
+ * read results back on the host and must not be recorded.
+ */
+int tgba_capture_begin(void *stream);
+int tgba_capture_end(void *stream, tgba_plan **out);
+int tgba_plan_info(const tgba_plan *plan, int64_t *nodes, int64_t *bytes);
+
 /* ---- dense symmetric eigensolve (Method section: diagonalise H_eff) ----- */
 
 #define TGBA_EIG_FP64 0x0    /* all stages in double precision                          */

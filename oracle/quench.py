@@ -77,7 +77,7 @@ def evolve(E, Z, c, times):
 
 def sigma_x(B, G, c):
     """<sigma^x>(t) = B^H G B / (c^H c) per column of B."""
-    num = np.einsum("it,ij,jt->t", B.conj(), G, B).real
+    num = np.sum(B.conj() * (G @ B), axis=0).real
     return num / np.vdot(c, c).real
 
 

@@ -176,6 +176,57 @@ class AssemblyPlan:
             pass
 
 
+class Plan:
+    """Library calls recorded into one hipGraph (tgba_capture_begin / tgba_capture_end);
+    launch() replays them.  The caller keeps every buffer of the recorded calls alive."""
+
+    def __init__(self, handle, keep=()):
+        self._p = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().tgba_plan_launch(self._p, _lib.stream_handle(stream)))
+
+    def info(self):
+        nodes, nbytes = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.load().tgba_plan_info(self._p, ctypes.byref(nodes), ctypes.byref(nbytes)))
+        return nodes.value, nbytes.value
+
+    def free(self):
+        if getattr(self, "_p", None):
+            _lib.load().tgba_plan_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class capture:
+    """Context manager recording the library calls made on `stream` (a created
+    torch.cuda.Stream) into a Plan, available as .plan after the block."""
+
+    def __init__(self, stream, keep=()):
+        self.stream, self.keep, self.plan = stream, keep, None
+
+    def __enter__(self):
+        _lib.check(_lib.load().tgba_capture_begin(_lib.stream_handle(self.stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        p = ctypes.c_void_p()
+        rc = _lib.load().tgba_capture_end(_lib.stream_handle(self.stream), ctypes.byref(p))
+        if exc_type is not None:
+            if rc == 0:
+                _lib.load().tgba_plan_free(p)
+            return False
+        _lib.check(rc)
+        self.plan = Plan(p, self.keep)
+        return False
+
+
 def eig_mixed(A, w, n_refine=200, stream=None):
     """Mixed-precision eigen-decomposition of one sector (tgba_eig_mixed); A is overwritten by Z."""
     _lib.check(_lib.load().tgba_eig_mixed(A.shape[0], _lib.ptr(A), _ld(A), _lib.ptr(w), int(n_refine),

@@ -29,6 +29,7 @@ EXPORTS = [
     "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free", "tgba_quench_weights",
     "tgba_assemble_cross", "tgba_dsf_cross", "tgba_assemble_corr", "tgba_quench_corr",
     "tgba_corr_table", "tgba_corr_signs",
+    "tgba_capture_begin", "tgba_capture_end", "tgba_plan_info",
 ]
 
 
@@ -105,6 +106,9 @@ def load():
                                             ctypes.POINTER(c_void_p)]
     L.tgba_plan_launch.argtypes = [c_void_p, c_void_p]
     L.tgba_plan_free.argtypes = [c_void_p]
+    L.tgba_capture_begin.argtypes = [c_void_p]
+    L.tgba_capture_end.argtypes = [c_void_p, ctypes.POINTER(c_void_p)]
+    L.tgba_plan_info.argtypes = [c_void_p, P_i64, P_i64]
     L.tgba_plan_free.restype = None
     L.tgba_autotune_report.argtypes = [ctypes.c_char_p, c_int64, P_i64]
     L.tgba_eig_mixed.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p]

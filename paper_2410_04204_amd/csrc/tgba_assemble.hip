@@ -888,22 +888,21 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
     if (rc) return rc;
     const int N = b->N;
     const size_t desc_bytes = o.desc.size() * sizeof(SectorDesc);
-    void *ws = nullptr;
-    if ((rc = workspace_get(desc_bytes, 0, &ws))) return rc;
-    SectorDesc *d_desc = (SectorDesc *)ws;
     auto run = [&](int cand) -> int {
         const int rows = kRowChoices[cand];
         std::vector<SectorDesc> dd;
         size_t lds = 0;
         const int64_t nblocks = asm_blocks(o, N, rows, dd, lds);
-        TGBA_HIP(hipMemcpyAsync(d_desc, dd.data(), desc_bytes, hipMemcpyHostToDevice, stream));
-        return asm_launch_rows(b, o, rows, d_desc, nsec, nblocks, lds, stream, true);
+        void *ws = nullptr;
+        int rc2 = upload(dd.data(), desc_bytes, ws::AssembleDesc, stream, &ws);
+        if (rc2) return rc2;
+        return asm_launch_rows(b, o, rows, (SectorDesc *)ws, nsec, nblocks, lds, stream, true);
     };
     const int fallback = rows_default(N) == 4 ? 1 : 0;
     int pick = fallback;
     if (o.elements >= 1e6) {  // worth timing: tuning runs are repeats of the same (idempotent) launch
         const std::string key = asm_key(N, o);
-        if (autotune_known(key)) {
+        if (autotune_known(key) || capturing()) {
             if ((rc = autotune(key, 2, fallback, run, stream, &pick))) return rc;  // cached pick, nothing runs
         } else {
             // keep the diagnostic counters of the basis out of the tuning runs
@@ -921,8 +920,7 @@ int assemble_sectors(const Basis *b, int nsec, const int *Ks, void *const *H, co
         const int64_t ntiles = asm_tiles(o, td);
         if (ntiles > 0) {
             void *ws2 = nullptr;
-            if ((rc = workspace_get(desc_bytes, 1, &ws2))) return rc;
-            TGBA_HIP(hipMemcpyAsync(ws2, td.data(), desc_bytes, hipMemcpyHostToDevice, stream));
+            if ((rc = upload(td.data(), desc_bytes, ws::AssembleTuneDesc, stream, &ws2))) return rc;
             if ((rc = asm_launch_mirror(o, (const SectorDesc *)ws2, nsec, ntiles, stream))) return rc;
         }
     }
@@ -973,7 +971,7 @@ int assemble_cross(const Basis *b, int Kr, int Kc, double *X, int64_t ld, hipStr
     TGBA_HIP(hipGetLastError());
     if (nblocks == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = workspace_get(2 * sizeof(SectorDesc), 29, &ws);
+    int rc = workspace_get(2 * sizeof(SectorDesc), ws::CrossDesc, &ws);
     if (rc) return rc;
     TGBA_HIP(hipMemcpyAsync(ws, d.data(), 2 * sizeof(SectorDesc), hipMemcpyHostToDevice, stream));
     AsmSetup o;
@@ -1039,7 +1037,7 @@ int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O
     const size_t ndesc = 2 * (size_t)nj;
     const size_t bytes = sizeof(double) * (htab.size() + hsign.size()) + ndesc * sizeof(SectorDesc) + 256;
     void *ws = nullptr;
-    int rc = workspace_get(bytes, 39, &ws);
+    int rc = workspace_get(bytes, ws::CorrWork, &ws);
     if (rc) return rc;
     double *d_tab = (double *)ws, *d_sign = d_tab + htab.size();
     SectorDesc *d_desc = (SectorDesc *)(((uintptr_t)(d_sign + hsign.size()) + 255) & ~(uintptr_t)255);
@@ -1115,21 +1113,6 @@ extern "C" int tgba_assemble_cross(const tgba_basis *hb, int K_rows, int K_cols,
 
 // ---- assembly plan: the launches of a batched assembly captured in a hipGraph ----
 
-struct tgba_plan {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    void *d_desc = nullptr, *d_tdesc = nullptr;
-};
-
-extern "C" void tgba_plan_free(tgba_plan *p) {
-    if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->d_desc) (void)hipFree(p->d_desc);
-    if (p->d_tdesc) (void)hipFree(p->d_tdesc);
-    delete p;
-}
-
 extern "C" int tgba_assembly_plan_create(const tgba_basis *hb, int nsec, const int *Ks, void *const *H,
                                          const int64_t *ld, int flags, tgba_plan **out) {
     using namespace tgba;
@@ -1163,10 +1146,16 @@ extern "C" int tgba_assembly_plan_create(const tgba_basis *hb, int nsec, const i
         tgba_plan_free(p);
         return set_error(code, msg);
     };
-    if (hipMalloc(&p->d_desc, bytes) != hipSuccess || (ntiles > 0 && hipMalloc(&p->d_tdesc, bytes) != hipSuccess))
-        return fail(TGBA_ENOMEM, "plan descriptor allocation failed");
-    if (hipMemcpy(p->d_desc, dd.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
-        (ntiles > 0 && hipMemcpy(p->d_tdesc, td.data(), bytes, hipMemcpyHostToDevice) != hipSuccess))
+    void *d_desc = nullptr, *d_tdesc = nullptr;
+    if (hipMalloc(&d_desc, bytes) != hipSuccess) return fail(TGBA_ENOMEM, "plan descriptor allocation failed");
+    p->owned.push_back(d_desc);
+    if (ntiles > 0) {
+        if (hipMalloc(&d_tdesc, bytes) != hipSuccess) return fail(TGBA_ENOMEM, "plan descriptor allocation failed");
+        p->owned.push_back(d_tdesc);
+    }
+    p->bytes = bytes * (ntiles > 0 ? 2 : 1);
+    if (hipMemcpy(d_desc, dd.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        (ntiles > 0 && hipMemcpy(d_tdesc, td.data(), bytes, hipMemcpyHostToDevice) != hipSuccess))
         return fail(TGBA_EDEVICE, "plan descriptor upload failed");
     // kernel attributes are set outside the capture
     if (lds > 65536) {
@@ -1177,8 +1166,8 @@ extern "C" int tgba_assembly_plan_create(const tgba_basis *hb, int nsec, const i
     }
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(TGBA_EDEVICE, "stream creation failed");
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(TGBA_EDEVICE, "capture failed");
-    rc = asm_launch_rows(b, o, rows, (const SectorDesc *)p->d_desc, nsec, nblocks, lds, cs, false);
-    if (!rc && ntiles > 0) rc = asm_launch_mirror(o, (const SectorDesc *)p->d_tdesc, nsec, ntiles, cs);
+    rc = asm_launch_rows(b, o, rows, (const SectorDesc *)d_desc, nsec, nblocks, lds, cs, false);
+    if (!rc && ntiles > 0) rc = asm_launch_mirror(o, (const SectorDesc *)d_tdesc, nsec, ntiles, cs);
     const hipError_t ec = hipStreamEndCapture(cs, &p->graph);
     if (rc) {
         std::string msg = tgba_last_error();
@@ -1188,15 +1177,11 @@ extern "C" int tgba_assembly_plan_create(const tgba_basis *hb, int nsec, const i
     if (ec != hipSuccess || !p->graph) return fail(TGBA_EDEVICE, "capture failed");
     if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
         return fail(TGBA_EDEVICE, "graph instantiation failed");
+    size_t nn = 0;
+    (void)hipGraphGetNodes(p->graph, nullptr, &nn);
+    p->nodes = (int64_t)nn;
     (void)hipStreamDestroy(cs);
     *out = p;
-    return TGBA_OK;
-}
-
-extern "C" int tgba_plan_launch(tgba_plan *p, void *stream) {
-    tgba::clear_error();
-    if (!p || !p->exec) return tgba::set_error(TGBA_EINVAL, "bad plan");
-    TGBA_HIP(hipGraphLaunch(p->exec, (hipStream_t)stream));
     return TGBA_OK;
 }
 

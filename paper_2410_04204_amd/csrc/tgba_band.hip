@@ -61,7 +61,8 @@ constexpr int SB = 16;             // columns of a panel-QR sub-block
 constexpr int QB = kQrMaxBlk * QP + BW;  // one partial-sum buffer of the panel QR (column q uses buffer q & 1)
 
 // workspace slots of this file
-constexpr int kSlotSecs = 30, kSlotWork = 31, kSlotParts = 32, kSlotGemm = 33, kSlotRed = 34;
+constexpr int kSlotSecs = ws::BandSecs, kSlotWork = ws::BandWork, kSlotParts = ws::BandParts, kSlotGemm = ws::BandGemm,
+              kSlotRed = ws::BandRed;
 
 struct BandSec {
     double *A;
@@ -522,9 +523,8 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         wg += S.cap;
     }
     void *wsd = nullptr;
-    if ((rc = workspace_get(nsec * sizeof(BandSec), kSlotSecs, &wsd))) return rc;
+    if ((rc = upload(secs.data(), nsec * sizeof(BandSec), kSlotSecs, stream, &wsd))) return rc;
     BandSec *d_secs = (BandSec *)wsd;
-    TGBA_HIP(hipMemcpyAsync(d_secs, secs.data(), nsec * sizeof(BandSec), hipMemcpyHostToDevice, stream));
 
     // split-K partial buffers: size for the largest panel call
     const int64_t nmax = secs[0].n;

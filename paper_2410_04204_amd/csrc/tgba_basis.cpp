@@ -180,7 +180,7 @@ static int learned_keep(const Basis &b, std::vector<Cand> &c, int64_t keep, cons
     void *ws = nullptr;
     const size_t bytes = (size_t)n * (sizeof(uint64_t) + sizeof(double) + kMlpIn * sizeof(float) + sizeof(float)) +
                          (size_t)n + 1024;
-    int rc = workspace_get(bytes, 24, &ws);
+    int rc = workspace_get(bytes, ws::LearnedKeep, &ws);
     if (rc) return rc;
     uint64_t *d_mk = (uint64_t *)ws;
     double *d_e = (double *)(d_mk + n);

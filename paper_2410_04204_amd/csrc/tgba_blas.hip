@@ -504,9 +504,8 @@ int sgemm_batched(std::vector<SGemmDesc> &descs, int slot, hipStream_t stream) {
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = workspace_get(descs.size() * sizeof(SGemmDesc), slot, &ws);
+    int rc = upload(descs.data(), descs.size() * sizeof(SGemmDesc), slot, stream, &ws);
     if (rc) return rc;
-    TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(SGemmDesc), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(sgemm_kernel, dim3((unsigned)total), dim3(256), 0, stream, (const SGemmDesc *)ws, (int)descs.size());
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
@@ -540,9 +539,8 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = workspace_get(descs.size() * sizeof(GemmDesc), slot, &ws);
+    int rc = upload(descs.data(), descs.size() * sizeof(GemmDesc), slot, stream, &ws);
     if (rc) return rc;
-    TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, stream));
     hipEvent_t ta = nullptr, tb = nullptr;
     const bool timed = timing_on();
     if (timed && (rc = timing_events(&ta, &tb))) return rc;
@@ -604,9 +602,8 @@ int splitk_reduce(std::vector<ReduceDesc> &descs, int slot, hipStream_t stream) 
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = workspace_get(descs.size() * sizeof(ReduceDesc), slot, &ws);
+    int rc = upload(descs.data(), descs.size() * sizeof(ReduceDesc), slot, stream, &ws);
     if (rc) return rc;
-    TGBA_HIP(hipMemcpyAsync(ws, descs.data(), descs.size() * sizeof(ReduceDesc), hipMemcpyHostToDevice, stream));
     const int64_t grid = std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)grid), dim3(256), 0, stream, (const ReduceDesc *)ws,
                        (int)descs.size(), total);
@@ -630,5 +627,5 @@ extern "C" int tgba_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t 
     std::vector<tgba::GemmDesc> d(1);
     d[0] = tgba::GemmDesc{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, transA == 1 ? 1 : 0, transB ? 1 : 0, 0, 0, 0};
     d[0].symm = transA == 2;
-    return tgba::dgemm_batched(d, 2, (hipStream_t)stream);
+    return tgba::dgemm_batched(d, tgba::ws::DgemmApi, (hipStream_t)stream);
 }

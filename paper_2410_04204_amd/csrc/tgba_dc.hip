@@ -402,10 +402,21 @@ __global__ void __launch_bounds__(256) dc_fill_v(const Merge *merges, const int6
     }
 }
 
+// beta of every merge: the coupling e[mid - 1] at its split point
+__global__ void merge_beta_kernel(Merge *m, int64_t nm, const double *e) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q < nm) m[q].beta = e[m[q].mid - 1];
+}
+
+__global__ void copy_vec_kernel(const double *src, double *dst, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
 }  // namespace
 
 // Host driver.  d (n) in: diagonal, out: ascending eigenvalues; e (n-1);
-// Z (n x n, ldz): eigenvectors.  Workspace from slot 8.
+// Z (n x n, ldz): eigenvectors.  Workspace from slot ws::DCWork.
 int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStream_t stream) {
     if (n == 0) return TGBA_OK;
     if (n == 1) {
@@ -433,7 +444,7 @@ int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStre
     const size_t bytes = sizeof(double) * (2 * nn * nn + 13 * nn) + sizeof(int64_t) * (15 * nn + 1) +
                          sizeof(double) * 4 * nn + 32 * 256;
     void *ws = nullptr;
-    int rc = workspace_get(bytes, 8, &ws);
+    int rc = workspace_get(bytes, ws::DCWork, &ws);
     if (rc) return rc;
     char *p = (char *)ws;
     auto takeD = [&](size_t cnt) { double *r = (double *)p; p += ((cnt * sizeof(double) + 255) / 256) * 256; return r; };
@@ -445,37 +456,45 @@ int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStre
     double *Dalt = takeD(nn);
     S.perm = takeI(nn); S.nd = takeI(nn); S.ndinv = takeI(nn); S.dpos = takeI(nn); S.org = takeI(nn);
     S.code = takeI(nn); S.rij = takeI(2 * nn); S.counts = takeI(4 * nn);
-    int64_t *d_first = takeI(nn + 1);
-    Merge *d_merges = (Merge *)takeD(4 * nn);
-    int64_t *d_splits = takeI(nn);
-
-    TGBA_HIP(hipMemcpyAsync(d_splits, splits.data(), splits.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL(tear_kernel, dim3(1), dim3(64), 0, stream, d, e, d_splits, (int)splits.size());
-    hipLaunchKernelGGL(identity_kernel, dim3(2048), dim3(256), 0, stream, Z, n, ldz);
-    TGBA_HIP(hipGetLastError());
-    std::vector<double> eh(nn - 1);
-    TGBA_HIP(hipMemcpyAsync(eh.data(), e, (nn - 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
-    TGBA_HIP(hipStreamSynchronize(stream));
-    double *Dcur = d, *Dnext = Dalt;
-    std::vector<Merge> lvl;
-    std::vector<int64_t> first;
+    // the merges of every level (tree shape only; each coupling is read from e on
+    // the device) and each merge's first work item within its level
+    std::vector<Merge> all;
+    std::vector<int64_t> first, lvl_off(H + 2, 0);
     for (int h = 1; h <= H; ++h) {
-        lvl.clear();
-        first.clear();
+        lvl_off[h] = (int64_t)all.size();
         int64_t tot = 0;
         for (auto &nd : nodes)
             if (nd.h == h) {
                 first.push_back(tot);
-                lvl.push_back(Merge{nd.lo, nd.mid, nd.hi, eh[nd.mid - 1]});
+                all.push_back(Merge{nd.lo, nd.mid, nd.hi, 0.0});
                 tot += nd.hi - nd.lo;
             }
-        if (lvl.empty()) continue;
-        const int nm = (int)lvl.size();
-        TGBA_HIP(hipMemcpyAsync(d_merges, lvl.data(), nm * sizeof(Merge), hipMemcpyHostToDevice, stream));
-        TGBA_HIP(hipMemcpyAsync(d_first, first.data(), nm * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    }
+    lvl_off[H + 1] = (int64_t)all.size();
+    void *p_split = nullptr, *p_merge = nullptr, *p_first = nullptr;
+    if ((rc = upload(splits.data(), splits.size() * sizeof(int64_t), ws::DCSplits, stream, &p_split)) ||
+        (rc = upload(all.data(), all.size() * sizeof(Merge), ws::DCMerges, stream, &p_merge)) ||
+        (rc = upload(first.data(), first.size() * sizeof(int64_t), ws::DCFirst, stream, &p_first)))
+        return rc;
+    int64_t *d_splits = (int64_t *)p_split, *d_first_all = (int64_t *)p_first;
+    Merge *d_merges_all = (Merge *)p_merge;
+    hipLaunchKernelGGL(merge_beta_kernel, dim3((unsigned)((all.size() + 255) / 256)), dim3(256), 0, stream, d_merges_all,
+                       (int64_t)all.size(), e);
+    hipLaunchKernelGGL(tear_kernel, dim3(1), dim3(64), 0, stream, d, e, d_splits, (int)splits.size());
+    hipLaunchKernelGGL(identity_kernel, dim3(2048), dim3(256), 0, stream, Z, n, ldz);
+    TGBA_HIP(hipGetLastError());
+    double *Dcur = d, *Dnext = Dalt;
+    for (int h = 1; h <= H; ++h) {
+        const int nm = (int)(lvl_off[h + 1] - lvl_off[h]);
+        if (nm == 0) continue;
+        const Merge *lvl = all.data() + lvl_off[h];
+        const Merge *d_merges = d_merges_all + lvl_off[h];
+        const int64_t *d_first = d_first_all + lvl_off[h];
+        int64_t tot = 0;
+        for (int q = 0; q < nm; ++q) tot += lvl[q].hi - lvl[q].lo;
         const unsigned gthreads = (unsigned)((tot + 255) / 256);
         // the same range is also copied so that Dnext holds the untouched entries of other blocks
-        TGBA_HIP(hipMemcpyAsync(Dnext, Dcur, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(copy_vec_kernel, dim3(256), dim3(256), 0, stream, Dcur, Dnext, n);
         hipLaunchKernelGGL(dc_prepare, dim3(nm), dim3(256), 0, stream, d_merges, Dcur, Z, ldz, S);
         hipLaunchKernelGGL(dc_compact, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, S);
         hipLaunchKernelGGL(dc_roots, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, S);
@@ -487,16 +506,20 @@ int stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, hipStre
         hipLaunchKernelGGL(dc_fill_v, dim3(gthreads), dim3(256), 0, stream, d_merges, d_first, nm, V, (int64_t)n, S);
         TGBA_HIP(hipGetLastError());
         std::vector<GemmDesc> gd;
-        for (auto &mg : lvl) {
+        for (int q = 0; q < nm; ++q) {
+            const Merge &mg = lvl[q];
             const int64_t k = mg.hi - mg.lo;
             gd.push_back(GemmDesc{Qtmp + mg.lo + mg.lo * n, n, V + mg.lo + mg.lo * n, n, Z + mg.lo + mg.lo * ldz, ldz,
                                   k, k, k, 1.0, 0.0, 0, 0, 0, 0, 0, 0});
         }
-        rc = dgemm_batched(gd, 9, stream);
+        rc = dgemm_batched(gd, ws::DCGemm, stream);
         if (rc) return rc;
         std::swap(Dcur, Dnext);
     }
-    if (Dcur != d) TGBA_HIP(hipMemcpyAsync(d, Dcur, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    if (Dcur != d) {
+        hipLaunchKernelGGL(copy_vec_kernel, dim3(256), dim3(256), 0, stream, Dcur, d, n);
+        TGBA_HIP(hipGetLastError());
+    }
     return TGBA_OK;
 }
 

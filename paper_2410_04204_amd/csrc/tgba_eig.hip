@@ -662,10 +662,9 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
     std::vector<TriSecT<T>> sorted(nsec);
     for (int k = 0; k < nsec; ++k) sorted[k] = secs[order[k]];
     void *ws = nullptr;
-    int rc = workspace_get(nsec * sizeof(TriSecT<T>), 3, &ws);
+    int rc = upload(sorted.data(), nsec * sizeof(TriSecT<T>), ws::TriSecs, stream, &ws);
     if (rc) return rc;
     TriSecT<T> *d_secs = (TriSecT<T> *)ws;
-    TGBA_HIP(hipMemcpyAsync(d_secs, sorted.data(), nsec * sizeof(TriSecT<T>), hipMemcpyHostToDevice, stream));
     for (auto &S : sorted) {
         hipLaunchKernelGGL(zero_kernel<T>, dim3(1), dim3(256), 0, stream, S.scal, (int64_t)S_LEN);
         TGBA_HIP(hipGetLastError());
@@ -743,12 +742,12 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
                     g1[q].ldb2 = g2[q].ldb;
                     g1[q].K2 = g2[q].K;
                 }
-                rc = gemm_batched(g1, 4, stream);
+                rc = gemm_batched(g1, ws::TriGemm, stream);
                 if (rc) return rc;
             } else {
-                rc = gemm_batched(g1, 4, stream);
+                rc = gemm_batched(g1, ws::TriGemm, stream);
                 if (rc) return rc;
-                rc = gemm_batched(g2, 5, stream);
+                rc = gemm_batched(g2, ws::TriGemm2, stream);
                 if (rc) return rc;
             }
         }
@@ -788,33 +787,33 @@ int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T
                                                       std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles_w, 1))});
             void *wp = nullptr;
             const size_t need = (size_t)ks_s * nbp * nbp + (size_t)ks_w * nbp * n;
-            if ((rc = workspace_get(need * sizeof(double), 36, &wp))) return rc;
+            if ((rc = workspace_get(need * sizeof(double), ws::OrmtrParts, &wp))) return rc;
             double *parts = (double *)wp;
             g[0].ksplit = ks_s;
             g[0].Cpart = parts;
-            if ((rc = gemm_batched(g, 11, stream))) return rc;
+            if ((rc = gemm_batched(g, ws::OrmtrGram, stream))) return rc;
             std::vector<ReduceDesc> red{ReduceDesc{Sg, nbp, nbp, nbp, parts, ks_s, 0.0, 0}};
-            if ((rc = splitk_reduce(red, 37, stream))) return rc;
+            if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
             hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
             TGBA_HIP(hipGetLastError());
             g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
             g[0].ksplit = ks_w;
             g[0].Cpart = parts + (size_t)ks_s * nbp * nbp;
-            if ((rc = gemm_batched(g, 12, stream))) return rc;
+            if ((rc = gemm_batched(g, ws::OrmtrW, stream))) return rc;
             red[0] = ReduceDesc{W1, nbp, nbp, n, parts + (size_t)ks_s * nbp * nbp, ks_w, 0.0, 0};
-            if ((rc = splitk_reduce(red, 37, stream))) return rc;
+            if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
         } else {
-            if ((rc = gemm_batched(g, 11, stream))) return rc;
+            if ((rc = gemm_batched(g, ws::OrmtrGram, stream))) return rc;
             hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
             TGBA_HIP(hipGetLastError());
             g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
-            if ((rc = gemm_batched(g, 12, stream))) return rc;
+            if ((rc = gemm_batched(g, ws::OrmtrW, stream))) return rc;
         }
         g[0] = G{Tm, nbp, W1, nbp, W2, nbp, nbp, n, nbp, T(1), T(0), 0, 0, 0, 0, 0, 0};
-        rc = gemm_batched(g, 13, stream);
+        rc = gemm_batched(g, ws::OrmtrT, stream);
         if (rc) return rc;
         g[0] = G{V, m, W2, nbp, Zs, ldz, m, n, nbp, T(-1), T(1), 0, 0, 0, 0, 0, 0};
-        rc = gemm_batched(g, 14, stream);
+        rc = gemm_batched(g, ws::OrmtrUpdate, stream);
         if (rc) return rc;
     }
     return TGBA_OK;
@@ -834,12 +833,12 @@ int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
         secs[k] = BisSec{in[k].d, in[k].e, in[k].w, in[k].n, total};
         total += in[k].n;
     }
-    void *ws = nullptr;
-    int rc = workspace_get(nsec * sizeof(BisSec) + nsec * 3 * sizeof(double) + 64, 6, &ws);
+    void *ws = nullptr, *wb = nullptr;
+    int rc = upload(secs.data(), nsec * sizeof(BisSec), ws::BisectSecs, stream, &ws);
     if (rc) return rc;
+    if ((rc = workspace_get(nsec * 3 * sizeof(double) + 64, ws::BisectBounds, &wb))) return rc;
     BisSec *d_secs = (BisSec *)ws;
-    double *bounds = (double *)((char *)ws + ((nsec * sizeof(BisSec) + 63) / 64) * 64);
-    TGBA_HIP(hipMemcpyAsync(d_secs, secs.data(), nsec * sizeof(BisSec), hipMemcpyHostToDevice, stream));
+    double *bounds = (double *)wb;
     hipLaunchKernelGGL(gersh_kernel, dim3(nsec), dim3(256), 0, stream, d_secs, bounds);
     hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, d_secs, nsec, bounds);
     TGBA_HIP(hipGetLastError());
@@ -858,7 +857,7 @@ extern "C" int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *
     hipStream_t st = (hipStream_t)stream;
     void *ws = nullptr;
     const size_t wbytes = sizeof(double) * ((size_t)n * kNB + S_LEN + 64 + (size_t)symv_partials(n));
-    int rc = workspace_get(wbytes, 7, &ws);
+    int rc = workspace_get(wbytes, ws::SytrdApiWork, &ws);
     if (rc) return rc;
     std::vector<TriSec> secs(1);
     double *base = (double *)ws;
@@ -911,7 +910,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
 static int refine_lowest(int64_t n, double *A, int64_t lda, double *Z, int64_t k, double *w, hipStream_t st) {
     void *ws = nullptr;
     const size_t count = 4 * (size_t)n * k + 6 * (size_t)k * k + 2 * (size_t)k + 64;
-    int rc = workspace_get(count * sizeof(double), 27, &ws);
+    int rc = workspace_get(count * sizeof(double), ws::RefineWork, &ws);
     if (rc) return rc;
     double *Y = (double *)ws, *Sk = Y + (size_t)n * k, *Gk = Sk + (size_t)n * k, *Xn = Gk + (size_t)n * k;
     double *Gm = Xn + (size_t)n * k, *P = Gm + (size_t)k * k, *T1 = P + (size_t)k * k, *Sm = T1 + (size_t)k * k;
@@ -925,30 +924,30 @@ static int refine_lowest(int64_t n, double *A, int64_t lda, double *Z, int64_t k
     TGBA_HIP(hipStreamSynchronize(st));
     const double thr = 1e-5 * std::max(std::fabs(wlo), std::fabs(whi));
     for (int sweep = 0; sweep < 2; ++sweep) {
-        if ((rc = gemm1(0, 0, n, k, n, 1.0, A, lda, Z, n, 0.0, Y, n, 28, st))) return rc;   // Y = A Z_k
-        if ((rc = gemm1(1, 0, n, k, n, 1.0, Z, n, Y, n, 0.0, Sk, n, 28, st))) return rc;   // Z^T A Z_k
-        if ((rc = gemm1(1, 0, n, k, n, 1.0, Z, n, Z, n, 0.0, Gk, n, 28, st))) return rc;   // Z^T Z_k
+        if ((rc = gemm1(0, 0, n, k, n, 1.0, A, lda, Z, n, 0.0, Y, n, ws::RefineGemm, st))) return rc;   // Y = A Z_k
+        if ((rc = gemm1(1, 0, n, k, n, 1.0, Z, n, Y, n, 0.0, Sk, n, ws::RefineGemm, st))) return rc;   // Z^T A Z_k
+        if ((rc = gemm1(1, 0, n, k, n, 1.0, Z, n, Z, n, 0.0, Gk, n, ws::RefineGemm, st))) return rc;   // Z^T Z_k
         hipLaunchKernelGGL(oa_correction_kernel, dim3(1024), dim3(256), 0, st, Sk, Gk, w, n, k, thr, Y);
         TGBA_HIP(hipMemcpyAsync(Xn, Z, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
-        if ((rc = gemm1(0, 0, n, k, n, 1.0, Z, n, Y, n, 1.0, Xn, n, 28, st))) return rc;   // Z_k + Z E
+        if ((rc = gemm1(0, 0, n, k, n, 1.0, Z, n, Y, n, 1.0, Xn, n, ws::RefineGemm, st))) return rc;   // Z_k + Z E
         TGBA_HIP(hipMemcpyAsync(Z, Xn, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
     // Rayleigh-Ritz on span Z_k
     double *X = Z;
-    if ((rc = gemm1(0, 0, n, k, n, 1.0, A, lda, X, n, 0.0, Y, n, 28, st))) return rc;      // Y = A X
-    if ((rc = gemm1(1, 0, k, k, n, 1.0, X, n, X, n, 0.0, Gm, k, 28, st))) return rc;       // G = X^T X
-    if ((rc = gemm1(1, 0, k, k, n, 1.0, X, n, Y, n, 0.0, P, k, 28, st))) return rc;        // P = X^T A X
+    if ((rc = gemm1(0, 0, n, k, n, 1.0, A, lda, X, n, 0.0, Y, n, ws::RefineGemm, st))) return rc;      // Y = A X
+    if ((rc = gemm1(1, 0, k, k, n, 1.0, X, n, X, n, 0.0, Gm, k, ws::RefineGemm, st))) return rc;       // G = X^T X
+    if ((rc = gemm1(1, 0, k, k, n, 1.0, X, n, Y, n, 0.0, P, k, ws::RefineGemm, st))) return rc;        // P = X^T A X
     hipLaunchKernelGGL(sym_avg_kernel, dim3(64), dim3(256), 0, st, Gm, k, k);
     double *Gp[1] = {Gm}, *gp[1] = {gv};
     if ((rc = eig_batched(1, &k, Gp, &k, gp, TGBA_EIG_FP64, st))) return rc;              // Gm <- U
     hipLaunchKernelGGL(scale_cols_kernel, dim3(64), dim3(256), 0, st, Gm, k, k, k, gv);    // Gm <- B
-    if ((rc = gemm1(0, 0, k, k, k, 1.0, P, k, Gm, k, 0.0, T1, k, 28, st))) return rc;      // T1 = P B
-    if ((rc = gemm1(1, 0, k, k, k, 1.0, Gm, k, T1, k, 0.0, Sm, k, 28, st))) return rc;     // S = B^T P B
+    if ((rc = gemm1(0, 0, k, k, k, 1.0, P, k, Gm, k, 0.0, T1, k, ws::RefineGemm, st))) return rc;      // T1 = P B
+    if ((rc = gemm1(1, 0, k, k, k, 1.0, Gm, k, T1, k, 0.0, Sm, k, ws::RefineGemm, st))) return rc;     // S = B^T P B
     hipLaunchKernelGGL(sym_avg_kernel, dim3(64), dim3(256), 0, st, Sm, k, k);
     double *Sp[1] = {Sm}, *tp[1] = {th};
     if ((rc = eig_batched(1, &k, Sp, &k, tp, TGBA_EIG_FP64, st))) return rc;              // Sm <- C
-    if ((rc = gemm1(0, 0, k, k, k, 1.0, Gm, k, Sm, k, 0.0, Mm, k, 28, st))) return rc;     // M = B C
-    if ((rc = gemm1(0, 0, n, k, k, 1.0, X, n, Mm, k, 0.0, Xn, n, 28, st))) return rc;      // X M
+    if ((rc = gemm1(0, 0, k, k, k, 1.0, Gm, k, Sm, k, 0.0, Mm, k, ws::RefineGemm, st))) return rc;     // M = B C
+    if ((rc = gemm1(0, 0, n, k, k, 1.0, X, n, Mm, k, 0.0, Xn, n, ws::RefineGemm, st))) return rc;      // X M
     TGBA_HIP(hipMemcpyAsync(X, Xn, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
     TGBA_HIP(hipMemcpyAsync(w, th, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, st));
     return TGBA_OK;
@@ -964,12 +963,12 @@ static int eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_ref
     const size_t nn = (size_t)n * n;
     const size_t fcount = 2 * nn + (size_t)n * kNB + 3 * (size_t)n + S_LEN + 64 + (size_t)symv_partials(n) +
                           4 * (size_t)n * kNB + 2 * kNB * kNB + 64;
-    int rc = workspace_get(fcount * sizeof(float), 25, &ws);
+    int rc = workspace_get(fcount * sizeof(float), ws::MixedF32, &ws);
     if (rc) return rc;
     float *A32 = (float *)ws, *Z32 = A32 + nn, *W32 = Z32 + nn, *d32 = W32 + (size_t)n * kNB, *e32 = d32 + n,
           *tau32 = e32 + n, *sc32 = tau32 + n, *P32 = sc32 + S_LEN + 64, *scr32 = P32 + symv_partials(n);
     void *ws2 = nullptr;
-    if ((rc = workspace_get((nn + 2 * (size_t)n + 64) * sizeof(double), 26, &ws2))) return rc;
+    if ((rc = workspace_get((nn + 2 * (size_t)n + 64) * sizeof(double), ws::MixedF64, &ws2))) return rc;
     double *Zt = (double *)ws2, *d64 = Zt + nn, *e64 = d64 + n;
     hipLaunchKernelGGL(lower_to_f32_kernel, dim3(4096), dim3(256), 0, st, A, lda, A32, n, n);
     std::vector<TriSecT<float>> sec(1);
@@ -1002,8 +1001,8 @@ static int eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_ref
 // Eigen-decomposition of several sectors: eigenvalues only by the two-stage
 // reduction and bisection, with vectors by the one-stage reduction, divide and
 // conquer and the back-transform.  The two paths use disjoint workspace slots
-// (the eigenvalue path: 6, 30-35, 38), so they may run at the same time on two
-// streams from two host threads (tgba_eig_batched_vec).
+// (the eigenvalue path: BisectSecs, Band*, EigNovecWork), so they may run at the
+// same time on two streams from two host threads (tgba_eig_batched_vec).
 int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
                 hipStream_t stream) {
     const bool novec = (flags & TGBA_EIG_NOVEC) != 0;
@@ -1015,7 +1014,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
             tot += 2 * (size_t)n[k] + 8;
         }
         void *ws = nullptr;
-        int rc = workspace_get(tot * sizeof(double), 38, &ws);
+        int rc = workspace_get(tot * sizeof(double), ws::EigNovecWork, &ws);
         if (rc) return rc;
         double *p = (double *)ws;
         std::vector<BandIn> bin;
@@ -1029,7 +1028,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         }
         if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
         if ((rc = stebz_batched(bis, stream))) return rc;
-        TGBA_HIP(hipStreamSynchronize(stream));
+        if (!capturing()) TGBA_HIP(hipStreamSynchronize(stream));
         return TGBA_OK;
     }
     if (flags & TGBA_EIG_MIXED) {
@@ -1048,7 +1047,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         total += (size_t)S_LEN + 64 + (size_t)n[k] * (kNB + 3) + (size_t)symv_partials(n[k]);
     }
     void *ws = nullptr;
-    int rc = workspace_get(total * sizeof(double), 7, &ws);
+    int rc = workspace_get(total * sizeof(double), ws::TriWork, &ws);
     if (rc) return rc;
     double *p = (double *)ws;
     std::vector<TriSec> secs;
@@ -1071,7 +1070,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
     if (novec) {
         rc = stebz_batched(bis, stream);
         if (rc) return rc;
-        TGBA_HIP(hipStreamSynchronize(stream));
+        if (!capturing()) TGBA_HIP(hipStreamSynchronize(stream));
         return TGBA_OK;
     }
     // eigenvectors: divide and conquer on T, then the back-transform, per sector
@@ -1080,7 +1079,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         const int64_t nn = S.n;
         void *zw = nullptr;
         const size_t zbytes = sizeof(double) * ((size_t)nn * nn + (size_t)nn * kNB + 3 * (size_t)nn * kNB + 2 * kNB * kNB + 1024);
-        rc = workspace_get(zbytes, 10, &zw);
+        rc = workspace_get(zbytes, ws::EigVecZ, &zw);
         if (rc) return rc;
         double *Zt = (double *)zw;
         double *scratch = Zt + (size_t)nn * nn;
@@ -1089,10 +1088,11 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         rc = ormtr(nn, S.A, S.lda, S.tau, Zt, nn, scratch, stream);
         if (rc) return rc;
         hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(4096), dim3(256), 0, stream, Zt, nn, S.A, S.lda, nn, nn);
-        TGBA_HIP(hipMemcpyAsync(bis[k].w, S.d, nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(64), dim3(256), 0, stream, (const double *)S.d, nn,
+                           bis[k].w, nn, nn, (int64_t)1);
         TGBA_HIP(hipGetLastError());
     }
-    TGBA_HIP(hipStreamSynchronize(stream));
+    if (!capturing()) TGBA_HIP(hipStreamSynchronize(stream));
     return TGBA_OK;
 }
 
@@ -1137,6 +1137,20 @@ extern "C" int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A
     hipStream_t s2 = nullptr;
     int rc = tgba::side_stream(&s2);
     if (rc) return rc;
+    if (tgba::capturing()) {
+        // recording only: both groups from this thread, the vector group on the
+        // side stream between a fork and a join of the capture
+        hipEvent_t fork = nullptr, join = nullptr;
+        if ((rc = tgba::capture_event(&fork)) || (rc = tgba::capture_event(&join))) return rc;
+        TGBA_HIP(hipEventRecord(fork, st));
+        TGBA_HIP(hipStreamWaitEvent(s2, fork, 0));
+        if ((rc = tgba::eig_batched((int)nv.size(), nv.data(), av.data(), lv.data(), wv.data(), 0, s2))) return rc;
+        if ((rc = tgba::eig_batched((int)nn.size(), nn.data(), an.data(), ln.data(), wn.data(), TGBA_EIG_NOVEC, st)))
+            return rc;
+        TGBA_HIP(hipEventRecord(join, s2));
+        TGBA_HIP(hipStreamWaitEvent(st, join, 0));
+        return TGBA_OK;
+    }
     hipEvent_t ev = nullptr;
     TGBA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     TGBA_HIP(hipEventRecord(ev, st));

@@ -64,8 +64,42 @@ int corr_table(const Basis *b, int sector, int j, std::vector<double> &tab, doub
                double &residual);
 double corr_sign(const Basis *b, int sector, int j, uint64_t mask);
 
-// Device workspace cache (grow-only, per device and slot).
+// Slots of the device workspace cache.  Every distinct use has its own slot:
+// calls on different streams (the two groups of the batched eigensolver, a
+// caller's own streams) then never write into one another's buffers.  The ids
+// are consecutive enumerators, hence unique by construction.
+namespace ws {
+enum Slot : int {
+    AssembleDesc, AssembleTuneDesc, DgemmApi, TriSecs, TriGemm, TriGemm2, BisectSecs, TriWork, DCWork, DCGemm,
+    EigVecZ, OrmtrGram, OrmtrW, OrmtrT, OrmtrUpdate, DsfWork, QuenchWork, QuenchGemm1, QuenchGemm2, QuenchWeights,
+    MlpScore, MlpSelect, MlpBackward, MlpTrain, LearnedKeep, MixedF32, MixedF64, RefineWork, RefineGemm, CrossDesc,
+    BandSecs, BandWork, BandParts, BandGemm, BandRed, OrmtrParts, OrmtrRed, EigNovecWork, CorrWork, QuenchCorrWork,
+    QuenchCorrGemm1, QuenchCorrGemm2, DsfCrossWork, SytrdApiWork, BisectBounds, DCMerges, DCFirst, DCSplits,
+    Count
+};
+}  // namespace ws
+constexpr int kWorkspaceSlots = 48;
+static_assert(ws::Count <= kWorkspaceSlots, "more workspace slots than the cache holds");
+
+// Device workspace cache (grow-only, per device and slot).  While this thread
+// captures a plan, the buffer comes from the plan instead (one per slot, owned
+// by the plan and never freed while it lives).
 int workspace_get(size_t bytes, int slot, void **out);
+
+// Host -> device copy of launch descriptors read by the next kernels on `st`.
+// Eager: into the workspace of `slot`, ordered on the stream.  While this
+// thread captures a plan: into a fresh piece of plan-owned memory (every
+// captured kernel keeps its own descriptors), filled once when the capture
+// ends; nothing is queued on the stream.
+int upload(const void *src, size_t bytes, int slot, hipStream_t st, void **dev);
+
+// True while this thread records library calls into a plan (tgba_capture_begin):
+// such calls queue work only -- no host reads of device data, no waits, no
+// autotuning runs, no event timing.
+bool capturing();
+// An event for dependencies between streams inside the capture (fork/join),
+// destroyed when the capture ends.
+int capture_event(hipEvent_t *ev);
 // A second stream of the current device (created once, default priority).
 int side_stream(hipStream_t *out);
 int release_all_workspace();
@@ -92,4 +126,14 @@ int timing_push(hipEvent_t a, hipEvent_t b, double units, int ch = 0);
 
 struct tgba_basis {
     tgba::Basis b;
+};
+
+// A plan: library calls captured into one hipGraph, with the device memory its
+// kernels address (descriptors, workspace) owned by the plan.
+struct tgba_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> owned;
+    int64_t nodes = 0;
+    size_t bytes = 0;
 };

@@ -377,7 +377,7 @@ int mlp_score_bf16(int64_t n, const float *X, int64_t ldx, const float *params, 
     if (n <= 0) return TGBA_OK;
     void *ws = nullptr;
     const size_t wbytes = sizeof(__bf16) * ((size_t)IN * H + 2 * (size_t)H * H);
-    int rc = workspace_get(wbytes, 20, &ws);
+    int rc = workspace_get(wbytes, ws::MlpScore, &ws);
     if (rc) return rc;
     __bf16 *W0t = (__bf16 *)ws, *W1t = W0t + IN * H, *W2t = W1t + H * H;
     hipLaunchKernelGGL(to_bf16_t_kernel, dim3((IN * H + 255) / 256), dim3(256), 0, st, params + OFF_W0, IN, H, W0t);
@@ -398,7 +398,7 @@ int mlp_select_top(int64_t n, const float *scores, int64_t keep, std::vector<int
     }
     void *ws = nullptr;
     const size_t bytes = 256 * sizeof(unsigned int) + 2 * sizeof(unsigned long long) + 2 * (size_t)n * sizeof(int64_t) + 64;
-    int rc = workspace_get(bytes, 21, &ws);
+    int rc = workspace_get(bytes, ws::MlpSelect, &ws);
     if (rc) return rc;
     unsigned int *hist = (unsigned int *)ws;
     unsigned long long *cnt = (unsigned long long *)(hist + 256);
@@ -524,7 +524,7 @@ extern "C" int tgba_mlp_backward(int64_t Bn, const float *X, int64_t ldx, const 
     clear_error();
     if (Bn <= 0 || !X || !params || !acts || !dy || !grads || ldx < kMlpIn) return set_error(TGBA_EINVAL, "bad arguments");
     void *ws = nullptr;
-    int rc = workspace_get(2 * (size_t)Bn * H * sizeof(float), 22, &ws);
+    int rc = workspace_get(2 * (size_t)Bn * H * sizeof(float), ws::MlpBackward, &ws);
     if (rc) return rc;
     Fwd z{(float *)acts, (float *)acts + Bn * H, (float *)acts + 2 * Bn * H};
     return backward_fp32(Bn, X, ldx, params, z, dy, grads, (float *)ws, (float *)ws + Bn * H, (hipStream_t)stream);
@@ -547,7 +547,7 @@ extern "C" int tgba_mlp_train(int64_t n, const float *X, int64_t ldx, const floa
     const int64_t bs = std::min(batch, n);
     void *ws = nullptr;
     const size_t fl = 5 * (size_t)bs * H + 2 * (size_t)bs + (size_t)kMlpParams + 64;
-    int rc = workspace_get(fl * sizeof(float), 23, &ws);
+    int rc = workspace_get(fl * sizeof(float), ws::MlpTrain, &ws);
     if (rc) return rc;
     float *base = (float *)ws;
     Fwd z{base, base + bs * H, base + 2 * bs * H};

@@ -2,6 +2,7 @@
 // request.  Kernels that need scratch memory (descriptors, counters, panel
 // buffers) take it from here so that repeated calls do not allocate.
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -13,7 +14,7 @@
 
 namespace tgba {
 namespace {
-constexpr int kSlots = 48;
+constexpr int kSlots = kWorkspaceSlots;
 constexpr int kDevices = 16;
 struct Buf {
     void *p = nullptr;
@@ -23,7 +24,82 @@ std::mutex g_mu;
 Buf g_ws[kDevices][kSlots];
 }  // namespace
 
+// ---- capture of library calls into a plan ----------------------------------------
+namespace {
+struct Capture {
+    hipStream_t st = nullptr;
+    std::vector<void *> owned;  // plan-owned device allocations
+    size_t bytes = 0;
+    struct Chunk {
+        char *dev = nullptr;
+        size_t cap = 0, used = 0;
+        std::vector<char> host;  // image of the uploaded descriptors
+    };
+    std::vector<Chunk> chunks;
+    std::map<int, std::pair<void *, size_t>> slots;  // plan workspace per slot
+    std::vector<hipEvent_t> events;
+};
+thread_local Capture *t_cap = nullptr;
+constexpr size_t kUploadChunk = 8u << 20;
+
+void capture_release(Capture *c, bool free_memory) {
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (free_memory)
+        for (void *p : c->owned) (void)hipFree(p);
+    delete c;
+}
+}  // namespace
+
+bool capturing() { return t_cap != nullptr; }
+
+int capture_event(hipEvent_t *ev) {
+    if (!t_cap) return set_error(TGBA_EINVAL, "capture_event outside a capture");
+    TGBA_HIP(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    t_cap->events.push_back(*ev);
+    return TGBA_OK;
+}
+
+int upload(const void *src, size_t bytes, int slot, hipStream_t st, void **dev) {
+    if (t_cap) {
+        const size_t b = (bytes + 255) & ~(size_t)255;
+        if (t_cap->chunks.empty() || t_cap->chunks.back().used + b > t_cap->chunks.back().cap) {
+            Capture::Chunk c;
+            c.cap = std::max(b, kUploadChunk);
+            if (hipMalloc((void **)&c.dev, c.cap) != hipSuccess) return set_error(TGBA_ENOMEM, "plan descriptor allocation failed");
+            t_cap->owned.push_back(c.dev);
+            t_cap->bytes += c.cap;
+            c.host.assign(c.cap, 0);
+            t_cap->chunks.push_back(std::move(c));
+        }
+        Capture::Chunk &c = t_cap->chunks.back();
+        if (bytes) std::memcpy(c.host.data() + c.used, src, bytes);
+        *dev = c.dev + c.used;
+        c.used += b;
+        return TGBA_OK;
+    }
+    void *ws = nullptr;
+    int rc = workspace_get(bytes, slot, &ws);
+    if (rc) return rc;
+    if (bytes) TGBA_HIP(hipMemcpyAsync(ws, src, bytes, hipMemcpyHostToDevice, st));
+    *dev = ws;
+    return TGBA_OK;
+}
+
 int workspace_get(size_t bytes, int slot, void **out) {
+    if (t_cap) {
+        if (slot < 0 || slot >= kSlots) return set_error(TGBA_EINVAL, "workspace slot out of range");
+        auto &e = t_cap->slots[slot];
+        if (e.second < bytes || !e.first) {
+            const size_t want = bytes < 4096 ? 4096 : bytes;
+            void *p = nullptr;
+            if (hipMalloc(&p, want) != hipSuccess) return set_error(TGBA_ENOMEM, "plan workspace allocation failed");
+            t_cap->owned.push_back(p);
+            t_cap->bytes += want;
+            e = {p, want};
+        }
+        *out = e.first;
+        return TGBA_OK;
+    }
     int dev = 0;
     TGBA_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= kDevices || slot < 0 || slot >= kSlots)
@@ -86,7 +162,7 @@ std::vector<Timed> g_pending;
 std::vector<hipEvent_t> g_pool;
 }  // namespace
 
-bool timing_on() { return g_timing; }
+bool timing_on() { return g_timing && !t_cap; }
 
 int timing_events(hipEvent_t *a, hipEvent_t *b) {
     std::lock_guard<std::mutex> lk(g_tmu);
@@ -122,13 +198,13 @@ int autotune(const std::string &key, int ncand, int fallback, const std::functio
              int *pick) {
     {
         std::lock_guard<std::mutex> lk(g_amu);
-        if (!g_autotune || ncand <= 1) {
-            *pick = fallback;
+        auto it = g_choices.find(key);
+        if (g_autotune && it != g_choices.end()) {
+            *pick = it->second.pick;
             return TGBA_OK;
         }
-        auto it = g_choices.find(key);
-        if (it != g_choices.end()) {
-            *pick = it->second.pick;
+        if (!g_autotune || ncand <= 1 || t_cap) {  // a capture never times: decided pick or the default
+            *pick = fallback;
             return TGBA_OK;
         }
     }
@@ -254,4 +330,91 @@ extern "C" int tgba_timing_read(double *ms, int64_t *launches, double *bytes) {
 extern "C" int tgba_release_workspace(void) {
     tgba::clear_error();
     return tgba::release_all_workspace();
+}
+
+// ---- plans ------------------------------------------------------------------------
+
+extern "C" int tgba_capture_begin(void *stream) {
+    tgba::clear_error();
+    using namespace tgba;
+    if (t_cap) return set_error(TGBA_EINVAL, "a capture is already active on this thread");
+    if (!stream) return set_error(TGBA_EINVAL, "a capture needs a created stream, not the NULL stream");
+    hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TGBA_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return set_error(TGBA_EINVAL, "the stream is already being captured");
+    TGBA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    t_cap = new Capture();
+    t_cap->st = st;
+    return TGBA_OK;
+}
+
+extern "C" int tgba_capture_end(void *stream, tgba_plan **out) {
+    tgba::clear_error();
+    using namespace tgba;
+    if (out) *out = nullptr;
+    Capture *c = t_cap;
+    if (!c) return set_error(TGBA_EINVAL, "no capture is active on this thread");
+    if ((hipStream_t)stream != c->st) return set_error(TGBA_EINVAL, "the capture was begun on another stream");
+    t_cap = nullptr;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->st, &g);
+    if (!out) {
+        if (g) (void)hipGraphDestroy(g);
+        capture_release(c, true);
+        return set_error(TGBA_EINVAL, "out must be non-NULL (the capture was discarded)");
+    }
+    if (e != hipSuccess || !g) {
+        capture_release(c, true);
+        return set_error(TGBA_EDEVICE, std::string("capture failed: ") + hipGetErrorString(e));
+    }
+    for (auto &ch : c->chunks) {
+        if (ch.used && hipMemcpy(ch.dev, ch.host.data(), ch.used, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            capture_release(c, true);
+            return set_error(TGBA_EDEVICE, "plan descriptor upload failed");
+        }
+    }
+    tgba_plan *p = new (std::nothrow) tgba_plan();
+    if (!p) {
+        (void)hipGraphDestroy(g);
+        capture_release(c, true);
+        return set_error(TGBA_ENOMEM, "host allocation failed");
+    }
+    p->graph = g;
+    size_t nn = 0;
+    (void)hipGraphGetNodes(g, nullptr, &nn);
+    p->nodes = (int64_t)nn;
+    p->owned.swap(c->owned);
+    p->bytes = c->bytes;
+    capture_release(c, false);
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        tgba_plan_free(p);
+        return set_error(TGBA_EDEVICE, "graph instantiation failed");
+    }
+    *out = p;
+    return TGBA_OK;
+}
+
+extern "C" void tgba_plan_free(tgba_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (void *q : p->owned) (void)hipFree(q);
+    delete p;
+}
+
+extern "C" int tgba_plan_launch(tgba_plan *p, void *stream) {
+    tgba::clear_error();
+    if (!p || !p->exec) return tgba::set_error(TGBA_EINVAL, "bad plan");
+    TGBA_HIP(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return TGBA_OK;
+}
+
+extern "C" int tgba_plan_info(const tgba_plan *p, int64_t *nodes, int64_t *bytes) {
+    tgba::clear_error();
+    if (!p) return tgba::set_error(TGBA_EINVAL, "bad plan");
+    if (nodes) *nodes = p->nodes;
+    if (bytes) *bytes = (int64_t)p->bytes;
+    return TGBA_OK;
 }

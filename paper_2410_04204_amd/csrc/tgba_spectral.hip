@@ -16,6 +16,7 @@
 // reordering the pair product into ascending momentum).
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "tgba_blas.h"
@@ -118,7 +119,8 @@ __global__ void phase_kernel(const double *w, const double *yr, const double *yi
 
 // per time column: sx = (B_re . GB_re + B_im . GB_im) / |c|^2, nrm = |B|
 __global__ void __launch_bounds__(256) quench_reduce_kernel(const double *Bm, const double *GB, int64_t n, int nt,
-                                                            double inv_c2, double *sx, double *nrm, double *Bout) {
+                                                            const double *c2, double *sx, double *nrm, double *Bout) {
+    const double inv_c2 = 1.0 / c2[0];
     const int q = blockIdx.x;
     double a1 = 0.0, a2 = 0.0;
     for (int64_t a = threadIdx.x; a < n; a += 256) {
@@ -238,17 +240,13 @@ __global__ void __launch_bounds__(256) corr_reduce_kernel(const double *Bm, cons
 
 using namespace tgba;
 
-extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
-                        int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
-                        void *stream) {
-    clear_error();
-    if (n <= 0 || !Z || !w || !G || !S || !omega || n_omega <= 0 || ldz < n || ldg < n || !(eta > 0.0))
-        return set_error(TGBA_EINVAL, "bad arguments");
-    hipStream_t st = (hipStream_t)stream;
-    void *ws = nullptr;
-    int rc = workspace_get(sizeof(double) * 3 * (size_t)n + 256, 15, &ws);
-    if (rc) return rc;
-    double *z0 = (double *)ws, *gz = z0 + n, *b = gz + n;
+namespace tgba {
+namespace {
+
+// S(omega) of one sector with the scratch `work` (3 n doubles: z0, G z0, b).
+int dsf_run(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg, int N_sites,
+            const double *omega, int n_omega, double eta, double *S, double *weights, double *work, hipStream_t st) {
+    double *z0 = work, *gz = z0 + n, *b = gz + n;
     hipLaunchKernelGGL(copy_col_kernel, dim3(256), dim3(256), 0, st, Z, z0, n);
     hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, gz, n);
     const int64_t tm = (n + 255) / 256;
@@ -258,6 +256,27 @@ extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w
                        2.0 * M_PI * (double)N_sites, S, weights, w);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
+}
+
+int dsf_check(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+              const double *omega, int n_omega, double eta, const double *S) {
+    if (n <= 0 || !Z || !w || !G || !S || !omega || n_omega <= 0 || ldz < n || ldg < n || !(eta > 0.0))
+        return set_error(TGBA_EINVAL, "bad arguments");
+    return TGBA_OK;
+}
+
+}  // namespace
+}  // namespace tgba
+
+extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+                        int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
+                        void *stream) {
+    clear_error();
+    int rc = dsf_check(n, Z, ldz, w, G, ldg, omega, n_omega, eta, S);
+    if (rc) return rc;
+    void *ws = nullptr;
+    if ((rc = workspace_get(sizeof(double) * 3 * (size_t)n + 256, ws::DsfWork, &ws))) return rc;
+    return dsf_run(n, Z, ldz, w, G, ldg, N_sites, omega, n_omega, eta, S, weights, (double *)ws, (hipStream_t)stream);
 }
 
 // ---- power spectrum of the quench signal (power-spectrum appendix) -------------
@@ -308,7 +327,7 @@ extern "C" int tgba_dsf_cross(int64_t nk, const double *Zk, int64_t ldz, const d
         return set_error(TGBA_EINVAL, "bad arguments");
     hipStream_t st = (hipStream_t)stream;
     void *ws = nullptr;
-    int rc = workspace_get(sizeof(double) * 2 * (size_t)nk + 256, 18, &ws);
+    int rc = workspace_get(sizeof(double) * 2 * (size_t)nk + 256, ws::DsfCrossWork, &ws);
     if (rc) return rc;
     double *gz = (double *)ws, *b = gz + nk;
     hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, gz, nk);
@@ -394,7 +413,7 @@ extern "C" int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double
     hipStream_t st = (hipStream_t)stream;
     const size_t cols = 2 * (size_t)nt;
     void *ws = nullptr;
-    int rc = workspace_get(sizeof(double) * (4 * (size_t)n + 3 * (size_t)n * cols + 64), 16, &ws);
+    int rc = workspace_get(sizeof(double) * (4 * (size_t)n + 3 * (size_t)n * cols + 64), ws::QuenchWork, &ws);
     if (rc) return rc;
     double *cr = (double *)ws, *ci = cr + n, *yr = ci + n, *yi = yr + n;
     double *U = yi + n, *Bm = U + n * cols, *GB = Bm + n * cols;
@@ -407,16 +426,18 @@ extern "C" int tgba_quench(int64_t n, const double *Z, int64_t ldz, const double
     TGBA_HIP(hipGetLastError());
     std::vector<GemmDesc> g(1);
     g[0] = GemmDesc{Z, ldz, U, n, Bm, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-    rc = dgemm_batched(g, 17, st);
+    rc = dgemm_batched(g, ws::QuenchGemm1, st);
     if (rc) return rc;
     g[0] = GemmDesc{G, ldg, Bm, n, GB, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-    rc = dgemm_batched(g, 18, st);
+    rc = dgemm_batched(g, ws::QuenchGemm2, st);
     if (rc) return rc;
-    double c2h = 0.0;
-    TGBA_HIP(hipMemcpyAsync(&c2h, c2, sizeof(double), hipMemcpyDeviceToHost, st));
-    TGBA_HIP(hipStreamSynchronize(st));
-    if (!(c2h > 0.0)) return set_error(TGBA_EINVAL, "initial state has zero overlap with the basis");
-    hipLaunchKernelGGL(quench_reduce_kernel, dim3(nt), dim3(256), 0, st, Bm, GB, n, nt, 1.0 / c2h, sx, nrm, B_out);
+    if (!capturing()) {  // a captured call cannot read |c|^2 back: a zero overlap then gives non-finite sx
+        double c2h = 0.0;
+        TGBA_HIP(hipMemcpyAsync(&c2h, c2, sizeof(double), hipMemcpyDeviceToHost, st));
+        TGBA_HIP(hipStreamSynchronize(st));
+        if (!(c2h > 0.0)) return set_error(TGBA_EINVAL, "initial state has zero overlap with the basis");
+    }
+    hipLaunchKernelGGL(quench_reduce_kernel, dim3(nt), dim3(256), 0, st, Bm, GB, n, nt, (const double *)c2, sx, nrm, B_out);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }
@@ -426,7 +447,7 @@ extern "C" int tgba_quench_weights(int64_t n, const double *Z, int64_t ldz, cons
     if (n <= 0 || !Z || !c || !w || ldz < n) return set_error(TGBA_EINVAL, "bad arguments");
     hipStream_t st = (hipStream_t)stream;
     void *ws = nullptr;
-    int rc = workspace_get(sizeof(double) * 4 * (size_t)n + 256, 19, &ws);
+    int rc = workspace_get(sizeof(double) * 4 * (size_t)n + 256, ws::QuenchWeights, &ws);
     if (rc) return rc;
     double *cr = (double *)ws, *ci = cr + n, *yr = ci + n, *yi = yr + n;
     hipLaunchKernelGGL(split_complex_kernel, dim3(256), dim3(256), 0, st, c, cr, ci, n);
@@ -496,7 +517,7 @@ extern "C" int tgba_quench_corr(int64_t n, const double *Z, int64_t ldz, const d
     const size_t per = (size_t)n * cols;
     const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nj, ((size_t)1 << 28) / per));
     void *ws = nullptr;
-    int rc = workspace_get(sizeof(double) * (4 * (size_t)n + 2 * per + (size_t)chunk * per + 64), 40, &ws);
+    int rc = workspace_get(sizeof(double) * (4 * (size_t)n + 2 * per + (size_t)chunk * per + 64), ws::QuenchCorrWork, &ws);
     if (rc) return rc;
     double *cr = (double *)ws, *ci = cr + n, *yr = ci + n, *yi = yr + n;
     double *U = yi + n, *Bm = U + per, *W = Bm + per, *c2 = W + (size_t)chunk * per;
@@ -508,7 +529,7 @@ extern "C" int tgba_quench_corr(int64_t n, const double *Z, int64_t ldz, const d
     TGBA_HIP(hipGetLastError());
     std::vector<GemmDesc> g(1);
     g[0] = GemmDesc{Z, ldz, U, n, Bm, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-    if ((rc = dgemm_batched(g, 41, st))) return rc;
+    if ((rc = dgemm_batched(g, ws::QuenchCorrGemm1, st))) return rc;
     double c2h = 0.0;
     TGBA_HIP(hipMemcpyAsync(&c2h, c2, sizeof(double), hipMemcpyDeviceToHost, st));
     TGBA_HIP(hipStreamSynchronize(st));
@@ -518,7 +539,7 @@ extern "C" int tgba_quench_corr(int64_t n, const double *Z, int64_t ldz, const d
         g.assign(cnt, GemmDesc{});
         for (int i = 0; i < cnt; ++i)
             g[i] = GemmDesc{O[i0 + i], ldo[i0 + i], Bm, n, W + (size_t)i * per, n, n, (int64_t)cols, n, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-        if ((rc = dgemm_batched(g, 42, st))) return rc;
+        if ((rc = dgemm_batched(g, ws::QuenchCorrGemm2, st))) return rc;
         hipLaunchKernelGGL(corr_reduce_kernel, dim3((unsigned)nt, (unsigned)cnt), dim3(256), 0, st, Bm, W, n, nt,
                            1.0 / c2h, sx, out + (size_t)i0 * nt);
         TGBA_HIP(hipGetLastError());

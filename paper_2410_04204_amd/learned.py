@@ -10,7 +10,9 @@
 
 `dim_for_gap` measures the second half of the headline metric: the smallest
 basis dimension, on a grid, at which the K = 0 gap is within `tol` of the
-reference (the whole candidate pool), for the energy order and the learned one.
+reference (an exact spectrum supplied by the caller, else the whole candidate
+pool), for the energy order and the learned one, with the E1 and m2/m1 errors
+and the wall time of each basis.
 """
 import time
 
@@ -73,31 +75,54 @@ def train(F, L, params0, epochs=200, batch=256, lr=1e-3, seed=0):
     return p, loss[:epochs].cpu().numpy()
 
 
-def k0_spectra(N, h, pool, chis, h_par=0.1, mlp=None, m_max=None, dev="cuda"):
-    """Lowest two K = 0 eigenvalues for every dimension in chis (one batched eigensolve)."""
+def k0_spectra(N, h, pool, chis, h_par=0.1, mlp=None, m_max=None, dev="cuda", levels=None):
+    """Lowest two K = 0 eigenvalues for every dimension in chis (one eigensolve per
+    dimension, eigenvalues only).  With levels=k: the k lowest, and the wall time of
+    each dimension (basis enumeration and scoring, assembly, eigensolve)."""
     import torch
-    Hs = []
+    out, secs = [], []
     for chi in chis:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         B = Basis(N, h, h_par, chi=[chi if K == 0 else 0 for K in range(N)], pool_e_cut=pool, m_max=m_max, mlp=mlp)
-        Hs.append(_k0_matrix(B, dev))
+        H = _k0_matrix(B, dev)
         B.free()
-    ws = [torch.empty(H.shape[0], dtype=torch.float64, device=dev) for H in Hs]
-    eig_batched(Hs, ws, TGBA_EIG_NOVEC)
-    return [(float(w[0]), float(w[1])) for w in ws]
+        w = torch.empty(H.shape[0], dtype=torch.float64, device=dev)
+        eig_batched([H], [w], TGBA_EIG_NOVEC)
+        k = levels or 2
+        out.append(tuple(float(x) for x in w[:k].cpu().numpy()))
+        secs.append(time.perf_counter() - t0)
+        del H
+    if levels is None:
+        return out
+    return out, secs
 
 
-def dim_for_gap(N, h, pool, grid, mlp, tol=1e-6, h_par=0.1, m_max=None, dev="cuda"):
-    """Smallest grid dimension with |gap - gap_ref| <= tol, energy order vs learned order."""
+def dim_for_gap(N, h, pool, grid, mlp, tol=1e-6, h_par=0.1, m_max=None, dev="cuda", reference=None):
+    """Smallest grid dimension with |gap - gap_ref| <= tol, energy order vs learned order.
+
+    reference: {"E1", "E2", "E3"} of the exact K = 0 spectrum (E3 - E1 = m2) when
+    known; otherwise the whole pool's lowest levels serve (self-referenced).
+    Per selector and grid point: the gap, E1 and m2/m1 errors and the wall time
+    of that basis (enumeration + scoring, assembly, eigensolve)."""
     t0 = time.perf_counter()
-    ref = k0_spectra(N, h, pool, [10 ** 9], h_par, None, m_max, dev)[0]
-    gref = ref[1] - ref[0]
-    out = {"reference": {"E1": ref[0], "gap": gref}, "grid": list(grid)}
+    if reference is None:
+        ref = k0_spectra(N, h, pool, [10 ** 9], h_par, None, m_max, dev, levels=3)[0][0]
+        reference = {"E1": ref[0], "E2": ref[1], "E3": ref[2], "kind": "self (whole pool)"}
+    gref = reference["E2"] - reference["E1"]
+    rref = (reference["E3"] - reference["E1"]) / gref
+    out = {"reference": dict(reference, gap=gref, m2_over_m1=rref), "grid": list(grid)}
     for name, p in (("cutoff", None), ("learned", mlp)):
-        sp = k0_spectra(N, h, pool, grid, h_par, p, m_max, dev)
-        err = [abs((b - a) - gref) for a, b in sp]
-        e1 = [a - ref[0] for a, _ in sp]
-        ok = [c for c, e in zip(grid, err) if e <= tol]
-        out[name] = {"dim": (min(ok) if ok else None), "gap_err": err, "E1_err": e1}
+        sp, secs = k0_spectra(N, h, pool, grid, h_par, p, m_max, dev, levels=3)
+        err = [abs((e[1] - e[0]) - gref) for e in sp]
+        e1 = [e[0] - reference["E1"] for e in sp]
+        r21 = [abs((e[2] - e[0]) / (e[1] - e[0]) - rref) for e in sp]
+        ok = [q for q, e in enumerate(err) if e <= tol]
+        q = min(ok) if ok else None
+        out[name] = {"dim": (grid[q] if q is not None else None), "gap_err": err, "E1_err": e1,
+                     "m2_over_m1_err": r21, "seconds_per_dim": secs,
+                     "at_dim": (None if q is None else {"E1_err": e1[q], "m2_over_m1_err": r21[q],
+                                                        "gap_err": err[q], "wall_s": secs[q]})}
     out["seconds"] = time.perf_counter() - t0
     return out
 

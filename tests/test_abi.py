@@ -74,3 +74,13 @@ def test_autotune_switches_and_empty_report():
     assert tg.autotune_report() == {}
     tg.autotune_enable(False)
     tg.autotune_enable(True)
+
+
+def test_capture_api_rejects_misuse_before_device_use():
+    from paper_2410_04204_amd import _lib
+    L = _lib.load()
+    assert L.tgba_capture_begin(None) == -1  # TGBA_EINVAL: the NULL stream cannot be captured
+    out = ctypes.c_void_p()
+    assert L.tgba_capture_end(None, ctypes.byref(out)) == -1  # no capture is active
+    assert out.value is None
+    assert L.tgba_plan_info(None, None, None) == -1
