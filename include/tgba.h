@@ -408,6 +408,22 @@ int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w, const dou
              void *stream);
 
 /*
+ * tgba_dsf without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, layout and result as tgba_dsf; the caller still
+ * owns every input and output.  Its scratch (3 n doubles: z0, G z0, b) is a
+ * static device array of TGBA_DSF_STATIC_MAX_N * 3 doubles (1.5 MiB) in the
+ * library, one per GPU, held until the process ends; n > TGBA_DSF_STATIC_MAX_N
+ * returns TGBA_EINVAL.  Every call on one GPU shares that array and leaves its
+ * contents behind (each call clears what it accumulates into), so calls that
+ * overlap on one GPU (different streams, different threads) race: serialize them.
+ */
+#define TGBA_DSF_STATIC_MAX_N 65536
+int tgba_dsf_static(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+                    int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
+                    void *stream);
+
+/*
  * S(k, omega_j) = 2 pi N sum_a |b_a|^2 (eta/pi) / ((omega_j - (wk_a - w0_0))^2 + eta^2),
  * b = Zk^T (X z0): the eigenpairs (Zk, wk) of sector k, the K = 0 ground state z0
  * (n0) with energy w0[0] (device), and X = tgba_assemble_cross(k, 0) (nk x n0).

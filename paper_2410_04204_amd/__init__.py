@@ -302,6 +302,15 @@ def dsf(Z, w, G, N_sites, omega, eta, S, weights=None, stream=None):
     return S
 
 
+def dsf_static(Z, w, G, N_sites, omega, eta, S, weights=None, stream=None):
+    """tgba_dsf with its scratch in the library's static device array (no allocation; n <= 65536)."""
+    n = w.shape[0]
+    _lib.check(_lib.load().tgba_dsf_static(int(n), _lib.ptr(Z), _ld(Z), _lib.ptr(w), _lib.ptr(G), _ld(G),
+                                           int(N_sites), _lib.ptr(omega), int(omega.shape[0]), float(eta),
+                                           _lib.ptr(S), _lib.ptr(weights), _lib.stream_handle(stream)))
+    return S
+
+
 def assemble_cross(basis, K_rows, K_cols, X, stream=None):
     """X[j][i] = <phi_j^(K_rows)|gamma_1|phi_i^(K_cols)> (real gauge; X shaped (n_cols, ld), column-major)."""
     _lib.check(_lib.load().tgba_assemble_cross(basis.handle, int(K_rows), int(K_cols), _lib.ptr(X), _ld(X),

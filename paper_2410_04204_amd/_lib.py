@@ -21,7 +21,7 @@ TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE = 0x0, 0x1, 0x2
 EXPORTS = [
     "tgba_last_error", "tgba_version", "tgba_build_basis", "tgba_basis_free", "tgba_basis_sector_size",
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
-    "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_quench", "tgba_quench_overlaps",
+    "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_dsf_static", "tgba_quench", "tgba_quench_overlaps",
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_eig_batched_vec", "tgba_sytrd", "tgba_sytrd_2stage", "tgba_stebz",
     "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_timing_read_channel", "tgba_power_spectrum", "tgba_basis_align", "tgba_quench_eps", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
@@ -78,6 +78,8 @@ def load():
     L.tgba_assemble_heff_batched.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
     L.tgba_eig.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_int, c_void_p]
     L.tgba_dsf.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int,
+                           c_double, c_void_p, c_void_p, c_void_p]
+    L.tgba_dsf_static.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int,
                            c_double, c_void_p, c_void_p, c_void_p]
     L.tgba_quench.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_double,
                               c_double, c_int, c_void_p, c_void_p, c_void_p, c_void_p]

@@ -16,6 +16,7 @@
 // reordering the pair product into ascending momentum).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -265,6 +266,32 @@ int dsf_check(int64_t n, const double *Z, int64_t ldz, const double *w, const do
     return TGBA_OK;
 }
 
+// Static scratch of the allocation-free DSF: z0, G z0 and b for sectors of up
+// to kDsfStaticMaxN states, one copy per device, held until the process ends.
+// Host code never passes `scratch` itself to a kernel: the name is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kDsfStaticMaxN = TGBA_DSF_STATIC_MAX_N;
+__device__ __align__(256) double scratch[3 * kDsfStaticMaxN];
+constexpr int kScratchDevices = 16;
+std::mutex g_scratch_mu;
+double *g_scratch[kScratchDevices] = {};
+
+int static_scratch(double **out) {
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return set_error(TGBA_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(TGBA_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = (double *)p;
+    }
+    *out = g_scratch[dev];
+    return TGBA_OK;
+}
+
 }  // namespace
 }  // namespace tgba
 
@@ -277,6 +304,20 @@ extern "C" int tgba_dsf(int64_t n, const double *Z, int64_t ldz, const double *w
     void *ws = nullptr;
     if ((rc = workspace_get(sizeof(double) * 3 * (size_t)n + 256, ws::DsfWork, &ws))) return rc;
     return dsf_run(n, Z, ldz, w, G, ldg, N_sites, omega, n_omega, eta, S, weights, (double *)ws, (hipStream_t)stream);
+}
+
+extern "C" int tgba_dsf_static(int64_t n, const double *Z, int64_t ldz, const double *w, const double *G, int64_t ldg,
+                               int N_sites, const double *omega, int n_omega, double eta, double *S, double *weights,
+                               void *stream) {
+    clear_error();
+    int rc = dsf_check(n, Z, ldz, w, G, ldg, omega, n_omega, eta, S);
+    if (rc) return rc;
+    if (n > kDsfStaticMaxN)
+        return set_error(TGBA_EINVAL, "tgba_dsf_static: n = " + std::to_string(n) + " exceeds the static scratch (" +
+                                          std::to_string(kDsfStaticMaxN) + " states)");
+    double *work = nullptr;
+    if ((rc = static_scratch(&work))) return rc;
+    return dsf_run(n, Z, ldz, w, G, ldg, N_sites, omega, n_omega, eta, S, weights, work, (hipStream_t)stream);
 }
 
 // ---- power spectrum of the quench signal (power-spectrum appendix) -------------
