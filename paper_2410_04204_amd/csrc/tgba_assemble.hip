@@ -130,15 +130,18 @@ __device__ __forceinline__ void phase_mi(int q, double v, double &re, double &im
 }
 
 // Packed upper-triangular tables of the ROWS per-row Schur complements S_a
-// (N x N, skew) are interleaved in LDS: element (u, v), u < v, of row r sits at
-//     tabs[(rowoff(u) + v) * ROWS + r],   rowoff(u) = u*N - u(u+1)/2 - u - 1,
-// so one address computation serves all rows of the workgroup (the row is an
-// immediate offset of the LDS load).
+// (N x N, skew) follow one another in LDS: element (u, v), u < v, of row r sits at
+//     tabs[r * ts + rowoff(u) + v],   rowoff(u) = u*N - u(u+1)/2 - u - 1,
+// ts = N(N-1)/2 rounded up to even.  One pair offset per ket serves all rows of
+// the workgroup (the row adds a uniform offset).  Consecutive pairs of a row are
+// 8 bytes apart, so the 64 lanes of a wave, each gathering its own ket's pair,
+// spread over all LDS banks; with the rows interleaved (pairs 8 ROWS bytes
+// apart) they met in ROWS times fewer banks.
 __device__ __forceinline__ int rowoff_of(int u, int N) { return u * N - (u * (u + 1)) / 2 - u - 1; }
 
 template <int ROWS>
-__device__ __forceinline__ double skew_at(const double *tabs, const int *s_rowoff, int r, int u, int v) {
-    return (u < v) ? tabs[(s_rowoff[u] + v) * ROWS + r] : -tabs[(s_rowoff[v] + u) * ROWS + r];
+__device__ __forceinline__ double skew_at(const double *tabs, const int *s_rowoff, int ts, int r, int u, int v) {
+    return (u < v) ? tabs[r * ts + s_rowoff[u] + v] : -tabs[r * ts + s_rowoff[v] + u];
 }
 
 // Pfaffian of the M x M skew matrix in A (row-major, ld kGenMax), destroyed.
@@ -179,7 +182,7 @@ __device__ __noinline__ double pf_eliminate(double *A, int M) {
 // Rare paths (private memory): a ket with more than 10 quasiparticles on the
 // row's Schur table, or a flagged row evaluated directly as Pf(R[I_a u I_b]).
 template <int ROWS, int NJ>
-__device__ __noinline__ double element_generic(const double *tabs, const int *s_rowoff, int r, int N, uint64_t ket,
+__device__ __noinline__ double element_generic(const double *tabs, const int *s_rowoff, int ts, int r, int N, uint64_t ket,
                                                int flagged, uint64_t bra, const double *__restrict__ R,
                                                unsigned long long *counters) {
     int g[kGenMax];
@@ -204,7 +207,7 @@ __device__ __noinline__ double element_generic(const double *tabs, const int *s_
     for (int i = 0; i < M; ++i) {
         A[i * kGenMax + i] = 0.0;
         for (int j = i + 1; j < M; ++j) {
-            const double v = flagged ? R[g[i] * n2 + g[j]] : tabs[(s_rowoff[g[i]] + g[j]) * ROWS + r];
+            const double v = flagged ? R[g[i] * n2 + g[j]] : tabs[r * ts + s_rowoff[g[i]] + g[j]];
             A[i * kGenMax + j] = v;
             A[j * kGenMax + i] = -v;
         }
@@ -222,9 +225,11 @@ struct KetIdx {
     static constexpr int MI = MB > 0 ? MB : 1;
     static constexpr int NP = (MB >= 2 && MB <= 6) ? MB * (MB - 1) / 2 : ((MB >= 8 && MB <= 10) ? MB - 1 : 1);
     int idx[MI], roff[MI], base[NP];
+    int ts;  // row stride of the tables
 
     template <int ROWS>
-    __device__ __forceinline__ void init(uint64_t ket, const int *s_rowoff) {
+    __device__ __forceinline__ void init(uint64_t ket, const int *s_rowoff, int tstride) {
+        ts = tstride;
         if constexpr (MB > 0) {
             uint64_t x = ket;
 #pragma unroll
@@ -239,10 +244,10 @@ struct KetIdx {
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
-                for (int j = i + 1; j < MB; ++j) base[t++] = (roff[i] + idx[j]) * ROWS;
+                for (int j = i + 1; j < MB; ++j) base[t++] = roff[i] + idx[j];
         } else if constexpr (MB >= 8 && MB <= 10) {
 #pragma unroll
-            for (int j = 1; j < MB; ++j) base[j - 1] = (roff[0] + idx[j]) * ROWS;
+            for (int j = 1; j < MB; ++j) base[j - 1] = roff[0] + idx[j];
         }
     }
 };
@@ -264,12 +269,12 @@ __device__ __forceinline__ double pf_ket(const double *tabs, const int *s_rowoff
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = i + 1; j < MB; ++j) a[i][j] = tabs[K.base[t++] + r] + md(i, j);
+            for (int j = i + 1; j < MB; ++j) a[i][j] = tabs[r * K.ts + K.base[t++]] + md(i, j);
         return pf_rec<(1u << MB) - 1u>(a);
     } else if constexpr (MB >= 8 && MB <= 10) {
         double r0[MB];
 #pragma unroll
-        for (int j = 1; j < MB; ++j) r0[j] = tabs[K.base[j - 1] + r] + md(0, j);
+        for (int j = 1; j < MB; ++j) r0[j] = tabs[r * K.ts + K.base[j - 1]] + md(0, j);
         int p = 1;
         double best = fabs(r0[1]);
 #pragma unroll
@@ -301,7 +306,7 @@ __device__ __forceinline__ double pf_ket(const double *tabs, const int *s_rowoff
             } else {
                 Xr[t] = Yr[t] = 0.0;
             }
-            x[t] = skew_at<ROWS>(tabs, s_rowoff, r, ip, ri[t]) + (MOD ? (Xp * Yr[t] - Yp * Xr[t]) * inv : 0.0);
+            x[t] = skew_at<ROWS>(tabs, s_rowoff, K.ts, r, ip, ri[t]) + (MOD ? (Xp * Yr[t] - Yp * Xr[t]) * inv : 0.0);
         }
         const double ipiv = 1.0 / piv;
         double a[10][10];
@@ -309,7 +314,7 @@ __device__ __forceinline__ double pf_ket(const double *tabs, const int *s_rowoff
         for (int t = 0; t < MB - 2; ++t)
 #pragma unroll
             for (int u = t + 1; u < MB - 2; ++u)
-                a[t][u] = tabs[(ro[t] + ri[u]) * ROWS + r] + (MOD ? (Xr[t] * Yr[u] - Yr[t] * Xr[u]) * inv : 0.0) +
+                a[t][u] = tabs[r * K.ts + ro[t] + ri[u]] + (MOD ? (Xr[t] * Yr[u] - Yr[t] * Xr[u]) * inv : 0.0) +
                           (x[t] * y[u] - y[t] * x[u]) * ipiv;
         const double sgn = (p & 1) ? 1.0 : -1.0;  // (-1)^(p-1)
         return sgn * piv * pf_rec<(1u << (MB - 2)) - 1u>(a);
@@ -321,19 +326,19 @@ __device__ __forceinline__ double pf_ket(const double *tabs, const int *s_rowoff
 // Pf(S_r[I_b]) * factor_r for all valid rows that are neither flagged nor
 // deflated, for a ket of MB quasiparticles (MB < 0: more than 10, generic).
 template <int MB, int ROWS, int NJ>
-__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, const int *s_rowoff, int N,
+__device__ __forceinline__ void row_values(double (&val)[ROWS], const double *tabs, const int *s_rowoff, int ts, int N,
                                            uint64_t ket, int nvalid, const int *s_flag, const int *s_defl,
                                            const uint64_t *s_bra, const double *s_fac, const double *__restrict__ R,
                                            unsigned long long *counters) {
     constexpr int MK = MB > 0 ? MB : 0;
     KetIdx<MK> K;
-    if constexpr (MB >= 0) K.template init<ROWS>(ket, s_rowoff);
+    if constexpr (MB >= 0) K.template init<ROWS>(ket, s_rowoff, ts);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         double pfv = 0.0;
         if (r < nvalid && !s_defl[r]) {
             if (MB < 0 || s_flag[r]) {
-                pfv = element_generic<ROWS, NJ>(tabs, s_rowoff, r, N, ket, s_flag[r], s_bra[r], R, counters);
+                pfv = element_generic<ROWS, NJ>(tabs, s_rowoff, ts, r, N, ket, s_flag[r], s_bra[r], R, counters);
             } else {
                 pfv = pf_ket<MK, ROWS, false>(tabs, s_rowoff, r, K, nullptr, nullptr, 0.0);
             }
@@ -361,10 +366,10 @@ __device__ __forceinline__ constexpr int dd_pair(int i, int j) {
 }
 
 template <int MB, int ROWS>
-__device__ __forceinline__ double defl2_value(const double *tabs, const int *s_rowoff, const double *dk, int r,
+__device__ __forceinline__ double defl2_value(const double *tabs, const int *s_rowoff, int ts, const double *dk, int r,
                                               int N, uint64_t ket, double delta, double Delta) {
     KetIdx<MB> K;
-    K.template init<ROWS>(ket, s_rowoff);
+    K.template init<ROWS>(ket, s_rowoff, ts);
     double X[KetIdx<MB>::MI], Y[KetIdx<MB>::MI];
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
@@ -379,7 +384,7 @@ __device__ __forceinline__ double defl2_value(const double *tabs, const int *s_r
 // Pf(S_r[J u I_b]) by pivoted elimination in private memory (four kept bra
 // indices, or a ket of more than 10 quasiparticles).
 template <int ROWS>
-__device__ __noinline__ double defl_generic(const double *tabs, const int *s_rowoff, const double *dk,
+__device__ __noinline__ double defl_generic(const double *tabs, const int *s_rowoff, int ts, const double *dk,
                                             const double *dd, int r, int N, uint64_t ket, int d,
                                             unsigned long long *counters) {
     int g[kGenMax];
@@ -396,7 +401,7 @@ __device__ __noinline__ double defl_generic(const double *tabs, const int *s_row
             double v;
             if (j < d) v = dd[dd_pair(i, j)];
             else if (i < d) v = dk[(r * kMaxDefl + i) * N + g[j]];
-            else v = tabs[(s_rowoff[g[i]] + g[j]) * ROWS + r];
+            else v = tabs[r * ts + s_rowoff[g[i]] + g[j]];
             A[i * kGenMax + j] = v;
             A[j * kGenMax + i] = -v;
         }
@@ -406,22 +411,22 @@ __device__ __noinline__ double defl_generic(const double *tabs, const int *s_row
 }
 
 template <int ROWS>
-__device__ __forceinline__ double deflated_value(const double *tabs, const int *s_rowoff, const double *dk,
+__device__ __forceinline__ double deflated_value(const double *tabs, const int *s_rowoff, int ts, const double *dk,
                                                  const double *dd, int r, int N, uint64_t ket, int Mb, int d,
                                                  double Delta, unsigned long long *counters) {
     if (d == 2) {
         const double delta = dd[0];
         switch (Mb) {
             case 0: return delta;
-            case 2: return defl2_value<2, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
-            case 4: return defl2_value<4, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
-            case 6: return defl2_value<6, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
-            case 8: return defl2_value<8, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
-            case 10: return defl2_value<10, ROWS>(tabs, s_rowoff, dk, r, N, ket, delta, Delta);
+            case 2: return defl2_value<2, ROWS>(tabs, s_rowoff, ts, dk, r, N, ket, delta, Delta);
+            case 4: return defl2_value<4, ROWS>(tabs, s_rowoff, ts, dk, r, N, ket, delta, Delta);
+            case 6: return defl2_value<6, ROWS>(tabs, s_rowoff, ts, dk, r, N, ket, delta, Delta);
+            case 8: return defl2_value<8, ROWS>(tabs, s_rowoff, ts, dk, r, N, ket, delta, Delta);
+            case 10: return defl2_value<10, ROWS>(tabs, s_rowoff, ts, dk, r, N, ket, delta, Delta);
             default: break;
         }
     }
-    return defl_generic<ROWS>(tabs, s_rowoff, dk, dd, r, N, ket, d, counters);
+    return defl_generic<ROWS>(tabs, s_rowoff, ts, dk, dd, r, N, ket, d, counters);
 }
 
 // 3 waves per SIMD (<= 168 VGPRs): the LDS of a workgroup at N = 40 allows 3
@@ -443,12 +448,13 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
     const double *__restrict__ R = NJ ? D.tab : R_model;
     const double r_max = NJ ? D.rmax : r_max_model;
     const double c0 = NJ ? D.fac : c0_model;
-    const int ts = 2 * N + NJ;  // table row stride
+    const int rts = 2 * N + NJ;  // row stride of the model (or string) table R
     const int64_t a0 = (int64_t)(blockIdx.x - D.first_block) * ROWS;
     const int ntab = N * (N - 1) / 2;
+    const int ts = (ntab + 1) & ~1;          // row stride of the tables
     const int wdim = D.max_m_bra + N;
-    double *tabs = lds;                      // ntab x ROWS interleaved
-    double *W = lds + ROWS * ntab;           // dense scratch wdim x wdim
+    double *tabs = lds;                      // ROWS tables of ts doubles
+    double *W = lds + ROWS * ts;             // dense scratch wdim x wdim
     double *dk = W + wdim * wdim;            // deflated rows: ROWS x kMaxDefl x N
     __shared__ double s_fac[ROWS];
     __shared__ double s_dd[ROWS][kMaxDefl * (kMaxDefl - 1) / 2];
@@ -486,7 +492,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const int gi = (i < Ma) ? s_bidx[i] : N + (i - Ma);
             for (int j = tx; j < n; j += 64) {
                 const int gj = (j < Ma) ? s_bidx[j] : N + (j - Ma);
-                W[i * wdim + j] = R[gi * ts + gj];
+                W[i * wdim + j] = R[gi * rts + gj];
             }
         }
         __syncthreads();
@@ -575,7 +581,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const int ro = s_rowoff[u];
             for (int v = u + 1 + tx; v < N; v += 64) {
                 const double val = W[(Ma + u) * wdim + Ma + v];
-                tabs[(ro + v) * ROWS + r] = val;
+                tabs[r * ts + ro + v] = val;
                 g = fmax(g, fabs(val));
             }
         }
@@ -657,13 +663,13 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         const int Mb = __popcll(ket);
         double val[ROWS];
         switch (Mb) {
-            case 0: row_values<0, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 2: row_values<2, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 4: row_values<4, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 6: row_values<6, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 8: row_values<8, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            case 10: row_values<10, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
-            default: row_values<-1, ROWS, NJ>(val, tabs, s_rowoff, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 0: row_values<0, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 2: row_values<2, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 4: row_values<4, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 6: row_values<6, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 8: row_values<8, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            case 10: row_values<10, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
+            default: row_values<-1, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
         }
         if constexpr (NJ > 0) {
             const double cs = D.csign ? D.csign[b] : 1.0;
@@ -688,7 +694,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             for (int r = 0; r < nvalid; ++r) {
                 const int d = s_defl[r];
                 if (!d) continue;
-                double v = s_fac[r] * deflated_value<ROWS>(tabs, s_rowoff, dk, s_dd[r], r, N, ket, Mb, d, r_max, counters);
+                double v = s_fac[r] * deflated_value<ROWS>(tabs, s_rowoff, ts, dk, s_dd[r], r, N, ket, Mb, d, r_max, counters);
                 if constexpr (NJ > 0) v *= D.csign ? D.csign[b] : 1.0;
                 if constexpr (CPLX) {
                     double re, im;
@@ -816,8 +822,8 @@ int asm_setup(const Basis *b, int nsec, const int *Ks, void *const *H, const int
 // Dynamic LDS of the rows kernel: the ROWS interleaved N x N tables, the
 // elimination scratch (max_m + N)^2 and the deflated rows' kMaxDefl x N blocks.
 size_t asm_lds(int rows, int N, int max_m) {
-    return sizeof(double) * ((size_t)rows * N * (N - 1) / 2 + (size_t)(max_m + N) * (max_m + N) +
-                             (size_t)rows * kMaxDefl * N);
+    const size_t ts = ((size_t)N * (N - 1) / 2 + 1) & ~(size_t)1;  // table row stride (as in the kernel)
+    return sizeof(double) * ((size_t)rows * ts + (size_t)(max_m + N) * (max_m + N) + (size_t)rows * kMaxDefl * N);
 }
 
 // Block layout for `rows` bra rows per workgroup; returns the grid size and LDS bytes.
