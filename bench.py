@@ -112,7 +112,17 @@ def cpu_baseline(w, B, seconds):
         seed += 1
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": done / dt, "unit": "H_eff elements/s", "cores": cores, "kind": "oracle",
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": done / dt, "unit": "H_eff elements/s", "cores": cores, "cpu_model": model,
+            "host_threads": os.cpu_count(), "kind": "oracle",
             "sample": f"{done} seeded (row, col) pairs of the K=0 sector ({n_ns}x{n_r} NS x R block), "
                       f"literal Wick-Pfaffian of size 2N+m, {dt:.1f} s"}
 
@@ -385,10 +395,10 @@ def correlator_study(N=60, chi=2000, m_max=6, js=tuple(range(1, 31)), t_max=20.0
     return out
 
 
-def overlap_study(chis=(1000, 2000, 4000, 8000), pool=14.0, m_max=6, h_pre=0.5, s=1, t_max=60.0, dt=0.05):
+def overlap_study(chis=(1000, 2000, 4000, 8000, 12000), pool=14.0, m_max=10, h_pre=0.5, s=1, t_max=60.0, dt=0.05):
     """Overlap-ranked truncation and its convergence (Quench section, eq. 10): N = 40 K = 0,
     the chi states with the largest |<phi|Phi_0>| among the candidates with at most m_max
-    quasiparticles and E - E0 <= pool (the paper first caps the quasiparticle number), the
+    quasiparticles (10: Appendix B keeps 8-10 near criticality) and E - E0 <= pool, the
     quench (h_pre, 0) -> (1, 0.1) from (|0>_NS + s |0>_R)/sqrt(2), B(t) to t_max, and
     eps(chi', chi) between successive dimensions; also the coverage sum |<phi|Phi_0>|^2
     and <sigma^x>(t_max)."""

@@ -979,7 +979,7 @@ int assemble_cross(const Basis *b, int Kr, int Kc, double *X, int64_t ld, hipStr
     void *ws = nullptr;
     int rc = workspace_get(2 * sizeof(SectorDesc), ws::CrossDesc, &ws);
     if (rc) return rc;
-    TGBA_HIP(hipMemcpyAsync(ws, d.data(), 2 * sizeof(SectorDesc), hipMemcpyHostToDevice, stream));
+    if ((rc = staged_copy(ws, d.data(), 2 * sizeof(SectorDesc), ws::CrossDesc, stream))) return rc;
     AsmSetup o;
     o.cplx = false;
     o.lower = 0;
@@ -1074,9 +1074,10 @@ int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O
             x.nblk = (cnt + rows - 1) / rows;
             nblocks += x.nblk;
         }
-    TGBA_HIP(hipMemcpyAsync(d_tab, htab.data(), sizeof(double) * htab.size(), hipMemcpyHostToDevice, stream));
-    TGBA_HIP(hipMemcpyAsync(d_sign, hsign.data(), sizeof(double) * hsign.size(), hipMemcpyHostToDevice, stream));
-    TGBA_HIP(hipMemcpyAsync(d_desc, d.data(), ndesc * sizeof(SectorDesc), hipMemcpyHostToDevice, stream));
+    if ((rc = staged_copy(d_tab, htab.data(), sizeof(double) * htab.size(), ws::CorrWork, stream)) ||
+        (rc = staged_copy(d_sign, hsign.data(), sizeof(double) * hsign.size(), ws::CorrWork, stream)) ||
+        (rc = staged_copy(d_desc, d.data(), ndesc * sizeof(SectorDesc), ws::CorrWork, stream)))
+        return rc;
     for (int i = 0; i < nj; ++i)  // the parity-changing blocks
         if (nn > 0 && nr > 0) {
             hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, stream, O[i] + nn, ld[i], nr, nn);
@@ -1085,8 +1086,7 @@ int assemble_corr(const Basis *b, int K, int nj, const int *js, double *const *O
     TGBA_HIP(hipGetLastError());
     if (nblocks == 0) return TGBA_OK;
     const size_t lds = asm_lds(rows, N, mb + 2);
-    // hipMemcpyAsync from pageable host memory returns once the data is staged,
-    // so the host vectors may go out of scope after this point
+    // the host vectors were copied into pinned staging: they may go out of scope
     hipEvent_t ta = nullptr, tb = nullptr;
     if (timing_on() && (rc = timing_events(&ta, &tb))) return rc;
     rc = (rows == 4)

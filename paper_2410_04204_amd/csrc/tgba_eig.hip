@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_col_update(TriSecT<T> *secs
         const int64_t r = rb0 + lane;
         T acc = T(0);
         if (r < n)
+#pragma unroll 4
             for (int t = grp; t + 1 < i; t += kWGroups)
                 acc += S.A[r + (int64_t)(j0 + t) * S.lda] * wc[t] + S.W[r + (int64_t)t * S.ldw] * vc[t];
         part[grp][lane] = acc;
@@ -348,12 +349,27 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSecT<T> *secs, int c, 
     const T *Pt = Pcol + symv_segments(n) * n;
     const int64_t nG = symv_segments(n - o);
     __shared__ T t12[2 * kNB];
+    __shared__ T t12p[kWGroups / 2][2 * kNB];
     __shared__ T part[kWGroups][64];
-    if ((int)threadIdx.x < 2 * i) {
-        const int idx = ((int)threadIdx.x < i) ? threadIdx.x : kNB + threadIdx.x - i;
+    static_assert(64 * kWGroups == (kWGroups / 2) * 2 * kNB, "t1, t2 gather: 2 kNB entries x kWGroups / 2 parts");
+    {   // t1, t2 from the segment partials: every thread adds a few segments, then
+        // one thread per entry adds the parts in a fixed order (no serial chain of loads)
+        const int q = threadIdx.x % (2 * kNB), gp = threadIdx.x / (2 * kNB);
         T a = T(0);
-        for (int64_t g = 0; g < nG; ++g) a += Pt[g * 2 * kNB + idx];
-        t12[idx] = a;
+        if (q < 2 * i) {
+            const int idx = (q < i) ? q : kNB + q - i;
+#pragma unroll 4
+            for (int64_t g = gp; g < nG; g += kWGroups / 2) a += Pt[g * 2 * kNB + idx];
+        }
+        t12p[gp][q] = a;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * i) {
+        const int q = threadIdx.x;
+        T a = T(0);
+#pragma unroll
+        for (int gp = 0; gp < kWGroups / 2; ++gp) a += t12p[gp][q];
+        t12[(q < i) ? q : kNB + q - i] = a;
     }
     __syncthreads();
     const T tau = sc[S_TAU], scale = sc[S_SCALE];
@@ -369,6 +385,7 @@ __global__ void __launch_bounds__(64 * kWGroups) tri_w(TriSecT<T> *secs, int c, 
 #pragma unroll 4
             for (int64_t J = grp; J <= Jr; J += kWGroups) y += Prow[J * n + r];
             for (int64_t g = grp; g < nGr; g += kWGroups) y += Pcol[g * n + r];
+#pragma unroll 4
             for (int t = grp; t < i; t += kWGroups)
                 y -= S.A[r + (int64_t)(j0 + t) * S.lda] * t12[t] + S.W[r + (int64_t)t * S.ldw] * t12[kNB + t];
         }

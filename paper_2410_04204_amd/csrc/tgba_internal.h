@@ -87,11 +87,15 @@ static_assert(ws::Count <= kWorkspaceSlots, "more workspace slots than the cache
 int workspace_get(size_t bytes, int slot, void **out);
 
 // Host -> device copy of launch descriptors read by the next kernels on `st`.
-// Eager: into the workspace of `slot`, ordered on the stream.  While this
+// Eager: into the workspace of `slot`, ordered on the stream, through pinned
+// staging (staged_copy).  While this
 // thread captures a plan: into a fresh piece of plan-owned memory (every
 // captured kernel keeps its own descriptors), filled once when the capture
 // ends; nothing is queued on the stream.
 int upload(const void *src, size_t bytes, int slot, hipStream_t st, void **dev);
+// The eager copy behind upload: host -> device through a pinned staging buffer of
+// `slot` (the caller's memory may be pageable and freed right after the call).
+int staged_copy(void *dst, const void *src, size_t bytes, int slot, hipStream_t st);
 
 // True while this thread records library calls into a plan (tgba_capture_begin):
 // such calls queue work only -- no host reads of device data, no waits, no

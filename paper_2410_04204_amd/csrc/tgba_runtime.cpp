@@ -52,6 +52,57 @@ void capture_release(Capture *c, bool free_memory) {
 
 bool capturing() { return t_cap != nullptr; }
 
+// ---- pinned staging of descriptor uploads ------------------------------------------
+// An asynchronous host-to-device copy reads its source from pinned memory owned
+// here, never from the caller's (pageable, short-lived) vector: each slot has a
+// ring of kStageRing pinned buffers, and an entry is refilled only after the
+// event recorded behind its previous copy has completed.
+namespace {
+constexpr int kStageRing = 8;
+struct Stage {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+struct StageRing {
+    std::mutex mu;
+    Stage e[kStageRing];
+    int next = 0;
+};
+StageRing g_stage[kDevices][kSlots];
+}  // namespace
+
+int staged_copy(void *dst, const void *src, size_t bytes, int slot, hipStream_t st) {
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kDevices || slot < 0 || slot >= kSlots)
+        return set_error(TGBA_EINVAL, "staging slot out of range");
+    StageRing &R = g_stage[dev][slot];
+    std::lock_guard<std::mutex> lk(R.mu);
+    Stage &e = R.e[R.next];
+    R.next = (R.next + 1) % kStageRing;
+    if (e.pending) {  // the entry's previous copy must have read its buffer
+        TGBA_HIP(hipEventSynchronize(e.done));
+        e.pending = false;
+    }
+    if (e.cap < bytes) {
+        if (e.host) TGBA_HIP(hipHostFree(e.host));
+        e.host = nullptr;
+        e.cap = 0;
+        const size_t want = bytes < 4096 ? 4096 : bytes;
+        if (hipHostMalloc(&e.host, want, hipHostMallocDefault) != hipSuccess)
+            return set_error(TGBA_ENOMEM, "pinned staging allocation failed");
+        e.cap = want;
+    }
+    if (!e.done) TGBA_HIP(hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
+    std::memcpy(e.host, src, bytes);
+    TGBA_HIP(hipMemcpyAsync(dst, e.host, bytes, hipMemcpyHostToDevice, st));
+    TGBA_HIP(hipEventRecord(e.done, st));
+    e.pending = true;
+    return TGBA_OK;
+}
+
 int capture_event(hipEvent_t *ev) {
     if (!t_cap) return set_error(TGBA_EINVAL, "capture_event outside a capture");
     TGBA_HIP(hipEventCreateWithFlags(ev, hipEventDisableTiming));
@@ -80,7 +131,7 @@ int upload(const void *src, size_t bytes, int slot, hipStream_t st, void **dev) 
     void *ws = nullptr;
     int rc = workspace_get(bytes, slot, &ws);
     if (rc) return rc;
-    if (bytes) TGBA_HIP(hipMemcpyAsync(ws, src, bytes, hipMemcpyHostToDevice, st));
+    if (bytes && (rc = staged_copy(ws, src, bytes, slot, st))) return rc;
     *dev = ws;
     return TGBA_OK;
 }

@@ -1,12 +1,17 @@
 """Learned truncation versus the energy cutoff (empirical; parity unpinned).
 
-The network is trained on the device (tgba_mlp_train) on K = 0 eigenvector
-weights of large-cutoff runs at N = 16..22, then selects the N = 24 K = 0
-basis from the E_cut = 14 pool.  The claim checked: at equal dimension the
-learned basis has the smaller gap error, and it reaches a 1e-6 gap error with
-a smaller dimension.  No oracle decides this (it is an empirical comparison);
-every step it uses is parity-tested elsewhere.
+The network is trained on the device (tgba_mlp_train) on the K = 0 eigenvector
+weights of large-cutoff runs at N = 14, 18, 22, then selects the K = 0 basis of
+N = 20 (held out) from the E_cut = 14 pool.  The reference is the exact K = 0
+spectrum of eq. 3 (the oracle's Lanczos ED, tests/golden/exact_gap_k0.txt).
+The claims checked: wherever the cutoff basis is still more than 1e-7 off the
+exact gap, the learned basis of the same dimension is closer, and the learned
+basis reaches a 1e-6 gap error with a smaller dimension.  No oracle decides
+this (it is an empirical comparison); every step it uses is parity-tested
+elsewhere.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -14,22 +19,32 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TRAIN_RUNS = [(16, 1.0, 14.0), (20, 1.0, 12.0), (20, 0.9, 12.0), (20, 1.1, 12.0), (22, 1.0, 11.0)]
+TRAIN_RUNS = [(14, 1.0, 30.0), (18, 1.0, 13.0), (18, 0.9, 13.0), (18, 1.1, 13.0), (22, 1.0, 11.5)]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_gap_k0.txt")
 
 
-def test_learned_basis_beats_energy_cutoff():
+def _exact(N):
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            p = line.split()
+            if int(p[0]) == N:
+                return {"E1": float(p[3]), "E2": float(p[4]), "E3": float(p[5])}
+    raise KeyError(N)
+
+
+def test_learned_basis_beats_energy_cutoff_against_exact_gap():
     import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
     from paper_2410_04204_amd import learned
+    assert torch.cuda.is_available()
     F, L = learned.training_data(TRAIN_RUNS)
     p0 = torch.as_tensor(workloads.mlp_params(0).astype(np.float32), device="cuda")
-    p, loss = learned.train(F, L, p0, epochs=200)
+    p, loss = learned.train(F, L, p0, epochs=300)
     assert loss[-1] < 0.1 * loss[0]
-    grid = [200, 400, 800, 1600, 3200]
-    r = learned.dim_for_gap(24, 1.0, 14.0, grid, p)
-    print(r)
+    grid = [200, 300, 400, 500, 600, 800, 1000]
+    r = learned.dim_for_gap(20, 1.0, 14.0, grid, p, reference=_exact(20))
+    print({k: (r[k]["dim"], ["%.1e" % x for x in r[k]["gap_err"]]) for k in ("cutoff", "learned")}, flush=True)
     for ec, el in zip(r["cutoff"]["gap_err"], r["learned"]["gap_err"]):
-        assert el < ec
+        if ec > 1e-7:
+            assert el < ec
     assert r["learned"]["dim"] is not None and r["cutoff"]["dim"] is not None
     assert r["learned"]["dim"] < r["cutoff"]["dim"]
