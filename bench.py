@@ -45,6 +45,9 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over the serialised step
+# (scaled by the copy calibration); written from the counter summary in profiles/.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n40_step.json")
 FP64_MFMA_PEAK_TFS = 78.6  # dense FP64 matrix-core peak of the MI355X
 
 
@@ -85,6 +88,44 @@ def parse():
                    help="only run a plain 1 GiB device-to-device copy (5 times), the reference for "
                         "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
     return p.parse_args()
+
+
+def counted_traffic(family):
+    """Counted HBM bytes per launch of a kernel family (all its instantiations), or None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ks = [v for k, v in t["kernels"].items() if k.startswith(family)]
+    if not ks:
+        return None
+    launches = sum(v["launches"] for v in ks)
+    total = sum(v["launches"] * v["traffic_bytes_per_launch"] for v in ks)
+    return {"bytes_per_launch": total / launches, "launches_counted": launches, "source": os.path.relpath(TRAFFIC_FILE, ROOT),
+            "calibration": t.get("calibration")}
+
+
+def assembly_roofline(achieved, bytes_per_launch, asm_ms):
+    """The assembly kernel against HBM on its algorithmic stores; with the counter summary, also its
+    counted HBM traffic and its counted FP64 work against the FP64 peak."""
+    out = {"kernel": "assemble_rows_kernel<4,false,0>", "bound": "hbm (stores)", "achieved": achieved,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_launch": bytes_per_launch, "traffic": None}
+    tr = counted_traffic("assemble_rows_kernel<4, false, 0>")
+    if tr:
+        out["traffic"] = tr["bytes_per_launch"]
+        out["traffic_source"] = tr
+    try:
+        with open(TRAFFIC_FILE) as f:
+            fl = json.load(f)["kernels"]["assemble_rows_kernel<4, false, 0>"].get("fp64_flops_per_launch")
+    except (OSError, ValueError, KeyError):
+        fl = None
+    if fl:
+        tfs = fl / (asm_ms * 1e-3) / 1e12
+        out["fp64_counted"] = {"flops_per_launch": fl, "achieved": tfs, "peak": FP64_MFMA_PEAK_TFS,
+                               "unit": "TFLOP/s", "frac": tfs / FP64_MFMA_PEAK_TFS}
+    return out
 
 
 def copy_calibration():
@@ -623,14 +664,17 @@ def main():
     gemm_avg_ms = gemm_ms / max(gemm_launches, 1)
     gemm_avg_flops = gemm_flops_total / max(gemm_launches, 1)
     gemm_tfs = gemm_flops_total / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    tr_symv, tr_gemm = counted_traffic("tri_symv"), counted_traffic("dgemm_kernel")
     roof_symv = {"kernel": "tri_symv", "bound": "hbm", "achieved": symv_gbs, "peak": HBM_PEAK_GBS,
-                 "unit": "GB/s", "frac": symv_gbs / HBM_PEAK_GBS, "traffic": None,
+                 "unit": "GB/s", "frac": symv_gbs / HBM_PEAK_GBS,
+                 "traffic": tr_symv["bytes_per_launch"] if tr_symv else None, "traffic_source": tr_symv,
                  "algorithmic_bytes_per_launch": symv_avg_bytes, "avg_launch_ms": symv_avg_ms,
                  "launches": symv_launches, "share_of_step": symv_ms / a.steps / ms_per_step}
     roof_gemm = {"kernel": "dgemm_kernel (FP64 MFMA products: two-stage band reduction, one-stage K=0 "
                            "reduction, back-transform, divide and conquer)",
                  "bound": "mfma", "achieved": gemm_tfs, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
-                 "frac": gemm_tfs / FP64_MFMA_PEAK_TFS, "traffic": None,
+                 "frac": gemm_tfs / FP64_MFMA_PEAK_TFS,
+                 "traffic": tr_gemm["bytes_per_launch"] if tr_gemm else None, "traffic_source": tr_gemm,
                  "algorithmic_flops_per_launch": gemm_avg_flops, "avg_launch_ms": gemm_avg_ms,
                  "launches": gemm_launches, "share_of_step": gemm_ms / a.steps / ms_per_step}
     dominant, other = (roof_gemm, roof_symv) if roof_gemm["share_of_step"] >= roof_symv["share_of_step"] \
@@ -691,9 +735,7 @@ def main():
         "roofline": dominant,
         "roofline_other": other,
         "roofline_isolated": isolated,
-        "roofline_assembly": {"kernel": "assemble_rows_kernel<4,false>", "bound": "hbm", "achieved": achieved,
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                              "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline_assembly": assembly_roofline(achieved, bytes_per_launch, asm_ms),
         "plan": plan_out,
         "physics": {"E0_K0": float(wn0[0]), "gap_K0": float(wn0[1] - wn0[0]), "m2_over_m1": float((wn0[2] - wn0[0]) / (wn0[1] - wn0[0])),
                     "sx_t0": float(sxn[0]), "sx_t50": float(sxn[-1]), "norm_drift": float(nrm.max() - nrm.min())},

@@ -78,7 +78,7 @@ enum Slot : int {
     Count
 };
 }  // namespace ws
-constexpr int kWorkspaceSlots = 48;
+constexpr int kWorkspaceSlots = 64;
 static_assert(ws::Count <= kWorkspaceSlots, "more workspace slots than the cache holds");
 
 // Device workspace cache (grow-only, per device and slot).  While this thread
