@@ -370,8 +370,14 @@ int tgba_sytrd(int64_t n, double *A, int64_t lda, double *d, double *e, double *
  *   symmetric A (lower triangle read; A is overwritten), by reduction to a band
  *   of half-bandwidth 64 (panel QR and two-sided blocked updates on the FP64
  *   matrix cores) and bulge chasing.  The reflectors are not kept (eigenvalues
- *   only).  n <= 65536.  Stream-ordered; does not synchronise.
- *   Errors: TGBA_EINVAL, TGBA_EUNSUPPORTED (n > 65536), TGBA_ENOMEM. */
+ *   only).  n <= 65536.  The bulge chasing is one launch per step of its
+ *   wavefront schedule.  With the environment variable
+ *   TGBA_BULGE_SCHEDULE=sweeps it is instead one persistent launch whose
+ *   workgroups take whole sweeps in order and wait, with a bound, for the
+ *   previous sweep's progress (the same tridiagonal, bit for bit); outside
+ *   graph recording such a call synchronises `stream` to check that no wait
+ *   reached its bound (TGBA_EDEVICE if one did).
+ *   Errors: TGBA_EINVAL, TGBA_EUNSUPPORTED (n > 65536), TGBA_ENOMEM, TGBA_EDEVICE. */
 int tgba_sytrd_2stage(int64_t n, double *A, int64_t lda, double *d, double *e, void *stream);
 int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream);
 /* tgba_stedc: eigenvalues (into d, ascending) and eigenvectors Z (n x n, ldz)
@@ -610,6 +616,11 @@ int tgba_timing_read(double *ms, int64_t *launches, double *bytes);
  * triangle for lower-only updates and for products with one triangle of a
  * symmetric operand.  Channel 2 is the rows kernel of tgba_assemble_corr,
  * units = bytes it writes (8 per element of the NS x NS and R x R blocks).
+ * Channel 3 is the bulge chasing of the two-stage reduction (one record per
+ * call, from before its first launch to after its last), units = algorithmic
+ * bytes: per task the lower triangle of the 64 x 64 diagonal block read and
+ * written, the block below it read and the bulge block written (the bulge
+ * block being the previous task's lower block, carried in registers).
  * Reading a channel consumes only that channel's records.
  */
 int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units);

@@ -23,4 +23,8 @@ size_t band_workspace_doubles(int64_t n);
 // reflectors are not kept).  Stream-ordered; orders up to 65536.
 int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream);
 
+// After an eager (not recorded) sytrd_2stage_batched on `stream`: waits for the
+// stream and reports TGBA_EDEVICE if a bulge-chasing wait reached its bound.
+int band_check(hipStream_t stream);
+
 }  // namespace tgba

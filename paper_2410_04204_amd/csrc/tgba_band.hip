@@ -29,17 +29,24 @@
 //   * applied from the left to the rest of that bulge block, from both sides
 //     to the diagonal block, from the right to the block below (the next
 //     bulge).
-// One workgroup runs the pair of tasks (i, 2 kap), (i, 2 kap + 1) in order, at
-// step t = 2 i + kap.  Every entry the pair touches lies in rows >= r(i, 2 kap),
-// and every entry of the concurrent pair (i + 1, kap - 2) in rows
-// <= r(i, 2 kap) - BW, so the pairs of one step are disjoint; every conflicting
-// pair of tasks keeps the order of the sequential algorithm (checked against
-// it, bit for bit, with the pairs of each step run in either order).  So each
-// step is one launch with one workgroup per pair of every sector.
+// Two schedules give the same band, bit for bit:
+//   * steps (default): the pair of tasks (i, 2 kap), (i, 2 kap + 1) at step
+//     t = 2 i + kap, one launch per step.  Every entry the pair touches lies
+//     in rows >= r(i, 2 kap), and every entry of the concurrent pair
+//     (i + 1, kap - 2) in rows <= r(i, 2 kap) - BW, so the pairs of one step
+//     are disjoint, and every conflicting pair of tasks keeps the order of the
+//     sequential algorithm;
+//   * sweeps (TGBA_BULGE_SCHEDULE=sweeps): one persistent launch; a workgroup
+//     takes a whole sweep from a ticket counter and runs its tasks in order,
+//     each task after sweep i - 1 of its sector has completed task k + 2
+//     (device-scope task counters; see sb2st_sweep_kernel).  Its per-task
+//     device-scope publication costs more than the launches it saves.
 //
 // The tridiagonal (d, e) then goes to the bisection of tgba_stebz.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "tgba_internal.h"
@@ -62,7 +69,7 @@ constexpr int QB = kQrMaxBlk * QP + BW;  // one partial-sum buffer of the panel 
 
 // workspace slots of this file
 constexpr int kSlotSecs = ws::BandSecs, kSlotWork = ws::BandWork, kSlotParts = ws::BandParts, kSlotGemm = ws::BandGemm,
-              kSlotRed = ws::BandRed;
+              kSlotRed = ws::BandRed, kSlotSched = ws::BandSched;
 
 struct BandSec {
     double *A;
@@ -78,6 +85,7 @@ struct BandSec {
     int64_t first_wg;  // stage 2: first workgroup of this sector in a step launch
     int64_t cap;       // stage 2: workgroups of this sector per step
     double *Q;      // n x 4 BW (ld n): a panel pair's [V1' V2 W1' W2] for the rank-4 BW update
+    int *prog;      // stage 2, sweep schedule: tasks completed per sweep (n)
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -302,20 +310,131 @@ __global__ void band_extract_kernel(const BandSec *__restrict__ secs) {
 // ---- stage 2: bulge chasing -----------------------------------------------------
 __device__ __forceinline__ double &bat(double *B, int64_t row, int64_t c) { return B[(row - c) + c * LDB]; }
 
-// One workgroup of 8 waves per pair of consecutive tasks (i, 2 kap) and
-// (i, 2 kap + 1) of a sweep.  Lane l is a row of every block, and thread (l, w)
+constexpr int kPairWaves = 8;              // waves of a bulge-chasing workgroup
+constexpr int NJ = BW / kPairWaves;         // block columns per thread
+
+// LDS of one bulge-chasing workgroup (lane-indexed vectors, BW <= 64).
+struct BulgeLds {
+    double vs[64], prow[kPairWaves][64], pcol[64], qrow[kPairWaves][64], wsv[64], qv[64];
+    double par[2];
+};
+
+// Task (i, k) of sweep i on the band B of a sector of order n, by one
+// workgroup of 8 waves.  Lane l is a row of every block, and thread (l, w)
 // holds columns w, w + 8, ... (8 of the 64) of the bulge block E (rows r..,
 // columns col .. col+63: column col is the one the reflector annihilates), the
 // diagonal block D (its lower triangle) and the block F below D, so that every
-// load is a contiguous column segment and all 24 are in flight before any
-// arithmetic.  F after the first task is exactly the second task's E (rows
-// r + BW.., columns r .. r+63, held by the same threads): it stays in
-// registers, which saves a store and a load of a 64 x 64 block per pair.
-constexpr int kPairWaves = 8;
+// load is a contiguous column segment and all of them are in flight before any
+// arithmetic.  F after task k is exactly task k + 1's E (rows r + BW..,
+// columns r .. r+63, held by the same threads): with e_in_regs the task takes
+// E from the registers (the previous task's F) instead of loading it, and with
+// keep_f it leaves F in the registers for the next task instead of storing it.
+// Callers put a barrier between two tasks of one workgroup (LDS reuse).
+__device__ __forceinline__ void bulge_task(double *__restrict__ B, int64_t n, int64_t i, int64_t k, bool e_in_regs,
+                                           bool keep_f, double (&E)[NJ], double (&D)[NJ], double (&F)[NJ],
+                                           BulgeLds &L) {
+    constexpr int NW = kPairWaves;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: column addresses stay scalar
+    const int64_t r = i + 1 + k * BW;
+    const int ln = (int)(n - r < BW ? n - r : BW);  // >= 2
+    const int64_t rest = n - r - ln;
+    const int ln2 = (int)(rest < 0 ? 0 : (rest < BW ? rest : BW));
+    const int64_t col = (k == 0) ? i : r - BW;
+    // band columns: ecol(j)[l] = entry (r + l, col + j); dcol(j)[l] = entry (r + l, r + j), l >= j
+    // (F: dcol(j)[ln + l]); B[(row - c) + c LDB] holds entry (row, c)
+    auto ecol = [&](int j) { return B + (col + j) * LDB + (r - col - j); };
+    auto dcol = [&](int j) { return B + (r + j) * LDB - j; };
+
+    // ---- loads ----
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + NW * jj;
+        if (!e_in_regs) E[jj] = (lane < ln && (k > 0 || j == 0)) ? ecol(j)[lane] : 0.0;
+        else E[jj] = F[jj];
+        D[jj] = (lane < ln && j <= lane) ? dcol(j)[lane] : 0.0;  // j < ln follows
+        F[jj] = (lane < ln2 && j < ln) ? dcol(j)[ln + lane] : 0.0;
+    }
+
+    if (tid < 64) L.pcol[tid] = 0.0;  // lanes beyond BW read it below
+    // ---- reflector from column col (wave 0: E[0] is column col) ----
+    if (wave == 0) {
+        const double x = E[0];
+        const double sig = wave_sum(lane > 0 ? x * x : 0.0);
+        const double alpha = __shfl(x, 0, 64);
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (sig != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        L.vs[lane] = (lane == 0) ? 1.0 : ((lane < ln) ? x * scale : 0.0);
+        if (lane < ln) ecol(0)[lane] = (lane == 0) ? beta : 0.0;
+        if (lane == 0) L.par[0] = tau;
+    }
+    __syncthreads();
+    const double tau = L.par[0];
+    const bool act = tau != 0.0;  // uniform; an identity reflector changes nothing
+    const double vl = L.vs[lane];
+
+    // ---- left application to the bulge block: E -= tau v (v^T E), columns col+1.. ----
+    // (stored when changed, and always when E came from registers)
+    if (k > 0 && (act || e_in_regs)) {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = wave + NW * jj;
+            if (j == 0) continue;  // column col: the reflector's own column, stored above
+            const double wc = act ? wave_sum(vl * E[jj]) : 0.0;
+            if (lane < ln) ecol(j)[lane] = E[jj] - tau * vl * wc;
+        }
+    }
+    if (!act) return;  // D, F unchanged; F as loaded is the next task's E
+    // ---- p = D v from the lower triangle; q = F v ----
+    double pr = 0.0, qr = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + NW * jj;
+        const double vj = L.vs[j];
+        pr += D[jj] * vj;                                                  // D[l][j], j <= l
+        const double pc = wave_sum((j < lane) ? D[jj] * vl : 0.0);        // sum_{l > j} D[l][j] v_l
+        if (lane == 0) L.pcol[j] = pc;
+        qr += F[jj] * vj;
+    }
+    L.prow[wave][lane] = pr;
+    L.qrow[wave][lane] = qr;
+    __syncthreads();
+    if (wave == 0) {
+        double ps = L.pcol[lane], qs = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            ps += L.prow[w][lane];
+            qs += L.qrow[w][lane];
+        }
+        const double pl = tau * ps;
+        const double kk = 0.5 * tau * wave_sum(pl * vl);
+        L.wsv[lane] = pl - kk * vl;
+        L.qv[lane] = qs;
+    }
+    __syncthreads();
+    // ---- D -= v w^T + w v^T (lower), F -= tau q v^T ----
+    const double wl = L.wsv[lane], ql = L.qv[lane];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + NW * jj;
+        const double vj = L.vs[j], wj = L.wsv[j];
+        if (lane < ln && j <= lane) dcol(j)[lane] = D[jj] - vl * wj - wl * vj;
+        if (lane < ln2 && j < ln) {
+            F[jj] -= tau * ql * vj;
+            if (!keep_f) dcol(j)[ln + lane] = F[jj];
+        }
+    }
+}
+
+// Step schedule: one launch per step t, one workgroup per pair of consecutive
+// tasks (i, 2 kap), (i, 2 kap + 1) of a sweep, the first task's F kept in
+// registers as the second's E.
 __global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(4))) sb2st_pair_kernel(const BandSec *__restrict__ secs, int nsec, int64_t t) {
-    constexpr int NW = kPairWaves, NJ = BW / NW;
-    __shared__ double vs[64], prow[NW][64], pcol[64], qrow[NW][64], wsv[64], qv[64];  // lane-indexed (BW <= 64)
-    __shared__ double par[2];
+    __shared__ BulgeLds L;
     __shared__ int64_t s_first[kMaxBandSecs], s_n[kMaxBandSecs], s_cap[kMaxBandSecs];
     __shared__ int s_sec;
     // sector of this workgroup: the sectors' first workgroups in LDS, one load each
@@ -342,109 +461,127 @@ __global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_p
     if (i < 0 || i > n - 3) return;
     const int64_t kmax = (n - 3 - i) / BW;  // tasks k = 0 .. kmax of sweep i
     if (2 * kap > kmax) return;
-    const BandSec S = secs[s];
-    double *B = S.band;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *B = secs[s].band;
     double E[NJ], D[NJ], F[NJ];
-
 #pragma nounroll
     for (int h = 0; h < 2; ++h) {
         const int64_t k = 2 * kap + h;
         if (k > kmax) break;  // uniform
-        const bool more = k + 1 <= kmax && h == 0;  // the next task takes F from registers
-        const int64_t r = i + 1 + k * BW;
-        const int ln = (int)(n - r < BW ? n - r : BW);  // >= 2
-        const int64_t rest = n - r - ln;
-        const int ln2 = (int)(rest < 0 ? 0 : (rest < BW ? rest : BW));
-        const int64_t col = (k == 0) ? i : r - BW;
-        if (h == 1) __syncthreads();  // the first task's readers of vs, wsv, qv, pcol are done
+        if (h == 1) __syncthreads();  // the first task's readers of the LDS vectors are done
+        bulge_task(B, n, i, k, h == 1, h == 0 && k + 1 <= kmax, E, D, F, L);
+    }
+}
 
-        // ---- loads (E of the second task: the first task's F) ----
-#pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const int j = wave + NW * jj;
-            if (h == 0) E[jj] = (lane < ln && (k > 0 || j == 0)) ? bat(B, r + lane, col + j) : 0.0;
-            else E[jj] = F[jj];
-            D[jj] = (lane < ln && j <= lane) ? bat(B, r + lane, r + j) : 0.0;  // j < ln follows
-            F[jj] = (lane < ln2 && j < ln) ? bat(B, r + ln + lane, r + j) : 0.0;
-        }
+// Sweep schedule, one persistent launch.  A workgroup takes whole sweeps from
+// a ticket counter, in the order (sweep i, sector) with i outer, and runs the
+// tasks k = 0 .. kmax of its sweep in order, F carried in registers from each
+// task to the next.  Task (i, k) touches band entries that tasks of sweep
+// i - 1 up to k + 2 touch (the farthest: the single entry (r + 127, r + 63),
+// in F of (i, k) and in E of (i - 1, k + 2)) and none beyond, so before task k
+// the workgroup waits until sweep i - 1 of its sector has completed
+// min(k + 3, all) tasks; earlier sweeps are then ordered through i - 1.  The
+// order of every pair of tasks that touch a common entry is that of the
+// sequential algorithm, so the band is the step schedule's, bit for bit.
+//
+// A task is published at device scope: every wave waits for its stores, then
+// one thread writes the L2 of its XCD back and stores the count; the waiting
+// workgroup polls the count and invalidates its caches before it loads.  (The
+// L2 of one XCD does not serve as the point of coherence between its compute
+// units here: with only the stores waited for and the L1 dropped, sweeps on
+// one XCD read stale band entries.)
+//
+// Every sweep's predecessor holds an earlier ticket, taken by a running
+// workgroup, so the earliest unfinished sweep can always proceed: the waits
+// end whatever the number of resident workgroups.  Each wait is also bounded
+// (kSweepSpinLimit polls): a wait that reaches the bound sets the abort flag,
+// and every workgroup then stops taking tickets and leaves its waits.
+struct SweepCtl {
+    int *ticket;         // next ticket (zero at launch)
+    int *abort;          // nonzero: a wait reached its bound (zero at launch)
+    const int64_t *seg;  // nseg rows (first ticket, first sweep, sectors taking part), then the ticket count
+    int nseg;
+};
+constexpr int kSweepSpinLimit = 1 << 22;
 
-        if (tid < 64) pcol[tid] = 0.0;  // lanes beyond BW read it below
-        // ---- reflector from column col (wave 0: E[0] is column col) ----
-        if (wave == 0) {
-            const double x = E[0];
-            const double sig = wave_sum(lane > 0 ? x * x : 0.0);
-            const double alpha = __shfl(x, 0, 64);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (sig != 0.0) {
-                beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            vs[lane] = (lane == 0) ? 1.0 : ((lane < ln) ? x * scale : 0.0);
-            if (lane < ln) bat(B, r + lane, col) = (lane == 0) ? beta : 0.0;
-            if (lane == 0) par[0] = tau;
+__global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(4))) sb2st_sweep_kernel(const BandSec *__restrict__ secs, SweepCtl ctl) {
+    __shared__ BulgeLds L;
+    __shared__ int64_t s_seg[3 * kMaxBandSecs + 1];
+    __shared__ int64_t s_tk;
+    __shared__ int s_stop;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 3 * ctl.nseg + 1; q += blockDim.x) s_seg[q] = ctl.seg[q];
+    __syncthreads();
+    const int64_t total = s_seg[3 * ctl.nseg];
+    double E[NJ], D[NJ], F[NJ];
+    for (;;) {
+        if (tid == 0) {
+            int64_t tk = -1;
+            if (__hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) tk = atomicAdd(ctl.ticket, 1);
+            s_tk = tk;
         }
         __syncthreads();
-        const double tau = par[0];
-        const bool act = tau != 0.0;  // uniform; an identity reflector changes nothing
-        const double vl = vs[lane];
-
-        // ---- left application to the bulge block: E -= tau v (v^T E), columns col+1.. ----
-        // (stored when changed, and always in the second task, whose E came from registers)
-        if (k > 0 && (act || h == 1)) {
-#pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) {
-                const int j = wave + NW * jj;
-                if (j == 0) continue;  // column col: the reflector's own column, stored above
-                const double wc = act ? wave_sum(vl * E[jj]) : 0.0;
-                if (lane < ln) bat(B, r + lane, col + j) = E[jj] - tau * vl * wc;
+        // ticket -> (sweep, sector), as wave-uniform scalars (tickets < 2^31)
+        const int tk = __builtin_amdgcn_readfirstlane((int)s_tk);
+        if (tk < 0 || tk >= total) return;  // uniform
+        int lo = 0, hi = ctl.nseg - 1;      // the row of the ticket: last row with first ticket <= tk
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_seg[3 * mid] <= tk) lo = mid; else hi = mid - 1;
+        }
+        const int act = __builtin_amdgcn_readfirstlane((int)s_seg[3 * lo + 2]);
+        const int off = tk - __builtin_amdgcn_readfirstlane((int)s_seg[3 * lo]);
+        const int64_t i = __builtin_amdgcn_readfirstlane((int)s_seg[3 * lo + 1]) + off / act;
+        const BandSec &S = secs[off % act];
+        double *B = S.band;
+        int *prog = S.prog;
+        const int64_t n = S.n;
+        const int64_t kmax = (n - 3 - i) / BW;
+        const int64_t prev_tasks = (i > 0) ? (n - 2 - i) / BW + 1 : 0;  // tasks of sweep i - 1
+        int seen = 0;
+        for (int64_t k = 0; k <= kmax; ++k) {
+            if (tid == 0) {
+                int stop = 0;
+                const int need = (int)(k + 3 < prev_tasks ? k + 3 : prev_tasks);
+                if (seen < need) {
+                    for (int spin = 0;; ++spin) {
+                        seen = __hip_atomic_load(prog + i - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (seen >= need) break;
+                        if ((spin & 255) == 255 &&
+                            __hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            stop = 1;
+                            break;
+                        }
+                        if (spin >= kSweepSpinLimit) {
+                            __hip_atomic_store(ctl.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            stop = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // sweep i - 1's stores, device-wide
+                }
+                s_stop = stop;
             }
-        }
-        if (!act) {
-            if (h == 0) continue;  // D, F unchanged; F is the next task's E as loaded
-            break;
-        }
-        // ---- p = D v from the lower triangle; q = F v ----
-        double pr = 0.0, qr = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const int j = wave + NW * jj;
-            const double vj = vs[j];
-            pr += D[jj] * vj;                                                  // D[l][j], j <= l
-            const double pc = wave_sum((j < lane) ? D[jj] * vl : 0.0);        // sum_{l > j} D[l][j] v_l
-            if (lane == 0) pcol[j] = pc;
-            qr += F[jj] * vj;
-        }
-        prow[wave][lane] = pr;
-        qrow[wave][lane] = qr;
-        __syncthreads();
-        if (wave == 0) {
-            double ps = pcol[lane], qs = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                ps += prow[w][lane];
-                qs += qrow[w][lane];
-            }
-            const double pl = tau * ps;
-            const double kk = 0.5 * tau * wave_sum(pl * vl);
-            wsv[lane] = pl - kk * vl;
-            qv[lane] = qs;
-        }
-        __syncthreads();
-        // ---- D -= v w^T + w v^T (lower), F -= tau q v^T ----
-        const double wl = wsv[lane], ql = qv[lane];
-#pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const int j = wave + NW * jj;
-            const double vj = vs[j], wj = wsv[j];
-            if (lane < ln && j <= lane) bat(B, r + lane, r + j) = D[jj] - vl * wj - wl * vj;
-            if (lane < ln2 && j < ln) {
-                F[jj] -= tau * ql * vj;
-                if (!more) bat(B, r + ln + lane, r + j) = F[jj];
+            __syncthreads();
+            if (s_stop) return;  // uniform
+            bulge_task(B, n, i, k, k > 0, k < kmax, E, D, F, L);
+            // publish task k: every wave's stores complete, the L2 written back, then the count
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(prog + i, (int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
+}
+
+// Zero the sweep counters of every sector and the ticket / abort words.
+__global__ void sweep_reset_kernel(const BandSec *__restrict__ secs, int *ctl) {
+    const BandSec S = secs[blockIdx.y];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < S.n; k += (int64_t)gridDim.x * blockDim.x)
+        S.prog[k] = 0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
 
 __global__ void band_tridiag_kernel(const BandSec *__restrict__ secs) {
@@ -457,10 +594,78 @@ __global__ void band_tridiag_kernel(const BandSec *__restrict__ secs) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The bulge chasing runs on the step schedule (one launch per step) unless
+// TGBA_BULGE_SCHEDULE=sweeps selects the persistent sweep schedule; both give
+// the same band bit for bit.
+bool step_schedule() {
+    const char *v = std::getenv("TGBA_BULGE_SCHEDULE");
+    return !(v && std::strcmp(v, "sweeps") == 0);
+}
+
+// Workgroups of the sweep schedule: as many as the device holds at once.
+int sweep_grid(int *grid) {
+    static int cached[64] = {0};
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(TGBA_EUNSUPPORTED, "device index above 63");
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        TGBA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sb2st_sweep_kernel, 64 * kPairWaves, 0));
+        TGBA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cached[dev] = std::max(1, per_cu) * std::max(1, cus);
+    }
+    *grid = cached[dev];
+    return TGBA_OK;
+}
+
+// The ticket and abort words of the last eager sweep-schedule launch of this
+// thread, and its ticket count.
+thread_local int *t_ctl = nullptr;
+thread_local int64_t t_total = 0;
+
+// Algorithmic bytes of the bulge chasing of one sector of order n: per task the
+// lower triangle of D read and written, F read, E written (its first column
+// read too in the first task of a sweep), and F written by the last task of a
+// sweep; E is the previous task's F, kept in registers.
+double bulge_task_bytes(int64_t n, int64_t i, int64_t k, int64_t kmax) {
+    const int64_t r = i + 1 + k * BW;
+    const int64_t ln = std::min<int64_t>(n - r, BW), ln2 = std::max<int64_t>(0, std::min<int64_t>(n - r - ln, BW));
+    int64_t e = ln * (ln + 1) + ln2 * ln + (k == 0 ? 2 * ln : ln * BW) + (k == kmax ? ln2 * ln : 0);
+    return 8.0 * (double)e;
+}
+double bulge_bytes(int64_t n) {
+    double tot = 0.0;
+    for (int64_t i = 0; i + 3 <= n; ++i) {
+        const int64_t kmax = (n - 3 - i) / BW;
+        // tasks 0, 1, kmax - 1, kmax may be short or carry extra loads and stores;
+        // tasks 2 .. kmax - 2 are full (ln = ln2 = BW) and alike
+        const int64_t ks[4] = {0, 1, kmax - 1, kmax};
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = ks[q];
+            bool seen = k < 0 || k > kmax;
+            for (int p = 0; p < q; ++p) seen = seen || ks[p] == k;
+            if (!seen) tot += bulge_task_bytes(n, i, k, kmax);
+        }
+        if (kmax >= 4) tot += (double)(kmax - 3) * bulge_task_bytes(n, i, 2, kmax);
+    }
+    return tot;
+}
+
 }  // namespace
 
+int band_check(hipStream_t stream) {
+    if (!t_ctl || capturing()) return TGBA_OK;
+    int h[2] = {0, 0};
+    TGBA_HIP(hipMemcpyAsync(h, t_ctl, sizeof(h), hipMemcpyDeviceToHost, stream));
+    TGBA_HIP(hipStreamSynchronize(stream));
+    t_ctl = nullptr;
+    if (h[1]) return set_error(TGBA_EDEVICE, "two-stage reduction: a bulge-chasing wait reached its bound");
+    if (h[0] < t_total) return set_error(TGBA_EDEVICE, "two-stage reduction: bulge-chasing sweeps left untaken");
+    return TGBA_OK;
+}
+
 size_t band_workspace_doubles(int64_t n) {
-    return (size_t)n * (7 * BW + LDB + 1) + 2 * (size_t)QB + 4 * BW * BW + 64;
+    return (size_t)n * (7 * BW + LDB + 1) + 2 * (size_t)QB + 4 * BW * BW + 64 + (size_t)(n + 1) / 2 + 1;
 }
 
 namespace {
@@ -491,12 +696,14 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
     std::vector<int> order(nsec);
     for (int k = 0; k < nsec; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return in[a].n > in[b].n; });
-    size_t total = 0;
+    size_t total = 8;  // the sweep schedule's ticket and abort words
     for (auto &x : in) total += band_workspace_doubles(x.n);
     void *wsp = nullptr;
     int rc = workspace_get(total * sizeof(double), kSlotWork, &wsp);
     if (rc) return rc;
     double *p = (double *)wsp;
+    int *ctl = (int *)p;
+    p += 8;
     std::vector<BandSec> secs(nsec);
     int64_t wg = 0;
     for (int q = 0; q < nsec; ++q) {
@@ -518,6 +725,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.Y = p; p += BW * BW;
         S.M = p; p += BW * BW;
         S.Q = p; p += (size_t)x.n * 4 * BW;
+        S.prog = (int *)p; p += (size_t)(x.n + 1) / 2 + 1;
         S.first_wg = wg;
         S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / (2 * kStride) + 2 : 0;  // pairs of one step, per sector
         wg += S.cap;
@@ -855,7 +1063,42 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
 
     // ---- stage 2 ----
     const int64_t n0 = secs[0].n;
-    if (n0 >= 3 && wg > 0) {
+    hipEvent_t ta = nullptr, tb = nullptr;
+    const bool timed = timing_on() && n0 >= 3 && wg > 0;
+    if (timed) {
+        if ((rc = timing_events(&ta, &tb))) return rc;
+        TGBA_HIP(hipEventRecord(ta, stream));
+    }
+    if (n0 >= 3 && wg > 0 && !step_schedule()) {
+        // tickets (sweep i, sector) with i outer: rows of constant sector count
+        std::vector<int64_t> seg;
+        int64_t tk = 0;
+        for (int q = nsec - 1; q >= 0; --q) {
+            const int64_t sw = std::max<int64_t>(secs[q].n - 2, 0);               // sweeps of sector q
+            const int64_t from = (q == nsec - 1) ? 0 : std::max<int64_t>(secs[q + 1].n - 2, 0);
+            if (sw <= from) continue;  // no sweep index where exactly sectors 0..q take part
+            seg.push_back(tk);
+            seg.push_back(from);
+            seg.push_back(q + 1);
+            tk += (sw - from) * (q + 1);
+        }
+        if (tk >= (int64_t)INT32_MAX) return set_error(TGBA_EUNSUPPORTED, "two-stage reduction: too many sweeps in one call");
+        const int nseg = (int)(seg.size() / 3);
+        seg.push_back(tk);
+        void *wss = nullptr;
+        if ((rc = upload(seg.data(), seg.size() * sizeof(int64_t), kSlotSched, stream, &wss))) return rc;
+        hipLaunchKernelGGL(sweep_reset_kernel, dim3(64, nsec), dim3(256), 0, stream, d_secs, ctl);
+        SweepCtl c{ctl, ctl + 1, (const int64_t *)wss, nseg};
+        int grid = 0;
+        if ((rc = sweep_grid(&grid))) return rc;
+        grid = (int)std::min<int64_t>(grid, tk);
+        hipLaunchKernelGGL(sb2st_sweep_kernel, dim3(grid), dim3(64 * kPairWaves), 0, stream, d_secs, c);
+        TGBA_HIP(hipGetLastError());
+        if (!capturing()) {
+            t_ctl = ctl;
+            t_total = tk;
+        }
+    } else if (n0 >= 3 && wg > 0) {
         // the last pair of a sector of order n is sweep n-3 at kap = 0: step kStride (n - 3)
         const int64_t tmax = kStride * (n0 - 3);
         int act = nsec;
@@ -866,6 +1109,12 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
             hipLaunchKernelGGL(sb2st_pair_kernel, dim3((unsigned)grid), dim3(64 * kPairWaves), 0, stream, d_secs, act, t);
         }
         TGBA_HIP(hipGetLastError());
+    }
+    if (timed) {
+        TGBA_HIP(hipEventRecord(tb, stream));
+        double bytes = 0.0;
+        for (auto &S : secs) bytes += bulge_bytes(S.n);
+        if ((rc = timing_push(ta, tb, bytes, 3))) return rc;
     }
     hipLaunchKernelGGL(band_tridiag_kernel, dim3(64, nsec), dim3(256), 0, stream, d_secs);
     TGBA_HIP(hipGetLastError());

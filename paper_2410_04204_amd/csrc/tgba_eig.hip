@@ -888,7 +888,8 @@ extern "C" int tgba_sytrd_2stage(int64_t n, double *A, int64_t lda, double *d, d
         return tgba::set_error(TGBA_EINVAL, "bad two-stage reduction arguments");
     if (n == 0) return TGBA_OK;
     std::vector<tgba::BandIn> in{tgba::BandIn{A, lda, n, d, e}};
-    return tgba::sytrd_2stage_batched(in, (hipStream_t)stream);
+    const int rc = tgba::sytrd_2stage_batched(in, (hipStream_t)stream);
+    return rc ? rc : tgba::band_check((hipStream_t)stream);
 }
 
 extern "C" int tgba_stebz(int64_t n, const double *d, const double *e, double *w, void *stream) {
@@ -1046,7 +1047,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
         if ((rc = stebz_batched(bis, stream))) return rc;
         if (!capturing()) TGBA_HIP(hipStreamSynchronize(stream));
-        return TGBA_OK;
+        return band_check(stream);
     }
     if (flags & TGBA_EIG_MIXED) {
         for (int k = 0; k < nsec; ++k) {

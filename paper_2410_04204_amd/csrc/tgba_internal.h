@@ -73,7 +73,7 @@ enum Slot : int {
     AssembleDesc, AssembleTuneDesc, DgemmApi, TriSecs, TriGemm, TriGemm2, BisectSecs, TriWork, DCWork, DCGemm,
     EigVecZ, OrmtrGram, OrmtrW, OrmtrT, OrmtrUpdate, DsfWork, QuenchWork, QuenchGemm1, QuenchGemm2, QuenchWeights,
     MlpScore, MlpSelect, MlpBackward, MlpTrain, LearnedKeep, MixedF32, MixedF64, RefineWork, RefineGemm, CrossDesc,
-    BandSecs, BandWork, BandParts, BandGemm, BandRed, OrmtrParts, OrmtrRed, EigNovecWork, CorrWork, QuenchCorrWork,
+    BandSecs, BandWork, BandParts, BandGemm, BandRed, BandSched, OrmtrParts, OrmtrRed, EigNovecWork, CorrWork, QuenchCorrWork,
     QuenchCorrGemm1, QuenchCorrGemm2, DsfCrossWork, SytrdApiWork, BisectBounds, DCMerges, DCFirst, DCSplits,
     Count
 };

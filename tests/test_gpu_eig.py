@@ -114,6 +114,45 @@ def test_two_stage_batched_uneven_sectors_match_lapack_and_one_stage():
         assert np.abs(w1 - ref).max() <= tol
 
 
+def test_bulge_chasing_sweep_schedule_equals_step_schedule(monkeypatch):
+    """The step schedule (default: one launch per step) and the persistent sweep
+    schedule (TGBA_BULGE_SCHEDULE=sweeps: workgroups take whole sweeps and wait
+    on the previous sweep's task counter) order every two tasks that touch a
+    common band entry as the sequential algorithm does, and the first stage has
+    no floating-point atomics: the tridiagonals, hence the eigenvalues, agree bit
+    for bit.  Sizes: many sectors, equal sizes, orders below 3, short last
+    tasks; one sector's (d, e) compared directly."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    sizes = [2049, 700, 700, 1500, 3, 1, 2, 64, 65, 66, 130, 257, 1000, 4, 67, 129]
+    As = [_rand_sym(n, 500 + n + k) for k, n in enumerate(sizes)]
+    got = {}
+    for sched in ("sweeps", "steps"):
+        if sched == "sweeps":
+            monkeypatch.setenv("TGBA_BULGE_SCHEDULE", "sweeps")
+        else:
+            monkeypatch.delenv("TGBA_BULGE_SCHEDULE", raising=False)
+        print(f"schedule {sched}: batched sizes {sizes}", flush=True)
+        mats = [_cm(A) for A in As]
+        ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+        tg.eig_batched(mats, ws, tg.TGBA_EIG_NOVEC)
+        n0 = 1537
+        dA = _cm(_rand_sym(n0, 42))
+        d = torch.empty(n0, dtype=torch.float64, device="cuda")
+        e = torch.empty(n0 - 1, dtype=torch.float64, device="cuda")
+        tg.sytrd_2stage(dA, d, e)
+        torch.cuda.synchronize()
+        got[sched] = ([w.cpu().numpy() for w in ws], d.cpu().numpy(), e.cpu().numpy())
+    monkeypatch.delenv("TGBA_BULGE_SCHEDULE", raising=False)
+    for a, b in zip(got["sweeps"][0], got["steps"][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(got["sweeps"][1], got["steps"][1])
+    assert np.array_equal(got["sweeps"][2], got["steps"][2])
+    for A, w in zip(As, got["sweeps"][0]):
+        ref = scipy.linalg.eigvalsh(A)
+        assert np.abs(w - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()) * np.sqrt(A.shape[0])
+
+
 def test_masked_split_k_symmetric_product():
     """tril(A) V + stril(A)^T V (the first stage's product with the trailing
     matrix, from its lower triangle) equals A V; exercised through the
