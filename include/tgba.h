@@ -76,6 +76,7 @@ typedef struct tgba_model {
 #define TGBA_TRUNC_CHI 1  /* keep chi[K] lowest per sector, order (E^(0), NS<R, mask)   */
 #define TGBA_TRUNC_LEARNED 2 /* keep chi[K] best-scored by the network (tgba_mlp_*)     */
 #define TGBA_TRUNC_OVERLAP 3 /* keep chi[K] with the largest |<phi|Phi_0>| (Quench section) */
+#define TGBA_TRUNC_UNION 4   /* keep the union of the LEARNED and the CHI selections       */
 
 /*
  * Truncation of the Gaussian basis (Method section; Appendix B).
@@ -83,9 +84,9 @@ typedef struct tgba_model {
  *   e_cut  ECUT: the cutoff.  CHI: cutoff of the candidate pool (< 0: the pool
  *          is the whole space, only sensible for small N).
  *   m_max  keep only M <= m_max quasiparticles (<= 0: no cap)
- *   chi    CHI, LEARNED: host array of N per-sector dimensions, or NULL to use
- *          chi_all
- *   mlp    LEARNED: device array of TGBA_MLP_PARAMS floats (the network of
+ *   chi    CHI, LEARNED, UNION, OVERLAP: host array of N per-sector
+ *          dimensions, or NULL to use chi_all
+ *   mlp    LEARNED, UNION: device array of TGBA_MLP_PARAMS floats (the network of
  *          tgba_mlp_*); ignored otherwise
  *   h_pre, s, ov_min   OVERLAP: the quench's initial state Phi_0 is the
  *          pre-quench vacuum at transverse field h_pre, |0,h_pre>_NS (s = 0) or
@@ -99,6 +100,9 @@ typedef struct tgba_model {
  * initial state): the pool is the e_cut / m_max set; per sector the chi[K]
  * states with the largest BF16 score of tgba_mlp_score on their features
  * (tgba_mlp_features) are kept, equal scores in the order (E^(0), NS<R, mask).
+ * UNION (a reference for comparing the two selections): per sector the union
+ * of the chi[K] best-scored states (LEARNED) and the chi[K] lowest in energy
+ * (CHI), between chi[K] and 2 chi[K] states; needs mlp and a pool cutoff.
  * OVERLAP (Quench section: order the states by the magnitude of their overlap
  * with the initial state, not by their energy): the pool is the e_cut / m_max
  * set; per sector the candidates are ordered by |<phi|Phi_0>| from the closed

@@ -37,11 +37,13 @@ class Basis:
     device tensor of TGBA_MLP_PARAMS floats) the chi states of every sector
     with the best network score are kept instead of the lowest in energy.
     With overlap=(h_pre, s[, ov_min]) the chi states with the largest overlap
-    with the quench's initial state are kept (TGBA_TRUNC_OVERLAP).
+    with the quench's initial state are kept (TGBA_TRUNC_OVERLAP).  With mlp and
+    union=True the union of the network's chi and the chi lowest in energy is
+    kept (TGBA_TRUNC_UNION).
     """
 
     def __init__(self, N, h_perp, h_par, e_cut=None, chi=None, m_max=None, pool_e_cut=None, mlp=None, overlap=None,
-                 stream=None):
+                 union=False, stream=None):
         L = _lib.load()
         self.N, self.h_perp, self.h_par = int(N), float(h_perp), float(h_par)
         model = _lib.Model(self.N, self.h_perp, self.h_par)
@@ -52,7 +54,7 @@ class Basis:
             tr = _lib.Trunc(_lib.TGBA_TRUNC_ECUT, float(e_cut), int(m_max or 0), None, 0)
         else:
             pool = -1.0 if pool_e_cut is None else float(pool_e_cut)
-            mode = _lib.TGBA_TRUNC_CHI if mlp is None else _lib.TGBA_TRUNC_LEARNED
+            mode = _lib.TGBA_TRUNC_CHI if mlp is None else (_lib.TGBA_TRUNC_UNION if union else _lib.TGBA_TRUNC_LEARNED)
             if overlap is not None:
                 mode = _lib.TGBA_TRUNC_OVERLAP
             if np.isscalar(chi):

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtgba.so")
 TGBA_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
 
-TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED, TGBA_TRUNC_OVERLAP = 0, 1, 2, 3
+TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED, TGBA_TRUNC_OVERLAP, TGBA_TRUNC_UNION = 0, 1, 2, 3, 4
 TGBA_HEFF, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_LOWER = 0x0, 0x1, 0x2, 0x4
 TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE = 0x0, 0x1, 0x2, 0x4
 

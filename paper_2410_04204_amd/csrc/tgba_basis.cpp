@@ -122,16 +122,17 @@ static int validate(const tgba_model *m, const tgba_trunc *t) {
     if (!(m->h_perp > 0.0) || !std::isfinite(m->h_perp) || !std::isfinite(m->h_par))
         return set_error(TGBA_EINVAL, "h_perp must be > 0 and fields finite");
     if (t->mode != TGBA_TRUNC_ECUT && t->mode != TGBA_TRUNC_CHI && t->mode != TGBA_TRUNC_LEARNED &&
-        t->mode != TGBA_TRUNC_OVERLAP)
+        t->mode != TGBA_TRUNC_OVERLAP && t->mode != TGBA_TRUNC_UNION)
         return set_error(TGBA_EINVAL, "unknown truncation mode");
     if (t->mode == TGBA_TRUNC_OVERLAP &&
         (!(t->h_pre >= 0.0) || !std::isfinite(t->h_pre) || t->s < -1 || t->s > 1 || !(t->e_cut >= 0.0)))
         return set_error(TGBA_EINVAL, "OVERLAP mode needs h_pre >= 0, s in {-1, 0, 1} and a pool cutoff e_cut >= 0");
-    if (t->mode == TGBA_TRUNC_LEARNED && (!t->mlp || !(t->e_cut >= 0.0)))
-        return set_error(TGBA_EINVAL, "LEARNED mode needs the network parameters and a pool cutoff e_cut >= 0");
+    if ((t->mode == TGBA_TRUNC_LEARNED || t->mode == TGBA_TRUNC_UNION) && (!t->mlp || !(t->e_cut >= 0.0)))
+        return set_error(TGBA_EINVAL, "LEARNED and UNION modes need the network parameters and a pool cutoff e_cut >= 0");
     if (t->mode == TGBA_TRUNC_ECUT && !(t->e_cut >= 0.0))
         return set_error(TGBA_EINVAL, "e_cut must be >= 0 in ECUT mode");
-    if (t->mode == TGBA_TRUNC_CHI || t->mode == TGBA_TRUNC_LEARNED || t->mode == TGBA_TRUNC_OVERLAP) {
+    if (t->mode == TGBA_TRUNC_CHI || t->mode == TGBA_TRUNC_LEARNED || t->mode == TGBA_TRUNC_OVERLAP ||
+        t->mode == TGBA_TRUNC_UNION) {
         if (t->chi) {
             for (int K = 0; K < m->N; ++K)
                 if (t->chi[K] < 0) return set_error(TGBA_EINVAL, "chi must be >= 0");
@@ -307,6 +308,27 @@ extern "C" int tgba_build_basis(const tgba_model *m, const tgba_trunc *t, void *
                     kept.push_back(c[ov[a].second]);
                 }
                 c.swap(kept);
+            } else if (t->mode == TGBA_TRUNC_UNION) {
+                const int64_t keep = t->chi ? t->chi[K] : t->chi_all;
+                if ((int64_t)c.size() > keep) {
+                    // the learned choice, then every candidate that is in it or among the
+                    // keep lowest in energy, in c's order (E, NS<R, mask)
+                    std::vector<Cand> lk(c);
+                    rc = learned_keep(b, lk, keep, t->mlp, (hipStream_t)stream);
+                    if (rc) {
+                        delete hb;
+                        return rc;
+                    }
+                    std::vector<std::pair<uint64_t, int>> lkey(lk.size());
+                    for (size_t a = 0; a < lk.size(); ++a) lkey[a] = {lk[a].mask, lk[a].s};
+                    std::sort(lkey.begin(), lkey.end());
+                    std::vector<Cand> kept;
+                    for (size_t a = 0; a < c.size(); ++a)
+                        if ((int64_t)a < keep ||
+                            std::binary_search(lkey.begin(), lkey.end(), std::make_pair(c[a].mask, c[a].s)))
+                            kept.push_back(c[a]);
+                    c.swap(kept);
+                }
             } else if (t->mode == TGBA_TRUNC_LEARNED) {
                 int64_t keep = t->chi ? t->chi[K] : t->chi_all;
                 if (keep == 0) {

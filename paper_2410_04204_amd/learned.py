@@ -123,8 +123,28 @@ def dim_for_gap(N, h, pool, grid, mlp, tol=1e-6, h_par=0.1, m_max=None, dev="cud
                      "m2_over_m1_err": r21, "seconds_per_dim": secs,
                      "at_dim": (None if q is None else {"E1_err": e1[q], "m2_over_m1_err": r21[q],
                                                         "gap_err": err[q], "wall_s": secs[q]})}
+    out["matched"] = matched_errors(out)
     out["seconds"] = time.perf_counter() - t0
     return out
+
+
+def matched_errors(r):
+    """The learned basis against the cutoff basis at equal error: the cutoff's E1
+    and m2/m1 errors at its dimension for the gap tolerance (its largest grid
+    dimension if it never reaches it), and the smallest learned grid dimension
+    whose gap, |E1| and m2/m1 errors are all at most the cutoff's there, with the
+    wall time of each basis."""
+    c, l, grid = r["cutoff"], r["learned"], r["grid"]
+    qc = grid.index(c["dim"]) if c["dim"] is not None else len(grid) - 1
+    tgt = {"gap_err": c["gap_err"][qc], "E1_err": abs(c["E1_err"][qc]), "m2_over_m1_err": c["m2_over_m1_err"][qc]}
+    ok = [q for q in range(len(grid)) if l["gap_err"][q] <= tgt["gap_err"] and abs(l["E1_err"][q]) <= tgt["E1_err"]
+          and l["m2_over_m1_err"][q] <= tgt["m2_over_m1_err"]]
+    ql = min(ok) if ok else None
+    return {"cutoff_dim": grid[qc], "cutoff_errors": tgt, "cutoff_wall_s": c["seconds_per_dim"][qc],
+            "learned_dim": grid[ql] if ql is not None else None,
+            "learned_errors": None if ql is None else {"gap_err": l["gap_err"][ql], "E1_err": abs(l["E1_err"][ql]),
+                                                       "m2_over_m1_err": l["m2_over_m1_err"][ql]},
+            "learned_wall_s": None if ql is None else l["seconds_per_dim"][ql]}
 
 
 def k0_quench(B, h_perp, nt, dt, dev="cuda"):
@@ -150,14 +170,20 @@ def k0_quench(B, h_perp, nt, dt, dev="cuda"):
 
 
 def quench_comparison(N, h, pool, m_max, chi, chi_ref, mlp, nt=1001, dt=0.05, h_par=0.1, log=None, dev="cuda"):
-    """<sigma^x>(t) from the learned basis of dimension chi, the energy cutoff of
-    the same dimension and the energy cutoff of dimension chi_ref (reference),
-    all K = 0 from the same candidate pool."""
+    """<sigma^x>(t) from the learned basis of dimension chi and the energy cutoff
+    of the same dimension, all K = 0 from the same candidate pool, against two
+    references: the union of the two bases (TGBA_TRUNC_UNION: it contains both,
+    so it favours neither) and, with chi_ref, the energy cutoff of dimension
+    chi_ref (which contains the cutoff basis but not the learned one)."""
     import numpy as np
     res = {}
-    for name, dim, p in (("learned", chi, mlp), ("cutoff", chi, None), ("reference", chi_ref, None)):
+    plan = [("learned", chi, mlp, False), ("cutoff", chi, None, False), ("union", chi, mlp, True)]
+    if chi_ref:
+        plan.append(("cutoff_ref", chi_ref, None, False))
+    for name, dim, p, uni in plan:
         t0 = time.perf_counter()
-        B = Basis(N, h, h_par, chi=[dim if K == 0 else 0 for K in range(N)], pool_e_cut=pool, m_max=m_max, mlp=p)
+        B = Basis(N, h, h_par, chi=[dim if K == 0 else 0 for K in range(N)], pool_e_cut=pool, m_max=m_max, mlp=p,
+                  union=uni)
         tb = time.perf_counter() - t0
         sx, e1 = k0_quench(B, h, nt, dt, dev)
         res[name] = {"dim": sum(B.sector_size(0)), "sx": sx, "E1": e1, "basis_s": tb,
@@ -165,12 +191,15 @@ def quench_comparison(N, h, pool, m_max, chi, chi_ref, mlp, nt=1001, dt=0.05, h_
         B.free()
         if log:
             log(f"{name}: dim {res[name]['dim']}, E1 {e1:.8f}, {res[name]['total_s']:.1f} s")
-    ref = res["reference"]["sx"]
     out = {k: {kk: vv for kk, vv in v.items() if kk != "sx"} for k, v in res.items()}
-    for k in ("learned", "cutoff"):
-        d = np.abs(res[k]["sx"] - ref)
-        out[k]["max_abs_dev_sx"] = float(d.max())
-        out[k]["mean_abs_dev_sx"] = float(d.mean())
-        out[k]["E1_minus_ref"] = res[k]["E1"] - res["reference"]["E1"]
-    out["sx_ref_t50"] = float(ref[-1])
+    for ref in ("union", "cutoff_ref"):
+        if ref not in res:
+            continue
+        r = res[ref]["sx"]
+        for k in ("learned", "cutoff"):
+            d = np.abs(res[k]["sx"] - r)
+            out[k][f"max_abs_dev_sx_vs_{ref}"] = float(d.max())
+            out[k][f"mean_abs_dev_sx_vs_{ref}"] = float(d.mean())
+            out[k][f"E1_minus_{ref}"] = res[k]["E1"] - res[ref]["E1"]
+        out[f"sx_{ref}_tmax"] = float(r[-1])
     return out

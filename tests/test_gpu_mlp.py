@@ -196,3 +196,26 @@ def test_learned_basis_matches_oracle_selection(tg):
                 assert (s, int(m)) in got
             elif v < thr - tol:
                 assert (s, int(m)) not in got
+
+
+def test_union_basis_is_union_of_learned_and_cutoff(tg):
+    """TGBA_TRUNC_UNION keeps exactly the states of the LEARNED basis and of the
+    CHI (lowest-energy) basis of the same chi and pool, every sector."""
+    N, h, pool, chi = 16, 1.0, 8.0, 30
+    p = f32(np.asarray(workloads.mlp_params(4), np.float32))
+    BL = tg.Basis(N, h, 0.1, chi=chi, pool_e_cut=pool, mlp=p)
+    BC = tg.Basis(N, h, 0.1, chi=chi, pool_e_cut=pool)
+    BU = tg.Basis(N, h, 0.1, chi=chi, pool_e_cut=pool, mlp=p, union=True)
+
+    def states(B, K):
+        masks, _ = B.sector(K)
+        n_ns, _ = B.sector_size(K)
+        return [(0, int(m)) for m in masks[:n_ns]] + [(1, int(m)) for m in masks[n_ns:]]
+
+    grew = 0
+    for K in range(N):
+        u = states(BU, K)
+        assert len(u) == len(set(u))
+        assert set(u) == set(states(BL, K)) | set(states(BC, K))
+        grew += len(u) > len(states(BC, K))
+    assert grew > 0  # the two selections differ somewhere
