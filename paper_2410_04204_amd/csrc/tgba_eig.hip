@@ -36,6 +36,7 @@ typedef const char __attribute__((address_space(1))) gchar;
 template <typename T> using gptr = const T __attribute__((address_space(1))) *;
 
 constexpr int kNB = 64;       // panel width
+constexpr int kBT = 4 * kNB;  // reflectors per block of the FP64 back-transform
 constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXED
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
 // Launch shapes of the symmetric product the autotuner chooses from:
@@ -548,6 +549,35 @@ __global__ void larft_kernel(const T *Sg, const T *tau, int nbp, T *Tm) {
     }
 }
 
+// The diagonal 64 x 64 blocks of T (nb x nb, ld nb) of nb reflectors, one
+// workgroup of 64 threads per block q (reflectors 64 q ..): T_ii = tau_i,
+// T(0:i, i) = -tau_i T(0:i, 0:i) (V^T V)(0:i, i) within the block, Sg = V^T V
+// (ld nb).  Workgroup q writes its whole column strip of T: zeros outside its
+// diagonal block (the blocks above it are filled by larft_combine).
+__global__ void larft_blocks_kernel(const double *Sg, const double *tau, int nb, double *Tm) {
+    __shared__ double Tl[64][65];
+    __shared__ double col[64];
+    const int j = threadIdx.x, c0 = 64 * blockIdx.x;
+    const int nbp = nb - c0 < 64 ? nb - c0 : 64;
+    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < nbp; ++i) {
+        const double ti = tau[c0 + i];
+        if (j < i) {
+            double acc = 0.0;
+            for (int l = j; l < i; ++l) acc += Tl[j][l] * Sg[(c0 + l) + (int64_t)(c0 + i) * nb];
+            col[j] = -ti * acc;
+        }
+        __syncthreads();
+        if (j < i) Tl[j][i] = col[j];
+        if (j == i) Tl[i][i] = ti;
+        __syncthreads();
+    }
+    for (int c = 0; c < nbp; ++c)
+        for (int r = j; r < nb; r += blockDim.x)
+            Tm[r + (int64_t)(c0 + c) * nb] = (r >= c0 && r < c0 + nbp) ? Tl[r - c0][c] : 0.0;
+}
+
 template <typename T>
 __global__ void copy_matrix_kernel(const T *src, int64_t lds, T *dst, int64_t ldd, int64_t m, int64_t n) {
     const int64_t tot = m * n;
@@ -775,9 +805,77 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
 
 // Z (n x n, ldz) <- Q Z with the reflectors of tgba_sytrd stored in A.
 // scratch: n*64 (V) + 3 n*64 (W1, W2) + 2*64*64 (S, T) doubles.
+size_t ormtr_scratch_doubles(int64_t n) {
+    return 3 * (size_t)n * kBT + 2 * (size_t)kBT * kBT + (size_t)kBT * kNB + 1024;
+}
+
+// FP64 back-transform in blocks of kBT = 4 kNB reflectors: per block the compact
+// WY form I - V T V^T (T from the four 64-blocks' T and the coupling blocks of the
+// Gram matrix: for V = [V_A V_B], T = [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]]), then
+// Z -= V (T (V^T Z)).  A product of depth kBT reads and writes Z once per 256
+// reflectors instead of once per 64.
+int ormtr_f64(int64_t n, const double *A, int64_t lda, const double *tau, double *Z, int64_t ldz, double *scratch,
+              hipStream_t stream) {
+    double *V = scratch;
+    double *W1 = V + (size_t)n * kBT;
+    double *W2 = W1 + (size_t)n * kBT;
+    double *Sg = W2 + (size_t)n * kBT;
+    double *Tm = Sg + (size_t)kBT * kBT;
+    double *Y = Tm + (size_t)kBT * kBT;
+    const int64_t nref = n - 1;
+    const int64_t nblk = (nref + kBT - 1) / kBT;
+    for (int64_t p = nblk - 1; p >= 0; --p) {
+        const int64_t j0 = p * kBT;
+        const int nb = (int)std::min<int64_t>(kBT, nref - j0);
+        const int nbk = (nb + kNB - 1) / kNB;
+        const int64_t m = n - j0 - 1;
+        hipLaunchKernelGGL(extract_v_kernel<double>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nb, V);
+        TGBA_HIP(hipGetLastError());
+        double *Zs = Z + (j0 + 1);
+        // the two products with K = m have few output tiles: split K over workgroups
+        const int ks_s = (int)std::min<int64_t>(64, std::max<int64_t>(1, m / 512));
+        const int64_t tiles_w = ((n + 127) / 128) * ((nb + 127) / 128);
+        const int ks_w = (int)std::min<int64_t>({32, std::max<int64_t>(1, m / 512),
+                                                  std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles_w, 1))});
+        void *wp = nullptr;
+        const size_t need = (size_t)ks_s * nb * nb + (size_t)ks_w * nb * n;
+        int rc;
+        if ((rc = workspace_get(need * sizeof(double), ws::OrmtrParts, &wp))) return rc;
+        double *parts = (double *)wp;
+        std::vector<GemmDesc> g(1);
+        g[0] = GemmDesc{V, m, V, m, Sg, nb, nb, nb, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+        g[0].ksplit = ks_s;
+        g[0].Cpart = parts;
+        if ((rc = dgemm_batched(g, ws::OrmtrGram, stream))) return rc;
+        std::vector<ReduceDesc> red{ReduceDesc{Sg, nb, nb, nb, parts, ks_s, 0.0, 0}};
+        if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
+        hipLaunchKernelGGL(larft_blocks_kernel, dim3(nbk), dim3(64), 0, stream, Sg, tau + j0, nb, Tm);
+        TGBA_HIP(hipGetLastError());
+        for (int q = 1; q < nbk; ++q) {  // T(0:a, a:a+w) = -T(0:a, 0:a) S(0:a, a:a+w) T(a:a+w, a:a+w)
+            const int a = q * kNB, w = std::min(kNB, nb - a);
+            g[0] = GemmDesc{Sg + (size_t)a * nb, nb, Tm + a + (size_t)a * nb, nb, Y, kBT, a, w, w, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+            if ((rc = dgemm_batched(g, ws::OrmtrT, stream))) return rc;
+            g[0] = GemmDesc{Tm, nb, Y, kBT, Tm + (size_t)a * nb, nb, a, w, a, -1.0, 0.0, 0, 0, 0, 0, 0, 0};
+            if ((rc = dgemm_batched(g, ws::OrmtrT, stream))) return rc;
+        }
+        g[0] = GemmDesc{V, m, Zs, ldz, W1, nb, nb, n, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
+        g[0].ksplit = ks_w;
+        g[0].Cpart = parts + (size_t)ks_s * nb * nb;
+        if ((rc = dgemm_batched(g, ws::OrmtrW, stream))) return rc;
+        red[0] = ReduceDesc{W1, nb, nb, n, parts + (size_t)ks_s * nb * nb, ks_w, 0.0, 0};
+        if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
+        g[0] = GemmDesc{Tm, nb, W1, nb, W2, nb, nb, n, nb, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
+        if ((rc = dgemm_batched(g, ws::OrmtrT, stream))) return rc;
+        g[0] = GemmDesc{V, m, W2, nb, Zs, ldz, m, n, nb, -1.0, 1.0, 0, 0, 0, 0, 0, 0};
+        if ((rc = dgemm_batched(g, ws::OrmtrUpdate, stream))) return rc;
+    }
+    return TGBA_OK;
+}
+
 template <typename T>
 int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream) {
     if (n < 2) return TGBA_OK;
+    if constexpr (sizeof(T) == 8) return ormtr_f64(n, A, lda, tau, Z, ldz, scratch, stream);
     using G = typename GemmOf<T>::type;
     T *V = scratch;
     T *W1 = V + (size_t)n * kNB;
@@ -1096,7 +1194,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         TriSec &S = secs[k];
         const int64_t nn = S.n;
         void *zw = nullptr;
-        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + (size_t)nn * kNB + 3 * (size_t)nn * kNB + 2 * kNB * kNB + 1024);
+        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + ormtr_scratch_doubles(nn));
         rc = workspace_get(zbytes, ws::EigVecZ, &zw);
         if (rc) return rc;
         double *Zt = (double *)zw;
