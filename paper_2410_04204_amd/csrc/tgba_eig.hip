@@ -36,7 +36,7 @@ typedef const char __attribute__((address_space(1))) gchar;
 template <typename T> using gptr = const T __attribute__((address_space(1))) *;
 
 constexpr int kNB = 64;       // panel width
-constexpr int kBT = 4 * kNB;  // reflectors per block of the FP64 back-transform
+constexpr int kBT = 8 * kNB;  // reflectors per block of the FP64 back-transform
 constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXED
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
 // Launch shapes of the symmetric product the autotuner chooses from:
