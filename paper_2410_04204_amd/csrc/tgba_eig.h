@@ -39,7 +39,7 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream);
 int stebz_batched(std::vector<BisIn> &in, hipStream_t stream);
 template <typename T>
 int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream);
-// Scratch (doubles) of the FP64 back-transform of order n.
-size_t ormtr_scratch_doubles(int64_t n);
+// Scratch elements (of T) of the back-transform of order n.
+size_t ormtr_scratch_elems(int64_t n);
 
 }  // namespace tgba

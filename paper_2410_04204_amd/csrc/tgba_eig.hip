@@ -36,7 +36,7 @@ typedef const char __attribute__((address_space(1))) gchar;
 template <typename T> using gptr = const T __attribute__((address_space(1))) *;
 
 constexpr int kNB = 64;       // panel width
-constexpr int kBT = 8 * kNB;  // reflectors per block of the FP64 back-transform
+constexpr int kBT = 8 * kNB;  // reflectors per block of the back-transform
 constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXED
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
 // Launch shapes of the symmetric product the autotuner chooses from:
@@ -522,49 +522,23 @@ __global__ void extract_v_kernel(const T *A, int64_t lda, int64_t n, int64_t j0,
     }
 }
 
-// Upper triangular T of the compact WY form I - V T V^T of H_j0 ... H_j0+nbp-1
-// (forward, columnwise): T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) (V^T V)(0:i, i).
-template <typename T>
-__global__ void larft_kernel(const T *Sg, const T *tau, int nbp, T *Tm) {
-    __shared__ T Tl[64][65];
-    __shared__ T col[64];
-    const int j = threadIdx.x;
-    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = T(0);
-    __syncthreads();
-    for (int i = 0; i < nbp; ++i) {
-        const T ti = tau[i];
-        if (j < i) {
-            T acc = T(0);
-            for (int l = j; l < i; ++l) acc += Tl[j][l] * Sg[l + i * nbp];
-            col[j] = -ti * acc;
-        }
-        __syncthreads();
-        if (j < i) Tl[j][i] = col[j];
-        if (j == i) Tl[i][i] = ti;
-        __syncthreads();
-    }
-    for (int k = j; k < nbp * nbp; k += blockDim.x) {
-        const int r = k % nbp, c = k / nbp;
-        Tm[r + c * nbp] = Tl[r][c];
-    }
-}
-
 // The diagonal 64 x 64 blocks of T (nb x nb, ld nb) of nb reflectors, one
 // workgroup of 64 threads per block q (reflectors 64 q ..): T_ii = tau_i,
 // T(0:i, i) = -tau_i T(0:i, 0:i) (V^T V)(0:i, i) within the block, Sg = V^T V
 // (ld nb).  Workgroup q writes its whole column strip of T: zeros outside its
 // diagonal block (the blocks above it are filled by larft_combine).
-__global__ void larft_blocks_kernel(const double *Sg, const double *tau, int nb, double *Tm) {
-    __shared__ double Tl[64][65];
-    __shared__ double col[64];
+template <typename T>
+__global__ void larft_blocks_kernel(const T *Sg, const T *tau, int nb, T *Tm) {
+    __shared__ T Tl[64][65];
+    __shared__ T col[64];
     const int j = threadIdx.x, c0 = 64 * blockIdx.x;
     const int nbp = nb - c0 < 64 ? nb - c0 : 64;
-    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = 0.0;
+    for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = T(0);
     __syncthreads();
     for (int i = 0; i < nbp; ++i) {
-        const double ti = tau[c0 + i];
+        const T ti = tau[c0 + i];
         if (j < i) {
-            double acc = 0.0;
+            T acc = T(0);
             for (int l = j; l < i; ++l) acc += Tl[j][l] * Sg[(c0 + l) + (int64_t)(c0 + i) * nb];
             col[j] = -ti * acc;
         }
@@ -575,7 +549,7 @@ __global__ void larft_blocks_kernel(const double *Sg, const double *tau, int nb,
     }
     for (int c = 0; c < nbp; ++c)
         for (int r = j; r < nb; r += blockDim.x)
-            Tm[r + (int64_t)(c0 + c) * nb] = (r >= c0 && r < c0 + nbp) ? Tl[r - c0][c] : 0.0;
+            Tm[r + (int64_t)(c0 + c) * nb] = (r >= c0 && r < c0 + nbp) ? Tl[r - c0][c] : T(0);
 }
 
 template <typename T>
@@ -805,23 +779,26 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
 
 // Z (n x n, ldz) <- Q Z with the reflectors of tgba_sytrd stored in A.
 // scratch: n*64 (V) + 3 n*64 (W1, W2) + 2*64*64 (S, T) doubles.
-size_t ormtr_scratch_doubles(int64_t n) {
+size_t ormtr_scratch_elems(int64_t n) {
     return 3 * (size_t)n * kBT + 2 * (size_t)kBT * kBT + (size_t)kBT * kNB + 1024;
 }
 
-// FP64 back-transform in blocks of kBT = 4 kNB reflectors: per block the compact
-// WY form I - V T V^T (T from the four 64-blocks' T and the coupling blocks of the
-// Gram matrix: for V = [V_A V_B], T = [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]]), then
-// Z -= V (T (V^T Z)).  A product of depth kBT reads and writes Z once per 256
-// reflectors instead of once per 64.
-int ormtr_f64(int64_t n, const double *A, int64_t lda, const double *tau, double *Z, int64_t ldz, double *scratch,
-              hipStream_t stream) {
-    double *V = scratch;
-    double *W1 = V + (size_t)n * kBT;
-    double *W2 = W1 + (size_t)n * kBT;
-    double *Sg = W2 + (size_t)n * kBT;
-    double *Tm = Sg + (size_t)kBT * kBT;
-    double *Y = Tm + (size_t)kBT * kBT;
+// Back-transform Z <- Q Z, Q = H_0 ... H_{n-2}, in blocks of kBT = 8 kNB
+// reflectors, last block first: per block the compact WY form I - V T V^T (T from
+// the 64-blocks' T and the coupling blocks of the Gram matrix: for V = [V_A V_B],
+// T = [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]]), then Z -= V (T (V^T Z)).  A
+// product of depth kBT reads and writes Z once per 512 reflectors.  In FP64 the
+// two products with K = m split K over workgroups.
+template <typename T>
+int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream) {
+    if (n < 2) return TGBA_OK;
+    using G = typename GemmOf<T>::type;
+    T *V = scratch;
+    T *W1 = V + (size_t)n * kBT;
+    T *W2 = W1 + (size_t)n * kBT;
+    T *Sg = W2 + (size_t)n * kBT;
+    T *Tm = Sg + (size_t)kBT * kBT;
+    T *Y = Tm + (size_t)kBT * kBT;
     const int64_t nref = n - 1;
     const int64_t nblk = (nref + kBT - 1) / kBT;
     for (int64_t p = nblk - 1; p >= 0; --p) {
@@ -829,107 +806,56 @@ int ormtr_f64(int64_t n, const double *A, int64_t lda, const double *tau, double
         const int nb = (int)std::min<int64_t>(kBT, nref - j0);
         const int nbk = (nb + kNB - 1) / kNB;
         const int64_t m = n - j0 - 1;
-        hipLaunchKernelGGL(extract_v_kernel<double>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nb, V);
+        hipLaunchKernelGGL(extract_v_kernel<T>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nb, V);
         TGBA_HIP(hipGetLastError());
-        double *Zs = Z + (j0 + 1);
-        // the two products with K = m have few output tiles: split K over workgroups
-        const int ks_s = (int)std::min<int64_t>(64, std::max<int64_t>(1, m / 512));
-        const int64_t tiles_w = ((n + 127) / 128) * ((nb + 127) / 128);
-        const int ks_w = (int)std::min<int64_t>({32, std::max<int64_t>(1, m / 512),
-                                                  std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles_w, 1))});
-        void *wp = nullptr;
-        const size_t need = (size_t)ks_s * nb * nb + (size_t)ks_w * nb * n;
+        T *Zs = Z + (j0 + 1);
+        std::vector<G> g(1);
         int rc;
-        if ((rc = workspace_get(need * sizeof(double), ws::OrmtrParts, &wp))) return rc;
-        double *parts = (double *)wp;
-        std::vector<GemmDesc> g(1);
-        g[0] = GemmDesc{V, m, V, m, Sg, nb, nb, nb, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
-        g[0].ksplit = ks_s;
-        g[0].Cpart = parts;
-        if ((rc = dgemm_batched(g, ws::OrmtrGram, stream))) return rc;
-        std::vector<ReduceDesc> red{ReduceDesc{Sg, nb, nb, nb, parts, ks_s, 0.0, 0}};
-        if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
-        hipLaunchKernelGGL(larft_blocks_kernel, dim3(nbk), dim3(64), 0, stream, Sg, tau + j0, nb, Tm);
+        double *parts = nullptr;
+        int ks_s = 1, ks_w = 1;
+        if constexpr (sizeof(T) == 8) {
+            ks_s = (int)std::min<int64_t>(64, std::max<int64_t>(1, m / 512));
+            const int64_t tiles_w = ((n + 127) / 128) * ((nb + 127) / 128);
+            ks_w = (int)std::min<int64_t>({32, std::max<int64_t>(1, m / 512),
+                                           std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles_w, 1))});
+            void *wp = nullptr;
+            const size_t need = (size_t)ks_s * nb * nb + (size_t)ks_w * nb * n;
+            if ((rc = workspace_get(need * sizeof(double), ws::OrmtrParts, &wp))) return rc;
+            parts = (double *)wp;
+        }
+        g[0] = G{V, m, V, m, Sg, nb, nb, nb, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
+        if constexpr (sizeof(T) == 8) {
+            g[0].ksplit = ks_s;
+            g[0].Cpart = parts;
+        }
+        if ((rc = gemm_batched(g, ws::OrmtrGram, stream))) return rc;
+        if constexpr (sizeof(T) == 8) {
+            std::vector<ReduceDesc> red{ReduceDesc{Sg, nb, nb, nb, parts, ks_s, 0.0, 0}};
+            if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
+        }
+        hipLaunchKernelGGL(larft_blocks_kernel<T>, dim3(nbk), dim3(64), 0, stream, Sg, tau + j0, nb, Tm);
         TGBA_HIP(hipGetLastError());
         for (int q = 1; q < nbk; ++q) {  // T(0:a, a:a+w) = -T(0:a, 0:a) S(0:a, a:a+w) T(a:a+w, a:a+w)
             const int a = q * kNB, w = std::min(kNB, nb - a);
-            g[0] = GemmDesc{Sg + (size_t)a * nb, nb, Tm + a + (size_t)a * nb, nb, Y, kBT, a, w, w, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-            if ((rc = dgemm_batched(g, ws::OrmtrT, stream))) return rc;
-            g[0] = GemmDesc{Tm, nb, Y, kBT, Tm + (size_t)a * nb, nb, a, w, a, -1.0, 0.0, 0, 0, 0, 0, 0, 0};
-            if ((rc = dgemm_batched(g, ws::OrmtrT, stream))) return rc;
+            g[0] = G{Sg + (size_t)a * nb, nb, Tm + a + (size_t)a * nb, nb, Y, kBT, a, w, w, T(1), T(0), 0, 0, 0, 0, 0, 0};
+            if ((rc = gemm_batched(g, ws::OrmtrT, stream))) return rc;
+            g[0] = G{Tm, nb, Y, kBT, Tm + (size_t)a * nb, nb, a, w, a, T(-1), T(0), 0, 0, 0, 0, 0, 0};
+            if ((rc = gemm_batched(g, ws::OrmtrT, stream))) return rc;
         }
-        g[0] = GemmDesc{V, m, Zs, ldz, W1, nb, nb, n, m, 1.0, 0.0, 1, 0, 0, 0, 0, 0};
-        g[0].ksplit = ks_w;
-        g[0].Cpart = parts + (size_t)ks_s * nb * nb;
-        if ((rc = dgemm_batched(g, ws::OrmtrW, stream))) return rc;
-        red[0] = ReduceDesc{W1, nb, nb, n, parts + (size_t)ks_s * nb * nb, ks_w, 0.0, 0};
-        if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
-        g[0] = GemmDesc{Tm, nb, W1, nb, W2, nb, nb, n, nb, 1.0, 0.0, 0, 0, 0, 0, 0, 0};
-        if ((rc = dgemm_batched(g, ws::OrmtrT, stream))) return rc;
-        g[0] = GemmDesc{V, m, W2, nb, Zs, ldz, m, n, nb, -1.0, 1.0, 0, 0, 0, 0, 0, 0};
-        if ((rc = dgemm_batched(g, ws::OrmtrUpdate, stream))) return rc;
-    }
-    return TGBA_OK;
-}
-
-template <typename T>
-int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream) {
-    if (n < 2) return TGBA_OK;
-    if constexpr (sizeof(T) == 8) return ormtr_f64(n, A, lda, tau, Z, ldz, scratch, stream);
-    using G = typename GemmOf<T>::type;
-    T *V = scratch;
-    T *W1 = V + (size_t)n * kNB;
-    T *W2 = W1 + (size_t)n * kNB;
-    T *Sg = W2 + (size_t)n * kNB;
-    T *Tm = Sg + kNB * kNB;
-    const int64_t nref = n - 1;
-    const int64_t npan = (nref + kNB - 1) / kNB;
-    for (int64_t p = npan - 1; p >= 0; --p) {
-        const int64_t j0 = p * kNB;
-        const int nbp = (int)std::min<int64_t>(kNB, nref - j0);
-        const int64_t m = n - j0 - 1;
-        hipLaunchKernelGGL(extract_v_kernel<T>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nbp, V);
-        TGBA_HIP(hipGetLastError());
-        std::vector<G> g(1);
-        T *Zs = Z + (j0 + 1);
-        g[0] = G{V, m, V, m, Sg, nbp, nbp, nbp, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
-        int rc;
+        g[0] = G{V, m, Zs, ldz, W1, nb, nb, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
         if constexpr (sizeof(T) == 8) {
-            // the two products with K = m have few output tiles: split K over workgroups
-            const int ks_s = (int)std::min<int64_t>(64, std::max<int64_t>(1, m / 512));
-            const int64_t tiles_w = (n + 127) / 128;
-            const int ks_w = (int)std::min<int64_t>({32, std::max<int64_t>(1, m / 512),
-                                                      std::max<int64_t>(1, 2048 / std::max<int64_t>(tiles_w, 1))});
-            void *wp = nullptr;
-            const size_t need = (size_t)ks_s * nbp * nbp + (size_t)ks_w * nbp * n;
-            if ((rc = workspace_get(need * sizeof(double), ws::OrmtrParts, &wp))) return rc;
-            double *parts = (double *)wp;
-            g[0].ksplit = ks_s;
-            g[0].Cpart = parts;
-            if ((rc = gemm_batched(g, ws::OrmtrGram, stream))) return rc;
-            std::vector<ReduceDesc> red{ReduceDesc{Sg, nbp, nbp, nbp, parts, ks_s, 0.0, 0}};
-            if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
-            hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
-            TGBA_HIP(hipGetLastError());
-            g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
             g[0].ksplit = ks_w;
-            g[0].Cpart = parts + (size_t)ks_s * nbp * nbp;
-            if ((rc = gemm_batched(g, ws::OrmtrW, stream))) return rc;
-            red[0] = ReduceDesc{W1, nbp, nbp, n, parts + (size_t)ks_s * nbp * nbp, ks_w, 0.0, 0};
-            if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
-        } else {
-            if ((rc = gemm_batched(g, ws::OrmtrGram, stream))) return rc;
-            hipLaunchKernelGGL(larft_kernel<T>, dim3(1), dim3(64), 0, stream, Sg, tau + j0, nbp, Tm);
-            TGBA_HIP(hipGetLastError());
-            g[0] = G{V, m, Zs, ldz, W1, nbp, nbp, n, m, T(1), T(0), 1, 0, 0, 0, 0, 0};
-            if ((rc = gemm_batched(g, ws::OrmtrW, stream))) return rc;
+            g[0].Cpart = parts + (size_t)ks_s * nb * nb;
         }
-        g[0] = G{Tm, nbp, W1, nbp, W2, nbp, nbp, n, nbp, T(1), T(0), 0, 0, 0, 0, 0, 0};
-        rc = gemm_batched(g, ws::OrmtrT, stream);
-        if (rc) return rc;
-        g[0] = G{V, m, W2, nbp, Zs, ldz, m, n, nbp, T(-1), T(1), 0, 0, 0, 0, 0, 0};
-        rc = gemm_batched(g, ws::OrmtrUpdate, stream);
-        if (rc) return rc;
+        if ((rc = gemm_batched(g, ws::OrmtrW, stream))) return rc;
+        if constexpr (sizeof(T) == 8) {
+            std::vector<ReduceDesc> red{ReduceDesc{W1, nb, nb, n, parts + (size_t)ks_s * nb * nb, ks_w, 0.0, 0}};
+            if ((rc = splitk_reduce(red, ws::OrmtrRed, stream))) return rc;
+        }
+        g[0] = G{Tm, nb, W1, nb, W2, nb, nb, n, nb, T(1), T(0), 0, 0, 0, 0, 0, 0};
+        if ((rc = gemm_batched(g, ws::OrmtrT, stream))) return rc;
+        g[0] = G{V, m, W2, nb, Zs, ldz, m, n, nb, T(-1), T(1), 0, 0, 0, 0, 0, 0};
+        if ((rc = gemm_batched(g, ws::OrmtrUpdate, stream))) return rc;
     }
     return TGBA_OK;
 }
@@ -1078,7 +1004,7 @@ static int eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_ref
     void *ws = nullptr;
     const size_t nn = (size_t)n * n;
     const size_t fcount = 2 * nn + (size_t)n * kNB + 3 * (size_t)n + S_LEN + 64 + (size_t)symv_partials(n) +
-                          4 * (size_t)n * kNB + 2 * kNB * kNB + 64;
+                          ormtr_scratch_elems(n);
     int rc = workspace_get(fcount * sizeof(float), ws::MixedF32, &ws);
     if (rc) return rc;
     float *A32 = (float *)ws, *Z32 = A32 + nn, *W32 = Z32 + nn, *d32 = W32 + (size_t)n * kNB, *e32 = d32 + n,
@@ -1194,7 +1120,7 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
         TriSec &S = secs[k];
         const int64_t nn = S.n;
         void *zw = nullptr;
-        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + ormtr_scratch_doubles(nn));
+        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + ormtr_scratch_elems(nn));
         rc = workspace_get(zbytes, ws::EigVecZ, &zw);
         if (rc) return rc;
         double *Zt = (double *)zw;
