@@ -777,8 +777,8 @@ int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream) {
 }
 
 
-// Z (n x n, ldz) <- Q Z with the reflectors of tgba_sytrd stored in A.
-// scratch: n*64 (V) + 3 n*64 (W1, W2) + 2*64*64 (S, T) doubles.
+// Scratch of the back-transform: V (n x kBT), W1 and W2 (kBT x n), the Gram
+// matrix and T (kBT x kBT each), the coupling product Y (kBT x kNB).
 size_t ormtr_scratch_elems(int64_t n) {
     return 3 * (size_t)n * kBT + 2 * (size_t)kBT * kBT + (size_t)kBT * kNB + 1024;
 }
