@@ -772,8 +772,13 @@ def main():
         "config": {"workload": a.workload, "N": N, "h_perp": w["h_perp"], "h_par": w["h_par"],
                    "sectors": N, "chi_min": int(min(n)), "chi_max": int(max(n)), "elements": elements,
                    "gauge": "real", "fill": "lower"},
+        "value_definition": "H_eff lower-triangle elements of all sectors of one step / wall time of the whole "
+                            "step (every sector's H_eff assembly, both eigensolve groups, the K=0 S(omega) and quench), "
+                            "basis already built and resident in HBM",
         "stages_ms": stage_ms,
         "assembly_elements_per_s": elements / (asm_ms * 1e-3),
+        "assembly_definition": "the same elements / the assembly kernel's own time (one all-sector launch, "
+                               "HIP events on its stream); the eigensolve is not in it",
         "basis_build_s": t_basis,
         "assembly_stats": {"flagged_rows": stats[0], "generic_elements": stats[1], "unsupported": stats[2],
                            "deflated_rows": stats[3]},
