@@ -36,6 +36,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 128, TN = 128, LDS_STRIDE = TM + 4;
 constexpr int TKD = 32;  // K-tile depth of the FP64 kernel
+constexpr int64_t kMaxLd = (int64_t)1 << 21;  // leading dimensions below this keep tile offsets in 32 bits
 // TNV: output-tile width, 128, or 64 for products with N <= 64 (panel products)
 
 __device__ __forceinline__ int gemm_desc_of(const GemmDesc *d, int nd, int64_t blk) {
@@ -62,6 +63,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t op_rsrc(const double *base, in
 }
 __device__ __forceinline__ double op_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// Stores past the extent are dropped by the hardware.
+__device__ __forceinline__ void op_st(__amdgpu_buffer_rsrc_t r, double v, uint32_t voff) {
+    using W = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, voff, 0u, 0);
 }
 
 // One K-tile (32) of op(A) (128 x 32) and op(B) (32 x TNV) into registers:
@@ -302,20 +308,45 @@ dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
                 }
         return;
     }
+    // C through one buffer resource whose extent ends at the tile's last entry (or at C's last
+    // element): TNV - 1 leading dimensions and a column of TM, below 2^31 bytes.  A masked
+    // element (beyond M or N, or above the diagonal of a lower-only update) is stored at offset
+    // 2^31, past the extent, where the hardware drops it, so the stores need no branches.  With
+    // beta != 0, C is read one block row (a) at a time, its loads all in flight before its
+    // stores, so a tile waits for memory four times rather than once per element; the loads
+    // need no mask (entries that are not stored are read and dropped, and reads past the
+    // extent return 0).
+    const int64_t ext = min((G.M - m0) + (G.N - 1 - n0) * G.ldc, (int64_t)(TNV - 1) * G.ldc + TM);
+    const auto crs = op_rsrc(G.C + m0 + n0 * G.ldc, ext * (int64_t)sizeof(double));
+    const uint32_t lc = (uint32_t)(G.ldc * (int64_t)sizeof(double));
+    const int il = 64 * wy + (lane & 15), jl = WN * wx + (lane >> 4);  // tile-local row, column of block (0, 0)
+    const uint32_t v0 = (uint32_t)il * 8u + (uint32_t)jl * lc;
+    auto dst = [&](int a, int b, int rr) -> uint32_t {
+        const int64_t i = m0 + il + 16 * a, j = n0 + jl + 16 * b + 4 * rr;
+        const bool keep = i < G.M && j < G.N && (!G.lower || i >= j);
+        return keep ? v0 + 128u * a + (uint32_t)(16 * b + 4 * rr) * lc : 0x80000000u;
+    };
+    if (G.beta == 0.0) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) op_st(crs, G.alpha * acc[a][b][rr], dst(a, b, rr));
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double cv[NB][4];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int64_t i = m0 + 64 * wy + 16 * a + (lane & 15);
-                const int64_t j = n0 + WN * wx + 16 * b + 4 * rr + (lane >> 4);
-                if (i < G.M && j < G.N && (!G.lower || i >= j)) {
-                    double *c = G.C + i + j * G.ldc;
-                    const double v = G.alpha * acc[a][b][rr];
-                    *c = (G.beta == 0.0) ? v : v + G.beta * (*c);
-                }
-            }
+            for (int rr = 0; rr < 4; ++rr) cv[b][rr] = op_ld(crs, v0 + 128u * a + (uint32_t)(16 * b + 4 * rr) * lc, 0u);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) op_st(crs, G.alpha * acc[a][b][rr] + G.beta * cv[b][rr], dst(a, b, rr));
+    }
 }
 
 }  // namespace
@@ -532,6 +563,10 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
             return set_error(TGBA_EINVAL, "symmetric operand: needs M == K and no second part, mask or lower-only output");
         if (g.K2 && (g.K % TKD))  // the second part starts at a K-tile boundary
             return set_error(TGBA_EINVAL, "two-part product: the first part's K must be a multiple of 32");
+        // the kernel addresses a tile's operands and C through 32-bit byte offsets from the
+        // tile's origin, up to 255 leading dimensions away (symmetric diagonal K-tiles)
+        if (std::max({g.lda, g.ldb, g.ldc, g.lda2, g.ldb2}) >= kMaxLd)
+            return set_error(TGBA_EINVAL, "leading dimension of 2^21 or more");
         g.tiles_m = (g.M + TM - 1) / TM;
         g.first_tile = total;
         g.ntile = gemm_tiles(g, tnv);

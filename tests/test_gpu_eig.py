@@ -46,6 +46,29 @@ def test_dgemm_matches_numpy(tA, tB, M, N, K):
     assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("beta", [0.0, -1.3])
+@pytest.mark.parametrize("M,N,K,ldc", [(130, 257, 33, 173), (300, 64, 200, 301), (129, 1, 40, 1000)])
+def test_dgemm_padded_c_keeps_its_padding(M, N, K, ldc, beta):
+    """C with a leading dimension above M: the rows M .. ldc-1 of every column are NaN and must
+    stay NaN (the epilogue reads them with the rest of a tile and never stores them); the
+    product matches numpy.  Ragged 128 x 128 and 128 x 64 tiles, beta zero and nonzero."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    rng = np.random.default_rng(M + 3 * N + 7 * K + ldc)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(K, N))
+    C = rng.normal(size=(M, N))
+    Cp = np.full((N, ldc), np.nan)
+    Cp[:, :M] = C.T
+    dA, dB = _cm(A), _cm(B)
+    dC = torch.as_tensor(Cp, device="cuda")
+    tg.dgemm(0, 0, M, N, K, 0.7, dA, dB, beta, dC)
+    got = dC.cpu().numpy()
+    assert np.isnan(got[:, M:]).all()
+    ref = 0.7 * (A @ B) + beta * C
+    assert np.abs(got[:, :M].T - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
 def _rand_sym(n, seed):
     rng = np.random.default_rng(seed)
     X = rng.normal(size=(n, n))
