@@ -356,7 +356,8 @@ namespace {
 // ---- single precision: v_mfma_f32_32x32x2f32 ---------------------------------
 // Lane layout: operand a of lane l is A[l%32][l/32], operand b is B[l/32][l%32];
 // accumulator r holds D[8(r/4) + 4(l/32) + r%4][l%32].  Each wave computes a
-// 64 x 64 sub-tile as 2 x 2 blocks of 32 x 32.
+// 64 x 64 sub-tile as 2 x 2 blocks of 32 x 32, each transposed (D = B^T A^T, as in
+// the FP64 kernel) so that 32 consecutive lanes store 32 consecutive rows of C.
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ int sgemm_desc_of(const SGemmDesc *d, int nd, int64_t blk) {
@@ -381,6 +382,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t op_rsrc_f(const float *base, i
 }
 __device__ __forceinline__ float op_ld_f(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void op_st_f(__amdgpu_buffer_rsrc_t r, float v, uint32_t voff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0u, 0);
 }
 
 // One K-tile (32) of op(A) (128 x 32) and op(B) (32 x 128): 16 values of each per
@@ -504,23 +508,41 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SGemmDesc *__restrict_
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(bf[b], af[a], acc[a][b], 0, 0, 0);
         }
     }
+    // epilogue as in dgemm_kernel: one buffer resource over the tile's footprint in C, masked
+    // elements stored past the extent, C read a block row at a time
+    const int64_t ext = min((G.M - m0) + (G.N - 1 - n0) * G.ldc, (int64_t)(TN - 1) * G.ldc + TM);
+    const auto crs = op_rsrc_f(G.C + m0 + n0 * G.ldc, ext);
+    const uint32_t lc = (uint32_t)(G.ldc * (int64_t)sizeof(float));
+    const int il = 64 * wy + (lane & 31), jl = 64 * wx + 4 * (lane >> 5);  // tile-local row, column of r = 0
+    const uint32_t v0 = (uint32_t)il * 4u + (uint32_t)jl * lc;
+    auto coff = [&](int a, int b, int r) -> uint32_t {
+        return v0 + 128u * a + (uint32_t)(32 * b + 8 * (r >> 2) + (r & 3)) * lc;
+    };
+    auto dst = [&](int a, int b, int r) -> uint32_t {
+        const int64_t i = m0 + il + 32 * a, j = n0 + jl + 32 * b + 8 * (r >> 2) + (r & 3);
+        return (i < G.M && j < G.N && (!G.lower || i >= j)) ? coff(a, b, r) : 0x80000000u;
+    };
+    const bool rd = G.beta != 0.0f;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a) {
+        float cv[2][16];
+        if (rd) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) cv[b][r] = op_ld_f(crs, coff(a, b, r), 0u);
+        }
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t i = m0 + 64 * wy + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t j = n0 + 64 * wx + 32 * b + (lane & 31);
-                if (i < G.M && j < G.N && (!G.lower || i >= j)) {
-                    float *c = G.C + i + j * G.ldc;
-                    const float v = G.alpha * acc[a][b][r];
-                    *c = (G.beta == 0.0f) ? v : v + G.beta * (*c);
-                }
+                const float v = G.alpha * acc[a][b][r];
+                op_st_f(crs, rd ? v + G.beta * cv[b][r] : v, dst(a, b, r));
             }
+    }
 }
 
 }  // namespace
@@ -528,6 +550,7 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SGemmDesc *__restrict_
 int sgemm_batched(std::vector<SGemmDesc> &descs, int slot, hipStream_t stream) {
     int64_t total = 0;
     for (auto &g : descs) {
+        if (std::max({g.lda, g.ldb, g.ldc}) >= kMaxLd) return set_error(TGBA_EINVAL, "leading dimension of 2^21 or more");
         g.tiles_m = (g.M + TM - 1) / TM;
         g.first_tile = total;
         const int64_t tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;

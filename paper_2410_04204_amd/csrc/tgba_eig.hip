@@ -433,36 +433,48 @@ __global__ void zero_kernel(T *p, int64_t n) {
 }
 
 // ---- bisection on Sturm counts (one thread per eigenvalue) ----------------
+// Every workgroup belongs to one sector, so the sector, and the index of the
+// Sturm recurrence, are the same for all its lanes: d and e are read with
+// scalar loads and broadcast to the lanes, where a per-lane read of the same
+// entry would pass 64 copies of it through the vector memory return path.
 struct BisSec {
     const double *d, *e;  // diagonal (n), off-diagonal (n-1)
     double *w;            // eigenvalues out (n)
     int64_t n;
-    int64_t first;        // first global thread of this sector
+    int64_t first;        // first workgroup of this sector
 };
+constexpr int kBisThreads = 256;
 
-__device__ __forceinline__ int64_t sturm_count(const double *d, const double *e, int64_t n, double x, double pivmin) {
-    int64_t cnt = 0;
+// d and e in the constant address space: the kernel never writes them, and a
+// wave-uniform load from there is a scalar load.
+typedef const double __attribute__((address_space(4))) *ConstF64;
+
+__device__ __forceinline__ int sturm_count(ConstF64 d, ConstF64 e, int n, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
-    cnt += (q < 0.0);
-    for (int64_t k = 1; k < n; ++k) {
-        q = d[k] - x - e[k - 1] * e[k - 1] / q;
+    int cnt = q < 0.0;
+#pragma unroll 4
+    for (int k = 1; k < n; ++k) {
+        const double ek = e[k - 1];
+        q = d[k] - x - ek * ek / q;
         if (fabs(q) < pivmin) q = -pivmin;
-        cnt += (q < 0.0);
+        cnt += q < 0.0;
     }
     return cnt;
 }
 
-__global__ void __launch_bounds__(256) bisect_kernel(const BisSec *secs, int nsec, const double *bounds) {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBisThreads) bisect_kernel(const BisSec *__restrict__ secs, int nsec,
+                                                             const double *__restrict__ bounds) {
+    const int64_t blk = blockIdx.x;
     int lo_s = 0, hi_s = nsec - 1;
     while (lo_s < hi_s) {
         int mid = (lo_s + hi_s + 1) >> 1;
-        if (secs[mid].first <= g) lo_s = mid; else hi_s = mid - 1;
+        if (secs[mid].first <= blk) lo_s = mid; else hi_s = mid - 1;
     }
     const BisSec S = secs[lo_s];
-    const int64_t k = g - S.first;
-    if (k < 0 || k >= S.n) return;
+    const int64_t k = (blk - S.first) * kBisThreads + threadIdx.x;
+    if (k >= S.n) return;
+    const int n = (int)S.n;
     double lo = bounds[3 * lo_s], hi = bounds[3 * lo_s + 1];
     const double pivmin = bounds[3 * lo_s + 2];
     // invariant: count(lo) <= k < count(hi)
@@ -470,7 +482,7 @@ __global__ void __launch_bounds__(256) bisect_kernel(const BisSec *secs, int nse
         const double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
         if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-        if (sturm_count(S.d, S.e, S.n, mid, pivmin) > k) hi = mid; else lo = mid;
+        if (sturm_count((ConstF64)S.d, (ConstF64)S.e, n, mid, pivmin) > k) hi = mid; else lo = mid;
     }
     S.w[k] = 0.5 * (lo + hi);
 }
@@ -869,10 +881,11 @@ int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
     const int nsec = (int)in.size();
     if (nsec == 0) return TGBA_OK;
     std::vector<BisSec> secs(nsec);
-    int64_t total = 0;
+    int64_t total = 0;  // workgroups
     for (int k = 0; k < nsec; ++k) {
+        if (in[k].n >= ((int64_t)1 << 31)) return set_error(TGBA_EINVAL, "bisection: order of 2^31 or more");
         secs[k] = BisSec{in[k].d, in[k].e, in[k].w, in[k].n, total};
-        total += in[k].n;
+        total += (in[k].n + kBisThreads - 1) / kBisThreads;
     }
     void *ws = nullptr, *wb = nullptr;
     int rc = upload(secs.data(), nsec * sizeof(BisSec), ws::BisectSecs, stream, &ws);
@@ -881,7 +894,8 @@ int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
     BisSec *d_secs = (BisSec *)ws;
     double *bounds = (double *)wb;
     hipLaunchKernelGGL(gersh_kernel, dim3(nsec), dim3(256), 0, stream, d_secs, bounds);
-    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, d_secs, nsec, bounds);
+    if (total > 0)
+        hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)total), dim3(kBisThreads), 0, stream, d_secs, nsec, bounds);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }
