@@ -303,6 +303,9 @@ int tgba_plan_info(const tgba_plan *plan, int64_t *nodes, int64_t *bytes);
 #define TGBA_EIG_NOVEC 0x2   /* eigenvalues only                                         */
 #define TGBA_EIG_ONESTAGE 0x4 /* with TGBA_EIG_NOVEC: the one-stage reduction of the vector path
                                 instead of the two-stage one (comparison and testing)     */
+#define TGBA_EIG_TWOSTAGE 0x8 /* with vectors: the two-stage reduction keeping its reflectors,
+                                divide and conquer on the tridiagonal, then the bulge
+                                reflectors' and the band reduction's back-transforms     */
 
 /*
  * Eigen-decomposition A = Z diag(w) Z^T of a real symmetric n x n device
@@ -345,11 +348,16 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
 /*
  * Several sectors, some with eigenvectors: want_vectors (host, nsec) marks the
  * sectors whose A is to be overwritten by Z; the others get eigenvalues only
- * (A overwritten).  The eigenvalue-only sectors take the two-stage path on
- * `stream`; the vector sectors run at the same time on a second stream of the
- * device (ordered after the work already queued on `stream`), from a second
- * host thread, so that the latency-bound parts of each path overlap the other.
- * Returns when both are done.  Errors: as tgba_eig_batched.
+ * (A overwritten).  All sectors go through one batched two-stage reduction; the
+ * eigenvalue-only sectors then take bisection on `stream`, and the vector
+ * sectors (whose reduction keeps its reflectors: 8 n^2 bytes of bulge
+ * reflectors per sector in the library's workspace) take divide and conquer and
+ * the two back-transforms (TGBA_EIG_TWOSTAGE) on a second stream of the device,
+ * joined back into `stream`.  With the environment variable
+ * TGBA_VEC_REDUCTION=onestage the vector sectors instead take the one-stage
+ * reduction (tgba_eig) on the second stream from a second host thread, beside
+ * the eigenvalue-only sectors' two-stage path.  Returns when all are done.
+ * Errors: as tgba_eig_batched.
  */
 int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,
                          const int *want_vectors, void *stream);

@@ -11,13 +11,13 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
+from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_EIG_TWOSTAGE, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_HEFF,
                    TGBA_LOWER, TgbaError)
 
 __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "assemble_corr",
            "quench_corr", "corr_table", "corr_signs", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
-           "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
+           "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TGBA_EIG_TWOSTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
            "mlp_select", "quench_weights", "autotune_enable", "autotune_report", "AssemblyPlan"]
 

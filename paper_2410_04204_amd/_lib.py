@@ -16,7 +16,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUP
 
 TGBA_TRUNC_ECUT, TGBA_TRUNC_CHI, TGBA_TRUNC_LEARNED, TGBA_TRUNC_OVERLAP, TGBA_TRUNC_UNION = 0, 1, 2, 3, 4
 TGBA_HEFF, TGBA_GAMMA1, TGBA_GAUGE_PAPER, TGBA_LOWER = 0x0, 0x1, 0x2, 0x4
-TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE = 0x0, 0x1, 0x2, 0x4
+TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONESTAGE, TGBA_EIG_TWOSTAGE = 0x0, 0x1, 0x2, 0x4, 0x8
 
 EXPORTS = [
     "tgba_last_error", "tgba_version", "tgba_build_basis", "tgba_basis_free", "tgba_basis_sector_size",

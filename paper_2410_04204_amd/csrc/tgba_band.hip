@@ -86,6 +86,8 @@ struct BandSec {
     int64_t cap;       // stage 2: workgroups of this sector per step
     double *Q;      // n x 4 BW (ld n): a panel pair's [V1' V2 W1' W2] for the rank-4 BW update
     int *prog;      // stage 2, sweep schedule: tasks completed per sweep (n)
+    double *v2;     // stage 2, optional: reflector of task (i, k) at v2 + (i v2ks + k) BW (slot 0: its tau)
+    int64_t v2ks;   // tasks per sweep in v2
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -332,7 +334,7 @@ struct BulgeLds {
 // Callers put a barrier between two tasks of one workgroup (LDS reuse).
 __device__ __forceinline__ void bulge_task(double *__restrict__ B, int64_t n, int64_t i, int64_t k, bool e_in_regs,
                                            bool keep_f, double (&E)[NJ], double (&D)[NJ], double (&F)[NJ],
-                                           BulgeLds &L) {
+                                           BulgeLds &L, double *__restrict__ v2, int64_t v2ks) {
     constexpr int NW = kPairWaves;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: column addresses stay scalar
@@ -371,6 +373,8 @@ __device__ __forceinline__ void bulge_task(double *__restrict__ B, int64_t n, in
         L.vs[lane] = (lane == 0) ? 1.0 : ((lane < ln) ? x * scale : 0.0);
         if (lane < ln) ecol(0)[lane] = (lane == 0) ? beta : 0.0;
         if (lane == 0) L.par[0] = tau;
+        // kept for the back-transform: v below its unit entry, tau in the unit entry's place
+        if (v2) v2[(i * v2ks + k) * BW + lane] = (lane == 0) ? tau : ((lane < ln) ? x * scale : 0.0);
     }
     __syncthreads();
     const double tau = L.par[0];
@@ -468,7 +472,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_p
         const int64_t k = 2 * kap + h;
         if (k > kmax) break;  // uniform
         if (h == 1) __syncthreads();  // the first task's readers of the LDS vectors are done
-        bulge_task(B, n, i, k, h == 1, h == 0 && k + 1 <= kmax, E, D, F, L);
+        bulge_task(B, n, i, k, h == 1, h == 0 && k + 1 <= kmax, E, D, F, L, secs[s].v2, secs[s].v2ks);
     }
 }
 
@@ -564,7 +568,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_p
             }
             __syncthreads();
             if (s_stop) return;  // uniform
-            bulge_task(B, n, i, k, k > 0, k < kmax, E, D, F, L);
+            bulge_task(B, n, i, k, k > 0, k < kmax, E, D, F, L, S.v2, S.v2ks);
             // publish task k: every wave's stores complete, the L2 written back, then the count
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
@@ -714,7 +718,8 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.n = x.n;
         S.d = x.d;
         S.e = x.e;
-        S.tau = p; p += x.n;
+        S.tau = x.tau ? x.tau : p;  // the caller keeps the panel reflectors' tau
+        p += x.n;
         S.V = p; p += (size_t)x.n * BW;
         S.X = p; p += (size_t)x.n * BW;
         S.W = p; p += (size_t)x.n * BW;
@@ -726,6 +731,8 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         S.M = p; p += BW * BW;
         S.Q = p; p += (size_t)x.n * 4 * BW;
         S.prog = (int *)p; p += (size_t)(x.n + 1) / 2 + 1;
+        S.v2 = x.v2;
+        S.v2ks = bulge_v2_stride(x.n);
         S.first_wg = wg;
         S.cap = (x.n >= 3) ? ((x.n - 3) / BW) / (2 * kStride) + 2 : 0;  // pairs of one step, per sector
         wg += S.cap;
@@ -1117,6 +1124,220 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
         if ((rc = timing_push(ta, tb, bytes, 3))) return rc;
     }
     hipLaunchKernelGGL(band_tridiag_kernel, dim3(64, nsec), dim3(256), 0, stream, d_secs);
+    TGBA_HIP(hipGetLastError());
+    return TGBA_OK;
+}
+
+// ---- back-transform of the second stage: Z <- Q2 Z ------------------------------
+// Q2 is the product of the bulge-chasing reflectors in the order the reduction
+// applied them: sweep i ascending, within a sweep task k ascending, H_{i,k}
+// acting on rows i + 1 + k BW .. + BW - 1.  Two reflectors of sweeps i < i' with
+// i' - i < BW share a row only when k' = k or k' = k - 1 (the row ranges are at
+// most BW long and start i' - i + (k' - k) BW apart), and reflectors of one
+// sweep never do.  Within a block of 64 consecutive sweeps i0 .. i0 + 63 the
+// product is therefore G_K ... G_1 G_0 with G_k = H_{i0,k} H_{i0+1,k} ...
+// H_{i0+63,k}: the reordering only moves reflectors past others on disjoint
+// rows.  G_k acts on the window of 2 BW - 1 rows from i0 + 1 + k BW, as
+// I - V_k T_k V_k^T where column j of V_k is the reflector of sweep i0 + j moved
+// down by j rows (compact WY form, T_k upper triangular).  Z <- Q2 Z applies the
+// blocks last first and, within a block, G_0 first.  Per block: q2_build_kernel
+// forms V_k and Y_k = -V_k T_k of every k; q2_apply_kernel gives each workgroup
+// 48 columns of Z and slides a 128-row window down the rows, BW rows per k:
+// W = V_k^T Zw and Zw += Y_k W on the FP64 matrix cores, then the top BW rows
+// are final for the block and go to memory while the rest stay in LDS.
+
+int64_t bulge_v2_stride(int64_t n) { return n >= 3 ? (n - 3) / BW + 1 : 0; }
+size_t bulge_v2_doubles(int64_t n) { return n >= 3 ? (size_t)(n - 2) * (size_t)bulge_v2_stride(n) * BW : 0; }
+
+namespace {
+typedef double q2d4 __attribute__((ext_vector_type(4)));
+constexpr int kQ2Frag = 16384;  // doubles of one G_k's operand fragments (V_k 8192, Y_k 8192)
+constexpr int LDZ2 = 129;       // LDS column stride of the window (odd: 16 lanes on 16 rows hit distinct banks)
+constexpr int kQ2Cols = 48;     // columns of Z per workgroup of q2_apply_kernel
+
+// One workgroup per k of the block at sweep i0.  Writes the matrix-core operand
+// fragments of G_k in the order q2_apply_kernel's lanes read them:
+//   F1[w][q][l] = V_k[4 q + l / 16][16 w + l % 16]        (w < 4, q < 32)
+//   F2[w][a][q][l] = Y_k[32 w + 16 a + l % 16][4 q + l / 16]  (w < 4, a < 2, q < 16)
+__global__ void __launch_bounds__(256) q2_build_kernel(const double *__restrict__ v2, int64_t n, int64_t ks, int64_t i0,
+                                                       double *__restrict__ F) {
+    __shared__ double Vs[128][65];  // V_k (window row, sweep j); row 127 stays zero
+    __shared__ double Ts[64][65];   // V_k^T V_k, overwritten column by column by T_k (upper)
+    __shared__ double tau[64], colv[64];
+    const int tid = threadIdx.x;
+    const int64_t k = blockIdx.x;
+    for (int e = tid; e < 128 * 64; e += 256) Vs[e >> 6][e & 63] = 0.0;
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int j = e >> 6, l = e & 63;
+        const int64_t i = i0 + j;
+        const bool ex = i <= n - 3 && k <= (n - 3 - i) / BW;  // task (i, k) exists
+        double v = ex ? v2[(i * ks + k) * BW + l] : 0.0;
+        if (l == 0) {
+            tau[j] = v;
+            v = ex ? 1.0 : 0.0;
+        }
+        Vs[j + l][j] = v;
+    }
+    __syncthreads();
+    // Gram (upper triangle): columns a <= b share the rows b .. a + 63
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int a = e >> 6, b = e & 63;
+        if (a <= b) {
+            double g = 0.0;
+            for (int r = b; r < a + 64; ++r) g += Vs[r][a] * Vs[r][b];
+            Ts[a][b] = g;
+        }
+    }
+    __syncthreads();
+    // T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j)
+    for (int j = 0; j < 64; ++j) {
+        if (tid < j) {
+            double acc = 0.0;
+            for (int l = tid; l < j; ++l) acc += Ts[tid][l] * Ts[l][j];
+            colv[tid] = -tau[j] * acc;
+        }
+        __syncthreads();
+        if (tid < j) Ts[tid][j] = colv[tid];
+        if (tid == j) Ts[j][j] = tau[j];
+        __syncthreads();
+    }
+    double *F1 = F + k * kQ2Frag, *F2 = F1 + kQ2Frag / 2;
+    for (int e = tid; e < 8192; e += 256) {
+        const int l = e & 63, q = (e >> 6) & 31, w = e >> 11;
+        F1[e] = Vs[4 * q + (l >> 4)][16 * w + (l & 15)];
+    }
+    // Y_k = -V_k T_k: entry (r, c) sums over sweeps a <= c whose column reaches row r
+    for (int e = tid; e < 8192; e += 256) {
+        const int l = e & 63, q = (e >> 6) & 15, a = (e >> 10) & 1, w = e >> 11;
+        const int r = 32 * w + 16 * a + (l & 15), c = 4 * q + (l >> 4);
+        const int alo = r - 63 > 0 ? r - 63 : 0, ahi = c < r ? c : r;
+        double y = 0.0;
+        for (int aa = alo; aa <= ahi; ++aa) y += Vs[r][aa] * Ts[aa][c];
+        F2[e] = -y;
+    }
+}
+
+// One workgroup of 4 waves per kQ2Cols columns of Z (n rows, ncol columns, ld
+// ldz), kc windows of the block at sweep i0.  Window row r of step k is global
+// row i0 + 1 + k BW + r and lives in LDS slot (r + 64 (k & 1)) & 127.  76 KB of
+// LDS and at most 256 registers: two workgroups per compute unit, so a launch
+// for n <= 24576 (512 workgroups) runs in one round.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q2_apply_kernel(double *__restrict__ Z, int64_t ldz, int64_t n, int64_t ncol,
+                                                       int64_t i0, int kc, const double *__restrict__ F) {
+    constexpr int CW = kQ2Cols, NBC = CW / 16, LDW = CW + 4;
+    __shared__ double Zs[CW * LDZ2];  // column c of the chunk at Zs + c LDZ2
+    __shared__ double Ws[64 * LDW];   // W = V_k^T Zw, row-major
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int64_t c0 = (int64_t)blockIdx.x * CW, w00 = i0 + 1;
+    double pre[CW / 4];
+    // 64 rows from global row g0 of the chunk's columns: lane -> row, wave + 4 j -> column
+    auto gload = [&](int64_t g0) {
+        const int64_t g = g0 + lane;
+#pragma unroll
+        for (int j = 0; j < CW / 4; ++j) {
+            const int64_t c = c0 + wave + 4 * j;
+            pre[j] = (g < n && c < ncol) ? Z[g + c * ldz] : 0.0;
+        }
+    };
+    auto lstore = [&](int slot0) {
+#pragma unroll
+        for (int j = 0; j < CW / 4; ++j) Zs[(wave + 4 * j) * LDZ2 + slot0 + lane] = pre[j];
+    };
+    // the first product's operand fragments of step k are issued before the step's
+    // barriers and LDS stores; the second product's are read as it goes
+    double f1[32];
+    auto load_f1 = [&](int k) {
+        const double *F1 = F + (int64_t)k * kQ2Frag + wave * 2048;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) f1[q] = F1[q * 64 + lane];
+    };
+    gload(w00);
+    lstore(0);
+    gload(w00 + 64);
+    for (int k = 0; k < kc; ++k) {
+        const int64_t w0 = w00 + (int64_t)k * BW;
+        const int sb = (k & 1) * 64;
+        load_f1(k);
+        __syncthreads();  // the previous step's readers of the slots below are done
+        lstore((64 + sb) & 127);  // window rows 64 .. 127
+        if (k + 1 < kc) gload(w0 + 128);  // the next step's rows 64 .. 127
+        __syncthreads();
+        // W rows 16 wave .. +15 = V_k^T Zw (K = 128 window rows)
+        q2d4 acc1[NBC];
+#pragma unroll
+        for (int bc = 0; bc < NBC; ++bc) acc1[bc] = q2d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int slot = (4 * q + lq + sb) & 127;
+#pragma unroll
+            for (int bc = 0; bc < NBC; ++bc)
+                acc1[bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[q], Zs[(16 * bc + lr) * LDZ2 + slot], acc1[bc], 0, 0, 0);
+        }
+#pragma unroll
+        for (int bc = 0; bc < NBC; ++bc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Ws[(16 * wave + 4 * r + lq) * LDW + 16 * bc + lr] = acc1[bc][r];
+        __syncthreads();
+        // window rows 32 wave .. +31: Zw += Y_k W, as (Zw^T) += W^T Y_k^T so that a lane holds a row
+        q2d4 acc2[2][NBC];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bc = 0; bc < NBC; ++bc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc2[a][bc][r] = Zs[(16 * bc + 4 * r + lq) * LDZ2 + ((32 * wave + 16 * a + lr + sb) & 127)];
+        const double *F2 = F + (int64_t)k * kQ2Frag + 8192 + wave * 2048;
+#pragma unroll 8
+        for (int q = 0; q < 16; ++q) {
+            const double y0 = F2[q * 64 + lane], y1 = F2[(16 + q) * 64 + lane];
+#pragma unroll
+            for (int bc = 0; bc < NBC; ++bc) {
+                const double wv = Ws[(4 * q + lq) * LDW + 16 * bc + lr];
+                acc2[0][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y0, acc2[0][bc], 0, 0, 0);
+                acc2[1][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y1, acc2[1][bc], 0, 0, 0);
+            }
+        }
+        // rows 0 .. 63 are final for the block (waves 0, 1); rows 64 .. 127 (waves 2, 3) are
+        // the next window's rows 0 .. 63 and stay in their slots, or go out after the last k
+        const bool out = wave < 2 || k + 1 == kc;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bc = 0; bc < NBC; ++bc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rw = 32 * wave + 16 * a + lr, cl = 16 * bc + 4 * r + lq;
+                    if (out) {
+                        const int64_t g = w0 + rw, c = c0 + cl;
+                        if (g < n && c < ncol) Z[g + c * ldz] = acc2[a][bc][r];
+                    } else {
+                        Zs[cl * LDZ2 + ((rw + sb) & 127)] = acc2[a][bc][r];
+                    }
+                }
+    }
+}
+}  // namespace
+
+int apply_bulge_q(int64_t n, const double *v2, double *Z, int64_t ldz, int64_t ncol, hipStream_t stream) {
+    if (n < 3 || ncol <= 0) return TGBA_OK;
+    if (!v2 || !Z || ldz < n) return set_error(TGBA_EINVAL, "bulge back-transform: bad arguments");
+    const int64_t ks = bulge_v2_stride(n);
+    const int64_t nblk = (n - 2 + 63) / 64;  // blocks of 64 sweeps (sweeps 0 .. n - 3)
+    const int kc0 = (int)((n - 3) / BW) + 1;
+    void *wf = nullptr;
+    int rc = workspace_get((size_t)kc0 * kQ2Frag * sizeof(double), ws::BulgeQ, &wf);
+    if (rc) return rc;
+    double *F = (double *)wf;
+    const unsigned chunks = (unsigned)((ncol + kQ2Cols - 1) / kQ2Cols);
+    for (int64_t s = nblk - 1; s >= 0; --s) {
+        const int64_t i0 = s * 64;
+        const int kc = (int)((n - 3 - i0) / BW) + 1;
+        hipLaunchKernelGGL(q2_build_kernel, dim3(kc), dim3(256), 0, stream, v2, n, ks, i0, F);
+        hipLaunchKernelGGL(q2_apply_kernel, dim3(chunks), dim3(256), 0, stream, Z, ldz, n, ncol, i0, kc, F);
+    }
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }

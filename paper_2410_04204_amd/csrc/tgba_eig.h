@@ -37,8 +37,12 @@ struct BisIn {
 template <typename T>
 int sytrd_batched(std::vector<TriSecT<T>> &secs, hipStream_t stream);
 int stebz_batched(std::vector<BisIn> &in, hipStream_t stream);
+// Z <- Q Z, Q = H_0 ... H_{nref-1}: reflector c has its unit entry at row c + off and
+// the rest of its vector below it in column c of A (the one-stage reduction: off = 1,
+// nref = n - 1; the first stage of the two-stage reduction: off = 64, nref = n - 65).
 template <typename T>
-int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream);
+int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream,
+          int64_t off = 1, int64_t nref = -1);
 // Scratch elements (of T) of the back-transform of order n.
 size_t ormtr_scratch_elems(int64_t n);
 

@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -41,7 +43,6 @@ constexpr int64_t kMixedRefine = 200;  // pairs refined in FP64 by TGBA_EIG_MIXE
 constexpr int kG = 256;       // workgroups per active sector for row-parallel kernels
 // Launch shapes of the symmetric product the autotuner chooses from:
 // (minimum waves per SIMD, cap on the number of workgroups).
-constexpr int kSymvOcc[2] = {2, 3};
 constexpr int kSymvGrid[3] = {4096, 16384, 65536};  // caps on the total workgroup count
 constexpr int kSymvDefault = 1;  // occupancy 2, up to 16384 workgroups
 
@@ -521,16 +522,16 @@ __global__ void __launch_bounds__(256) gersh_kernel(const BisSec *secs, double *
 
 // ---- back-transform Z <- Q Z with Q = H_0 ... H_{n-2} ------------------------
 
-// V (m x nbp, ld m) of panel columns j0..j0+nbp-1: row r <-> global row j0+1+r,
-// explicit zeros above the unit diagonal entry of each reflector.
+// V (m x nbp, ld m) of the reflectors of columns j0..j0+nbp-1: row r <-> global
+// row j0+off+r, explicit zeros above the unit entry (row c + off) of each reflector.
 template <typename T>
-__global__ void extract_v_kernel(const T *A, int64_t lda, int64_t n, int64_t j0, int nbp, T *V) {
-    const int64_t m = n - j0 - 1;
+__global__ void extract_v_kernel(const T *A, int64_t lda, int64_t n, int64_t j0, int nbp, int64_t off, T *V) {
+    const int64_t m = n - j0 - off;
     const int64_t tot = m * nbp;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = k % m, t = k / m;
-        const int64_t R = j0 + 1 + r, c = j0 + t;
-        V[r + t * m] = (R < c + 1) ? T(0) : ((R == c + 1) ? T(1) : A[R + c * lda]);
+        const int64_t R = j0 + off + r, c = j0 + t;
+        V[r + t * m] = (R < c + off) ? T(0) : ((R == c + off) ? T(1) : A[R + c * lda]);
     }
 }
 
@@ -802,8 +803,11 @@ size_t ormtr_scratch_elems(int64_t n) {
 // product of depth kBT reads and writes Z once per 512 reflectors.  In FP64 the
 // two products with K = m split K over workgroups.
 template <typename T>
-int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream) {
-    if (n < 2) return TGBA_OK;
+int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T *scratch, hipStream_t stream,
+          int64_t off, int64_t nref) {
+    if (nref < 0) nref = n - off;
+    if (off < 1 || nref > n - off) return set_error(TGBA_EINVAL, "back-transform: bad reflector range");
+    if (nref < 1) return TGBA_OK;
     using G = typename GemmOf<T>::type;
     T *V = scratch;
     T *W1 = V + (size_t)n * kBT;
@@ -811,16 +815,15 @@ int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T
     T *Sg = W2 + (size_t)n * kBT;
     T *Tm = Sg + (size_t)kBT * kBT;
     T *Y = Tm + (size_t)kBT * kBT;
-    const int64_t nref = n - 1;
     const int64_t nblk = (nref + kBT - 1) / kBT;
     for (int64_t p = nblk - 1; p >= 0; --p) {
         const int64_t j0 = p * kBT;
         const int nb = (int)std::min<int64_t>(kBT, nref - j0);
         const int nbk = (nb + kNB - 1) / kNB;
-        const int64_t m = n - j0 - 1;
-        hipLaunchKernelGGL(extract_v_kernel<T>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nb, V);
+        const int64_t m = n - j0 - off;
+        hipLaunchKernelGGL(extract_v_kernel<T>, dim3(1024), dim3(256), 0, stream, A, lda, n, j0, nb, off, V);
         TGBA_HIP(hipGetLastError());
-        T *Zs = Z + (j0 + 1);
+        T *Zs = Z + (j0 + off);
         std::vector<G> g(1);
         int rc;
         double *parts = nullptr;
@@ -874,8 +877,10 @@ int ormtr(int64_t n, const T *A, int64_t lda, const T *tau, T *Z, int64_t ldz, T
 
 template int sytrd_batched<double>(std::vector<TriSecT<double>> &, hipStream_t);
 template int sytrd_batched<float>(std::vector<TriSecT<float>> &, hipStream_t);
-template int ormtr<double>(int64_t, const double *, int64_t, const double *, double *, int64_t, double *, hipStream_t);
-template int ormtr<float>(int64_t, const float *, int64_t, const float *, float *, int64_t, float *, hipStream_t);
+template int ormtr<double>(int64_t, const double *, int64_t, const double *, double *, int64_t, double *, hipStream_t,
+                           int64_t, int64_t);
+template int ormtr<float>(int64_t, const float *, int64_t, const float *, float *, int64_t, float *, hipStream_t, int64_t,
+                          int64_t);
 
 int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
     const int nsec = (int)in.size();
@@ -1054,14 +1059,115 @@ static int eig_mixed(int64_t n, double *A, int64_t lda, double *w, int64_t n_ref
     return TGBA_OK;
 }
 
+// TGBA_VEC_REDUCTION=onestage: tgba_eig_batched_vec takes the vector sectors through
+// the one-stage reduction on a second stream beside the two-stage eigenvalue
+// sectors (the earlier arrangement, kept for comparison).
+bool vec_onestage() {
+    const char *v = std::getenv("TGBA_VEC_REDUCTION");
+    return v && std::strcmp(v, "onestage") == 0;
+}
+
+// Eigen-decomposition of several sectors in one two-stage reduction: every
+// sector's tridiagonal comes from the same batched launches; the sectors without
+// vectors then take bisection on `stream`, and the sectors with vectors (whose
+// reduction kept its reflectors) take divide and conquer on the tridiagonal, the
+// bulge reflectors' back-transform and the first stage's back-transform,
+// A = Q1 Q2 T Q2^T Q1^T => Z = Q1 (Q2 Z_T), on a second stream when both kinds
+// are present, so that bisection and the vector work overlap.
+int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, const int *want,
+                  hipStream_t stream) {
+    size_t tot = 0, tv = 0;
+    for (int k = 0; k < nsec; ++k) {
+        if (n[k] < 0 || lda[k] < std::max<int64_t>(1, n[k]) || (n[k] > 0 && (!A[k] || !w[k])))
+            return set_error(TGBA_EINVAL, "bad eigensolver arguments");
+        tot += 2 * (size_t)n[k] + 8;
+        if (want[k]) tv += (size_t)n[k] + bulge_v2_doubles(n[k]) + 8;
+    }
+    void *ws = nullptr, *wv = nullptr;
+    int rc = workspace_get(tot * sizeof(double), ws::EigNovecWork, &ws);
+    if (rc) return rc;
+    if (tv && (rc = workspace_get(tv * sizeof(double), ws::EigVec2Stage, &wv))) return rc;
+    double *p = (double *)ws, *q = (double *)wv;
+    struct VecSec {
+        int k;
+        double *d, *e, *tau, *v2;
+    };
+    std::vector<BandIn> bin;
+    std::vector<BisIn> bis;
+    std::vector<VecSec> vs;
+    for (int k = 0; k < nsec; ++k) {
+        if (n[k] == 0) continue;
+        double *d = p, *e = p + n[k];
+        p += 2 * n[k] + 8;
+        BandIn b{A[k], lda[k], n[k], d, e};
+        if (want[k]) {
+            b.tau = q;
+            b.v2 = q + n[k];
+            q += (size_t)n[k] + bulge_v2_doubles(n[k]) + 8;
+            vs.push_back(VecSec{k, d, e, b.tau, b.v2});
+        } else {
+            bis.push_back(BisIn{d, e, w[k], n[k]});
+        }
+        bin.push_back(b);
+    }
+    if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
+    hipStream_t sv = stream;
+    hipEvent_t join = nullptr;
+    const bool fork = !vs.empty() && !bis.empty();
+    if (fork) {
+        if ((rc = side_stream(&sv))) return rc;
+        hipEvent_t ev = nullptr;
+        if (capturing()) {
+            if ((rc = capture_event(&ev)) || (rc = capture_event(&join))) return rc;
+        } else {
+            TGBA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            TGBA_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        }
+        TGBA_HIP(hipEventRecord(ev, stream));
+        TGBA_HIP(hipStreamWaitEvent(sv, ev, 0));
+        if (!capturing()) TGBA_HIP(hipEventDestroy(ev));
+    }
+    if (!bis.empty() && (rc = stebz_batched(bis, stream))) return rc;
+    for (const VecSec &V : vs) {
+        const int64_t nn = n[V.k];
+        void *zw = nullptr;
+        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + ormtr_scratch_elems(nn));
+        if ((rc = workspace_get(zbytes, ws::EigVecZ, &zw))) return rc;
+        double *Zt = (double *)zw;
+        double *scratch = Zt + (size_t)nn * nn;
+        if ((rc = stedc(nn, V.d, V.e, Zt, nn, sv))) return rc;
+        if ((rc = apply_bulge_q(nn, V.v2, Zt, nn, nn, sv))) return rc;
+        if (nn - kBandWidth - 1 > 0 &&
+            (rc = ormtr(nn, (const double *)A[V.k], lda[V.k], (const double *)V.tau, Zt, nn, scratch, sv,
+                        (int64_t)kBandWidth, nn - kBandWidth - 1)))
+            return rc;
+        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(4096), dim3(256), 0, sv, Zt, nn, A[V.k], lda[V.k], nn, nn);
+        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(64), dim3(256), 0, sv, (const double *)V.d, nn, w[V.k], nn,
+                           nn, (int64_t)1);
+        TGBA_HIP(hipGetLastError());
+    }
+    if (fork) {
+        TGBA_HIP(hipEventRecord(join, sv));
+        TGBA_HIP(hipStreamWaitEvent(stream, join, 0));
+        if (!capturing()) TGBA_HIP(hipEventDestroy(join));
+    }
+    if (capturing()) return TGBA_OK;
+    TGBA_HIP(hipStreamSynchronize(stream));
+    return band_check(stream);
+}
+
 // Eigen-decomposition of several sectors: eigenvalues only by the two-stage
 // reduction and bisection, with vectors by the one-stage reduction, divide and
-// conquer and the back-transform.  The two paths use disjoint workspace slots
+// conquer and the back-transform (or, with TGBA_EIG_TWOSTAGE, eig_two_stage).  The two paths use disjoint workspace slots
 // (the eigenvalue path: BisectSecs, Band*, EigNovecWork), so they may run at the
 // same time on two streams from two host threads (tgba_eig_batched_vec).
 int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, int flags,
                 hipStream_t stream) {
     const bool novec = (flags & TGBA_EIG_NOVEC) != 0;
+    if (!novec && (flags & TGBA_EIG_TWOSTAGE) && !(flags & TGBA_EIG_MIXED)) {
+        std::vector<int> want(nsec, 1);
+        return eig_two_stage(nsec, n, A, lda, w, want.data(), stream);
+    }
     if (novec && !(flags & (TGBA_EIG_ONESTAGE | TGBA_EIG_MIXED))) {
         size_t tot = 0;
         for (int k = 0; k < nsec; ++k) {
@@ -1156,7 +1262,8 @@ int eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t *lda
 
 extern "C" int tgba_eig(int64_t n, double *A, int64_t lda, double *w, int flags, void *stream) {
     clear_error();
-    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC | TGBA_EIG_ONESTAGE)) return set_error(TGBA_EINVAL, "unknown flags");
+    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC | TGBA_EIG_ONESTAGE | TGBA_EIG_TWOSTAGE))
+        return set_error(TGBA_EINVAL, "unknown flags");
     double *As[1] = {A};
     double *ws[1] = {w};
     return eig_batched(1, &n, As, &lda, ws, flags, (hipStream_t)stream);
@@ -1184,6 +1291,7 @@ extern "C" int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A
         }
     }
     hipStream_t st = (hipStream_t)stream;
+    if (!tgba::vec_onestage()) return tgba::eig_two_stage(nsec, n, A, lda, w, want_vectors, st);
     if (nv.empty() || nn.empty()) {
         if (!nv.empty()) return tgba::eig_batched((int)nv.size(), nv.data(), av.data(), lv.data(), wv.data(), 0, st);
         return tgba::eig_batched((int)nn.size(), nn.data(), an.data(), ln.data(), wn.data(), TGBA_EIG_NOVEC, st);
@@ -1236,6 +1344,7 @@ extern "C" int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, co
                                 int flags, void *stream) {
     clear_error();
     if (nsec < 0 || (nsec > 0 && (!n || !A || !lda || !w))) return set_error(TGBA_EINVAL, "bad arguments");
-    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC | TGBA_EIG_ONESTAGE)) return set_error(TGBA_EINVAL, "unknown flags");
+    if (flags & ~(TGBA_EIG_MIXED | TGBA_EIG_NOVEC | TGBA_EIG_ONESTAGE | TGBA_EIG_TWOSTAGE))
+        return set_error(TGBA_EINVAL, "unknown flags");
     return eig_batched(nsec, n, A, lda, w, flags, (hipStream_t)stream);
 }

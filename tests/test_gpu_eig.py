@@ -197,9 +197,9 @@ def test_masked_split_k_symmetric_product():
 
 
 def test_eig_batched_vec_concurrent_groups():
-    """Sectors with and without eigenvectors in one call (two streams, two host
-    threads): eigenvalues against LAPACK, and A Z = Z diag(w), Z^T Z = 1 for the
-    vector sectors."""
+    """Sectors with and without eigenvectors in one call (one two-stage reduction;
+    bisection and the vector sectors' back-transforms on two streams): eigenvalues
+    against LAPACK, and A Z = Z diag(w), Z^T Z = 1 for the vector sectors."""
     import paper_2410_04204_amd as tg
     torch = _t()
     sizes = [1500, 700, 2049, 65, 900, 3]
@@ -321,6 +321,53 @@ def test_eig_with_vectors_random(n):
     assert np.abs(wn - ref).max() <= 1e-12 * nrm * np.sqrt(n)
     assert np.abs(A @ Z - Z * wn).max() <= 1e-12 * nrm * np.sqrt(n)
     assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-12 * np.sqrt(n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 64, 65, 66, 67, 130, 200, 1000, 2049, 3001])
+def test_eig_two_stage_with_vectors_random(n):
+    """TGBA_EIG_TWOSTAGE: the band reduction and the bulge chasing keep their
+    reflectors; divide and conquer on the tridiagonal, then Z = Q1 (Q2 Z_T) (the
+    bulge reflectors in blocks of 64 sweeps, the panel reflectors in blocks of 512).
+    Orders around the band width, several blocks of sweeps with a ragged last one."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    A = _rand_sym(n, 7 * n + 1)
+    dA = _cm(A)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg.eig(dA, w, tg.TGBA_EIG_TWOSTAGE)
+    torch.cuda.synchronize()
+    Z = _np(dA)
+    wn = w.cpu().numpy()
+    ref = scipy.linalg.eigvalsh(A)
+    nrm = max(1.0, np.abs(ref).max())
+    print(f"n={n} eig {np.abs(wn - ref).max():.2e} residual {np.abs(A @ Z - Z * wn).max():.2e} "
+          f"orth {np.abs(Z.T @ Z - np.eye(n)).max():.2e}", flush=True)
+    assert np.abs(wn - ref).max() <= 1e-12 * nrm * np.sqrt(n)
+    assert np.abs(A @ Z - Z * wn).max() <= 1e-12 * nrm * np.sqrt(n)
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-12 * np.sqrt(n)
+
+
+def test_eig_batched_vec_one_stage_switch(monkeypatch):
+    """TGBA_VEC_REDUCTION=onestage: the vector sectors through the one-stage reduction
+    on a second stream beside the two-stage eigenvalue sectors."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    monkeypatch.setenv("TGBA_VEC_REDUCTION", "onestage")
+    sizes = [900, 400, 1300, 3]
+    want = [True, False, False, True]
+    As = [_rand_sym(n, 500 + n) for n in sizes]
+    mats = [_cm(A) for A in As]
+    ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+    tg.eig_batched_vec(mats, ws, want)
+    for A, M, w, v in zip(As, mats, ws, want):
+        ref = scipy.linalg.eigvalsh(A)
+        n = A.shape[0]
+        wn = w.cpu().numpy()
+        assert np.abs(np.sort(wn) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()) * np.sqrt(n)
+        if v:
+            Z = _np(M)
+            assert np.abs(A @ Z - Z * wn[None, :]).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+            assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-10
 
 
 def test_eig_with_vectors_heff_n24_k0():
