@@ -7,20 +7,23 @@ K <-> N-K), FP64 throughout.  One step = one pass of the device hot path over
 that input, with the basis (host enumeration + contraction table) resident:
   1. H_eff of all 40 sectors in one launch (real gauge, column-major, FP64,
      lower triangle: the part the eigensolver reads);
-  2. eigen-decomposition of every sector (eigenvalues; eigenvectors of K = 0);
+  2. eigen-decomposition of every sector: one batched two-stage reduction of all
+     40 sectors, eigenvalues of K != 0 by bisection, the K = 0 eigenvectors by
+     divide and conquer and the bulge and panel back-transforms (on a second
+     stream beside the bisection);
   3. gamma_1 matrix of K = 0 and the dynamic structure factor S(0, omega) on
      4096 frequencies;
   4. quench from the K = 0 ground state of H0: <sigma^x>(t) on 1001 times
      (t = 0 .. 50, dt = 0.05).
 
 Prints ONE JSON line.  `value` = H_eff elements (sum_K chi_NS chi_R) per second
-of the whole step.  `roofline` is that of the step's dominant kernel family:
-the FP64 matrix-core products (the two-stage band reduction of the
-eigenvalue-only sectors, the K = 0 reduction, back-transform and divide and
-conquer; MFMA bound), or the one-stage reduction's symmetric matrix-vector
-product (HBM bound) if it takes the larger share.  Algorithmic flops or bytes
-and launch durations come from the library's own HIP-event timing of every
-launch in the timed steps; the other family is reported as `roofline_other`.
+of the whole step.  `roofline` is that of the step's dominant kernel family,
+the FP64 matrix-core products (the two-stage band reduction, the K = 0 panel
+back-transform and divide and conquer; MFMA bound), unless the bulge
+back-transform of K = 0 (MFMA) takes the larger share.  Algorithmic flops or
+bytes and launch durations come from the library's own HIP-event timing of every
+launch in the timed steps; the other family is reported as `roofline_other`, the
+bulge chasing as `roofline_bulge_chasing`.
 Per-stage times, the assembly kernel's roofline and the oracle's CPU baseline
 are reported beside it, and,
 after the timed steps: the power spectrum of the K = 0 quench to t = 480; the
@@ -76,7 +79,7 @@ def parse():
                    help="skip the equal-time correlator study (N=60, chi=2000, the two quenches of the "
                         "appendix's correlator figure, j = 1..30, t <= 20)")
     p.add_argument("--no-isolated", action="store_true",
-                   help="skip the extra step with the two eigensolve groups serialised (per-kernel rates "
+                   help="skip the extra step with the K = 0 vector work serialised after the bisection (per-kernel rates "
                         "without the other stream's kernels beside them)")
     p.add_argument("--no-plan", action="store_true",
                    help="skip recording the step into one hipGraph plan and timing its replays")
@@ -84,7 +87,7 @@ def parse():
     p.add_argument("--profile-assembly", action="store_true",
                    help="only run the all-sector assembly (warm-up + timed launches) and exit (counter passes)")
     p.add_argument("--profile-serial", action="store_true",
-                   help="only run warm-up + timed steps with the two eigensolve groups serialised on one "
+                   help="only run warm-up + timed steps with the K = 0 vector work serialised on one "
                         "stream from one thread, print a marker line and exit (rocprofv3 counter passes)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (5 times), the reference for "
@@ -634,12 +637,16 @@ def main():
         tg.assemble_heff_batched(B, Ks, Hs, tg.TGBA_HEFF | tg.TGBA_LOWER, stream=st)
         mark(1)
         if serial:
-            # the same two groups one after the other on one stream (kernel-quality view)
-            tg.eig_batched(Hs[1:], ws[1:], tg.TGBA_EIG_NOVEC, stream=st)
-            tg.eig_batched(Hs[:1], ws[:1], tg.TGBA_EIG_FP64, stream=st)
+            # the same call with the K = 0 vector work after the bisection on one stream
+            # (kernel-quality view: every kernel alone on the device)
+            os.environ["TGBA_VEC_SIDE_STREAM"] = "0"
+            try:
+                tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))], stream=st)
+            finally:
+                del os.environ["TGBA_VEC_SIDE_STREAM"]
         else:
-            # spectra of the K != 0 sectors (two-stage) and the eigenpairs of K = 0 (one-stage,
-            # with vectors) in one call: the two groups run concurrently on two streams
+            # one two-stage reduction of all sectors; the spectra of K != 0 by bisection and
+            # the eigenpairs of K = 0 (divide and conquer, back-transforms) on two streams
             tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))], stream=st)
         mark(2)
         tg.assemble_heff(B, 0, G0, tg.TGBA_GAMMA1, stream=st)
@@ -659,8 +666,8 @@ def main():
                           "lower_triangle_bytes": int(sum(x * (x + 1) // 2 for x in n)) * 8}), flush=True)
         return
     if a.profile_serial:
-        # profiling run: warm-up and timed steps with the two eigensolve groups one after
-        # the other, every launch issued from this thread (for rocprofv3 counter passes)
+        # profiling run: warm-up and timed steps with the K = 0 vector work after the bisection
+        # on one stream, every launch issued from this thread (for rocprofv3 counter passes)
         for i in range(a.warmup + a.steps):
             step(serial=True)
             torch.cuda.synchronize()
@@ -673,7 +680,7 @@ def main():
         torch.cuda.synchronize()
         print(f"warmup step {i} done", file=sys.stderr, flush=True)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(a.steps)]
-    for ch in (0, 1, 3):  # discard launches of the warmup steps
+    for ch in (0, 1, 3, 4):  # discard launches of the warmup steps
         tg.timing_read(ch)
     tg.timing_enable(True)
     torch.cuda.synchronize()
@@ -687,12 +694,13 @@ def main():
     symv_ms, symv_launches, symv_bytes_total = tg.timing_read(0)
     gemm_ms, gemm_launches, gemm_flops_total = tg.timing_read(1)
     bulge_ms, bulge_calls, bulge_bytes_total = tg.timing_read(3)
+    q2_ms, q2_calls, q2_flops_total = tg.timing_read(4)
     stage_ms = {st: float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k, st in enumerate(stages)}
     asm_ms = stage_ms["assemble"]
     ms_per_step = wall * 1000.0 / a.steps
     bytes_per_launch = float(sum(x * (x + 1) // 2 for x in n)) * 8.0  # lower triangle incl. diagonal
     achieved = bytes_per_launch / (asm_ms * 1e-3) / 1e9
-    # dominant kernel: the reduction's symmetric product (one launch per column)
+    # the one-stage reduction's symmetric product (only with TGBA_VEC_REDUCTION=onestage)
     symv_avg_ms = symv_ms / max(symv_launches, 1)
     symv_avg_bytes = symv_bytes_total / max(symv_launches, 1)
     symv_gbs = symv_avg_bytes / (symv_avg_ms * 1e-3) / 1e9 if symv_ms > 0 else 0.0
@@ -705,8 +713,8 @@ def main():
                  "traffic": tr_symv["bytes_per_launch"] if tr_symv else None, "traffic_source": tr_symv,
                  "algorithmic_bytes_per_launch": symv_avg_bytes, "avg_launch_ms": symv_avg_ms,
                  "launches": symv_launches, "share_of_step": symv_ms / a.steps / ms_per_step}
-    roof_gemm = {"kernel": "dgemm_kernel (FP64 MFMA products: two-stage band reduction, one-stage K=0 "
-                           "reduction, back-transform, divide and conquer)",
+    roof_gemm = {"kernel": "dgemm_kernel (FP64 MFMA products: two-stage band reduction of all sectors, "
+                           "K=0 panel back-transform, divide and conquer)",
                  "bound": "mfma", "achieved": gemm_tfs, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                  "frac": gemm_tfs / FP64_MFMA_PEAK_TFS,
                  "traffic": tr_gemm["bytes_per_launch"] if tr_gemm else None, "traffic_source": tr_gemm,
@@ -718,11 +726,20 @@ def main():
                   "algorithmic_bytes_per_call": bulge_bytes_total / max(bulge_calls, 1),
                   "avg_call_ms": bulge_ms / max(bulge_calls, 1), "calls": bulge_calls,
                   "share_of_step": bulge_ms / a.steps / ms_per_step}
-    dominant, other = (roof_gemm, roof_symv) if roof_gemm["share_of_step"] >= roof_symv["share_of_step"] \
-        else (roof_symv, roof_gemm)
-    # One more (untimed for the metric) step with the two eigensolve groups serialised: inside the
-    # timed steps the two streams share the chip, so the per-launch durations above include the
-    # other group's kernels running beside them.  This pass shows each kernel on its own.
+    q2_tfs = q2_flops_total / (q2_ms * 1e-3) / 1e12 if q2_ms > 0 else 0.0
+    roof_q2 = {"kernel": "q2_build_kernel + q2_apply_kernel (K=0 bulge back-transform, one record per call)",
+               "bound": "mfma", "achieved": q2_tfs, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+               "frac": q2_tfs / FP64_MFMA_PEAK_TFS, "traffic": None,
+               "algorithmic_flops_per_call": q2_flops_total / max(q2_calls, 1),
+               "avg_call_ms": q2_ms / max(q2_calls, 1), "calls": q2_calls,
+               "share_of_step": q2_ms / a.steps / ms_per_step}
+    fams = sorted([r for r in (roof_gemm, roof_q2, roof_symv) if r["share_of_step"] > 0],
+                  key=lambda r: -r["share_of_step"])
+    dominant, other = fams[0], (fams[1] if len(fams) > 1 else None)
+    # One more (untimed for the metric) step with the K = 0 vector work serialised after the
+    # bisection: inside the timed steps the two streams share the chip, so the per-launch
+    # durations above include the other stream's kernels running beside them.  This pass shows
+    # each kernel on its own.
     isolated = {}
     if not a.no_isolated:
         tg.timing_enable(True)
@@ -734,6 +751,7 @@ def main():
         i_sm, i_sl, i_sb = tg.timing_read(0)
         i_gm, i_gl, i_gf = tg.timing_read(1)
         i_bm, i_bl, i_bb = tg.timing_read(3)
+        i_qm, i_ql, i_qf = tg.timing_read(4)
         i_eig = ev_iso[1].elapsed_time(ev_iso[2])
         isolated = {
             "eig_ms": i_eig,
@@ -744,10 +762,14 @@ def main():
             "bulge_chasing": {"achieved": i_bb / (i_bm * 1e-3) / 1e9 if i_bm > 0 else 0.0, "unit": "GB/s",
                               "peak": HBM_PEAK_GBS, "ms": i_bm, "calls": i_bl,
                               "frac": (i_bb / (i_bm * 1e-3) / 1e9 if i_bm > 0 else 0.0) / HBM_PEAK_GBS},
-            "tri_symv": {"achieved": i_sb / (i_sm * 1e-3) / 1e9 if i_sm > 0 else 0.0, "unit": "GB/s",
-                         "peak": HBM_PEAK_GBS, "avg_launch_ms": i_sm / max(i_sl, 1), "launches": i_sl,
-                         "frac": (i_sb / (i_sm * 1e-3) / 1e9 if i_sm > 0 else 0.0) / HBM_PEAK_GBS},
+            "bulge_backtransform": {"achieved": i_qf / (i_qm * 1e-3) / 1e12 if i_qm > 0 else 0.0,
+                                    "unit": "TFLOP/s", "peak": FP64_MFMA_PEAK_TFS, "ms": i_qm, "calls": i_ql,
+                                    "frac": (i_qf / (i_qm * 1e-3) / 1e12 if i_qm > 0 else 0.0) / FP64_MFMA_PEAK_TFS},
         }
+        if i_sl > 0:
+            isolated["tri_symv"] = {"achieved": i_sb / (i_sm * 1e-3) / 1e9, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                                    "avg_launch_ms": i_sm / i_sl, "launches": i_sl,
+                                    "frac": i_sb / (i_sm * 1e-3) / 1e9 / HBM_PEAK_GBS}
     stats = B.stats()
     sxn = sx.cpu().numpy()
     wn0 = ws[0].cpu().numpy()

@@ -356,7 +356,9 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
  * joined back into `stream`.  With the environment variable
  * TGBA_VEC_REDUCTION=onestage the vector sectors instead take the one-stage
  * reduction (tgba_eig) on the second stream from a second host thread, beside
- * the eigenvalue-only sectors' two-stage path.  Returns when all are done.
+ * the eigenvalue-only sectors' two-stage path.  With TGBA_VEC_SIDE_STREAM=0
+ * the vector sectors' work runs on `stream` after the bisection (one kernel at a
+ * time on the device: per-kernel rates).  Returns when all are done.
  * Errors: as tgba_eig_batched.
  */
 int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,
@@ -633,6 +635,9 @@ int tgba_timing_read(double *ms, int64_t *launches, double *bytes);
  * bytes: per task the lower triangle of the 64 x 64 diagonal block read and
  * written, the block below it read and the bulge block written (the bulge
  * block being the previous task's lower block, carried in registers).
+ * Channel 4 is the bulge reflectors' back-transform of TGBA_EIG_TWOSTAGE (one
+ * record per call), units = algorithmic flops: 4 l ncol per reflector of
+ * length l applied to ncol columns.
  * Reading a channel consumes only that channel's records.
  */
 int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units);

@@ -423,7 +423,8 @@ def timing_read(channel=0):
     """(kernel ms, launches, algorithmic units) of one channel since its previous read:
     channel 0 the symmetric product (bytes), channel 1 the FP64 products (flops), channel 2
     the rows kernel of assemble_corr (bytes written), channel 3 the bulge chasing of the
-    two-stage reduction (algorithmic bytes, one record per call)."""
+    two-stage reduction (algorithmic bytes, one record per call), channel 4 the bulge
+    reflectors' back-transform (algorithmic flops, one record per call)."""
     ms, n, un = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
     _lib.check(_lib.load().tgba_timing_read_channel(int(channel), ctypes.byref(ms), ctypes.byref(n),
                                                     ctypes.byref(un)))

@@ -1142,7 +1142,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
 // down by j rows (compact WY form, T_k upper triangular).  Z <- Q2 Z applies the
 // blocks last first and, within a block, G_0 first.  Per block: q2_build_kernel
 // forms V_k and Y_k = -V_k T_k of every k; q2_apply_kernel gives each workgroup
-// 48 columns of Z and slides a 128-row window down the rows, BW rows per k:
+// 32 columns of Z and slides a 128-row window down the rows, BW rows per k:
 // W = V_k^T Zw and Zw += Y_k W on the FP64 matrix cores, then the top BW rows
 // are final for the block and go to memory while the rest stay in LDS.
 
@@ -1153,7 +1153,7 @@ namespace {
 typedef double q2d4 __attribute__((ext_vector_type(4)));
 constexpr int kQ2Frag = 16384;  // doubles of one G_k's operand fragments (V_k 8192, Y_k 8192)
 constexpr int LDZ2 = 129;       // LDS column stride of the window (odd: 16 lanes on 16 rows hit distinct banks)
-constexpr int kQ2Cols = 48;     // columns of Z per workgroup of q2_apply_kernel
+constexpr int kQ2Cols = 32;     // columns of Z per workgroup of q2_apply_kernel
 
 // One workgroup per k of the block at sweep i0.  Writes the matrix-core operand
 // fragments of G_k in the order q2_apply_kernel's lanes read them:
@@ -1220,10 +1220,11 @@ __global__ void __launch_bounds__(256) q2_build_kernel(const double *__restrict_
 
 // One workgroup of 4 waves per kQ2Cols columns of Z (n rows, ncol columns, ld
 // ldz), kc windows of the block at sweep i0.  Window row r of step k is global
-// row i0 + 1 + k BW + r and lives in LDS slot (r + 64 (k & 1)) & 127.  76 KB of
-// LDS and at most 256 registers: two workgroups per compute unit, so a launch
-// for n <= 24576 (512 workgroups) runs in one round.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q2_apply_kernel(double *__restrict__ Z, int64_t ldz, int64_t n, int64_t ncol,
+// row i0 + 1 + k BW + r and lives in LDS slot (r + 64 (k & 1)) & 127.  51 KB of
+// LDS and at most 168 registers: three workgroups per compute unit, so a launch
+// for n <= 24576 (768 workgroups) runs in one round; it then takes kc steps of one
+// workgroup's chain, whatever the number of chunks.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) q2_apply_kernel(double *__restrict__ Z, int64_t ldz, int64_t n, int64_t ncol,
                                                        int64_t i0, int kc, const double *__restrict__ F) {
     constexpr int CW = kQ2Cols, NBC = CW / 16, LDW = CW + 4;
     __shared__ double Zs[CW * LDZ2];  // column c of the chunk at Zs + c LDZ2
@@ -1245,13 +1246,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q
 #pragma unroll
         for (int j = 0; j < CW / 4; ++j) Zs[(wave + 4 * j) * LDZ2 + slot0 + lane] = pre[j];
     };
-    // the first product's operand fragments of step k are issued before the step's
-    // barriers and LDS stores; the second product's are read as it goes
-    double f1[32];
+    // V_k and Y_k are banded: column j of V_k is zero outside window rows j .. j + 63, and
+    // Y_k(r, c) = 0 for c < r - 63.  The first product of wave w (sweeps 16 w .. 16 w + 15)
+    // takes window rows 16 w .. 16 w + 79 only (K-steps q = 4 w .. 4 w + 19); the second
+    // skips the K-steps below 4 ra - 16 for its row block ra.
+    const int q1 = 4 * wave;
+    const int qa0 = 8 * wave - 16 > 0 ? 8 * wave - 16 : 0, qa1 = 8 * wave - 12 > 0 ? 8 * wave - 12 : 0;
+    // The first product's fragments are requested at the start of a step; the
+    // second's are read as it goes.
+    double f1[20];
     auto load_f1 = [&](int k) {
         const double *F1 = F + (int64_t)k * kQ2Frag + wave * 2048;
 #pragma unroll
-        for (int q = 0; q < 32; ++q) f1[q] = F1[q * 64 + lane];
+        for (int t = 0; t < 20; ++t) f1[t] = F1[(q1 + t) * 64 + lane];
     };
     gload(w00);
     lstore(0);
@@ -1269,11 +1276,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q
 #pragma unroll
         for (int bc = 0; bc < NBC; ++bc) acc1[bc] = q2d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            const int slot = (4 * q + lq + sb) & 127;
+        for (int t = 0; t < 20; ++t) {
+            const int slot = (4 * (q1 + t) + lq + sb) & 127;
 #pragma unroll
             for (int bc = 0; bc < NBC; ++bc)
-                acc1[bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[q], Zs[(16 * bc + lr) * LDZ2 + slot], acc1[bc], 0, 0, 0);
+                acc1[bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[t], Zs[(16 * bc + lr) * LDZ2 + slot], acc1[bc], 0, 0, 0);
         }
 #pragma unroll
         for (int bc = 0; bc < NBC; ++bc)
@@ -1292,12 +1299,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q
         const double *F2 = F + (int64_t)k * kQ2Frag + 8192 + wave * 2048;
 #pragma unroll 8
         for (int q = 0; q < 16; ++q) {
-            const double y0 = F2[q * 64 + lane], y1 = F2[(16 + q) * 64 + lane];
+            if (q < qa0) continue;  // uniform over the wave
+            const bool b1 = q >= qa1;
+            const double y0 = F2[q * 64 + lane], y1 = b1 ? F2[(16 + q) * 64 + lane] : 0.0;
 #pragma unroll
             for (int bc = 0; bc < NBC; ++bc) {
                 const double wv = Ws[(4 * q + lq) * LDW + 16 * bc + lr];
                 acc2[0][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y0, acc2[0][bc], 0, 0, 0);
-                acc2[1][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y1, acc2[1][bc], 0, 0, 0);
+                if (b1) acc2[1][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y1, acc2[1][bc], 0, 0, 0);
             }
         }
         // rows 0 .. 63 are final for the block (waves 0, 1); rows 64 .. 127 (waves 2, 3) are
@@ -1332,6 +1341,12 @@ int apply_bulge_q(int64_t n, const double *v2, double *Z, int64_t ldz, int64_t n
     if (rc) return rc;
     double *F = (double *)wf;
     const unsigned chunks = (unsigned)((ncol + kQ2Cols - 1) / kQ2Cols);
+    hipEvent_t ta = nullptr, tb = nullptr;
+    const bool timed = timing_on();
+    if (timed) {
+        if ((rc = timing_events(&ta, &tb))) return rc;
+        TGBA_HIP(hipEventRecord(ta, stream));
+    }
     for (int64_t s = nblk - 1; s >= 0; --s) {
         const int64_t i0 = s * 64;
         const int kc = (int)((n - 3 - i0) / BW) + 1;
@@ -1339,6 +1354,14 @@ int apply_bulge_q(int64_t n, const double *v2, double *Z, int64_t ldz, int64_t n
         hipLaunchKernelGGL(q2_apply_kernel, dim3(chunks), dim3(256), 0, stream, Z, ldz, n, ncol, i0, kc, F);
     }
     TGBA_HIP(hipGetLastError());
+    if (timed) {
+        // algorithmic flops: 4 l ncol per reflector of length l (its dot products and update)
+        double refl_len = 0.0;
+        for (int64_t i = 0; i + 3 <= n; ++i)
+            for (int64_t k = 0; k <= (n - 3 - i) / BW; ++k) refl_len += (double)std::min<int64_t>(BW, n - (i + 1 + k * BW));
+        TGBA_HIP(hipEventRecord(tb, stream));
+        if ((rc = timing_push(ta, tb, 4.0 * refl_len * (double)ncol, 4))) return rc;
+    }
     return TGBA_OK;
 }
 

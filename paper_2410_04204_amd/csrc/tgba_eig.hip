@@ -1066,6 +1066,12 @@ bool vec_onestage() {
     const char *v = std::getenv("TGBA_VEC_REDUCTION");
     return v && std::strcmp(v, "onestage") == 0;
 }
+// TGBA_VEC_SIDE_STREAM=0: the vector sectors' work after bisection on the caller's
+// stream (every kernel of the call alone on the device; for per-kernel rates).
+bool vec_side_stream() {
+    const char *v = std::getenv("TGBA_VEC_SIDE_STREAM");
+    return !(v && std::strcmp(v, "0") == 0);
+}
 
 // Eigen-decomposition of several sectors in one two-stage reduction: every
 // sector's tridiagonal comes from the same batched launches; the sectors without
@@ -1113,7 +1119,7 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
     if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
     hipStream_t sv = stream;
     hipEvent_t join = nullptr;
-    const bool fork = !vs.empty() && !bis.empty();
+    const bool fork = !vs.empty() && !bis.empty() && vec_side_stream();
     if (fork) {
         if ((rc = side_stream(&sv))) return rc;
         hipEvent_t ev = nullptr;

@@ -204,7 +204,7 @@ int side_stream(hipStream_t *out) {
 namespace {
 struct Timed {
     hipEvent_t a, b;
-    double units;  // bytes (channels 0, 2, 3) or flops (channel 1)
+    double units;  // bytes (channels 0, 2, 3) or flops (channels 1, 4)
     int ch;
 };
 std::mutex g_tmu;
@@ -348,7 +348,7 @@ extern "C" int tgba_timing_enable(int on) {
 extern "C" int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units) {
     tgba::clear_error();
     if (!ms || !launches || !units) return tgba::set_error(TGBA_EINVAL, "NULL output");
-    if (channel < 0 || channel > 3) return tgba::set_error(TGBA_EINVAL, "unknown timing channel");
+    if (channel < 0 || channel > 4) return tgba::set_error(TGBA_EINVAL, "unknown timing channel");
     std::lock_guard<std::mutex> lk(tgba::g_tmu);
     double tot = 0.0, un = 0.0;
     int64_t cnt = 0;
