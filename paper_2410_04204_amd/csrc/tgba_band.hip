@@ -1142,7 +1142,7 @@ int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
 // down by j rows (compact WY form, T_k upper triangular).  Z <- Q2 Z applies the
 // blocks last first and, within a block, G_0 first.  Per block: q2_build_kernel
 // forms V_k and Y_k = -V_k T_k of every k; q2_apply_kernel gives each workgroup
-// 32 columns of Z and slides a 128-row window down the rows, BW rows per k:
+// 48 columns of Z and slides a 128-row window down the rows, BW rows per k:
 // W = V_k^T Zw and Zw += Y_k W on the FP64 matrix cores, then the top BW rows
 // are final for the block and go to memory while the rest stay in LDS.
 
@@ -1153,7 +1153,7 @@ namespace {
 typedef double q2d4 __attribute__((ext_vector_type(4)));
 constexpr int kQ2Frag = 16384;  // doubles of one G_k's operand fragments (V_k 8192, Y_k 8192)
 constexpr int LDZ2 = 129;       // LDS column stride of the window (odd: 16 lanes on 16 rows hit distinct banks)
-constexpr int kQ2Cols = 32;     // columns of Z per workgroup of q2_apply_kernel
+constexpr int kQ2Cols = 48;     // columns of Z per workgroup of q2_apply_kernel
 
 // One workgroup per k of the block at sweep i0.  Writes the matrix-core operand
 // fragments of G_k in the order q2_apply_kernel's lanes read them:
@@ -1218,29 +1218,57 @@ __global__ void __launch_bounds__(256) q2_build_kernel(const double *__restrict_
     }
 }
 
+// Raw buffer access for the bulge back-transform: loads past the extent return
+// 0 and stores past it are dropped, so masked lanes take offset 2^31 (every
+// extent here is below 2^31 bytes).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t q2_rsrc(const double *base, int64_t bytes) {
+    const uint64_t b = (uint64_t)base;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(lo | (hi << 32)), (short)0,
+                                             __builtin_amdgcn_readfirstlane((int)(uint32_t)bytes), 0x00020000);
+}
+__device__ __forceinline__ double q2_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void q2_st(__amdgpu_buffer_rsrc_t r, double v, uint32_t voff) {
+    using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, voff, 0u, 0);
+}
+constexpr uint32_t kQ2Off = 0x80000000u;  // offset of a masked access
+
 // One workgroup of 4 waves per kQ2Cols columns of Z (n rows, ncol columns, ld
 // ldz), kc windows of the block at sweep i0.  Window row r of step k is global
-// row i0 + 1 + k BW + r and lives in LDS slot (r + 64 (k & 1)) & 127.  51 KB of
-// LDS and at most 168 registers: three workgroups per compute unit, so a launch
-// for n <= 24576 (768 workgroups) runs in one round; it then takes kc steps of one
-// workgroup's chain, whatever the number of chunks.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) q2_apply_kernel(double *__restrict__ Z, int64_t ldz, int64_t n, int64_t ncol,
+// row i0 + 1 + k BW + r and lives in LDS slot (r + 64 (k & 1)) & 127.  76 KB of
+// LDS and at most 256 registers: two workgroups per compute unit, so a launch
+// for n <= 24576 (512 workgroups) runs in one round; it then takes kc steps of one
+// workgroup's chain.  (80 columns at one workgroup per unit measured no faster:
+// a step then waits on LDS and barrier latency with one wave per SIMD.)  The global loads of a step
+// are requested in the order the step waits for them (the memory counter is in
+// order): both products' fragments at the start of the step, then the next
+// step's rows of Z, which have a whole step to arrive.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q2_apply_kernel(double *__restrict__ Z, int64_t ldz, int64_t n, int64_t ncol,
                                                        int64_t i0, int kc, const double *__restrict__ F) {
     constexpr int CW = kQ2Cols, NBC = CW / 16, LDW = CW + 4;
     __shared__ double Zs[CW * LDZ2];  // column c of the chunk at Zs + c LDZ2
     __shared__ double Ws[64 * LDW];   // W = V_k^T Zw, row-major
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
-    const int64_t c0 = (int64_t)blockIdx.x * CW, w00 = i0 + 1;
+    const int64_t c0 = (int64_t)blockIdx.x * CW;
+    const int w00 = (int)i0 + 1;
+    const int ccount = (int)(ncol - c0 < CW ? ncol - c0 : CW);
+    const auto rz = q2_rsrc(Z + c0 * ldz, ((int64_t)(ccount - 1) * ldz + n) * (int64_t)sizeof(double));
+    const auto rf = q2_rsrc(F, (int64_t)kc * kQ2Frag * (int64_t)sizeof(double));
+    const uint32_t lz = (uint32_t)(ldz * (int64_t)sizeof(double));
+    const int n32 = (int)n;
+    auto zoff = [&](int g, int c) -> uint32_t {  // entry (g, c0 + c) of Z, or masked
+        return (g < n32 && c < ccount) ? (uint32_t)g * 8u + (uint32_t)c * lz : kQ2Off;
+    };
     double pre[CW / 4];
     // 64 rows from global row g0 of the chunk's columns: lane -> row, wave + 4 j -> column
-    auto gload = [&](int64_t g0) {
-        const int64_t g = g0 + lane;
+    auto gload = [&](int g0) {
 #pragma unroll
-        for (int j = 0; j < CW / 4; ++j) {
-            const int64_t c = c0 + wave + 4 * j;
-            pre[j] = (g < n && c < ncol) ? Z[g + c * ldz] : 0.0;
-        }
+        for (int j = 0; j < CW / 4; ++j) pre[j] = q2_ld(rz, zoff(g0 + lane, wave + 4 * j), 0u);
     };
     auto lstore = [&](int slot0) {
 #pragma unroll
@@ -1249,29 +1277,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) q
     // V_k and Y_k are banded: column j of V_k is zero outside window rows j .. j + 63, and
     // Y_k(r, c) = 0 for c < r - 63.  The first product of wave w (sweeps 16 w .. 16 w + 15)
     // takes window rows 16 w .. 16 w + 79 only (K-steps q = 4 w .. 4 w + 19); the second
-    // skips the K-steps below 4 ra - 16 for its row block ra.
+    // skips the K-steps below 4 ra - 16 for its row block ra (their fragments are zero).
     const int q1 = 4 * wave;
     const int qa0 = 8 * wave - 16 > 0 ? 8 * wave - 16 : 0, qa1 = 8 * wave - 12 > 0 ? 8 * wave - 12 : 0;
-    // The first product's fragments are requested at the start of a step; the
-    // second's are read as it goes.
-    double f1[20];
+    const uint32_t fl = (uint32_t)(wave * 2048 + lane) * 8u;  // this lane's fragment offset in a step
+    double f1[20], f2[32];
     auto load_f1 = [&](int k) {
-        const double *F1 = F + (int64_t)k * kQ2Frag + wave * 2048;
 #pragma unroll
-        for (int t = 0; t < 20; ++t) f1[t] = F1[(q1 + t) * 64 + lane];
+        for (int t = 0; t < 20; ++t) f1[t] = q2_ld(rf, fl + (uint32_t)((q1 + t) * 512), (uint32_t)k * (kQ2Frag * 8u));
+    };
+    auto load_f2 = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) f2[q] = q2_ld(rf, fl + 65536u + (uint32_t)(q * 512), (uint32_t)k * (kQ2Frag * 8u));
     };
     gload(w00);
     lstore(0);
     gload(w00 + 64);
     for (int k = 0; k < kc; ++k) {
-        const int64_t w0 = w00 + (int64_t)k * BW;
+        const int w0 = w00 + k * BW;
         const int sb = (k & 1) * 64;
         load_f1(k);
+        load_f2(k);
         __syncthreads();  // the previous step's readers of the slots below are done
         lstore((64 + sb) & 127);  // window rows 64 .. 127
         if (k + 1 < kc) gload(w0 + 128);  // the next step's rows 64 .. 127
         __syncthreads();
-        // W rows 16 wave .. +15 = V_k^T Zw (K = 128 window rows)
+        // W rows 16 wave .. +15 = V_k^T Zw
         q2d4 acc1[NBC];
 #pragma unroll
         for (int bc = 0; bc < NBC; ++bc) acc1[bc] = q2d4{0.0, 0.0, 0.0, 0.0};
@@ -1296,17 +1327,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) q
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     acc2[a][bc][r] = Zs[(16 * bc + 4 * r + lq) * LDZ2 + ((32 * wave + 16 * a + lr + sb) & 127)];
-        const double *F2 = F + (int64_t)k * kQ2Frag + 8192 + wave * 2048;
-#pragma unroll 8
-        for (int q = 0; q < 16; ++q) {
-            if (q < qa0) continue;  // uniform over the wave
-            const bool b1 = q >= qa1;
-            const double y0 = F2[q * 64 + lane], y1 = b1 ? F2[(16 + q) * 64 + lane] : 0.0;
 #pragma unroll
-            for (int bc = 0; bc < NBC; ++bc) {
-                const double wv = Ws[(4 * q + lq) * LDW + 16 * bc + lr];
-                acc2[0][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y0, acc2[0][bc], 0, 0, 0);
-                if (b1) acc2[1][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, y1, acc2[1][bc], 0, 0, 0);
+        for (int q = 0; q < 16; ++q) {
+            if (q >= qa0) {  // uniform over the wave
+                const bool b1 = q >= qa1;
+#pragma unroll
+                for (int bc = 0; bc < NBC; ++bc) {
+                    const double wv = Ws[(4 * q + lq) * LDW + 16 * bc + lr];
+                    acc2[0][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, f2[q], acc2[0][bc], 0, 0, 0);
+                    if (b1) acc2[1][bc] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, f2[16 + q], acc2[1][bc], 0, 0, 0);
+                }
             }
         }
         // rows 0 .. 63 are final for the block (waves 0, 1); rows 64 .. 127 (waves 2, 3) are
@@ -1319,12 +1349,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) q
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int rw = 32 * wave + 16 * a + lr, cl = 16 * bc + 4 * r + lq;
-                    if (out) {
-                        const int64_t g = w0 + rw, c = c0 + cl;
-                        if (g < n && c < ncol) Z[g + c * ldz] = acc2[a][bc][r];
-                    } else {
+                    if (out)
+                        q2_st(rz, acc2[a][bc][r], zoff(w0 + rw, cl));
+                    else
                         Zs[cl * LDZ2 + ((rw + sb) & 127)] = acc2[a][bc][r];
-                    }
                 }
     }
 }
@@ -1333,6 +1361,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) q
 int apply_bulge_q(int64_t n, const double *v2, double *Z, int64_t ldz, int64_t ncol, hipStream_t stream) {
     if (n < 3 || ncol <= 0) return TGBA_OK;
     if (!v2 || !Z || ldz < n) return set_error(TGBA_EINVAL, "bulge back-transform: bad arguments");
+    if (ldz >= 5000000 || (n - 3) / BW + 1 > 1024)  // 32-bit buffer offsets in q2_apply_kernel
+        return set_error(TGBA_EUNSUPPORTED, "bulge back-transform: order or leading dimension too large");
     const int64_t ks = bulge_v2_stride(n);
     const int64_t nblk = (n - 2 + 63) / 64;  // blocks of 64 sweeps (sweeps 0 .. n - 3)
     const int kc0 = (int)((n - 3) / BW) + 1;
