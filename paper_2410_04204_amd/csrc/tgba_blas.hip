@@ -232,7 +232,7 @@ __device__ __forceinline__ void store_tile(const GemmDesc &G, int64_t m0, int64_
 // Two waves per SIMD (the accumulators then live in VGPRs): 1.75x the
 // throughput of one wave per SIMD with accumulation registers on 8192^3.
 template <int TNV, bool SYM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TNV == 64 ? 3 : 2)))
 dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
     constexpr int WN = TNV / 2, NB = WN / 16;
     __shared__ double As[TKD][LDS_STRIDE];  // As[k][i]
