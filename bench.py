@@ -489,8 +489,9 @@ def overlap_study(chis=(1000, 2000, 4000, 8000, 12000), pool=14.0, m_max=10, h_p
 
 
 def mixed_precision(n_refine=200):
-    """FP64 versus mixed-precision eigen-decomposition (with vectors) of the
-    N = 40 K = 0 sector at E_cut = 10.85: wall times, the difference of the
+    """FP64 (one-stage, and two-stage with both back-transforms) versus
+    mixed-precision eigen-decomposition (with vectors) of the N = 40 K = 0
+    sector at E_cut = 10.85, one sector alone: wall times, the difference of the
     lowest n_refine eigenvalues, the largest unrefined difference and that of
     S(0, omega) computed from each set of eigenvectors."""
     import torch
@@ -505,13 +506,15 @@ def mixed_precision(n_refine=200):
     tg.assemble_heff(B, 0, G, tg.TGBA_GAMMA1)
     omega = torch.as_tensor(workloads.omega_grid(4096, 8.0), device="cuda")
     out = {}
-    for name in ("fp64", "mixed"):
+    for name in ("fp64", "fp64_two_stage", "mixed"):
         A = H.clone()
         ev = torch.empty(n, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if name == "fp64":
             tg.eig(A, ev, tg.TGBA_EIG_FP64)
+        elif name == "fp64_two_stage":
+            tg.eig(A, ev, tg.TGBA_EIG_TWOSTAGE)
         else:
             tg.eig_mixed(A, ev, n_refine)
         torch.cuda.synchronize()
@@ -521,9 +524,12 @@ def mixed_precision(n_refine=200):
         out[name] = (ev.cpu().numpy(), S.cpu().numpy(), dt)
         del A
     wf, Sf, tf = out["fp64"]
+    w2, S2, t2 = out["fp64_two_stage"]
     wm, Sm, tm = out["mixed"]
     return {"workload": f"N=40 K=0, E_cut={w['e_cut']}, n={n}, eigenvectors", "n_refine": n_refine,
-            "fp64_s": tf, "mixed_s": tm, "speedup": tf / tm,
+            "fp64_s": tf, "fp64_two_stage_s": t2, "mixed_s": tm, "speedup": tf / tm,
+            "speedup_vs_two_stage": t2 / tm,
+            "two_stage_vs_one_stage_max_abs_diff": float(np.abs(w2 - wf).max()),
             "lowest_refined_max_abs_diff": float(np.abs(wm[:n_refine] - wf[:n_refine]).max()),
             "unrefined_max_abs_diff": float(np.abs(np.sort(wm) - wf).max()),
             "dsf_max_rel_diff": float(np.abs(Sm - Sf).max() / np.abs(Sf).max()),
@@ -727,9 +733,12 @@ def main():
                   "avg_call_ms": bulge_ms / max(bulge_calls, 1), "calls": bulge_calls,
                   "share_of_step": bulge_ms / a.steps / ms_per_step}
     q2_tfs = q2_flops_total / (q2_ms * 1e-3) / 1e12 if q2_ms > 0 else 0.0
+    tr_q2 = [counted_traffic(k) for k in ("q2_apply_kernel", "q2_build_kernel")]
+    q2_traffic = sum(t["bytes_per_launch"] * t["launches_counted"] for t in tr_q2) if all(tr_q2) else None
     roof_q2 = {"kernel": "q2_build_kernel + q2_apply_kernel (K=0 bulge back-transform, one record per call)",
                "bound": "mfma", "achieved": q2_tfs, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
-               "frac": q2_tfs / FP64_MFMA_PEAK_TFS, "traffic": None,
+               "frac": q2_tfs / FP64_MFMA_PEAK_TFS, "traffic": q2_traffic,
+               "traffic_note": "counted HBM bytes of one call (both kernels, all launches of the serialised step)",
                "algorithmic_flops_per_call": q2_flops_total / max(q2_calls, 1),
                "avg_call_ms": q2_ms / max(q2_calls, 1), "calls": q2_calls,
                "share_of_step": q2_ms / a.steps / ms_per_step}
