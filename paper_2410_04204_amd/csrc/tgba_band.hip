@@ -108,11 +108,16 @@ __device__ __forceinline__ double lane_f64(double v, int l) {
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
     return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
 }
-__device__ __forceinline__ double wave_sum(double v) {
+// The sum over each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ double row_sum16(double v) {
     v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
     v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
     v += dpp_f64<0x141>(v);  // row_half_mirror
     v += dpp_f64<0x140>(v);  // row_mirror
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_sum16(v);
     return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
@@ -156,19 +161,26 @@ __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict_
                 if (c0 + jj > q) acc[jj] += x * P[r + (c0 + jj) * lda];
         }
     }
-    __shared__ double red[4][QP];
+    // row sums (16 lanes) of each wave to LDS, the 16 of them summed below
+    __shared__ double red[16][QP];
+    const int rrow = 4 * wave + (lane >> 4);
 #pragma unroll
     for (int jj = 0; jj < SB; ++jj) {
         if (c0 + jj > q) {  // q is uniform: the branch is too
-            const double v = wave_sum(acc[jj]);
-            if (lane == 0) red[wave][c0 + jj] = v;
+            const double v = row_sum16(acc[jj]);
+            if ((lane & 15) == 0) red[rrow][c0 + jj] = v;
         }
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) red[wave][BW] = nrm;
+    nrm = row_sum16(nrm);
+    if ((lane & 15) == 0) red[rrow][BW] = nrm;
     __syncthreads();
     double *out = S.qpart + (int64_t)blk * QP;
-    if (tid < QP && ((tid > q && tid < c1) || tid == BW)) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (tid < QP && ((tid > q && tid < c1) || tid == BW)) {
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a += red[r][tid];
+        out[tid] = a;
+    }
     if (blk == 0 && tid >= q && tid < c1) S.qpart[kQrMaxBlk * QP + tid] = P[q + tid * lda];
 }
 
@@ -197,7 +209,7 @@ __global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict_
     const double *qin = S.qpart + (q & 1) * QB;
     double *qout = S.qpart + ((q + 1) & 1) * QB;
     __shared__ double sums[QP], w[BW], par[3];
-    __shared__ double red[4][QP];
+    __shared__ double red[16][QP];
     const double *top = qin + kQrMaxBlk * QP;
     if (tid < QP && ((tid > q && tid < c1) || tid == BW)) {
         double a = 0.0;
@@ -254,18 +266,24 @@ __global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict_
         if (next && r > qn) nrm += x * x;  // sum_{r > qn} P[r][qn]^2
     }
     if (!next) return;
+    const int rrow = 4 * wave + (lane >> 4);
 #pragma unroll
     for (int jj = 0; jj < SB; ++jj) {
         if (c0 + jj > qn) {  // uniform
-            const double v = wave_sum(acc[jj]);
-            if (lane == 0) red[wave][c0 + jj] = v;
+            const double v = row_sum16(acc[jj]);
+            if ((lane & 15) == 0) red[rrow][c0 + jj] = v;
         }
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) red[wave][BW] = nrm;
+    nrm = row_sum16(nrm);
+    if ((lane & 15) == 0) red[rrow][BW] = nrm;
     __syncthreads();
     double *out = qout + (int64_t)blk * QP;
-    if (tid < QP && ((tid > qn && tid < c1) || tid == BW)) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (tid < QP && ((tid > qn && tid < c1) || tid == BW)) {
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a += red[r][tid];
+        out[tid] = a;
+    }
 }
 
 // Columns [c0, c0 + SB) of V (m x BW, ld n): unit lower trapezoidal reflectors
@@ -383,7 +401,7 @@ __device__ __forceinline__ void bulge_task(double *__restrict__ B, int64_t n, in
     if (wave == 0) {
         const double x = E[0];
         const double sig = wave_sum(lane > 0 ? x * x : 0.0);
-        const double alpha = __shfl(x, 0, 64);
+        const double alpha = lane_f64(x, 0);
         double tau = 0.0, beta = alpha, scale = 0.0;
         if (sig != 0.0) {
             beta = -copysign(sqrt(alpha * alpha + sig), alpha);
