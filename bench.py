@@ -7,10 +7,10 @@ K <-> N-K), FP64 throughout.  One step = one pass of the device hot path over
 that input, with the basis (host enumeration + contraction table) resident:
   1. H_eff of all 40 sectors in one launch (real gauge, column-major, FP64,
      lower triangle: the part the eigensolver reads);
-  2. eigen-decomposition of every sector: one batched two-stage reduction of all
-     40 sectors, eigenvalues of K != 0 by bisection, the K = 0 eigenvectors by
-     divide and conquer and the bulge and panel back-transforms (on a second
-     stream beside the bisection);
+  2. eigen-decomposition of every sector by the two-stage reduction: the 39
+     K != 0 sectors batched, then bisection, on the caller's stream; the K = 0
+     sector on a second stream at the same time, keeping its reflectors, then
+     divide and conquer and the bulge and panel back-transforms;
   3. gamma_1 matrix of K = 0 and the dynamic structure factor S(0, omega) on
      4096 frequencies;
   4. quench from the K = 0 ground state of H0: <sigma^x>(t) on 1001 times
@@ -643,16 +643,16 @@ def main():
         tg.assemble_heff_batched(B, Ks, Hs, tg.TGBA_HEFF | tg.TGBA_LOWER, stream=st)
         mark(1)
         if serial:
-            # the same call with the K = 0 vector work after the bisection on one stream
-            # (kernel-quality view: every kernel alone on the device)
+            # the same call with one reduction of all sectors and the K = 0 vector work after
+            # the bisection, on one stream (kernel-quality view: every kernel alone on the device)
             os.environ["TGBA_VEC_SIDE_STREAM"] = "0"
             try:
                 tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))], stream=st)
             finally:
                 del os.environ["TGBA_VEC_SIDE_STREAM"]
         else:
-            # one two-stage reduction of all sectors; the spectra of K != 0 by bisection and
-            # the eigenpairs of K = 0 (divide and conquer, back-transforms) on two streams
+            # the K != 0 sectors' two-stage reduction and bisection, and the K = 0 sector's
+            # reduction, divide and conquer and back-transforms, on two streams at once
             tg.eig_batched_vec(Hs, ws, [K == 0 for K in range(len(Hs))], stream=st)
         mark(2)
         tg.assemble_heff(B, 0, G0, tg.TGBA_GAMMA1, stream=st)
@@ -729,6 +729,9 @@ def main():
     bulge_gbs = bulge_bytes_total / (bulge_ms * 1e-3) / 1e9 if bulge_ms > 0 else 0.0
     roof_bulge = {"kernel": "sb2st_pair_kernel (bulge chasing, one launch per step)", "bound": "hbm",
                   "achieved": bulge_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bulge_gbs / HBM_PEAK_GBS,
+                  "note": "bytes over the summed durations of the step's calls: the K != 0 and K = 0 reductions "
+                          "run at the same time on two streams, so their durations overlap and this rate "
+                          "understates the device's; roofline_isolated has the single-reduction rate",
                   "algorithmic_bytes_per_call": bulge_bytes_total / max(bulge_calls, 1),
                   "avg_call_ms": bulge_ms / max(bulge_calls, 1), "calls": bulge_calls,
                   "share_of_step": bulge_ms / a.steps / ms_per_step}

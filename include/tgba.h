@@ -348,17 +348,21 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
 /*
  * Several sectors, some with eigenvectors: want_vectors (host, nsec) marks the
  * sectors whose A is to be overwritten by Z; the others get eigenvalues only
- * (A overwritten).  All sectors go through one batched two-stage reduction; the
- * eigenvalue-only sectors then take bisection on `stream`, and the vector
- * sectors (whose reduction keeps its reflectors: 8 n^2 bytes of bulge
- * reflectors per sector in the library's workspace) take divide and conquer and
- * the two back-transforms (TGBA_EIG_TWOSTAGE) on a second stream of the device,
- * joined back into `stream`.  With the environment variable
+ * (A overwritten).  Every sector takes the two-stage reduction; the vector
+ * sectors keep its reflectors (8 n^2 bytes of bulge reflectors per sector in the
+ * library's workspace) and take divide and conquer and the two back-transforms
+ * (TGBA_EIG_TWOSTAGE), the others bisection.  When both kinds are present, the
+ * vector sectors' whole path runs on a second stream of the device from a second
+ * host thread, beside the eigenvalue sectors' batched reduction and bisection on
+ * `stream` (ordered after the work already queued on `stream`).  With
+ * TGBA_VEC_CONCURRENT=0 all sectors share one batched reduction and only the
+ * vector work runs on the second stream, joined back into `stream`.  With the environment variable
  * TGBA_VEC_REDUCTION=onestage the vector sectors instead take the one-stage
  * reduction (tgba_eig) on the second stream from a second host thread, beside
  * the eigenvalue-only sectors' two-stage path.  With TGBA_VEC_SIDE_STREAM=0
- * the vector sectors' work runs on `stream` after the bisection (one kernel at a
- * time on the device: per-kernel rates).  Returns when all are done.
+ * all sectors share one batched reduction and the vector sectors' work runs on
+ * `stream` after the bisection (one kernel at a time on the device: per-kernel
+ * rates).  Returns when all are done.
  * Errors: as tgba_eig_batched.
  */
 int tgba_eig_batched_vec(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w,

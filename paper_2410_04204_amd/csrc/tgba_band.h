@@ -34,8 +34,9 @@ size_t band_workspace_doubles(int64_t n);
 // Tridiagonal similar to every sector's matrix, A = Q1 Q2 T (Q1 Q2)^T.  The
 // reflectors of Q1 (first stage) and Q2 (bulge chasing) are kept for the
 // sectors that give BandIn::tau and BandIn::v2.  Stream-ordered; orders up to
-// 65536.
-int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream);
+// 65536.  slot_set (0 or 1) picks one of two sets of workspace slots: calls with
+// different sets may run at the same time on two streams.
+int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream, int slot_set = 0);
 
 // Z <- Q2 Z for the second stage's reflectors v2 of a sector of order n (Z: n x ncol,
 // column-major, ld ldz): blocks of 64 consecutive sweeps, the last block first.

@@ -68,8 +68,14 @@ constexpr int SB = 16;             // columns of a panel-QR sub-block
 constexpr int QB = kQrMaxBlk * QP + BW;  // one partial-sum buffer of the panel QR (column q uses buffer q & 1)
 
 // workspace slots of this file
-constexpr int kSlotSecs = ws::BandSecs, kSlotWork = ws::BandWork, kSlotParts = ws::BandParts, kSlotGemm = ws::BandGemm,
-              kSlotRed = ws::BandRed, kSlotSched = ws::BandSched;
+// workspace slots of this file: two sets, so that two calls may run at the same time (set 1:
+// the vector sectors' reduction on a second stream beside the eigenvalue sectors')
+struct BandSlots {
+    int secs, work, parts, gemm, red, sched;
+};
+constexpr BandSlots kBandSlots[2] = {
+    {ws::BandSecs, ws::BandWork, ws::BandParts, ws::BandGemm, ws::BandRed, ws::BandSched},
+    {ws::BandSecs2, ws::BandWork2, ws::BandParts2, ws::BandGemm2, ws::BandRed2, ws::BandSched2}};
 
 struct BandSec {
     double *A;
@@ -728,7 +734,11 @@ __global__ void __launch_bounds__(256) pair_copy_kernel(const BandSec *__restric
 }
 }  // namespace
 
-int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream) {
+int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream, int slot_set) {
+    if (slot_set < 0 || slot_set > 1) return set_error(TGBA_EINVAL, "two-stage reduction: slot set must be 0 or 1");
+    const int kSlotSecs = kBandSlots[slot_set].secs, kSlotWork = kBandSlots[slot_set].work,
+              kSlotParts = kBandSlots[slot_set].parts, kSlotGemm = kBandSlots[slot_set].gemm,
+              kSlotRed = kBandSlots[slot_set].red, kSlotSched = kBandSlots[slot_set].sched;
     const int nsec = (int)in.size();
     if (nsec == 0) return TGBA_OK;
     if (nsec > kMaxBandSecs) return set_error(TGBA_EUNSUPPORTED, "two-stage reduction: more than 256 sectors in one call");

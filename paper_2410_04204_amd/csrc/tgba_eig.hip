@@ -1072,14 +1072,25 @@ bool vec_side_stream() {
     const char *v = std::getenv("TGBA_VEC_SIDE_STREAM");
     return !(v && std::strcmp(v, "0") == 0);
 }
+// The vector sectors take their own two-stage reduction on the second stream, from a
+// second host thread, beside the eigenvalue sectors' reduction (TGBA_VEC_CONCURRENT=0:
+// one reduction of all sectors, then the vector work beside the bisection).
+bool vec_concurrent() {
+    const char *v = std::getenv("TGBA_VEC_CONCURRENT");
+    return !(v && std::strcmp(v, "0") == 0);
+}
 
-// Eigen-decomposition of several sectors in one two-stage reduction: every
-// sector's tridiagonal comes from the same batched launches; the sectors without
-// vectors then take bisection on `stream`, and the sectors with vectors (whose
-// reduction kept its reflectors) take divide and conquer on the tridiagonal, the
-// bulge reflectors' back-transform and the first stage's back-transform,
-// A = Q1 Q2 T Q2^T Q1^T => Z = Q1 (Q2 Z_T), on a second stream when both kinds
-// are present, so that bisection and the vector work overlap.
+// Eigen-decomposition of several sectors by the two-stage reduction.  The sectors
+// with vectors keep their reflectors and then take divide and conquer on the
+// tridiagonal, the bulge reflectors' back-transform and the first stage's
+// back-transform, A = Q1 Q2 T Q2^T Q1^T => Z = Q1 (Q2 Z_T); the others take
+// bisection.  When both kinds are present (and not recording), the vector sectors'
+// whole path runs on a second stream from a second host thread beside the
+// eigenvalue sectors' reduction and bisection on `stream` (two batched reductions,
+// with separate workspace slot sets): the latency-bound parts of each (panel QR
+// columns, bulge-chasing steps, the back-transform's windows) leave room for the
+// other's.  Otherwise (or with TGBA_VEC_CONCURRENT=0) all sectors share one batched
+// reduction and only the vector work runs beside the bisection.
 int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *lda, double *const *w, const int *want,
                   hipStream_t stream) {
     size_t tot = 0, tv = 0;
@@ -1116,6 +1127,65 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
         }
         bin.push_back(b);
     }
+    // divide and conquer and the two back-transforms of the vector sectors, on sv
+    auto vec_tail = [&](hipStream_t sv) -> int {
+        int rc = TGBA_OK;
+        for (const VecSec &V : vs) {
+            const int64_t nn = n[V.k];
+            void *zw = nullptr;
+            const size_t zbytes = sizeof(double) * ((size_t)nn * nn + ormtr_scratch_elems(nn));
+            if ((rc = workspace_get(zbytes, ws::EigVecZ, &zw))) return rc;
+            double *Zt = (double *)zw;
+            double *scratch = Zt + (size_t)nn * nn;
+            if ((rc = stedc(nn, V.d, V.e, Zt, nn, sv))) return rc;
+            if ((rc = apply_bulge_q(nn, V.v2, Zt, nn, nn, sv))) return rc;
+            if (nn - kBandWidth - 1 > 0 &&
+                (rc = ormtr(nn, (const double *)A[V.k], lda[V.k], (const double *)V.tau, Zt, nn, scratch, sv,
+                            (int64_t)kBandWidth, nn - kBandWidth - 1)))
+                return rc;
+            hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(4096), dim3(256), 0, sv, Zt, nn, A[V.k], lda[V.k], nn, nn);
+            hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(64), dim3(256), 0, sv, (const double *)V.d, nn, w[V.k],
+                               nn, nn, (int64_t)1);
+            TGBA_HIP(hipGetLastError());
+        }
+        return TGBA_OK;
+    };
+    if (!vs.empty() && !bis.empty() && vec_concurrent() && vec_side_stream() && !capturing()) {
+        // two reductions at once: the vector sectors' (workspace slot set 1) on the second
+        // stream from a second host thread, the eigenvalue sectors' on `stream`
+        std::vector<BandIn> bvec, bnov;
+        for (const BandIn &b : bin) (b.v2 ? bvec : bnov).push_back(b);
+        hipStream_t s2 = nullptr;
+        if ((rc = side_stream(&s2))) return rc;
+        hipEvent_t ev = nullptr;
+        TGBA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        TGBA_HIP(hipEventRecord(ev, stream));
+        TGBA_HIP(hipStreamWaitEvent(s2, ev, 0));
+        int dev = 0;
+        TGBA_HIP(hipGetDevice(&dev));
+        int rc2 = TGBA_OK;
+        std::string err2;
+        std::thread th([&] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                rc2 = TGBA_EDEVICE;
+                err2 = "hipSetDevice failed in the vector thread";
+                return;
+            }
+            rc2 = sytrd_2stage_batched(bvec, s2, 1);
+            if (!rc2) rc2 = vec_tail(s2);
+            if (!rc2 && hipStreamSynchronize(s2) != hipSuccess) rc2 = set_error(TGBA_EDEVICE, "vector stream failed");
+            if (!rc2) rc2 = band_check(s2);
+            if (rc2) err2 = tgba_last_error();
+        });
+        rc = sytrd_2stage_batched(bnov, stream, 0);
+        if (!rc) rc = stebz_batched(bis, stream);
+        th.join();
+        (void)hipEventDestroy(ev);
+        if (rc) return rc;
+        if (rc2) return set_error(rc2, err2);
+        TGBA_HIP(hipStreamSynchronize(stream));
+        return band_check(stream);
+    }
     if ((rc = sytrd_2stage_batched(bin, stream))) return rc;
     hipStream_t sv = stream;
     hipEvent_t join = nullptr;
@@ -1134,24 +1204,7 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
         if (!capturing()) TGBA_HIP(hipEventDestroy(ev));
     }
     if (!bis.empty() && (rc = stebz_batched(bis, stream))) return rc;
-    for (const VecSec &V : vs) {
-        const int64_t nn = n[V.k];
-        void *zw = nullptr;
-        const size_t zbytes = sizeof(double) * ((size_t)nn * nn + ormtr_scratch_elems(nn));
-        if ((rc = workspace_get(zbytes, ws::EigVecZ, &zw))) return rc;
-        double *Zt = (double *)zw;
-        double *scratch = Zt + (size_t)nn * nn;
-        if ((rc = stedc(nn, V.d, V.e, Zt, nn, sv))) return rc;
-        if ((rc = apply_bulge_q(nn, V.v2, Zt, nn, nn, sv))) return rc;
-        if (nn - kBandWidth - 1 > 0 &&
-            (rc = ormtr(nn, (const double *)A[V.k], lda[V.k], (const double *)V.tau, Zt, nn, scratch, sv,
-                        (int64_t)kBandWidth, nn - kBandWidth - 1)))
-            return rc;
-        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(4096), dim3(256), 0, sv, Zt, nn, A[V.k], lda[V.k], nn, nn);
-        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3(64), dim3(256), 0, sv, (const double *)V.d, nn, w[V.k], nn,
-                           nn, (int64_t)1);
-        TGBA_HIP(hipGetLastError());
-    }
+    if ((rc = vec_tail(sv))) return rc;
     if (fork) {
         TGBA_HIP(hipEventRecord(join, sv));
         TGBA_HIP(hipStreamWaitEvent(stream, join, 0));

@@ -75,7 +75,7 @@ enum Slot : int {
     MlpScore, MlpSelect, MlpBackward, MlpTrain, LearnedKeep, MixedF32, MixedF64, RefineWork, RefineGemm, CrossDesc,
     BandSecs, BandWork, BandParts, BandGemm, BandRed, BandSched, OrmtrParts, OrmtrRed, EigNovecWork, CorrWork, QuenchCorrWork,
     QuenchCorrGemm1, QuenchCorrGemm2, DsfCrossWork, SytrdApiWork, BisectBounds, DCMerges, DCFirst, DCSplits,
-    BulgeQ, EigVec2Stage, Count
+    BulgeQ, EigVec2Stage, BandSecs2, BandWork2, BandParts2, BandGemm2, BandRed2, BandSched2, Count
 };
 }  // namespace ws
 constexpr int kWorkspaceSlots = 64;

@@ -197,9 +197,10 @@ def test_masked_split_k_symmetric_product():
 
 
 def test_eig_batched_vec_concurrent_groups():
-    """Sectors with and without eigenvectors in one call (one two-stage reduction;
-    bisection and the vector sectors' back-transforms on two streams): eigenvalues
-    against LAPACK, and A Z = Z diag(w), Z^T Z = 1 for the vector sectors."""
+    """Sectors with and without eigenvectors in one call (two two-stage reductions on two
+    streams from two host threads; bisection, and divide and conquer with the two
+    back-transforms): eigenvalues against LAPACK, and A Z = Z diag(w), Z^T Z = 1 for the
+    vector sectors."""
     import paper_2410_04204_amd as tg
     torch = _t()
     sizes = [1500, 700, 2049, 65, 900, 3]
@@ -345,6 +346,31 @@ def test_eig_two_stage_with_vectors_random(n):
     assert np.abs(wn - ref).max() <= 1e-12 * nrm * np.sqrt(n)
     assert np.abs(A @ Z - Z * wn).max() <= 1e-12 * nrm * np.sqrt(n)
     assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-12 * np.sqrt(n)
+
+
+@pytest.mark.parametrize("mode", ["TGBA_VEC_CONCURRENT", "TGBA_VEC_SIDE_STREAM"])
+def test_eig_batched_vec_single_reduction(monkeypatch, mode):
+    """TGBA_VEC_CONCURRENT=0 (all sectors in one batched reduction, the vector work beside
+    the bisection) and TGBA_VEC_SIDE_STREAM=0 (the same, all on one stream) give the
+    eigenpairs of the default (two reductions on two streams) within the FP64 bar."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    monkeypatch.setenv(mode, "0")
+    sizes = [1300, 700, 2049, 3, 900]
+    want = [True, False, False, True, False]
+    As = [_rand_sym(n, 900 + n) for n in sizes]
+    mats = [_cm(A) for A in As]
+    ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+    tg.eig_batched_vec(mats, ws, want)
+    for A, M, w, v in zip(As, mats, ws, want):
+        ref = scipy.linalg.eigvalsh(A)
+        n = A.shape[0]
+        wn = w.cpu().numpy()
+        assert np.abs(np.sort(wn) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()) * np.sqrt(n)
+        if v:
+            Z = _np(M)
+            assert np.abs(A @ Z - Z * wn[None, :]).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+            assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-10
 
 
 def test_eig_batched_vec_one_stage_switch(monkeypatch):
