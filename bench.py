@@ -89,26 +89,32 @@ def parse():
     p.add_argument("--profile-serial", action="store_true",
                    help="only run warm-up + timed steps with the K = 0 vector work serialised on one "
                         "stream from one thread, print a marker line and exit (rocprofv3 counter passes)")
+    p.add_argument("--profile-step", action="store_true",
+                   help="only run warm-up + timed steps as the timed region runs them (the K = 0 vector "
+                        "work on a second stream beside the bisection), print a marker line and exit "
+                        "(rocprofv3 counter passes)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (5 times), the reference for "
                         "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes")
     return p.parse_args()
 
 
-def counted_traffic(family):
-    """Counted HBM bytes per launch of a kernel family (all its instantiations), or None."""
+def counted_traffic(family, section="kernels"):
+    """Counted HBM bytes per launch of a kernel family (all its instantiations), or None.
+    `section` "kernels" holds the serialised step's launches (and the assembly-only passes),
+    "step_kernels" the launches of a step run as the timed region runs it."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    ks = [v for k, v in t["kernels"].items() if k.startswith(family)]
+    ks = [v for k, v in t.get(section, {}).items() if k.startswith(family)]
     if not ks:
         return None
     launches = sum(v["launches"] for v in ks)
     total = sum(v["launches"] * v["traffic_bytes_per_launch"] for v in ks)
     return {"bytes_per_launch": total / launches, "launches_counted": launches, "source": os.path.relpath(TRAFFIC_FILE, ROOT),
-            "calibration": t.get("calibration")}
+            "section": section, "calibration": t.get("calibration")}
 
 
 def assembly_roofline(achieved, bytes_per_launch, asm_ms):
@@ -671,14 +677,16 @@ def main():
         print(json.dumps({"profile_assembly": True, "launches": a.warmup + a.steps, "elements": elements,
                           "lower_triangle_bytes": int(sum(x * (x + 1) // 2 for x in n)) * 8}), flush=True)
         return
-    if a.profile_serial:
-        # profiling run: warm-up and timed steps with the K = 0 vector work after the bisection
-        # on one stream, every launch issued from this thread (for rocprofv3 counter passes)
+    if a.profile_serial or a.profile_step:
+        # profiling run (rocprofv3 counter passes): warm-up and timed steps, either with the K = 0
+        # vector work after the bisection on one stream, every launch issued from this thread, or
+        # as the timed region runs them
         for i in range(a.warmup + a.steps):
-            step(serial=True)
+            step(serial=a.profile_serial)
             torch.cuda.synchronize()
-            print(f"serial step {i} done", file=sys.stderr, flush=True)
-        print(json.dumps({"profile_serial": True, "steps": a.warmup + a.steps, "workload": a.workload}), flush=True)
+            print(f"{'serial' if a.profile_serial else 'profiled'} step {i} done", file=sys.stderr, flush=True)
+        print(json.dumps({"profile_serial": bool(a.profile_serial), "profile_step": bool(a.profile_step),
+                          "steps": a.warmup + a.steps, "workload": a.workload}), flush=True)
         return
 
     for i in range(a.warmup):
@@ -713,7 +721,8 @@ def main():
     gemm_avg_ms = gemm_ms / max(gemm_launches, 1)
     gemm_avg_flops = gemm_flops_total / max(gemm_launches, 1)
     gemm_tfs = gemm_flops_total / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
-    tr_symv, tr_gemm = counted_traffic("tri_symv"), counted_traffic("dgemm_kernel")
+    # the timed step's launches: counted on a step run the same way (two streams)
+    tr_symv, tr_gemm = counted_traffic("tri_symv", "step_kernels"), counted_traffic("dgemm_kernel", "step_kernels")
     roof_symv = {"kernel": "tri_symv", "bound": "hbm", "achieved": symv_gbs, "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "frac": symv_gbs / HBM_PEAK_GBS,
                  "traffic": tr_symv["bytes_per_launch"] if tr_symv else None, "traffic_source": tr_symv,
@@ -736,12 +745,12 @@ def main():
                   "avg_call_ms": bulge_ms / max(bulge_calls, 1), "calls": bulge_calls,
                   "share_of_step": bulge_ms / a.steps / ms_per_step}
     q2_tfs = q2_flops_total / (q2_ms * 1e-3) / 1e12 if q2_ms > 0 else 0.0
-    tr_q2 = [counted_traffic(k) for k in ("q2_apply_kernel", "q2_build_kernel")]
+    tr_q2 = [counted_traffic(k, "step_kernels") for k in ("q2_apply_kernel", "q2_build_kernel")]
     q2_traffic = sum(t["bytes_per_launch"] * t["launches_counted"] for t in tr_q2) if all(tr_q2) else None
     roof_q2 = {"kernel": "q2_build_kernel + q2_apply_kernel (K=0 bulge back-transform, one record per call)",
                "bound": "mfma", "achieved": q2_tfs, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                "frac": q2_tfs / FP64_MFMA_PEAK_TFS, "traffic": q2_traffic,
-               "traffic_note": "counted HBM bytes of one call (both kernels, all launches of the serialised step)",
+               "traffic_note": "counted HBM bytes of one call (both kernels, all launches of a step run as timed)",
                "algorithmic_flops_per_call": q2_flops_total / max(q2_calls, 1),
                "avg_call_ms": q2_ms / max(q2_calls, 1), "calls": q2_calls,
                "share_of_step": q2_ms / a.steps / ms_per_step}
@@ -770,7 +779,8 @@ def main():
             "dgemm_kernel": {"achieved": i_gf / (i_gm * 1e-3) / 1e12 if i_gm > 0 else 0.0, "unit": "TFLOP/s",
                              "peak": FP64_MFMA_PEAK_TFS, "avg_launch_ms": i_gm / max(i_gl, 1),
                              "launches": i_gl, "frac": (i_gf / (i_gm * 1e-3) / 1e12 if i_gm > 0 else 0.0)
-                             / FP64_MFMA_PEAK_TFS},
+                             / FP64_MFMA_PEAK_TFS,
+                             "traffic": (counted_traffic("dgemm_kernel") or {}).get("bytes_per_launch")},
             "bulge_chasing": {"achieved": i_bb / (i_bm * 1e-3) / 1e9 if i_bm > 0 else 0.0, "unit": "GB/s",
                               "peak": HBM_PEAK_GBS, "ms": i_bm, "calls": i_bl,
                               "frac": (i_bb / (i_bm * 1e-3) / 1e9 if i_bm > 0 else 0.0) / HBM_PEAK_GBS},
