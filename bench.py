@@ -51,6 +51,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over the serialised step
 # (scaled by the copy calibration); written from the counter summary in profiles/.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n40_step.json")
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions per second (16 lanes per SIMD per cycle)
 FP64_MFMA_PEAK_TFS = 78.6  # dense FP64 matrix-core peak of the MI355X
 
 
@@ -136,6 +137,19 @@ def assembly_roofline(achieved, bytes_per_launch, asm_ms):
         tfs = fl / (asm_ms * 1e-3) / 1e12
         out["fp64_counted"] = {"flops_per_launch": fl, "achieved": tfs, "peak": FP64_MFMA_PEAK_TFS,
                                "unit": "TFLOP/s", "frac": tfs / FP64_MFMA_PEAK_TFS}
+    try:
+        with open(TRAFFIC_FILE) as f:
+            vi = json.load(f)["kernels"]["assemble_rows_kernel<4, false, 0>"].get("valu_insts_per_launch")
+    except (OSError, ValueError, KeyError):
+        vi = None
+    if vi:
+        # VALU issue: a wave64 vector instruction holds its SIMD's 16 lanes for 4 cycles, so the
+        # chip issues at most 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 6.14e11 of them per second
+        rate = vi / (asm_ms * 1e-3)
+        out["valu_issue"] = {"bound": "alu", "insts_per_launch": vi, "achieved": rate / 1e9,
+                             "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G wave64 VALU instructions/s",
+                             "frac": rate / VALU_ISSUE_PEAK,
+                             "note": "counted instructions (index work included), not algorithmic operations"}
     return out
 
 
