@@ -82,6 +82,17 @@ struct TileRegs {
     double a[16], b[16];
 };
 
+// The thread index rebuilt where a K-tile's loads are issued: the lane from the mbcnt
+// instructions (kept in place by the asm statement), the wave's first thread from a scalar
+// register.  Kept live across the K loop instead, the index is spilled by the narrow tiles
+// (three waves per SIMD), and its reload from scratch waits for the loads issued before it
+// (the vector memory counter retires in order), exposing a memory latency per K-tile.
+__device__ __forceinline__ int tid_now(int wave_base) {
+    int lane;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane));
+    return wave_base + lane;
+}
+
 // Storage order of the K-tile of op(A) at kt for the row tile at m0: 0 = A[i + k lda]
 // (op(A) = A), 1 = A[k + i lda] (op(A) = A^T), 2 = element by element (the
 // K-tiles of a symmetric operand that meet the row tile's diagonal block: the
@@ -273,13 +284,14 @@ dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
         }
         kstop = kend;
     }
+    const int wave_base = __builtin_amdgcn_readfirstlane(tid) & ~63;
     if (kbeg < kstop) load_tile<TNV, SYM>(G, m0, n0, kbeg, kend, tid, r);
     for (int64_t k0 = kbeg; k0 < kstop; k0 += TKD) {
         __syncthreads();  // the previous tile's readers are done
-        mask_tile<TNV, SYM>(G, m0, k0, kend, tid, r);
+        mask_tile<TNV, SYM>(G, m0, k0, kend, tid_now(wave_base), r);
         store_tile<TNV, SYM>(G, m0, k0, tid, r, As, Bs);
         __syncthreads();
-        if (k0 + TKD < kstop) load_tile<TNV, SYM>(G, m0, n0, k0 + TKD, kend, tid, r);
+        if (k0 + TKD < kstop) load_tile<TNV, SYM>(G, m0, n0, k0 + TKD, kend, tid_now(wave_base), r);
 #pragma unroll
         for (int kk = 0; kk < TKD; kk += 4) {
             double af[4], bf[NB];
