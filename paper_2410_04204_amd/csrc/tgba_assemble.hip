@@ -71,6 +71,10 @@ struct SectorDesc {
 
 namespace {
 
+// A complex entry (re, im) as a native two-double vector: assignable through a pointer in
+// the global address space (HIP's double2 is not)
+typedef double dcplx __attribute__((ext_vector_type(2)));
+
 constexpr int kThreads = 256;
 constexpr int kGenMax = 24;          // largest Pfaffian of the generic path
 constexpr double kGrowthLimit = 1e12; // flag a row whose Schur complement is (near) singular
@@ -475,7 +479,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             if (tid == 0) { s_fac[r] = 0.0; s_flag[r] = 0; s_defl[r] = 0; s_mbra[r] = 0; s_bra[r] = 0; }
             continue;
         }
-        const uint64_t bra = D.masks[a];
+        const uint64_t bra = as_global(D.masks)[a];
         const int Ma = __popcll(bra) + NJ;  // eliminated block: the common prefix, then the bra indices
         if (tid == 0) {
             int m = 0;
@@ -604,7 +608,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const bool bad = !keep_d || !(pf != 0.0) || !(s_growth <= kGrowthLimit * r_max) || !isfinite(pf);
             s_flag[r] = bad ? 1 : 0;
             s_defl[r] = bad ? 0 : d;
-            const double rs = (NJ && D.rsign) ? D.rsign[a] : 1.0;
+            const double rs = (NJ && D.rsign) ? as_global(D.rsign)[a] : 1.0;
             s_fac[r] = bad ? c0 * scale * rs : c0 * scale * pf * rs;
             if (bad) atomicAdd(&counters[0], 1ULL);
             if (!bad && d > 0) {
@@ -623,11 +627,11 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
         const int64_t a = a0 + r;
         const int64_t i0 = lower ? a : 0;
         for (int64_t i = i0 + tid; i < D.n_ns; i += kThreads) {
-            const double v = (i == a && with_diag) ? D.e[a] : 0.0;
+            const double v = (i == a && with_diag) ? as_global(D.e)[a] : 0.0;
             if constexpr (CPLX) {
-                reinterpret_cast<double2 *>(D.H)[i + a * ld] = make_double2(v, 0.0);
+                as_global(reinterpret_cast<dcplx *>(D.H))[i + a * ld] = dcplx{v, 0.0};
             } else {
-                reinterpret_cast<double *>(D.H)[i + a * ld] = v;
+                as_global(reinterpret_cast<double *>(D.H))[i + a * ld] = v;
             }
         }
     }
@@ -641,23 +645,23 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             const int64_t j = D.n_ns + bc;
             const int64_t i0 = lower ? j : D.n_ns;
             for (int64_t i = i0 + tid; i < D.n_ns + D.n_r; i += kThreads) {
-                const double v = (i == j && with_diag) ? D.e[j] : 0.0;
+                const double v = (i == j && with_diag) ? as_global(D.e)[j] : 0.0;
                 if constexpr (CPLX) {
-                    reinterpret_cast<double2 *>(D.H)[i + j * ld] = make_double2(v, 0.0);
+                    as_global(reinterpret_cast<dcplx *>(D.H))[i + j * ld] = dcplx{v, 0.0};
                 } else {
-                    reinterpret_cast<double *>(D.H)[i + j * ld] = v;
+                    as_global(reinterpret_cast<double *>(D.H))[i + j * ld] = v;
                 }
             }
         }
     }
 
     // ---- B elements -------------------------------------------------------
-    using T = typename std::conditional<CPLX, double2, double>::type;
-    T *Hb = reinterpret_cast<T *>(D.H);
-    T *colA[ROWS];  // columns a0 + r (B^T part, coalesced along b)
+    using T = typename std::conditional<CPLX, dcplx, double>::type;
+    const gptr<T> Hb = as_global(reinterpret_cast<T *>(D.H));
+    gptr<T> colA[ROWS];  // columns a0 + r (B^T part, coalesced along b)
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) colA[r] = Hb + (a0 + r) * ld + D.row_off;
-    const uint64_t *kmask = D.ket;
+    const auto kmask = as_global(D.ket);
     for (int64_t b = tid; nvalid > 0 && b < D.n_r; b += kThreads) {
         const uint64_t ket = kmask[b];
         const int Mb = __popcll(ket);
@@ -672,7 +676,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             default: row_values<-1, ROWS, NJ>(val, tabs, s_rowoff, ts, N, ket, nvalid, s_flag, s_defl, s_bra, s_fac, R, counters); break;
         }
         if constexpr (NJ > 0) {
-            const double cs = D.csign ? D.csign[b] : 1.0;
+            const double cs = D.csign ? as_global(D.csign)[b] : 1.0;
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) val[r] *= cs;
         }
@@ -683,7 +687,7 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
             if constexpr (CPLX) {
                 double re, im;
                 phase_mi((s_mbra[r] + Mb) / 2, val[r], re, im);
-                colA[r][b] = make_double2(re, -im);
+                colA[r][b] = dcplx{re, -im};
             } else {
                 if (D.mode == 2) Hb[(a0 + r) + (D.row_off + b) * ld] = val[r];  // bra row, ket column
                 else colA[r][b] = val[r];
@@ -695,11 +699,11 @@ assemble_rows_kernel(const SectorDesc *__restrict__ descs, int nsec, int N, cons
                 const int d = s_defl[r];
                 if (!d) continue;
                 double v = s_fac[r] * deflated_value<ROWS>(tabs, s_rowoff, ts, dk, s_dd[r], r, N, ket, Mb, d, r_max, counters);
-                if constexpr (NJ > 0) v *= D.csign ? D.csign[b] : 1.0;
+                if constexpr (NJ > 0) v *= D.csign ? as_global(D.csign)[b] : 1.0;
                 if constexpr (CPLX) {
                     double re, im;
                     phase_mi((s_mbra[r] + Mb) / 2, v, re, im);
-                    Hb[(a0 + r) * ld + D.row_off + b] = make_double2(re, -im);
+                    Hb[(a0 + r) * ld + D.row_off + b] = dcplx{re, -im};
                 } else {
                     if (D.mode == 2) Hb[(a0 + r) + (D.row_off + b) * ld] = v;
                     else Hb[(a0 + r) * ld + D.row_off + b] = v;

@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict_
     if (q >= nref) return;
     const int64_t nblk = (m - q + QCH - 1) / QCH;
     if (blk >= nblk) return;
-    const double *P = S.A + (j0 + BW) + j0 * S.lda;
+    const auto P = as_global(S.A + (j0 + BW) + j0 * S.lda);
     const int64_t lda = S.lda;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c0 = q & ~(SB - 1), c1 = c0 + SB;
@@ -180,14 +180,14 @@ __global__ void __launch_bounds__(256) qr_dots_kernel(const BandSec *__restrict_
     nrm = row_sum16(nrm);
     if ((lane & 15) == 0) red[rrow][BW] = nrm;
     __syncthreads();
-    double *out = S.qpart + (int64_t)blk * QP;
+    const auto out = as_global(S.qpart + (int64_t)blk * QP);
     if (tid < QP && ((tid > q && tid < c1) || tid == BW)) {
         double a = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) a += red[r][tid];
         out[tid] = a;
     }
-    if (blk == 0 && tid >= q && tid < c1) S.qpart[kQrMaxBlk * QP + tid] = P[q + tid * lda];
+    if (blk == 0 && tid >= q && tid < c1) as_global(S.qpart)[kQrMaxBlk * QP + tid] = P[q + tid * lda];
 }
 
 // Column q of the sub-block [c0, c0 + SB): the reflector from the partial sums of
@@ -209,14 +209,14 @@ __global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict_
     const int c0 = q & ~(SB - 1), c1 = c0 + SB;
     const int64_t nblk = (m - c0 + QCH - 1) / QCH;
     if (blk >= nblk) return;
-    double *P = S.A + (j0 + BW) + j0 * S.lda;
+    const auto P = as_global(S.A + (j0 + BW) + j0 * S.lda);
     const int64_t lda = S.lda;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const double *qin = S.qpart + (q & 1) * QB;
-    double *qout = S.qpart + ((q + 1) & 1) * QB;
+    const auto qin = as_global(S.qpart + (q & 1) * QB);
+    const auto qout = as_global(S.qpart + ((q + 1) & 1) * QB);
     __shared__ double sums[QP], w[BW], par[3];
     __shared__ double red[16][QP];
-    const double *top = qin + kQrMaxBlk * QP;
+    const auto top = qin + kQrMaxBlk * QP;
     if (tid < QP && ((tid > q && tid < c1) || tid == BW)) {
         double a = 0.0;
         for (int64_t b = 0; b < nblk; ++b) a += qin[b * QP + tid];
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict_
         par[0] = tau;
         par[1] = beta;
         par[2] = scale;
-        if (blk == 0) S.tau[j0 + q] = tau;
+        if (blk == 0) as_global(S.tau)[j0 + q] = tau;
     }
     __syncthreads();
     const double tau = par[0], beta = par[1], scale = par[2];
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict_
     nrm = row_sum16(nrm);
     if ((lane & 15) == 0) red[rrow][BW] = nrm;
     __syncthreads();
-    double *out = qout + (int64_t)blk * QP;
+    const auto out = qout + (int64_t)blk * QP;
     if (tid < QP && ((tid > qn && tid < c1) || tid == BW)) {
         double a = 0.0;
 #pragma unroll
@@ -299,16 +299,17 @@ __global__ void extract_panel_v_kernel(const BandSec *__restrict__ secs, int64_t
     const int64_t m = S.n - j0 - BW;
     if (m < 2) return;
     const int64_t nref = m - 1 < BW ? m - 1 : BW;
-    const double *P = S.A + (j0 + BW) + j0 * S.lda;
+    const auto P = as_global(S.A + (j0 + BW) + j0 * S.lda);
+    const auto V = as_global(S.V);
     const int64_t tot = m * SB;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = k % m, c = c0 + k / m;
         double v = 0.0;
         if (c < nref) v = (r < c) ? 0.0 : ((r == c) ? 1.0 : P[r + c * S.lda]);
-        S.V[r + c * S.n] = v;
+        V[r + c * S.n] = v;
     }
     const int c = c0 + (int)threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < SB && c >= nref) S.tau[j0 + c] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x < SB && c >= nref) as_global(S.tau)[j0 + c] = 0.0;
 }
 
 // T (nb x nb, upper, ld BW) of H_c0 ... H_{c0+nb-1} = I - V T V^T from the
@@ -318,14 +319,14 @@ __global__ void extract_panel_v_kernel(const BandSec *__restrict__ secs, int64_t
 __global__ void larft_panel_kernel(const BandSec *__restrict__ secs, int64_t j0, int c0, int nb, int sub) {
     const BandSec S = secs[blockIdx.x];
     if (S.n - j0 - BW < 2) return;
-    const double *Gm = sub ? S.Y : S.S;
-    double *Tm = sub ? S.M : S.T;
+    const auto Gm = as_global(sub ? S.Y : S.S);
+    const auto Tm = as_global(sub ? S.M : S.T);
     __shared__ double Tl[BW][BW + 1];
     __shared__ double col[BW];
     const int j = threadIdx.x;  // BW threads
     for (int k = 0; k < BW; ++k) Tl[j][k] = 0.0;
     __syncthreads();
-    const double *tau = S.tau + j0 + c0;
+    const auto tau = as_global(S.tau + j0 + c0);
     for (int i = 0; i < nb; ++i) {
         const double ti = tau[i];
         if (j < i) {
@@ -389,8 +390,9 @@ __device__ __forceinline__ void bulge_task(double *__restrict__ B, int64_t n, in
     const int64_t col = (k == 0) ? i : r - BW;
     // band columns: ecol(j)[l] = entry (r + l, col + j); dcol(j)[l] = entry (r + l, r + j), l >= j
     // (F: dcol(j)[ln + l]); B[(row - c) + c LDB] holds entry (row, c)
-    auto ecol = [&](int j) { return B + (col + j) * LDB + (r - col - j); };
-    auto dcol = [&](int j) { return B + (r + j) * LDB - j; };
+    const gptr<double> Bg = as_global(B);
+    auto ecol = [&](int j) { return Bg + (col + j) * LDB + (r - col - j); };
+    auto dcol = [&](int j) { return Bg + (r + j) * LDB - j; };
 
     // ---- loads ----
 #pragma unroll
@@ -418,7 +420,7 @@ __device__ __forceinline__ void bulge_task(double *__restrict__ B, int64_t n, in
         if (lane < ln) ecol(0)[lane] = (lane == 0) ? beta : 0.0;
         if (lane == 0) L.par[0] = tau;
         // kept for the back-transform: v below its unit entry, tau in the unit entry's place
-        if (v2) v2[(i * v2ks + k) * BW + lane] = (lane == 0) ? tau : ((lane < ln) ? x * scale : 0.0);
+        if (v2) as_global(v2)[(i * v2ks + k) * BW + lane] = (lane == 0) ? tau : ((lane < ln) ? x * scale : 0.0);
     }
     __syncthreads();
     const double tau = L.par[0];

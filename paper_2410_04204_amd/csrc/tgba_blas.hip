@@ -307,7 +307,7 @@ dgemm_kernel(const GemmDesc *__restrict__ descs, int nd) {
     }
     // epilogue: D[4r + l/16][l%16] of block (a, b)
     if (G.Cpart) {
-        double *P = G.Cpart + kc * G.M * G.N;
+        const auto P = as_global(G.Cpart + kc * G.M * G.N);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -657,8 +657,9 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(const ReduceDesc *__
         const int64_t loc = e - D.first, mn = D.M * D.N;
         const int64_t i = loc % D.M, j = loc / D.M;
         double acc = 0.0;
-        for (int p = 0; p < D.nparts; ++p) acc += D.parts[p * mn + loc];
-        double *c = D.C + i + j * D.ldc;
+        const auto parts = as_global(D.parts);
+        for (int p = 0; p < D.nparts; ++p) acc += parts[p * mn + loc];
+        const auto c = as_global(D.C + i + j * D.ldc);
         *c = (D.beta == 0.0) ? acc : acc + D.beta * (*c);
     }
 }

@@ -24,6 +24,18 @@ void clear_error();
             return ::tgba::set_error(TGBA_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Device memory reached through a pointer in the global address space: loads and stores
+// compile to global_* instructions, counted by the vector memory counter only.  Through a
+// generic pointer (one read from a descriptor in memory) they become flat_* instructions,
+// which also count in the LDS counter, so every wait for an LDS access then waits for the
+// outstanding device-memory loads and stores as well.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T *p) {
+    return (gptr<T>)p;
+}
+
 constexpr int kNS = 0, kR = 1;
 constexpr int kMaxN = 64;
 
