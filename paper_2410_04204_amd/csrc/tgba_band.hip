@@ -1281,9 +1281,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t q2_rsrc(const double *base, in
 __device__ __forceinline__ double q2_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-__device__ __forceinline__ void q2_st(__amdgpu_buffer_rsrc_t r, double v, uint32_t voff) {
+__device__ __forceinline__ void q2_st(__amdgpu_buffer_rsrc_t r, double v, uint32_t voff, uint32_t soff) {
     using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, voff, 0u, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, voff, soff, 0);
 }
 constexpr uint32_t kQ2Off = 0x80000000u;  // offset of a masked access
 
@@ -1311,14 +1311,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q
     const auto rf = q2_rsrc(F, (int64_t)kc * kQ2Frag * (int64_t)sizeof(double));
     const uint32_t lz = (uint32_t)(ldz * (int64_t)sizeof(double));
     const int n32 = (int)n;
-    auto zoff = [&](int g, int c) -> uint32_t {  // entry (g, c0 + c) of Z, or masked
-        return (g < n32 && c < ccount) ? (uint32_t)g * 8u + (uint32_t)c * lz : kQ2Off;
+    // Entry (g, c0 + c) of Z at the per-lane offset zrow(g, cl) plus the wave-uniform offset
+    // cu lz (c = cl + cu), the latter in a scalar register: no per-column offsets are kept in
+    // vector registers.  A row g >= n is masked (offset 2^31 and up, past the extent); a
+    // column c >= ccount lies past the extent by itself.  Offsets stay below 2^32 (ldz < 5e6).
+    auto zrow = [&](int g, int cl) -> uint32_t {
+        return g < n32 ? (uint32_t)g * 8u + (uint32_t)cl * lz : kQ2Off;
     };
     double pre[CW / 4];
     // 64 rows from global row g0 of the chunk's columns: lane -> row, wave + 4 j -> column
     auto gload = [&](int g0) {
+        const uint32_t v = zrow(g0 + lane, wave);
 #pragma unroll
-        for (int j = 0; j < CW / 4; ++j) pre[j] = q2_ld(rz, zoff(g0 + lane, wave + 4 * j), 0u);
+        for (int j = 0; j < CW / 4; ++j) pre[j] = q2_ld(rz, v, (uint32_t)(4 * j) * lz);
     };
     auto lstore = [&](int slot0) {
 #pragma unroll
@@ -1393,17 +1398,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) q
         // the next window's rows 0 .. 63 and stay in their slots, or go out after the last k
         const bool out = wave < 2 || k + 1 == kc;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a) {
+            const int rw = 32 * wave + 16 * a + lr;
+            const uint32_t v = zrow(w0 + rw, lq);
 #pragma unroll
             for (int bc = 0; bc < NBC; ++bc)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int rw = 32 * wave + 16 * a + lr, cl = 16 * bc + 4 * r + lq;
+                    const int cl = 16 * bc + 4 * r + lq;
                     if (out)
-                        q2_st(rz, acc2[a][bc][r], zoff(w0 + rw, cl));
+                        q2_st(rz, acc2[a][bc][r], v, (uint32_t)(16 * bc + 4 * r) * lz);
                     else
                         Zs[cl * LDZ2 + ((rw + sb) & 127)] = acc2[a][bc][r];
                 }
+        }
     }
 }
 }  // namespace
