@@ -464,8 +464,32 @@ __device__ __forceinline__ int sturm_count(ConstF64 d, ConstF64 e, int n, double
     return cnt;
 }
 
+// Multisection before the bisection: the Gershgorin interval [lo, hi] of a sector is cut at
+// kMultiSect - 1 interior shifts, one Sturm count each (one thread per shift), and every
+// eigenvalue's bisection starts from the cell that holds it, log2(kMultiSect) halvings in.
+constexpr int kMultiSect = 1024;
+__device__ __forceinline__ double msect_shift(double lo, double hi, int j) {
+    return j == 0 ? lo : (j == kMultiSect ? hi : lo + (hi - lo) * ((double)j / kMultiSect));
+}
+// counts: kMultiSect + 1 per sector, count(shift j) at j (0 at lo, n at hi)
+__global__ void __launch_bounds__(256) msect_kernel(const BisSec *__restrict__ secs, const double *__restrict__ bounds,
+                                                    int *__restrict__ counts) {
+    const int sec = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;  // 0 .. kMultiSect
+    if (j > kMultiSect) return;
+    const BisSec S = secs[sec];
+    const int n = (int)S.n;
+    int c = 0;
+    if (j == kMultiSect) c = n;
+    else if (j > 0 && n > 0)
+        c = sturm_count((ConstF64)S.d, (ConstF64)S.e, n, msect_shift(bounds[3 * sec], bounds[3 * sec + 1], j),
+                        bounds[3 * sec + 2]);
+    as_global(counts)[(int64_t)sec * (kMultiSect + 1) + j] = c;
+}
+
 __global__ void __launch_bounds__(kBisThreads) bisect_kernel(const BisSec *__restrict__ secs, int nsec,
-                                                             const double *__restrict__ bounds) {
+                                                             const double *__restrict__ bounds,
+                                                             const int *__restrict__ counts) {
     const int64_t blk = blockIdx.x;
     int lo_s = 0, hi_s = nsec - 1;
     while (lo_s < hi_s) {
@@ -473,10 +497,22 @@ __global__ void __launch_bounds__(kBisThreads) bisect_kernel(const BisSec *__res
         if (secs[mid].first <= blk) lo_s = mid; else hi_s = mid - 1;
     }
     const BisSec S = secs[lo_s];
+    // the sector's multisection counts (every workgroup belongs to one sector)
+    __shared__ int cs[kMultiSect + 1];
+    for (int j = threadIdx.x; j <= kMultiSect; j += kBisThreads) cs[j] = counts[(int64_t)lo_s * (kMultiSect + 1) + j];
+    __syncthreads();
     const int64_t k = (blk - S.first) * kBisThreads + threadIdx.x;
     if (k >= S.n) return;
     const int n = (int)S.n;
-    double lo = bounds[3 * lo_s], hi = bounds[3 * lo_s + 1];
+    // the cell [a, b] with cs[a] <= k < cs[b] (cs[0] = 0 <= k < n = cs[kMultiSect])
+    int a = 0, b = kMultiSect;
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (cs[m] <= k) a = m; else b = m;
+    }
+    while (a + 1 < b && cs[a + 1] <= k) ++a;  // counts that fail to increase with the shift
+    const double L = bounds[3 * lo_s], H = bounds[3 * lo_s + 1];
+    double lo = msect_shift(L, H, a), hi = msect_shift(L, H, b);
     const double pivmin = bounds[3 * lo_s + 2];
     // invariant: count(lo) <= k < count(hi)
     for (int it = 0; it < 200; ++it) {
@@ -885,6 +921,7 @@ template int ormtr<float>(int64_t, const float *, int64_t, const float *, float 
 int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
     const int nsec = (int)in.size();
     if (nsec == 0) return TGBA_OK;
+    if (nsec > 65535) return set_error(TGBA_EUNSUPPORTED, "bisection: more than 65535 sectors in one call");
     std::vector<BisSec> secs(nsec);
     int64_t total = 0;  // workgroups
     for (int k = 0; k < nsec; ++k) {
@@ -895,12 +932,17 @@ int stebz_batched(std::vector<BisIn> &in, hipStream_t stream) {
     void *ws = nullptr, *wb = nullptr;
     int rc = upload(secs.data(), nsec * sizeof(BisSec), ws::BisectSecs, stream, &ws);
     if (rc) return rc;
-    if ((rc = workspace_get(nsec * 3 * sizeof(double) + 64, ws::BisectBounds, &wb))) return rc;
+    const size_t bbytes = ((size_t)nsec * 3 * sizeof(double) + 255) & ~(size_t)255;
+    if ((rc = workspace_get(bbytes + (size_t)nsec * (kMultiSect + 1) * sizeof(int) + 64, ws::BisectBounds, &wb)))
+        return rc;
     BisSec *d_secs = (BisSec *)ws;
     double *bounds = (double *)wb;
+    int *counts = (int *)((char *)wb + bbytes);
     hipLaunchKernelGGL(gersh_kernel, dim3(nsec), dim3(256), 0, stream, d_secs, bounds);
+    hipLaunchKernelGGL(msect_kernel, dim3((kMultiSect + 256) / 256, nsec), dim3(256), 0, stream, d_secs, bounds, counts);
     if (total > 0)
-        hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)total), dim3(kBisThreads), 0, stream, d_secs, nsec, bounds);
+        hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)total), dim3(kBisThreads), 0, stream, d_secs, nsec, bounds,
+                           counts);
     TGBA_HIP(hipGetLastError());
     return TGBA_OK;
 }
