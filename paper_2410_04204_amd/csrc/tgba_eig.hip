@@ -450,6 +450,15 @@ constexpr int kBisThreads = 256;
 // wave-uniform load from there is a scalar load.
 typedef const double __attribute__((address_space(4))) *ConstF64;
 
+// e^2 / q through the hardware reciprocal and two Newton steps (an error of an ulp or two,
+// like a slightly perturbed e_k; no special cases arise: |q| >= pivmin keeps 1 / q and
+// e^2 / q finite), in place of the correctly rounded division's longer chain.
+__device__ __forceinline__ double sturm_div(double e2, double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(fma(-q, r, 1.0), r, r);
+    r = fma(fma(-q, r, 1.0), r, r);
+    return e2 * r;
+}
 __device__ __forceinline__ int sturm_count(ConstF64 d, ConstF64 e, int n, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -457,7 +466,7 @@ __device__ __forceinline__ int sturm_count(ConstF64 d, ConstF64 e, int n, double
 #pragma unroll 4
     for (int k = 1; k < n; ++k) {
         const double ek = e[k - 1];
-        q = d[k] - x - ek * ek / q;
+        q = d[k] - x - sturm_div(ek * ek, q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
     }
