@@ -250,19 +250,31 @@ __global__ void __launch_bounds__(256) qr_step_kernel(const BandSec *__restrict_
     for (int it = 0; it < QCH / 256; ++it) {
         const int64_t r = c0 + (int64_t)blk * QCH + it * 256 + tid;
         if (r >= m || r < q) continue;
-        if (r == q) {
-            for (int j = q + 1; j < c1; ++j) P[q + j * lda] -= tau * w[j];
-            P[q + q * lda] = beta;
+        if (r == q) {  // row q: all its loads, then its stores, without branches between them
+            double yq[SB];
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj) yq[jj] = P[q + (c0 + jj) * lda];
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj) {  // entries left of column q are final: written back as read
+                const int j = c0 + jj;
+                P[q + j * lda] = (j > q) ? yq[jj] - tau * w[j] : ((j == q) ? beta : yq[jj]);
+            }
             continue;
         }
-        const double v = P[r + q * lda] * scale;
+        // every load of the row before its first store: the stores may alias the loads as far
+        // as the compiler knows, so loads after a store would each wait for the previous store
+        const double xq = P[r + q * lda];
+        double yr[SB];
+#pragma unroll
+        for (int jj = 0; jj < SB; ++jj) yr[jj] = (c0 + jj > q) ? P[r + (c0 + jj) * lda] : 0.0;  // uniform
+        const double v = xq * scale;
         P[r + q * lda] = v;
         double x = 0.0;
 #pragma unroll
         for (int jj = 0; jj < SB; ++jj) {
             const int j = c0 + jj;
             if (j > q) {  // uniform
-                const double y = P[r + j * lda] - tau * v * w[j];
+                const double y = yr[jj] - tau * v * w[j];
                 P[r + j * lda] = y;
                 if (j == qn) x = y;                    // column qn of this row (qn < any later j)
                 if (next && j > qn) acc[jj] += x * y;  // sum_{r >= qn} P[r][qn] P[r][j]
