@@ -334,16 +334,21 @@ __global__ void larft_panel_kernel(const BandSec *__restrict__ secs, int64_t j0,
     const auto Gm = as_global(sub ? S.Y : S.S);
     const auto Tm = as_global(sub ? S.M : S.T);
     __shared__ double Tl[BW][BW + 1];
-    __shared__ double col[BW];
+    __shared__ double Gl[BW][BW + 1];  // G staged in LDS: the recurrence reads it nb times over
+    __shared__ double col[BW], tl[BW];
     const int j = threadIdx.x;  // BW threads
+    const auto tau = as_global(S.tau + j0 + c0);
+    if (j < nb) {
+        for (int i = 0; i < nb; ++i) Gl[j][i] = Gm[j + i * BW];  // all loads in flight together
+        tl[j] = tau[j];
+    }
     for (int k = 0; k < BW; ++k) Tl[j][k] = 0.0;
     __syncthreads();
-    const auto tau = as_global(S.tau + j0 + c0);
     for (int i = 0; i < nb; ++i) {
-        const double ti = tau[i];
+        const double ti = tl[i];
         if (j < i) {
             double acc = 0.0;
-            for (int l = j; l < i; ++l) acc += Tl[j][l] * Gm[l + i * BW];
+            for (int l = j; l < i; ++l) acc += Tl[j][l] * Gl[l][i];
             col[j] = -ti * acc;
         }
         __syncthreads();

@@ -588,16 +588,21 @@ __global__ void extract_v_kernel(const T *A, int64_t lda, int64_t n, int64_t j0,
 template <typename T>
 __global__ void larft_blocks_kernel(const T *Sg, const T *tau, int nb, T *Tm) {
     __shared__ T Tl[64][65];
-    __shared__ T col[64];
+    __shared__ T Gl[64][65];  // the diagonal block of Sg staged in LDS: the recurrence reads it nbp times over
+    __shared__ T col[64], tl[64];
     const int j = threadIdx.x, c0 = 64 * blockIdx.x;
     const int nbp = nb - c0 < 64 ? nb - c0 : 64;
+    if (j < nbp) {
+        for (int i = 0; i < nbp; ++i) Gl[j][i] = Sg[(c0 + j) + (int64_t)(c0 + i) * nb];  // all loads in flight together
+        tl[j] = tau[c0 + j];
+    }
     for (int k = j; k < 64 * 64; k += blockDim.x) Tl[k / 64][k % 64] = T(0);
     __syncthreads();
     for (int i = 0; i < nbp; ++i) {
-        const T ti = tau[c0 + i];
+        const T ti = tl[i];
         if (j < i) {
             T acc = T(0);
-            for (int l = j; l < i; ++l) acc += Tl[j][l] * Sg[(c0 + l) + (int64_t)(c0 + i) * nb];
+            for (int l = j; l < i; ++l) acc += Tl[j][l] * Gl[l][i];
             col[j] = -ti * acc;
         }
         __syncthreads();
