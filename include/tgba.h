@@ -25,7 +25,10 @@
  *    ordinary CPU memory.  The caller owns every input and output buffer.
  *    The library owns only the opaque tgba_basis handle (freed by
  *    tgba_basis_free) and internal workspace it allocates with hipMalloc
- *    and keeps cached per device until tgba_release_workspace().
+ *    and keeps cached per device until tgba_release_workspace().  It also
+ *    keeps the read-only launch descriptors of its matrix products (up to
+ *    256 MB per device, until the process ends) and reuses a set it has seen
+ *    before instead of copying it again; TGBA_DESC_CACHE=0 turns that off.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *    work on that stream and return without synchronising unless stated.
  *  - Dense matrices are column-major with an explicit leading dimension

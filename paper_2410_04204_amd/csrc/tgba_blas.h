@@ -40,6 +40,7 @@ struct GemmDesc {
     // writes alpha * (its partial product) to Cpart + kc * M * N (column-major, ld M); C
     // is not touched and a ReduceDesc sums the parts (requires lower == 0 and K2 == 0)
     int ksplit = 1;
+    int pad2 = 0;  // explicit, so that no byte of a descriptor is indeterminate (they are compared)
     double *Cpart = nullptr;
     int64_t ntile = 0;  // output tiles (filled by dgemm_batched)
 };
@@ -49,12 +50,15 @@ struct ReduceDesc {
     double *C;
     int64_t ldc, M, N;
     const double *parts;
-    int nparts;
+    int64_t nparts;  // 64 bits: no padding, so no byte of a descriptor is indeterminate (they are compared)
     double beta;
     int64_t first;  // filled by splitk_reduce
 };
 
 // The same in single precision (FP32 matrix cores, v_mfma_f32_32x32x2f32).
+static_assert(sizeof(GemmDesc) == 192, "GemmDesc: no implicit padding");
+static_assert(sizeof(ReduceDesc) == 64, "ReduceDesc: no implicit padding");
+
 struct SGemmDesc {
     const float *A;
     int64_t lda;

@@ -570,7 +570,7 @@ int sgemm_batched(std::vector<SGemmDesc> &descs, int slot, hipStream_t stream) {
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = upload(descs.data(), descs.size() * sizeof(SGemmDesc), slot, stream, &ws);
+    int rc = upload_const(descs.data(), descs.size() * sizeof(SGemmDesc), slot, stream, &ws);
     if (rc) return rc;
     hipLaunchKernelGGL(sgemm_kernel, dim3((unsigned)total), dim3(256), 0, stream, (const SGemmDesc *)ws, (int)descs.size());
     TGBA_HIP(hipGetLastError());
@@ -609,7 +609,7 @@ int dgemm_batched(std::vector<GemmDesc> &descs, int slot, hipStream_t stream) {
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = upload(descs.data(), descs.size() * sizeof(GemmDesc), slot, stream, &ws);
+    int rc = upload_const(descs.data(), descs.size() * sizeof(GemmDesc), slot, stream, &ws);
     if (rc) return rc;
     hipEvent_t ta = nullptr, tb = nullptr;
     const bool timed = timing_on();
@@ -673,7 +673,7 @@ int splitk_reduce(std::vector<ReduceDesc> &descs, int slot, hipStream_t stream) 
     }
     if (total == 0) return TGBA_OK;
     void *ws = nullptr;
-    int rc = upload(descs.data(), descs.size() * sizeof(ReduceDesc), slot, stream, &ws);
+    int rc = upload_const(descs.data(), descs.size() * sizeof(ReduceDesc), slot, stream, &ws);
     if (rc) return rc;
     const int64_t grid = std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)grid), dim3(256), 0, stream, (const ReduceDesc *)ws,

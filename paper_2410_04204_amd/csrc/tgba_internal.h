@@ -105,6 +105,12 @@ int workspace_get(size_t bytes, int slot, void **out);
 // captured kernel keeps its own descriptors), filled once when the capture
 // ends; nothing is queued on the stream.
 int upload(const void *src, size_t bytes, int slot, hipStream_t st, void **dev);
+// upload for read-only launch descriptors (the products' and split-K reductions'): a
+// descriptor set seen before on this device is reused from device memory kept by the
+// library (up to 256 MB per device, held until the process ends), so a repeated call
+// with the same geometry queues no copy; a first use copies as upload does.  A reuse on
+// another stream than the first copy's waits for that copy.  TGBA_DESC_CACHE=0 turns it off.
+int upload_const(const void *src, size_t bytes, int slot, hipStream_t st, void **dev);
 // The eager copy behind upload: host -> device through a pinned staging buffer of
 // `slot` (the caller's memory may be pageable and freed right after the call).
 int staged_copy(void *dst, const void *src, size_t bytes, int slot, hipStream_t st);
