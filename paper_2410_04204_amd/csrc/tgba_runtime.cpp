@@ -151,9 +151,10 @@ struct ConstCache {
     std::unordered_map<uint64_t, std::vector<ConstEntry>> map;
     char *cur = nullptr;
     size_t used = 0, cap = 0, total = 0;
+    size_t live_events = 0;  // entries whose copy has not been seen completed
 };
 ConstCache g_const[kDevices];
-constexpr size_t kConstMax = (size_t)256 << 20, kConstChunk = (size_t)16 << 20;
+constexpr size_t kConstMax = (size_t)256 << 20, kConstChunk = (size_t)16 << 20, kConstMaxEvents = 65536;
 
 bool const_cache_on() {
     static const bool on = [] {
@@ -191,16 +192,24 @@ int upload_const(const void *src, size_t bytes, int slot, hipStream_t st, void *
             if (e.bytes.size() != bytes || std::memcmp(e.bytes.data(), p, bytes) != 0) continue;
             if (!e.settled) {
                 const hipError_t q = hipEventQuery(e.done);
-                if (q == hipSuccess) e.settled = true;
-                else if (q != hipErrorNotReady) return set_error(TGBA_EDEVICE, "descriptor copy event query failed");
-                else if (st != e.stream) TGBA_HIP(hipStreamWaitEvent(st, e.done, 0));
+                if (q == hipSuccess) {  // the copy is done: the event is no longer needed
+                    e.settled = true;
+                    TGBA_HIP(hipEventDestroy(e.done));
+                    e.done = nullptr;
+                    --C.live_events;
+                } else if (q != hipErrorNotReady) {
+                    return set_error(TGBA_EDEVICE, "descriptor copy event query failed");
+                } else if (st != e.stream) {
+                    TGBA_HIP(hipStreamWaitEvent(st, e.done, 0));
+                }
             }
             *dev = e.dev;
             return TGBA_OK;
         }
     }
     const size_t b = (bytes + 255) & ~(size_t)255;
-    if (C.total + b > kConstMax) return upload(src, bytes, slot, st, dev);  // full: the plain path
+    if (C.total + b > kConstMax || C.live_events >= kConstMaxEvents)
+        return upload(src, bytes, slot, st, dev);  // full: the plain path
     if (!C.cur || C.used + b > C.cap) {
         const size_t want = std::max(kConstChunk, b);
         void *m = nullptr;
@@ -215,6 +224,7 @@ int upload_const(const void *src, size_t bytes, int slot, hipStream_t st, void *
     ConstEntry e{q, std::vector<unsigned char>(p, p + bytes), st, nullptr, false};
     TGBA_HIP(hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
     TGBA_HIP(hipEventRecord(e.done, st));
+    ++C.live_events;
     C.used += b;
     C.total += b;
     C.map[h].push_back(std::move(e));
