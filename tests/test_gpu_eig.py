@@ -69,6 +69,36 @@ def test_dgemm_padded_c_keeps_its_padding(M, N, K, ldc, beta):
     assert np.abs(got[:, :M].T - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.gpu
+def test_dgemm_repeated_geometry_reads_new_data():
+    """The same product geometry and buffers three times, the second time on another stream: the
+    launch descriptors are then reused from device memory, and every result must follow the
+    operands' current contents (compared with numpy each time)."""
+    import paper_2410_04204_amd as tg
+    torch = _t()
+    M, N, K = 300, 200, 96
+    rng = np.random.default_rng(11)
+    dA = _cm(rng.normal(size=(M, K)))
+    dB = _cm(rng.normal(size=(K, N)))
+    dC = torch.zeros((N, M), dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        A = rng.normal(size=(M, K))
+        B = rng.normal(size=(K, N))
+        dA.copy_(torch.as_tensor(A.T.copy(), device="cuda"))
+        dB.copy_(torch.as_tensor(B.T.copy(), device="cuda"))
+        torch.cuda.synchronize()
+        if rep == 1:
+            with torch.cuda.stream(side):
+                tg.dgemm(0, 0, M, N, K, 1.0, dA, dB, 0.0, dC, stream=side)
+            side.synchronize()
+        else:
+            tg.dgemm(0, 0, M, N, K, 1.0, dA, dB, 0.0, dC)
+            torch.cuda.synchronize()
+        ref = A @ B
+        assert np.abs(dC.cpu().numpy().T - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), rep
+
+
 def _rand_sym(n, seed):
     rng = np.random.default_rng(seed)
     X = rng.normal(size=(n, n))
