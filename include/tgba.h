@@ -357,7 +357,11 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
  * (TGBA_EIG_TWOSTAGE), the others bisection.  When both kinds are present, the
  * vector sectors' whole path runs on a second stream of the device from a second
  * host thread, beside the eigenvalue sectors' batched reduction and bisection on
- * `stream` (ordered after the work already queued on `stream`).  With
+ * `stream` (ordered after the work already queued on `stream`).  Of the
+ * eigenvalue sectors (four or more), those of order below a fraction of the
+ * largest (TGBA_EIG_SPLIT, default 0.8; 0 keeps one group) take their reduction
+ * on a third stream from a third host thread; the bisection of all of them runs
+ * on `stream` after both reductions.  With
  * TGBA_VEC_CONCURRENT=0 all sectors share one batched reduction and only the
  * vector work runs on the second stream, joined back into `stream`.  With the environment variable
  * TGBA_VEC_REDUCTION=onestage the vector sectors instead take the one-stage

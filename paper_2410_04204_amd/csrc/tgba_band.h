@@ -34,7 +34,7 @@ size_t band_workspace_doubles(int64_t n);
 // Tridiagonal similar to every sector's matrix, A = Q1 Q2 T (Q1 Q2)^T.  The
 // reflectors of Q1 (first stage) and Q2 (bulge chasing) are kept for the
 // sectors that give BandIn::tau and BandIn::v2.  Stream-ordered; orders up to
-// 65536.  slot_set (0 or 1) picks one of two sets of workspace slots: calls with
+// 65536.  slot_set (0, 1 or 2) picks one of three sets of workspace slots: calls with
 // different sets may run at the same time on two streams.
 int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream, int slot_set = 0);
 

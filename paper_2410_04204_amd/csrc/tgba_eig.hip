@@ -1131,6 +1131,18 @@ bool vec_side_stream() {
 // The vector sectors take their own two-stage reduction on the second stream, from a
 // second host thread, beside the eigenvalue sectors' reduction (TGBA_VEC_CONCURRENT=0:
 // one reduction of all sectors, then the vector work beside the bisection).
+// Fraction of the largest eigenvalue-only order below which a sector takes the third
+// stream in the concurrent eigensolve (TGBA_EIG_SPLIT; 0 keeps one group).
+double eig_split_fraction() {
+    static const double f = [] {
+        const char *v = std::getenv("TGBA_EIG_SPLIT");
+        if (!v) return 0.8;
+        const double x = std::atof(v);
+        return (x > 0.0 && x < 1.0) ? x : 0.0;
+    }();
+    return f;
+}
+
 bool vec_concurrent() {
     const char *v = std::getenv("TGBA_VEC_CONCURRENT");
     return !(v && std::strcmp(v, "0") == 0);
@@ -1208,17 +1220,50 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
     };
     if (!vs.empty() && !bis.empty() && vec_concurrent() && vec_side_stream() && !capturing()) {
         // two reductions at once: the vector sectors' (workspace slot set 1) on the second
-        // stream from a second host thread, the eigenvalue sectors' on `stream`
-        std::vector<BandIn> bvec, bnov;
+        // stream from a second host thread, the eigenvalue sectors' on `stream`; the smaller
+        // eigenvalue sectors (below a fraction of the largest order) may take a third stream and
+        // thread (slot set 2), so that their bulge chasing runs while the larger sectors are
+        // still in the first stage
+        std::vector<BandIn> bvec, bnov, bsmall;
         for (const BandIn &b : bin) (b.v2 ? bvec : bnov).push_back(b);
-        hipStream_t s2 = nullptr;
+        const double frac = eig_split_fraction();
+        if (frac > 0.0 && bnov.size() >= 4) {
+            int64_t nmax = 0;
+            for (const BandIn &b : bnov) nmax = std::max(nmax, b.n);
+            std::vector<BandIn> big;
+            for (const BandIn &b : bnov) ((double)b.n < frac * (double)nmax ? bsmall : big).push_back(b);
+            if (bsmall.empty() || big.empty()) bsmall.clear();
+            else bnov.swap(big);
+        }
+        hipStream_t s2 = nullptr, s3 = nullptr;
         if ((rc = side_stream(&s2))) return rc;
-        hipEvent_t ev = nullptr;
+        if (!bsmall.empty() && (rc = side_stream2(&s3))) return rc;
+        hipEvent_t ev = nullptr, done3 = nullptr;
         TGBA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         TGBA_HIP(hipEventRecord(ev, stream));
         TGBA_HIP(hipStreamWaitEvent(s2, ev, 0));
+        if (s3) {
+            TGBA_HIP(hipStreamWaitEvent(s3, ev, 0));
+            TGBA_HIP(hipEventCreateWithFlags(&done3, hipEventDisableTiming));
+        }
         int dev = 0;
         TGBA_HIP(hipGetDevice(&dev));
+        int rc3 = TGBA_OK;
+        std::string err3;
+        std::thread th3;
+        if (s3)
+            th3 = std::thread([&] {
+                if (hipSetDevice(dev) != hipSuccess) {
+                    rc3 = TGBA_EDEVICE;
+                    err3 = "hipSetDevice failed in the third eigensolver thread";
+                    return;
+                }
+                rc3 = sytrd_2stage_batched(bsmall, s3, 2);
+                if (!rc3 && hipEventRecord(done3, s3) != hipSuccess) rc3 = set_error(TGBA_EDEVICE, "event record failed");
+                if (!rc3 && hipStreamSynchronize(s3) != hipSuccess) rc3 = set_error(TGBA_EDEVICE, "third stream failed");
+                if (!rc3) rc3 = band_check(s3);
+                if (rc3) err3 = tgba_last_error();
+            });
         int rc2 = TGBA_OK;
         std::string err2;
         std::thread th([&] {
@@ -1234,10 +1279,17 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
             if (rc2) err2 = tgba_last_error();
         });
         rc = sytrd_2stage_batched(bnov, stream, 0);
-        if (!rc) rc = stebz_batched(bis, stream);
+        if (s3) {
+            th3.join();
+            if (!rc && !rc3 && hipStreamWaitEvent(stream, done3, 0) != hipSuccess)
+                rc = set_error(TGBA_EDEVICE, "stream wait failed");
+        }
+        if (!rc && !rc3) rc = stebz_batched(bis, stream);
         th.join();
         (void)hipEventDestroy(ev);
+        if (done3) (void)hipEventDestroy(done3);
         if (rc) return rc;
+        if (rc3) return set_error(rc3, err3);
         if (rc2) return set_error(rc2, err2);
         TGBA_HIP(hipStreamSynchronize(stream));
         return band_check(stream);

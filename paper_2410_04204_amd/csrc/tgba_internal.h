@@ -87,7 +87,8 @@ enum Slot : int {
     MlpScore, MlpSelect, MlpBackward, MlpTrain, LearnedKeep, MixedF32, MixedF64, RefineWork, RefineGemm, CrossDesc,
     BandSecs, BandWork, BandParts, BandGemm, BandRed, BandSched, OrmtrParts, OrmtrRed, EigNovecWork, CorrWork, QuenchCorrWork,
     QuenchCorrGemm1, QuenchCorrGemm2, DsfCrossWork, SytrdApiWork, BisectBounds, DCMerges, DCFirst, DCSplits,
-    BulgeQ, EigVec2Stage, BandSecs2, BandWork2, BandParts2, BandGemm2, BandRed2, BandSched2, Count
+    BulgeQ, EigVec2Stage, BandSecs2, BandWork2, BandParts2, BandGemm2, BandRed2, BandSched2, BandSecs3, BandWork3,
+    BandParts3, BandGemm3, BandRed3, BandSched3, Count
 };
 }  // namespace ws
 constexpr int kWorkspaceSlots = 64;
@@ -124,6 +125,9 @@ bool capturing();
 int capture_event(hipEvent_t *ev);
 // A second stream of the current device (created once, default priority).
 int side_stream(hipStream_t *out);
+// A second library-owned stream of the current device (default priority), for a third
+// concurrent group of the batched eigensolver.
+int side_stream2(hipStream_t *out);
 int release_all_workspace();
 
 // Autotuner: on first use of `key`, time run(c) for every candidate c (one

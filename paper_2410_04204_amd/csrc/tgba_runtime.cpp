@@ -283,6 +283,7 @@ int release_all_workspace() {
 
 namespace {
 hipStream_t g_side[kDevices] = {};
+hipStream_t g_side2[kDevices] = {};
 std::mutex g_smu;
 }  // namespace
 
@@ -293,6 +294,16 @@ int side_stream(hipStream_t *out) {
     std::lock_guard<std::mutex> lk(g_smu);
     if (!g_side[dev]) TGBA_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
     *out = g_side[dev];
+    return TGBA_OK;
+}
+
+int side_stream2(hipStream_t *out) {
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kDevices) return set_error(TGBA_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_smu);
+    if (!g_side2[dev]) TGBA_HIP(hipStreamCreateWithFlags(&g_side2[dev], hipStreamNonBlocking));
+    *out = g_side2[dev];
     return TGBA_OK;
 }
 
