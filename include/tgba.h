@@ -652,6 +652,10 @@ int tgba_timing_read(double *ms, int64_t *launches, double *bytes);
  * Reading a channel consumes only that channel's records.
  */
 int tgba_timing_read_channel(int channel, double *ms, int64_t *launches, double *units);
+/* As tgba_timing_read_channel, and busy_ms (host) = the length of the union of the
+ * channel's launch intervals: launches on several streams at once overlap, so their summed
+ * durations exceed the time during which at least one of them ran.  Consumes the records. */
+int tgba_timing_read_busy(int channel, double *ms, int64_t *launches, double *units, double *busy_ms);
 
 /* Free the cached device workspace of the current device. */
 int tgba_release_workspace(void);

@@ -17,7 +17,7 @@ from ._lib import (TGBA_EIG_FP64, TGBA_EIG_MIXED, TGBA_EIG_NOVEC, TGBA_EIG_ONEST
 __all__ = ["Basis", "assemble_heff", "assemble_heff_batched", "assemble_cross", "dsf_cross", "assemble_corr",
            "quench_corr", "corr_table", "corr_signs", "eig", "eig_mixed", "eig_batched_vec", "dsf", "quench", "quench_overlaps", "power_spectrum", "quench_eps",
            "TGBA_HEFF", "TGBA_GAMMA1", "TGBA_GAUGE_PAPER", "TGBA_LOWER", "TGBA_EIG_FP64", "TGBA_EIG_MIXED",
-           "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TGBA_EIG_TWOSTAGE", "TgbaError", "version", "timing_enable", "timing_read", "MLP_PARAMS",
+           "TGBA_EIG_NOVEC", "TGBA_EIG_ONESTAGE", "TGBA_EIG_TWOSTAGE", "TgbaError", "version", "timing_enable", "timing_read", "timing_read_busy", "MLP_PARAMS",
            "mlp_features", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_train", "mlp_score", "mlp_labels",
            "mlp_select", "quench_weights", "autotune_enable", "autotune_report", "AssemblyPlan"]
 
@@ -429,6 +429,15 @@ def timing_read(channel=0):
     _lib.check(_lib.load().tgba_timing_read_channel(int(channel), ctypes.byref(ms), ctypes.byref(n),
                                                     ctypes.byref(un)))
     return ms.value, n.value, un.value
+
+
+def timing_read_busy(channel=0):
+    """As timing_read, plus the length (ms) of the union of the launch intervals: the time during
+    which at least one launch of the channel ran (launches on several streams overlap)."""
+    ms, n, un, busy = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().tgba_timing_read_busy(int(channel), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(un),
+                                                 ctypes.byref(busy)))
+    return ms.value, n.value, un.value, busy.value
 
 
 # ---- learned truncation ---------------------------------------------------------

@@ -23,7 +23,7 @@ EXPORTS = [
     "tgba_basis_sector_copy", "tgba_basis_constants", "tgba_basis_gauge", "tgba_assemble_heff",
     "tgba_assemble_heff_batched", "tgba_eig", "tgba_dsf", "tgba_dsf_static", "tgba_quench", "tgba_quench_overlaps",
     "tgba_release_workspace", "tgba_basis_stats", "tgba_eig_batched", "tgba_eig_batched_vec", "tgba_sytrd", "tgba_sytrd_2stage", "tgba_stebz",
-    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_timing_read_channel", "tgba_power_spectrum", "tgba_basis_align", "tgba_quench_eps", "tgba_mlp_features",
+    "tgba_dgemm", "tgba_stedc", "tgba_timing_enable", "tgba_timing_read", "tgba_timing_read_channel", "tgba_timing_read_busy", "tgba_power_spectrum", "tgba_basis_align", "tgba_quench_eps", "tgba_mlp_features",
     "tgba_mlp_forward", "tgba_mlp_backward", "tgba_mlp_adam", "tgba_mlp_train", "tgba_mlp_score", "tgba_mlp_labels",
     "tgba_mlp_select", "tgba_eig_mixed", "tgba_autotune_enable", "tgba_autotune_report",
     "tgba_assembly_plan_create", "tgba_plan_launch", "tgba_plan_free", "tgba_quench_weights",
@@ -130,6 +130,8 @@ def load():
                                   c_void_p, c_void_p]
     L.tgba_power_spectrum.argtypes = [c_int64, c_double, c_double, c_void_p, c_int, c_void_p, c_void_p, c_void_p]
     L.tgba_timing_read_channel.argtypes = [c_int, ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double)]
+    L.tgba_timing_read_busy.argtypes = [c_int, ctypes.POINTER(c_double), P_i64, ctypes.POINTER(c_double),
+                                        ctypes.POINTER(c_double)]
     for name in EXPORTS:
         if name not in ("tgba_last_error", "tgba_version", "tgba_basis_free", "tgba_plan_free"):
             getattr(L, name).restype = c_int

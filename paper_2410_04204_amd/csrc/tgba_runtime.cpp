@@ -481,6 +481,58 @@ extern "C" int tgba_timing_read_channel(int channel, double *ms, int64_t *launch
     return TGBA_OK;
 }
 
+extern "C" int tgba_timing_read_busy(int channel, double *ms, int64_t *launches, double *units, double *busy_ms) {
+    tgba::clear_error();
+    if (!ms || !launches || !units || !busy_ms) return tgba::set_error(TGBA_EINVAL, "NULL output");
+    if (channel < 0 || channel > 4) return tgba::set_error(TGBA_EINVAL, "unknown timing channel");
+    std::lock_guard<std::mutex> lk(tgba::g_tmu);
+    double tot = 0.0, un = 0.0;
+    int64_t cnt = 0;
+    std::vector<tgba::Timed> keep;
+    std::vector<std::pair<double, double>> iv;  // [start, end] in ms after the channel's first start event
+    hipEvent_t ref = nullptr;
+    for (auto &t : tgba::g_pending) {
+        if (t.ch != channel) {
+            keep.push_back(t);
+            continue;
+        }
+        TGBA_HIP(hipEventSynchronize(t.b));
+        if (!ref) ref = t.a;
+        float e = 0.0f, s0 = 0.0f, s1 = 0.0f;
+        TGBA_HIP(hipEventElapsedTime(&e, t.a, t.b));
+        TGBA_HIP(hipEventElapsedTime(&s0, ref, t.a));
+        TGBA_HIP(hipEventElapsedTime(&s1, ref, t.b));
+        iv.emplace_back((double)s0, (double)s1);
+        tot += e;
+        un += t.units;
+        ++cnt;
+    }
+    // union of the launch intervals (launches on several streams overlap)
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, cs = 0.0, ce = -1e300;
+    for (auto &x : iv) {
+        if (x.first > ce) {
+            if (ce > cs) busy += ce - cs;
+            cs = x.first;
+            ce = x.second;
+        } else if (x.second > ce) {
+            ce = x.second;
+        }
+    }
+    if (!iv.empty() && ce > cs) busy += ce - cs;
+    for (auto &t : tgba::g_pending)
+        if (t.ch == channel) {
+            tgba::g_pool.push_back(t.a);
+            tgba::g_pool.push_back(t.b);
+        }
+    *ms = tot;
+    *launches = cnt;
+    *units = un;
+    *busy_ms = busy;
+    tgba::g_pending.swap(keep);
+    return TGBA_OK;
+}
+
 extern "C" int tgba_timing_read(double *ms, int64_t *launches, double *bytes) {
     return tgba_timing_read_channel(0, ms, launches, bytes);
 }
