@@ -360,8 +360,10 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
  * `stream` (ordered after the work already queued on `stream`).  Of the
  * eigenvalue sectors (four or more), those of order below a fraction of the
  * largest (TGBA_EIG_SPLIT, default 0.8; 0 keeps one group) take their reduction
- * on a third stream from a third host thread; the bisection of all of them runs
- * on `stream` after both reductions.  With
+ * on a third stream from a third host thread, and of those the ones below a
+ * second fraction (TGBA_EIG_SPLIT2, default 0.65; 0 keeps them together) on a
+ * fourth stream from a fourth host thread; the bisection of all of them runs on
+ * `stream` after the reductions.  With
  * TGBA_VEC_CONCURRENT=0 all sectors share one batched reduction and only the
  * vector work runs on the second stream, joined back into `stream`.  With the environment variable
  * TGBA_VEC_REDUCTION=onestage the vector sectors instead take the one-stage

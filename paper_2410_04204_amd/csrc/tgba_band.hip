@@ -73,10 +73,11 @@ constexpr int QB = kQrMaxBlk * QP + BW;  // one partial-sum buffer of the panel 
 struct BandSlots {
     int secs, work, parts, gemm, red, sched;
 };
-constexpr BandSlots kBandSlots[3] = {
+constexpr BandSlots kBandSlots[4] = {
     {ws::BandSecs, ws::BandWork, ws::BandParts, ws::BandGemm, ws::BandRed, ws::BandSched},
     {ws::BandSecs2, ws::BandWork2, ws::BandParts2, ws::BandGemm2, ws::BandRed2, ws::BandSched2},
-    {ws::BandSecs3, ws::BandWork3, ws::BandParts3, ws::BandGemm3, ws::BandRed3, ws::BandSched3}};
+    {ws::BandSecs3, ws::BandWork3, ws::BandParts3, ws::BandGemm3, ws::BandRed3, ws::BandSched3},
+    {ws::BandSecs4, ws::BandWork4, ws::BandParts4, ws::BandGemm4, ws::BandRed4, ws::BandSched4}};
 
 struct BandSec {
     double *A;
@@ -755,7 +756,7 @@ __global__ void __launch_bounds__(256) pair_copy_kernel(const BandSec *__restric
 }  // namespace
 
 int sytrd_2stage_batched(std::vector<BandIn> &in, hipStream_t stream, int slot_set) {
-    if (slot_set < 0 || slot_set > 2) return set_error(TGBA_EINVAL, "two-stage reduction: slot set must be 0, 1 or 2");
+    if (slot_set < 0 || slot_set > 3) return set_error(TGBA_EINVAL, "two-stage reduction: slot set must be 0 to 3");
     const int kSlotSecs = kBandSlots[slot_set].secs, kSlotWork = kBandSlots[slot_set].work,
               kSlotParts = kBandSlots[slot_set].parts, kSlotGemm = kBandSlots[slot_set].gemm,
               kSlotRed = kBandSlots[slot_set].red, kSlotSched = kBandSlots[slot_set].sched;

@@ -1143,6 +1143,18 @@ double eig_split_fraction() {
     return f;
 }
 
+// Fraction below which an eigenvalue sector of the third stream's group moves on to a fourth
+// stream (TGBA_EIG_SPLIT2, default 0.65; 0: three groups at most).
+double eig_split_fraction2() {
+    static const double f = [] {
+        const char *v = std::getenv("TGBA_EIG_SPLIT2");
+        if (!v) return 0.65;
+        const double x = std::atof(v);
+        return (x > 0.0 && x < 1.0) ? x : 0.0;
+    }();
+    return f;
+}
+
 bool vec_concurrent() {
     const char *v = std::getenv("TGBA_VEC_CONCURRENT");
     return !(v && std::strcmp(v, "0") == 0);
@@ -1224,7 +1236,7 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
         // eigenvalue sectors (below a fraction of the largest order) may take a third stream and
         // thread (slot set 2), so that their bulge chasing runs while the larger sectors are
         // still in the first stage
-        std::vector<BandIn> bvec, bnov, bsmall;
+        std::vector<BandIn> bvec, bnov, bsmall, btiny;
         for (const BandIn &b : bin) (b.v2 ? bvec : bnov).push_back(b);
         const double frac = eig_split_fraction();
         if (frac > 0.0 && bnov.size() >= 4) {
@@ -1234,17 +1246,30 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
             for (const BandIn &b : bnov) ((double)b.n < frac * (double)nmax ? bsmall : big).push_back(b);
             if (bsmall.empty() || big.empty()) bsmall.clear();
             else bnov.swap(big);
+            const double frac2 = eig_split_fraction2();
+            if (frac2 > 0.0 && frac2 < frac && bsmall.size() >= 2) {
+                std::vector<BandIn> mid;
+                for (const BandIn &b : bsmall) ((double)b.n < frac2 * (double)nmax ? btiny : mid).push_back(b);
+                if (btiny.empty() || mid.empty()) btiny.clear();
+                else bsmall.swap(mid);
+            }
         }
         hipStream_t s2 = nullptr, s3 = nullptr;
         if ((rc = side_stream(&s2))) return rc;
         if (!bsmall.empty() && (rc = side_stream2(&s3))) return rc;
-        hipEvent_t ev = nullptr, done3 = nullptr;
+        hipStream_t s4 = nullptr;
+        if (!btiny.empty() && (rc = side_stream3(&s4))) return rc;
+        hipEvent_t ev = nullptr, done3 = nullptr, done4 = nullptr;
         TGBA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         TGBA_HIP(hipEventRecord(ev, stream));
         TGBA_HIP(hipStreamWaitEvent(s2, ev, 0));
         if (s3) {
             TGBA_HIP(hipStreamWaitEvent(s3, ev, 0));
             TGBA_HIP(hipEventCreateWithFlags(&done3, hipEventDisableTiming));
+        }
+        if (s4) {
+            TGBA_HIP(hipStreamWaitEvent(s4, ev, 0));
+            TGBA_HIP(hipEventCreateWithFlags(&done4, hipEventDisableTiming));
         }
         int dev = 0;
         TGBA_HIP(hipGetDevice(&dev));
@@ -1263,6 +1288,22 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
                 if (!rc3 && hipStreamSynchronize(s3) != hipSuccess) rc3 = set_error(TGBA_EDEVICE, "third stream failed");
                 if (!rc3) rc3 = band_check(s3);
                 if (rc3) err3 = tgba_last_error();
+            });
+        int rc4 = TGBA_OK;
+        std::string err4;
+        std::thread th4;
+        if (s4)
+            th4 = std::thread([&] {
+                if (hipSetDevice(dev) != hipSuccess) {
+                    rc4 = TGBA_EDEVICE;
+                    err4 = "hipSetDevice failed in the fourth eigensolver thread";
+                    return;
+                }
+                rc4 = sytrd_2stage_batched(btiny, s4, 3);
+                if (!rc4 && hipEventRecord(done4, s4) != hipSuccess) rc4 = set_error(TGBA_EDEVICE, "event record failed");
+                if (!rc4 && hipStreamSynchronize(s4) != hipSuccess) rc4 = set_error(TGBA_EDEVICE, "fourth stream failed");
+                if (!rc4) rc4 = band_check(s4);
+                if (rc4) err4 = tgba_last_error();
             });
         int rc2 = TGBA_OK;
         std::string err2;
@@ -1284,12 +1325,19 @@ int eig_two_stage(int nsec, const int64_t *n, double *const *A, const int64_t *l
             if (!rc && !rc3 && hipStreamWaitEvent(stream, done3, 0) != hipSuccess)
                 rc = set_error(TGBA_EDEVICE, "stream wait failed");
         }
-        if (!rc && !rc3) rc = stebz_batched(bis, stream);
+        if (s4) {
+            th4.join();
+            if (!rc && !rc4 && hipStreamWaitEvent(stream, done4, 0) != hipSuccess)
+                rc = set_error(TGBA_EDEVICE, "stream wait failed");
+        }
+        if (!rc && !rc3 && !rc4) rc = stebz_batched(bis, stream);
         th.join();
         (void)hipEventDestroy(ev);
         if (done3) (void)hipEventDestroy(done3);
+        if (done4) (void)hipEventDestroy(done4);
         if (rc) return rc;
         if (rc3) return set_error(rc3, err3);
+        if (rc4) return set_error(rc4, err4);
         if (rc2) return set_error(rc2, err2);
         TGBA_HIP(hipStreamSynchronize(stream));
         return band_check(stream);

@@ -88,10 +88,11 @@ enum Slot : int {
     BandSecs, BandWork, BandParts, BandGemm, BandRed, BandSched, OrmtrParts, OrmtrRed, EigNovecWork, CorrWork, QuenchCorrWork,
     QuenchCorrGemm1, QuenchCorrGemm2, DsfCrossWork, SytrdApiWork, BisectBounds, DCMerges, DCFirst, DCSplits,
     BulgeQ, EigVec2Stage, BandSecs2, BandWork2, BandParts2, BandGemm2, BandRed2, BandSched2, BandSecs3, BandWork3,
-    BandParts3, BandGemm3, BandRed3, BandSched3, Count
+    BandParts3, BandGemm3, BandRed3, BandSched3, BandSecs4, BandWork4, BandParts4, BandGemm4, BandRed4, BandSched4,
+    Count
 };
 }  // namespace ws
-constexpr int kWorkspaceSlots = 64;
+constexpr int kWorkspaceSlots = 80;
 static_assert(ws::Count <= kWorkspaceSlots, "more workspace slots than the cache holds");
 
 // Device workspace cache (grow-only, per device and slot).  While this thread
@@ -128,6 +129,7 @@ int side_stream(hipStream_t *out);
 // A second library-owned stream of the current device (default priority), for a third
 // concurrent group of the batched eigensolver.
 int side_stream2(hipStream_t *out);
+int side_stream3(hipStream_t *out);
 int release_all_workspace();
 
 // Autotuner: on first use of `key`, time run(c) for every candidate c (one

@@ -284,6 +284,7 @@ int release_all_workspace() {
 namespace {
 hipStream_t g_side[kDevices] = {};
 hipStream_t g_side2[kDevices] = {};
+hipStream_t g_side3[kDevices] = {};
 std::mutex g_smu;
 }  // namespace
 
@@ -304,6 +305,16 @@ int side_stream2(hipStream_t *out) {
     std::lock_guard<std::mutex> lk(g_smu);
     if (!g_side2[dev]) TGBA_HIP(hipStreamCreateWithFlags(&g_side2[dev], hipStreamNonBlocking));
     *out = g_side2[dev];
+    return TGBA_OK;
+}
+
+int side_stream3(hipStream_t *out) {
+    int dev = 0;
+    TGBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kDevices) return set_error(TGBA_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_smu);
+    if (!g_side3[dev]) TGBA_HIP(hipStreamCreateWithFlags(&g_side3[dev], hipStreamNonBlocking));
+    *out = g_side3[dev];
     return TGBA_OK;
 }
 
