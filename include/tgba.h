@@ -359,9 +359,9 @@ int tgba_eig_batched(int nsec, const int64_t *n, double *const *A, const int64_t
  * host thread, beside the eigenvalue sectors' batched reduction and bisection on
  * `stream` (ordered after the work already queued on `stream`).  Of the
  * eigenvalue sectors (four or more), those of order below a fraction of the
- * largest (TGBA_EIG_SPLIT, default 0.8; 0 keeps one group) take their reduction
+ * largest (TGBA_EIG_SPLIT, default 0.9; 0 keeps one group) take their reduction
  * on a third stream from a third host thread, and of those the ones below a
- * second fraction (TGBA_EIG_SPLIT2, default 0.65; 0 keeps them together) on a
+ * second fraction (TGBA_EIG_SPLIT2, default 0.7; 0 keeps them together) on a
  * fourth stream from a fourth host thread; the bisection of all of them runs on
  * `stream` after the reductions.  With
  * TGBA_VEC_CONCURRENT=0 all sectors share one batched reduction and only the

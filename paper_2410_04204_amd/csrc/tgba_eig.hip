@@ -1136,7 +1136,7 @@ bool vec_side_stream() {
 double eig_split_fraction() {
     static const double f = [] {
         const char *v = std::getenv("TGBA_EIG_SPLIT");
-        if (!v) return 0.8;
+        if (!v) return 0.9;
         const double x = std::atof(v);
         return (x > 0.0 && x < 1.0) ? x : 0.0;
     }();
@@ -1144,11 +1144,11 @@ double eig_split_fraction() {
 }
 
 // Fraction below which an eigenvalue sector of the third stream's group moves on to a fourth
-// stream (TGBA_EIG_SPLIT2, default 0.65; 0: three groups at most).
+// stream (TGBA_EIG_SPLIT2, default 0.7; 0: three groups at most).
 double eig_split_fraction2() {
     static const double f = [] {
         const char *v = std::getenv("TGBA_EIG_SPLIT2");
-        if (!v) return 0.65;
+        if (!v) return 0.7;
         const double x = std::atof(v);
         return (x > 0.0 && x < 1.0) ? x : 0.0;
     }();
